@@ -1,0 +1,147 @@
+"""Pins of the oracle's view map (Eq. (1)-(3)) and interlacing (Alg. 1), CPU only."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import viewmap
+from paper_2407_14053_amd import synth
+
+TINY_PANELS = [
+    # (w, h, N, tan, pitch, offset)
+    (20, 9, 8, Fraction(1, 3), Fraction(53, 10), Fraction(0)),
+    (17, 11, 45, Fraction(1, 6), Fraction(37, 5), Fraction(0)),
+    (13, 12, 60, Fraction(1, 5), Fraction(91, 10), Fraction(0)),
+    (16, 10, 48, Fraction(-1, 27), Fraction(16, 3), Fraction(0)),          # Fig. 2(b) slant and pitch
+    (15, 7, 7, Fraction(2, 7), Fraction(23, 5), Fraction(13, 4)),          # positive offset
+    (11, 6, 5, Fraction(-3, 8), Fraction(9, 2), Fraction(-5, 3)),          # negative slant and offset
+    (12, 8, 4, Fraction(1, 3), Fraction(53, 10), Fraction(0)),             # N < L_x
+]
+
+
+@pytest.mark.parametrize("panel", TINY_PANELS)
+def test_integer_map_equals_fraction_definition(panel):
+    w, h, N, t, p, k = panel
+    ref = viewmap.view_map_fraction(w, h, N, t, p, k)
+    got = viewmap.view_map(w, h, N, t, p, k).astype(np.int64)
+    assert np.array_equal(ref, got)
+    assert got.min() >= 0 and got.max() < N
+
+
+@pytest.mark.parametrize("name", ["tiny", "uhd45", "8k60", "fig2b", "fhd16"])
+def test_full_panel_samples_equal_fraction_definition(name):
+    d = synth.make_named_display(name)
+    V = viewmap.view_map(d.width, d.height, d.n_views, d.tan_slant, d.pitch, d.offset)
+    assert V.shape == (d.height, 3 * d.width)
+    rng = np.random.default_rng(7)
+    xs = rng.integers(0, d.height, 400)
+    ss = rng.integers(0, 3 * d.width, 400)
+    # include the last row and column
+    xs = np.r_[xs, d.height - 1, 0, d.height - 1]
+    ss = np.r_[ss, 3 * d.width - 1, 3 * d.width - 1, 0]
+    for x, s in zip(xs, ss):
+        assert V[x, s] == viewmap.view_of_subpixel(int(x), int(s) // 3, int(s) % 3, d.n_views, d.tan_slant,
+                                                   d.pitch, d.offset)
+
+
+@pytest.mark.parametrize("name", ["tiny", "uhd45", "8k60", "fhd16", "fig2b"])
+def test_periodic_in_lens_pitch_and_sheared_by_slant(name):
+    """d_offset grows by 1 per subpixel column, so with L_x = p/q the map repeats every p columns; one row
+    down adds 3 tan(alpha) = 3a/b, so b' rows down and 3a' columns left (a'/b' = 3a/b in lowest terms) is
+    the same lens position."""
+    d = synth.make_named_display(name)
+    V = viewmap.view_map(d.width, d.height, d.n_views, d.tan_slant, d.pitch, d.offset).astype(np.int64)
+    p = d.pitch.numerator
+    assert np.array_equal(V[:, p:], V[:, :-p])
+    r = 3 * d.tan_slant
+    dx, ds = r.denominator, r.numerator
+    if ds >= 0:
+        assert np.array_equal(V[dx:, :V.shape[1] - ds], V[:-dx, ds:])
+    else:
+        assert np.array_equal(V[dx:, -ds:], V[:-dx, :V.shape[1] + ds])
+
+
+@pytest.mark.parametrize("name", ["tiny", "uhd45", "8k60", "fhd16", "fhd45", "fig2b"])
+def test_three_views_per_pixel(name):
+    """Sec. 5: the R, G and B subpixels under one pixel have distinct x_offset and hence distinct views, so
+    an encoded frame needs 3wh rays (Sec. 1: three times the panel resolution).  This holds when
+    N >= L_x > 2: adjacent subpixels differ by 1 in d_offset, i.e. by about N / L_x >= 1 views."""
+    d = synth.make_named_display(name)
+    assert d.n_views >= d.pitch > 2
+    V = viewmap.view_map(d.width, d.height, d.n_views, d.tan_slant, d.pitch, d.offset).astype(np.int64)
+    P = V.reshape(d.height, d.width, 3)
+    assert np.all(P[:, :, 0] != P[:, :, 1])
+    assert np.all(P[:, :, 1] != P[:, :, 2])
+    assert np.all(P[:, :, 0] != P[:, :, 2])
+
+
+def test_shared_views_when_fewer_views_than_pitch():
+    """With N < L_x two subpixels of one pixel can share a view; the ray set then has fewer than 3wh rays
+    but never fewer than wh (Sec. 5: 1 <= N_rays / wh <= 3)."""
+    d = synth.make_named_display("fd64")
+    V = viewmap.view_map(d.width, d.height, d.n_views, d.tan_slant, d.pitch, d.offset)
+    rv, rx, ry, index = viewmap.subpixel_rays(V)
+    wh = d.width * d.height
+    assert wh <= len(rv) < 3 * wh
+    # every subpixel's ray carries that subpixel's view and position
+    xs, ys = np.meshgrid(np.arange(d.height), np.arange(d.width), indexing="ij")
+    for k in range(3):
+        r = index[:, :, k]
+        assert np.array_equal(rv[r], V[:, k::3].astype(np.int64))
+        assert np.array_equal(rx[r], xs)
+        assert np.array_equal(ry[r], ys)
+
+
+def _rational(x, den=10 ** 6):
+    return Fraction(round(x * den), den)
+
+
+@pytest.mark.parametrize("w,h,lx,deg,koff,n", [
+    (1536, 2048, 6.2221, 10.8232, 4.2077, 48),   # 7.9-inch panel of the display table
+    (3840, 2160, 5.3344, 6.8526, 1.2547, 60),    # 15.6-inch panel
+])
+def test_standard_paradigm_wastes_over_90_percent(w, h, lx, deg, koff, n):
+    """Sec. 1: over 90% of the multi-view pixels are never shown.  Used fraction = distinct rays / (N w h)."""
+    V = viewmap.view_map(w, h, n, _rational(math.tan(math.radians(deg))), _rational(lx), _rational(koff))
+    P = np.sort(V.reshape(h, w, 3).astype(np.int64), axis=2)
+    distinct = 1 + (P[:, :, 1] != P[:, :, 0]).sum() / (w * h) + (P[:, :, 2] != P[:, :, 1]).sum() / (w * h)
+    used = distinct / n
+    assert 1 - used > 0.90
+    # every view owns about 1/N of the subpixels
+    counts = np.bincount(V.ravel().astype(np.int64), minlength=n)
+    assert counts.sum() == 3 * w * h
+    assert counts.min() > 0.4 * 3 * w * h / n
+
+
+def test_interleave_alg1_picks_view_of_each_subpixel():
+    """Alg. 1: M_e[x, y, k] = M_m[V[x, 3y + k], x, y, k]; with views filled by 10^4 v + 10 x + y/1000 + k/10
+    the result decodes back to V and the position."""
+    d = synth.make_named_display("tiny")
+    V = viewmap.view_map(d.width, d.height, d.n_views, d.tan_slant, d.pitch, d.offset)
+    n, h, w = d.n_views, d.height, d.width
+    v = np.arange(n)[:, None, None, None]
+    x = np.arange(h)[None, :, None, None]
+    y = np.arange(w)[None, None, :, None]
+    k = np.arange(3)[None, None, None, :]
+    views = (1e4 * v + 10.0 * x + y / 1000.0 + k / 10.0) * np.ones((n, h, w, 3))
+    enc = viewmap.interleave(views, V)
+    for kk in range(3):
+        dec_v = np.floor(enc[:, :, kk] / 1e4 + 1e-9).astype(np.int64)
+        assert np.array_equal(dec_v, V[:, kk::3].astype(np.int64))
+    xs, ys = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    rest = enc - 1e4 * V.reshape(h, w, 3)
+    assert np.allclose(rest, 10.0 * xs[:, :, None] + ys[:, :, None] / 1000.0 + np.arange(3) / 10.0)
+
+
+def test_literal_fp64_formula_misassigns_lens_boundaries():
+    """Why the arithmetic is exact: evaluating Eq. (2)-(3) in binary FP64 puts some subpixels that sit
+    exactly on a lens boundary into the neighbouring view for rational panels."""
+    d = synth.make_named_display("fig2b")
+    V = viewmap.view_map(d.width, 256, d.n_views, d.tan_slant, d.pitch, d.offset).astype(np.int64)
+    x = np.arange(256)[:, None].astype(np.float64)
+    s = np.arange(3 * d.width)[None, :].astype(np.float64)
+    doff = s + 3 * x * float(d.tan_slant) - float(d.offset)
+    xo = np.mod(doff, float(d.pitch))
+    Vf = np.floor(d.n_views * xo / float(d.pitch)).astype(np.int64)
+    assert (Vf != V).sum() > 0
