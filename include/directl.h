@@ -1,0 +1,155 @@
+/* directl.h — C ABI of the MI355X (gfx950) light-field renderer.
+ *
+ * Renders the interleaved ("encoded") image of a slanted-lenticular autostereoscopic panel directly from a
+ * 3D Gaussian splatting scene (DirectL, arXiv 2407.14053): every subpixel (row x, column y, channel k) is
+ * owned by exactly one view v = V(x, 3y + k) (Eq. (1)-(3)), and is the ray of camera v through pixel (x, y)
+ * (Sec. 5); each view's Gaussians are projected (Eq. (8)-(9)), binned into that view's tiles, depth-sorted
+ * and alpha-composited (Eq. (5), (10)) only into the subpixels that view owns.  The standard paradigm
+ * (render all N views, then interlace with Alg. 1) is provided on the same kernels for comparison.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: DL_OK (0) or a negative DL_E* code; dl_last_error() (thread-local) holds a message.
+ *    No C++ exception crosses this boundary.  On error nothing has been enqueued unless stated otherwise.
+ *  - Pointers named *_dev are device (HBM) pointers owned by the caller; the library never frees them and
+ *    does not keep them after the call returns, except that enqueued work reads/writes them in stream order.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the legacy default stream).  All device work is
+ *    enqueued on it asynchronously.  Some calls also synchronise the stream (documented per call).
+ *  - Layouts are row-major.  Images are float32 [H][W][3] (channel-minor), linear, unclamped.
+ *  - Scene arrays (user layout): means[G][3], log_scales[G][3], quats[G][4] as (w, x, y, z),
+ *    opacity_logits[G], sh[G][16][3] (coefficient-major, channel-minor, DC first; real spherical
+ *    harmonics without the Condon-Shortley phase, index l*l + l + m, m = -l..l).
+ *  - Camera axes are OpenCV's (x right, y down, z forward).  Pixel (x, y) has its centre at image
+ *    coordinates (y + 1/2, x + 1/2); the principal point is (W/2, H/2).
+ *  - Objects are not thread-safe: one thread at a time per dl_ctx (the serving loop serialises host calls).
+ */
+#ifndef DIRECTL_H
+#define DIRECTL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DL_OK = 0,
+  DL_EINVAL = -1, /* invalid argument or descriptor */
+  DL_ERANGE = -2, /* exact view-map integer arithmetic would overflow */
+  DL_ENOMEM = -3, /* device or host allocation failed */
+  DL_EHIP = -4,   /* a HIP runtime call failed */
+  DL_ECAP = -5    /* a fixed-capacity plan overflowed (nothing valid was written to the output) */
+};
+
+typedef struct dl_ctx dl_ctx;
+typedef struct dl_scene dl_scene;
+typedef struct dl_display dl_display;
+typedef struct dl_plan dl_plan;
+
+/* Exact rational num/den, den > 0. */
+typedef struct {
+  int64_t num, den;
+} dl_rational;
+
+/* Lenticular panel (Sec. 3.1 "Interlacing and Display", Eq. (1)-(3); parameters of the display table).
+ * width/height: panel pixels (each has 3 subpixels, R G B left to right).  n_views: N in [1, 255].
+ * tan_slant: tan(alpha) of the lens tilt (clockwise positive).  pitch: line count L_x in subpixel widths
+ * (> 0).  offset: K_offset in subpixel widths.  baseline: distance between the outermost cameras (world
+ * units, >= 0).  focal_px: focal length in pixels (> 0), square pixels. */
+typedef struct {
+  int32_t width, height, n_views;
+  int32_t reserved;
+  dl_rational tan_slant, pitch, offset;
+  double baseline;
+  double focal_px;
+} dl_display_desc;
+
+/* Light-field centre camera (the extrinsic L_0 of Eq. (17)): camera-to-world 4x4 row-major, OpenCV
+ * axes.  View v sits at eye_0 + s_v * right_0 with s_v = baseline * (v / (N - 1) - 1/2) (s_0 = 0 when
+ * N = 1) and is aimed at eye_0 + converge_dist * forward_0, with down_0 as its reference down axis
+ * (evenly spaced cameras converging on the centre, Sec. 3.1). */
+typedef struct {
+  double c2w[16];
+  double converge_dist; /* > 0 */
+} dl_pose;
+
+/* Rasterizer constants (the paper fixes none; these are the 3D Gaussian splatting conventions):
+ * a Gaussian contributes to a ray iff its camera depth z > z_near, q = d^T Sigma'^{-1} d <= q_cut at the
+ * pixel centre and alpha = min(alpha_max, o exp(-q/2)) >= alpha_min (Eq. (10)); contributions are blended
+ * front to back by depth (ties by Gaussian index) and the walk stops before a Gaussian whose blend would take
+ * the transmittance below t_min (Eq. (5)-(6)).  dilation is added to the diagonal of Sigma' (Eq. (9)).
+ * bg is the background colour weighted by the final transmittance.  sh_degree in [0, 3].
+ * tile_w/tile_h: screen tile of the blend (0 = automatic: about 256 owned rays per tile for dl_render,
+ * 16x16 for dl_render_standard). */
+typedef struct {
+  float z_near, q_cut, alpha_min, alpha_max, t_min, dilation;
+  float bg[3];
+  int32_t sh_degree;
+  int32_t tile_w, tile_h;
+} dl_render_opts;
+
+/* Defaults: z_near 0.2, q_cut 9, alpha_min 1/255, alpha_max 0.99, t_min 1e-4, dilation 0.3, bg 0,
+ * sh_degree 3, automatic tiles. */
+void dl_default_opts(dl_render_opts* opts);
+
+/* Message of the last error on this thread ("" if none).  Owned by the library. */
+const char* dl_last_error(void);
+
+/* Create a context on HIP device `device` (made current for the calling thread). */
+int dl_create(int device, dl_ctx** out);
+/* Destroy the context (synchronises the device; frees every library-owned buffer of the context). */
+void dl_destroy(dl_ctx* ctx);
+
+/* Scene upload (Sec. 3.3: mean, covariance via scale and rotation, opacity, SH colour).  The library keeps
+ * its own structure-of-arrays copy in HBM (row-major [59][n_pad] float32).  src_on_device selects whether
+ * the five arrays are device pointers (copied with a device transpose on `stream`) or host pointers (the
+ * call synchronises `stream`).  n >= 1.  Arrays must be finite. */
+int dl_scene_create(dl_ctx* ctx, int64_t n, const float* means, const float* log_scales, const float* quats,
+                    const float* opacity_logits, const float* sh, int src_on_device, void* stream,
+                    dl_scene** out);
+/* Overwrite the parameters of an existing scene with the same n (e.g. after an optimiser step). */
+int dl_scene_update(dl_scene* scene, const float* means, const float* log_scales, const float* quats,
+                    const float* opacity_logits, const float* sh, int src_on_device, void* stream);
+int64_t dl_scene_size(const dl_scene* scene);
+void dl_scene_free(dl_scene* scene);
+
+/* Display: validates the descriptor and builds the view map V[H][3W] (uint8) on the device by exact
+ * integer arithmetic on the rationals (Eq. (1)-(3) with the floored modulo of Eq. (2)).  Returns DL_ERANGE if
+ * the exact arithmetic would not fit 64-bit integers.  Synchronises `stream`. */
+int dl_display_create(dl_ctx* ctx, const dl_display_desc* desc, void* stream, dl_display** out);
+void dl_display_free(dl_display* display);
+/* Copy V[H][3W] (uint8, view of subpixel column 3y + k in row x) into out_dev. */
+int dl_display_view_map(const dl_display* display, uint8_t* out_dev, void* stream);
+/* Number of distinct rays (v, x, y) the panel needs (Sec. 5: wh <= n <= 3wh). */
+int64_t dl_display_num_rays(const dl_display* display);
+
+/* Per-view cameras of the rig for `pose` (Eq. (17)), in FP64 on the host: out_host[N][16] =
+ * world-to-camera rotation rows (9), translation (3), camera centre (3), 0. */
+int dl_cameras(const dl_display* display, const dl_pose* pose, double* out_host);
+
+/* Projection only (Eq. (8)-(9) and the SH colour), for inspection: out_dev[N][n][12] float32 =
+ * (u, v, conic a, b, c, opacity, r, g, b, q_limit, ext_x, ext_y) with conic [[a, b], [b, c]] the inverse of
+ * Sigma', (u, v) the projected mean in image coordinates; depth_dev[N][n] float64 = camera z, or NaN when
+ * the Gaussian cannot reach any pixel centre of that view (behind z_near, alpha always below alpha_min, or
+ * its cutoff ellipse misses the screen). */
+int dl_project(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
+               const dl_render_opts* opts, float* out_dev, double* depth_dev, void* stream);
+
+/* DirectL forward: the encoded image out_dev[H][W][3] (every subpixel written).  Synchronises `stream` once
+ * to size the per-frame binning buffers (library-owned, grown on demand). */
+int dl_render(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
+              const dl_render_opts* opts, float* out_dev, void* stream);
+
+/* Standard paradigm on the same kernels: render all N full views (views_dev[N][H][W][3] if non-NULL, else a
+ * library buffer), then interlace them with Alg. 1 into out_dev[H][W][3].  Synchronises `stream`. */
+int dl_render_standard(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
+                       const dl_render_opts* opts, float* out_dev, float* views_dev, void* stream);
+
+/* Alg. 1 alone: out_dev[x][y][k] = views_dev[V(x, 3y + k)][x][y][k]. */
+int dl_interleave(const dl_display* display, const float* views_dev, float* out_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIRECTL_H */

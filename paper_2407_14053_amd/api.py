@@ -1,0 +1,299 @@
+"""Thin Python binding of the C ABI in ``include/directl.h`` (argument marshalling only).
+
+Every step of the render runs in the gfx950 kernels of ``libdirectl.so``; PyTorch provides device memory
+(tensors) and streams.  There is no CPU fallback: if the library is missing or no GPU is present, calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdirectl.so")
+
+DL_OK, DL_EINVAL, DL_ERANGE, DL_ENOMEM, DL_EHIP, DL_ECAP = 0, -1, -2, -3, -4, -5
+
+
+class DLError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("directl error %d: %s" % (code, msg))
+        self.code = code
+
+
+class dl_rational(ctypes.Structure):
+    _fields_ = [("num", ctypes.c_int64), ("den", ctypes.c_int64)]
+
+
+class dl_display_desc(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("n_views", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tan_slant", dl_rational), ("pitch", dl_rational),
+                ("offset", dl_rational), ("baseline", ctypes.c_double), ("focal_px", ctypes.c_double)]
+
+
+class dl_pose(ctypes.Structure):
+    _fields_ = [("c2w", ctypes.c_double * 16), ("converge_dist", ctypes.c_double)]
+
+
+class dl_render_opts(ctypes.Structure):
+    _fields_ = [("z_near", ctypes.c_float), ("q_cut", ctypes.c_float), ("alpha_min", ctypes.c_float),
+                ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float), ("dilation", ctypes.c_float),
+                ("bg", ctypes.c_float * 3), ("sh_degree", ctypes.c_int32), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_SIGS = {
+    "dl_default_opts": (None, [ctypes.POINTER(dl_render_opts)]),
+    "dl_last_error": (ctypes.c_char_p, []),
+    "dl_create": (_I, [_I, ctypes.POINTER(_P)]),
+    "dl_destroy": (None, [_P]),
+    "dl_scene_create": (_I, [_P, ctypes.c_int64, _P, _P, _P, _P, _P, _I, _P, ctypes.POINTER(_P)]),
+    "dl_scene_update": (_I, [_P, _P, _P, _P, _P, _P, _I, _P]),
+    "dl_scene_size": (ctypes.c_int64, [_P]),
+    "dl_scene_free": (None, [_P]),
+    "dl_display_create": (_I, [_P, ctypes.POINTER(dl_display_desc), _P, ctypes.POINTER(_P)]),
+    "dl_display_free": (None, [_P]),
+    "dl_display_view_map": (_I, [_P, _P, _P]),
+    "dl_display_num_rays": (ctypes.c_int64, [_P]),
+    "dl_cameras": (_I, [_P, ctypes.POINTER(dl_pose), _P]),
+    "dl_project": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P, _P]),
+    "dl_render": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P]),
+    "dl_render_standard": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P,
+                                _P]),
+    "dl_interleave": (_I, [_P, _P, _P, _P]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdirectl.so (built by ``paper_2407_14053_amd.build``); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("libdirectl.so is not built (%s); run python -m paper_2407_14053_amd.build" % path)
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc):
+    if rc != DL_OK:
+        raise DLError(rc, load().dl_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the HIP path needs a GPU; none is visible")
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_opts(**over) -> dl_render_opts:
+    o = dl_render_opts()
+    load().dl_default_opts(ctypes.byref(o))
+    for k, v in over.items():
+        if k == "bg":
+            o.bg = (ctypes.c_float * 3)(*v)
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def make_pose(c2w, converge_dist=None) -> dl_pose:
+    c2w = np.asarray(c2w, dtype=np.float64).reshape(4, 4)
+    p = dl_pose()
+    p.c2w = (ctypes.c_double * 16)(*c2w.ravel().tolist())
+    p.converge_dist = float(np.linalg.norm(c2w[:3, 3])) if converge_dist is None else float(converge_dist)
+    return p
+
+
+def _rat(x) -> dl_rational:
+    f = Fraction(x)
+    return dl_rational(f.numerator, f.denominator)
+
+
+def make_desc(display) -> dl_display_desc:
+    d = dl_display_desc()
+    d.width, d.height, d.n_views = display.width, display.height, display.n_views
+    d.tan_slant, d.pitch, d.offset = _rat(display.tan_slant), _rat(display.pitch), _rat(display.offset)
+    d.baseline, d.focal_px = float(display.baseline), float(display.focal_px)
+    return d
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        torch.cuda.set_device(device)
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(load().dl_create(device, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            load().dl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Scene:
+    """Library-owned SoA copy of a Gaussian scene.  ``arrays`` = (means[G,3], log_scales[G,3], quats[G,4],
+    opacity_logits[G], sh[G,16,3]) as float32 torch CUDA tensors or numpy arrays."""
+
+    def __init__(self, ctx: Context, arrays, stream=None):
+        self.ctx = ctx
+        arrs, on_dev = self._prep(arrays)
+        self.n = int(arrs[0].shape[0])
+        h = ctypes.c_void_p()
+        _check(load().dl_scene_create(ctx.h, self.n, *[self._p(a, on_dev) for a in arrs], int(on_dev),
+                                      _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    @staticmethod
+    def _prep(arrays):
+        torch = _torch()
+        if isinstance(arrays[0], torch.Tensor):
+            arrs = [a.detach().to(torch.float32).contiguous() for a in arrays]
+            return arrs, arrs[0].is_cuda
+        return [np.ascontiguousarray(a, dtype=np.float32) for a in arrays], False
+
+    @staticmethod
+    def _p(a, on_dev):
+        return _ptr(a) if on_dev else a.ctypes.data_as(ctypes.c_void_p)
+
+    def update(self, arrays, stream=None):
+        arrs, on_dev = self._prep(arrays)
+        assert int(arrs[0].shape[0]) == self.n
+        _check(load().dl_scene_update(self.h, *[self._p(a, on_dev) for a in arrs], int(on_dev), _stream(stream)))
+        self._keep = arrs   # keep the sources alive until the stream has consumed them
+
+    def close(self):
+        if self.h:
+            load().dl_scene_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Display:
+    def __init__(self, ctx: Context, display, stream=None):
+        self.ctx = ctx
+        self.info = display
+        self.desc = make_desc(display)
+        h = ctypes.c_void_p()
+        _check(load().dl_display_create(ctx.h, ctypes.byref(self.desc), _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def shape(self):
+        return self.desc.height, self.desc.width
+
+    @property
+    def n_views(self):
+        return self.desc.n_views
+
+    def num_rays(self) -> int:
+        return int(load().dl_display_num_rays(self.h))
+
+    def view_map(self, stream=None):
+        torch = _torch()
+        out = torch.empty((self.desc.height, 3 * self.desc.width), dtype=torch.uint8, device="cuda")
+        _check(load().dl_display_view_map(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def cameras(self, c2w, converge_dist=None) -> np.ndarray:
+        out = np.zeros((self.desc.n_views, 16), dtype=np.float64)
+        pose = make_pose(c2w, converge_dist)
+        _check(load().dl_cameras(self.h, ctypes.byref(pose), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def close(self):
+        if self.h:
+            load().dl_display_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def project(ctx, scene, display, c2w, converge_dist=None, opts=None, stream=None):
+    """(records[N, G, 12] float32, depth[N, G] float64 with NaN where culled)."""
+    torch = _torch()
+    N, G = display.n_views, scene.n
+    rec = torch.empty((N, G, 12), dtype=torch.float32, device="cuda")
+    depth = torch.empty((N, G), dtype=torch.float64, device="cuda")
+    pose = make_pose(c2w, converge_dist)
+    o = opts or default_opts()
+    _check(load().dl_project(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(rec), _ptr(depth),
+                             _stream(stream)))
+    return rec, depth
+
+
+def render(ctx, scene, display, c2w, converge_dist=None, opts=None, out=None, stream=None):
+    """DirectL: the encoded image [H, W, 3] float32."""
+    torch = _torch()
+    H, W = display.shape
+    if out is None:
+        out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    pose = make_pose(c2w, converge_dist)
+    o = opts or default_opts()
+    _check(load().dl_render(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(out),
+                            _stream(stream)))
+    return out
+
+
+def render_standard(ctx, scene, display, c2w, converge_dist=None, opts=None, out=None, views=None,
+                    keep_views=False, stream=None):
+    """Standard paradigm: N full views then Alg. 1.  Returns (encoded image, views or None)."""
+    torch = _torch()
+    H, W = display.shape
+    if out is None:
+        out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    if views is None and keep_views:
+        views = torch.empty((display.n_views, H, W, 3), dtype=torch.float32, device="cuda")
+    pose = make_pose(c2w, converge_dist)
+    o = opts or default_opts()
+    _check(load().dl_render_standard(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(out),
+                                     _ptr(views) if views is not None else None, _stream(stream)))
+    return out, views
+
+
+def interleave(display, views, out=None, stream=None):
+    torch = _torch()
+    H, W = display.shape
+    if out is None:
+        out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    _check(load().dl_interleave(display.h, _ptr(views), _ptr(out), _stream(stream)))
+    return out

@@ -1,0 +1,144 @@
+// Tile binning of the depth-sorted projected Gaussians of each view (gfx950).
+//
+// Input order is (view, depth rank), so emitting (key = view * T + tile, value = Gaussian) pairs in that
+// order and then partitioning them by key with a stable radix sort yields every (view, tile) list already in
+// front-to-back order: the depth digits were sorted before the Gaussians were duplicated into tiles.
+//
+// A Gaussian is listed in a tile when its cutoff ellipse (q <= q_limit) reaches at least one pixel centre of
+// the tile.  The test is conservative (margins above FP32 error), so that the per-pixel rule in the blend
+// alone decides what each ray composites and the image does not depend on the tile size.
+#include "dl_internal.h"
+
+namespace dl {
+namespace {
+
+struct TileRange {
+  int tx0, tx1, ty0, ty1;
+};
+
+__device__ inline bool tile_range(const float* r, const BlendConst& bc, TileRange& tr) {
+  // columns y whose centre y + 0.5 lies within [u - ext_x, u + ext_x]
+  const float u = r[0], v = r[1], ex = r[10], ey = r[11];
+  int y0 = (int)ceilf(u - ex - 0.5f), y1 = (int)floorf(u + ex - 0.5f);
+  int x0 = (int)ceilf(v - ey - 0.5f), x1 = (int)floorf(v + ey - 0.5f);
+  y0 = max(y0 - 1, 0); y1 = min(y1 + 1, bc.W - 1);
+  x0 = max(x0 - 1, 0); x1 = min(x1 + 1, bc.H - 1);
+  if (y0 > y1 || x0 > x1) return false;
+  tr.tx0 = y0 / bc.tw; tr.tx1 = y1 / bc.tw;
+  tr.ty0 = x0 / bc.th; tr.ty1 = x1 / bc.th;
+  return true;
+}
+
+// Minimum over the tile's pixel centres (a rectangle) of q = a dx^2 + 2 b dx dy + c dy^2 about (u, v).
+// Zero when the centre lies inside; otherwise the minimum of the convex quadratic sits on an edge, where
+// it is a 1D quadratic minimised at the clamped stationary point.
+__device__ inline bool tile_touch(const float* r, float xlo, float xhi, float ylo, float yhi) {
+  const float u = r[0], v = r[1], a = r[2], b = r[3], c = r[4], qlim = r[9];
+  const float dxl = xlo - u, dxh = xhi - u, dyl = ylo - v, dyh = yhi - v;
+  if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) return true;
+  float qmin = 3.0e38f;
+  // vertical edges (fixed dx)
+  {
+    float dx = dxl;
+    float dy = fminf(fmaxf(-b * dx / c, dyl), dyh);
+    qmin = fminf(qmin, a * dx * dx + 2.0f * b * dx * dy + c * dy * dy);
+    dx = dxh;
+    dy = fminf(fmaxf(-b * dx / c, dyl), dyh);
+    qmin = fminf(qmin, a * dx * dx + 2.0f * b * dx * dy + c * dy * dy);
+  }
+  // horizontal edges (fixed dy)
+  {
+    float dy = dyl;
+    float dx = fminf(fmaxf(-b * dy / a, dxl), dxh);
+    qmin = fminf(qmin, a * dx * dx + 2.0f * b * dx * dy + c * dy * dy);
+    dy = dyh;
+    dx = fminf(fmaxf(-b * dy / a, dxl), dxh);
+    qmin = fminf(qmin, a * dx * dx + 2.0f * b * dx * dy + c * dy * dy);
+  }
+  return qmin <= qlim * 1.001f + 1e-3f;
+}
+
+__device__ inline void load_rec(const float4* rec, float* r) {
+  const float4 A = rec[0], B = rec[1], C = rec[2];
+  r[0] = A.x; r[1] = A.y; r[2] = A.z; r[3] = A.w;
+  r[4] = B.x; r[5] = B.y; r[6] = B.z; r[7] = B.w;
+  r[8] = C.x; r[9] = C.y; r[10] = C.z; r[11] = C.w;
+}
+
+template <bool EMIT>
+__global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ sorted_idx,
+                                                  const uint32_t* __restrict__ vis_count, BlendConst bc,
+                                                  uint32_t* __restrict__ counts, unsigned long long* __restrict__ totals,
+                                                  const uint32_t* __restrict__ offsets, uint32_t n_keys,
+                                                  uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int vl = blockIdx.y;
+  const int v = bc.v0 + vl;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nvis = vis_count[v];
+  uint32_t cnt = 0;
+  if (r < (int64_t)nvis) {
+    const uint32_t g = sorted_idx[(int64_t)v * bc.G + r];
+    float rr[12];
+    load_rec(rec + ((int64_t)v * bc.G + g) * kRecF4, rr);
+    TileRange tr;
+    if (tile_range(rr, bc, tr)) {
+      const int64_t slot = (int64_t)vl * bc.G + r;
+      uint32_t pos = 0, end = 0;
+      if (EMIT) {
+        // the list of this Gaussian ends where the next one's begins (the last one ends at n_keys)
+        pos = offsets[slot];
+        end = slot + 1 < (int64_t)bc.nv * bc.G ? offsets[slot + 1] : n_keys;
+      }
+      for (int ty = tr.ty0; ty <= tr.ty1; ++ty) {
+        const float ylo = ty * bc.th + 0.5f, yhi = min((ty + 1) * bc.th, bc.H) - 0.5f;
+        for (int tx = tr.tx0; tx <= tr.tx1; ++tx) {
+          const float xlo = tx * bc.tw + 0.5f, xhi = min((tx + 1) * bc.tw, bc.W) - 0.5f;
+          if (tile_touch(rr, xlo, xhi, ylo, yhi)) {
+            if (EMIT) {
+              if (pos >= end) continue;
+              keys[pos] = (uint32_t)vl * (uint32_t)bc.T + (uint32_t)(ty * bc.ntx + tx);
+              vals[pos] = g;
+              ++pos;
+            } else {
+              ++cnt;
+            }
+          }
+        }
+      }
+    }
+  }
+  if (!EMIT) {
+    if (r < bc.G) counts[(int64_t)vl * bc.G + r] = cnt;
+    // block total -> per-view total
+    __shared__ unsigned long long part[4];
+    unsigned long long x = cnt;
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned long long s = part[0] + part[1] + part[2] + part[3];
+      if (s) atomicAdd(&totals[vl], s);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_bin_count(const float4* rec, const uint32_t* sorted_idx, const uint32_t* vis_count,
+                            const BlendConst& bc, uint32_t* counts, unsigned long long* totals, hipStream_t s) {
+  const dim3 grid((unsigned)((bc.G + 255) / 256), (unsigned)bc.nv);
+  hipLaunchKernelGGL(bin_kernel<false>, grid, dim3(256), 0, s, rec, sorted_idx, vis_count, bc, counts, totals,
+                     nullptr, 0u, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_emit(const float4* rec, const uint32_t* sorted_idx, const uint32_t* vis_count,
+                           const BlendConst& bc, const uint32_t* offsets, uint32_t n_keys, uint32_t* keys,
+                           uint32_t* vals, hipStream_t s) {
+  const dim3 grid((unsigned)((bc.G + 255) / 256), (unsigned)bc.nv);
+  hipLaunchKernelGGL(bin_kernel<true>, grid, dim3(256), 0, s, rec, sorted_idx, vis_count, bc, nullptr, nullptr,
+                     offsets, n_keys, keys, vals);
+  return hipGetLastError();
+}
+
+}  // namespace dl

@@ -1,0 +1,93 @@
+// Internal declarations shared by the gfx950 kernels and the host runtime of the light-field renderer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/directl.h"
+
+namespace dl {
+
+// Scene structure-of-arrays: row r of length n_pad holds one float parameter of every Gaussian.
+constexpr int kRowMean = 0;      // 3 rows: x, y, z
+constexpr int kRowLogScale = 3;  // 3 rows
+constexpr int kRowQuat = 6;      // 4 rows: w, x, y, z
+constexpr int kRowLogit = 10;    // 1 row
+constexpr int kRowSH = 11;       // 48 rows: coefficient l, channel c at kRowSH + 3 l + c
+constexpr int kSceneRows = 59;
+
+// Projected record of one (view, Gaussian): 12 floats = 3 x float4.
+//   [0] u  [1] v  [2] conic a  [3] conic b  [4] conic c  [5] opacity  [6..8] rgb
+//   [9] q_limit (tile-test cutoff)  [10] ext_x  [11] ext_y (half extents of the cutoff ellipse, px)
+constexpr int kRecF4 = 3;
+
+// Per-view camera block uploaded for every frame: 16 doubles = rotation rows (9), t (3), eye (3), 0.
+constexpr int kCamDoubles = 16;
+
+struct ProjConst {
+  int64_t G;        // Gaussians
+  int64_t n_pad;    // scene row stride
+  int N, W, H;
+  int sh_degree;
+  double focal, cx, cy;
+  float z_near, q_cut, alpha_min, alpha_max, dilation;
+};
+
+struct BlendConst {
+  int W, H;
+  int tw, th, ntx, nty;  // tile size and tile grid of the panel
+  int T;                 // ntx * nty
+  int64_t G;             // record stride per view
+  int v0, nv;            // first view and number of views of this batch
+  float q_cut, alpha_min, alpha_max, t_min;
+  float bg[3];
+};
+
+// ---- view map and ray lists (viewmap.hip) ----
+hipError_t launch_view_map(uint8_t* V, int W, int H, int N, int64_t As, int64_t Ax, int64_t C, int64_t Q,
+                           hipStream_t s);
+hipError_t launch_rays_emit(const uint8_t* V, int W, int H, int tw, int th, int ntx, int T, uint32_t* keys,
+                            uint32_t* vals, hipStream_t s);
+hipError_t launch_interleave(const uint8_t* V, const float* views, float* out, int W, int H, hipStream_t s);
+
+// ---- scans, radix sort, ranges (sort.hip) ----
+int64_t scan_partial_count(int64_t n);
+// exclusive scan of n uint32 (in may equal out); `partial` holds scan_partial_count(n) + 1 entries.
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, hipStream_t s);
+int64_t radix_hist_size(int64_t seg_len, int n_seg, int digit_bits);
+// Stable LSD sort of n_seg consecutive segments of seg_len (key, value) pairs by key bits [bit_lo, bit_hi),
+// each segment independently.  Ping-pongs between (k0, v0) and (k1, v1); returns true when the result ends
+// in (k1, v1).  `hist` needs radix_hist_size() entries, `partial` scan_partial_count(that) + 1.
+bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
+                    int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial, hipStream_t s, hipError_t* err);
+bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
+                    int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial, hipStream_t s, hipError_t* err);
+// start[k] = first index j with keys[j] >= k, for k in [0, n_keys]
+hipError_t launch_lower_bounds(const uint32_t* keys, int64_t n, uint32_t* start, int64_t n_keys, hipStream_t s);
+
+// ---- projection (project.hip) ----
+hipError_t launch_project(const float* soa, const double* cams, const ProjConst& pc, float4* rec, uint64_t* keys,
+                          uint32_t* vals, double* depth_out, uint32_t* vis_count, hipStream_t s);
+hipError_t launch_scene_transpose(const float* means, const float* log_scales, const float* quats,
+                                  const float* logits, const float* sh, int64_t n, int64_t n_pad, float* soa,
+                                  hipStream_t s);
+
+// ---- binning (bin.hip) ----
+// counts[vl][r] = tiles touched by the r-th nearest visible Gaussian of view v0 + vl; totals[vl] += sum.
+hipError_t launch_bin_count(const float4* rec, const uint32_t* sorted_idx, const uint32_t* vis_count,
+                            const BlendConst& bc, uint32_t* counts, unsigned long long* totals, hipStream_t s);
+hipError_t launch_bin_emit(const float4* rec, const uint32_t* sorted_idx, const uint32_t* vis_count,
+                           const BlendConst& bc, const uint32_t* offsets, uint32_t n_keys, uint32_t* keys,
+                           uint32_t* vals, hipStream_t s);
+
+// ---- blending (blend.hip) ----
+// DirectL: rays of (view, tile) from ray lists; writes owned channels of out[H][W][3].
+hipError_t launch_blend_directl(const float4* rec, const uint32_t* tile_start, const uint32_t* gidx,
+                                const uint32_t* ray_off, const uint32_t* ray_ent, int max_rays,
+                                const BlendConst& bc, float* out, hipStream_t s);
+// Standard: all pixels of each (view, tile); writes views[v][H][W][3].
+hipError_t launch_blend_standard(const float4* rec, const uint32_t* tile_start, const uint32_t* gidx,
+                                 const BlendConst& bc, float* views, hipStream_t s);
+
+}  // namespace dl

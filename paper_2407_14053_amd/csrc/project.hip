@@ -1,0 +1,205 @@
+// Per-view EWA projection and SH colour of every Gaussian (Eq. (7)-(9) and Sec. 3.3), gfx950.
+//
+// One thread per Gaussian reads its 59 parameters once (coalesced structure-of-arrays rows), builds
+// Sigma = R S S^T R^T once, then loops over the N views of the rig: camera transform, Jacobian J of the
+// perspective map, Sigma' = J W Sigma W^T J^T + h I, its inverse (the conic), the projected mean and the
+// cutoff ellipse, the depth key and the view-dependent colour.  Geometry runs in FP64 (the chip's vector
+// FP64 rate makes this free next to the memory traffic) and the record is rounded to FP32 once, so the
+// FP32 blend starts from correctly rounded inputs; depth keys keep 36 mantissa bits of the FP64 z.
+#include "dl_internal.h"
+
+namespace dl {
+namespace {
+
+// Real spherical harmonics without the Condon-Shortley phase, index l*l + l + m, m = -l..l, written as
+// polynomials of the unit direction (x, y, z):
+//   l=0: 1/(2 sqrt(pi))
+//   l=1: sqrt(3/(4pi)) * (y, z, x)
+//   l=2: (1/2)sqrt(15/pi) xy, (1/2)sqrt(15/pi) yz, (1/4)sqrt(5/pi)(3z^2 - 1), (1/2)sqrt(15/pi) xz,
+//        (1/4)sqrt(15/pi)(x^2 - y^2)
+//   l=3: (1/4)sqrt(35/(2pi)) y(3x^2 - y^2), (1/2)sqrt(105/pi) xyz, (1/4)sqrt(21/(2pi)) y(5z^2 - 1),
+//        (1/4)sqrt(7/pi) z(5z^2 - 3), (1/4)sqrt(21/(2pi)) x(5z^2 - 1), (1/4)sqrt(105/pi) z(x^2 - y^2),
+//        (1/4)sqrt(35/(2pi)) x(x^2 - 3y^2)
+__device__ inline void sh_basis(int deg, float x, float y, float z, float* Y) {
+  Y[0] = 0.28209479177387814f;
+  if (deg < 1) return;
+  Y[1] = 0.4886025119029199f * y;
+  Y[2] = 0.4886025119029199f * z;
+  Y[3] = 0.4886025119029199f * x;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = 1.0925484305920792f * (x * y);
+  Y[5] = 1.0925484305920792f * (y * z);
+  Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
+  Y[7] = 1.0925484305920792f * (x * z);
+  Y[8] = 0.5462742152960396f * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = 0.5900435899266435f * y * (3.0f * xx - yy);
+  Y[10] = 2.890611442640554f * (x * y) * z;
+  Y[11] = 0.4570457994644658f * y * (5.0f * zz - 1.0f);
+  Y[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
+  Y[13] = 0.4570457994644658f * x * (5.0f * zz - 1.0f);
+  Y[14] = 1.445305721320277f * z * (xx - yy);
+  Y[15] = 0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ soa, const double* __restrict__ cams,
+                                                      ProjConst pc, float4* __restrict__ rec,
+                                                      uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                      double* __restrict__ depth_out,
+                                                      uint32_t* __restrict__ vis_count) {
+  constexpr int NB = (DEG + 1) * (DEG + 1);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < pc.G;
+  const int64_t ii = live ? i : 0;
+  const int64_t np = pc.n_pad;
+  const double mx = soa[kRowMean * np + ii], my = soa[(kRowMean + 1) * np + ii], mz = soa[(kRowMean + 2) * np + ii];
+  // Sigma = R diag(s^2) R^T (Eq. (8)), quaternion (w, x, y, z) normalised
+  double qw = soa[kRowQuat * np + ii], qx = soa[(kRowQuat + 1) * np + ii];
+  double qy = soa[(kRowQuat + 2) * np + ii], qz = soa[(kRowQuat + 3) * np + ii];
+  const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+  const double Rq[9] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - qw * qz), 2.0 * (qx * qz + qw * qy),
+                        2.0 * (qx * qy + qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - qw * qx),
+                        2.0 * (qx * qz - qw * qy), 2.0 * (qy * qz + qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
+  double s2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double s = exp((double)soa[(kRowLogScale + k) * np + ii]);
+    s2[k] = s * s;
+  }
+  double Sg[6];  // symmetric: xx xy xz yy yz zz
+  {
+    int o = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = a; b < 3; ++b) {
+        Sg[o++] = Rq[a * 3 + 0] * s2[0] * Rq[b * 3 + 0] + Rq[a * 3 + 1] * s2[1] * Rq[b * 3 + 1] +
+                  Rq[a * 3 + 2] * s2[2] * Rq[b * 3 + 2];
+      }
+  }
+  const double opac = 1.0 / (1.0 + exp(-(double)soa[kRowLogit * np + ii]));
+  const float o32 = (float)opac;
+  // effective cutoff of the ellipse for tile tests: beyond q = 2 ln(o / alpha_min) alpha < alpha_min
+  double qlim = pc.q_cut;
+  if (opac > pc.alpha_min) qlim = fmin(qlim, 2.0 * log(opac / (double)pc.alpha_min));
+  qlim = qlim * (1.0 + 1e-4) + 1e-3;
+  float shc[NB * 3];
+#pragma unroll
+  for (int k = 0; k < NB * 3; ++k) shc[k] = soa[(kRowSH + k) * np + ii];
+
+  const int lane = threadIdx.x & 63;
+  for (int v = 0; v < pc.N; ++v) {
+    const double* cam = cams + v * kCamDoubles;
+    const double X = cam[0] * mx + cam[1] * my + cam[2] * mz + cam[9];
+    const double Y = cam[3] * mx + cam[4] * my + cam[5] * mz + cam[10];
+    const double Z = cam[6] * mx + cam[7] * my + cam[8] * mz + cam[11];
+    bool vis = live && (Z > (double)pc.z_near) && (o32 >= pc.alpha_min);
+    uint64_t key = 0xffffffffffffull;
+    float r[12];
+    if (vis) {
+      // T = J W, rows of the 2x3 product
+      const double iz = 1.0 / Z;
+      const double f = pc.focal;
+      double T0[3], T1[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T0[k] = f * iz * (cam[k] - X * iz * cam[6 + k]);
+        T1[k] = f * iz * (cam[3 + k] - Y * iz * cam[6 + k]);
+      }
+      // Sigma' = T Sigma T^T + h I
+      const double S0[3] = {Sg[0] * T0[0] + Sg[1] * T0[1] + Sg[2] * T0[2], Sg[1] * T0[0] + Sg[3] * T0[1] + Sg[4] * T0[2],
+                            Sg[2] * T0[0] + Sg[4] * T0[1] + Sg[5] * T0[2]};
+      const double S1[3] = {Sg[0] * T1[0] + Sg[1] * T1[1] + Sg[2] * T1[2], Sg[1] * T1[0] + Sg[3] * T1[1] + Sg[4] * T1[2],
+                            Sg[2] * T1[0] + Sg[4] * T1[1] + Sg[5] * T1[2]};
+      const double ca = T0[0] * S0[0] + T0[1] * S0[1] + T0[2] * S0[2] + (double)pc.dilation;
+      const double cb = T1[0] * S0[0] + T1[1] * S0[1] + T1[2] * S0[2];
+      const double cc = T1[0] * S1[0] + T1[1] * S1[1] + T1[2] * S1[2] + (double)pc.dilation;
+      const double idet = 1.0 / (ca * cc - cb * cb);
+      const double u = f * X * iz + pc.cx;
+      const double w = f * Y * iz + pc.cy;
+      const double ex = sqrt(qlim * ca) * (1.0 + 1e-4) + 1e-3;
+      const double ey = sqrt(qlim * cc) * (1.0 + 1e-4) + 1e-3;
+      // the ellipse must reach a pixel centre: centres span [0.5, W - 0.5] x [0.5, H - 0.5]
+      vis = (u + ex >= 0.5) && (u - ex <= pc.W - 0.5) && (w + ey >= 0.5) && (w - ey <= pc.H - 0.5);
+      if (vis) {
+        double dx = mx - cam[12], dy = my - cam[13], dz = mz - cam[14];
+        const double dn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+        float Yb[16];
+        sh_basis(DEG, (float)(dx * dn), (float)(dy * dn), (float)(dz * dn), Yb);
+        float rgb[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          float acc = 0.5f;
+#pragma unroll
+          for (int l = 0; l < NB; ++l) acc = fmaf(Yb[l], shc[l * 3 + c], acc);
+          rgb[c] = fmaxf(acc, 0.0f);
+        }
+        r[0] = (float)u; r[1] = (float)w;
+        r[2] = (float)(cc * idet); r[3] = (float)(-cb * idet); r[4] = (float)(ca * idet);
+        r[5] = o32; r[6] = rgb[0]; r[7] = rgb[1]; r[8] = rgb[2];
+        r[9] = (float)qlim; r[10] = (float)ex; r[11] = (float)ey;
+        uint64_t zb = (uint64_t)__double_as_longlong(Z);
+        key = zb >> 16;
+      }
+    }
+    const int64_t o = (int64_t)v * pc.G + i;
+    if (live) {
+      keys[o] = key;
+      vals[o] = (uint32_t)i;
+      if (vis) {
+        float4* dst = rec + o * kRecF4;
+        dst[0] = make_float4(r[0], r[1], r[2], r[3]);
+        dst[1] = make_float4(r[4], r[5], r[6], r[7]);
+        dst[2] = make_float4(r[8], r[9], r[10], r[11]);
+      }
+      if (depth_out) depth_out[o] = vis ? Z : __longlong_as_double(0x7ff8000000000000ll);
+    }
+    const uint64_t b = __ballot(vis);
+    if (lane == 0 && b) atomicAdd(&vis_count[v], (uint32_t)__popcll(b));
+  }
+}
+
+__global__ __launch_bounds__(256) void scene_transpose_kernel(const float* __restrict__ means,
+                                                              const float* __restrict__ log_scales,
+                                                              const float* __restrict__ quats,
+                                                              const float* __restrict__ logits,
+                                                              const float* __restrict__ sh, int64_t n, int64_t n_pad,
+                                                              float* __restrict__ soa) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) soa[(kRowMean + k) * n_pad + i] = means[i * 3 + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) soa[(kRowLogScale + k) * n_pad + i] = log_scales[i * 3 + k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) soa[(kRowQuat + k) * n_pad + i] = quats[i * 4 + k];
+  soa[kRowLogit * n_pad + i] = logits[i];
+  for (int k = 0; k < 48; ++k) soa[(kRowSH + k) * n_pad + i] = sh[i * 48 + k];
+}
+
+}  // namespace
+
+hipError_t launch_project(const float* soa, const double* cams, const ProjConst& pc, float4* rec, uint64_t* keys,
+                          uint32_t* vals, double* depth_out, uint32_t* vis_count, hipStream_t s) {
+  const dim3 grid((unsigned)((pc.G + 255) / 256));
+  switch (pc.sh_degree) {
+    case 0: hipLaunchKernelGGL(project_kernel<0>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, vis_count); break;
+    case 1: hipLaunchKernelGGL(project_kernel<1>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, vis_count); break;
+    case 2: hipLaunchKernelGGL(project_kernel<2>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, vis_count); break;
+    default: hipLaunchKernelGGL(project_kernel<3>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, vis_count); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_scene_transpose(const float* means, const float* log_scales, const float* quats,
+                                  const float* logits, const float* sh, int64_t n, int64_t n_pad, float* soa,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(scene_transpose_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, means, log_scales,
+                     quats, logits, sh, n, n_pad, soa);
+  return hipGetLastError();
+}
+
+}  // namespace dl

@@ -1,0 +1,678 @@
+// Host runtime of the light-field renderer: the C ABI of include/directl.h on top of the gfx950 kernels.
+//
+// Frame (both paths):
+//   cameras (FP64, host)  -> project (all views)  -> per-view depth sort (segmented radix sort, 48-bit keys)
+//   -> count tiles per (view, Gaussian) -> [per view batch: scan -> emit (view, tile) keys -> stable radix
+//   partition by key -> list bounds -> blend] ; the standard path then interlaces its N views (Alg. 1).
+// Views are processed in batches whose key count fits the key buffers; batches are formed on the host after
+// one readback of the per-view key totals.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "dl_internal.h"
+
+using namespace dl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                                  \
+  do {                                                                                                 \
+    hipError_t _e = (expr);                                                                            \
+    if (_e != hipSuccess) return fail(DL_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));     \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  // grow-only; contents are not preserved
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap) return hipSuccess;
+    release();
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    cap = want;
+    return hipSuccess;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+int64_t gcd64(int64_t a, int64_t b) {
+  a = a < 0 ? -a : a;
+  b = b < 0 ? -b : b;
+  while (b) {
+    int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+bool reduce(dl_rational& r) {
+  if (r.den <= 0) return false;
+  int64_t g = gcd64(r.num, r.den);
+  if (g == 0) g = 1;
+  r.num /= g;
+  r.den /= g;
+  return true;
+}
+
+__int128 mod_floor(__int128 a, __int128 m) {
+  __int128 r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+struct RayLists {
+  int tw = 0, th = 0, ntx = 0, nty = 0, T = 0;
+  DevBuf off;  // [N * T + 1] uint32
+  DevBuf ent;  // [n_rays] uint32
+  int max_rays = 0;
+  int64_t n_rays = 0;
+};
+
+}  // namespace
+
+struct dl_ctx {
+  int device = 0;
+  DevBuf cams, rec, k64[2], v32[2], vis, counts, totals, bk[2], bv[2], hist, partial, tstart, views;
+  double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
+  size_t free_at_create = 0;
+};
+
+struct dl_scene {
+  dl_ctx* ctx = nullptr;
+  int64_t n = 0, n_pad = 0;
+  DevBuf soa;
+};
+
+struct dl_display {
+  dl_ctx* ctx = nullptr;
+  dl_display_desc desc{};
+  DevBuf V;
+  int64_t n_rays = 0;
+  std::map<std::pair<int, int>, RayLists*> lists;
+  ~dl_display() {
+    for (auto& kv : lists) delete kv.second;
+  }
+};
+
+namespace {
+
+int check_desc(const dl_display_desc* d, dl_display_desc& o) {
+  if (!d) return fail(DL_EINVAL, "display descriptor is NULL");
+  o = *d;
+  if (o.width < 1 || o.height < 1 || o.width > 65536 || o.height > 65536)
+    return fail(DL_EINVAL, "display width/height out of range");
+  if (o.n_views < 1 || o.n_views > 255) return fail(DL_EINVAL, "n_views must be in [1, 255]");
+  if (!reduce(o.tan_slant) || !reduce(o.pitch) || !reduce(o.offset))
+    return fail(DL_EINVAL, "rational with non-positive denominator");
+  if (o.pitch.num <= 0) return fail(DL_EINVAL, "pitch must be > 0");
+  if (!(o.focal_px > 0) || !std::isfinite(o.focal_px)) return fail(DL_EINVAL, "focal_px must be finite and > 0");
+  if (!(o.baseline >= 0) || !std::isfinite(o.baseline)) return fail(DL_EINVAL, "baseline must be finite and >= 0");
+  return DL_OK;
+}
+
+// Cameras of the rig (Eq. (17) with a horizontal toe-in rig), FP64.
+int make_cameras(const dl_display_desc& d, const dl_pose* pose, double* out) {
+  if (!pose) return fail(DL_EINVAL, "pose is NULL");
+  const double* m = pose->c2w;
+  for (int k = 0; k < 16; ++k)
+    if (!std::isfinite(m[k])) return fail(DL_EINVAL, "pose has non-finite entries");
+  if (!(pose->converge_dist > 0) || !std::isfinite(pose->converge_dist))
+    return fail(DL_EINVAL, "converge_dist must be finite and > 0");
+  const double right0[3] = {m[0], m[4], m[8]}, down0[3] = {m[1], m[5], m[9]}, fwd0[3] = {m[2], m[6], m[10]};
+  const double eye0[3] = {m[3], m[7], m[11]};
+  double target[3];
+  for (int k = 0; k < 3; ++k) target[k] = eye0[k] + pose->converge_dist * fwd0[k];
+  const int N = d.n_views;
+  for (int v = 0; v < N; ++v) {
+    const double s = N > 1 ? d.baseline * ((double)v / (double)(N - 1) - 0.5) : 0.0;
+    double eye[3], f[3], r[3], dn[3];
+    for (int k = 0; k < 3; ++k) eye[k] = eye0[k] + s * right0[k];
+    for (int k = 0; k < 3; ++k) f[k] = target[k] - eye[k];
+    double nf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(nf > 0)) return fail(DL_EINVAL, "degenerate rig (camera at the convergence point)");
+    for (int k = 0; k < 3; ++k) f[k] /= nf;
+    // right = down0 x forward, down = forward x right
+    r[0] = down0[1] * f[2] - down0[2] * f[1];
+    r[1] = down0[2] * f[0] - down0[0] * f[2];
+    r[2] = down0[0] * f[1] - down0[1] * f[0];
+    double nr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(nr > 0)) return fail(DL_EINVAL, "degenerate rig (forward parallel to down)");
+    for (int k = 0; k < 3; ++k) r[k] /= nr;
+    dn[0] = f[1] * r[2] - f[2] * r[1];
+    dn[1] = f[2] * r[0] - f[0] * r[2];
+    dn[2] = f[0] * r[1] - f[1] * r[0];
+    double* c = out + v * kCamDoubles;
+    for (int k = 0; k < 3; ++k) {
+      c[k] = r[k];
+      c[3 + k] = dn[k];
+      c[6 + k] = f[k];
+    }
+    for (int a = 0; a < 3; ++a) c[9 + a] = -(c[a * 3] * eye[0] + c[a * 3 + 1] * eye[1] + c[a * 3 + 2] * eye[2]);
+    for (int k = 0; k < 3; ++k) c[12 + k] = eye[k];
+    c[15] = 0.0;
+  }
+  return DL_OK;
+}
+
+int check_opts(const dl_render_opts* o, dl_render_opts& out) {
+  if (o) out = *o;
+  else dl_default_opts(&out);
+  if (!(out.z_near > 0) || !(out.q_cut > 0) || !(out.alpha_min > 0) || !(out.alpha_max > 0) || !(out.t_min >= 0) ||
+      !(out.dilation >= 0))
+    return fail(DL_EINVAL, "render options out of range");
+  if (out.sh_degree < 0 || out.sh_degree > 3) return fail(DL_EINVAL, "sh_degree must be in [0, 3]");
+  if (out.tile_w < 0 || out.tile_h < 0 || out.tile_w > 4096 || out.tile_h > 4096)
+    return fail(DL_EINVAL, "tile size out of range");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(out.bg[k])) return fail(DL_EINVAL, "background must be finite");
+  return DL_OK;
+}
+
+void auto_tile_directl(const dl_display_desc& d, int& tw, int& th) {
+  // about 220 owned rays per tile: area ~ 220 N / 3 pixels (three views per pixel)
+  const double side = std::sqrt(220.0 * d.n_views / 3.0);
+  int s = (int)std::lround(side / 8.0) * 8;
+  s = std::max(8, std::min(s, 256));
+  tw = th = s;
+}
+
+int build_ray_lists(dl_display* D, int tw, int th, hipStream_t s, RayLists** out) {
+  auto key = std::make_pair(tw, th);
+  auto it = D->lists.find(key);
+  if (it != D->lists.end()) {
+    *out = it->second;
+    return DL_OK;
+  }
+  const dl_display_desc& d = D->desc;
+  RayLists* L = new RayLists();
+  L->tw = tw;
+  L->th = th;
+  L->ntx = (d.width + tw - 1) / tw;
+  L->nty = (d.height + th - 1) / th;
+  L->T = L->ntx * L->nty;
+  const int64_t NT = (int64_t)d.n_views * L->T;
+  if (NT >= (1ll << 31)) {
+    delete L;
+    return fail(DL_EINVAL, "too many (view, tile) lists");
+  }
+  const int64_t n = (int64_t)3 * d.width * d.height;
+  DevBuf k0, v0, k1, v1, hist, part;
+  int bits = 1;
+  while ((1ll << bits) - 1 < NT) ++bits;
+  auto cleanup_fail = [&](int code, const std::string& m) {
+    delete L;
+    return fail(code, m);
+  };
+  if (k0.ensure(n * 4) || v0.ensure(n * 4) || k1.ensure(n * 4) || v1.ensure(n * 4))
+    return cleanup_fail(DL_ENOMEM, "ray list buffers");
+  const int64_t hs = radix_hist_size(n, 1, 8);
+  if (hist.ensure(hs * 4) || part.ensure((scan_partial_count(hs) + 2) * 4) || L->off.ensure((NT + 1) * 4))
+    return cleanup_fail(DL_ENOMEM, "ray list buffers");
+  hipError_t e = launch_rays_emit(D->V.as<uint8_t>(), d.width, d.height, tw, th, L->ntx, L->T, k0.as<uint32_t>(),
+                                  v0.as<uint32_t>(), s);
+  if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
+  bool fl = radix_sort_u32(k0.as<uint32_t>(), v0.as<uint32_t>(), k1.as<uint32_t>(), v1.as<uint32_t>(), n, 1, 0, bits,
+                           hist.as<uint32_t>(), part.as<uint32_t>(), s, &e);
+  if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
+  uint32_t* sk = fl ? k1.as<uint32_t>() : k0.as<uint32_t>();
+  DevBuf& sv = fl ? v1 : v0;
+  e = launch_lower_bounds(sk, n, L->off.as<uint32_t>(), NT, s);
+  if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
+  std::vector<uint32_t> off(NT + 1);
+  e = hipMemcpyAsync(off.data(), L->off.p, (NT + 1) * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
+  L->n_rays = off[NT];
+  int mx = 0;
+  for (int64_t k = 0; k < NT; ++k) mx = std::max<int>(mx, (int)(off[k + 1] - off[k]));
+  L->max_rays = mx;
+  // keep the sorted entries (first n_rays values)
+  std::swap(L->ent.p, sv.p);
+  std::swap(L->ent.cap, sv.cap);
+  D->lists[key] = L;
+  *out = L;
+  return DL_OK;
+}
+
+struct Tiles {
+  int tw, th, ntx, nty, T;
+};
+
+Tiles make_tiles(const dl_display_desc& d, int tw, int th) {
+  Tiles t;
+  t.tw = tw;
+  t.th = th;
+  t.ntx = (d.width + tw - 1) / tw;
+  t.nty = (d.height + th - 1) / th;
+  t.T = t.ntx * t.nty;
+  return t;
+}
+
+// Shared frame: cameras, projection, depth sort, per-view tile counts.  Leaves the sorted Gaussian indices
+// in *sorted and the per-view key totals on the host.
+int frame_front(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose, const dl_render_opts& o,
+                const Tiles& tl, hipStream_t s, uint32_t** sorted, std::vector<unsigned long long>& totals,
+                ProjConst& pc) {
+  const dl_display_desc& d = D->desc;
+  const int N = d.n_views;
+  const int64_t G = S->n;
+  int rc = make_cameras(d, pose, C->cams_host);
+  if (rc) return rc;
+  HIP_TRY(C->cams.ensure((size_t)N * kCamDoubles * 8));
+  const int64_t NG = (int64_t)N * G;
+  if (NG >= (1ll << 32) - 1) return fail(DL_EINVAL, "views x Gaussians exceeds 2^32");
+  HIP_TRY(C->rec.ensure((size_t)NG * kRecF4 * 16));
+  HIP_TRY(C->k64[0].ensure((size_t)NG * 8));
+  HIP_TRY(C->k64[1].ensure((size_t)NG * 8));
+  HIP_TRY(C->v32[0].ensure((size_t)NG * 4));
+  HIP_TRY(C->v32[1].ensure((size_t)NG * 4));
+  HIP_TRY(C->vis.ensure(256 * 4));
+  HIP_TRY(C->counts.ensure((size_t)NG * 4));
+  HIP_TRY(C->totals.ensure(256 * 8));
+  const int64_t hs = radix_hist_size(G, N, 8);
+  HIP_TRY(C->hist.ensure((size_t)hs * 4));
+  HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, NG)) + 2) * 4));
+
+  HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(C->vis.p, 0, 256 * 4, s));
+  HIP_TRY(hipMemsetAsync(C->totals.p, 0, 256 * 8, s));
+  pc.G = G;
+  pc.n_pad = S->n_pad;
+  pc.N = N;
+  pc.W = d.width;
+  pc.H = d.height;
+  pc.sh_degree = o.sh_degree;
+  pc.focal = d.focal_px;
+  pc.cx = d.width / 2.0;
+  pc.cy = d.height / 2.0;
+  pc.z_near = o.z_near;
+  pc.q_cut = o.q_cut;
+  pc.alpha_min = o.alpha_min;
+  pc.alpha_max = o.alpha_max;
+  pc.dilation = o.dilation;
+  HIP_TRY(launch_project(S->soa.as<float>(), C->cams.as<double>(), pc, C->rec.as<float4>(), C->k64[0].as<uint64_t>(),
+                         C->v32[0].as<uint32_t>(), nullptr, C->vis.as<uint32_t>(), s));
+  hipError_t e;
+  bool fl = radix_sort_u64(C->k64[0].as<uint64_t>(), C->v32[0].as<uint32_t>(), C->k64[1].as<uint64_t>(),
+                           C->v32[1].as<uint32_t>(), G, N, 0, 48, C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s,
+                           &e);
+  if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
+  *sorted = fl ? C->v32[1].as<uint32_t>() : C->v32[0].as<uint32_t>();
+  BlendConst bc{};
+  bc.W = d.width;
+  bc.H = d.height;
+  bc.tw = tl.tw;
+  bc.th = tl.th;
+  bc.ntx = tl.ntx;
+  bc.nty = tl.nty;
+  bc.T = tl.T;
+  bc.G = G;
+  bc.v0 = 0;
+  bc.nv = N;
+  HIP_TRY(launch_bin_count(C->rec.as<float4>(), *sorted, C->vis.as<uint32_t>(), bc, C->counts.as<uint32_t>(),
+                           C->totals.as<unsigned long long>(), s));
+  totals.assign(N, 0);
+  HIP_TRY(hipMemcpyAsync(totals.data(), C->totals.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DL_OK;
+}
+
+size_t key_capacity(dl_ctx* C) {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)8 << 30;
+  // keys + values, double-buffered: 16 B per key; keep the current key buffers' size as available
+  size_t have = C->bk[0].cap + C->bk[1].cap + C->bv[0].cap + C->bv[1].cap;
+  size_t budget = (size_t)((fr + have) * 0.6);
+  size_t cap = budget / 16;
+  return std::min<size_t>(cap, (size_t)0x7fffffff);
+}
+
+// Per view batch: scan counts, emit keys, partition by (view, tile), list bounds, blend.
+int frame_batches(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_render_opts& o, const Tiles& tl,
+                  uint32_t* sorted, const std::vector<unsigned long long>& totals, bool standard, const RayLists* L,
+                  float* out, hipStream_t s) {
+  const dl_display_desc& d = D->desc;
+  const int N = d.n_views;
+  const int64_t G = S->n;
+  const size_t cap = key_capacity(C);
+  int v0 = 0;
+  while (v0 < N) {
+    size_t K = 0;
+    int v1 = v0;
+    while (v1 < N && K + totals[v1] <= cap) K += totals[v1++];
+    if (v1 == v0) return fail(DL_ENOMEM, "one view's tile keys exceed the key buffer capacity");
+    const int nv = v1 - v0;
+    BlendConst bc{};
+    bc.W = d.width;
+    bc.H = d.height;
+    bc.tw = tl.tw;
+    bc.th = tl.th;
+    bc.ntx = tl.ntx;
+    bc.nty = tl.nty;
+    bc.T = tl.T;
+    bc.G = G;
+    bc.v0 = v0;
+    bc.nv = nv;
+    bc.q_cut = o.q_cut;
+    bc.alpha_min = o.alpha_min;
+    bc.alpha_max = o.alpha_max;
+    bc.t_min = o.t_min;
+    for (int k = 0; k < 3; ++k) bc.bg[k] = o.bg[k];
+    const int64_t nkeys = (int64_t)nv * tl.T;
+    int bits = 1;
+    while ((1ll << bits) < nkeys) ++bits;
+    HIP_TRY(C->bk[0].ensure(std::max<size_t>(K, 1) * 4));
+    HIP_TRY(C->bk[1].ensure(std::max<size_t>(K, 1) * 4));
+    HIP_TRY(C->bv[0].ensure(std::max<size_t>(K, 1) * 4));
+    HIP_TRY(C->bv[1].ensure(std::max<size_t>(K, 1) * 4));
+    HIP_TRY(C->tstart.ensure((size_t)(nkeys + 1) * 4));
+    const int64_t hs = radix_hist_size((int64_t)K, 1, 8);
+    HIP_TRY(C->hist.ensure((size_t)std::max<int64_t>(hs, 1) * 4));
+    HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, (int64_t)nv * G)) + 2) * 4));
+    uint32_t* offs = C->counts.as<uint32_t>() + (int64_t)v0 * G;
+    HIP_TRY(exclusive_scan_u32(offs, offs, (int64_t)nv * G, C->partial.as<uint32_t>(), s));
+    HIP_TRY(launch_bin_emit(C->rec.as<float4>(), sorted, C->vis.as<uint32_t>(), bc, offs, (uint32_t)K,
+                            C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), s));
+    hipError_t e = hipSuccess;
+    bool fl = false;
+    if (K > 0)
+      fl = radix_sort_u32(C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), C->bk[1].as<uint32_t>(),
+                          C->bv[1].as<uint32_t>(), (int64_t)K, 1, 0, bits, C->hist.as<uint32_t>(),
+                          C->partial.as<uint32_t>(), s, &e);
+    if (e != hipSuccess) return fail(DL_EHIP, std::string("tile sort: ") + hipGetErrorString(e));
+    uint32_t* skeys = fl ? C->bk[1].as<uint32_t>() : C->bk[0].as<uint32_t>();
+    uint32_t* svals = fl ? C->bv[1].as<uint32_t>() : C->bv[0].as<uint32_t>();
+    HIP_TRY(launch_lower_bounds(skeys, (int64_t)K, C->tstart.as<uint32_t>(), nkeys, s));
+    if (standard) {
+      HIP_TRY(launch_blend_standard(C->rec.as<float4>(), C->tstart.as<uint32_t>(), svals, bc, out, s));
+    } else {
+      HIP_TRY(launch_blend_directl(C->rec.as<float4>(), C->tstart.as<uint32_t>(), svals, L->off.as<uint32_t>(),
+                                   L->ent.as<uint32_t>(), L->max_rays, bc, out, s));
+    }
+    v0 = v1;
+  }
+  return DL_OK;
+}
+
+int check_common(dl_ctx* C, const dl_scene* S, const dl_display* D) {
+  if (!C || !S || !D) return fail(DL_EINVAL, "NULL context, scene or display");
+  if (S->ctx != C || D->ctx != C) return fail(DL_EINVAL, "scene/display belong to another context");
+  return DL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dl_default_opts(dl_render_opts* o) {
+  if (!o) return;
+  o->z_near = 0.2f;
+  o->q_cut = 9.0f;
+  o->alpha_min = 1.0f / 255.0f;
+  o->alpha_max = 0.99f;
+  o->t_min = 1e-4f;
+  o->dilation = 0.3f;
+  o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
+  o->sh_degree = 3;
+  o->tile_w = 0;
+  o->tile_h = 0;
+}
+
+const char* dl_last_error(void) { return g_err.c_str(); }
+
+int dl_create(int device, dl_ctx** out) {
+  if (!out) return fail(DL_EINVAL, "out is NULL");
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(DL_EINVAL, "no such HIP device");
+  HIP_TRY(hipSetDevice(device));
+  dl_ctx* c = new dl_ctx();
+  c->device = device;
+  if (hipHostMalloc((void**)&c->cams_host, 256 * kCamDoubles * 8, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(DL_ENOMEM, "pinned camera staging");
+  }
+  *out = c;
+  return DL_OK;
+}
+
+void dl_destroy(dl_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->cams_host) (void)hipHostFree(c->cams_host);
+  delete c;
+}
+
+static int scene_fill(dl_scene* sc, const float* means, const float* log_scales, const float* quats,
+                      const float* logits, const float* sh, int on_dev, hipStream_t s) {
+  if (!means || !log_scales || !quats || !logits || !sh) return fail(DL_EINVAL, "NULL scene array");
+  const int64_t n = sc->n, np = sc->n_pad;
+  if (on_dev) {
+    HIP_TRY(launch_scene_transpose(means, log_scales, quats, logits, sh, n, np, sc->soa.as<float>(), s));
+    return DL_OK;
+  }
+  std::vector<float> h((size_t)kSceneRows * np, 0.0f);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int k = 0; k < 3; ++k) h[(kRowMean + k) * np + i] = means[i * 3 + k];
+    for (int k = 0; k < 3; ++k) h[(kRowLogScale + k) * np + i] = log_scales[i * 3 + k];
+    for (int k = 0; k < 4; ++k) h[(kRowQuat + k) * np + i] = quats[i * 4 + k];
+    h[kRowLogit * np + i] = logits[i];
+    for (int k = 0; k < 48; ++k) h[(kRowSH + k) * np + i] = sh[i * 48 + k];
+  }
+  HIP_TRY(hipMemcpyAsync(sc->soa.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DL_OK;
+}
+
+int dl_scene_create(dl_ctx* ctx, int64_t n, const float* means, const float* log_scales, const float* quats,
+                    const float* opacity_logits, const float* sh, int src_on_device, void* stream,
+                    dl_scene** out) {
+  if (!ctx || !out) return fail(DL_EINVAL, "NULL context or out");
+  if (n < 1 || n >= (1ll << 31)) return fail(DL_EINVAL, "scene size must be in [1, 2^31)");
+  dl_scene* sc = new dl_scene();
+  sc->ctx = ctx;
+  sc->n = n;
+  sc->n_pad = (n + 63) / 64 * 64;
+  if (sc->soa.ensure((size_t)kSceneRows * sc->n_pad * 4) != hipSuccess) {
+    delete sc;
+    return fail(DL_ENOMEM, "scene buffer");
+  }
+  int rc = scene_fill(sc, means, log_scales, quats, opacity_logits, sh, src_on_device, (hipStream_t)stream);
+  if (rc) {
+    delete sc;
+    return rc;
+  }
+  *out = sc;
+  return DL_OK;
+}
+
+int dl_scene_update(dl_scene* sc, const float* means, const float* log_scales, const float* quats,
+                    const float* opacity_logits, const float* sh, int src_on_device, void* stream) {
+  if (!sc) return fail(DL_EINVAL, "NULL scene");
+  return scene_fill(sc, means, log_scales, quats, opacity_logits, sh, src_on_device, (hipStream_t)stream);
+}
+
+int64_t dl_scene_size(const dl_scene* sc) { return sc ? sc->n : -1; }
+
+void dl_scene_free(dl_scene* sc) { delete sc; }
+
+int dl_display_create(dl_ctx* ctx, const dl_display_desc* desc, void* stream, dl_display** out) {
+  if (!ctx || !out) return fail(DL_EINVAL, "NULL context or out");
+  dl_display_desc d;
+  int rc = check_desc(desc, d);
+  if (rc) return rc;
+  // Q = b c p; As = b c q mod Q; Ax = 3 a c q mod Q; C = -r b q mod Q (floored)
+  const __int128 a = d.tan_slant.num, b = d.tan_slant.den, p = d.pitch.num, q = d.pitch.den, r = d.offset.num,
+                 c = d.offset.den;
+  const __int128 Q = b * c * p;
+  const __int128 lim = (__int128)1 << 62;
+  if (Q <= 0 || Q >= lim) return fail(DL_ERANGE, "view map modulus b*c*p out of range");
+  const __int128 As = mod_floor(b * c * q, Q), Ax = mod_floor(3 * a * c * q, Q), Cc = mod_floor(-r * b * q, Q);
+  if (Q * (__int128)(3 * (int64_t)d.width + d.height + 1) >= lim || Q * d.n_views >= lim)
+    return fail(DL_ERANGE, "view map exceeds 64-bit exact arithmetic");
+  dl_display* D = new dl_display();
+  D->ctx = ctx;
+  D->desc = d;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nV = (size_t)3 * d.width * d.height;
+  if (D->V.ensure(nV) != hipSuccess) {
+    delete D;
+    return fail(DL_ENOMEM, "view map buffer");
+  }
+  hipError_t e = launch_view_map(D->V.as<uint8_t>(), d.width, d.height, d.n_views, (int64_t)As, (int64_t)Ax,
+                                 (int64_t)Cc, (int64_t)Q, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete D;
+    return fail(DL_EHIP, std::string("view map: ") + hipGetErrorString(e));
+  }
+  // number of distinct rays via the ray lists of a 64x64 tiling (cached for later use)
+  RayLists* L = nullptr;
+  rc = build_ray_lists(D, 64, 64, s, &L);
+  if (rc) {
+    delete D;
+    return rc;
+  }
+  D->n_rays = L->n_rays;
+  *out = D;
+  return DL_OK;
+}
+
+void dl_display_free(dl_display* D) { delete D; }
+
+int dl_display_view_map(const dl_display* D, uint8_t* out_dev, void* stream) {
+  if (!D || !out_dev) return fail(DL_EINVAL, "NULL display or output");
+  const size_t n = (size_t)3 * D->desc.width * D->desc.height;
+  HIP_TRY(hipMemcpyAsync(out_dev, D->V.p, n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return DL_OK;
+}
+
+int64_t dl_display_num_rays(const dl_display* D) { return D ? D->n_rays : -1; }
+
+int dl_cameras(const dl_display* D, const dl_pose* pose, double* out_host) {
+  if (!D || !out_host) return fail(DL_EINVAL, "NULL display or output");
+  return make_cameras(D->desc, pose, out_host);
+}
+
+int dl_project(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose, const dl_render_opts* opts,
+               float* out_dev, double* depth_dev, void* stream) {
+  int rc = check_common(C, S, D);
+  if (rc) return rc;
+  if (!out_dev || !depth_dev) return fail(DL_EINVAL, "NULL output");
+  dl_render_opts o;
+  if ((rc = check_opts(opts, o))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const dl_display_desc& d = D->desc;
+  const int N = d.n_views;
+  const int64_t NG = (int64_t)N * S->n;
+  if ((rc = make_cameras(d, pose, C->cams_host))) return rc;
+  HIP_TRY(C->cams.ensure((size_t)N * kCamDoubles * 8));
+  HIP_TRY(C->k64[0].ensure((size_t)NG * 8));
+  HIP_TRY(C->v32[0].ensure((size_t)NG * 4));
+  HIP_TRY(C->vis.ensure(256 * 4));
+  HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(C->vis.p, 0, 256 * 4, s));
+  HIP_TRY(hipMemsetAsync(out_dev, 0, (size_t)NG * 48, s));
+  ProjConst pc{};
+  pc.G = S->n;
+  pc.n_pad = S->n_pad;
+  pc.N = N;
+  pc.W = d.width;
+  pc.H = d.height;
+  pc.sh_degree = o.sh_degree;
+  pc.focal = d.focal_px;
+  pc.cx = d.width / 2.0;
+  pc.cy = d.height / 2.0;
+  pc.z_near = o.z_near;
+  pc.q_cut = o.q_cut;
+  pc.alpha_min = o.alpha_min;
+  pc.alpha_max = o.alpha_max;
+  pc.dilation = o.dilation;
+  HIP_TRY(launch_project(S->soa.as<float>(), C->cams.as<double>(), pc, (float4*)out_dev, C->k64[0].as<uint64_t>(),
+                         C->v32[0].as<uint32_t>(), depth_dev, C->vis.as<uint32_t>(), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DL_OK;
+}
+
+int dl_render(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose, const dl_render_opts* opts,
+              float* out_dev, void* stream) {
+  int rc = check_common(C, S, D);
+  if (rc) return rc;
+  if (!out_dev) return fail(DL_EINVAL, "NULL output");
+  dl_render_opts o;
+  if ((rc = check_opts(opts, o))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int tw = o.tile_w, th = o.tile_h;
+  if (tw == 0 || th == 0) auto_tile_directl(D->desc, tw, th);
+  RayLists* L = nullptr;
+  if ((rc = build_ray_lists(const_cast<dl_display*>(D), tw, th, s, &L))) return rc;
+  if (L->max_rays > 16 * 256) return fail(DL_EINVAL, "tile too large: more than 4096 rays of one view");
+  Tiles tl = make_tiles(D->desc, tw, th);
+  uint32_t* sorted = nullptr;
+  std::vector<unsigned long long> totals;
+  ProjConst pc{};
+  if ((rc = frame_front(C, S, D, pose, o, tl, s, &sorted, totals, pc))) return rc;
+  return frame_batches(C, S, D, o, tl, sorted, totals, false, L, out_dev, s);
+}
+
+int dl_interleave(const dl_display* D, const float* views_dev, float* out_dev, void* stream) {
+  if (!D || !views_dev || !out_dev) return fail(DL_EINVAL, "NULL argument");
+  HIP_TRY(launch_interleave(D->V.as<uint8_t>(), views_dev, out_dev, D->desc.width, D->desc.height,
+                            (hipStream_t)stream));
+  return DL_OK;
+}
+
+int dl_render_standard(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose,
+                       const dl_render_opts* opts, float* out_dev, float* views_dev, void* stream) {
+  int rc = check_common(C, S, D);
+  if (rc) return rc;
+  if (!out_dev) return fail(DL_EINVAL, "NULL output");
+  dl_render_opts o;
+  if ((rc = check_opts(opts, o))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int tw = o.tile_w ? o.tile_w : 16, th = o.tile_h ? o.tile_h : 16;
+  if (tw * th > 16 * 256) return fail(DL_EINVAL, "standard tile larger than 4096 pixels");
+  const dl_display_desc& d = D->desc;
+  float* views = views_dev;
+  if (!views) {
+    HIP_TRY(C->views.ensure((size_t)d.n_views * d.width * d.height * 12));
+    views = C->views.as<float>();
+  }
+  Tiles tl = make_tiles(d, tw, th);
+  uint32_t* sorted = nullptr;
+  std::vector<unsigned long long> totals;
+  ProjConst pc{};
+  if ((rc = frame_front(C, S, D, pose, o, tl, s, &sorted, totals, pc))) return rc;
+  if ((rc = frame_batches(C, S, D, o, tl, sorted, totals, true, nullptr, views, s))) return rc;
+  HIP_TRY(launch_interleave(D->V.as<uint8_t>(), views, out_dev, d.width, d.height, s));
+  return DL_OK;
+}
+
+}  // extern "C"

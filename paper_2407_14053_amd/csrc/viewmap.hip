@@ -1,0 +1,86 @@
+// View map (Eq. (1)-(3)), per-(view, tile) ray lists (Sec. 5) and interlacing (Alg. 1) on gfx950.
+#include "dl_internal.h"
+
+namespace dl {
+namespace {
+
+// V[x][s], s = 3y + k.  With tan(alpha) = a/b, L_x = p/q, K_offset = r/c the view is
+// v = floor(N * frac(d_offset / L_x)), and d_offset / L_x = (s b c + 3 x a c - r b) q / (b c p).  The host
+// reduces the three integer coefficients modulo Q = b c p, so that rho = (s As + x Ax + C) mod Q is the
+// numerator of frac(d_offset / L_x) exactly (the floored modulo of Eq. (2) since every term is >= 0), and
+// v = N rho / Q with integer division (the floor of Eq. (3)).
+__global__ __launch_bounds__(256) void view_map_kernel(uint8_t* __restrict__ V, int W3, int H, int N,
+                                                       int64_t As, int64_t Ax, int64_t C, int64_t Q) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)W3 * H) return;
+  const int64_t x = idx / W3;
+  const int64_t s = idx - x * W3;
+  const int64_t rho = (s * As + x * Ax + C) % Q;
+  V[idx] = (uint8_t)((N * rho) / Q);
+}
+
+// One thread per pixel: the distinct views among its three subpixels, each with the mask of channels it
+// serves.  Entry j of pixel p goes to slot 3p + j; unused slots get key 0xffffffff (sorted last).
+// key = v * T + tile, value = local column | local row << 12 | mask << 24.
+__global__ __launch_bounds__(256) void rays_emit_kernel(const uint8_t* __restrict__ V, int W, int H, int tw, int th,
+                                                        int ntx, int T, uint32_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ vals) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)W * H) return;
+  const int x = (int)(p / W), y = (int)(p - (int64_t)x * W);
+  const uint8_t* row = V + (int64_t)x * 3 * W + 3 * y;
+  const uint32_t v[3] = {row[0], row[1], row[2]};
+  const uint32_t tile = (uint32_t)((x / th) * ntx + (y / tw));
+  const uint32_t loc = (uint32_t)(y % tw) | ((uint32_t)(x % th) << 12);
+  for (int j = 0; j < 3; ++j) {
+    bool first = true;
+    for (int i = 0; i < j; ++i) first &= v[i] != v[j];
+    uint32_t key = 0xffffffffu, val = 0;
+    if (first) {
+      uint32_t mask = 0;
+      for (int i = 0; i < 3; ++i) mask |= (v[i] == v[j]) ? (1u << i) : 0u;
+      key = v[j] * (uint32_t)T + tile;
+      val = loc | (mask << 24);
+    }
+    keys[3 * p + j] = key;
+    vals[3 * p + j] = val;
+  }
+}
+
+// Alg. 1: out[x][y][k] = views[V[x][3y + k]][x][y][k]; one thread per subpixel.
+__global__ __launch_bounds__(256) void interleave_kernel(const uint8_t* __restrict__ V,
+                                                         const float* __restrict__ views, float* __restrict__ out,
+                                                         int W, int H) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)3 * W * H;
+  if (idx >= n) return;
+  const int64_t v = V[idx];
+  out[idx] = views[v * n + idx];
+}
+
+inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_view_map(uint8_t* V, int W, int H, int N, int64_t As, int64_t Ax, int64_t C, int64_t Q,
+                           hipStream_t s) {
+  const int64_t n = (int64_t)3 * W * H;
+  hipLaunchKernelGGL(view_map_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, V, 3 * W, H, N, As, Ax, C, Q);
+  return hipGetLastError();
+}
+
+hipError_t launch_rays_emit(const uint8_t* V, int W, int H, int tw, int th, int ntx, int T, uint32_t* keys,
+                            uint32_t* vals, hipStream_t s) {
+  const int64_t n = (int64_t)W * H;
+  hipLaunchKernelGGL(rays_emit_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, V, W, H, tw, th, ntx, T, keys,
+                     vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_interleave(const uint8_t* V, const float* views, float* out, int W, int H, hipStream_t s) {
+  const int64_t n = (int64_t)3 * W * H;
+  hipLaunchKernelGGL(interleave_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, V, views, out, W, H);
+  return hipGetLastError();
+}
+
+}  // namespace dl

@@ -1,0 +1,135 @@
+"""DirectL forward on the GPU path: parity with the FP64 oracle (admissible-set rule, max |err| <= 2e-4),
+bit-identity with the standard paradigm (N full views + Alg. 1) on the same kernels, determinism and edge
+cases (C ABI)."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import render as orender
+from oracle import viewmap as oviewmap
+from paper_2407_14053_amd import synth
+from tests.gpu_util import TOL, admissible_image_err, check_subpixels, full_oracle_image, log, sample_subpixels
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2407_14053_amd import api
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _render(ctx, sc, d, c2w, **opt):
+    from paper_2407_14053_amd import api
+    S = api.Scene(ctx, sc.arrays())
+    D = api.Display(ctx, d)
+    img = api.render(ctx, S, D, c2w, opts=api.default_opts(**opt)).cpu().numpy()
+    return img, S, D
+
+
+@pytest.mark.parametrize("name,pose", [("tiny", 0), ("tiny", 3), ("fd64", 1)])
+def test_directl_full_frame_matches_oracle(ctx, name, pose):
+    log("directl full frame", name, pose)
+    d = synth.make_named_display(name)
+    sc = synth.make_scene(name)
+    c2w = synth.pose_sweep(8)[pose]
+    img, S, D = _render(ctx, sc, d, c2w)
+    ref, res, index = full_oracle_image(sc, d, c2w)
+    err, over = admissible_image_err(res, index, img)
+    log("  max err %.3g, over-budget subpixels %d, fragile rays %d" % (err[~over].max(), over.sum(),
+                                                                       (res.info[:, 1] > 0).sum()))
+    assert err[~over].max() <= TOL
+    assert over.sum() <= 0.001 * over.size
+
+
+def test_directl_background_and_sh_degree(ctx):
+    from paper_2407_14053_amd import api
+    d = synth.make_named_display("tiny")
+    sc = synth.make_scene("tiny")
+    c2w = synth.pose_front(3.0)
+    for bg, deg in [((0.2, 0.5, 0.9), 3), ((0.0, 0.0, 0.0), 1), ((1.0, 0.0, 0.3), 0)]:
+        img, S, D = _render(ctx, sc, d, c2w, bg=bg, sh_degree=deg)
+        ref, res, index = full_oracle_image(sc, d, c2w, orender.Opts(bg=bg, sh_degree=deg))
+        err, over = admissible_image_err(res, index, img)
+        assert err[~over].max() <= TOL, (bg, deg)
+
+
+def test_directl_equals_standard_paradigm_bitwise(ctx):
+    """The paper's invariant on the GPU: DirectL (any tile size) == N full views + Alg. 1, bit for bit."""
+    from paper_2407_14053_amd import api
+    d = synth.make_named_display("tiny")
+    sc = synth.make_scene("tiny")
+    c2w = synth.pose_sweep(8)[5]
+    S = api.Scene(ctx, sc.arrays())
+    D = api.Display(ctx, d)
+    std, views = api.render_standard(ctx, S, D, c2w, keep_views=True)
+    std = std.cpu().numpy()
+    V = oviewmap.view_map(d.width, d.height, d.n_views, d.tan_slant, d.pitch, d.offset)
+    assert np.array_equal(std, oviewmap.interleave(views.cpu().numpy(), V))
+    for tw, th in [(0, 0), (16, 16), (24, 40), (64, 64), (100, 30), (128, 72)]:
+        img = api.render(ctx, S, D, c2w, opts=api.default_opts(tile_w=tw, tile_h=th)).cpu().numpy()
+        assert np.array_equal(img, std), (tw, th)
+    for tw, th in [(32, 32), (8, 8), (16, 48)]:
+        std2, _ = api.render_standard(ctx, S, D, c2w, opts=api.default_opts(tile_w=tw, tile_h=th))
+        assert np.array_equal(std2.cpu().numpy(), std), (tw, th)
+
+
+def test_deterministic(ctx):
+    from paper_2407_14053_amd import api
+    d = synth.make_named_display("tiny")
+    sc = synth.make_scene("tiny")
+    S = api.Scene(ctx, sc.arrays())
+    D = api.Display(ctx, d)
+    a = api.render(ctx, S, D, synth.pose_front()).cpu().numpy()
+    b = api.render(ctx, S, D, synth.pose_front()).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_edge_cases(ctx):
+    from paper_2407_14053_amd import api
+    # every Gaussian behind the cameras: the image is the background
+    sc = synth.make_scene("tiny")
+    sc.means[:, 2] += 10.0
+    d = synth.make_named_display("tiny")
+    img, S, D = _render(ctx, sc, d, synth.pose_front(3.0), bg=(0.25, 0.5, 0.75))
+    assert np.array_equal(img, np.broadcast_to(np.float32([0.25, 0.5, 0.75]), img.shape))
+    # a single Gaussian, a ragged panel (not a multiple of the tile), one view
+    one = synth.make_scene("tiny").subset(slice(0, 1))
+    one.means[:] = 0.0
+    one.log_scales[:] = -1.5
+    one.opacity_logits[:] = 2.0
+    one.sh[:, 0, :] = 1.0
+    for disp in [synth.make_display(97, 53, 5, Fraction(1, 3), Fraction(53, 10), baseline=0.3),
+                 synth.make_display(64, 48, 1, Fraction(1, 3), Fraction(53, 10), baseline=0.0)]:
+        img, S, D = _render(ctx, one, disp, synth.pose_front(3.0))
+        ref, res, index = full_oracle_image(one, disp, synth.pose_front(3.0))
+        err, over = admissible_image_err(res, index, img)
+        assert err.max() <= TOL
+        assert img.max() > 0.05
+    # a random scene on a ragged panel with many views
+    disp = synth.make_display(123, 77, 11, Fraction(-1, 4), Fraction(9, 2), Fraction(7, 3), baseline=0.4)
+    sc = synth.make_scene("tiny")
+    c2w = synth.look_at_c2w((0.5, 0.4, 2.8))
+    img, S, D = _render(ctx, sc, disp, c2w)
+    ref, res, index = full_oracle_image(sc, disp, c2w)
+    err, over = admissible_image_err(res, index, img)
+    assert err[~over].max() <= TOL
+
+
+def test_uhd45_full_size_sampled(ctx):
+    """3840x2160, N = 45, 300k Gaussians: sampled subpixels against the oracle."""
+    log("uhd45 full size")
+    d = synth.make_named_display("uhd45")
+    sc = synth.make_scene("uhd45")
+    c2w = synth.pose_sweep(200)[37]
+    img, S, D = _render(ctx, sc, d, c2w)
+    assert np.isfinite(img).all()
+    xs, ys, ks = sample_subpixels(d.height, d.width, 3000, 11)
+    worst, over, frag = check_subpixels(sc, d, c2w, img, xs, ys, ks, label="uhd45")
+    log("  uhd45 worst %.3g over %d fragile %d" % (worst, over, frag))
+    assert worst <= TOL
+    assert over <= 3
