@@ -135,18 +135,59 @@ int dl_cameras(const dl_display* display, const dl_pose* pose, double* out_host)
 int dl_project(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
                const dl_render_opts* opts, float* out_dev, double* depth_dev, void* stream);
 
-/* DirectL forward: the encoded image out_dev[H][W][3] (every subpixel written).  Synchronises `stream` once
- * to size the per-frame binning buffers (library-owned, grown on demand). */
+/* DirectL forward: the encoded image out_dev[H][W][3] (every subpixel written).  The visible Gaussians of
+ * each view are binned and blended in depth chunks, front to back; tiles whose rays have all terminated take
+ * no further keys.  Synchronises `stream` at the end of the frame to check the library-owned key buffers
+ * (grown, and the frame rendered again, if a chunk overflowed them). */
 int dl_render(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
               const dl_render_opts* opts, float* out_dev, void* stream);
 
-/* Standard paradigm on the same kernels: render all N full views (views_dev[N][H][W][3] if non-NULL, else a
- * library buffer), then interlace them with Alg. 1 into out_dev[H][W][3].  Synchronises `stream`. */
+/* Standard paradigm on the same kernels and chunking: render all N full views (views_dev[N][H][W][3] if
+ * non-NULL, else a library buffer), then interlace them with Alg. 1 into out_dev[H][W][3].  Synchronises
+ * `stream`. */
 int dl_render_standard(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
                        const dl_render_opts* opts, float* out_dev, float* views_dev, void* stream);
 
 /* Alg. 1 alone: out_dev[x][y][k] = views_dev[V(x, 3y + k)][x][y][k]. */
 int dl_interleave(const dl_display* display, const float* views_dev, float* out_dev, void* stream);
+
+/* Per-depth-chunk capacity of the context's tile-key buffers (0 until the first frame sizes it).  A frame
+ * whose chunk needs more keys grows the buffers and renders again; setting a smaller value is allowed (the
+ * buffers shrink lazily only in the sense that the value bounds new growth decisions). */
+int dl_set_key_capacity(dl_ctx* ctx, int64_t keys);
+int64_t dl_key_capacity(const dl_ctx* ctx);
+
+/* ---- measurement ---- */
+enum {
+  DL_STAGE_UPLOAD = 0,     /* camera upload and counter clears */
+  DL_STAGE_PROJECT = 1,    /* projection + SH of all views */
+  DL_STAGE_DEPTH_SORT = 2, /* per-view depth sort */
+  DL_STAGE_BIN_COUNT = 3,  /* tiles per (view, Gaussian) */
+  DL_STAGE_SCAN = 4,       /* key offsets */
+  DL_STAGE_BIN_EMIT = 5,   /* (view, tile) keys */
+  DL_STAGE_TILE_SORT = 6,  /* partition of the keys by (view, tile) */
+  DL_STAGE_BOUNDS = 7,     /* list bounds */
+  DL_STAGE_BLEND = 8,      /* compositing */
+  DL_STAGE_INTERLEAVE = 9, /* Alg. 1 (standard path only) */
+  DL_NSTAGES = 10
+};
+
+/* Per-frame measurements of the last dl_render / dl_render_standard made with profiling on.
+ * stage_ms: summed HIP-event durations per stage on the render stream; stage_launches: occurrences.
+ * keys: the largest number of (view, tile) list entries of one depth chunk; visible: (view, Gaussian) pairs
+ * that reach the screen;
+ * evaluations: (ray, list entry) pairs the blend examined; blends: pairs composited; rays: rays rendered. */
+typedef struct {
+  double stage_ms[DL_NSTAGES];
+  int32_t stage_launches[DL_NSTAGES];
+  int64_t keys, visible, evaluations, blends, rays;
+  int32_t batches, tile_w, tile_h, rays_per_lane;
+} dl_frame_stats;
+
+/* Turn per-stage HIP-event timing and work counters on or off for subsequent frames of this context. */
+int dl_set_profiling(dl_ctx* ctx, int enable);
+/* Read the measurements of the last profiled frame (synchronises on its events). */
+int dl_frame_stats_get(dl_ctx* ctx, dl_frame_stats* out);
 
 #ifdef __cplusplus
 }

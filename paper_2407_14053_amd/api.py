@@ -45,6 +45,18 @@ class dl_render_opts(ctypes.Structure):
                 ("tile_h", ctypes.c_int32)]
 
 
+NSTAGES = 10
+STAGES = ["upload", "project", "depth_sort", "bin_count", "scan", "bin_emit", "tile_sort", "bounds", "blend",
+          "interleave"]
+
+
+class dl_frame_stats(ctypes.Structure):
+    _fields_ = [("stage_ms", ctypes.c_double * NSTAGES), ("stage_launches", ctypes.c_int32 * NSTAGES),
+                ("keys", ctypes.c_int64), ("visible", ctypes.c_int64), ("evaluations", ctypes.c_int64),
+                ("blends", ctypes.c_int64), ("rays", ctypes.c_int64), ("batches", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("rays_per_lane", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _SIGS = {
@@ -66,6 +78,10 @@ _SIGS = {
     "dl_render_standard": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P,
                                 _P]),
     "dl_interleave": (_I, [_P, _P, _P, _P]),
+    "dl_set_profiling": (_I, [_P, _I]),
+    "dl_set_key_capacity": (_I, [_P, ctypes.c_int64]),
+    "dl_key_capacity": (ctypes.c_int64, [_P]),
+    "dl_frame_stats_get": (_I, [_P, ctypes.POINTER(dl_frame_stats)]),
 }
 
 _lib = None
@@ -148,6 +164,24 @@ class Context:
         h = ctypes.c_void_p()
         _check(load().dl_create(device, ctypes.byref(h)))
         self.h = h
+
+    def set_key_capacity(self, keys: int):
+        _check(load().dl_set_key_capacity(self.h, int(keys)))
+
+    def key_capacity(self) -> int:
+        return int(load().dl_key_capacity(self.h))
+
+    def set_profiling(self, on: bool):
+        _check(load().dl_set_profiling(self.h, int(bool(on))))
+
+    def frame_stats(self) -> dict:
+        st = dl_frame_stats()
+        _check(load().dl_frame_stats_get(self.h, ctypes.byref(st)))
+        d = {k: getattr(st, k) for k in ("keys", "visible", "evaluations", "blends", "rays", "batches", "tile_w",
+                                         "tile_h", "rays_per_lane")}
+        d["stage_ms"] = {STAGES[i]: st.stage_ms[i] for i in range(NSTAGES)}
+        d["stage_launches"] = {STAGES[i]: st.stage_launches[i] for i in range(NSTAGES)}
+        return d
 
     def close(self):
         if self.h:

@@ -33,12 +33,14 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
                                                           const uint32_t* __restrict__ gidx,
                                                           const uint32_t* __restrict__ ray_off,
                                                           const uint32_t* __restrict__ ray_ent, BlendConst bc,
-                                                          float* __restrict__ out) {
+                                                          BlendChunk bk, uint8_t* __restrict__ alive,
+                                                          float4* __restrict__ state, float* __restrict__ out) {
   __shared__ float4 sm[kThreads * kRecF4];
   const uint32_t wi = xcd_remap(blockIdx.x, gridDim.x);
-  const int vl = (int)(wi / (uint32_t)bc.T);
-  const int t = (int)(wi - (uint32_t)vl * (uint32_t)bc.T);
-  const int v = bc.v0 + vl;
+  const int v = (int)(wi / (uint32_t)bc.T);
+  const int t = (int)(wi - (uint32_t)v * (uint32_t)bc.T);
+  const int64_t vt = (int64_t)v * bc.T + t;
+  if (!alive[vt]) return;
   const int tx = t % bc.ntx, ty = t / bc.ntx;
   const int ox = tx * bc.tw, oy = ty * bc.th;
   int nr, r0 = 0, cw = 0;
@@ -46,21 +48,22 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
     cw = min(bc.tw, bc.W - ox);
     nr = cw * min(bc.th, bc.H - oy);
   } else {
-    r0 = (int)ray_off[(int64_t)v * bc.T + t];
-    nr = (int)ray_off[(int64_t)v * bc.T + t + 1] - r0;
+    r0 = (int)ray_off[vt];
+    nr = (int)ray_off[vt + 1] - r0;
   }
   if (nr <= 0) return;
 
   float px[RPT], py[RPT], Tr[RPT], C0[RPT], C1[RPT], C2[RPT];
-  uint32_t mask[RPT];
+  uint32_t mask[RPT], nev[RPT], nbl[RPT];
+  int64_t gid[RPT];
   bool live[RPT];
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int idx = threadIdx.x + j * kThreads;
-    live[j] = idx < nr;
+    const bool valid = idx < nr;
     int lx = 0, ly = 0;
     mask[j] = 0;
-    if (live[j]) {
+    if (valid) {
       if (STD) {
         ly = idx / cw;
         lx = idx - ly * cw;
@@ -74,12 +77,24 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
     }
     px[j] = (float)(ox + lx) + 0.5f;
     py[j] = (float)(oy + ly) + 0.5f;
+    gid[j] = STD ? ((int64_t)v * bc.H + oy + ly) * bc.W + ox + lx : (int64_t)r0 + idx;
     Tr[j] = 1.0f;
     C0[j] = C1[j] = C2[j] = 0.0f;
+    live[j] = valid;
+    if (valid && !bk.first) {
+      // transmittance carries the ray's state in its sign: negative once the ray has terminated
+      const float4 st = state[gid[j]];
+      live[j] = !signbit(st.x);
+      Tr[j] = fabsf(st.x);
+      C0[j] = st.y;
+      C1[j] = st.z;
+      C2[j] = st.w;
+    }
+    nev[j] = nbl[j] = 0;
   }
   const float q_cut = bc.q_cut, a_min = bc.alpha_min, a_max = bc.alpha_max, t_min = bc.t_min;
-  const uint32_t ls = tile_start[(int64_t)vl * bc.T + t];
-  const uint32_t le = tile_start[(int64_t)vl * bc.T + t + 1];
+  const uint32_t ls = tile_start[vt];
+  const uint32_t le = tile_start[vt + 1];
   const float4* vrec = rec + (int64_t)v * bc.G * kRecF4;
 
   for (uint32_t base = ls; base < le; base += kThreads) {
@@ -97,30 +112,28 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
     for (int j = 0; j < RPT; ++j) any |= live[j];
     if (__ballot(any) != 0ull) {
       for (int k = 0; k < n; ++k) {
-        const float4 A = sm[k * kRecF4 + 0];  // u, v, conic a, conic b
-        const float4 B = sm[k * kRecF4 + 1];  // conic c, opacity, r, g
+        const float4 A = sm[k * kRecF4 + 0];    // u, v, conic a, conic b
+        const float4 B = sm[k * kRecF4 + 1];    // conic c, opacity, r, g
         const float bb = sm[k * kRecF4 + 2].x;  // b (blue)
         bool any_live = false;
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-          if (!live[j]) continue;
+          // per-pixel rule and front-to-back update, without branches
           const float dx = px[j] - A.x, dy = py[j] - A.y;
           const float q = fmaf(A.z * dx, dx, fmaf(2.0f * A.w * dx, dy, B.x * dy * dy));
-          if (q <= q_cut) {
-            const float alpha = fminf(a_max, B.y * __expf(-0.5f * q));
-            if (alpha >= a_min) {
-              const float tn = Tr[j] * (1.0f - alpha);
-              if (tn < t_min) {
-                live[j] = false;
-              } else {
-                const float w = alpha * Tr[j];
-                C0[j] = fmaf(w, B.z, C0[j]);
-                C1[j] = fmaf(w, B.w, C1[j]);
-                C2[j] = fmaf(w, bb, C2[j]);
-                Tr[j] = tn;
-              }
-            }
-          }
+          const float alpha = fminf(a_max, B.y * __expf(-0.5f * q));
+          const bool ok = live[j] && (q <= q_cut) && (alpha >= a_min);
+          const float tn = Tr[j] * (1.0f - alpha);
+          const bool stop = ok && (tn < t_min);
+          const bool take = ok && !stop;
+          nev[j] += live[j] ? 1u : 0u;
+          nbl[j] += take ? 1u : 0u;
+          live[j] = live[j] && !stop;
+          const float w = take ? alpha * Tr[j] : 0.0f;
+          C0[j] = fmaf(w, B.z, C0[j]);
+          C1[j] = fmaf(w, B.w, C1[j]);
+          C2[j] = fmaf(w, bb, C2[j]);
+          Tr[j] = take ? tn : Tr[j];
           any_live |= live[j];
         }
         if (__ballot(any_live) == 0ull) break;
@@ -131,39 +144,77 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
     for (int j = 0; j < RPT; ++j) mine |= live[j];
     if (!__syncthreads_or(mine)) break;
   }
+  bool mine = false;
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) mine |= live[j];
+  const bool tile_live = __syncthreads_or(mine);
+  if (!tile_live && threadIdx.x == 0) alive[vt] = 0;
+
+  if (bc.stats) {
+    unsigned long long e = 0, b = 0, r = 0;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      e += nev[j];
+      b += nbl[j];
+      r += (bk.first && threadIdx.x + j * kThreads < nr) ? 1 : 0;
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+      e += __shfl_xor(e, d, 64);
+      b += __shfl_xor(b, d, 64);
+      r += __shfl_xor(r, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      // spread over slots: same-address atomics from every wavefront would serialise
+      unsigned long long* slot = bc.stats + 3 * ((blockIdx.x * 4 + (threadIdx.x >> 6)) % kStatSlots);
+      atomicAdd(&slot[0], e);
+      atomicAdd(&slot[1], b);
+      atomicAdd(&slot[2], r);
+    }
+  }
 
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int idx = threadIdx.x + j * kThreads;
     if (idx >= nr) continue;
-    const int xr = (int)(py[j] - 0.5f), yc = (int)(px[j] - 0.5f);
-    const float c[3] = {fmaf(Tr[j], bc.bg[0], C0[j]), fmaf(Tr[j], bc.bg[1], C1[j]), fmaf(Tr[j], bc.bg[2], C2[j])};
-    if (STD) {
-      float* dst = out + (((int64_t)v * bc.H + xr) * bc.W + yc) * 3;
-      dst[0] = c[0];
-      dst[1] = c[1];
-      dst[2] = c[2];
-    } else {
-      float* dst = out + ((int64_t)xr * bc.W + yc) * 3;
+    if (!bk.last && tile_live) state[gid[j]] = make_float4(live[j] ? Tr[j] : -Tr[j], C0[j], C1[j], C2[j]);
+    if (bk.last || !tile_live) {
+      const int xr = (int)(py[j] - 0.5f), yc = (int)(px[j] - 0.5f);
+      const float c[3] = {fmaf(Tr[j], bc.bg[0], C0[j]), fmaf(Tr[j], bc.bg[1], C1[j]),
+                          fmaf(Tr[j], bc.bg[2], C2[j])};
+      if (STD) {
+        float* dst = out + (((int64_t)v * bc.H + xr) * bc.W + yc) * 3;
+        dst[0] = c[0];
+        dst[1] = c[1];
+        dst[2] = c[2];
+      } else {
+        float* dst = out + ((int64_t)xr * bc.W + yc) * 3;
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        if (mask[j] & (1u << k)) dst[k] = c[k];
+        for (int k = 0; k < 3; ++k)
+          if (mask[j] & (1u << k)) dst[k] = c[k];
+      }
     }
   }
 }
 
 template <bool STD>
 hipError_t launch_rpt(int rpt, unsigned nblocks, const float4* rec, const uint32_t* tile_start, const uint32_t* gidx,
-                      const uint32_t* ray_off, const uint32_t* ray_ent, const BlendConst& bc, float* out,
-                      hipStream_t s) {
+                      const uint32_t* ray_off, const uint32_t* ray_ent, const BlendConst& bc, BlendChunk bk,
+                      uint8_t* alive, float4* state, float* out, hipStream_t s) {
+#define DL_BLEND_CASE(R)                                                                                        \
+  case R:                                                                                                      \
+    hipLaunchKernelGGL((blend_kernel<STD, R>), dim3(nblocks), dim3(kThreads), 0, s, rec, tile_start, gidx,    \
+                       ray_off, ray_ent, bc, bk, alive, state, out);                                           \
+    break;
   switch (rpt) {
-    case 1: hipLaunchKernelGGL((blend_kernel<STD, 1>), dim3(nblocks), dim3(kThreads), 0, s, rec, tile_start, gidx, ray_off, ray_ent, bc, out); break;
-    case 2: hipLaunchKernelGGL((blend_kernel<STD, 2>), dim3(nblocks), dim3(kThreads), 0, s, rec, tile_start, gidx, ray_off, ray_ent, bc, out); break;
-    case 4: hipLaunchKernelGGL((blend_kernel<STD, 4>), dim3(nblocks), dim3(kThreads), 0, s, rec, tile_start, gidx, ray_off, ray_ent, bc, out); break;
-    case 8: hipLaunchKernelGGL((blend_kernel<STD, 8>), dim3(nblocks), dim3(kThreads), 0, s, rec, tile_start, gidx, ray_off, ray_ent, bc, out); break;
-    case 16: hipLaunchKernelGGL((blend_kernel<STD, 16>), dim3(nblocks), dim3(kThreads), 0, s, rec, tile_start, gidx, ray_off, ray_ent, bc, out); break;
-    default: return hipErrorInvalidValue;
+    DL_BLEND_CASE(1)
+    DL_BLEND_CASE(2)
+    DL_BLEND_CASE(4)
+    DL_BLEND_CASE(8)
+    DL_BLEND_CASE(16)
+    default:
+      return hipErrorInvalidValue;
   }
+#undef DL_BLEND_CASE
   return hipGetLastError();
 }
 
@@ -177,17 +228,21 @@ int rpt_for(int max_rays) {
 
 hipError_t launch_blend_directl(const float4* rec, const uint32_t* tile_start, const uint32_t* gidx,
                                 const uint32_t* ray_off, const uint32_t* ray_ent, int max_rays,
-                                const BlendConst& bc, float* out, hipStream_t s) {
-  const unsigned nb = (unsigned)((int64_t)bc.nv * bc.T);
+                                const BlendConst& bc, BlendChunk bk, uint8_t* alive, float4* state, float* out,
+                                hipStream_t s) {
+  const unsigned nb = (unsigned)((int64_t)bc.N * bc.T);
   if (nb == 0) return hipSuccess;
-  return launch_rpt<false>(rpt_for(max_rays), nb, rec, tile_start, gidx, ray_off, ray_ent, bc, out, s);
+  return launch_rpt<false>(rpt_for(max_rays), nb, rec, tile_start, gidx, ray_off, ray_ent, bc, bk, alive, state, out,
+                           s);
 }
 
 hipError_t launch_blend_standard(const float4* rec, const uint32_t* tile_start, const uint32_t* gidx,
-                                 const BlendConst& bc, float* views, hipStream_t s) {
-  const unsigned nb = (unsigned)((int64_t)bc.nv * bc.T);
+                                 const BlendConst& bc, BlendChunk bk, uint8_t* alive, float4* state, float* views,
+                                 hipStream_t s) {
+  const unsigned nb = (unsigned)((int64_t)bc.N * bc.T);
   if (nb == 0) return hipSuccess;
-  return launch_rpt<true>(rpt_for(bc.tw * bc.th), nb, rec, tile_start, gidx, nullptr, nullptr, bc, views, s);
+  return launch_rpt<true>(rpt_for(bc.tw * bc.th), nb, rec, tile_start, gidx, nullptr, nullptr, bc, bk, alive, state,
+                          views, s);
 }
 
 }  // namespace dl

@@ -38,10 +38,24 @@ struct BlendConst {
   int W, H;
   int tw, th, ntx, nty;  // tile size and tile grid of the panel
   int T;                 // ntx * nty
+  int N;                 // views
   int64_t G;             // record stride per view
-  int v0, nv;            // first view and number of views of this batch
   float q_cut, alpha_min, alpha_max, t_min;
   float bg[3];
+  unsigned long long* stats;  // optional work counters, kStatSlots x {evaluations, blends, rays}
+};
+constexpr int kStatSlots = 1024;
+
+// Depth chunk: ranks [n_v num_lo / den, n_v num_hi / den) of every view; `stride` bounds its length.
+struct ChunkArgs {
+  int64_t num_lo, num_hi, den;
+  int64_t stride;
+  uint32_t cap;  // key capacity
+};
+
+// Per-chunk blend flags
+struct BlendChunk {
+  int first, last;
 };
 
 // ---- view map and ray lists (viewmap.hip) ----
@@ -53,18 +67,22 @@ hipError_t launch_interleave(const uint8_t* V, const float* views, float* out, i
 
 // ---- scans, radix sort, ranges (sort.hip) ----
 int64_t scan_partial_count(int64_t n);
-// exclusive scan of n uint32 (in may equal out); `partial` holds scan_partial_count(n) + 1 entries.
+// exclusive scan of n uint32 (in may equal out); `partial` holds scan_partial_count(n) + 1 entries and
+// receives the grand total in partial[scan_partial_count(n)].
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, hipStream_t s);
-int64_t radix_hist_size(int64_t seg_len, int n_seg, int digit_bits);
-// Stable LSD sort of n_seg consecutive segments of seg_len (key, value) pairs by key bits [bit_lo, bit_hi),
-// each segment independently.  Ping-pongs between (k0, v0) and (k1, v1); returns true when the result ends
-// in (k1, v1).  `hist` needs radix_hist_size() entries, `partial` scan_partial_count(that) + 1.
+int64_t radix_hist_size(int64_t seg_len, int n_seg);
+// Stable LSD sort of n_seg segments (static length seg_len, live length seg_n[s] clamped to cap when seg_n is
+// given) of (key, value) pairs by key bits [bit_lo, bit_hi), each segment independently.  Ping-pongs between
+// (k0, v0) and (k1, v1); returns true when the result ends in (k1, v1).
 bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
-                    int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial, hipStream_t s, hipError_t* err);
+                    const uint32_t* seg_n, uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial,
+                    hipStream_t s, hipError_t* err);
 bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
-                    int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial, hipStream_t s, hipError_t* err);
-// start[k] = first index j with keys[j] >= k, for k in [0, n_keys]
-hipError_t launch_lower_bounds(const uint32_t* keys, int64_t n, uint32_t* start, int64_t n_keys, hipStream_t s);
+                    const uint32_t* seg_n, uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial,
+                    hipStream_t s, hipError_t* err);
+// start[k] = first index j < n with keys[j] >= k, for k in [0, n_keys]; n = min(*n_dev, cap) or n_static
+hipError_t launch_lower_bounds(const uint32_t* keys, const uint32_t* n_dev, uint32_t cap, int64_t n_static,
+                               uint32_t* start, int64_t n_keys, hipStream_t s);
 
 // ---- projection (project.hip) ----
 hipError_t launch_project(const float* soa, const double* cams, const ProjConst& pc, float4* rec, uint64_t* keys,
@@ -74,20 +92,28 @@ hipError_t launch_scene_transpose(const float* means, const float* log_scales, c
                                   hipStream_t s);
 
 // ---- binning (bin.hip) ----
-// counts[vl][r] = tiles touched by the r-th nearest visible Gaussian of view v0 + vl; totals[vl] += sum.
+// counts[v][i] = live tiles touched by the Gaussian of depth rank lo_c(v) + i of view v; *total += sum.
 hipError_t launch_bin_count(const float4* rec, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                            const BlendConst& bc, uint32_t* counts, unsigned long long* totals, hipStream_t s);
+                            const BlendConst& bc, const ChunkArgs& ch, const uint8_t* alive, uint32_t* counts,
+                            unsigned long long* total, hipStream_t s);
 hipError_t launch_bin_emit(const float4* rec, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                           const BlendConst& bc, const uint32_t* offsets, uint32_t n_keys, uint32_t* keys,
-                           uint32_t* vals, hipStream_t s);
+                           const BlendConst& bc, const ChunkArgs& ch, const uint8_t* alive, const uint32_t* offsets,
+                           uint32_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_finalize_count(const unsigned long long* total, uint32_t cap, uint32_t* n_out,
+                                 unsigned long long* max_total, hipStream_t s);
+hipError_t launch_init_alive(uint8_t* alive, const uint32_t* ray_off, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
 
 // ---- blending (blend.hip) ----
-// DirectL: rays of (view, tile) from ray lists; writes owned channels of out[H][W][3].
+// DirectL: rays of (view, tile) from ray lists; writes owned channels of out[H][W][3]; per-ray state
+// (signed transmittance, colour) carried between depth chunks in `state`.
 hipError_t launch_blend_directl(const float4* rec, const uint32_t* tile_start, const uint32_t* gidx,
                                 const uint32_t* ray_off, const uint32_t* ray_ent, int max_rays,
-                                const BlendConst& bc, float* out, hipStream_t s);
+                                const BlendConst& bc, BlendChunk bk, uint8_t* alive, float4* state, float* out,
+                                hipStream_t s);
 // Standard: all pixels of each (view, tile); writes views[v][H][W][3].
 hipError_t launch_blend_standard(const float4* rec, const uint32_t* tile_start, const uint32_t* gidx,
-                                 const BlendConst& bc, float* views, hipStream_t s);
+                                 const BlendConst& bc, BlendChunk bk, uint8_t* alive, float4* state, float* views,
+                                 hipStream_t s);
 
 }  // namespace dl

@@ -1,11 +1,13 @@
 // Host runtime of the light-field renderer: the C ABI of include/directl.h on top of the gfx950 kernels.
 //
 // Frame (both paths):
-//   cameras (FP64, host)  -> project (all views)  -> per-view depth sort (segmented radix sort, 48-bit keys)
-//   -> count tiles per (view, Gaussian) -> [per view batch: scan -> emit (view, tile) keys -> stable radix
-//   partition by key -> list bounds -> blend] ; the standard path then interlaces its N views (Alg. 1).
-// Views are processed in batches whose key count fits the key buffers; batches are formed on the host after
-// one readback of the per-view key totals.
+//   cameras (FP64, host) -> project (all views) -> per-view depth sort (segmented radix sort, 48-bit keys)
+//   -> for each depth chunk, front to back: count keys of live (view, tile) pairs -> scan -> emit
+//      (view, tile) keys -> stable radix partition by key -> list bounds -> blend (carrying per-ray state,
+//      retiring tiles whose rays have all terminated)
+//   ; the standard path then interlaces its N views (Alg. 1).
+// Every launch has a static grid; data-dependent sizes (visible counts, key counts) stay on the device.  The
+// only host synchronisation is the end-of-frame check that no chunk overflowed the key capacity.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -98,9 +100,49 @@ struct RayLists {
 
 struct dl_ctx {
   int device = 0;
-  DevBuf cams, rec, k64[2], v32[2], vis, counts, totals, bk[2], bv[2], hist, partial, tstart, views;
+  DevBuf cams, rec, k64[2], v32[2], vis, counts, bk[2], bv[2], hist, partial, tstart, views, stats, alive, state,
+      dtotal, nkeys;
+  uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
   double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
-  size_t free_at_create = 0;
+  // profiling: HIP events around each stage of the last frame, and work counters
+  bool prof = false;
+  struct Mark {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  std::vector<Mark> marks;
+  int64_t keys = 0, visible = 0;
+  int batches = 0, tile_w = 0, tile_h = 0, rpt = 0;
+  ~dl_ctx() {
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+  }
+  hipEvent_t ev() {
+    if (evused == evpool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      evpool.push_back(e);
+    }
+    return evpool[evused++];
+  }
+  void frame_begin() {
+    evused = 0;
+    marks.clear();
+    keys = visible = 0;
+    batches = 0;
+  }
+  int begin(int stage, hipStream_t s) {
+    if (!prof) return -1;
+    Mark m{stage, ev(), ev()};
+    if (!m.a || !m.b) return -1;
+    (void)hipEventRecord(m.a, s);
+    marks.push_back(m);
+    return (int)marks.size() - 1;
+  }
+  void end(int i, hipStream_t s) {
+    if (i >= 0) (void)hipEventRecord(marks[i].b, s);
+  }
 };
 
 struct dl_scene {
@@ -231,18 +273,18 @@ int build_ray_lists(dl_display* D, int tw, int th, hipStream_t s, RayLists** out
   };
   if (k0.ensure(n * 4) || v0.ensure(n * 4) || k1.ensure(n * 4) || v1.ensure(n * 4))
     return cleanup_fail(DL_ENOMEM, "ray list buffers");
-  const int64_t hs = radix_hist_size(n, 1, 8);
+  const int64_t hs = radix_hist_size(n, 1);
   if (hist.ensure(hs * 4) || part.ensure((scan_partial_count(hs) + 2) * 4) || L->off.ensure((NT + 1) * 4))
     return cleanup_fail(DL_ENOMEM, "ray list buffers");
   hipError_t e = launch_rays_emit(D->V.as<uint8_t>(), d.width, d.height, tw, th, L->ntx, L->T, k0.as<uint32_t>(),
                                   v0.as<uint32_t>(), s);
   if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
-  bool fl = radix_sort_u32(k0.as<uint32_t>(), v0.as<uint32_t>(), k1.as<uint32_t>(), v1.as<uint32_t>(), n, 1, 0, bits,
-                           hist.as<uint32_t>(), part.as<uint32_t>(), s, &e);
+  bool fl = radix_sort_u32(k0.as<uint32_t>(), v0.as<uint32_t>(), k1.as<uint32_t>(), v1.as<uint32_t>(), n, 1, nullptr,
+                           0, 0, bits, hist.as<uint32_t>(), part.as<uint32_t>(), s, &e);
   if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
   uint32_t* sk = fl ? k1.as<uint32_t>() : k0.as<uint32_t>();
   DevBuf& sv = fl ? v1 : v0;
-  e = launch_lower_bounds(sk, n, L->off.as<uint32_t>(), NT, s);
+  e = launch_lower_bounds(sk, nullptr, 0, n, L->off.as<uint32_t>(), NT, s);
   if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
   std::vector<uint32_t> off(NT + 1);
   e = hipMemcpyAsync(off.data(), L->off.p, (NT + 1) * 4, hipMemcpyDeviceToHost, s);
@@ -274,34 +316,66 @@ Tiles make_tiles(const dl_display_desc& d, int tw, int th) {
   return t;
 }
 
-// Shared frame: cameras, projection, depth sort, per-view tile counts.  Leaves the sorted Gaussian indices
-// in *sorted and the per-view key totals on the host.
-int frame_front(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose, const dl_render_opts& o,
-                const Tiles& tl, hipStream_t s, uint32_t** sorted, std::vector<unsigned long long>& totals,
-                ProjConst& pc) {
+// Depth chunks (fractions of each view's visible depth ranks, in 1/1024): front chunks are small so that most
+// tiles terminate before the bulk of the keys would be produced.
+constexpr int kChunkDen = 1024;
+constexpr int kChunkBounds[] = {0, 64, 128, 256, 512, 1024};
+constexpr int kChunks = sizeof(kChunkBounds) / sizeof(kChunkBounds[0]) - 1;
+constexpr uint32_t kMaxKeyCap = 0x7fffffffu;
+
+int64_t chunk_stride(int64_t G, int c) { return G * (kChunkBounds[c + 1] - kChunkBounds[c]) / kChunkDen + 1; }
+
+// One frame of either path: cameras, projection, depth sort, then per depth chunk: count live (view, tile)
+// keys, scan, emit, partition by (view, tile), list bounds, blend.  Returns DL_ECAP (with *need set) if a
+// chunk produced more keys than the capacity; the caller grows it and renders again.
+int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose, const dl_render_opts& o,
+                 const Tiles& tl, bool standard, const RayLists* L, float* out, hipStream_t s,
+                 unsigned long long* need) {
   const dl_display_desc& d = D->desc;
   const int N = d.n_views;
   const int64_t G = S->n;
   int rc = make_cameras(d, pose, C->cams_host);
   if (rc) return rc;
-  HIP_TRY(C->cams.ensure((size_t)N * kCamDoubles * 8));
   const int64_t NG = (int64_t)N * G;
   if (NG >= (1ll << 32) - 1) return fail(DL_EINVAL, "views x Gaussians exceeds 2^32");
+  const int64_t NT = (int64_t)N * tl.T;
+  if (NT >= (1ll << 31)) return fail(DL_EINVAL, "too many (view, tile) lists");
+  if (C->key_cap == 0) C->key_cap = (uint32_t)std::min<int64_t>(kMaxKeyCap, std::max<int64_t>(1 << 22, 2 * NG));
+  const uint32_t cap = C->key_cap;
+  const int64_t nstate = standard ? (int64_t)N * d.width * d.height : L->n_rays;
+  const int64_t max_stride = chunk_stride(G, kChunks - 1) + 64;
+  HIP_TRY(C->cams.ensure((size_t)N * kCamDoubles * 8));
   HIP_TRY(C->rec.ensure((size_t)NG * kRecF4 * 16));
   HIP_TRY(C->k64[0].ensure((size_t)NG * 8));
   HIP_TRY(C->k64[1].ensure((size_t)NG * 8));
   HIP_TRY(C->v32[0].ensure((size_t)NG * 4));
   HIP_TRY(C->v32[1].ensure((size_t)NG * 4));
   HIP_TRY(C->vis.ensure(256 * 4));
-  HIP_TRY(C->counts.ensure((size_t)NG * 4));
-  HIP_TRY(C->totals.ensure(256 * 8));
-  const int64_t hs = radix_hist_size(G, N, 8);
+  HIP_TRY(C->counts.ensure((size_t)N * max_stride * 4));
+  HIP_TRY(C->bk[0].ensure((size_t)cap * 4));
+  HIP_TRY(C->bk[1].ensure((size_t)cap * 4));
+  HIP_TRY(C->bv[0].ensure((size_t)cap * 4));
+  HIP_TRY(C->bv[1].ensure((size_t)cap * 4));
+  HIP_TRY(C->tstart.ensure((size_t)(NT + 1) * 4));
+  HIP_TRY(C->alive.ensure((size_t)NT));
+  HIP_TRY(C->state.ensure((size_t)std::max<int64_t>(nstate, 1) * 16));
+  HIP_TRY(C->dtotal.ensure(2 * 8));
+  HIP_TRY(C->nkeys.ensure(4));
+  const int64_t hs = std::max(radix_hist_size(G, N), radix_hist_size(cap, 1));
   HIP_TRY(C->hist.ensure((size_t)hs * 4));
-  HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, NG)) + 2) * 4));
+  HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, N * max_stride)) + 2) * 4));
+  if (C->prof) HIP_TRY(C->stats.ensure((size_t)kStatSlots * 3 * 8));
 
+  C->frame_begin();
+  int mk = C->begin(DL_STAGE_UPLOAD, s);
   HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(C->vis.p, 0, 256 * 4, s));
-  HIP_TRY(hipMemsetAsync(C->totals.p, 0, 256 * 8, s));
+  HIP_TRY(launch_fill_u64(C->dtotal.as<unsigned long long>(), 2, 0ull, s));
+  if (C->prof) HIP_TRY(launch_fill_u64(C->stats.as<unsigned long long>(), kStatSlots * 3, 0ull, s));
+  HIP_TRY(launch_init_alive(C->alive.as<uint8_t>(), standard ? nullptr : L->off.as<uint32_t>(), NT, s));
+  C->end(mk, s);
+
+  ProjConst pc{};
   pc.G = G;
   pc.n_pad = S->n_pad;
   pc.N = N;
@@ -316,14 +390,19 @@ int frame_front(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose
   pc.alpha_min = o.alpha_min;
   pc.alpha_max = o.alpha_max;
   pc.dilation = o.dilation;
+  mk = C->begin(DL_STAGE_PROJECT, s);
   HIP_TRY(launch_project(S->soa.as<float>(), C->cams.as<double>(), pc, C->rec.as<float4>(), C->k64[0].as<uint64_t>(),
                          C->v32[0].as<uint32_t>(), nullptr, C->vis.as<uint32_t>(), s));
+  C->end(mk, s);
   hipError_t e;
+  mk = C->begin(DL_STAGE_DEPTH_SORT, s);
   bool fl = radix_sort_u64(C->k64[0].as<uint64_t>(), C->v32[0].as<uint32_t>(), C->k64[1].as<uint64_t>(),
-                           C->v32[1].as<uint32_t>(), G, N, 0, 48, C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s,
-                           &e);
+                           C->v32[1].as<uint32_t>(), G, N, nullptr, 0, 0, 48, C->hist.as<uint32_t>(),
+                           C->partial.as<uint32_t>(), s, &e);
   if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
-  *sorted = fl ? C->v32[1].as<uint32_t>() : C->v32[0].as<uint32_t>();
+  C->end(mk, s);
+  const uint32_t* sorted = fl ? C->v32[1].as<uint32_t>() : C->v32[0].as<uint32_t>();
+
   BlendConst bc{};
   bc.W = d.width;
   bc.H = d.height;
@@ -332,92 +411,92 @@ int frame_front(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose
   bc.ntx = tl.ntx;
   bc.nty = tl.nty;
   bc.T = tl.T;
+  bc.N = N;
   bc.G = G;
-  bc.v0 = 0;
-  bc.nv = N;
-  HIP_TRY(launch_bin_count(C->rec.as<float4>(), *sorted, C->vis.as<uint32_t>(), bc, C->counts.as<uint32_t>(),
-                           C->totals.as<unsigned long long>(), s));
-  totals.assign(N, 0);
-  HIP_TRY(hipMemcpyAsync(totals.data(), C->totals.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  return DL_OK;
-}
-
-size_t key_capacity(dl_ctx* C) {
-  size_t fr = 0, tot = 0;
-  if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)8 << 30;
-  // keys + values, double-buffered: 16 B per key; keep the current key buffers' size as available
-  size_t have = C->bk[0].cap + C->bk[1].cap + C->bv[0].cap + C->bv[1].cap;
-  size_t budget = (size_t)((fr + have) * 0.6);
-  size_t cap = budget / 16;
-  return std::min<size_t>(cap, (size_t)0x7fffffff);
-}
-
-// Per view batch: scan counts, emit keys, partition by (view, tile), list bounds, blend.
-int frame_batches(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_render_opts& o, const Tiles& tl,
-                  uint32_t* sorted, const std::vector<unsigned long long>& totals, bool standard, const RayLists* L,
-                  float* out, hipStream_t s) {
-  const dl_display_desc& d = D->desc;
-  const int N = d.n_views;
-  const int64_t G = S->n;
-  const size_t cap = key_capacity(C);
-  int v0 = 0;
-  while (v0 < N) {
-    size_t K = 0;
-    int v1 = v0;
-    while (v1 < N && K + totals[v1] <= cap) K += totals[v1++];
-    if (v1 == v0) return fail(DL_ENOMEM, "one view's tile keys exceed the key buffer capacity");
-    const int nv = v1 - v0;
-    BlendConst bc{};
-    bc.W = d.width;
-    bc.H = d.height;
-    bc.tw = tl.tw;
-    bc.th = tl.th;
-    bc.ntx = tl.ntx;
-    bc.nty = tl.nty;
-    bc.T = tl.T;
-    bc.G = G;
-    bc.v0 = v0;
-    bc.nv = nv;
-    bc.q_cut = o.q_cut;
-    bc.alpha_min = o.alpha_min;
-    bc.alpha_max = o.alpha_max;
-    bc.t_min = o.t_min;
-    for (int k = 0; k < 3; ++k) bc.bg[k] = o.bg[k];
-    const int64_t nkeys = (int64_t)nv * tl.T;
-    int bits = 1;
-    while ((1ll << bits) < nkeys) ++bits;
-    HIP_TRY(C->bk[0].ensure(std::max<size_t>(K, 1) * 4));
-    HIP_TRY(C->bk[1].ensure(std::max<size_t>(K, 1) * 4));
-    HIP_TRY(C->bv[0].ensure(std::max<size_t>(K, 1) * 4));
-    HIP_TRY(C->bv[1].ensure(std::max<size_t>(K, 1) * 4));
-    HIP_TRY(C->tstart.ensure((size_t)(nkeys + 1) * 4));
-    const int64_t hs = radix_hist_size((int64_t)K, 1, 8);
-    HIP_TRY(C->hist.ensure((size_t)std::max<int64_t>(hs, 1) * 4));
-    HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, (int64_t)nv * G)) + 2) * 4));
-    uint32_t* offs = C->counts.as<uint32_t>() + (int64_t)v0 * G;
-    HIP_TRY(exclusive_scan_u32(offs, offs, (int64_t)nv * G, C->partial.as<uint32_t>(), s));
-    HIP_TRY(launch_bin_emit(C->rec.as<float4>(), sorted, C->vis.as<uint32_t>(), bc, offs, (uint32_t)K,
-                            C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), s));
-    hipError_t e = hipSuccess;
-    bool fl = false;
-    if (K > 0)
-      fl = radix_sort_u32(C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), C->bk[1].as<uint32_t>(),
-                          C->bv[1].as<uint32_t>(), (int64_t)K, 1, 0, bits, C->hist.as<uint32_t>(),
-                          C->partial.as<uint32_t>(), s, &e);
+  bc.q_cut = o.q_cut;
+  bc.alpha_min = o.alpha_min;
+  bc.alpha_max = o.alpha_max;
+  bc.t_min = o.t_min;
+  for (int k = 0; k < 3; ++k) bc.bg[k] = o.bg[k];
+  bc.stats = C->prof ? C->stats.as<unsigned long long>() : nullptr;
+  int bits = 1;
+  while ((1ll << bits) < NT) ++bits;
+  unsigned long long* total = C->dtotal.as<unsigned long long>();
+  for (int c = 0; c < kChunks; ++c) {
+    ChunkArgs ch;
+    ch.num_lo = kChunkBounds[c];
+    ch.num_hi = kChunkBounds[c + 1];
+    ch.den = kChunkDen;
+    ch.stride = chunk_stride(G, c);
+    ch.cap = cap;
+    const int64_t ncount = (int64_t)N * ch.stride;
+    mk = C->begin(DL_STAGE_BIN_COUNT, s);
+    HIP_TRY(launch_fill_u64(total, 1, 0ull, s));
+    HIP_TRY(launch_bin_count(C->rec.as<float4>(), sorted, C->vis.as<uint32_t>(), bc, ch, C->alive.as<uint8_t>(),
+                             C->counts.as<uint32_t>(), total, s));
+    C->end(mk, s);
+    mk = C->begin(DL_STAGE_SCAN, s);
+    HIP_TRY(exclusive_scan_u32(C->counts.as<uint32_t>(), C->counts.as<uint32_t>(), ncount, C->partial.as<uint32_t>(), s));
+    HIP_TRY(launch_finalize_count(total, cap, C->nkeys.as<uint32_t>(), total + 1, s));
+    C->end(mk, s);
+    mk = C->begin(DL_STAGE_BIN_EMIT, s);
+    HIP_TRY(launch_bin_emit(C->rec.as<float4>(), sorted, C->vis.as<uint32_t>(), bc, ch, C->alive.as<uint8_t>(),
+                            C->counts.as<uint32_t>(), C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), s));
+    C->end(mk, s);
+    mk = C->begin(DL_STAGE_TILE_SORT, s);
+    bool f2 = radix_sort_u32(C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), C->bk[1].as<uint32_t>(),
+                             C->bv[1].as<uint32_t>(), cap, 1, C->nkeys.as<uint32_t>(), cap, 0, bits,
+                             C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s, &e);
     if (e != hipSuccess) return fail(DL_EHIP, std::string("tile sort: ") + hipGetErrorString(e));
-    uint32_t* skeys = fl ? C->bk[1].as<uint32_t>() : C->bk[0].as<uint32_t>();
-    uint32_t* svals = fl ? C->bv[1].as<uint32_t>() : C->bv[0].as<uint32_t>();
-    HIP_TRY(launch_lower_bounds(skeys, (int64_t)K, C->tstart.as<uint32_t>(), nkeys, s));
+    C->end(mk, s);
+    uint32_t* skeys = f2 ? C->bk[1].as<uint32_t>() : C->bk[0].as<uint32_t>();
+    uint32_t* svals = f2 ? C->bv[1].as<uint32_t>() : C->bv[0].as<uint32_t>();
+    mk = C->begin(DL_STAGE_BOUNDS, s);
+    HIP_TRY(launch_lower_bounds(skeys, C->nkeys.as<uint32_t>(), cap, 0, C->tstart.as<uint32_t>(), NT, s));
+    C->end(mk, s);
+    BlendChunk bk{c == 0, c == kChunks - 1};
+    mk = C->begin(DL_STAGE_BLEND, s);
     if (standard) {
-      HIP_TRY(launch_blend_standard(C->rec.as<float4>(), C->tstart.as<uint32_t>(), svals, bc, out, s));
+      HIP_TRY(launch_blend_standard(C->rec.as<float4>(), C->tstart.as<uint32_t>(), svals, bc, bk,
+                                    C->alive.as<uint8_t>(), C->state.as<float4>(), out, s));
     } else {
       HIP_TRY(launch_blend_directl(C->rec.as<float4>(), C->tstart.as<uint32_t>(), svals, L->off.as<uint32_t>(),
-                                   L->ent.as<uint32_t>(), L->max_rays, bc, out, s));
+                                   L->ent.as<uint32_t>(), L->max_rays, bc, bk, C->alive.as<uint8_t>(),
+                                   C->state.as<float4>(), out, s));
     }
-    v0 = v1;
+    C->end(mk, s);
+  }
+  unsigned long long mx = 0;
+  std::vector<uint32_t> vis(N, 0);
+  HIP_TRY(hipMemcpyAsync(&mx, total + 1, 8, hipMemcpyDeviceToHost, s));
+  if (C->prof) HIP_TRY(hipMemcpyAsync(vis.data(), C->vis.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  C->keys = (int64_t)mx;
+  for (int v = 0; v < N; ++v) C->visible += vis[v];
+  if (mx > cap) {
+    *need = mx;
+    return DL_ECAP;
   }
   return DL_OK;
+}
+
+// Render with the context's key buffers, growing them once if a depth chunk overflowed.
+int render_grow(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose, const dl_render_opts& o,
+                const Tiles& tl, bool standard, const RayLists* L, float* out, hipStream_t s) {
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    unsigned long long need = 0;
+    int rc = render_frame(C, S, D, pose, o, tl, standard, L, out, s, &need);
+    if (rc != DL_ECAP) return rc;
+    if (need > kMaxKeyCap) return fail(DL_ENOMEM, "a depth chunk needs more than 2^31 tile keys");
+    const unsigned long long want = std::min<unsigned long long>(kMaxKeyCap, need + need / 4 + 1024);
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+      const size_t have = C->bk[0].cap + C->bk[1].cap + C->bv[0].cap + C->bv[1].cap;
+      if ((size_t)want * 16 > fr + have) return fail(DL_ENOMEM, "tile key buffers do not fit in device memory");
+    }
+    C->key_cap = (uint32_t)want;
+  }
+  return fail(DL_ECAP, "tile key capacity kept overflowing");
 }
 
 int check_common(dl_ctx* C, const dl_scene* S, const dl_display* D) {
@@ -635,11 +714,57 @@ int dl_render(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* 
   if ((rc = build_ray_lists(const_cast<dl_display*>(D), tw, th, s, &L))) return rc;
   if (L->max_rays > 16 * 256) return fail(DL_EINVAL, "tile too large: more than 4096 rays of one view");
   Tiles tl = make_tiles(D->desc, tw, th);
-  uint32_t* sorted = nullptr;
-  std::vector<unsigned long long> totals;
-  ProjConst pc{};
-  if ((rc = frame_front(C, S, D, pose, o, tl, s, &sorted, totals, pc))) return rc;
-  return frame_batches(C, S, D, o, tl, sorted, totals, false, L, out_dev, s);
+  C->tile_w = tw;
+  C->tile_h = th;
+  C->rpt = (L->max_rays + 255) / 256;
+  return render_grow(C, S, D, pose, o, tl, false, L, out_dev, s);
+}
+
+int dl_set_key_capacity(dl_ctx* C, int64_t keys) {
+  if (!C) return fail(DL_EINVAL, "NULL context");
+  if (keys < 1 || keys > (int64_t)kMaxKeyCap) return fail(DL_EINVAL, "key capacity must be in [1, 2^31)");
+  C->key_cap = (uint32_t)keys;
+  return DL_OK;
+}
+
+int64_t dl_key_capacity(const dl_ctx* C) { return C ? (int64_t)C->key_cap : -1; }
+
+int dl_set_profiling(dl_ctx* C, int enable) {
+  if (!C) return fail(DL_EINVAL, "NULL context");
+  C->prof = enable != 0;
+  return DL_OK;
+}
+
+int dl_frame_stats_get(dl_ctx* C, dl_frame_stats* out) {
+  if (!C || !out) return fail(DL_EINVAL, "NULL argument");
+  std::memset(out, 0, sizeof *out);
+  if (!C->prof) return fail(DL_EINVAL, "profiling is off");
+  for (const auto& m : C->marks) {
+    HIP_TRY(hipEventSynchronize(m.b));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, m.a, m.b));
+    if (m.stage >= 0 && m.stage < DL_NSTAGES) {
+      out->stage_ms[m.stage] += ms;
+      out->stage_launches[m.stage] += 1;
+    }
+  }
+  unsigned long long st[3] = {0, 0, 0};
+  if (C->stats.p) {
+    std::vector<unsigned long long> sl((size_t)kStatSlots * 3);
+    HIP_TRY(hipMemcpy(sl.data(), C->stats.p, sl.size() * 8, hipMemcpyDeviceToHost));
+    for (int i = 0; i < kStatSlots; ++i)
+      for (int k = 0; k < 3; ++k) st[k] += sl[(size_t)i * 3 + k];
+  }
+  out->keys = C->keys;
+  out->visible = C->visible;
+  out->evaluations = (int64_t)st[0];
+  out->blends = (int64_t)st[1];
+  out->rays = (int64_t)st[2];
+  out->batches = C->batches;
+  out->tile_w = C->tile_w;
+  out->tile_h = C->tile_h;
+  out->rays_per_lane = C->rpt;
+  return DL_OK;
 }
 
 int dl_interleave(const dl_display* D, const float* views_dev, float* out_dev, void* stream) {
@@ -666,12 +791,13 @@ int dl_render_standard(dl_ctx* C, const dl_scene* S, const dl_display* D, const 
     views = C->views.as<float>();
   }
   Tiles tl = make_tiles(d, tw, th);
-  uint32_t* sorted = nullptr;
-  std::vector<unsigned long long> totals;
-  ProjConst pc{};
-  if ((rc = frame_front(C, S, D, pose, o, tl, s, &sorted, totals, pc))) return rc;
-  if ((rc = frame_batches(C, S, D, o, tl, sorted, totals, true, nullptr, views, s))) return rc;
+  C->tile_w = tw;
+  C->tile_h = th;
+  C->rpt = (tw * th + 255) / 256;
+  if ((rc = render_grow(C, S, D, pose, o, tl, true, nullptr, views, s))) return rc;
+  int mk = C->begin(DL_STAGE_INTERLEAVE, s);
   HIP_TRY(launch_interleave(D->V.as<uint8_t>(), views, out_dev, d.width, d.height, s));
+  C->end(mk, s);
   return DL_OK;
 }
 

@@ -1,20 +1,28 @@
-// Device exclusive scan and stable LSD radix sort (64-wide wavefronts, LDS ranking) for gfx950.
+// Device exclusive scan and stable LSD radix sort for gfx950 (64-wide wavefronts, LDS ranking).
 //
-// The sort orders each of n_seg equal-length segments independently: block histograms are laid out
-// [segment][digit][block-in-segment], so one exclusive scan of the whole histogram array yields, for every
-// block and digit, the output position of that block's first item with that digit -- the segment stays
-// the most significant key.  Ranking within a block is stable: items are taken in 256-item chunks in
-// order, and inside a wavefront the lanes holding the same digit are found with one ballot per digit bit.
+// Sort structure: n_seg segments of static length seg_len, each sorted independently; the live length of a
+// segment may be given on the device (seg_n), so that launches have static grids (graph capture) while the
+// work follows the data.  A fixed number of blocks per segment each own one contiguous range of the segment.
+// Per pass:
+//   hist    : per block, counts of each digit (per-wavefront LDS counters, then summed)
+//   scan    : one exclusive scan over hist laid out [segment][digit][block] gives every block's first output
+//             position for every digit (the segment stays the most significant key)
+//   scatter : per block, 4096-item tiles; each wavefront ranks its quarter of the tile with one ballot per
+//             digit bit (stable: lane order, then row order, then wavefront order), the tile is reordered by
+//             digit in LDS, and written out as contiguous runs per digit.
 #include "dl_internal.h"
 
 namespace dl {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
 constexpr int kScanIPT = 16;
-constexpr int kScanTile = kThreads * kScanIPT;  // items per scan block
-constexpr int kSortIPT = 16;
-constexpr int kSortTile = kThreads * kSortIPT;  // items per sort block
+constexpr int kScanTile = kThreads * kScanIPT;
+constexpr int kRows = 16;                        // rows of 64 items per wavefront per tile
+constexpr int kTile = kThreads * kRows;          // 4096 items per tile
+constexpr int kMaxBits = 8;
+constexpr int kMaxRadix = 1 << kMaxBits;
 
 __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
 #pragma unroll
@@ -25,16 +33,15 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
   return x;
 }
 
-// Exclusive scan of one value per thread across a 256-thread block; returns the block total in *total.
 __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* total) {
-  __shared__ uint32_t wsum[kThreads / 64];
+  __shared__ uint32_t wsum[kWaves];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint32_t inc = wave_incl_scan(x, lane);
   if (lane == 63) wsum[w] = inc;
   __syncthreads();
   uint32_t before = 0, tot = 0;
 #pragma unroll
-  for (int i = 0; i < kThreads / 64; ++i) {
+  for (int i = 0; i < kWaves; ++i) {
     if (i < w) before += wsum[i];
     tot += wsum[i];
   }
@@ -55,7 +62,6 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* _
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-// Single block: exclusive scan of the block totals in place; partial[np] receives the grand total.
 __global__ __launch_bounds__(kThreads) void scan_partials_kernel(uint32_t* __restrict__ partial, int64_t np) {
   uint32_t carry = 0;
   for (int64_t base = 0; base < np; base += kThreads) {
@@ -88,95 +94,167 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* in,
   }
 }
 
-template <typename K>
-__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const K* __restrict__ keys, int64_t seg_len,
-                                                                int blocks_per_seg, int shift, int bits,
-                                                                uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[256];
-  const int radix = 1 << bits;
-  const uint32_t dmask = (uint32_t)radix - 1;
-  for (int d = threadIdx.x; d < radix; d += kThreads) h[d] = 0;
-  __syncthreads();
-  const int seg = blockIdx.x / blocks_per_seg;
-  const int bis = blockIdx.x - seg * blocks_per_seg;
-  const int64_t seg_base = (int64_t)seg * seg_len;
-  const int64_t lo = seg_base + (int64_t)bis * kSortTile;
-  const int64_t hi = min(lo + (int64_t)kSortTile, seg_base + seg_len);
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-    const uint32_t d = (uint32_t)(keys[i] >> shift) & dmask;
-    atomicAdd(&h[d], 1u);
-  }
-  __syncthreads();
-  for (int d = threadIdx.x; d < radix; d += kThreads)
-    hist[((int64_t)seg * radix + d) * blocks_per_seg + bis] = h[d];
+// Range [lo, hi) of block `bis` within a segment whose live length is n (ranges are whole tiles).
+__device__ inline void block_range(int64_t n, int bps, int bis, int64_t& lo, int64_t& hi) {
+  int64_t per = (n + bps - 1) / bps;
+  per = (per + kTile - 1) / kTile * kTile;
+  lo = min((int64_t)bis * per, n);
+  hi = min(lo + per, n);
 }
 
 template <typename K>
-__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const K* __restrict__ kin,
-                                                                   const uint32_t* __restrict__ vin,
-                                                                   K* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                                   int64_t seg_len, int blocks_per_seg, int shift,
-                                                                   int bits, const uint32_t* __restrict__ hist) {
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[kThreads / 64][256];
-  const int radix = 1 << bits;
+struct SortArgs {
+  const K* kin;
+  const uint32_t* vin;
+  K* kout;
+  uint32_t* vout;
+  int64_t seg_len;
+  const uint32_t* seg_n;  // device live lengths (nullptr: seg_len)
+  uint32_t cap;           // clamp of device lengths
+  int bps;                // blocks per segment
+  int shift, bits;
+  uint32_t* hist;
+};
+
+template <typename K>
+__device__ inline int64_t live_len(const SortArgs<K>& a, int seg) {
+  if (!a.seg_n) return a.seg_len;
+  return min((int64_t)min(a.seg_n[seg], a.cap), a.seg_len);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void radix_hist_kernel(SortArgs<K> a) {
+  __shared__ uint32_t h[kWaves][kMaxRadix];
+  const int radix = 1 << a.bits;
+  const uint32_t dmask = (uint32_t)radix - 1;
+  const int w = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < radix; d += kThreads)
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) h[i][d] = 0;
+  __syncthreads();
+  const int seg = blockIdx.x / a.bps;
+  const int bis = blockIdx.x - seg * a.bps;
+  int64_t lo, hi;
+  block_range(live_len(a, seg), a.bps, bis, lo, hi);
+  const K* kin = a.kin + (int64_t)seg * a.seg_len;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+    const uint32_t d = (uint32_t)(kin[i] >> a.shift) & dmask;
+    atomicAdd(&h[w][d], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < radix; d += kThreads) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) s += h[i][d];
+    a.hist[((int64_t)seg * radix + d) * a.bps + bis] = s;
+  }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) {
+  __shared__ uint32_t run[kMaxRadix];          // next global position per digit
+  __shared__ uint32_t wc[kWaves][kMaxRadix];   // per-wavefront digit counts within the tile
+  __shared__ uint32_t loff[kMaxRadix];         // tile-local start per digit
+  __shared__ K skey[kTile];
+  __shared__ uint32_t sval[kTile];
+  const int radix = 1 << a.bits;
   const uint32_t dmask = (uint32_t)radix - 1;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int seg = blockIdx.x / blocks_per_seg;
-  const int bis = blockIdx.x - seg * blocks_per_seg;
-  const int64_t seg_base = (int64_t)seg * seg_len;
-  const int64_t lo = seg_base + (int64_t)bis * kSortTile;
-  const int64_t hi = min(lo + (int64_t)kSortTile, seg_base + seg_len);
-  for (int d = threadIdx.x; d < radix; d += kThreads) {
-    run[d] = hist[((int64_t)seg * radix + d) * blocks_per_seg + bis];
-#pragma unroll
-    for (int i = 0; i < kThreads / 64; ++i) wcnt[i][d] = 0;
-  }
-  __syncthreads();
+  const int seg = blockIdx.x / a.bps;
+  const int bis = blockIdx.x - seg * a.bps;
+  int64_t lo, hi;
+  block_range(live_len(a, seg), a.bps, bis, lo, hi);
+  const K* kin = a.kin + (int64_t)seg * a.seg_len;
+  const uint32_t* vin = a.vin + (int64_t)seg * a.seg_len;
+  K* kout = a.kout + (int64_t)seg * a.seg_len;
+  uint32_t* vout = a.vout + (int64_t)seg * a.seg_len;
+  // the scan runs over all segments; subtract the segment's first offset so positions are segment-relative
+  const uint32_t seg0 = a.hist[(int64_t)seg * radix * a.bps];
+  for (int d = threadIdx.x; d < radix; d += kThreads)
+    run[d] = a.hist[((int64_t)seg * radix + d) * a.bps + bis] - seg0;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int64_t c = lo; c < hi; c += kThreads) {
-    const int64_t idx = c + threadIdx.x;
-    const bool valid = idx < hi;
-    K key = 0;
-    uint32_t val = 0, d = 0;
-    if (valid) {
-      key = kin[idx];
-      val = vin[idx];
-      d = (uint32_t)(key >> shift) & dmask;
-    }
-    uint64_t m = __ballot(valid);
-    for (int b = 0; b < bits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bal = __ballot(bit);
-      m &= bit ? bal : ~bal;
-    }
-    const uint32_t lrank = (uint32_t)__popcll(m & below);
-    if (valid && lrank == 0) wcnt[w][d] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = run[d] + lrank;
-      for (int i = 0; i < w; ++i) pos += wcnt[i][d];
-      kout[pos] = key;
-      vout[pos] = val;
-    }
-    __syncthreads();
-    for (int dd = threadIdx.x; dd < radix; dd += kThreads) {
-      uint32_t add = 0;
+
+  for (int64_t t0 = lo; t0 < hi; t0 += kTile) {
+    const int tn = (int)min((int64_t)kTile, hi - t0);
+    for (int d = threadIdx.x; d < radix; d += kThreads)
 #pragma unroll
-      for (int i = 0; i < kThreads / 64; ++i) {
-        add += wcnt[i][dd];
-        wcnt[i][dd] = 0;
+      for (int i = 0; i < kWaves; ++i) wc[i][d] = 0;
+    __syncthreads();
+    // wavefront w ranks items [w * 1024, (w + 1) * 1024) of the tile, 64 at a time, in order
+    K key[kRows];
+    uint32_t val[kRows], dig[kRows], rnk[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const int li = w * (kRows * 64) + r * 64 + lane;
+      const bool valid = li < tn;
+      key[r] = valid ? kin[t0 + li] : (K)0;
+      val[r] = valid ? vin[t0 + li] : 0u;
+      const uint32_t d = (uint32_t)(key[r] >> a.shift) & dmask;
+      dig[r] = d;
+      uint64_t m = __ballot(valid);
+      for (int b = 0; b < a.bits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        m &= bit ? bal : ~bal;
       }
-      run[dd] += add;
+      const uint32_t lr = (uint32_t)__popcll(m & below);
+      const uint32_t base = valid ? wc[w][d] : 0u;
+      rnk[r] = valid ? base + lr : 0xffffffffu;
+      if (valid && lr == 0) wc[w][d] = base + (uint32_t)__popcll(m);
     }
+    __syncthreads();
+    // tile-local digit offsets (exclusive scan over digits) and per-wavefront bases
+    uint32_t tot = 0;
+    if (threadIdx.x < radix) {
+#pragma unroll
+      for (int i = 0; i < kWaves; ++i) tot += wc[i][threadIdx.x];
+    }
+    uint32_t total;
+    uint32_t ex = block_excl_scan(threadIdx.x < radix ? tot : 0u, &total);
+    if (radix > kThreads) {
+      // radix <= 256 == kThreads always; kept for clarity
+    }
+    if (threadIdx.x < radix) {
+      loff[threadIdx.x] = ex;
+      uint32_t acc = ex;
+#pragma unroll
+      for (int i = 0; i < kWaves; ++i) {
+        const uint32_t c = wc[i][threadIdx.x];
+        wc[i][threadIdx.x] = acc;  // becomes the tile-local base of wavefront i for this digit
+        acc += c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      if (rnk[r] != 0xffffffffu) {
+        const uint32_t p = wc[w][dig[r]] + rnk[r];
+        skey[p] = key[r];
+        sval[p] = val[r];
+      }
+    }
+    __syncthreads();
+    // contiguous runs per digit: consecutive lanes write consecutive addresses
+    for (int p = threadIdx.x; p < tn; p += kThreads) {
+      const K k = skey[p];
+      const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
+      const uint32_t g = run[d] + (uint32_t)p - loff[d];
+      kout[g] = k;
+      vout[g] = sval[p];
+    }
+    __syncthreads();
+    if (threadIdx.x < radix) run[threadIdx.x] += tot;
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(kThreads) void lower_bounds_kernel(const uint32_t* __restrict__ keys, int64_t n,
-                                                                  uint32_t* __restrict__ start, int64_t n_keys) {
+__global__ __launch_bounds__(kThreads) void lower_bounds_kernel(const uint32_t* __restrict__ keys,
+                                                                  const uint32_t* __restrict__ n_dev, uint32_t cap,
+                                                                  int64_t n_static, uint32_t* __restrict__ start,
+                                                                  int64_t n_keys) {
   const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (k > n_keys) return;
+  const int64_t n = n_dev ? (int64_t)min(*n_dev, cap) : n_static;
   int64_t lo = 0, hi = n;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
@@ -186,29 +264,48 @@ __global__ __launch_bounds__(kThreads) void lower_bounds_kernel(const uint32_t* 
   start[k] = (uint32_t)lo;
 }
 
+int blocks_per_seg(int64_t seg_len, int n_seg) {
+  // enough blocks to fill the chip (~2048 in flight), never more than one per tile of the segment
+  int64_t tiles = (seg_len + kTile - 1) / kTile;
+  int64_t want = (2048 + n_seg - 1) / n_seg;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, want));
+}
+
 template <typename K>
-bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, int n_seg, int bit_lo, int bit_hi,
-                     uint32_t* hist, uint32_t* partial, hipStream_t s, hipError_t* err) {
+bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, int n_seg, const uint32_t* seg_n,
+                     uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial, hipStream_t s,
+                     hipError_t* err) {
   *err = hipSuccess;
-  const int blocks_per_seg = (int)((seg_len + kSortTile - 1) / kSortTile);
-  const int64_t nblocks = (int64_t)blocks_per_seg * n_seg;
+  if (seg_len == 0 || n_seg == 0 || bit_hi <= bit_lo) return false;
+  const int bps = blocks_per_seg(seg_len, n_seg);
+  const int64_t nblocks = (int64_t)bps * n_seg;
+  // split the bit range into the fewest passes of at most 8 bits, as even as possible
+  const int nbits = bit_hi - bit_lo;
+  const int passes = (nbits + kMaxBits - 1) / kMaxBits;
   bool flipped = false;
-  if (seg_len == 0 || n_seg == 0) return false;
-  for (int shift = bit_lo; shift < bit_hi; shift += 8) {
-    const int bits = (bit_hi - shift) < 8 ? (bit_hi - shift) : 8;
-    const int64_t hsize = (int64_t)n_seg * (1 << bits) * blocks_per_seg;
-    K* ki = flipped ? k1 : k0;
-    uint32_t* vi = flipped ? v1 : v0;
-    K* ko = flipped ? k0 : k1;
-    uint32_t* vo = flipped ? v0 : v1;
-    hipLaunchKernelGGL(radix_hist_kernel<K>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, ki, seg_len,
-                       blocks_per_seg, shift, bits, hist);
+  int shift = bit_lo;
+  for (int p = 0; p < passes; ++p) {
+    const int bits = (nbits - (shift - bit_lo) + (passes - p) - 1) / (passes - p);
+    SortArgs<K> a;
+    a.kin = flipped ? k1 : k0;
+    a.vin = flipped ? v1 : v0;
+    a.kout = flipped ? k0 : k1;
+    a.vout = flipped ? v0 : v1;
+    a.seg_len = seg_len;
+    a.seg_n = seg_n;
+    a.cap = cap;
+    a.bps = bps;
+    a.shift = shift;
+    a.bits = bits;
+    a.hist = hist;
+    const int64_t hsize = (int64_t)n_seg * (1 << bits) * bps;
+    hipLaunchKernelGGL(radix_hist_kernel<K>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
     if ((*err = hipGetLastError()) != hipSuccess) return flipped;
     if ((*err = exclusive_scan_u32(hist, hist, hsize, partial, s)) != hipSuccess) return flipped;
-    hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, ki, vi, ko, vo,
-                       seg_len, blocks_per_seg, shift, bits, hist);
+    hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
     if ((*err = hipGetLastError()) != hipSuccess) return flipped;
     flipped = !flipped;
+    shift += bits;
   }
   return flipped;
 }
@@ -226,24 +323,28 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
   return hipGetLastError();
 }
 
-int64_t radix_hist_size(int64_t seg_len, int n_seg, int digit_bits) {
-  const int64_t bps = (seg_len + kSortTile - 1) / kSortTile;
-  return bps * n_seg * (1 << digit_bits);
+int64_t radix_hist_size(int64_t seg_len, int n_seg) {
+  return (int64_t)blocks_per_seg(seg_len, n_seg) * n_seg * kMaxRadix;
 }
 
-bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg, int bit_lo,
-                    int bit_hi, uint32_t* hist, uint32_t* partial, hipStream_t s, hipError_t* err) {
-  return radix_sort_impl<uint64_t>(k0, v0, k1, v1, seg_len, n_seg, bit_lo, bit_hi, hist, partial, s, err);
+bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
+                    const uint32_t* seg_n, uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial,
+                    hipStream_t s, hipError_t* err) {
+  return radix_sort_impl<uint64_t>(k0, v0, k1, v1, seg_len, n_seg, seg_n, cap, bit_lo, bit_hi, hist, partial, s,
+                                   err);
 }
 
-bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t seg_len, int n_seg, int bit_lo,
-                    int bit_hi, uint32_t* hist, uint32_t* partial, hipStream_t s, hipError_t* err) {
-  return radix_sort_impl<uint32_t>(k0, v0, k1, v1, seg_len, n_seg, bit_lo, bit_hi, hist, partial, s, err);
+bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
+                    const uint32_t* seg_n, uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial,
+                    hipStream_t s, hipError_t* err) {
+  return radix_sort_impl<uint32_t>(k0, v0, k1, v1, seg_len, n_seg, seg_n, cap, bit_lo, bit_hi, hist, partial, s,
+                                   err);
 }
 
-hipError_t launch_lower_bounds(const uint32_t* keys, int64_t n, uint32_t* start, int64_t n_keys, hipStream_t s) {
+hipError_t launch_lower_bounds(const uint32_t* keys, const uint32_t* n_dev, uint32_t cap, int64_t n_static,
+                               uint32_t* start, int64_t n_keys, hipStream_t s) {
   hipLaunchKernelGGL(lower_bounds_kernel, dim3((unsigned)((n_keys + 1 + kThreads - 1) / kThreads)), dim3(kThreads),
-                     0, s, keys, n, start, n_keys);
+                     0, s, keys, n_dev, cap, n_static, start, n_keys);
   return hipGetLastError();
 }
 

@@ -78,6 +78,25 @@ def test_directl_equals_standard_paradigm_bitwise(ctx):
         assert np.array_equal(std2.cpu().numpy(), std), (tw, th)
 
 
+def test_key_capacity_overflow_regrows(ctx):
+    """A depth chunk with more tile keys than the buffers hold is detected on the device; the frame is
+    rendered again with larger buffers and equals the frame rendered with ample capacity."""
+    from paper_2407_14053_amd import api
+    d = synth.make_named_display("tiny")
+    sc = synth.make_scene("tiny")
+    S = api.Scene(ctx, sc.arrays())
+    D = api.Display(ctx, d)
+    c2w = synth.pose_sweep(8)[2]
+    ref = api.render(ctx, S, D, c2w).cpu().numpy()
+    ctx.set_key_capacity(100)
+    img = api.render(ctx, S, D, c2w).cpu().numpy()
+    assert ctx.key_capacity() > 100
+    assert np.array_equal(img, ref)
+    ctx.set_key_capacity(100)
+    std, _ = api.render_standard(ctx, S, D, c2w)
+    assert np.array_equal(std.cpu().numpy(), ref)
+
+
 def test_deterministic(ctx):
     from paper_2407_14053_amd import api
     d = synth.make_named_display("tiny")
