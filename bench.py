@@ -114,6 +114,8 @@ def run_gpu(args):
         "p99_ms": round(percentile(frame_ms, 99), 3),
         "stage_ms": {k: round(v, 4) for k, v in st_ms.items() if v > 0},
         "work": {k: int(v) for k, v in cnt.items()},
+        "chunk_ms": [{k: round(sum(s_["chunk_ms"][c].get(k, 0.0) for s_ in stages) / len(stages), 4)
+                      for k in stages[0]["chunk_ms"][c]} for c in range(len(stages[0]["chunk_ms"]))],
     }
 
     # roofline of the dominant kernel (largest per-frame stage time, one launch per frame for these)
@@ -148,11 +150,12 @@ def run_gpu(args):
     res["roofline"] = roof
 
     if not args.no_standard:
-        # the standard paradigm on the same kernels: all 45 full views at 16x16 tiles, then Alg. 1
+        # the standard paradigm on the same kernels: all 45 full views at its best tile (32x32), then Alg. 1
         out_std = torch.empty_like(out)
         api.render_standard(ctx, S, D, poses[0], out=out_std)
         torch.cuda.synchronize()
-        ms = []
+        ms, sst = [], []
+        ctx.set_profiling(True)
         ts0 = time.perf_counter()
         for i in range(args.std_steps):
             e0 = torch.cuda.Event(enable_timing=True)
@@ -160,16 +163,22 @@ def run_gpu(args):
             e0.record(stream)
             api.render_standard(ctx, S, D, poses[(args.warmup + i) % len(poses)], out=out_std)
             e1.record(stream)
+            sst.append(ctx.frame_stats())
             e1.synchronize()
             ms.append(e0.elapsed_time(e1))
         torch.cuda.synchronize()
         ts1 = time.perf_counter()
+        ctx.set_profiling(False)
+        std_stage, std_cnt = mean_stats(sst)
         std_fps = args.std_steps / (ts1 - ts0)
         # the last standard frame and a DirectL frame of the same pose agree bit for bit
         api.render(ctx, S, D, poses[(args.warmup + args.std_steps - 1) % len(poses)], opts=opts, out=out)
         same = bool(torch.equal(out, out_std))
         res["standard"] = {"frames_per_s": round(std_fps, 4), "ms_per_frame": round(1000 * (ts1 - ts0) / args.std_steps, 2),
-                           "steps": args.std_steps, "tile": [16, 16], "bit_identical_to_directl": same}
+                           "steps": args.std_steps, "tile": [sst[0]["tile_w"], sst[0]["tile_h"]],
+                           "bit_identical_to_directl": same,
+                           "stage_ms": {k: round(v, 3) for k, v in std_stage.items() if v > 0},
+                           "work": {k: int(v) for k, v in std_cnt.items()}}
         res["speedup_vs_standard"] = round(fps / std_fps, 2)
         print("standard: %.3f frames/s" % std_fps, file=sys.stderr, flush=True)
     S.close()

@@ -79,8 +79,8 @@ typedef struct {
  * front to back by depth (ties by Gaussian index) and the walk stops before a Gaussian whose blend would take
  * the transmittance below t_min (Eq. (5)-(6)).  dilation is added to the diagonal of Sigma' (Eq. (9)).
  * bg is the background colour weighted by the final transmittance.  sh_degree in [0, 3].
- * tile_w/tile_h: screen tile of the blend (0 = automatic: about 256 owned rays per tile for dl_render,
- * 16x16 for dl_render_standard). */
+ * tile_w/tile_h: screen tile of the blend (0 = automatic: about 900 owned rays per tile for dl_render,
+ * 32x32 for dl_render_standard). */
 typedef struct {
   float z_near, q_cut, alpha_min, alpha_max, t_min, dilation;
   float bg[3];
@@ -128,8 +128,10 @@ int64_t dl_display_num_rays(const dl_display* display);
 int dl_cameras(const dl_display* display, const dl_pose* pose, double* out_host);
 
 /* Projection only (Eq. (8)-(9) and the SH colour), for inspection: out_dev[N][n][12] float32 =
- * (u, v, conic a, b, c, opacity, r, g, b, q_limit, ext_x, ext_y) with conic [[a, b], [b, c]] the inverse of
- * Sigma', (u, v) the projected mean in image coordinates; depth_dev[N][n] float64 = camera z, or NaN when
+ * (u, v, A, B, C, Q_limit, ext_x, ext_y, opacity, r, g, b) where (u, v) is the projected mean in image
+ * coordinates and A = a log2(e)/2, B = b log2(e), C = c log2(e)/2 for the conic [[a, b], [b, c]] = Sigma'^-1
+ * (so that exp(-q/2) = 2^-(A dx^2 + B dx dy + C dy^2)); Q_limit is the tile-test cutoff on the same scale
+ * and (ext_x, ext_y) the half extents of that ellipse in pixels; depth_dev[N][n] float64 = camera z, or NaN when
  * the Gaussian cannot reach any pixel centre of that view (behind z_near, alpha always below alpha_min, or
  * its cutoff ellipse misses the screen). */
 int dl_project(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
@@ -177,11 +179,14 @@ enum {
  * keys: the largest number of (view, tile) list entries of one depth chunk; visible: (view, Gaussian) pairs
  * that reach the screen;
  * evaluations: (ray, list entry) pairs the blend examined; blends: pairs composited; rays: rays rendered. */
+#define DL_MAX_CHUNKS 8
 typedef struct {
   double stage_ms[DL_NSTAGES];
   int32_t stage_launches[DL_NSTAGES];
   int64_t keys, visible, evaluations, blends, rays;
   int32_t batches, tile_w, tile_h, rays_per_lane;
+  int32_t chunks;                               /* depth chunks of the frame */
+  double chunk_ms[DL_MAX_CHUNKS][DL_NSTAGES];   /* stage_ms split by depth chunk (frame-level stages in 0) */
 } dl_frame_stats;
 
 /* Turn per-stage HIP-event timing and work counters on or off for subsequent frames of this context. */

@@ -54,7 +54,8 @@ class dl_frame_stats(ctypes.Structure):
     _fields_ = [("stage_ms", ctypes.c_double * NSTAGES), ("stage_launches", ctypes.c_int32 * NSTAGES),
                 ("keys", ctypes.c_int64), ("visible", ctypes.c_int64), ("evaluations", ctypes.c_int64),
                 ("blends", ctypes.c_int64), ("rays", ctypes.c_int64), ("batches", ctypes.c_int32),
-                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("rays_per_lane", ctypes.c_int32)]
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("rays_per_lane", ctypes.c_int32),
+                ("chunks", ctypes.c_int32), ("chunk_ms", (ctypes.c_double * NSTAGES) * 8)]
 
 
 _P = ctypes.c_void_p
@@ -181,6 +182,8 @@ class Context:
                                          "tile_h", "rays_per_lane")}
         d["stage_ms"] = {STAGES[i]: st.stage_ms[i] for i in range(NSTAGES)}
         d["stage_launches"] = {STAGES[i]: st.stage_launches[i] for i in range(NSTAGES)}
+        d["chunk_ms"] = [{STAGES[i]: st.chunk_ms[c][i] for i in range(NSTAGES) if st.chunk_ms[c][i] > 0}
+                         for c in range(st.chunks)]
         return d
 
     def close(self):

@@ -1,6 +1,6 @@
 // Tile binning of the depth-sorted projected Gaussians of each view, one depth chunk at a time (gfx950).
 //
-// Input order is (view, depth rank), so emitting (key = view * T + tile, value = Gaussian) pairs in that
+// Input order is (view, depth rank), so emitting (key = view * T + tile, value = rank) pairs in that
 // order and then partitioning them by key with a stable radix sort yields every (view, tile) list already in
 // front-to-back order: the depth digits were sorted before the Gaussians were duplicated into tiles.
 //
@@ -22,7 +22,7 @@ struct TileRange {
 
 __device__ inline bool tile_range(const float* r, const BlendConst& bc, TileRange& tr) {
   // columns y whose centre y + 0.5 lies within [u - ext_x, u + ext_x], widened by one pixel
-  const float u = r[0], v = r[1], ex = r[10], ey = r[11];
+  const float u = r[0], v = r[1], ex = r[6], ey = r[7];
   int y0 = (int)ceilf(u - ex - 0.5f), y1 = (int)floorf(u + ex - 0.5f);
   int x0 = (int)ceilf(v - ey - 0.5f), x1 = (int)floorf(v + ey - 0.5f);
   y0 = max(y0 - 1, 0); y1 = min(y1 + 1, bc.W - 1);
@@ -33,41 +33,63 @@ __device__ inline bool tile_range(const float* r, const BlendConst& bc, TileRang
   return true;
 }
 
-// Minimum over the tile's pixel centres (a rectangle) of q = a dx^2 + 2 b dx dy + c dy^2 about (u, v).
+// Minimum over the tile's pixel centres (a rectangle) of Q = A dx^2 + B dx dy + C dy^2 about (u, v).
 // Zero when the centre lies inside; otherwise the minimum of the convex quadratic sits on an edge, where
-// it is a 1D quadratic minimised at the clamped stationary point (-b dx / c along a vertical edge,
-// -b dy / a along a horizontal one).  ia = 1 / a and ic = 1 / c are precomputed per Gaussian.
-__device__ inline bool tile_touch(const float* r, float ia, float ic, float xlo, float xhi, float ylo, float yhi) {
-  const float u = r[0], v = r[1], a = r[2], b = r[3], c = r[4], qlim = r[9];
+// it is a 1D quadratic minimised at the clamped stationary point (-B dx / 2C along a vertical edge,
+// -B dy / 2A along a horizontal one).  hA = 1 / 2A and hC = 1 / 2C are precomputed per Gaussian.
+__device__ inline bool tile_touch(const float* r, float hA, float hC, float xlo, float xhi, float ylo, float yhi) {
+  const float u = r[0], v = r[1], A = r[2], B = r[3], C = r[4], qlim = r[5];
   const float dxl = xlo - u, dxh = xhi - u, dyl = ylo - v, dyh = yhi - v;
   if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) return true;
   float qmin = 3.0e38f;
   {
     float dx = dxl;
-    float dy = fminf(fmaxf(-b * dx * ic, dyl), dyh);
-    qmin = fminf(qmin, a * dx * dx + 2.0f * b * dx * dy + c * dy * dy);
+    float dy = fminf(fmaxf(-B * dx * hC, dyl), dyh);
+    qmin = fminf(qmin, A * dx * dx + B * dx * dy + C * dy * dy);
     dx = dxh;
-    dy = fminf(fmaxf(-b * dx * ic, dyl), dyh);
-    qmin = fminf(qmin, a * dx * dx + 2.0f * b * dx * dy + c * dy * dy);
+    dy = fminf(fmaxf(-B * dx * hC, dyl), dyh);
+    qmin = fminf(qmin, A * dx * dx + B * dx * dy + C * dy * dy);
   }
   {
     float dy = dyl;
-    float dx = fminf(fmaxf(-b * dy * ia, dxl), dxh);
-    qmin = fminf(qmin, a * dx * dx + 2.0f * b * dx * dy + c * dy * dy);
+    float dx = fminf(fmaxf(-B * dy * hA, dxl), dxh);
+    qmin = fminf(qmin, A * dx * dx + B * dx * dy + C * dy * dy);
     dy = dyh;
-    dx = fminf(fmaxf(-b * dy * ia, dxl), dxh);
-    qmin = fminf(qmin, a * dx * dx + 2.0f * b * dx * dy + c * dy * dy);
+    dx = fminf(fmaxf(-B * dy * hA, dxl), dxh);
+    qmin = fminf(qmin, A * dx * dx + B * dx * dy + C * dy * dy);
   }
   return qmin <= qlim * 1.001f + 1e-3f;
 }
 
-__device__ inline void load_rec(const float4* rec, float* r) {
-  const float4 A = rec[0], B = rec[1], C = rec[2];
+// The geometric half of a record: u, v, A, B, C, Q_limit, ext_x, ext_y.
+__device__ inline void load_rec_geom(const float4* rec, float* r) {
+  const float4 A = rec[0], B = rec[1];
   r[0] = A.x; r[1] = A.y; r[2] = A.z; r[3] = A.w;
   r[4] = B.x; r[5] = B.y; r[6] = B.z; r[7] = B.w;
-  r[8] = C.x; r[9] = C.y; r[10] = C.z; r[11] = C.w;
 }
 
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// Per-wavefront staging of its 64 Gaussians.
+struct WaveBin {
+  float u[64], v[64], A[64], B[64], C[64], qlim[64], hA[64], hC[64];
+  int tx0[64], ty0[64], wr[64];
+  uint32_t pre[64], g[64], run[64], end[64];
+};
+
+// Each wavefront takes 64 consecutive depth ranks of one view (one per lane), computes every Gaussian's
+// tile rectangle, and then walks the flattened list of (Gaussian, tile of its rectangle) pairs 64 at a time,
+// so that a large splat is shared by all lanes instead of stalling one.  COUNT stores the number of live
+// tiles each Gaussian touches; EMIT writes its (view, tile) keys into the range given by the scanned
+// counts (the order inside one Gaussian's range is irrelevant: the stable sort that follows keeps
+// different Gaussians in depth order within every tile).
 template <bool EMIT>
 __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ sorted_idx,
                                                   const uint32_t* __restrict__ vis_count, BlendConst bc, ChunkArgs ch,
@@ -75,58 +97,93 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
                                                   unsigned long long* __restrict__ total,
                                                   const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys,
                                                   uint32_t* __restrict__ vals) {
+  __shared__ WaveBin wb[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  WaveBin& W = wb[w];
   const int v = blockIdx.y;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nv = vis_count[v];
   const int64_t lo = nv * ch.num_lo / ch.den, hi = nv * ch.num_hi / ch.den;
   const int64_t r = lo + idx;
   const int64_t slot = (int64_t)v * ch.stride + idx;
-  uint32_t cnt = 0;
+  uint32_t nt = 0;
+  W.run[lane] = 0;
+  W.end[lane] = 0;
   if (idx < ch.stride && r < hi) {
-    const uint32_t g = sorted_idx[(int64_t)v * bc.G + r];
-    float rr[12];
-    load_rec(rec + ((int64_t)v * bc.G + g) * kRecF4, rr);
+    const uint32_t g = (uint32_t)r;  // records are in depth-rank order; the list entry is the rank
+    float rr[8];
+    load_rec_geom(rec + ((int64_t)v * bc.G + r) * kRecF4, rr);
     TileRange tr;
     if (tile_range(rr, bc, tr)) {
-      const float ia = 1.0f / rr[2], ic = 1.0f / rr[4];
-      uint32_t pos = 0, end = 0;
+      W.u[lane] = rr[0];
+      W.v[lane] = rr[1];
+      W.A[lane] = rr[2];
+      W.B[lane] = rr[3];
+      W.C[lane] = rr[4];
+      W.qlim[lane] = rr[5];
+      W.hA[lane] = 0.5f / rr[2];
+      W.hC[lane] = 0.5f / rr[4];
+      W.tx0[lane] = tr.tx0;
+      W.ty0[lane] = tr.ty0;
+      W.wr[lane] = tr.tx1 - tr.tx0 + 1;
+      W.g[lane] = g;
+      nt = (uint32_t)((tr.tx1 - tr.tx0 + 1) * (tr.ty1 - tr.ty0 + 1));
       if (EMIT) {
         // this Gaussian's keys end where the next slot's begin; nothing is written past the capacity
-        pos = offsets[slot];
+        const uint32_t pos = offsets[slot];
         const uint32_t nxt = slot + 1 < (int64_t)bc.N * ch.stride ? offsets[slot + 1] : 0xffffffffu;
-        end = min(min(nxt, ch.cap), pos + (uint32_t)((tr.tx1 - tr.tx0 + 1) * (tr.ty1 - tr.ty0 + 1)));
+        W.run[lane] = pos;
+        W.end[lane] = min(min(nxt, ch.cap), pos + nt);
       }
-      const uint8_t* al = alive ? alive + (int64_t)v * bc.T : nullptr;
-      for (int ty = tr.ty0; ty <= tr.ty1; ++ty) {
+    }
+  }
+  const uint32_t incl = wave_incl_scan_u32(nt, lane);
+  W.pre[lane] = incl - nt;
+  const uint32_t S = __shfl(incl, 63, 64);
+  __syncthreads();
+
+  const uint8_t* al = alive ? alive + (int64_t)v * bc.T : nullptr;
+  for (uint32_t s0 = 0; s0 < S; s0 += 64) {
+    const uint32_t p = s0 + (uint32_t)lane;
+    if (p < S) {
+      // the Gaussian owning pair p: the last lane i with pre[i] <= p (it has a non-empty rectangle)
+      int i = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1)
+        if (i + step < 64 && W.pre[i + step] <= p) i += step;
+      const int q = (int)(p - W.pre[i]);
+      const int wr = W.wr[i];
+      const int row = q / wr;
+      const int tx = W.tx0[i] + (q - row * wr), ty = W.ty0[i] + row;
+      const int t = ty * bc.ntx + tx;
+      bool hit = !al || al[t];
+      if (hit) {
+        const float xlo = tx * bc.tw + 0.5f, xhi = min((tx + 1) * bc.tw, bc.W) - 0.5f;
         const float ylo = ty * bc.th + 0.5f, yhi = min((ty + 1) * bc.th, bc.H) - 0.5f;
-        for (int tx = tr.tx0; tx <= tr.tx1; ++tx) {
-          const int t = ty * bc.ntx + tx;
-          if (al && !al[t]) continue;
-          const float xlo = tx * bc.tw + 0.5f, xhi = min((tx + 1) * bc.tw, bc.W) - 0.5f;
-          if (!tile_touch(rr, ia, ic, xlo, xhi, ylo, yhi)) continue;
-          if (EMIT) {
-            if (pos < end) {
-              keys[pos] = (uint32_t)v * (uint32_t)bc.T + (uint32_t)t;
-              vals[pos] = g;
-            }
-            ++pos;
-          } else {
-            ++cnt;
-          }
+        const float rr[8] = {W.u[i], W.v[i], W.A[i], W.B[i], W.C[i], W.qlim[i], 0.f, 0.f};
+        hit = tile_touch(rr, W.hA[i], W.hC[i], xlo, xhi, ylo, yhi);
+      }
+      if (hit) {
+        const uint32_t pos = atomicAdd(&W.run[i], 1u);
+        if (EMIT && pos < W.end[i]) {
+          keys[pos] = (uint32_t)v * (uint32_t)bc.T + (uint32_t)t;
+          vals[pos] = W.g[i];
         }
       }
     }
   }
   if (!EMIT) {
+    __syncthreads();
+    const uint32_t cnt = W.run[lane];
     if (idx < ch.stride) counts[slot] = cnt;
     __shared__ unsigned long long part[4];
     unsigned long long x = cnt;
     for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    if (lane == 0) part[w] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
-      const unsigned long long s = part[0] + part[1] + part[2] + part[3];
-      if (s) atomicAdd(total, s);
+      const unsigned long long sum = part[0] + part[1] + part[2] + part[3];
+      if (sum) atomicAdd(total, sum);
     }
   }
 }

@@ -6,7 +6,8 @@
 // staged through LDS 256 records at a time (one coalesced 48-byte record per lane); every lane then reads
 // the records as LDS broadcasts and applies, per ray, the per-pixel rule and Eq. (5)/(10):
 //   q = d^T Sigma'^{-1} d,  alpha = min(alpha_max, o exp(-q/2)),  blend iff q <= q_cut and alpha >= alpha_min,
-//   stop (without blending) when T (1 - alpha) < t_min.
+//   stop (without blending) when T (1 - alpha) < t_min,
+// with q held as Q = q log2(e)/2 (the record's conic is pre-scaled) and exp(-q/2) = 2^-Q (one v_exp_f32).
 // A wavefront leaves the LDS chunk as soon as a ballot shows all its rays finished, and the workgroup
 // leaves the list when none of its lanes has a live ray.  The epilogue writes C + T bg into the owned
 // subpixels of the encoded image (DirectL) or into all three channels of the view image (standard).
@@ -108,20 +109,25 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
     }
     __syncthreads();
     bool any = false;
+    bool slot[RPT];  // wavefront has a live ray in slot j (slots other than the first are often empty)
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) any |= live[j];
+    for (int j = 0; j < RPT; ++j) {
+      any |= live[j];
+      slot[j] = __ballot(live[j]) != 0ull;
+    }
     if (__ballot(any) != 0ull) {
       for (int k = 0; k < n; ++k) {
-        const float4 A = sm[k * kRecF4 + 0];    // u, v, conic a, conic b
-        const float4 B = sm[k * kRecF4 + 1];    // conic c, opacity, r, g
-        const float bb = sm[k * kRecF4 + 2].x;  // b (blue)
+        const float4 A = sm[k * kRecF4 + 0];    // u, v, conic A, B (scaled)
+        const float cC = sm[k * kRecF4 + 1].x;  // conic C (scaled)
+        const float4 B = sm[k * kRecF4 + 2];    // opacity, r, g, b
         bool any_live = false;
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
+          if (j > 0 && !slot[j]) continue;
           // per-pixel rule and front-to-back update, without branches
           const float dx = px[j] - A.x, dy = py[j] - A.y;
-          const float q = fmaf(A.z * dx, dx, fmaf(2.0f * A.w * dx, dy, B.x * dy * dy));
-          const float alpha = fminf(a_max, B.y * __expf(-0.5f * q));
+          const float q = fmaf(A.z * dx, dx, fmaf(cC, dy, A.w * dx) * dy);
+          const float alpha = fminf(a_max, B.x * __builtin_amdgcn_exp2f(-q));
           const bool ok = live[j] && (q <= q_cut) && (alpha >= a_min);
           const float tn = Tr[j] * (1.0f - alpha);
           const bool stop = ok && (tn < t_min);
@@ -130,9 +136,9 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
           nbl[j] += take ? 1u : 0u;
           live[j] = live[j] && !stop;
           const float w = take ? alpha * Tr[j] : 0.0f;
-          C0[j] = fmaf(w, B.z, C0[j]);
-          C1[j] = fmaf(w, B.w, C1[j]);
-          C2[j] = fmaf(w, bb, C2[j]);
+          C0[j] = fmaf(w, B.y, C0[j]);
+          C1[j] = fmaf(w, B.z, C1[j]);
+          C2[j] = fmaf(w, B.w, C2[j]);
           Tr[j] = take ? tn : Tr[j];
           any_live |= live[j];
         }

@@ -17,9 +17,11 @@ constexpr int kRowLogit = 10;    // 1 row
 constexpr int kRowSH = 11;       // 48 rows: coefficient l, channel c at kRowSH + 3 l + c
 constexpr int kSceneRows = 59;
 
-// Projected record of one (view, Gaussian): 12 floats = 3 x float4.
-//   [0] u  [1] v  [2] conic a  [3] conic b  [4] conic c  [5] opacity  [6..8] rgb
-//   [9] q_limit (tile-test cutoff)  [10] ext_x  [11] ext_y (half extents of the cutoff ellipse, px)
+// Projected record of one (view, Gaussian): 12 floats = 3 x float4 (binning reads only the first two).
+//   [0] u  [1] v  [2] A  [3] B  [4] C  [5] Q_limit (tile-test cutoff, same scale as A, B, C)
+//   [6] ext_x  [7] ext_y (half extents of the cutoff ellipse, px)  [8] opacity  [9..11] rgb
+// with A = a log2(e)/2, B = b log2(e), C = c log2(e)/2 for the conic [[a, b], [b, c]] = Sigma'^{-1}, so that
+// Q = A dx^2 + B dx dy + C dy^2 = q log2(e)/2 and o exp(-q/2) = o 2^-Q.
 constexpr int kRecF4 = 3;
 
 // Per-view camera block uploaded for every frame: 16 doubles = rotation rows (9), t (3), eye (3), 0.
@@ -40,7 +42,8 @@ struct BlendConst {
   int T;                 // ntx * nty
   int N;                 // views
   int64_t G;             // record stride per view
-  float q_cut, alpha_min, alpha_max, t_min;
+  float q_cut;  // in the scaled units of the record (q_cut log2(e)/2)
+  float alpha_min, alpha_max, t_min;
   float bg[3];
   unsigned long long* stats;  // optional work counters, kStatSlots x {evaluations, blends, rays}
 };
@@ -86,13 +89,19 @@ hipError_t launch_lower_bounds(const uint32_t* keys, const uint32_t* n_dev, uint
 
 // ---- projection (project.hip) ----
 hipError_t launch_project(const float* soa, const double* cams, const ProjConst& pc, float4* rec, uint64_t* keys,
-                          uint32_t* vals, double* depth_out, uint32_t* vis_count, hipStream_t s);
+                          uint32_t* vals, double* depth_out, hipStream_t s);
+// rec_sorted[v][r] = rec[v][sorted[v][r]] for r < vis_count[v]
+hipError_t launch_gather_records(const float4* rec, const uint32_t* sorted, const uint32_t* vis_count, int64_t G,
+                                 int N, float4* out, hipStream_t s);
+// vis_count[v] = number of visible Gaussians of view v, from its depth-sorted keys
+hipError_t launch_count_visible(const uint64_t* sorted_keys, int64_t G, int N, uint32_t* vis_count, hipStream_t s);
 hipError_t launch_scene_transpose(const float* means, const float* log_scales, const float* quats,
                                   const float* logits, const float* sh, int64_t n, int64_t n_pad, float* soa,
                                   hipStream_t s);
 
 // ---- binning (bin.hip) ----
 // counts[v][i] = live tiles touched by the Gaussian of depth rank lo_c(v) + i of view v; *total += sum.
+// `rec` holds the records in depth-rank order; emitted values are ranks.
 hipError_t launch_bin_count(const float4* rec, const uint32_t* sorted_idx, const uint32_t* vis_count,
                             const BlendConst& bc, const ChunkArgs& ch, const uint8_t* alive, uint32_t* counts,
                             unsigned long long* total, hipStream_t s);

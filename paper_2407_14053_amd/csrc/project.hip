@@ -6,6 +6,8 @@
 // cutoff ellipse, the depth key and the view-dependent colour.  Geometry runs in FP64 (the chip's vector
 // FP64 rate makes this free next to the memory traffic) and the record is rounded to FP32 once, so the
 // FP32 blend starts from correctly rounded inputs; depth keys keep 36 mantissa bits of the FP64 z.
+// The conic is stored pre-multiplied by log2(e)/2 (A, C) and log2(e) (B), so that the blend evaluates
+// alpha = o * 2^-(A dx^2 + B dx dy + C dy^2) with one hardware exp2.
 #include "dl_internal.h"
 
 namespace dl {
@@ -47,8 +49,7 @@ template <int DEG>
 __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ soa, const double* __restrict__ cams,
                                                       ProjConst pc, float4* __restrict__ rec,
                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                      double* __restrict__ depth_out,
-                                                      uint32_t* __restrict__ vis_count) {
+                                                      double* __restrict__ depth_out) {
   constexpr int NB = (DEG + 1) * (DEG + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < pc.G;
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
 #pragma unroll
   for (int k = 0; k < NB * 3; ++k) shc[k] = soa[(kRowSH + k) * np + ii];
 
-  const int lane = threadIdx.x & 63;
+  const double ks = 0.72134752044448170368;  // log2(e) / 2
   for (int v = 0; v < pc.N; ++v) {
     const double* cam = cams + v * kCamDoubles;
     const double X = cam[0] * mx + cam[1] * my + cam[2] * mz + cam[9];
@@ -138,9 +139,9 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
           rgb[c] = fmaxf(acc, 0.0f);
         }
         r[0] = (float)u; r[1] = (float)w;
-        r[2] = (float)(cc * idet); r[3] = (float)(-cb * idet); r[4] = (float)(ca * idet);
-        r[5] = o32; r[6] = rgb[0]; r[7] = rgb[1]; r[8] = rgb[2];
-        r[9] = (float)qlim; r[10] = (float)ex; r[11] = (float)ey;
+        r[2] = (float)(ks * cc * idet); r[3] = (float)(-2.0 * ks * cb * idet); r[4] = (float)(ks * ca * idet);
+        r[5] = (float)(ks * qlim); r[6] = (float)ex; r[7] = (float)ey;
+        r[8] = o32; r[9] = rgb[0]; r[10] = rgb[1]; r[11] = rgb[2];
         uint64_t zb = (uint64_t)__double_as_longlong(Z);
         key = zb >> 16;
       }
@@ -157,9 +158,39 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
       }
       if (depth_out) depth_out[o] = vis ? Z : __longlong_as_double(0x7ff8000000000000ll);
     }
-    const uint64_t b = __ballot(vis);
-    if (lane == 0 && b) atomicAdd(&vis_count[v], (uint32_t)__popcll(b));
   }
+}
+
+// Records in depth order: rec_sorted[v][r] = rec[v][sorted[v][r]] for the n_v visible ranks of view v, so
+// that binning reads consecutive records and the blend's list entries are ranks.
+__global__ __launch_bounds__(256) void gather_records_kernel(const float4* __restrict__ rec,
+                                                             const uint32_t* __restrict__ sorted,
+                                                             const uint32_t* __restrict__ vis_count, int64_t G,
+                                                             float4* __restrict__ out) {
+  const int v = blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (int64_t)vis_count[v]) return;
+  const int64_t o = (int64_t)v * G;
+  const float4* src = rec + (o + sorted[o + r]) * kRecF4;
+  float4* dst = out + (o + r) * kRecF4;
+  dst[0] = src[0];
+  dst[1] = src[1];
+  dst[2] = src[2];
+}
+
+// Visible Gaussians of view v = position of the first culled key (all 48 bits set) in its sorted segment.
+__global__ __launch_bounds__(64) void count_visible_kernel(const uint64_t* __restrict__ sorted_keys, int64_t G, int N,
+                                                           uint32_t* __restrict__ vis_count) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const uint64_t* k = sorted_keys + (int64_t)v * G;
+  int64_t lo = 0, hi = G;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (k[mid] < 0xffffffffffffull) lo = mid + 1;
+    else hi = mid;
+  }
+  vis_count[v] = (uint32_t)lo;
 }
 
 __global__ __launch_bounds__(256) void scene_transpose_kernel(const float* __restrict__ means,
@@ -183,14 +214,27 @@ __global__ __launch_bounds__(256) void scene_transpose_kernel(const float* __res
 }  // namespace
 
 hipError_t launch_project(const float* soa, const double* cams, const ProjConst& pc, float4* rec, uint64_t* keys,
-                          uint32_t* vals, double* depth_out, uint32_t* vis_count, hipStream_t s) {
+                          uint32_t* vals, double* depth_out, hipStream_t s) {
   const dim3 grid((unsigned)((pc.G + 255) / 256));
   switch (pc.sh_degree) {
-    case 0: hipLaunchKernelGGL(project_kernel<0>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, vis_count); break;
-    case 1: hipLaunchKernelGGL(project_kernel<1>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, vis_count); break;
-    case 2: hipLaunchKernelGGL(project_kernel<2>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, vis_count); break;
-    default: hipLaunchKernelGGL(project_kernel<3>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, vis_count); break;
+    case 0: hipLaunchKernelGGL(project_kernel<0>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out); break;
+    case 1: hipLaunchKernelGGL(project_kernel<1>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out); break;
+    case 2: hipLaunchKernelGGL(project_kernel<2>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out); break;
+    default: hipLaunchKernelGGL(project_kernel<3>, grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_records(const float4* rec, const uint32_t* sorted, const uint32_t* vis_count, int64_t G,
+                                 int N, float4* out, hipStream_t s) {
+  hipLaunchKernelGGL(gather_records_kernel, dim3((unsigned)((G + 255) / 256), (unsigned)N), dim3(256), 0, s, rec, sorted,
+                     vis_count, G, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_visible(const uint64_t* sorted_keys, int64_t G, int N, uint32_t* vis_count, hipStream_t s) {
+  hipLaunchKernelGGL(count_visible_kernel, dim3((unsigned)((N + 63) / 64)), dim3(64), 0, s, sorted_keys, G, N,
+                     vis_count);
   return hipGetLastError();
 }
 

@@ -100,16 +100,17 @@ struct RayLists {
 
 struct dl_ctx {
   int device = 0;
-  DevBuf cams, rec, k64[2], v32[2], vis, counts, bk[2], bv[2], hist, partial, tstart, views, stats, alive, state,
-      dtotal, nkeys;
+  DevBuf cams, rec, srec, k64[2], v32[2], vis, counts, bk[2], bv[2], hist, partial, tstart, views, stats, alive,
+      state, dtotal, nkeys;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
   double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
   // profiling: HIP events around each stage of the last frame, and work counters
   bool prof = false;
   struct Mark {
-    int stage;
+    int stage, chunk;
     hipEvent_t a, b;
   };
+  int chunk = 0;  // depth chunk of the marks being recorded
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   std::vector<Mark> marks;
@@ -128,13 +129,14 @@ struct dl_ctx {
   }
   void frame_begin() {
     evused = 0;
+    chunk = 0;
     marks.clear();
     keys = visible = 0;
     batches = 0;
   }
   int begin(int stage, hipStream_t s) {
     if (!prof) return -1;
-    Mark m{stage, ev(), ev()};
+    Mark m{stage, chunk, ev(), ev()};
     if (!m.a || !m.b) return -1;
     (void)hipEventRecord(m.a, s);
     marks.push_back(m);
@@ -237,9 +239,11 @@ int check_opts(const dl_render_opts* o, dl_render_opts& out) {
 }
 
 void auto_tile_directl(const dl_display_desc& d, int& tw, int& th) {
-  // about 220 owned rays per tile: area ~ 220 N / 3 pixels (three views per pixel)
-  const double side = std::sqrt(220.0 * d.n_views / 3.0);
-  int s = (int)std::lround(side / 8.0) * 8;
+  // A view owns about 3/N of a tile's pixels.  Tiles of about 900 owned rays (3-4 per lane of a 256-lane
+  // workgroup) amortise each LDS-staged record over many rays and keep the tile-key count low, while the
+  // extra per-ray evaluations of a larger tile stay small next to the splat sizes.
+  const double side = std::sqrt(300.0 * d.n_views);
+  int s = (int)std::floor(side / 8.0) * 8;
   s = std::max(8, std::min(s, 256));
   tw = th = s;
 }
@@ -346,6 +350,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   const int64_t max_stride = chunk_stride(G, kChunks - 1) + 64;
   HIP_TRY(C->cams.ensure((size_t)N * kCamDoubles * 8));
   HIP_TRY(C->rec.ensure((size_t)NG * kRecF4 * 16));
+  HIP_TRY(C->srec.ensure((size_t)NG * kRecF4 * 16));
   HIP_TRY(C->k64[0].ensure((size_t)NG * 8));
   HIP_TRY(C->k64[1].ensure((size_t)NG * 8));
   HIP_TRY(C->v32[0].ensure((size_t)NG * 4));
@@ -392,7 +397,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   pc.dilation = o.dilation;
   mk = C->begin(DL_STAGE_PROJECT, s);
   HIP_TRY(launch_project(S->soa.as<float>(), C->cams.as<double>(), pc, C->rec.as<float4>(), C->k64[0].as<uint64_t>(),
-                         C->v32[0].as<uint32_t>(), nullptr, C->vis.as<uint32_t>(), s));
+                         C->v32[0].as<uint32_t>(), nullptr, s));
   C->end(mk, s);
   hipError_t e;
   mk = C->begin(DL_STAGE_DEPTH_SORT, s);
@@ -400,8 +405,10 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                            C->v32[1].as<uint32_t>(), G, N, nullptr, 0, 0, 48, C->hist.as<uint32_t>(),
                            C->partial.as<uint32_t>(), s, &e);
   if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
-  C->end(mk, s);
+  HIP_TRY(launch_count_visible(fl ? C->k64[1].as<uint64_t>() : C->k64[0].as<uint64_t>(), G, N, C->vis.as<uint32_t>(), s));
   const uint32_t* sorted = fl ? C->v32[1].as<uint32_t>() : C->v32[0].as<uint32_t>();
+  HIP_TRY(launch_gather_records(C->rec.as<float4>(), sorted, C->vis.as<uint32_t>(), G, N, C->srec.as<float4>(), s));
+  C->end(mk, s);
 
   BlendConst bc{};
   bc.W = d.width;
@@ -413,7 +420,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   bc.T = tl.T;
   bc.N = N;
   bc.G = G;
-  bc.q_cut = o.q_cut;
+  bc.q_cut = (float)(0.72134752044448170368 * (double)o.q_cut);  // log2(e)/2 scale of the record's conic
   bc.alpha_min = o.alpha_min;
   bc.alpha_max = o.alpha_max;
   bc.t_min = o.t_min;
@@ -423,6 +430,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   while ((1ll << bits) < NT) ++bits;
   unsigned long long* total = C->dtotal.as<unsigned long long>();
   for (int c = 0; c < kChunks; ++c) {
+    C->chunk = c;
     ChunkArgs ch;
     ch.num_lo = kChunkBounds[c];
     ch.num_hi = kChunkBounds[c + 1];
@@ -432,7 +440,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     const int64_t ncount = (int64_t)N * ch.stride;
     mk = C->begin(DL_STAGE_BIN_COUNT, s);
     HIP_TRY(launch_fill_u64(total, 1, 0ull, s));
-    HIP_TRY(launch_bin_count(C->rec.as<float4>(), sorted, C->vis.as<uint32_t>(), bc, ch, C->alive.as<uint8_t>(),
+    HIP_TRY(launch_bin_count(C->srec.as<float4>(), sorted, C->vis.as<uint32_t>(), bc, ch, C->alive.as<uint8_t>(),
                              C->counts.as<uint32_t>(), total, s));
     C->end(mk, s);
     mk = C->begin(DL_STAGE_SCAN, s);
@@ -440,7 +448,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     HIP_TRY(launch_finalize_count(total, cap, C->nkeys.as<uint32_t>(), total + 1, s));
     C->end(mk, s);
     mk = C->begin(DL_STAGE_BIN_EMIT, s);
-    HIP_TRY(launch_bin_emit(C->rec.as<float4>(), sorted, C->vis.as<uint32_t>(), bc, ch, C->alive.as<uint8_t>(),
+    HIP_TRY(launch_bin_emit(C->srec.as<float4>(), sorted, C->vis.as<uint32_t>(), bc, ch, C->alive.as<uint8_t>(),
                             C->counts.as<uint32_t>(), C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), s));
     C->end(mk, s);
     mk = C->begin(DL_STAGE_TILE_SORT, s);
@@ -457,10 +465,10 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     BlendChunk bk{c == 0, c == kChunks - 1};
     mk = C->begin(DL_STAGE_BLEND, s);
     if (standard) {
-      HIP_TRY(launch_blend_standard(C->rec.as<float4>(), C->tstart.as<uint32_t>(), svals, bc, bk,
+      HIP_TRY(launch_blend_standard(C->srec.as<float4>(), C->tstart.as<uint32_t>(), svals, bc, bk,
                                     C->alive.as<uint8_t>(), C->state.as<float4>(), out, s));
     } else {
-      HIP_TRY(launch_blend_directl(C->rec.as<float4>(), C->tstart.as<uint32_t>(), svals, L->off.as<uint32_t>(),
+      HIP_TRY(launch_blend_directl(C->srec.as<float4>(), C->tstart.as<uint32_t>(), svals, L->off.as<uint32_t>(),
                                    L->ent.as<uint32_t>(), L->max_rays, bc, bk, C->alive.as<uint8_t>(),
                                    C->state.as<float4>(), out, s));
     }
@@ -695,7 +703,7 @@ int dl_project(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose*
   pc.alpha_max = o.alpha_max;
   pc.dilation = o.dilation;
   HIP_TRY(launch_project(S->soa.as<float>(), C->cams.as<double>(), pc, (float4*)out_dev, C->k64[0].as<uint64_t>(),
-                         C->v32[0].as<uint32_t>(), depth_dev, C->vis.as<uint32_t>(), s));
+                         C->v32[0].as<uint32_t>(), depth_dev, s));
   HIP_TRY(hipStreamSynchronize(s));
   return DL_OK;
 }
@@ -746,6 +754,7 @@ int dl_frame_stats_get(dl_ctx* C, dl_frame_stats* out) {
     if (m.stage >= 0 && m.stage < DL_NSTAGES) {
       out->stage_ms[m.stage] += ms;
       out->stage_launches[m.stage] += 1;
+      if (m.chunk >= 0 && m.chunk < DL_MAX_CHUNKS) out->chunk_ms[m.chunk][m.stage] += ms;
     }
   }
   unsigned long long st[3] = {0, 0, 0};
@@ -755,6 +764,7 @@ int dl_frame_stats_get(dl_ctx* C, dl_frame_stats* out) {
     for (int i = 0; i < kStatSlots; ++i)
       for (int k = 0; k < 3; ++k) st[k] += sl[(size_t)i * 3 + k];
   }
+  out->chunks = kChunks;
   out->keys = C->keys;
   out->visible = C->visible;
   out->evaluations = (int64_t)st[0];
@@ -782,7 +792,7 @@ int dl_render_standard(dl_ctx* C, const dl_scene* S, const dl_display* D, const 
   dl_render_opts o;
   if ((rc = check_opts(opts, o))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  int tw = o.tile_w ? o.tile_w : 16, th = o.tile_h ? o.tile_h : 16;
+  int tw = o.tile_w ? o.tile_w : 32, th = o.tile_h ? o.tile_h : 32;
   if (tw * th > 16 * 256) return fail(DL_EINVAL, "standard tile larger than 4096 pixels");
   const dl_display_desc& d = D->desc;
   float* views = views_dev;

@@ -21,7 +21,7 @@ constexpr int kScanIPT = 16;
 constexpr int kScanTile = kThreads * kScanIPT;
 constexpr int kRows = 16;                        // rows of 64 items per wavefront per tile
 constexpr int kTile = kThreads * kRows;          // 4096 items per tile
-constexpr int kMaxBits = 8;
+constexpr int kMaxBits = 9;
 constexpr int kMaxRadix = 1 << kMaxBits;
 
 __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
@@ -203,24 +203,38 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
       if (valid && lr == 0) wc[w][d] = base + (uint32_t)__popcll(m);
     }
     __syncthreads();
-    // tile-local digit offsets (exclusive scan over digits) and per-wavefront bases
-    uint32_t tot = 0;
-    if (threadIdx.x < radix) {
+    // tile-local digit offsets (exclusive scan over digits; thread t owns digits 2t and 2t + 1) and
+    // per-wavefront bases
+    uint32_t tot0 = 0, tot1 = 0;
+    const int d0 = 2 * threadIdx.x, d1 = 2 * threadIdx.x + 1;
+    if (d0 < radix) {
 #pragma unroll
-      for (int i = 0; i < kWaves; ++i) tot += wc[i][threadIdx.x];
+      for (int i = 0; i < kWaves; ++i) tot0 += wc[i][d0];
+    }
+    if (d1 < radix) {
+#pragma unroll
+      for (int i = 0; i < kWaves; ++i) tot1 += wc[i][d1];
     }
     uint32_t total;
-    uint32_t ex = block_excl_scan(threadIdx.x < radix ? tot : 0u, &total);
-    if (radix > kThreads) {
-      // radix <= 256 == kThreads always; kept for clarity
-    }
-    if (threadIdx.x < radix) {
-      loff[threadIdx.x] = ex;
-      uint32_t acc = ex;
+    const uint32_t ex0 = block_excl_scan(tot0 + tot1, &total);
+    if (d0 < radix) {
+      loff[d0] = ex0;
+      uint32_t acc = ex0;
 #pragma unroll
       for (int i = 0; i < kWaves; ++i) {
-        const uint32_t c = wc[i][threadIdx.x];
-        wc[i][threadIdx.x] = acc;  // becomes the tile-local base of wavefront i for this digit
+        const uint32_t c = wc[i][d0];
+        wc[i][d0] = acc;  // becomes the tile-local base of wavefront i for this digit
+        acc += c;
+      }
+    }
+    if (d1 < radix) {
+      const uint32_t ex1 = ex0 + tot0;
+      loff[d1] = ex1;
+      uint32_t acc = ex1;
+#pragma unroll
+      for (int i = 0; i < kWaves; ++i) {
+        const uint32_t c = wc[i][d1];
+        wc[i][d1] = acc;
         acc += c;
       }
     }
@@ -243,7 +257,8 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
       vout[g] = sval[p];
     }
     __syncthreads();
-    if (threadIdx.x < radix) run[threadIdx.x] += tot;
+    if (d0 < radix) run[d0] += tot0;
+    if (d1 < radix) run[d1] += tot1;
     __syncthreads();
   }
 }

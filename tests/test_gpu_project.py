@@ -54,10 +54,13 @@ def test_projected_records_match_oracle(ctx, case):
         assert np.allclose(depth[v][vis], r[:, 9], rtol=1e-13)
         assert np.allclose(g[:, 0], r[:, 0], rtol=2e-7, atol=2e-4)
         assert np.allclose(g[:, 1], r[:, 1], rtol=2e-7, atol=2e-4)
+        # the GPU record holds the conic scaled by log2(e)/2 (a, c) and log2(e) (b)
+        ks = np.log2(np.e) / 2
+        conic = g[:, 2:5] / np.array([ks, 2 * ks, ks])
         scale = np.sqrt(np.abs(r[:, 2] * r[:, 4]))
-        for k in (2, 3, 4):
-            assert np.all(np.abs(g[:, k] - r[:, k]) <= 1e-6 * scale + 1e-12)
-        assert np.allclose(g[:, 5], r[:, 5], rtol=1e-7)
-        assert np.allclose(g[:, 6:9], r[:, 6:9], atol=5e-6)
+        for k in (0, 1, 2):
+            assert np.all(np.abs(conic[:, k] - r[:, 2 + k]) <= 1e-6 * scale + 1e-12)
+        assert np.allclose(g[:, 8], r[:, 5], rtol=1e-7)
+        assert np.allclose(g[:, 9:12], r[:, 6:9], atol=5e-6)
     S.close()
     D.close()
