@@ -152,3 +152,21 @@ def test_uhd45_full_size_sampled(ctx):
     log("  uhd45 worst %.3g over %d fragile %d" % (worst, over, frag))
     assert worst <= TOL
     assert over <= 3
+
+
+def test_8k60_full_size_sampled(ctx):
+    """7680x4320, N = 60, 3M clustered Gaussians: sampled subpixels against the oracle, plus the orbit pose
+    at a quarter turn."""
+    log("8k60 full size")
+    d = synth.make_named_display("8k60")
+    sc = synth.make_scene("8k60")
+    for c2w in [synth.pose_orbit(120)[0], synth.pose_orbit(120)[30]]:
+        img, S, D = _render(ctx, sc, d, c2w)
+        assert np.isfinite(img).all()
+        xs, ys, ks = sample_subpixels(d.height, d.width, 500, 13)
+        worst, over, frag = check_subpixels(sc, d, c2w, img, xs, ys, ks, label="8k60")
+        log("  8k60 worst %.3g over %d fragile %d" % (worst, over, frag))
+        assert worst <= TOL
+        assert over <= 2
+        S.close()
+        D.close()
