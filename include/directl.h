@@ -150,6 +150,19 @@ int dl_render(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, con
 int dl_render_standard(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
                        const dl_render_opts* opts, float* out_dev, float* views_dev, void* stream);
 
+/* Backward of dl_render (the paper names backpropagation as future work, Sec. 9; here the rasterized
+ * DirectL forward is differentiated): given the forward's encoded image out_dev[H][W][3] for the same scene,
+ * display, pose and options, and grad_out_dev = d loss / d out_dev, writes d loss / d parameters in the
+ * user layouts g_means[G][3], g_log_scales[G][3], g_quats[G][4] (w.r.t. the unnormalised quaternion),
+ * g_opacity_logits[G], g_sh[G][16][3] (device buffers, overwritten).  The forward's tile lists are recomputed
+ * (no per-pixel blend state is stored); threshold and termination decisions are the forward's and carry no
+ * gradient, and neither does the colour clamp at 0 nor the opacity clamp at alpha_max.  Per-Gaussian
+ * gradients are accumulated with floating-point atomics (summation order is not deterministic).
+ * Synchronises `stream`. */
+int dl_render_backward(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
+                       const dl_render_opts* opts, const float* out_dev, const float* grad_out_dev, float* g_means,
+                       float* g_log_scales, float* g_quats, float* g_opacity_logits, float* g_sh, void* stream);
+
 /* Alg. 1 alone: out_dev[x][y][k] = views_dev[V(x, 3y + k)][x][y][k]. */
 int dl_interleave(const dl_display* display, const float* views_dev, float* out_dev, void* stream);
 

@@ -79,6 +79,8 @@ _SIGS = {
     "dl_render_standard": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P,
                                 _P]),
     "dl_interleave": (_I, [_P, _P, _P, _P]),
+    "dl_render_backward": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P, _P, _P,
+                                _P, _P, _P, _P]),
     "dl_set_profiling": (_I, [_P, _I]),
     "dl_set_key_capacity": (_I, [_P, ctypes.c_int64]),
     "dl_key_capacity": (ctypes.c_int64, [_P]),
@@ -325,6 +327,23 @@ def render_standard(ctx, scene, display, c2w, converge_dist=None, opts=None, out
     _check(load().dl_render_standard(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(out),
                                      _ptr(views) if views is not None else None, _stream(stream)))
     return out, views
+
+
+def render_backward(ctx, scene, display, c2w, out, grad_out, converge_dist=None, opts=None, stream=None):
+    """Gradients (means[G,3], log_scales[G,3], quats[G,4], opacity_logits[G], sh[G,16,3]) of a loss whose
+    gradient with respect to the DirectL image `out` is `grad_out`."""
+    torch = _torch()
+    G = scene.n
+    dev = dict(dtype=torch.float32, device="cuda")
+    g = (torch.empty((G, 3), **dev), torch.empty((G, 3), **dev), torch.empty((G, 4), **dev), torch.empty((G,), **dev),
+         torch.empty((G, 16, 3), **dev))
+    out = out.contiguous()
+    grad_out = grad_out.to(torch.float32).contiguous()
+    pose = make_pose(c2w, converge_dist)
+    o = opts or default_opts()
+    _check(load().dl_render_backward(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(out),
+                                     _ptr(grad_out), *[_ptr(x) for x in g], _stream(stream)))
+    return g
 
 
 def interleave(display, views, out=None, stream=None):

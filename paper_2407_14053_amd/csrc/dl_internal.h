@@ -125,4 +125,16 @@ hipError_t launch_blend_standard(const float4* rec, const uint32_t* tile_start, 
                                  const BlendConst& bc, BlendChunk bk, uint8_t* alive, float4* state, float* views,
                                  hipStream_t s);
 
+// ---- backward (backward.hip) ----
+// Replays the DirectL blend of one depth chunk and accumulates d loss / d (u, v, A, B, C, o, r, g, b) per
+// (view, Gaussian) into acc[9][N * G]; fwd is the forward's encoded image, gout d loss / d image.
+hipError_t launch_blend_backward(const float4* rec, const uint32_t* tile_start, const uint32_t* gidx,
+                                 const uint32_t* sorted, const uint32_t* ray_off, const uint32_t* ray_ent,
+                                 int max_rays, const BlendConst& bc, BlendChunk bk, uint8_t* alive, float4* state,
+                                 const float* fwd, const float* gout, float* acc, hipStream_t s);
+// Chains acc through the projection of every view; writes gradients in the user layouts (overwritten).
+hipError_t launch_project_backward(const float* soa, const double* cams, const ProjConst& pc, const float* acc,
+                                   float* g_means, float* g_log_scales, float* g_quats, float* g_logits, float* g_sh,
+                                   hipStream_t s);
+
 }  // namespace dl

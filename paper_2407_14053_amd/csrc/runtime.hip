@@ -101,7 +101,7 @@ struct RayLists {
 struct dl_ctx {
   int device = 0;
   DevBuf cams, rec, srec, k64[2], v32[2], vis, counts, bk[2], bv[2], hist, partial, tstart, views, stats, alive,
-      state, dtotal, nkeys;
+      state, dtotal, nkeys, gacc;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
   double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
   // profiling: HIP events around each stage of the last frame, and work counters
@@ -329,12 +329,19 @@ constexpr uint32_t kMaxKeyCap = 0x7fffffffu;
 
 int64_t chunk_stride(int64_t G, int c) { return G * (kChunkBounds[c + 1] - kChunkBounds[c]) / kChunkDen + 1; }
 
+// Backward inputs/outputs of a frame (DirectL only).
+struct BwdArgs {
+  const float* fwd;   // forward encoded image
+  const float* gout;  // d loss / d image
+  float *g_means, *g_log_scales, *g_quats, *g_logits, *g_sh;
+};
+
 // One frame of either path: cameras, projection, depth sort, then per depth chunk: count live (view, tile)
 // keys, scan, emit, partition by (view, tile), list bounds, blend.  Returns DL_ECAP (with *need set) if a
 // chunk produced more keys than the capacity; the caller grows it and renders again.
 int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose, const dl_render_opts& o,
                  const Tiles& tl, bool standard, const RayLists* L, float* out, hipStream_t s,
-                 unsigned long long* need) {
+                 unsigned long long* need, const BwdArgs* bwd) {
   const dl_display_desc& d = D->desc;
   const int N = d.n_views;
   const int64_t G = S->n;
@@ -370,6 +377,10 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   HIP_TRY(C->hist.ensure((size_t)hs * 4));
   HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, N * max_stride)) + 2) * 4));
   if (C->prof) HIP_TRY(C->stats.ensure((size_t)kStatSlots * 3 * 8));
+  if (bwd) {
+    HIP_TRY(C->gacc.ensure((size_t)NG * 9 * 4));
+    HIP_TRY(hipMemsetAsync(C->gacc.p, 0, (size_t)NG * 9 * 4, s));
+  }
 
   C->frame_begin();
   int mk = C->begin(DL_STAGE_UPLOAD, s);
@@ -464,7 +475,12 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     C->end(mk, s);
     BlendChunk bk{c == 0, c == kChunks - 1};
     mk = C->begin(DL_STAGE_BLEND, s);
-    if (standard) {
+    if (bwd) {
+      HIP_TRY(launch_blend_backward(C->srec.as<float4>(), C->tstart.as<uint32_t>(), svals, sorted,
+                                    L->off.as<uint32_t>(), L->ent.as<uint32_t>(), L->max_rays, bc, bk,
+                                    C->alive.as<uint8_t>(), C->state.as<float4>(), bwd->fwd, bwd->gout,
+                                    C->gacc.as<float>(), s));
+    } else if (standard) {
       HIP_TRY(launch_blend_standard(C->srec.as<float4>(), C->tstart.as<uint32_t>(), svals, bc, bk,
                                     C->alive.as<uint8_t>(), C->state.as<float4>(), out, s));
     } else {
@@ -472,6 +488,12 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                                    L->ent.as<uint32_t>(), L->max_rays, bc, bk, C->alive.as<uint8_t>(),
                                    C->state.as<float4>(), out, s));
     }
+    C->end(mk, s);
+  }
+  if (bwd) {
+    mk = C->begin(DL_STAGE_PROJECT, s);
+    HIP_TRY(launch_project_backward(S->soa.as<float>(), C->cams.as<double>(), pc, C->gacc.as<float>(), bwd->g_means,
+                                    bwd->g_log_scales, bwd->g_quats, bwd->g_logits, bwd->g_sh, s));
     C->end(mk, s);
   }
   unsigned long long mx = 0;
@@ -490,10 +512,11 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
 
 // Render with the context's key buffers, growing them once if a depth chunk overflowed.
 int render_grow(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose, const dl_render_opts& o,
-                const Tiles& tl, bool standard, const RayLists* L, float* out, hipStream_t s) {
+                const Tiles& tl, bool standard, const RayLists* L, float* out, hipStream_t s,
+                const BwdArgs* bwd = nullptr) {
   for (int attempt = 0; attempt < 3; ++attempt) {
     unsigned long long need = 0;
-    int rc = render_frame(C, S, D, pose, o, tl, standard, L, out, s, &need);
+    int rc = render_frame(C, S, D, pose, o, tl, standard, L, out, s, &need, bwd);
     if (rc != DL_ECAP) return rc;
     if (need > kMaxKeyCap) return fail(DL_ENOMEM, "a depth chunk needs more than 2^31 tile keys");
     const unsigned long long want = std::min<unsigned long long>(kMaxKeyCap, need + need / 4 + 1024);
@@ -775,6 +798,29 @@ int dl_frame_stats_get(dl_ctx* C, dl_frame_stats* out) {
   out->tile_h = C->tile_h;
   out->rays_per_lane = C->rpt;
   return DL_OK;
+}
+
+int dl_render_backward(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose,
+                       const dl_render_opts* opts, const float* out_dev, const float* grad_out_dev, float* g_means,
+                       float* g_log_scales, float* g_quats, float* g_opacity_logits, float* g_sh, void* stream) {
+  int rc = check_common(C, S, D);
+  if (rc) return rc;
+  if (!out_dev || !grad_out_dev || !g_means || !g_log_scales || !g_quats || !g_opacity_logits || !g_sh)
+    return fail(DL_EINVAL, "NULL buffer");
+  dl_render_opts o;
+  if ((rc = check_opts(opts, o))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int tw = o.tile_w, th = o.tile_h;
+  if (tw == 0 || th == 0) auto_tile_directl(D->desc, tw, th);
+  RayLists* L = nullptr;
+  if ((rc = build_ray_lists(const_cast<dl_display*>(D), tw, th, s, &L))) return rc;
+  if (L->max_rays > 16 * 256) return fail(DL_EINVAL, "tile too large: more than 4096 rays of one view");
+  Tiles tl = make_tiles(D->desc, tw, th);
+  C->tile_w = tw;
+  C->tile_h = th;
+  C->rpt = (L->max_rays + 255) / 256;
+  BwdArgs b{out_dev, grad_out_dev, g_means, g_log_scales, g_quats, g_opacity_logits, g_sh};
+  return render_grow(C, S, D, pose, o, tl, false, L, nullptr, s, &b);
 }
 
 int dl_interleave(const dl_display* D, const float* views_dev, float* out_dev, void* stream) {
