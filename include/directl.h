@@ -166,6 +166,28 @@ int dl_render_backward(dl_ctx* ctx, const dl_scene* scene, const dl_display* dis
 /* Alg. 1 alone: out_dev[x][y][k] = views_dev[V(x, 3y + k)][x][y][k]. */
 int dl_interleave(const dl_display* display, const float* views_dev, float* out_dev, void* stream);
 
+/* ---- plans: fixed-buffer frames replayed as HIP graphs (serving) ----
+ * A plan owns every per-frame buffer of one (scene, display, options) at fixed capacity, sized by an eager
+ * DirectL frame at probe_pose: the per-chunk tile-key capacity is the larger of min_key_capacity and the probe's
+ * largest depth chunk plus 30%.  Scene and display
+ * may be shared by many plans and contexts of the same device; both must outlive the plan, and the scene keeps
+ * its size.  out_dev: caller-owned device image [H][W][3] float32 that every launch of the plan writes; it must
+ * outlive the plan.
+ * The frame is captured into a HIP graph on `stream` when the plan is created.  dl_plan_render uploads the
+ * cameras of `pose`, then launches that graph on `stream`; it does not synchronise.  Streams must not be the
+ * null stream.  Launches of one plan must be
+ * ordered (one stream, or the previous frame completed): they share the plan's buffers.  After a launch has
+ * completed, dl_plan_check returns DL_OK, or DL_ECAP if a depth chunk overflowed the plan's capacity — the image
+ * is then invalid and *need holds the keys that chunk required (render that request eagerly or with a new plan).
+ * dl_plan_bytes: device bytes the plan holds.  dl_plan_free waits for the plan's work to finish. */
+int dl_plan_create(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_render_opts* opts,
+                   const dl_pose* probe_pose, int64_t min_key_capacity, float* out_dev, void* stream,
+                   dl_plan** out);
+int dl_plan_render(dl_plan* plan, const dl_pose* pose, void* stream);
+int dl_plan_check(const dl_plan* plan, int64_t* need);
+int64_t dl_plan_bytes(const dl_plan* plan);
+void dl_plan_free(dl_plan* plan);
+
 /* Per-depth-chunk capacity of the context's tile-key buffers (0 until the first frame sizes it).  A frame
  * whose chunk needs more keys grows the buffers and renders again; setting a smaller value is allowed (the
  * buffers shrink lazily only in the sense that the value bounds new growth decisions). */

@@ -85,6 +85,12 @@ _SIGS = {
     "dl_set_key_capacity": (_I, [_P, ctypes.c_int64]),
     "dl_key_capacity": (ctypes.c_int64, [_P]),
     "dl_frame_stats_get": (_I, [_P, ctypes.POINTER(dl_frame_stats)]),
+    "dl_plan_create": (_I, [_P, _P, _P, ctypes.POINTER(dl_render_opts), ctypes.POINTER(dl_pose), ctypes.c_int64,
+                            _P, _P, ctypes.POINTER(_P)]),
+    "dl_plan_render": (_I, [_P, ctypes.POINTER(dl_pose), _P]),
+    "dl_plan_check": (_I, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "dl_plan_bytes": (ctypes.c_int64, [_P]),
+    "dl_plan_free": (None, [_P]),
 }
 
 _lib = None
@@ -353,3 +359,49 @@ def interleave(display, views, out=None, stream=None):
         out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     _check(load().dl_interleave(display.h, _ptr(views), _ptr(out), _stream(stream)))
     return out
+
+
+class Plan:
+    """A DirectL frame of one (scene, display, options) with fixed buffers, replayed as a HIP graph.
+
+    `out` is the image every launch writes.  `launch` is asynchronous on `stream` (not the null stream);
+    `check` is valid once that launch has completed and raises nothing: it returns (ok, keys_needed)."""
+
+    def __init__(self, ctx: Context, scene: Scene, display: Display, probe_c2w, converge_dist=None, opts=None,
+                 min_key_capacity: int = 0, stream=None):
+        torch = _torch()
+        H, W = display.shape
+        self.ctx, self.scene, self.display = ctx, scene, display  # kept alive while the plan lives
+        self.out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+        self.opts = opts or default_opts()
+        self.converge_dist = converge_dist
+        pose = make_pose(probe_c2w, converge_dist)
+        h = ctypes.c_void_p()
+        _check(load().dl_plan_create(ctx.h, scene.h, display.h, ctypes.byref(self.opts), ctypes.byref(pose),
+                                     int(min_key_capacity), _ptr(self.out), _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.bytes = int(load().dl_plan_bytes(self.h)) + self.out.numel() * 4
+
+    def launch(self, c2w, stream=None, converge_dist=None):
+        cd = self.converge_dist if converge_dist is None else converge_dist
+        pose = make_pose(c2w, cd)
+        _check(load().dl_plan_render(self.h, ctypes.byref(pose), _stream(stream)))
+        return self.out
+
+    def check(self):
+        need = ctypes.c_int64(0)
+        rc = load().dl_plan_check(self.h, ctypes.byref(need))
+        if rc not in (DL_OK, DL_ECAP):
+            _check(rc)
+        return rc == DL_OK, int(need.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().dl_plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -329,6 +329,14 @@ constexpr uint32_t kMaxKeyCap = 0x7fffffffu;
 
 int64_t chunk_stride(int64_t G, int c) { return G * (kChunkBounds[c + 1] - kChunkBounds[c]) / kChunkDen + 1; }
 
+// How a frame is issued: eager frames upload their cameras and end with the overflow check; a frame being
+// captured into a graph does neither (the plan uploads the cameras before each launch and reads the overflow
+// flag after completion).
+struct FrameMode {
+  bool upload = true;
+  bool finish = true;
+};
+
 // Backward inputs/outputs of a frame (DirectL only).
 struct BwdArgs {
   const float* fwd;   // forward encoded image
@@ -341,12 +349,14 @@ struct BwdArgs {
 // chunk produced more keys than the capacity; the caller grows it and renders again.
 int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose, const dl_render_opts& o,
                  const Tiles& tl, bool standard, const RayLists* L, float* out, hipStream_t s,
-                 unsigned long long* need, const BwdArgs* bwd) {
+                 unsigned long long* need, const BwdArgs* bwd, FrameMode mode = FrameMode()) {
   const dl_display_desc& d = D->desc;
   const int N = d.n_views;
   const int64_t G = S->n;
-  int rc = make_cameras(d, pose, C->cams_host);
-  if (rc) return rc;
+  if (mode.upload) {
+    int rc = make_cameras(d, pose, C->cams_host);
+    if (rc) return rc;
+  }
   const int64_t NG = (int64_t)N * G;
   if (NG >= (1ll << 32) - 1) return fail(DL_EINVAL, "views x Gaussians exceeds 2^32");
   const int64_t NT = (int64_t)N * tl.T;
@@ -384,8 +394,8 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
 
   C->frame_begin();
   int mk = C->begin(DL_STAGE_UPLOAD, s);
-  HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(C->vis.p, 0, 256 * 4, s));
+  if (mode.upload)
+    HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(launch_fill_u64(C->dtotal.as<unsigned long long>(), 2, 0ull, s));
   if (C->prof) HIP_TRY(launch_fill_u64(C->stats.as<unsigned long long>(), kStatSlots * 3, 0ull, s));
   HIP_TRY(launch_init_alive(C->alive.as<uint8_t>(), standard ? nullptr : L->off.as<uint32_t>(), NT, s));
@@ -496,6 +506,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                                     bwd->g_log_scales, bwd->g_quats, bwd->g_logits, bwd->g_sh, s));
     C->end(mk, s);
   }
+  if (!mode.finish) return DL_OK;
   unsigned long long mx = 0;
   std::vector<uint32_t> vis(N, 0);
   HIP_TRY(hipMemcpyAsync(&mx, total + 1, 8, hipMemcpyDeviceToHost, s));
@@ -532,7 +543,8 @@ int render_grow(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose
 
 int check_common(dl_ctx* C, const dl_scene* S, const dl_display* D) {
   if (!C || !S || !D) return fail(DL_EINVAL, "NULL context, scene or display");
-  if (S->ctx != C || D->ctx != C) return fail(DL_EINVAL, "scene/display belong to another context");
+  if (S->ctx->device != C->device || D->ctx->device != C->device)
+    return fail(DL_EINVAL, "scene/display live on another device");
   return DL_OK;
 }
 
@@ -750,6 +762,157 @@ int dl_render(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* 
   C->rpt = (L->max_rays + 255) / 256;
   return render_grow(C, S, D, pose, o, tl, false, L, out_dev, s);
 }
+
+}  // extern "C"
+
+struct dl_plan {
+  dl_ctx* C = nullptr;  // private frame buffers
+  const dl_scene* S = nullptr;
+  const dl_display* D = nullptr;
+  dl_render_opts o{};
+  Tiles tl{};
+  RayLists* L = nullptr;
+  float* out = nullptr;  // caller's [H][W][3] image
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t copied = nullptr;                // after the last camera upload: the staging may be rewritten
+  unsigned long long* status_host = nullptr;  // pinned: largest chunk key total of the last launch
+  ~dl_plan() {
+    if (copied) {
+      (void)hipEventSynchronize(copied);
+      (void)hipEventDestroy(copied);
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (status_host) (void)hipHostFree(status_host);
+    dl_destroy(C);
+  }
+};
+
+namespace {
+size_t ctx_bytes(const dl_ctx* C) {
+  const DevBuf* b[] = {&C->cams, &C->rec, &C->srec, &C->k64[0], &C->k64[1], &C->v32[0], &C->v32[1], &C->vis,
+                       &C->counts, &C->bk[0], &C->bk[1], &C->bv[0], &C->bv[1], &C->hist, &C->partial, &C->tstart,
+                       &C->views, &C->stats, &C->alive, &C->state, &C->dtotal, &C->nkeys, &C->gacc};
+  size_t t = 0;
+  for (const DevBuf* x : b) t += x->cap;
+  return t;
+}
+// Record one frame of the plan into a graph (cameras are uploaded outside it, before every launch).
+int plan_capture(dl_plan* P, hipStream_t s) {
+  unsigned long long need = 0;
+  FrameMode m;
+  m.upload = false;
+  m.finish = false;
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc = render_frame(P->C, P->S, P->D, nullptr, P->o, P->tl, false, P->L, P->out, s, &need, nullptr, m);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(DL_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  P->graph = g;
+  HIP_TRY(hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0));
+  return DL_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int dl_plan_create(dl_ctx* ctx, const dl_scene* S, const dl_display* D, const dl_render_opts* opts,
+                   const dl_pose* probe_pose, int64_t min_key_capacity, float* out_dev, void* stream,
+                   dl_plan** out) {
+  int rc = check_common(ctx, S, D);
+  if (rc) return rc;
+  if (!out || !probe_pose || !out_dev) return fail(DL_EINVAL, "NULL argument");
+  if (min_key_capacity < 0 || min_key_capacity > (int64_t)kMaxKeyCap) return fail(DL_EINVAL, "key capacity range");
+  dl_render_opts o;
+  if ((rc = check_opts(opts, o))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(DL_EINVAL, "plans are captured on a created stream, not the null stream");
+  dl_plan* P = new dl_plan();
+  if ((rc = dl_create(ctx->device, &P->C))) {
+    delete P;
+    return rc;
+  }
+  P->S = S;
+  P->D = D;
+  P->o = o;
+  P->out = out_dev;
+  int tw = o.tile_w, th = o.tile_h;
+  if (tw == 0 || th == 0) auto_tile_directl(D->desc, tw, th);
+  P->tl = make_tiles(D->desc, tw, th);
+  // first guess of the per-chunk key capacity; the probe grows it to what the pose needs
+  P->C->key_cap = (uint32_t)std::min<int64_t>(1 << 22, std::max<int64_t>(1 << 16, (int64_t)D->desc.n_views * S->n / 2));
+  if ((rc = build_ray_lists(const_cast<dl_display*>(D), tw, th, s, &P->L))) {
+    delete P;
+    return rc;
+  }
+  if (P->L->max_rays > 16 * 256) {
+    delete P;
+    return fail(DL_EINVAL, "tile too large: more than 4096 rays of one view");
+  }
+  if (hipHostMalloc((void**)&P->status_host, 8, hipHostMallocDefault) != hipSuccess) {
+    delete P;
+    return fail(DL_ENOMEM, "plan status word");
+  }
+  // size every buffer with an eager frame at the probe pose, then refit the key buffers to the largest chunk
+  // total seen plus 30% headroom (buffers are grow-only, so release those that depend on the capacity)
+  if ((rc = render_grow(P->C, S, D, probe_pose, o, P->tl, false, P->L, P->out, s))) {
+    delete P;
+    return rc;
+  }
+  const unsigned long long k = (unsigned long long)P->C->keys;
+  P->C->key_cap = (uint32_t)std::min<unsigned long long>(
+      kMaxKeyCap, std::max<unsigned long long>((unsigned long long)min_key_capacity, k + k * 3 / 10 + 4096));
+  for (DevBuf* b : {&P->C->bk[0], &P->C->bk[1], &P->C->bv[0], &P->C->bv[1], &P->C->hist, &P->C->partial})
+    b->release();
+  if ((rc = render_grow(P->C, S, D, probe_pose, o, P->tl, false, P->L, P->out, s))) {
+    delete P;
+    return rc;
+  }
+  if (hipEventCreateWithFlags(&P->copied, hipEventDisableTiming) != hipSuccess) {
+    delete P;
+    return fail(DL_EHIP, "plan event");
+  }
+  if ((rc = plan_capture(P, s))) {
+    delete P;
+    return rc;
+  }
+  *P->status_host = 0;
+  *out = P;
+  return DL_OK;
+}
+
+int64_t dl_plan_bytes(const dl_plan* P) { return P ? (int64_t)ctx_bytes(P->C) : -1; }
+
+int dl_plan_render(dl_plan* P, const dl_pose* pose, void* stream) {
+  if (!P) return fail(DL_EINVAL, "NULL plan");
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(DL_EINVAL, "plans are launched on a created stream, not the null stream");
+  dl_ctx* C = P->C;
+  const int N = P->D->desc.n_views;
+  HIP_TRY(hipEventSynchronize(P->copied));  // the previous launch's upload has left the staging buffer
+  int rc = make_cameras(P->D->desc, pose, C->cams_host);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(P->copied, s));
+  HIP_TRY(hipGraphLaunch(P->exec, s));
+  HIP_TRY(hipMemcpyAsync(P->status_host, C->dtotal.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, s));
+  return DL_OK;
+}
+
+int dl_plan_check(const dl_plan* P, int64_t* need) {
+  if (!P) return fail(DL_EINVAL, "NULL plan");
+  const unsigned long long mx = *P->status_host;
+  if (need) *need = (int64_t)mx;
+  if (mx > P->C->key_cap) return fail(DL_ECAP, "a depth chunk overflowed the plan's key capacity");
+  return DL_OK;
+}
+
+void dl_plan_free(dl_plan* P) { delete P; }
 
 int dl_set_key_capacity(dl_ctx* C, int64_t keys) {
   if (!C) return fail(DL_EINVAL, "NULL context");

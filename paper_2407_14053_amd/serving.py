@@ -1,0 +1,317 @@
+"""Request loop that serves DirectL light-field frames from scenes kept resident in device memory.
+
+Each request names a resident scene, a display and a centre-camera pose.  Frames are rendered by plans
+(fixed-buffer DirectL frames replayed as HIP graphs, one plan per (scene, display) pair, more than one when the
+same pair is in flight twice).  The loop admits requests against a device-memory budget: a new plan is created
+only when its bytes fit beside the resident scenes and the plans already held, after evicting idle plans in
+least-recently-used order; a request that cannot get a plan waits (it is counted as deferred).  Admitted frames
+run concurrently on a few streams; each request's latency runs from its arrival to the completion of its frame.
+
+Everything the GPU does goes through the C ABI (`api.Plan`); this module only schedules.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from collections import OrderedDict, deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import api, synth
+
+
+@dataclass
+class Request:
+    rid: int
+    scene: str
+    display: str
+    c2w: np.ndarray
+    arrival: float  # seconds after the start of the run
+
+
+@dataclass
+class Done:
+    rid: int
+    scene: str
+    display: str
+    arrival: float
+    launched: float
+    finished: float
+    deferred: bool
+    replans: int
+    image: object = None  # the frame, when the server keeps images
+
+    @property
+    def latency_ms(self) -> float:
+        return 1e3 * (self.finished - self.arrival)
+
+
+def poisson_requests(n: int, rate: float, scenes, displays, seed: int = 2000, distance: float = 3.0) -> list:
+    """n requests with exponential inter-arrival times of mean 1/rate; scene, display and orbit angle uniform."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n)
+    t = np.cumsum(gaps) - gaps[0]
+    si = rng.integers(0, len(scenes), size=n)
+    di = rng.integers(0, len(displays), size=n)
+    th = rng.uniform(0.0, 2.0 * math.pi, size=n)
+    out = []
+    for i in range(n):
+        eye = (distance * math.sin(th[i]), 0.0, distance * math.cos(th[i]))
+        out.append(Request(i, scenes[si[i]], displays[di[i]], synth.look_at_c2w(eye), float(t[i])))
+    return out
+
+
+class _PlanEntry:
+    def __init__(self, key, plan: api.Plan):
+        self.key = key
+        self.plan = plan
+        self.busy = False
+        self.bytes = plan.bytes
+
+
+class _Slot:
+    def __init__(self, torch):
+        self.stream = torch.cuda.Stream()
+        self.event = torch.cuda.Event()
+        self.entry = None
+        self.req = None
+        self.launched = 0.0
+        self.image = None
+
+
+@dataclass
+class Report:
+    done: list
+    wall_s: float
+    admitted: int
+    deferred: int
+    replans: int
+    plans_created: int
+    plans_evicted: int
+    hbm_high_water: int
+    budget: int
+    resident_bytes: int
+    per_display: dict = field(default_factory=dict)
+
+    def summary(self) -> dict:
+        lat = np.array([d.latency_ms for d in self.done]) if self.done else np.zeros(1)
+        out = {
+            "requests": len(self.done),
+            "frames_per_s": len(self.done) / self.wall_s if self.wall_s > 0 else 0.0,
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "admitted": self.admitted,
+            "deferred": self.deferred,
+            "replans": self.replans,
+            "plans_created": self.plans_created,
+            "plans_evicted": self.plans_evicted,
+            "hbm_high_water_gb": self.hbm_high_water / 2**30,
+            "budget_gb": self.budget / 2**30,
+            "resident_scene_gb": self.resident_bytes / 2**30,
+        }
+        per = {}
+        for name in sorted({d.display for d in self.done}):
+            l = np.array([d.latency_ms for d in self.done if d.display == name])
+            per[name] = {"n": int(l.size), "p50_ms": float(np.percentile(l, 50)), "p99_ms": float(np.percentile(l, 99))}
+        out["per_display"] = per
+        return out
+
+
+class Server:
+    """Resident scenes + displays, a plan cache bounded by a device-memory budget, and `n_slots` streams."""
+
+    def __init__(self, ctx: api.Context, budget_bytes: int | None = None, n_slots: int = 4, opts=None,
+                 keep_images: bool = False, probe_c2w=None):
+        torch = api._torch()
+        self.torch = torch
+        self.ctx = ctx
+        self.opts = opts or api.default_opts()
+        self.keep_images = keep_images
+        self.probe_c2w = probe_c2w if probe_c2w is not None else synth.look_at_c2w((0.0, 0.0, 3.0))
+        self.scenes: dict[str, api.Scene] = {}
+        self.scene_bytes: dict[str, int] = {}
+        self.displays: dict[str, api.Display] = {}
+        self.plans: OrderedDict = OrderedDict()  # id(entry) -> entry, least recently used first
+        self.plan_bytes = 0
+        self.est: dict = {}  # (scene, display) -> bytes of the last plan made for it
+        self.min_keys: dict = {}  # (scene, display) -> capacity a previous overflow asked for
+        self.slots = [_Slot(torch) for _ in range(n_slots)]
+        free, total = torch.cuda.mem_get_info()
+        self.total = total
+        self.budget = int(budget_bytes) if budget_bytes is not None else int(0.9 * free)
+        self.high_water = total - free
+        self.created = self.evicted = 0
+
+    # ---- residency ----
+    def add_scene(self, name: str, scene) -> None:
+        """Upload a `synth.Scene` (or the 5-tuple of arrays) once; it stays resident."""
+        arrays = scene.arrays() if hasattr(scene, "arrays") else scene
+        self.scenes[name] = api.Scene(self.ctx, arrays)
+        g = self.scenes[name].n
+        self.scene_bytes[name] = 59 * 4 * ((g + 63) // 64 * 64)
+        self._sample_memory()
+
+    def add_display(self, name: str, display) -> None:
+        self.displays[name] = api.Display(self.ctx, display)
+
+    @property
+    def resident_bytes(self) -> int:
+        return sum(self.scene_bytes.values())
+
+    def _sample_memory(self):
+        free, total = self.torch.cuda.mem_get_info()
+        self.high_water = max(self.high_water, total - free)
+
+    def _used(self) -> int:
+        return self.resident_bytes + self.plan_bytes
+
+    def _estimate(self, key) -> int:
+        if key in self.est:
+            return self.est[key]
+        # before the first plan of a pair: two record arrays, depth keys and values (double-buffered), chunk
+        # counts, the probe's first guess of the tile-key capacity (four buffers), ray state and the image
+        g = self.scenes[key[0]].n
+        disp = self.displays[key[1]]
+        ng = disp.n_views * g
+        h, w = disp.shape
+        cap = min(1 << 22, max(1 << 16, ng // 2))
+        return ng * (2 * 48 + 2 * 8 + 2 * 4) + 4 * ng // 2 + 16 * cap + 16 * 3 * h * w + 12 * h * w
+
+    # ---- plans ----
+    def _evict_for(self, need: int) -> bool:
+        """Free idle plans (least recently used first) until `need` more bytes fit in the budget; evict nothing
+        if even freeing every idle plan would not make room."""
+        idle = sum(e.bytes for e in self.plans.values() if not e.busy)
+        if self._used() - idle + need > self.budget:
+            return False
+        while self._used() + need > self.budget:
+            victim = next((e for e in self.plans.values() if not e.busy), None)
+            if victim is None:
+                return False
+            del self.plans[id(victim)]
+            self.plan_bytes -= victim.bytes
+            victim.plan.close()
+            self.evicted += 1
+        return True
+
+    def _get_plan(self, key, stream):
+        for e in self.plans.values():
+            if e.key == key and not e.busy:
+                self.plans.move_to_end(id(e))
+                return e
+        need = self._estimate(key)
+        if not self._evict_for(need):
+            return None
+        plan = api.Plan(self.ctx, self.scenes[key[0]], self.displays[key[1]], self.probe_c2w, opts=self.opts,
+                        min_key_capacity=self.min_keys.get(key, 0), stream=stream)
+        e = _PlanEntry(key, plan)
+        self.est[key] = e.bytes
+        self.plans[id(e)] = e
+        self.plan_bytes += e.bytes
+        self.created += 1
+        self._sample_memory()
+        if self._used() > self.budget and not self._evict_for(0):
+            pass  # the plan was larger than estimated; idle plans are gone and this one is kept
+        return e
+
+    def warm(self, keys=None) -> None:
+        """Create one plan per (scene, display) pair (or those in `keys`) before timing, as far as the budget allows."""
+        keys = keys or [(s, d) for s in self.scenes for d in self.displays]
+        s = self.slots[0].stream
+        for k in keys:
+            e = self._get_plan(k, s)
+            if e is None:
+                break
+        self.torch.cuda.synchronize()
+
+    # ---- the loop ----
+    def run(self, requests: list, realtime: bool = True) -> Report:
+        """Serve `requests` (sorted by arrival).  With realtime=False every request is taken as already arrived."""
+        torch = self.torch
+        pending = deque(dataclasses.replace(r) for r in sorted(requests, key=lambda r: r.arrival))
+        queue: deque = deque()
+        done: list = []
+        deferred_ids: set = set()
+        replans = {}
+        admitted = 0
+        t0 = time.perf_counter()
+        base = pending[0].arrival if pending else 0.0
+        now = lambda: time.perf_counter() - t0  # noqa: E731
+        while pending or queue or any(sl.req is not None for sl in self.slots):
+            t = now()
+            while pending and (not realtime or pending[0].arrival - base <= t):
+                r = pending.popleft()
+                if not realtime:
+                    r.arrival = base
+                r.arrival -= base
+                queue.append(r)
+            # completions
+            for sl in self.slots:
+                if sl.req is None or not sl.event.query():
+                    continue
+                t_done = now()
+                r, e = sl.req, sl.entry
+                ok, need = e.plan.check()
+                e.busy = False
+                sl.req = sl.entry = None
+                if not ok:
+                    # the frame overflowed the plan's tile-key capacity: replace the plan and serve the request again
+                    self.min_keys[e.key] = need + need * 3 // 10 + 4096
+                    del self.plans[id(e)]
+                    self.plan_bytes -= e.bytes
+                    e.plan.close()
+                    replans[r.rid] = replans.get(r.rid, 0) + 1
+                    queue.appendleft(r)
+                    continue
+                done.append(Done(r.rid, r.scene, r.display, r.arrival, sl.launched, t_done, r.rid in deferred_ids,
+                                 replans.get(r.rid, 0), sl.image))
+                sl.image = None
+            # admissions, in arrival order, into free slots
+            free = [sl for sl in self.slots if sl.req is None]
+            i = 0
+            while free and i < len(queue):
+                r = queue[i]
+                sl = free[0]
+                key = (r.scene, r.display)
+                e = self._get_plan(key, sl.stream)
+                if e is None:
+                    deferred_ids.add(r.rid)
+                    i += 1
+                    continue
+                del queue[i]
+                free.pop(0)
+                e.busy = True
+                sl.req, sl.entry = r, e
+                sl.launched = now()
+                out = e.plan.launch(r.c2w, stream=sl.stream)
+                if self.keep_images:
+                    with torch.cuda.stream(sl.stream):
+                        sl.image = out.clone()
+                sl.event.record(sl.stream)
+                admitted += 1
+            if queue and all(sl.req is None for sl in self.slots):
+                raise RuntimeError(f"request {queue[0].rid} ({queue[0].scene}, {queue[0].display}) does not fit in "
+                                   f"the device-memory budget of {self.budget / 2**30:.2f} GiB")
+            if not free or not queue:
+                time.sleep(0)  # let the host breathe while frames run
+        wall = now()
+        self._sample_memory()
+        return Report(done=sorted(done, key=lambda d: d.rid), wall_s=wall, admitted=admitted,
+                      deferred=len(deferred_ids), replans=sum(replans.values()), plans_created=self.created,
+                      plans_evicted=self.evicted, hbm_high_water=self.high_water, budget=self.budget,
+                      resident_bytes=self.resident_bytes)
+
+    def close(self):
+        torch = self.torch
+        torch.cuda.synchronize()
+        for e in list(self.plans.values()):
+            e.plan.close()
+        self.plans.clear()
+        self.plan_bytes = 0
+        for d in self.displays.values():
+            d.close()
+        for s in self.scenes.values():
+            s.close()

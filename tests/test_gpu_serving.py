@@ -1,0 +1,205 @@
+"""Serving path on the GPU: plans replayed as HIP graphs equal eager frames bitwise (with eager work between
+replays), overflow of a plan's capacity is reported and recovered, and in a mixed request stream each request's
+image equals the same request rendered alone, bitwise, and the oracle on sampled subpixels; admission under a
+small device-memory budget evicts and defers but still serves every request."""
+import numpy as np
+import pytest
+
+from paper_2407_14053_amd import synth
+from tests.gpu_util import TOL, check_subpixels, log, sample_subpixels
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2407_14053_amd import api
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _eager(ctx, S, D, c2w):
+    from paper_2407_14053_amd import api
+    return api.render(ctx, S, D, c2w).cpu().numpy()
+
+
+def test_plan_replays_equal_eager_frames(ctx):
+    import torch
+    from paper_2407_14053_amd import api
+    log("plan replays vs eager")
+    d = synth.make_named_display("tiny")
+    sc = synth.make_scene("tiny")
+    other = synth.scene_uniform(5000, 1.5, 77)
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    S2 = api.Scene(ctx, other.arrays())
+    poses = synth.pose_sweep(6)
+    ref = [_eager(ctx, S, D, p) for p in poses]
+    stream = torch.cuda.Stream()
+    plan = api.Plan(ctx, S, D, poses[0], stream=stream)
+    for rep in range(3):
+        for i in (0, 3, 1, 4):
+            out = plan.launch(poses[i], stream=stream)
+            stream.synchronize()
+            ok, need = plan.check()
+            assert ok, need
+            got = out.cpu().numpy()
+            assert np.array_equal(got, ref[i]), (rep, i, float(np.abs(got - ref[i]).max()))
+            # unrelated eager work on the same device between replays
+            _eager(ctx, S2, D, poses[(i + 2) % 6])
+            torch.ones(1 << 20, device="cuda").mul_(2.0).sum().item()
+    plan.close()
+
+
+def test_plan_back_to_back_launches_on_one_stream(ctx):
+    import torch
+    from paper_2407_14053_amd import api
+    log("plan back-to-back")
+    d = synth.make_named_display("fd64")
+    sc = synth.make_scene("tiny")
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    poses = synth.pose_sweep(5)
+    ref = [_eager(ctx, S, D, p) for p in poses]
+    stream = torch.cuda.Stream()
+    plan = api.Plan(ctx, S, D, poses[0], stream=stream)
+    outs = []
+    with torch.cuda.stream(stream):
+        for p in poses:
+            plan.launch(p, stream=stream)
+            outs.append(plan.out.clone())
+    stream.synchronize()
+    for i, o in enumerate(outs):
+        assert np.array_equal(o.cpu().numpy(), ref[i]), i
+    plan.close()
+
+
+def test_plan_overflow_is_reported_and_rebuilt_plan_is_exact(ctx):
+    import torch
+    from paper_2407_14053_amd import api
+    log("plan overflow")
+    d = synth.make_named_display("tiny")
+    sc = synth.scene_uniform(20_000, 2.0, 1004)
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    # from inside the cube most Gaussians are behind the camera or cover saturated tiles; from far away every
+    # Gaussian covers about one live tile, so the largest depth chunk holds many more keys
+    probe = synth.look_at_c2w((0.3, 0.2, 1.6))
+    req = synth.look_at_c2w((0.0, 0.0, 40.0))
+    keys = []
+    prof = api.Context(0)  # a second context on the same device, with per-frame counters
+    prof.set_profiling(True)
+    for p in (probe, req):
+        _eager(prof, S, D, p)
+        keys.append(prof.frame_stats()["keys"])
+    prof.close()
+    log("  largest chunk keys: probe %d, request %d" % tuple(keys))
+    assert keys[1] > keys[0] * 13 // 10 + 4096  # the request must outgrow the probe's capacity
+    stream = torch.cuda.Stream()
+    plan = api.Plan(ctx, S, D, probe, stream=stream)
+    plan.launch(req, stream=stream)
+    stream.synchronize()
+    ok, need = plan.check()
+    assert not ok and need == keys[1]
+    plan.close()
+    plan = api.Plan(ctx, S, D, probe, min_key_capacity=need + need // 4, stream=stream)
+    out = plan.launch(req, stream=stream)
+    stream.synchronize()
+    assert plan.check()[0]
+    assert np.array_equal(out.cpu().numpy(), _eager(ctx, S, D, req))
+    plan.close()
+
+
+def test_plan_rejects_null_stream(ctx):
+    from paper_2407_14053_amd import api
+    d = synth.make_named_display("fd64")
+    sc = synth.make_scene("fd64")
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+
+    class _Null:
+        cuda_stream = 0
+
+    with pytest.raises(api.DLError):
+        api.Plan(ctx, S, D, synth.pose_front(3.0), stream=_Null())
+
+
+def _server(ctx, budget=None, n_slots=4, probe=None):
+    from paper_2407_14053_amd import serving
+    srv = serving.Server(ctx, budget_bytes=budget, n_slots=n_slots, keep_images=True, probe_c2w=probe)
+    scenes = {"s2k": synth.make_scene("tiny"), "s20k": synth.scene_uniform(20_000, 2.0, 1004)}
+    for k, v in scenes.items():
+        srv.add_scene(k, v)
+    displays = {"tiny": synth.make_named_display("tiny"), "fd64": synth.make_named_display("fd64"),
+                "wide": synth.make_display(320, 180, 12, "1/4", "37/5", baseline=0.6)}
+    for k, v in displays.items():
+        srv.add_display(k, v)
+    return srv, scenes, displays
+
+
+def _check_alone(ctx, srv, rep, scenes, displays, reqs, n_oracle=2):
+    from paper_2407_14053_amd import api
+    by_id = {r.rid: r for r in reqs}
+    assert len(rep.done) == len(reqs)
+    for k, dn in enumerate(rep.done):
+        r = by_id[dn.rid]
+        alone = api.render(ctx, srv.scenes[r.scene], srv.displays[r.display], r.c2w).cpu().numpy()
+        got = dn.image.cpu().numpy()
+        assert np.array_equal(got, alone), (dn.rid, r.scene, r.display, float(np.abs(got - alone).max()))
+        if k < n_oracle:
+            d = displays[r.display]
+            xs, ys, ks = sample_subpixels(d.height, d.width, 300, 40 + k)
+            worst, over, _ = check_subpixels(scenes[r.scene], d, r.c2w, got, xs, ys, ks, label="serving")
+            assert worst <= TOL and over <= 2
+
+
+def test_serving_mix_equals_alone(ctx):
+    from paper_2407_14053_amd import serving
+    log("serving mix vs alone")
+    srv, scenes, displays = _server(ctx)
+    reqs = serving.poisson_requests(36, 200.0, list(scenes), list(displays), seed=2000)
+    rep = srv.run(reqs, realtime=True)
+    s = rep.summary()
+    log("  ", {k: v for k, v in s.items() if k != "per_display"})
+    assert s["requests"] == 36 and rep.admitted == 36
+    assert s["p99_ms"] >= s["p50_ms"] > 0
+    _check_alone(ctx, srv, rep, scenes, displays, reqs)
+    srv.close()
+
+
+def test_serving_small_budget_evicts_and_defers(ctx):
+    from paper_2407_14053_amd import serving
+    log("serving small budget")
+    srv, scenes, displays = _server(ctx, budget=1 << 40, n_slots=3)
+    srv.warm()
+    largest = max(e.bytes for e in srv.plans.values())
+    est = dict(srv.est)
+    srv.close()
+    srv, scenes, displays = _server(ctx, n_slots=3)
+    srv.est = est  # plan sizes known from the first server
+    srv.budget = srv.resident_bytes + int(1.5 * largest)
+    reqs = serving.poisson_requests(24, 1000.0, list(scenes), list(displays), seed=2001)
+    rep = srv.run(reqs, realtime=False)
+    log("  ", {k: v for k, v in rep.summary().items() if k != "per_display"})
+    assert rep.plans_evicted > 0 and rep.deferred > 0
+    _check_alone(ctx, srv, rep, scenes, displays, reqs, n_oracle=1)
+    srv.close()
+
+
+def test_serving_recovers_from_plan_overflow(ctx):
+    from paper_2407_14053_amd import serving
+    log("serving overflow recovery")
+    # plans sized at a pose inside the 20k scene's cube overflow on requests from far away (see the test above)
+    srv, scenes, displays = _server(ctx, probe=synth.look_at_c2w((0.3, 0.2, 1.6)))
+    reqs = serving.poisson_requests(12, 500.0, list(scenes), list(displays), seed=2002, distance=40.0)
+    rep = srv.run(reqs, realtime=False)
+    assert rep.replans > 0
+    _check_alone(ctx, srv, rep, scenes, displays, reqs, n_oracle=0)
+    srv.close()
+
+
+def test_serving_rejects_request_larger_than_budget(ctx):
+    from paper_2407_14053_amd import serving
+    srv, scenes, displays = _server(ctx)
+    srv.budget = srv.resident_bytes + 1024
+    reqs = serving.poisson_requests(2, 100.0, list(scenes), list(displays), seed=3)
+    with pytest.raises(RuntimeError, match="does not fit"):
+        srv.run(reqs, realtime=False)
+    srv.close()
