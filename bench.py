@@ -9,6 +9,11 @@ on a +-10 degree azimuth sweep of 200 poses.  Inputs are synthetic and resident 
 
 One step = one full light-field frame through the whole path (cameras, projection + SH of all views, depth
 sort, tile binning and sort, blend into the owned subpixels).  Prints one JSON line.
+
+The serving section (form 5) keeps four scenes resident (0.5M, 1M, 2M, 3M Gaussians, uniform in [-2, 2]^3)
+and serves Poisson arrivals (200 requests/s, exponential gaps) of uniformly drawn (scene, display) pairs over
+three panels (1920x1080 N=16, 3840x2160 N=45, 7680x4320 N=60), camera on a distance-3 orbit at a uniform
+angle; latency runs from arrival to the frame's completion event.
 """
 from __future__ import annotations
 
@@ -33,6 +38,21 @@ FLOP_Q = 11
 FLOP_BLEND = 13
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the kernel's source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "blend_uhd45_hbm_traffic.md")
+    try:
+        kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith("|"))
+        src = open(os.path.join(ROOT, kv["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if kv.get("kernel") != kernel or hashlib.sha256(src).hexdigest() != kv.get("source_sha256"):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def percentile(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -40,6 +60,18 @@ def percentile(xs, p):
     k = (len(xs) - 1) * p / 100.0
     f, c = math.floor(k), math.ceil(k)
     return xs[f] if f == c else xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def copy_probe(nbytes: int = 256 << 20):
+    """A plain device copy of known size, so that a hardware byte counter read in the same profiled process can
+    be converted to bytes (the copy kernel moves nbytes in and nbytes out per launch)."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print("copy probe: 3 x %d bytes" % nbytes, file=sys.stderr, flush=True)
 
 
 def run_gpu(args):
@@ -64,25 +96,37 @@ def run_gpu(args):
     torch.cuda.synchronize()
     print("warmup done", file=sys.stderr, flush=True)
 
-    ctx.set_profiling(True)
+    # timed region: per-stage HIP events only (profiling level 1); each frame ends with the library's own
+    # overflow readback, so frames do not overlap
+    ctx.set_profiling(1)
     frame_ms, stages = [], []
+    timed_poses = [poses[(args.warmup + i) % len(poses)] for i in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for c2w in timed_poses:
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        api.render(ctx, S, D, poses[(args.warmup + i) % len(poses)], opts=opts, out=out)
+        api.render(ctx, S, D, c2w, opts=opts, out=out)
         e1.record(stream)
         stages.append(ctx.frame_stats())
         e1.synchronize()
         frame_ms.append(e0.elapsed_time(e1))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ctx.set_profiling(False)
     wall = t1 - t0
     fps = args.steps / wall
     print("directl: %.2f frames/s" % fps, file=sys.stderr, flush=True)
+    # work counters of the same frames (level 2 adds atomics to the blend, so it is not timed)
+    ctx.set_profiling(2)
+    counted = []
+    for c2w in timed_poses:
+        api.render(ctx, S, D, c2w, opts=opts, out=out)
+        counted.append(ctx.frame_stats())
+    ctx.set_profiling(0)
+    for st, ct in zip(stages, counted):
+        for k in ("evaluations", "blends", "rays"):
+            st[k] = ct[k]
 
     def mean_stats(sts):
         keys = sts[0]["stage_ms"].keys()
@@ -118,17 +162,20 @@ def run_gpu(args):
                       for k in stages[0]["chunk_ms"][c]} for c in range(len(stages[0]["chunk_ms"]))],
     }
 
-    # roofline of the dominant kernel (largest per-frame stage time, one launch per frame for these)
-    dom = max(st_ms, key=lambda k: st_ms[k])
+    # roofline of the dominant kernel: the blend (one kernel per depth chunk) has the largest per-frame time of any
+    # single kernel; the depth-sort stage is longer only as the sum of ~30 sort, scan and gather launches
+    dom = "blend" if st_ms.get("blend", 0) > 0 else max(st_ms, key=lambda k: st_ms[k])
     launches = max(1, stages[0]["stage_launches"][dom])
     per_launch_ms = st_ms[dom] / launches
     G, N = scene.n, disp.n_views
     if dom == "blend":
         flops = (cnt["evaluations"] * FLOP_Q + cnt["blends"] * FLOP_BLEND) / launches
         ach = flops / (per_launch_ms * 1e-3) / 1e12
+        tr = measured_traffic("blend_kernel<false, 4>") if stages[0]["rays_per_lane"] == 4 else None
         roof = {"kernel": "blend", "bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
-                "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4), "traffic": None,
-                "per_launch_ms": round(per_launch_ms, 4)}
+                "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4),
+                "traffic": None if tr is None else round(tr), "per_launch_ms": round(per_launch_ms, 4),
+                "flop_per_launch": round(flops)}
     else:
         # HBM models: bytes each launch must move
         if dom == "tile_sort":
@@ -155,7 +202,7 @@ def run_gpu(args):
         api.render_standard(ctx, S, D, poses[0], out=out_std)
         torch.cuda.synchronize()
         ms, sst = [], []
-        ctx.set_profiling(True)
+        ctx.set_profiling(1)
         ts0 = time.perf_counter()
         for i in range(args.std_steps):
             e0 = torch.cuda.Event(enable_timing=True)
@@ -168,7 +215,7 @@ def run_gpu(args):
             ms.append(e0.elapsed_time(e1))
         torch.cuda.synchronize()
         ts1 = time.perf_counter()
-        ctx.set_profiling(False)
+        ctx.set_profiling(0)
         std_stage, std_cnt = mean_stats(sst)
         std_fps = args.std_steps / (ts1 - ts0)
         # the last standard frame and a DirectL frame of the same pose agree bit for bit
@@ -185,6 +232,115 @@ def run_gpu(args):
     D.close()
     ctx.close()
     return res, scene, disp, poses
+
+
+def run_backward(args):
+    """Form 3: one training step = DirectL forward, L1 loss against a target image, backward to the Gaussian
+    parameters, on 500k Gaussians and a 1920x1080 N=45 panel (target: the same scene with means + N(0, 0.01^2))."""
+    import numpy as np
+    import torch
+
+    from paper_2407_14053_amd import api, synth
+
+    disp = synth.make_named_display("fhd45")
+    scene = synth.make_scene("train500k")
+    target_scene = scene.subset(np.arange(scene.n))
+    target_scene.means = (scene.means + np.random.default_rng(1).normal(0, 0.01, scene.means.shape)).astype(np.float32)
+    ctx = api.Context(0)
+    S = api.Scene(ctx, scene.arrays())
+    T = api.Scene(ctx, target_scene.arrays())
+    D = api.Display(ctx, disp)
+    c2w = synth.pose_front(3.0)
+    target = api.render(ctx, T, D, c2w).clone()
+    n = target.numel()
+
+    def step():
+        out = api.render(ctx, S, D, c2w)
+        grad = torch.sign(out - target) / n
+        return api.render_backward(ctx, S, D, c2w, out, grad)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    ms_f, ms_s = [], []
+    for _ in range(args.bwd_steps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        out = api.render(ctx, S, D, c2w)
+        e1.record()
+        grad = torch.sign(out - target) / n
+        api.render_backward(ctx, S, D, c2w, out, grad)
+        e2.record()
+        e2.synchronize()
+        ms_f.append(e0.elapsed_time(e1))
+        ms_s.append(e0.elapsed_time(e2))
+    for x in (S, T, D):
+        x.close()
+    ctx.close()
+    fwd, tot = sum(ms_f) / len(ms_f), sum(ms_s) / len(ms_s)
+    print("training step: %.2f ms (forward %.2f ms)" % (tot, fwd), file=sys.stderr, flush=True)
+    return {"workload": "500k Gaussians (uniform [-2,2]^3), 1920x1080 N=45, L1 loss", "steps": args.bwd_steps,
+            "step_ms": round(tot, 3), "forward_ms": round(fwd, 3), "backward_ms": round(tot - fwd, 3),
+            "steps_per_s": round(1000.0 / tot, 3)}
+
+
+SERVING_SCENES = {"g500k": (500_000, 1004), "g1m": (1_000_000, 1005), "g2m": (2_000_000, 1006),
+                  "g3m": (3_000_000, 1007)}
+SERVING_DISPLAYS = ("fhd16", "uhd45", "8k60")
+
+
+def run_serving(args):
+    """Form 5: resident scenes, plans as HIP graphs, admission by device memory, several streams."""
+    import numpy as np
+    import torch
+
+    from paper_2407_14053_amd import api, serving, synth
+
+    ctx = api.Context(0)
+    srv = serving.Server(ctx, n_slots=args.serve_slots)
+    tb = time.perf_counter()
+    for name, (n, seed) in SERVING_SCENES.items():
+        srv.add_scene(name, synth.serving_scene(n, seed))
+    for name in SERVING_DISPLAYS:
+        srv.add_display(name, synth.make_named_display(name))
+    t_res = time.perf_counter() - tb
+    tb = time.perf_counter()
+    # one plan per pair, checked at eight orbit angles
+    probes = [synth.look_at_c2w((3.0 * math.sin(a), 0.0, 3.0 * math.cos(a))) for a in np.arange(8) * math.pi / 4]
+    srv.warm(log=lambda m: print("serving: " + m, file=sys.stderr, flush=True), probe_poses=probes)
+    t_warm = time.perf_counter() - tb
+    print("serving: resident in %.1f s, %d plans in %.1f s" % (t_res, len(srv.plans), t_warm), file=sys.stderr,
+          flush=True)
+    reqs = serving.poisson_requests(args.serve_requests, args.serve_rate, list(SERVING_SCENES), list(SERVING_DISPLAYS),
+                                    seed=2000)
+    def tidy(summ):
+        for k in ("frames_per_s", "p50_ms", "p99_ms", "service_p50_ms", "service_p99_ms", "hbm_high_water_gb",
+                  "budget_gb", "resident_scene_gb"):
+            summ[k] = round(summ[k], 3)
+        for v in summ["per_display"].values():
+            for k in list(v):
+                if k.endswith("_ms"):
+                    v[k] = round(v[k], 3)
+        print("serving at %.1f req/s: %.1f frames/s, p50 %.1f ms, p99 %.1f ms" % (
+            summ["rate_req_per_s"], summ["frames_per_s"], summ["p50_ms"], summ["p99_ms"]), file=sys.stderr, flush=True)
+        return summ
+
+    rep = srv.run(reqs, realtime=True)
+    summ = rep.summary()
+    summ.update({"rate_req_per_s": args.serve_rate, "slots": args.serve_slots, "plans_warm_s": round(t_warm, 2),
+                 "scenes": {k: v[0] for k, v in SERVING_SCENES.items()}, "displays": list(SERVING_DISPLAYS)})
+    tidy(summ)
+    # the same mix offered at 70% of the throughput just measured, where latency is not dominated by the queue
+    rate2 = round(0.7 * summ["frames_per_s"], 1)
+    reqs2 = serving.poisson_requests(args.serve_requests // 2, rate2, list(SERVING_SCENES), list(SERVING_DISPLAYS),
+                                     seed=2001)
+    s2 = srv.run(reqs2, realtime=True).summary()
+    s2["rate_req_per_s"] = rate2
+    summ["below_saturation"] = tidy(s2)
+    srv.close()
+    ctx.close()
+    torch.cuda.synchronize()
+    return summ
 
 
 def cpu_baseline(args, scene, disp, poses):
@@ -226,16 +382,30 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--std-steps", type=int, default=2)
     ap.add_argument("--tile", type=int, default=0, help="DirectL tile side (0 = automatic)")
-    ap.add_argument("--cpu-subpixels", type=int, default=1536)
+    ap.add_argument("--cpu-subpixels", type=int, default=200_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-standard", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--bwd-steps", type=int, default=5)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 256 MiB device-to-device 3 times (calibrates HBM byte counters)")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this renderer has no multi-GPU path (requested %d GPUs)"
               % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
     res, scene, disp, poses = run_gpu(args)
+    if not args.no_backward:
+        res["training_step"] = run_backward(args)
+    if not args.no_serve:
+        res["serving"] = run_serving(args)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(args, scene, disp, poses)
     print(json.dumps(res), flush=True)

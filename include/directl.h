@@ -213,7 +213,8 @@ enum {
  * stage_ms: summed HIP-event durations per stage on the render stream; stage_launches: occurrences.
  * keys: the largest number of (view, tile) list entries of one depth chunk; visible: (view, Gaussian) pairs
  * that reach the screen;
- * evaluations: (ray, list entry) pairs the blend examined; blends: pairs composited; rays: rays rendered. */
+ * evaluations: (ray, list entry) pairs the blend examined; blends: pairs composited; rays: rays rendered
+ * (these three are zero unless profiling is at level 2). */
 #define DL_MAX_CHUNKS 8
 typedef struct {
   double stage_ms[DL_NSTAGES];
@@ -224,8 +225,10 @@ typedef struct {
   double chunk_ms[DL_MAX_CHUNKS][DL_NSTAGES];   /* stage_ms split by depth chunk (frame-level stages in 0) */
 } dl_frame_stats;
 
-/* Turn per-stage HIP-event timing and work counters on or off for subsequent frames of this context. */
-int dl_set_profiling(dl_ctx* ctx, int enable);
+/* Profiling of subsequent frames of this context: 0 off; 1 per-stage HIP-event timing (a few events per
+ * stage, negligible cost); 2 timing plus the blend's work counters (evaluations, blends, rays), which cost
+ * atomics in the blend kernel — time with level 1, count with level 2.  Other levels: DL_EINVAL. */
+int dl_set_profiling(dl_ctx* ctx, int level);
 /* Read the measurements of the last profiled frame (synchronises on its events). */
 int dl_frame_stats_get(dl_ctx* ctx, dl_frame_stats* out);
 

@@ -180,8 +180,10 @@ class Context:
     def key_capacity(self) -> int:
         return int(load().dl_key_capacity(self.h))
 
-    def set_profiling(self, on: bool):
-        _check(load().dl_set_profiling(self.h, int(bool(on))))
+    def set_profiling(self, level):
+        """0/False off, 1 stage timing, 2/True timing and blend work counters."""
+        level = 2 if level is True else int(level)
+        _check(load().dl_set_profiling(self.h, level))
 
     def frame_stats(self) -> dict:
         st = dl_frame_stats()

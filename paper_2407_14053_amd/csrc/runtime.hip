@@ -104,8 +104,8 @@ struct dl_ctx {
       state, dtotal, nkeys, gacc;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
   double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
-  // profiling: HIP events around each stage of the last frame, and work counters
-  bool prof = false;
+  // profiling: 0 off, 1 HIP events around each stage of the last frame, 2 events and work counters
+  int prof = 0;
   struct Mark {
     int stage, chunk;
     hipEvent_t a, b;
@@ -386,7 +386,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   const int64_t hs = std::max(radix_hist_size(G, N), radix_hist_size(cap, 1));
   HIP_TRY(C->hist.ensure((size_t)hs * 4));
   HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, N * max_stride)) + 2) * 4));
-  if (C->prof) HIP_TRY(C->stats.ensure((size_t)kStatSlots * 3 * 8));
+  if (C->prof >= 2) HIP_TRY(C->stats.ensure((size_t)kStatSlots * 3 * 8));
   if (bwd) {
     HIP_TRY(C->gacc.ensure((size_t)NG * 9 * 4));
     HIP_TRY(hipMemsetAsync(C->gacc.p, 0, (size_t)NG * 9 * 4, s));
@@ -397,7 +397,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   if (mode.upload)
     HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(launch_fill_u64(C->dtotal.as<unsigned long long>(), 2, 0ull, s));
-  if (C->prof) HIP_TRY(launch_fill_u64(C->stats.as<unsigned long long>(), kStatSlots * 3, 0ull, s));
+  if (C->prof >= 2) HIP_TRY(launch_fill_u64(C->stats.as<unsigned long long>(), kStatSlots * 3, 0ull, s));
   HIP_TRY(launch_init_alive(C->alive.as<uint8_t>(), standard ? nullptr : L->off.as<uint32_t>(), NT, s));
   C->end(mk, s);
 
@@ -446,7 +446,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   bc.alpha_max = o.alpha_max;
   bc.t_min = o.t_min;
   for (int k = 0; k < 3; ++k) bc.bg[k] = o.bg[k];
-  bc.stats = C->prof ? C->stats.as<unsigned long long>() : nullptr;
+  bc.stats = C->prof >= 2 ? C->stats.as<unsigned long long>() : nullptr;
   int bits = 1;
   while ((1ll << bits) < NT) ++bits;
   unsigned long long* total = C->dtotal.as<unsigned long long>();
@@ -923,9 +923,10 @@ int dl_set_key_capacity(dl_ctx* C, int64_t keys) {
 
 int64_t dl_key_capacity(const dl_ctx* C) { return C ? (int64_t)C->key_cap : -1; }
 
-int dl_set_profiling(dl_ctx* C, int enable) {
+int dl_set_profiling(dl_ctx* C, int level) {
   if (!C) return fail(DL_EINVAL, "NULL context");
-  C->prof = enable != 0;
+  if (level < 0 || level > 2) return fail(DL_EINVAL, "profiling level is 0, 1 or 2");
+  C->prof = level;
   return DL_OK;
 }
 
@@ -944,7 +945,7 @@ int dl_frame_stats_get(dl_ctx* C, dl_frame_stats* out) {
     }
   }
   unsigned long long st[3] = {0, 0, 0};
-  if (C->stats.p) {
+  if (C->prof >= 2 && C->stats.p) {
     std::vector<unsigned long long> sl((size_t)kStatSlots * 3);
     HIP_TRY(hipMemcpy(sl.data(), C->stats.p, sl.size() * 8, hipMemcpyDeviceToHost));
     for (int i = 0; i < kStatSlots; ++i)

@@ -2,10 +2,11 @@
 
 Each request names a resident scene, a display and a centre-camera pose.  Frames are rendered by plans
 (fixed-buffer DirectL frames replayed as HIP graphs, one plan per (scene, display) pair, more than one when the
-same pair is in flight twice).  The loop admits requests against a device-memory budget: a new plan is created
-only when its bytes fit beside the resident scenes and the plans already held, after evicting idle plans in
-least-recently-used order; a request that cannot get a plan waits (it is counted as deferred).  Admitted frames
-run concurrently on a few streams; each request's latency runs from its arrival to the completion of its frame.
+same pair is in flight twice and memory is spare).  The loop admits requests against a device-memory budget: a
+pair's first plan is created when its bytes fit beside the resident scenes and the plans already held, after
+evicting idle plans of other pairs in least-recently-used order; a request that cannot get a plan waits (counted
+as deferred when it waited for memory) while later requests of other pairs go ahead.  Admitted frames run
+concurrently on a few streams; each request's latency runs from its arrival to the completion of its frame.
 
 Everything the GPU does goes through the C ABI (`api.Plan`); this module only schedules.
 """
@@ -88,6 +89,7 @@ class Report:
     wall_s: float
     admitted: int
     deferred: int
+    waited: int
     replans: int
     plans_created: int
     plans_evicted: int
@@ -98,13 +100,17 @@ class Report:
 
     def summary(self) -> dict:
         lat = np.array([d.latency_ms for d in self.done]) if self.done else np.zeros(1)
+        svc = np.array([1e3 * (d.finished - d.launched) for d in self.done]) if self.done else np.zeros(1)
         out = {
             "requests": len(self.done),
             "frames_per_s": len(self.done) / self.wall_s if self.wall_s > 0 else 0.0,
             "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)),
+            "service_p50_ms": float(np.percentile(svc, 50)),
+            "service_p99_ms": float(np.percentile(svc, 99)),
             "admitted": self.admitted,
             "deferred": self.deferred,
+            "waited_for_plan": self.waited,
             "replans": self.replans,
             "plans_created": self.plans_created,
             "plans_evicted": self.plans_evicted,
@@ -115,7 +121,9 @@ class Report:
         per = {}
         for name in sorted({d.display for d in self.done}):
             l = np.array([d.latency_ms for d in self.done if d.display == name])
-            per[name] = {"n": int(l.size), "p50_ms": float(np.percentile(l, 50)), "p99_ms": float(np.percentile(l, 99))}
+            v = np.array([1e3 * (d.finished - d.launched) for d in self.done if d.display == name])
+            per[name] = {"n": int(l.size), "p50_ms": float(np.percentile(l, 50)), "p99_ms": float(np.percentile(l, 99)),
+                         "service_p50_ms": float(np.percentile(v, 50)), "service_p99_ms": float(np.percentile(v, 99))}
         out["per_display"] = per
         return out
 
@@ -198,13 +206,22 @@ class Server:
         return True
 
     def _get_plan(self, key, stream):
+        """An idle plan of the pair, or a new one; (None, reason) when the request has to wait.  A pair's first
+        plan may evict idle plans of other pairs; further plans of a pair (for overlapping requests) are made only
+        from unused budget, so busy pairs never push other pairs out."""
+        have = False
         for e in self.plans.values():
-            if e.key == key and not e.busy:
-                self.plans.move_to_end(id(e))
-                return e
+            if e.key == key:
+                have = True
+                if not e.busy:
+                    self.plans.move_to_end(id(e))
+                    return e, None
         need = self._estimate(key)
-        if not self._evict_for(need):
-            return None
+        if have:
+            if self._used() + need > self.budget:
+                return None, "busy"
+        elif not self._evict_for(need):
+            return None, "memory"
         plan = api.Plan(self.ctx, self.scenes[key[0]], self.displays[key[1]], self.probe_c2w, opts=self.opts,
                         min_key_capacity=self.min_keys.get(key, 0), stream=stream)
         e = _PlanEntry(key, plan)
@@ -213,18 +230,33 @@ class Server:
         self.plan_bytes += e.bytes
         self.created += 1
         self._sample_memory()
-        if self._used() > self.budget and not self._evict_for(0):
-            pass  # the plan was larger than estimated; idle plans are gone and this one is kept
-        return e
+        return e, None
 
-    def warm(self, keys=None) -> None:
-        """Create one plan per (scene, display) pair (or those in `keys`) before timing, as far as the budget allows."""
+    def warm(self, keys=None, log=None, probe_poses=()) -> None:
+        """Create one plan per (scene, display) pair (or those in `keys`) before timing, as far as the budget allows.
+        Each plan is also run at `probe_poses`; a plan that overflows there is rebuilt with room for them."""
         keys = keys or [(s, d) for s in self.scenes for d in self.displays]
         s = self.slots[0].stream
         for k in keys:
-            e = self._get_plan(k, s)
+            e, _ = self._get_plan(k, s)
             if e is None:
                 break
+            for attempt in range(2):
+                worst_ok = True
+                for c2w in probe_poses:
+                    e.plan.launch(c2w, stream=s)
+                    s.synchronize()
+                    ok, need = e.plan.check()
+                    self.min_keys[k] = max(self.min_keys.get(k, 0), need + need * 3 // 10 + 4096)
+                    worst_ok &= ok
+                if worst_ok:
+                    break
+                del self.plans[id(e)]
+                self.plan_bytes -= e.bytes
+                e.plan.close()
+                e, _ = self._get_plan(k, s)
+            if log:
+                log("plan %s/%s: %.2f GB" % (k[0], k[1], e.bytes / 2**30))
         self.torch.cuda.synchronize()
 
     # ---- the loop ----
@@ -234,9 +266,11 @@ class Server:
         pending = deque(dataclasses.replace(r) for r in sorted(requests, key=lambda r: r.arrival))
         queue: deque = deque()
         done: list = []
-        deferred_ids: set = set()
+        deferred_ids: set = set()  # waited for device memory
+        waited_ids: set = set()  # waited for a busy plan of their pair
         replans = {}
         admitted = 0
+        created0, evicted0 = self.created, self.evicted
         t0 = time.perf_counter()
         base = pending[0].arrival if pending else 0.0
         now = lambda: time.perf_counter() - t0  # noqa: E731
@@ -257,9 +291,10 @@ class Server:
                 ok, need = e.plan.check()
                 e.busy = False
                 sl.req = sl.entry = None
+                # plans made later for this pair get 30% headroom over the largest chunk seen so far
+                self.min_keys[e.key] = max(self.min_keys.get(e.key, 0), need + need * 3 // 10 + 4096)
                 if not ok:
                     # the frame overflowed the plan's tile-key capacity: replace the plan and serve the request again
-                    self.min_keys[e.key] = need + need * 3 // 10 + 4096
                     del self.plans[id(e)]
                     self.plan_bytes -= e.bytes
                     e.plan.close()
@@ -276,9 +311,9 @@ class Server:
                 r = queue[i]
                 sl = free[0]
                 key = (r.scene, r.display)
-                e = self._get_plan(key, sl.stream)
+                e, why = self._get_plan(key, sl.stream)
                 if e is None:
-                    deferred_ids.add(r.rid)
+                    (deferred_ids if why == "memory" else waited_ids).add(r.rid)
                     i += 1
                     continue
                 del queue[i]
@@ -300,8 +335,9 @@ class Server:
         wall = now()
         self._sample_memory()
         return Report(done=sorted(done, key=lambda d: d.rid), wall_s=wall, admitted=admitted,
-                      deferred=len(deferred_ids), replans=sum(replans.values()), plans_created=self.created,
-                      plans_evicted=self.evicted, hbm_high_water=self.high_water, budget=self.budget,
+                      deferred=len(deferred_ids), waited=len(waited_ids), replans=sum(replans.values()),
+                      plans_created=self.created - created0,
+                      plans_evicted=self.evicted - evicted0, hbm_high_water=self.high_water, budget=self.budget,
                       resident_bytes=self.resident_bytes)
 
     def close(self):
