@@ -81,36 +81,37 @@ __device__ inline uint32_t wave_incl_scan_u32(uint32_t x, int lane) {
 struct WaveBin {
   float u[64], v[64], A[64], B[64], C[64], qlim[64], hA[64], hC[64];
   int tx0[64], ty0[64], wr[64];
-  uint32_t pre[64], g[64], run[64], end[64];
+  uint32_t pre[64];
 };
 
 // Each wavefront takes 64 consecutive depth ranks of one view (one per lane), computes every Gaussian's
 // tile rectangle, and then walks the flattened list of (Gaussian, tile of its rectangle) pairs 64 at a time,
-// so that a large splat is shared by all lanes instead of stalling one.  COUNT stores the number of live
-// tiles each Gaussian touches; EMIT writes its (view, tile) keys into the range given by the scanned
-// counts (the order inside one Gaussian's range is irrelevant: the stable sort that follows keeps
-// different Gaussians in depth order within every tile).
+// so that a large splat is shared by all lanes instead of stalling one.  Pairs are visited Gaussian by
+// Gaussian in rank order, and the hits of each step are compacted with a ballot, so the wavefront's keys come
+// out in rank order within every tile.  COUNT stores the number of keys of each wavefront; EMIT writes them
+// from the wavefront's scanned offset.  A view none of whose tiles is live (`live`, chunks after the first)
+// produces no keys and reads no records.
 template <bool EMIT>
-__global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ sorted_idx,
-                                                  const uint32_t* __restrict__ vis_count, BlendConst bc, ChunkArgs ch,
+__global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ vis_count,
+                                                  const uint32_t* __restrict__ live, BlendConst bc, ChunkArgs ch,
                                                   const uint8_t* __restrict__ alive, uint32_t* __restrict__ counts,
                                                   unsigned long long* __restrict__ total,
                                                   const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys,
                                                   uint32_t* __restrict__ vals) {
   __shared__ WaveBin wb[4];
+  __shared__ unsigned long long part[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   WaveBin& W = wb[w];
   const int v = blockIdx.y;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t wslot = (int64_t)v * ch.wstride + (idx >> 6);
+  const bool wave_in = (idx >> 6) < ch.wstride;
   const int64_t nv = vis_count[v];
   const int64_t lo = nv * ch.num_lo / ch.den, hi = nv * ch.num_hi / ch.den;
   const int64_t r = lo + idx;
-  const int64_t slot = (int64_t)v * ch.stride + idx;
+  const bool view_live = !live || live[v] != 0;
   uint32_t nt = 0;
-  W.run[lane] = 0;
-  W.end[lane] = 0;
-  if (idx < ch.stride && r < hi) {
-    const uint32_t g = (uint32_t)r;  // records are in depth-rank order; the list entry is the rank
+  if (view_live && idx < ch.stride && r < hi) {
     float rr[8];
     load_rec_geom(rec + ((int64_t)v * bc.G + r) * kRecF4, rr);
     TileRange tr;
@@ -126,15 +127,7 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
       W.tx0[lane] = tr.tx0;
       W.ty0[lane] = tr.ty0;
       W.wr[lane] = tr.tx1 - tr.tx0 + 1;
-      W.g[lane] = g;
       nt = (uint32_t)((tr.tx1 - tr.tx0 + 1) * (tr.ty1 - tr.ty0 + 1));
-      if (EMIT) {
-        // this Gaussian's keys end where the next slot's begin; nothing is written past the capacity
-        const uint32_t pos = offsets[slot];
-        const uint32_t nxt = slot + 1 < (int64_t)bc.N * ch.stride ? offsets[slot + 1] : 0xffffffffu;
-        W.run[lane] = pos;
-        W.end[lane] = min(min(nxt, ch.cap), pos + nt);
-      }
     }
   }
   const uint32_t incl = wave_incl_scan_u32(nt, lane);
@@ -142,12 +135,15 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
   const uint32_t S = __shfl(incl, 63, 64);
   __syncthreads();
 
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint32_t pos = EMIT && wave_in ? offsets[wslot] : 0u;  // next key of this wavefront
   const uint8_t* al = alive ? alive + (int64_t)v * bc.T : nullptr;
   for (uint32_t s0 = 0; s0 < S; s0 += 64) {
     const uint32_t p = s0 + (uint32_t)lane;
+    bool hit = false;
+    int i = 0, t = 0;
     if (p < S) {
       // the Gaussian owning pair p: the last lane i with pre[i] <= p (it has a non-empty rectangle)
-      int i = 0;
 #pragma unroll
       for (int step = 32; step >= 1; step >>= 1)
         if (i + step < 64 && W.pre[i + step] <= p) i += step;
@@ -155,37 +151,49 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
       const int wr = W.wr[i];
       const int row = q / wr;
       const int tx = W.tx0[i] + (q - row * wr), ty = W.ty0[i] + row;
-      const int t = ty * bc.ntx + tx;
-      bool hit = !al || al[t];
+      t = ty * bc.ntx + tx;
+      hit = !al || al[t];
       if (hit) {
         const float xlo = tx * bc.tw + 0.5f, xhi = min((tx + 1) * bc.tw, bc.W) - 0.5f;
         const float ylo = ty * bc.th + 0.5f, yhi = min((ty + 1) * bc.th, bc.H) - 0.5f;
         const float rr[8] = {W.u[i], W.v[i], W.A[i], W.B[i], W.C[i], W.qlim[i], 0.f, 0.f};
         hit = tile_touch(rr, W.hA[i], W.hC[i], xlo, xhi, ylo, yhi);
       }
-      if (hit) {
-        const uint32_t pos = atomicAdd(&W.run[i], 1u);
-        if (EMIT && pos < W.end[i]) {
-          keys[pos] = (uint32_t)v * (uint32_t)bc.T + (uint32_t)t;
-          vals[pos] = W.g[i];
-        }
+    }
+    const uint64_t bal = __ballot(hit);
+    if (EMIT && hit) {
+      const uint32_t at = pos + (uint32_t)__popcll(bal & below);
+      if (at < ch.cap) {
+        keys[at] = (uint32_t)v * (uint32_t)bc.T + (uint32_t)t;
+        vals[at] = (uint32_t)(lo + ((int64_t)blockIdx.x * blockDim.x + (w << 6) + i));  // depth rank
       }
     }
+    pos += (uint32_t)__popcll(bal);
   }
   if (!EMIT) {
-    __syncthreads();
-    const uint32_t cnt = W.run[lane];
-    if (idx < ch.stride) counts[slot] = cnt;
-    __shared__ unsigned long long part[4];
-    unsigned long long x = cnt;
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    if (lane == 0) part[w] = x;
+    if (lane == 0) {
+      if (wave_in) counts[wslot] = pos;
+      part[w] = pos;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       const unsigned long long sum = part[0] + part[1] + part[2] + part[3];
       if (sum) atomicAdd(total, sum);
     }
   }
+}
+
+// Live tiles of each view (one workgroup per view), read by the binning of the next depth chunk.
+__global__ __launch_bounds__(256) void view_live_kernel(const uint8_t* __restrict__ alive, int64_t T,
+                                                         uint32_t* __restrict__ live) {
+  __shared__ uint32_t part[4];
+  const int v = blockIdx.x;
+  uint32_t c = 0;
+  for (int64_t t = threadIdx.x; t < T; t += 256) c += alive[(int64_t)v * T + t];
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) live[v] = part[0] + part[1] + part[2] + part[3];
 }
 
 // n = min(total, cap); record the largest total seen and whether any chunk overflowed.
@@ -210,21 +218,26 @@ __global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long
 
 }  // namespace
 
-hipError_t launch_bin_count(const float4* rec, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                            const BlendConst& bc, const ChunkArgs& ch, const uint8_t* alive, uint32_t* counts,
-                            unsigned long long* total, hipStream_t s) {
+hipError_t launch_bin_count(const float4* rec, const uint32_t* vis_count, const uint32_t* live, const BlendConst& bc,
+                            const ChunkArgs& ch, const uint8_t* alive, uint32_t* counts, unsigned long long* total,
+                            hipStream_t s) {
   const dim3 grid((unsigned)((ch.stride + 255) / 256), (unsigned)bc.N);
-  hipLaunchKernelGGL(bin_kernel<false>, grid, dim3(256), 0, s, rec, sorted_idx, vis_count, bc, ch, alive, counts,
-                     total, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL(bin_kernel<false>, grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, counts, total,
+                     nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_bin_emit(const float4* rec, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                           const BlendConst& bc, const ChunkArgs& ch, const uint8_t* alive, const uint32_t* offsets,
-                           uint32_t* keys, uint32_t* vals, hipStream_t s) {
+hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const uint32_t* live, const BlendConst& bc,
+                           const ChunkArgs& ch, const uint8_t* alive, const uint32_t* offsets, uint32_t* keys,
+                           uint32_t* vals, hipStream_t s) {
   const dim3 grid((unsigned)((ch.stride + 255) / 256), (unsigned)bc.N);
-  hipLaunchKernelGGL(bin_kernel<true>, grid, dim3(256), 0, s, rec, sorted_idx, vis_count, bc, ch, alive, nullptr,
-                     nullptr, offsets, keys, vals);
+  hipLaunchKernelGGL(bin_kernel<true>, grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, nullptr, nullptr,
+                     offsets, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, hipStream_t s) {
+  hipLaunchKernelGGL(view_live_kernel, dim3((unsigned)N), dim3(256), 0, s, alive, T, live);
   return hipGetLastError();
 }
 

@@ -34,7 +34,14 @@ struct ProjConst {
   int sh_degree;
   double focal, cx, cy;
   float z_near, q_cut, alpha_min, alpha_max, dilation;
+  int key_e0;  // biased FP64 exponent of z_near: depth keys count exponents from it
 };
+
+// Depth keys: (exponent of z - key_e0, saturated at kDepthExpMax) << 36 | top 36 mantissa bits of the FP64 z.
+// Monotone in z (strictly, to 2^-36 relative, below 2^kDepthExpMax z_near); culled items carry kDepthCulled.
+constexpr int kDepthKeyBits = 41;
+constexpr int kDepthExpMax = 30;
+constexpr uint64_t kDepthCulled = (1ull << kDepthKeyBits) - 1;
 
 struct BlendConst {
   int W, H;
@@ -52,8 +59,9 @@ constexpr int kStatSlots = 1024;
 // Depth chunk: ranks [n_v num_lo / den, n_v num_hi / den) of every view; `stride` bounds its length.
 struct ChunkArgs {
   int64_t num_lo, num_hi, den;
-  int64_t stride;
-  uint32_t cap;  // key capacity
+  int64_t stride;   // item slots per view (a multiple of 64 is not required)
+  int64_t wstride;  // wavefront slots per view: ceil(stride / 64)
+  uint32_t cap;     // key capacity
 };
 
 // Per-chunk blend flags
@@ -80,6 +88,11 @@ int64_t radix_hist_size(int64_t seg_len, int n_seg);
 bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
                     const uint32_t* seg_n, uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial,
                     hipStream_t s, hipError_t* err);
+// As radix_sort_u64 over full segments, with the first pass leaving out items whose key is drop_key; kept[seg]
+// receives each segment's kept count (the sorted kept items occupy the front of the segment).
+bool radix_sort_u64_drop(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
+                         int bit_lo, int bit_hi, uint64_t drop_key, uint32_t* kept, uint32_t* hist, uint32_t* partial,
+                         hipStream_t s, hipError_t* err);
 bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
                     const uint32_t* seg_n, uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial,
                     hipStream_t s, hipError_t* err);
@@ -102,12 +115,14 @@ hipError_t launch_scene_transpose(const float* means, const float* log_scales, c
 // ---- binning (bin.hip) ----
 // counts[v][i] = live tiles touched by the Gaussian of depth rank lo_c(v) + i of view v; *total += sum.
 // `rec` holds the records in depth-rank order; emitted values are ranks.
-hipError_t launch_bin_count(const float4* rec, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                            const BlendConst& bc, const ChunkArgs& ch, const uint8_t* alive, uint32_t* counts,
-                            unsigned long long* total, hipStream_t s);
-hipError_t launch_bin_emit(const float4* rec, const uint32_t* sorted_idx, const uint32_t* vis_count,
-                           const BlendConst& bc, const ChunkArgs& ch, const uint8_t* alive, const uint32_t* offsets,
-                           uint32_t* keys, uint32_t* vals, hipStream_t s);
+// counts: one per wavefront of 64 ranks, [N][wstride]; live: live tiles per view (nullptr: all views live)
+hipError_t launch_bin_count(const float4* rec, const uint32_t* vis_count, const uint32_t* live, const BlendConst& bc,
+                            const ChunkArgs& ch, const uint8_t* alive, uint32_t* counts, unsigned long long* total,
+                            hipStream_t s);
+hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const uint32_t* live, const BlendConst& bc,
+                           const ChunkArgs& ch, const uint8_t* alive, const uint32_t* offsets, uint32_t* keys,
+                           uint32_t* vals, hipStream_t s);
+hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, hipStream_t s);
 hipError_t launch_finalize_count(const unsigned long long* total, uint32_t cap, uint32_t* n_out,
                                  unsigned long long* max_total, hipStream_t s);
 hipError_t launch_init_alive(uint8_t* alive, const uint32_t* ray_off, int64_t n, hipStream_t s);

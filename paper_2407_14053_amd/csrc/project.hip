@@ -5,7 +5,8 @@
 // perspective map, Sigma' = J W Sigma W^T J^T + h I, its inverse (the conic), the projected mean and the
 // cutoff ellipse, the depth key and the view-dependent colour.  Geometry runs in FP64 (the chip's vector
 // FP64 rate makes this free next to the memory traffic) and the record is rounded to FP32 once, so the
-// FP32 blend starts from correctly rounded inputs; depth keys keep 36 mantissa bits of the FP64 z.
+// FP32 blend starts from correctly rounded inputs; depth keys keep 36 mantissa bits of the FP64 z and its
+// exponent counted from that of z_near (41 bits: five radix passes).
 // The conic is stored pre-multiplied by log2(e)/2 (A, C) and log2(e) (B), so that the blend evaluates
 // alpha = o * 2^-(A dx^2 + B dx dy + C dy^2) with one hardware exp2.
 #include "dl_internal.h"
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
     const double Y = cam[3] * mx + cam[4] * my + cam[5] * mz + cam[10];
     const double Z = cam[6] * mx + cam[7] * my + cam[8] * mz + cam[11];
     bool vis = live && (Z > (double)pc.z_near) && (o32 >= pc.alpha_min);
-    uint64_t key = 0xffffffffffffull;
+    uint64_t key = kDepthCulled;
     float r[12];
     if (vis) {
       // T = J W, rows of the 2x3 product
@@ -142,8 +143,10 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
         r[2] = (float)(ks * cc * idet); r[3] = (float)(-2.0 * ks * cb * idet); r[4] = (float)(ks * ca * idet);
         r[5] = (float)(ks * qlim); r[6] = (float)ex; r[7] = (float)ey;
         r[8] = o32; r[9] = rgb[0]; r[10] = rgb[1]; r[11] = rgb[2];
-        uint64_t zb = (uint64_t)__double_as_longlong(Z);
-        key = zb >> 16;
+        const uint64_t zb = (uint64_t)__double_as_longlong(Z);
+        const int e = (int)(zb >> 52) - pc.key_e0;  // >= 0 since Z > z_near
+        key = e > kDepthExpMax ? (((uint64_t)(kDepthExpMax + 1) << 36) - 1)
+                               : (((uint64_t)e << 36) | ((zb >> 16) & ((1ull << 36) - 1)));
       }
     }
     const int64_t o = (int64_t)v * pc.G + i;
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(256) void gather_records_kernel(const float4* __res
   dst[2] = src[2];
 }
 
-// Visible Gaussians of view v = position of the first culled key (all 48 bits set) in its sorted segment.
+// Visible Gaussians of view v = position of the first culled key in its sorted segment.
 __global__ __launch_bounds__(64) void count_visible_kernel(const uint64_t* __restrict__ sorted_keys, int64_t G, int N,
                                                            uint32_t* __restrict__ vis_count) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(64) void count_visible_kernel(const uint64_t* __res
   int64_t lo = 0, hi = G;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if (k[mid] < 0xffffffffffffull) lo = mid + 1;
+    if (k[mid] < kDepthCulled) lo = mid + 1;
     else hi = mid;
   }
   vis_count[v] = (uint32_t)lo;

@@ -100,6 +100,7 @@ struct RayLists {
 
 struct dl_ctx {
   int device = 0;
+  DevBuf live;  // live tiles per view after the last blended chunk
   DevBuf cams, rec, srec, k64[2], v32[2], vis, counts, bk[2], bv[2], hist, partial, tstart, views, stats, alive,
       state, dtotal, nkeys, gacc;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
@@ -327,6 +328,13 @@ constexpr int kChunkBounds[] = {0, 64, 128, 256, 512, 1024};
 constexpr int kChunks = sizeof(kChunkBounds) / sizeof(kChunkBounds[0]) - 1;
 constexpr uint32_t kMaxKeyCap = 0x7fffffffu;
 
+int depth_key_e0(float z_near) {
+  uint64_t b;
+  const double z = (double)z_near;
+  std::memcpy(&b, &z, 8);
+  return (int)(b >> 52);
+}
+
 int64_t chunk_stride(int64_t G, int c) { return G * (kChunkBounds[c + 1] - kChunkBounds[c]) / kChunkDen + 1; }
 
 // How a frame is issued: eager frames upload their cameras and end with the overflow check; a frame being
@@ -373,7 +381,9 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   HIP_TRY(C->v32[0].ensure((size_t)NG * 4));
   HIP_TRY(C->v32[1].ensure((size_t)NG * 4));
   HIP_TRY(C->vis.ensure(256 * 4));
-  HIP_TRY(C->counts.ensure((size_t)N * max_stride * 4));
+  const int64_t max_wstride = (max_stride + 63) / 64;
+  HIP_TRY(C->counts.ensure((size_t)N * max_wstride * 4));
+  HIP_TRY(C->live.ensure((size_t)N * 4));
   HIP_TRY(C->bk[0].ensure((size_t)cap * 4));
   HIP_TRY(C->bk[1].ensure((size_t)cap * 4));
   HIP_TRY(C->bv[0].ensure((size_t)cap * 4));
@@ -385,7 +395,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   HIP_TRY(C->nkeys.ensure(4));
   const int64_t hs = std::max(radix_hist_size(G, N), radix_hist_size(cap, 1));
   HIP_TRY(C->hist.ensure((size_t)hs * 4));
-  HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, N * max_stride)) + 2) * 4));
+  HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, N * max_wstride)) + 2) * 4));
   if (C->prof >= 2) HIP_TRY(C->stats.ensure((size_t)kStatSlots * 3 * 8));
   if (bwd) {
     HIP_TRY(C->gacc.ensure((size_t)NG * 9 * 4));
@@ -416,17 +426,18 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   pc.alpha_min = o.alpha_min;
   pc.alpha_max = o.alpha_max;
   pc.dilation = o.dilation;
+  pc.key_e0 = depth_key_e0(o.z_near);
   mk = C->begin(DL_STAGE_PROJECT, s);
   HIP_TRY(launch_project(S->soa.as<float>(), C->cams.as<double>(), pc, C->rec.as<float4>(), C->k64[0].as<uint64_t>(),
                          C->v32[0].as<uint32_t>(), nullptr, s));
   C->end(mk, s);
   hipError_t e;
   mk = C->begin(DL_STAGE_DEPTH_SORT, s);
-  bool fl = radix_sort_u64(C->k64[0].as<uint64_t>(), C->v32[0].as<uint32_t>(), C->k64[1].as<uint64_t>(),
-                           C->v32[1].as<uint32_t>(), G, N, nullptr, 0, 0, 48, C->hist.as<uint32_t>(),
-                           C->partial.as<uint32_t>(), s, &e);
+  // culled items are left out by the first pass; vis[v] = visible Gaussians of view v
+  bool fl = radix_sort_u64_drop(C->k64[0].as<uint64_t>(), C->v32[0].as<uint32_t>(), C->k64[1].as<uint64_t>(),
+                                C->v32[1].as<uint32_t>(), G, N, 0, kDepthKeyBits, kDepthCulled,
+                                C->vis.as<uint32_t>(), C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s, &e);
   if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
-  HIP_TRY(launch_count_visible(fl ? C->k64[1].as<uint64_t>() : C->k64[0].as<uint64_t>(), G, N, C->vis.as<uint32_t>(), s));
   const uint32_t* sorted = fl ? C->v32[1].as<uint32_t>() : C->v32[0].as<uint32_t>();
   HIP_TRY(launch_gather_records(C->rec.as<float4>(), sorted, C->vis.as<uint32_t>(), G, N, C->srec.as<float4>(), s));
   C->end(mk, s);
@@ -457,11 +468,14 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     ch.num_hi = kChunkBounds[c + 1];
     ch.den = kChunkDen;
     ch.stride = chunk_stride(G, c);
+    ch.wstride = (ch.stride + 63) / 64;
     ch.cap = cap;
-    const int64_t ncount = (int64_t)N * ch.stride;
+    const int64_t ncount = (int64_t)N * ch.wstride;
+    // views with no live tile left produce no keys in this chunk (the first chunk has every tile live)
+    const uint32_t* live = c > 0 ? C->live.as<uint32_t>() : nullptr;
     mk = C->begin(DL_STAGE_BIN_COUNT, s);
     HIP_TRY(launch_fill_u64(total, 1, 0ull, s));
-    HIP_TRY(launch_bin_count(C->srec.as<float4>(), sorted, C->vis.as<uint32_t>(), bc, ch, C->alive.as<uint8_t>(),
+    HIP_TRY(launch_bin_count(C->srec.as<float4>(), C->vis.as<uint32_t>(), live, bc, ch, C->alive.as<uint8_t>(),
                              C->counts.as<uint32_t>(), total, s));
     C->end(mk, s);
     mk = C->begin(DL_STAGE_SCAN, s);
@@ -469,7 +483,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     HIP_TRY(launch_finalize_count(total, cap, C->nkeys.as<uint32_t>(), total + 1, s));
     C->end(mk, s);
     mk = C->begin(DL_STAGE_BIN_EMIT, s);
-    HIP_TRY(launch_bin_emit(C->srec.as<float4>(), sorted, C->vis.as<uint32_t>(), bc, ch, C->alive.as<uint8_t>(),
+    HIP_TRY(launch_bin_emit(C->srec.as<float4>(), C->vis.as<uint32_t>(), live, bc, ch, C->alive.as<uint8_t>(),
                             C->counts.as<uint32_t>(), C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), s));
     C->end(mk, s);
     mk = C->begin(DL_STAGE_TILE_SORT, s);
@@ -498,6 +512,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                                    L->ent.as<uint32_t>(), L->max_rays, bc, bk, C->alive.as<uint8_t>(),
                                    C->state.as<float4>(), out, s));
     }
+    if (c + 1 < kChunks) HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), s));
     C->end(mk, s);
   }
   if (bwd) {
@@ -737,6 +752,7 @@ int dl_project(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose*
   pc.alpha_min = o.alpha_min;
   pc.alpha_max = o.alpha_max;
   pc.dilation = o.dilation;
+  pc.key_e0 = depth_key_e0(o.z_near);
   HIP_TRY(launch_project(S->soa.as<float>(), C->cams.as<double>(), pc, (float4*)out_dev, C->k64[0].as<uint64_t>(),
                          C->v32[0].as<uint32_t>(), depth_dev, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -793,7 +809,7 @@ namespace {
 size_t ctx_bytes(const dl_ctx* C) {
   const DevBuf* b[] = {&C->cams, &C->rec, &C->srec, &C->k64[0], &C->k64[1], &C->v32[0], &C->v32[1], &C->vis,
                        &C->counts, &C->bk[0], &C->bk[1], &C->bv[0], &C->bv[1], &C->hist, &C->partial, &C->tstart,
-                       &C->views, &C->stats, &C->alive, &C->state, &C->dtotal, &C->nkeys, &C->gacc};
+                       &C->views, &C->stats, &C->alive, &C->state, &C->dtotal, &C->nkeys, &C->gacc, &C->live};
   size_t t = 0;
   for (const DevBuf* x : b) t += x->cap;
   return t;

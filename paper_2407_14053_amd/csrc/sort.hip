@@ -2,7 +2,9 @@
 //
 // Sort structure: n_seg segments of static length seg_len, each sorted independently; the live length of a
 // segment may be given on the device (seg_n), so that launches have static grids (graph capture) while the
-// work follows the data.  A fixed number of blocks per segment each own one contiguous range of the segment.
+// work follows the data.  The first pass may also leave out every item with one given key (culled items):
+// the kept items of each segment are compacted to its front, their count written on the device, and later
+// passes only touch them.  A fixed number of blocks per segment each own one contiguous range of the segment.
 // Per pass:
 //   hist    : per block, counts of each digit (per-wavefront LDS counters, then summed)
 //   scan    : one exclusive scan over hist laid out [segment][digit][block] gives every block's first output
@@ -114,6 +116,8 @@ struct SortArgs {
   int bps;                // blocks per segment
   int shift, bits;
   uint32_t* hist;
+  int drop;               // this pass leaves out items whose key equals drop_key (the first pass only)
+  K drop_key;
 };
 
 template <typename K>
@@ -138,7 +142,9 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(SortArgs<K> a) {
   block_range(live_len(a, seg), a.bps, bis, lo, hi);
   const K* kin = a.kin + (int64_t)seg * a.seg_len;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-    const uint32_t d = (uint32_t)(kin[i] >> a.shift) & dmask;
+    const K k = kin[i];
+    if (a.drop && k == a.drop_key) continue;
+    const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
     atomicAdd(&h[w][d], 1u);
   }
   __syncthreads();
@@ -186,9 +192,10 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
       const int li = w * (kRows * 64) + r * 64 + lane;
-      const bool valid = li < tn;
+      bool valid = li < tn;
       key[r] = valid ? kin[t0 + li] : (K)0;
       val[r] = valid ? vin[t0 + li] : 0u;
+      if (a.drop && key[r] == a.drop_key) valid = false;
       const uint32_t d = (uint32_t)(key[r] >> a.shift) & dmask;
       dig[r] = d;
       uint64_t m = __ballot(valid);
@@ -248,8 +255,8 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
       }
     }
     __syncthreads();
-    // contiguous runs per digit: consecutive lanes write consecutive addresses
-    for (int p = threadIdx.x; p < tn; p += kThreads) {
+    // contiguous runs per digit: consecutive lanes write consecutive addresses (`total` = kept items)
+    for (int p = threadIdx.x; p < (int)total; p += kThreads) {
       const K k = skey[p];
       const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
       const uint32_t g = run[d] + (uint32_t)p - loff[d];
@@ -261,6 +268,17 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
     if (d1 < radix) run[d1] += tot1;
     __syncthreads();
   }
+}
+
+// Items kept per segment by a dropping pass, from its scanned histogram ([segment][digit][block], exclusive)
+// and the scan's grand total.
+__global__ void segment_counts_kernel(const uint32_t* __restrict__ hist, const uint32_t* __restrict__ grand_total,
+                                      int n_seg, int64_t per_seg, uint32_t* __restrict__ counts) {
+  const int seg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg >= n_seg) return;
+  const uint32_t a = hist[(int64_t)seg * per_seg];
+  const uint32_t b = seg + 1 < n_seg ? hist[(int64_t)(seg + 1) * per_seg] : *grand_total;
+  counts[seg] = b - a;
 }
 
 __global__ __launch_bounds__(kThreads) void lower_bounds_kernel(const uint32_t* __restrict__ keys,
@@ -289,12 +307,12 @@ int blocks_per_seg(int64_t seg_len, int n_seg) {
 template <typename K>
 bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, int n_seg, const uint32_t* seg_n,
                      uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial, hipStream_t s,
-                     hipError_t* err) {
+                     hipError_t* err, const K* drop_key = nullptr, uint32_t* kept = nullptr) {
   *err = hipSuccess;
   if (seg_len == 0 || n_seg == 0 || bit_hi <= bit_lo) return false;
   const int bps = blocks_per_seg(seg_len, n_seg);
   const int64_t nblocks = (int64_t)bps * n_seg;
-  // split the bit range into the fewest passes of at most 8 bits, as even as possible
+  // split the bit range into the fewest passes of at most kMaxBits bits, as even as possible
   const int nbits = bit_hi - bit_lo;
   const int passes = (nbits + kMaxBits - 1) / kMaxBits;
   bool flipped = false;
@@ -313,10 +331,22 @@ bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, 
     a.shift = shift;
     a.bits = bits;
     a.hist = hist;
+    a.drop = (p == 0 && drop_key) ? 1 : 0;
+    a.drop_key = drop_key ? *drop_key : (K)0;
+    if (p > 0 && drop_key) {
+      // after the dropping pass every segment holds only its kept items
+      a.seg_n = kept;
+      a.cap = (uint32_t)std::min<int64_t>(seg_len, 0xffffffffll);
+    }
     const int64_t hsize = (int64_t)n_seg * (1 << bits) * bps;
     hipLaunchKernelGGL(radix_hist_kernel<K>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
     if ((*err = hipGetLastError()) != hipSuccess) return flipped;
     if ((*err = exclusive_scan_u32(hist, hist, hsize, partial, s)) != hipSuccess) return flipped;
+    if (a.drop) {
+      hipLaunchKernelGGL(segment_counts_kernel, dim3((unsigned)((n_seg + 63) / 64)), dim3(64), 0, s, hist,
+                         partial + scan_partial_count(hsize), n_seg, (int64_t)(1 << bits) * bps, kept);
+      if ((*err = hipGetLastError()) != hipSuccess) return flipped;
+    }
     hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
     if ((*err = hipGetLastError()) != hipSuccess) return flipped;
     flipped = !flipped;
@@ -347,6 +377,13 @@ bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int6
                     hipStream_t s, hipError_t* err) {
   return radix_sort_impl<uint64_t>(k0, v0, k1, v1, seg_len, n_seg, seg_n, cap, bit_lo, bit_hi, hist, partial, s,
                                    err);
+}
+
+bool radix_sort_u64_drop(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
+                         int bit_lo, int bit_hi, uint64_t drop_key, uint32_t* kept, uint32_t* hist, uint32_t* partial,
+                         hipStream_t s, hipError_t* err) {
+  return radix_sort_impl<uint64_t>(k0, v0, k1, v1, seg_len, n_seg, nullptr, 0, bit_lo, bit_hi, hist, partial, s, err,
+                                   &drop_key, kept);
 }
 
 bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
