@@ -171,7 +171,7 @@ def run_gpu(args):
     if dom == "blend":
         flops = (cnt["evaluations"] * FLOP_Q + cnt["blends"] * FLOP_BLEND) / launches
         ach = flops / (per_launch_ms * 1e-3) / 1e12
-        tr = measured_traffic("blend_kernel<false, 4>") if stages[0]["rays_per_lane"] == 4 else None
+        tr = measured_traffic("blend_kernel<false, 4, false>") if stages[0]["rays_per_lane"] == 4 else None
         roof = {"kernel": "blend", "bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4),
                 "traffic": None if tr is None else round(tr), "per_launch_ms": round(per_launch_ms, 4),

@@ -1,8 +1,9 @@
 // Tile binning of the depth-sorted projected Gaussians of each view, one depth chunk at a time (gfx950).
 //
-// Input order is (view, depth rank), so emitting (key = view * T + tile, value = rank) pairs in that
-// order and then partitioning them by key with a stable radix sort yields every (view, tile) list already in
-// front-to-back order: the depth digits were sorted before the Gaussians were duplicated into tiles.
+// Input order is (view, depth rank), so emitting (key = tile, value = rank) pairs in that order — each view's
+// pairs in one contiguous range — and then partitioning every view's range by tile with a stable radix pass
+// yields every (view, tile) list already in front-to-back order: the depth digits were sorted before the
+// Gaussians were duplicated into tiles.
 //
 // Depth chunks: chunk c of view v holds the visible Gaussians of depth rank [n_v lo_c, n_v hi_c) / den.
 // Chunks are binned and blended front to back; a tile whose rays have all terminated is marked dead by the
@@ -103,83 +104,111 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   WaveBin& W = wb[w];
   const int v = blockIdx.y;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t wslot = (int64_t)v * ch.wstride + (idx >> 6);
-  const bool wave_in = (idx >> 6) < ch.wstride;
   const int64_t nv = vis_count[v];
   const int64_t lo = nv * ch.num_lo / ch.den, hi = nv * ch.num_hi / ch.den;
-  const int64_t r = lo + idx;
   const bool view_live = !live || live[v] != 0;
-  uint32_t nt = 0;
-  if (view_live && idx < ch.stride && r < hi) {
-    float rr[8];
-    load_rec_geom(rec + ((int64_t)v * bc.G + r) * kRecF4, rr);
-    TileRange tr;
-    if (tile_range(rr, bc, tr)) {
-      W.u[lane] = rr[0];
-      W.v[lane] = rr[1];
-      W.A[lane] = rr[2];
-      W.B[lane] = rr[3];
-      W.C[lane] = rr[4];
-      W.qlim[lane] = rr[5];
-      W.hA[lane] = 0.5f / rr[2];
-      W.hC[lane] = 0.5f / rr[4];
-      W.tx0[lane] = tr.tx0;
-      W.ty0[lane] = tr.ty0;
-      W.wr[lane] = tr.tx1 - tr.tx0 + 1;
-      nt = (uint32_t)((tr.tx1 - tr.tx0 + 1) * (tr.ty1 - tr.ty0 + 1));
-    }
-  }
-  const uint32_t incl = wave_incl_scan_u32(nt, lane);
-  W.pre[lane] = incl - nt;
-  const uint32_t S = __shfl(incl, 63, 64);
-  __syncthreads();
-
+  const int64_t groups = (ch.stride + 255) / 256;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-  uint32_t pos = EMIT && wave_in ? offsets[wslot] : 0u;  // next key of this wavefront
   const uint8_t* al = alive ? alive + (int64_t)v * bc.T : nullptr;
-  for (uint32_t s0 = 0; s0 < S; s0 += 64) {
-    const uint32_t p = s0 + (uint32_t)lane;
-    bool hit = false;
-    int i = 0, t = 0;
-    if (p < S) {
-      // the Gaussian owning pair p: the last lane i with pre[i] <= p (it has a non-empty rectangle)
+  if (!view_live) {
+    // no live tile: no keys; the count pass still owes a zero per wavefront slot
+    if (!EMIT)
+      for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < ch.wstride; j += (int64_t)gridDim.x * 256)
+        counts[(int64_t)v * ch.wstride + j] = 0;
+    return;
+  }
+  unsigned long long block_sum = 0;
+  // groups of 256 consecutive ranks, strided over the view's workgroups
+  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+    const int64_t idx = grp * 256 + threadIdx.x;
+    const int64_t wslot = (int64_t)v * ch.wstride + (idx >> 6);
+    const bool wave_in = (idx >> 6) < ch.wstride;
+    const int64_t r = lo + idx;
+    uint32_t nt = 0;
+    if (idx < ch.stride && r < hi) {
+      float rr[8];
+      load_rec_geom(rec + ((int64_t)v * bc.G + r) * kRecF4, rr);
+      TileRange tr;
+      if (tile_range(rr, bc, tr)) {
+        W.u[lane] = rr[0];
+        W.v[lane] = rr[1];
+        W.A[lane] = rr[2];
+        W.B[lane] = rr[3];
+        W.C[lane] = rr[4];
+        W.qlim[lane] = rr[5];
+        W.hA[lane] = 0.5f / rr[2];
+        W.hC[lane] = 0.5f / rr[4];
+        W.tx0[lane] = tr.tx0;
+        W.ty0[lane] = tr.ty0;
+        W.wr[lane] = tr.tx1 - tr.tx0 + 1;
+        nt = (uint32_t)((tr.tx1 - tr.tx0 + 1) * (tr.ty1 - tr.ty0 + 1));
+      }
+    }
+    const uint32_t incl = wave_incl_scan_u32(nt, lane);
+    W.pre[lane] = incl - nt;
+    const uint32_t S = __shfl(incl, 63, 64);
+    __syncthreads();
+
+    uint32_t pos = EMIT && wave_in && S ? offsets[wslot] : 0u;  // next key of this wavefront
+    for (uint32_t s0 = 0; s0 < S; s0 += 64) {
+      const uint32_t p = s0 + (uint32_t)lane;
+      bool hit = false;
+      int i = 0, t = 0;
+      if (p < S) {
+        // the Gaussian owning pair p: the last lane i with pre[i] <= p (it has a non-empty rectangle)
 #pragma unroll
-      for (int step = 32; step >= 1; step >>= 1)
-        if (i + step < 64 && W.pre[i + step] <= p) i += step;
-      const int q = (int)(p - W.pre[i]);
-      const int wr = W.wr[i];
-      const int row = q / wr;
-      const int tx = W.tx0[i] + (q - row * wr), ty = W.ty0[i] + row;
-      t = ty * bc.ntx + tx;
-      hit = !al || al[t];
-      if (hit) {
-        const float xlo = tx * bc.tw + 0.5f, xhi = min((tx + 1) * bc.tw, bc.W) - 0.5f;
-        const float ylo = ty * bc.th + 0.5f, yhi = min((ty + 1) * bc.th, bc.H) - 0.5f;
-        const float rr[8] = {W.u[i], W.v[i], W.A[i], W.B[i], W.C[i], W.qlim[i], 0.f, 0.f};
-        hit = tile_touch(rr, W.hA[i], W.hC[i], xlo, xhi, ylo, yhi);
+        for (int step = 32; step >= 1; step >>= 1)
+          if (i + step < 64 && W.pre[i + step] <= p) i += step;
+        const int q = (int)(p - W.pre[i]);
+        const int wr = W.wr[i];
+        const int row = q / wr;
+        const int tx = W.tx0[i] + (q - row * wr), ty = W.ty0[i] + row;
+        t = ty * bc.ntx + tx;
+        hit = !al || al[t];
+        if (hit) {
+          const float xlo = tx * bc.tw + 0.5f, xhi = min((tx + 1) * bc.tw, bc.W) - 0.5f;
+          const float ylo = ty * bc.th + 0.5f, yhi = min((ty + 1) * bc.th, bc.H) - 0.5f;
+          const float rr[8] = {W.u[i], W.v[i], W.A[i], W.B[i], W.C[i], W.qlim[i], 0.f, 0.f};
+          hit = tile_touch(rr, W.hA[i], W.hC[i], xlo, xhi, ylo, yhi);
+        }
       }
-    }
-    const uint64_t bal = __ballot(hit);
-    if (EMIT && hit) {
-      const uint32_t at = pos + (uint32_t)__popcll(bal & below);
-      if (at < ch.cap) {
-        keys[at] = (uint32_t)v * (uint32_t)bc.T + (uint32_t)t;
-        vals[at] = (uint32_t)(lo + ((int64_t)blockIdx.x * blockDim.x + (w << 6) + i));  // depth rank
+      const uint64_t bal = __ballot(hit);
+      if (EMIT && hit) {
+        const uint32_t at = pos + (uint32_t)__popcll(bal & below);
+        if (at < ch.cap) {
+          keys[at] = (uint32_t)t;  // the view is the segment: keys of view v lie in its scanned range
+          vals[at] = (uint32_t)(r - lane + i);  // depth rank of the Gaussian in lane i
+        }
       }
+      pos += (uint32_t)__popcll(bal);
     }
-    pos += (uint32_t)__popcll(bal);
+    if (!EMIT && lane == 0) {
+      if (wave_in) counts[wslot] = pos;
+      block_sum += pos;
+    }
+    __syncthreads();  // the wavefront staging is rewritten by the next group
   }
   if (!EMIT) {
-    if (lane == 0) {
-      if (wave_in) counts[wslot] = pos;
-      part[w] = pos;
-    }
+    if (lane == 0) part[w] = block_sum;
     __syncthreads();
     if (threadIdx.x == 0) {
       const unsigned long long sum = part[0] + part[1] + part[2] + part[3];
       if (sum) atomicAdd(total, sum);
     }
+  }
+}
+
+// Start of each view's key range: the scanned wavefront counts at the view's first wavefront; the end of the
+// last view is the chunk's total.
+__global__ void view_starts_kernel(const uint32_t* __restrict__ scanned, int64_t wstride, int N,
+                                   const unsigned long long* __restrict__ total, uint32_t* __restrict__ start) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > N) return;
+  if (v == N) {
+    const unsigned long long t = *total;
+    start[v] = (uint32_t)(t < 0xffffffffull ? t : 0xffffffffull);
+  } else {
+    start[v] = scanned[(int64_t)v * wstride];
   }
 }
 
@@ -218,10 +247,14 @@ __global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long
 
 }  // namespace
 
+// Workgroups per view: enough to fill the chip for one chunk of a large scene, few enough that a chunk whose
+// views are dead costs little more than its launch.
+unsigned bin_blocks(const ChunkArgs& ch) { return (unsigned)std::min<int64_t>((ch.stride + 255) / 256, 96); }
+
 hipError_t launch_bin_count(const float4* rec, const uint32_t* vis_count, const uint32_t* live, const BlendConst& bc,
                             const ChunkArgs& ch, const uint8_t* alive, uint32_t* counts, unsigned long long* total,
                             hipStream_t s) {
-  const dim3 grid((unsigned)((ch.stride + 255) / 256), (unsigned)bc.N);
+  const dim3 grid(bin_blocks(ch), (unsigned)bc.N);
   hipLaunchKernelGGL(bin_kernel<false>, grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, counts, total,
                      nullptr, nullptr, nullptr);
   return hipGetLastError();
@@ -230,9 +263,16 @@ hipError_t launch_bin_count(const float4* rec, const uint32_t* vis_count, const 
 hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const uint32_t* live, const BlendConst& bc,
                            const ChunkArgs& ch, const uint8_t* alive, const uint32_t* offsets, uint32_t* keys,
                            uint32_t* vals, hipStream_t s) {
-  const dim3 grid((unsigned)((ch.stride + 255) / 256), (unsigned)bc.N);
+  const dim3 grid(bin_blocks(ch), (unsigned)bc.N);
   hipLaunchKernelGGL(bin_kernel<true>, grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, nullptr, nullptr,
                      offsets, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_view_starts(const uint32_t* scanned, int64_t wstride, int N, const unsigned long long* total,
+                              uint32_t* start, hipStream_t s) {
+  hipLaunchKernelGGL(view_starts_kernel, dim3((unsigned)((N + 1 + 63) / 64)), dim3(64), 0, s, scanned, wstride, N, total,
+                     start);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   return x * q + min(x, rem) + k;
 }
 
-template <bool STD, int RPT>
+template <bool STD, int RPT, bool STATS>
 __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restrict__ rec,
                                                           const uint32_t* __restrict__ tile_start,
                                                           const uint32_t* __restrict__ gidx,
@@ -132,8 +132,10 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
           const float tn = Tr[j] * (1.0f - alpha);
           const bool stop = ok && (tn < t_min);
           const bool take = ok && !stop;
-          nev[j] += live[j] ? 1u : 0u;
-          nbl[j] += take ? 1u : 0u;
+          if (STATS) {
+            nev[j] += live[j] ? 1u : 0u;
+            nbl[j] += take ? 1u : 0u;
+          }
           live[j] = live[j] && !stop;
           const float w = take ? alpha * Tr[j] : 0.0f;
           C0[j] = fmaf(w, B.y, C0[j]);
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
   const bool tile_live = __syncthreads_or(mine);
   if (!tile_live && threadIdx.x == 0) alive[vt] = 0;
 
-  if (bc.stats) {
+  if (STATS) {
     unsigned long long e = 0, b = 0, r = 0;
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
@@ -208,8 +210,12 @@ hipError_t launch_rpt(int rpt, unsigned nblocks, const float4* rec, const uint32
                       uint8_t* alive, float4* state, float* out, hipStream_t s) {
 #define DL_BLEND_CASE(R)                                                                                        \
   case R:                                                                                                      \
-    hipLaunchKernelGGL((blend_kernel<STD, R>), dim3(nblocks), dim3(kThreads), 0, s, rec, tile_start, gidx,    \
-                       ray_off, ray_ent, bc, bk, alive, state, out);                                           \
+    if (bc.stats)                                                                                              \
+      hipLaunchKernelGGL((blend_kernel<STD, R, true>), dim3(nblocks), dim3(kThreads), 0, s, rec, tile_start,  \
+                         gidx, ray_off, ray_ent, bc, bk, alive, state, out);                                   \
+    else                                                                                                       \
+      hipLaunchKernelGGL((blend_kernel<STD, R, false>), dim3(nblocks), dim3(kThreads), 0, s, rec, tile_start, \
+                         gidx, ray_off, ray_ent, bc, bk, alive, state, out);                                   \
     break;
   switch (rpt) {
     DL_BLEND_CASE(1)

@@ -80,8 +80,21 @@ hipError_t launch_interleave(const uint8_t* V, const float* views, float* out, i
 int64_t scan_partial_count(int64_t n);
 // exclusive scan of n uint32 (in may equal out); `partial` holds scan_partial_count(n) + 1 entries and
 // receives the grand total in partial[scan_partial_count(n)].
-hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, hipStream_t s);
+// With n_dev, only the first min(n, *n_dev) entries are scanned (the grand total then lands in
+// partial[scan_partial_count(n)] only when *n_dev >= n).
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, hipStream_t s,
+                              const uint32_t* n_dev = nullptr);
 int64_t radix_hist_size(int64_t seg_len, int n_seg);
+// Stable partition of (key = digit < n_dig, value) pairs within each of n_seg segments given as device ranges
+// [seg_start[s], seg_start[s + 1]) of one array (clamped to cap): afterwards every segment holds its values
+// grouped by digit, in input order within a digit.  start[s * n_dig + d] receives the first position of
+// digit d in segment s, start[n_seg * n_dig] the end.  Returns the buffer holding the partitioned values
+// (v0 or v1); keys k0/k1 are scratch.  hist: tile_partition_hist_size(n_seg) entries; layout: 2 n_seg + 1
+// entries; n_seg <= 256.
+int64_t tile_partition_hist_size(int n_seg);
+const uint32_t* tile_partition(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int n_seg,
+                               const uint32_t* seg_start, uint32_t cap, int n_dig, uint32_t* hist, uint32_t* partial,
+                               uint32_t* layout, uint32_t* start, hipStream_t s, hipError_t* err);
 // Stable LSD sort of n_seg segments (static length seg_len, live length seg_n[s] clamped to cap when seg_n is
 // given) of (key, value) pairs by key bits [bit_lo, bit_hi), each segment independently.  Ping-pongs between
 // (k0, v0) and (k1, v1); returns true when the result ends in (k1, v1).
@@ -123,6 +136,9 @@ hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const u
                            const ChunkArgs& ch, const uint8_t* alive, const uint32_t* offsets, uint32_t* keys,
                            uint32_t* vals, hipStream_t s);
 hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, hipStream_t s);
+// start[v] = scanned[v * wstride] for v < N, start[N] = *total (saturated to 32 bits)
+hipError_t launch_view_starts(const uint32_t* scanned, int64_t wstride, int N, const unsigned long long* total,
+                              uint32_t* start, hipStream_t s);
 hipError_t launch_finalize_count(const unsigned long long* total, uint32_t cap, uint32_t* n_out,
                                  unsigned long long* max_total, hipStream_t s);
 hipError_t launch_init_alive(uint8_t* alive, const uint32_t* ray_off, int64_t n, hipStream_t s);

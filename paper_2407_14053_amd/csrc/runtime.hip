@@ -100,7 +100,8 @@ struct RayLists {
 
 struct dl_ctx {
   int device = 0;
-  DevBuf live;  // live tiles per view after the last blended chunk
+  DevBuf live;    // live tiles per view after the last blended chunk
+  DevBuf vstart;  // start of each view's tile keys in the current chunk [N + 1]
   DevBuf cams, rec, srec, k64[2], v32[2], vis, counts, bk[2], bv[2], hist, partial, tstart, views, stats, alive,
       state, dtotal, nkeys, gacc;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
@@ -384,6 +385,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   const int64_t max_wstride = (max_stride + 63) / 64;
   HIP_TRY(C->counts.ensure((size_t)N * max_wstride * 4));
   HIP_TRY(C->live.ensure((size_t)N * 4));
+  HIP_TRY(C->vstart.ensure((size_t)(3 * N + 2) * 4));  // view starts, then the partition layout
   HIP_TRY(C->bk[0].ensure((size_t)cap * 4));
   HIP_TRY(C->bk[1].ensure((size_t)cap * 4));
   HIP_TRY(C->bv[0].ensure((size_t)cap * 4));
@@ -393,7 +395,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   HIP_TRY(C->state.ensure((size_t)std::max<int64_t>(nstate, 1) * 16));
   HIP_TRY(C->dtotal.ensure(2 * 8));
   HIP_TRY(C->nkeys.ensure(4));
-  const int64_t hs = std::max(radix_hist_size(G, N), radix_hist_size(cap, 1));
+  const int64_t hs = std::max(radix_hist_size(G, N), tile_partition_hist_size(N));
   HIP_TRY(C->hist.ensure((size_t)hs * 4));
   HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, N * max_wstride)) + 2) * 4));
   if (C->prof >= 2) HIP_TRY(C->stats.ensure((size_t)kStatSlots * 3 * 8));
@@ -458,8 +460,6 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   bc.t_min = o.t_min;
   for (int k = 0; k < 3; ++k) bc.bg[k] = o.bg[k];
   bc.stats = C->prof >= 2 ? C->stats.as<unsigned long long>() : nullptr;
-  int bits = 1;
-  while ((1ll << bits) < NT) ++bits;
   unsigned long long* total = C->dtotal.as<unsigned long long>();
   for (int c = 0; c < kChunks; ++c) {
     C->chunk = c;
@@ -487,15 +487,12 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                             C->counts.as<uint32_t>(), C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), s));
     C->end(mk, s);
     mk = C->begin(DL_STAGE_TILE_SORT, s);
-    bool f2 = radix_sort_u32(C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), C->bk[1].as<uint32_t>(),
-                             C->bv[1].as<uint32_t>(), cap, 1, C->nkeys.as<uint32_t>(), cap, 0, bits,
-                             C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s, &e);
-    if (e != hipSuccess) return fail(DL_EHIP, std::string("tile sort: ") + hipGetErrorString(e));
-    C->end(mk, s);
-    uint32_t* skeys = f2 ? C->bk[1].as<uint32_t>() : C->bk[0].as<uint32_t>();
-    uint32_t* svals = f2 ? C->bv[1].as<uint32_t>() : C->bv[0].as<uint32_t>();
-    mk = C->begin(DL_STAGE_BOUNDS, s);
-    HIP_TRY(launch_lower_bounds(skeys, C->nkeys.as<uint32_t>(), cap, 0, C->tstart.as<uint32_t>(), NT, s));
+    HIP_TRY(launch_view_starts(C->counts.as<uint32_t>(), ch.wstride, N, total, C->vstart.as<uint32_t>(), s));
+    const uint32_t* svals = tile_partition(C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), C->bk[1].as<uint32_t>(),
+                                           C->bv[1].as<uint32_t>(), N, C->vstart.as<uint32_t>(), cap, tl.T,
+                                           C->hist.as<uint32_t>(), C->partial.as<uint32_t>(),
+                                           C->vstart.as<uint32_t>() + (N + 1), C->tstart.as<uint32_t>(), s, &e);
+    if (e != hipSuccess) return fail(DL_EHIP, std::string("tile partition: ") + hipGetErrorString(e));
     C->end(mk, s);
     BlendChunk bk{c == 0, c == kChunks - 1};
     mk = C->begin(DL_STAGE_BLEND, s);
@@ -809,7 +806,7 @@ namespace {
 size_t ctx_bytes(const dl_ctx* C) {
   const DevBuf* b[] = {&C->cams, &C->rec, &C->srec, &C->k64[0], &C->k64[1], &C->v32[0], &C->v32[1], &C->vis,
                        &C->counts, &C->bk[0], &C->bk[1], &C->bv[0], &C->bv[1], &C->hist, &C->partial, &C->tstart,
-                       &C->views, &C->stats, &C->alive, &C->state, &C->dtotal, &C->nkeys, &C->gacc, &C->live};
+                       &C->views, &C->stats, &C->alive, &C->state, &C->dtotal, &C->nkeys, &C->gacc, &C->live, &C->vstart};
   size_t t = 0;
   for (const DevBuf* x : b) t += x->cap;
   return t;

@@ -23,8 +23,9 @@ constexpr int kScanIPT = 16;
 constexpr int kScanTile = kThreads * kScanIPT;
 constexpr int kRows = 16;                        // rows of 64 items per wavefront per tile
 constexpr int kTile = kThreads * kRows;          // 4096 items per tile
-constexpr int kMaxBits = 9;
-constexpr int kMaxRadix = 1 << kMaxBits;
+constexpr int kMaxBits = 9;    // digit width of the general sorts
+constexpr int kPartBits = 10;  // digit width of the tile partition (one pass for up to 1024 tiles per view)
+constexpr int kMaxRadix = 1 << kPartBits;
 
 __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
 #pragma unroll
@@ -52,8 +53,11 @@ __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* total) {
   return before + inc - x;
 }
 
+// The scans take a static length n, or a device length *n_dev (<= n; grids are sized for n).
 __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                                 const uint32_t* __restrict__ n_dev,
                                                                  uint32_t* __restrict__ partial) {
+  if (n_dev) n = min(n, (int64_t)*n_dev);
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
   uint32_t s = 0;
 #pragma unroll
@@ -78,7 +82,10 @@ __global__ __launch_bounds__(kThreads) void scan_partials_kernel(uint32_t* __res
 }
 
 __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* in, uint32_t* out, int64_t n,
+                                                               const uint32_t* __restrict__ n_dev,
                                                                const uint32_t* __restrict__ partial) {
+  if (n_dev) n = min(n, (int64_t)*n_dev);
+  if ((int64_t)blockIdx.x * kScanTile >= n) return;
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
   uint32_t v[kScanIPT];
   uint32_t s = 0;
@@ -118,7 +125,20 @@ struct SortArgs {
   uint32_t* hist;
   int drop;               // this pass leaves out items whose key equals drop_key (the first pass only)
   K drop_key;
+  // device segment ranges [seg_start[s], seg_start[s + 1]) (clamped to cap) of one array, written back to the
+  // same ranges at absolute positions; nullptr: segment s is [s * seg_len, s * seg_len + live length)
+  const uint32_t* seg_start;
+  // with seg_start: histogram layout [segment][digit < ndig][block < bpse[seg]] from offset hoff[seg]; empty
+  // segments take no entries and no blocks
+  const uint32_t* hoff;
+  const uint32_t* bpse;
+  int ndig;
 };
+
+template <typename K>
+__device__ inline int64_t hist_at(const SortArgs<K>& a, int seg, int d, int bis, int bps, int radix) {
+  return a.seg_start ? (int64_t)a.hoff[seg] + (int64_t)d * bps + bis : ((int64_t)seg * radix + d) * a.bps + bis;
+}
 
 template <typename K>
 __device__ inline int64_t live_len(const SortArgs<K>& a, int seg) {
@@ -126,9 +146,22 @@ __device__ inline int64_t live_len(const SortArgs<K>& a, int seg) {
   return min((int64_t)min(a.seg_n[seg], a.cap), a.seg_len);
 }
 
+// Input range of segment `seg` and whether output positions are absolute.
 template <typename K>
+__device__ inline void seg_range(const SortArgs<K>& a, int seg, int64_t& base, int64_t& n) {
+  if (a.seg_start) {
+    base = min(a.seg_start[seg], a.cap);
+    n = (int64_t)min(a.seg_start[seg + 1], a.cap) - base;
+  } else {
+    base = (int64_t)seg * a.seg_len;
+    n = live_len(a, seg);
+  }
+}
+
+
+template <typename K, int RB>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(SortArgs<K> a) {
-  __shared__ uint32_t h[kWaves][kMaxRadix];
+  __shared__ uint32_t h[kWaves][1 << RB];
   const int radix = 1 << a.bits;
   const uint32_t dmask = (uint32_t)radix - 1;
   const int w = threadIdx.x >> 6;
@@ -138,9 +171,13 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(SortArgs<K> a) {
   __syncthreads();
   const int seg = blockIdx.x / a.bps;
   const int bis = blockIdx.x - seg * a.bps;
-  int64_t lo, hi;
-  block_range(live_len(a, seg), a.bps, bis, lo, hi);
-  const K* kin = a.kin + (int64_t)seg * a.seg_len;
+  const int bps = a.seg_start ? (int)a.bpse[seg] : a.bps;
+  if (bis >= bps) return;
+  const int ndig = a.seg_start ? a.ndig : radix;
+  int64_t base, n, lo, hi;
+  seg_range(a, seg, base, n);
+  block_range(n, bps, bis, lo, hi);
+  const K* kin = a.kin + base;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
     const K k = kin[i];
     if (a.drop && k == a.drop_key) continue;
@@ -148,19 +185,20 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(SortArgs<K> a) {
     atomicAdd(&h[w][d], 1u);
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < radix; d += kThreads) {
+  for (int d = threadIdx.x; d < ndig; d += kThreads) {
     uint32_t s = 0;
 #pragma unroll
     for (int i = 0; i < kWaves; ++i) s += h[i][d];
-    a.hist[((int64_t)seg * radix + d) * a.bps + bis] = s;
+    a.hist[hist_at(a, seg, d, bis, bps, radix)] = s;
   }
 }
 
-template <typename K>
+template <typename K, int RB>
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) {
-  __shared__ uint32_t run[kMaxRadix];          // next global position per digit
-  __shared__ uint32_t wc[kWaves][kMaxRadix];   // per-wavefront digit counts within the tile
-  __shared__ uint32_t loff[kMaxRadix];         // tile-local start per digit
+  constexpr int DPT = (1 << RB) / kThreads;     // digits owned by each thread in the tile-local scan
+  __shared__ uint32_t run[1 << RB];             // next output position per digit
+  __shared__ uint32_t wc[kWaves][1 << RB];      // per-wavefront digit counts within the tile
+  __shared__ uint32_t loff[1 << RB];            // tile-local start per digit
   __shared__ K skey[kTile];
   __shared__ uint32_t sval[kTile];
   const int radix = 1 << a.bits;
@@ -168,16 +206,22 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int seg = blockIdx.x / a.bps;
   const int bis = blockIdx.x - seg * a.bps;
-  int64_t lo, hi;
-  block_range(live_len(a, seg), a.bps, bis, lo, hi);
-  const K* kin = a.kin + (int64_t)seg * a.seg_len;
-  const uint32_t* vin = a.vin + (int64_t)seg * a.seg_len;
-  K* kout = a.kout + (int64_t)seg * a.seg_len;
-  uint32_t* vout = a.vout + (int64_t)seg * a.seg_len;
-  // the scan runs over all segments; subtract the segment's first offset so positions are segment-relative
-  const uint32_t seg0 = a.hist[(int64_t)seg * radix * a.bps];
+  const int bps = a.seg_start ? (int)a.bpse[seg] : a.bps;
+  if (bis >= bps) return;
+  const int ndig = a.seg_start ? a.ndig : radix;
+  int64_t base, n, lo, hi;
+  seg_range(a, seg, base, n);
+  block_range(n, bps, bis, lo, hi);
+  const K* kin = a.kin + base;
+  const uint32_t* vin = a.vin + base;
+  // the scan runs over all segments: its values are absolute positions when segments are ranges of one
+  // array (seg_start), else subtract the segment's first offset so positions are segment-relative
+  const int64_t obase = a.seg_start ? 0 : base;
+  K* kout = a.kout ? a.kout + obase : nullptr;
+  uint32_t* vout = a.vout + obase;
+  const uint32_t seg0 = a.seg_start ? 0u : a.hist[(int64_t)seg * radix * a.bps];
   for (int d = threadIdx.x; d < radix; d += kThreads)
-    run[d] = a.hist[((int64_t)seg * radix + d) * a.bps + bis] - seg0;
+    run[d] = d < ndig ? a.hist[hist_at(a, seg, d, bis, bps, radix)] - seg0 : 0u;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
   for (int64_t t0 = lo; t0 < hi; t0 += kTile) {
@@ -210,40 +254,36 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
       if (valid && lr == 0) wc[w][d] = base + (uint32_t)__popcll(m);
     }
     __syncthreads();
-    // tile-local digit offsets (exclusive scan over digits; thread t owns digits 2t and 2t + 1) and
+    // tile-local digit offsets (exclusive scan over digits; thread t owns digits [DPT t, DPT t + DPT)) and
     // per-wavefront bases
-    uint32_t tot0 = 0, tot1 = 0;
-    const int d0 = 2 * threadIdx.x, d1 = 2 * threadIdx.x + 1;
-    if (d0 < radix) {
+    uint32_t tot[DPT];
+    uint32_t mysum = 0;
 #pragma unroll
-      for (int i = 0; i < kWaves; ++i) tot0 += wc[i][d0];
-    }
-    if (d1 < radix) {
+    for (int q = 0; q < DPT; ++q) {
+      const int d = DPT * threadIdx.x + q;
+      tot[q] = 0;
+      if (d < radix) {
 #pragma unroll
-      for (int i = 0; i < kWaves; ++i) tot1 += wc[i][d1];
+        for (int i = 0; i < kWaves; ++i) tot[q] += wc[i][d];
+      }
+      mysum += tot[q];
     }
     uint32_t total;
-    const uint32_t ex0 = block_excl_scan(tot0 + tot1, &total);
-    if (d0 < radix) {
-      loff[d0] = ex0;
-      uint32_t acc = ex0;
+    uint32_t acc_d = block_excl_scan(mysum, &total);
 #pragma unroll
-      for (int i = 0; i < kWaves; ++i) {
-        const uint32_t c = wc[i][d0];
-        wc[i][d0] = acc;  // becomes the tile-local base of wavefront i for this digit
-        acc += c;
-      }
-    }
-    if (d1 < radix) {
-      const uint32_t ex1 = ex0 + tot0;
-      loff[d1] = ex1;
-      uint32_t acc = ex1;
+    for (int q = 0; q < DPT; ++q) {
+      const int d = DPT * threadIdx.x + q;
+      if (d < radix) {
+        loff[d] = acc_d;
+        uint32_t acc = acc_d;
 #pragma unroll
-      for (int i = 0; i < kWaves; ++i) {
-        const uint32_t c = wc[i][d1];
-        wc[i][d1] = acc;
-        acc += c;
+        for (int i = 0; i < kWaves; ++i) {
+          const uint32_t c = wc[i][d];
+          wc[i][d] = acc;  // becomes the tile-local base of wavefront i for this digit
+          acc += c;
+        }
       }
+      acc_d += tot[q];
     }
     __syncthreads();
 #pragma unroll
@@ -260,14 +300,80 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
       const K k = skey[p];
       const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
       const uint32_t g = run[d] + (uint32_t)p - loff[d];
-      kout[g] = k;
+      if (kout) kout[g] = k;
       vout[g] = sval[p];
     }
     __syncthreads();
-    if (d0 < radix) run[d0] += tot0;
-    if (d1 < radix) run[d1] += tot1;
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int d = DPT * threadIdx.x + q;
+      if (d < radix) run[d] += tot[q];
+    }
     __syncthreads();
   }
+}
+
+// List starts of a one-pass partition: the first output position of digit t in segment v is the scanned
+// histogram at [v][t][block 0] (an empty segment has no entries: its lists start at its range);
+// start[n_seg * n_dig] = end of the last segment.
+__global__ __launch_bounds__(kThreads) void hist_starts_kernel(const uint32_t* __restrict__ hist,
+                                                                 const uint32_t* __restrict__ hoff,
+                                                                 const uint32_t* __restrict__ bpse, int n_dig,
+                                                                 int n_seg, const uint32_t* __restrict__ seg_start,
+                                                                 uint32_t cap, uint32_t* __restrict__ start) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t n = (int64_t)n_seg * n_dig;
+  if (i > n) return;
+  if (i == n) {
+    start[i] = min(seg_start[n_seg], cap);
+    return;
+  }
+  const int v = (int)(i / n_dig);
+  const int t = (int)(i - (int64_t)v * n_dig);
+  const uint32_t b = bpse[v];
+  start[i] = b ? hist[(int64_t)hoff[v] + (int64_t)t * b] : min(seg_start[v], cap);
+}
+
+// Histogram layout of a partition: blocks per segment = its tiles of kTile items (at most bps_max, none for an
+// empty segment), offsets = exclusive scan of n_dig x blocks; hoff[n_seg] = entries in use.  One workgroup;
+// n_seg <= kThreads.
+__global__ __launch_bounds__(kThreads) void part_layout_kernel(const uint32_t* __restrict__ seg_start, uint32_t cap,
+                                                                 int n_seg, int n_dig, int bps_max,
+                                                                 uint32_t* __restrict__ bpse,
+                                                                 uint32_t* __restrict__ hoff) {
+  const int v = threadIdx.x;
+  uint32_t b = 0;
+  if (v < n_seg) {
+    const uint32_t n = min(seg_start[v + 1], cap) - min(seg_start[v], cap);
+    b = (uint32_t)min((int64_t)bps_max, ((int64_t)n + kTile - 1) / kTile);
+    bpse[v] = b;
+  }
+  uint32_t total;
+  const uint32_t off = block_excl_scan(b * (uint32_t)n_dig, &total);
+  if (v < n_seg) hoff[v] = off;
+  if (v == 0) hoff[n_seg] = total;
+}
+
+// List starts after a multi-pass partition: first position in segment v whose key is >= t.
+__global__ __launch_bounds__(kThreads) void segment_bounds_kernel(const uint32_t* __restrict__ keys, int n_dig,
+                                                                    int n_seg, const uint32_t* __restrict__ seg_start,
+                                                                    uint32_t cap, uint32_t* __restrict__ start) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t n = (int64_t)n_seg * n_dig;
+  if (i > n) return;
+  if (i == n) {
+    start[i] = min(seg_start[n_seg], cap);
+    return;
+  }
+  const int v = (int)(i / n_dig);
+  const uint32_t t = (uint32_t)(i - (int64_t)v * n_dig);
+  uint32_t lo = min(seg_start[v], cap), hi = min(seg_start[v + 1], cap);
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (keys[mid] < t) lo = mid + 1;
+    else hi = mid;
+  }
+  start[i] = lo;
 }
 
 // Items kept per segment by a dropping pass, from its scanned histogram ([segment][digit][block], exclusive)
@@ -339,7 +445,10 @@ bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, 
       a.cap = (uint32_t)std::min<int64_t>(seg_len, 0xffffffffll);
     }
     const int64_t hsize = (int64_t)n_seg * (1 << bits) * bps;
-    hipLaunchKernelGGL(radix_hist_kernel<K>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
+    a.seg_start = nullptr;
+    a.hoff = a.bpse = nullptr;
+    a.ndig = 1 << bits;
+    hipLaunchKernelGGL((radix_hist_kernel<K, kMaxBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
     if ((*err = hipGetLastError()) != hipSuccess) return flipped;
     if ((*err = exclusive_scan_u32(hist, hist, hsize, partial, s)) != hipSuccess) return flipped;
     if (a.drop) {
@@ -347,7 +456,7 @@ bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, 
                          partial + scan_partial_count(hsize), n_seg, (int64_t)(1 << bits) * bps, kept);
       if ((*err = hipGetLastError()) != hipSuccess) return flipped;
     }
-    hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((radix_scatter_kernel<K, kMaxBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
     if ((*err = hipGetLastError()) != hipSuccess) return flipped;
     flipped = !flipped;
     shift += bits;
@@ -355,16 +464,19 @@ bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, 
   return flipped;
 }
 
+int part_blocks_per_seg(int n_seg) { return std::max(1, (2048 + n_seg - 1) / n_seg); }
+
 }  // namespace
 
 int64_t scan_partial_count(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
-hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, hipStream_t s) {
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, hipStream_t s,
+                              const uint32_t* n_dev) {
   if (n <= 0) return hipSuccess;
   const int64_t np = scan_partial_count(n);
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, n, partial);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, n, n_dev, partial);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kThreads), 0, s, partial, np);
-  hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, out, n, partial);
+  hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, out, n, n_dev, partial);
   return hipGetLastError();
 }
 
@@ -391,6 +503,76 @@ bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int6
                     hipStream_t s, hipError_t* err) {
   return radix_sort_impl<uint32_t>(k0, v0, k1, v1, seg_len, n_seg, seg_n, cap, bit_lo, bit_hi, hist, partial, s,
                                    err);
+}
+
+int64_t tile_partition_hist_size(int n_seg) { return (int64_t)part_blocks_per_seg(n_seg) * n_seg * kMaxRadix; }
+
+const uint32_t* tile_partition(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int n_seg,
+                               const uint32_t* seg_start, uint32_t cap, int n_dig, uint32_t* hist, uint32_t* partial,
+                               uint32_t* layout, uint32_t* start, hipStream_t s, hipError_t* err) {
+  *err = hipSuccess;
+  if (n_seg > kThreads) {
+    *err = hipErrorInvalidValue;
+    return nullptr;
+  }
+  uint32_t* bpse = layout;               // [n_seg]
+  uint32_t* hoff = layout + n_seg;       // [n_seg + 1]
+  int bits = 1;
+  while ((1 << bits) < n_dig) ++bits;
+  const int bps = part_blocks_per_seg(n_seg);
+  const int64_t nblocks = (int64_t)bps * n_seg;
+  const int passes = (bits + kPartBits - 1) / kPartBits;
+  bool flipped = false;
+  int shift = 0;
+  for (int p = 0; p < passes; ++p) {
+    const int pb = (bits - shift + (passes - p) - 1) / (passes - p);
+    const bool last = p == passes - 1;
+    SortArgs<uint32_t> a{};
+    a.kin = flipped ? k1 : k0;
+    a.vin = flipped ? v1 : v0;
+    a.kout = (last && passes == 1) ? nullptr : (flipped ? k0 : k1);  // keys are not needed after one pass
+    a.vout = flipped ? v0 : v1;
+    a.seg_len = 0;
+    a.seg_n = nullptr;
+    a.cap = cap;
+    a.bps = bps;
+    a.shift = shift;
+    a.bits = pb;
+    a.hist = hist;
+    a.drop = 0;
+    a.drop_key = 0;
+    a.seg_start = seg_start;
+    a.hoff = hoff;
+    a.bpse = bpse;
+    a.ndig = passes == 1 ? n_dig : (1 << pb);
+    const int64_t hsize = (int64_t)n_seg * a.ndig * bps;
+    hipLaunchKernelGGL(part_layout_kernel, dim3(1), dim3(kThreads), 0, s, seg_start, cap, n_seg, a.ndig, bps, bpse,
+                       hoff);
+    if (pb > kMaxBits)
+      hipLaunchKernelGGL((radix_hist_kernel<uint32_t, kPartBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((radix_hist_kernel<uint32_t, kMaxBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
+    if ((*err = hipGetLastError()) != hipSuccess) return nullptr;
+    if ((*err = exclusive_scan_u32(hist, hist, hsize, partial, s, hoff + n_seg)) != hipSuccess) return nullptr;
+    if (pb > kMaxBits)
+      hipLaunchKernelGGL((radix_scatter_kernel<uint32_t, kPartBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((radix_scatter_kernel<uint32_t, kMaxBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
+    if ((*err = hipGetLastError()) != hipSuccess) return nullptr;
+    if (last) {
+      const int64_t ns = (int64_t)n_seg * n_dig + 1;
+      if (passes == 1)
+        hipLaunchKernelGGL(hist_starts_kernel, dim3((unsigned)((ns + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                           hist, hoff, bpse, n_dig, n_seg, seg_start, cap, start);
+      else
+        hipLaunchKernelGGL(segment_bounds_kernel, dim3((unsigned)((ns + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                           s, (const uint32_t*)a.kout, n_dig, n_seg, seg_start, cap, start);
+      if ((*err = hipGetLastError()) != hipSuccess) return nullptr;
+    }
+    flipped = !flipped;
+    shift += pb;
+  }
+  return flipped ? v1 : v0;
 }
 
 hipError_t launch_lower_bounds(const uint32_t* keys, const uint32_t* n_dev, uint32_t cap, int64_t n_static,
