@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
       C2[j] = st.w;
     }
   }
-  const float q_cut = bc.q_cut, a_min = bc.alpha_min, a_max = bc.alpha_max, t_min = bc.t_min;
+  const float a_max = bc.alpha_max, t_min = bc.t_min;
   const uint32_t ls = tile_start[vt];
   const uint32_t le = tile_start[vt + 1];
   const int64_t vG = (int64_t)v * bc.G;
@@ -112,9 +112,12 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
     if ((int)threadIdx.x < n) {
       const uint32_t rk = gidx[base + threadIdx.x];
       const float4* src = vrec + (int64_t)rk * kRecF4;
+      const float4 r1 = src[1], r2 = src[2];
       sm[threadIdx.x * kRecF4 + 0] = src[0];
-      sm[threadIdx.x * kRecF4 + 1] = src[1];
-      sm[threadIdx.x * kRecF4 + 2] = src[2];
+      // the LDS copy carries, in place of the binning's Q limit, the blend's own: Q <= min(Q_cut, log2(o / a_min))
+      // holds exactly when q <= q_cut and o exp(-q/2) >= alpha_min (up to the rounding of the logarithm)
+      sm[threadIdx.x * kRecF4 + 1] = make_float4(r1.x, blend_qlim(r2.x, bc), r1.z, r1.w);
+      sm[threadIdx.x * kRecF4 + 2] = r2;
       sg[threadIdx.x] = sorted[vG + rk];
     }
     for (int i = threadIdx.x; i < (kThreads / 64) * kThreads * kG; i += kThreads) (&part[0][0][0])[i] = 0.0f;
@@ -125,7 +128,8 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
     if (__ballot(any) != 0ull) {
       for (int k = 0; k < n; ++k) {
         const float4 A = sm[k * kRecF4 + 0];
-        const float cC = sm[k * kRecF4 + 1].x;
+        const float2 CQ = *reinterpret_cast<const float2*>(&sm[k * kRecF4 + 1]);
+        const float cC = CQ.x;
         const float4 B = sm[k * kRecF4 + 2];
         float gr[kG];
 #pragma unroll
@@ -138,12 +142,12 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
           const float q = fmaf(A.z * dx, dx, fmaf(cC, dy, A.w * dx) * dy);
           const float ga = B.x * __builtin_amdgcn_exp2f(-q);
           const float alpha = fminf(a_max, ga);
-          const bool ok = live[j] && (q <= q_cut) && (alpha >= a_min);
-          const float tn = Tr[j] * (1.0f - alpha);
+          const bool ok = live[j] && (q <= CQ.y);
+          const float tn = fmaf(-alpha, Tr[j], Tr[j]);
           const bool stop = ok && (tn < t_min);
           const bool take = ok && !stop;
           live[j] = live[j] && !stop;
-          const float w = take ? alpha * Tr[j] : 0.0f;
+          const float w = take ? Tr[j] - tn : 0.0f;
           const float n0 = fmaf(w, B.y, C0[j]), n1 = fmaf(w, B.z, C1[j]), n2 = fmaf(w, B.w, C2[j]);
           if (take) {
             // dC/dc = alpha T ; dC/dalpha = T c - (C_end - C_<=j) / (1 - alpha)

@@ -5,7 +5,8 @@
 // channel mask), for the standard paradigm every pixel of the tile.  The tile's depth-ordered list is
 // staged through LDS 256 records at a time (one coalesced 48-byte record per lane); every lane then reads
 // the records as LDS broadcasts and applies, per ray, the per-pixel rule and Eq. (5)/(10):
-//   q = d^T Sigma'^{-1} d,  alpha = min(alpha_max, o exp(-q/2)),  blend iff q <= q_cut and alpha >= alpha_min,
+//   q = d^T Sigma'^{-1} d,  alpha = min(alpha_max, o exp(-q/2)),  blend iff q <= q_cut and alpha >= alpha_min
+//   (tested as one bound on q per record),
 //   stop (without blending) when T (1 - alpha) < t_min,
 // with q held as Q = q log2(e)/2 (the record's conic is pre-scaled) and exp(-q/2) = 2^-Q (one v_exp_f32).
 // A wavefront leaves the LDS chunk as soon as a ballot shows all its rays finished, and the workgroup
@@ -54,10 +55,10 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
   }
   if (nr <= 0) return;
 
-  float px[RPT], py[RPT], Tr[RPT], C0[RPT], C1[RPT], C2[RPT];
+  // sT: the ray's transmittance, its sign carrying the ray's state (negative once terminated or absent)
+  float px[RPT], py[RPT], sT[RPT], C0[RPT], C1[RPT], C2[RPT];
   uint32_t mask[RPT], nev[RPT], nbl[RPT];
   int64_t gid[RPT];
-  bool live[RPT];
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int idx = threadIdx.x + j * kThreads;
@@ -79,21 +80,18 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
     px[j] = (float)(ox + lx) + 0.5f;
     py[j] = (float)(oy + ly) + 0.5f;
     gid[j] = STD ? ((int64_t)v * bc.H + oy + ly) * bc.W + ox + lx : (int64_t)r0 + idx;
-    Tr[j] = 1.0f;
+    sT[j] = valid ? 1.0f : -1.0f;
     C0[j] = C1[j] = C2[j] = 0.0f;
-    live[j] = valid;
     if (valid && !bk.first) {
-      // transmittance carries the ray's state in its sign: negative once the ray has terminated
       const float4 st = state[gid[j]];
-      live[j] = !signbit(st.x);
-      Tr[j] = fabsf(st.x);
+      sT[j] = st.x;
       C0[j] = st.y;
       C1[j] = st.z;
       C2[j] = st.w;
     }
     nev[j] = nbl[j] = 0;
   }
-  const float q_cut = bc.q_cut, a_min = bc.alpha_min, a_max = bc.alpha_max, t_min = bc.t_min;
+  const float a_max = bc.alpha_max, t_min = bc.t_min;
   const uint32_t ls = tile_start[vt];
   const uint32_t le = tile_start[vt + 1];
   const float4* vrec = rec + (int64_t)v * bc.G * kRecF4;
@@ -103,58 +101,65 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
     if ((int)threadIdx.x < n) {
       const uint32_t g = gidx[base + threadIdx.x];
       const float4* src = vrec + (int64_t)g * kRecF4;
+      const float4 r1 = src[1], r2 = src[2];
       sm[threadIdx.x * kRecF4 + 0] = src[0];
-      sm[threadIdx.x * kRecF4 + 1] = src[1];
-      sm[threadIdx.x * kRecF4 + 2] = src[2];
+      // the LDS copy carries, in place of the binning's Q limit, the blend's own: Q <= min(Q_cut, log2(o / a_min))
+      // holds exactly when q <= q_cut and o exp(-q/2) >= alpha_min (up to the rounding of the logarithm)
+      sm[threadIdx.x * kRecF4 + 1] = make_float4(r1.x, blend_qlim(r2.x, bc), r1.z, r1.w);
+      sm[threadIdx.x * kRecF4 + 2] = r2;
     }
     __syncthreads();
     bool any = false;
     bool slot[RPT];  // wavefront has a live ray in slot j (slots other than the first are often empty)
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-      any |= live[j];
-      slot[j] = __ballot(live[j]) != 0ull;
+      any |= sT[j] > 0.0f;
+      slot[j] = __ballot(sT[j] > 0.0f) != 0ull;
     }
     if (__ballot(any) != 0ull) {
       for (int k = 0; k < n; ++k) {
         const float4 A = sm[k * kRecF4 + 0];    // u, v, conic A, B (scaled)
-        const float cC = sm[k * kRecF4 + 1].x;  // conic C (scaled)
+        const float2 CQ = *reinterpret_cast<const float2*>(&sm[k * kRecF4 + 1]);  // conic C (scaled), Q limit
+        const float cC = CQ.x;
         const float4 B = sm[k * kRecF4 + 2];    // opacity, r, g, b
         bool any_live = false;
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
           if (j > 0 && !slot[j]) continue;
-          // per-pixel rule and front-to-back update, without branches
+          // per-pixel rule and front-to-back update, without branches:
+          //   T' = T (1 - alpha) as one FMA, the colour weight as T - T' (alpha T up to one rounding of T')
           const float dx = px[j] - A.x, dy = py[j] - A.y;
           const float q = fmaf(A.z * dx, dx, fmaf(cC, dy, A.w * dx) * dy);
           const float alpha = fminf(a_max, B.x * __builtin_amdgcn_exp2f(-q));
-          const bool ok = live[j] && (q <= q_cut) && (alpha >= a_min);
-          const float tn = Tr[j] * (1.0f - alpha);
+          const float T = sT[j];
+          const float tn = fmaf(-alpha, T, T);
+          const bool live = T > 0.0f;
+          const bool ok = live && (q <= CQ.y);
           const bool stop = ok && (tn < t_min);
           const bool take = ok && !stop;
+          const float Tt = take ? tn : T;
+          const float w = T - Tt;
           if (STATS) {
-            nev[j] += live[j] ? 1u : 0u;
+            nev[j] += live ? 1u : 0u;
             nbl[j] += take ? 1u : 0u;
           }
-          live[j] = live[j] && !stop;
-          const float w = take ? alpha * Tr[j] : 0.0f;
           C0[j] = fmaf(w, B.y, C0[j]);
           C1[j] = fmaf(w, B.z, C1[j]);
           C2[j] = fmaf(w, B.w, C2[j]);
-          Tr[j] = take ? tn : Tr[j];
-          any_live |= live[j];
+          sT[j] = stop ? -T : Tt;
+          any_live |= live && !stop;
         }
         if (__ballot(any_live) == 0ull) break;
       }
     }
     bool mine = false;
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) mine |= live[j];
+    for (int j = 0; j < RPT; ++j) mine |= sT[j] > 0.0f;
     if (!__syncthreads_or(mine)) break;
   }
   bool mine = false;
 #pragma unroll
-  for (int j = 0; j < RPT; ++j) mine |= live[j];
+  for (int j = 0; j < RPT; ++j) mine |= sT[j] > 0.0f;
   const bool tile_live = __syncthreads_or(mine);
   if (!tile_live && threadIdx.x == 0) alive[vt] = 0;
 
@@ -184,11 +189,11 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
   for (int j = 0; j < RPT; ++j) {
     const int idx = threadIdx.x + j * kThreads;
     if (idx >= nr) continue;
-    if (!bk.last && tile_live) state[gid[j]] = make_float4(live[j] ? Tr[j] : -Tr[j], C0[j], C1[j], C2[j]);
+    if (!bk.last && tile_live) state[gid[j]] = make_float4(sT[j], C0[j], C1[j], C2[j]);
     if (bk.last || !tile_live) {
       const int xr = (int)(py[j] - 0.5f), yc = (int)(px[j] - 0.5f);
-      const float c[3] = {fmaf(Tr[j], bc.bg[0], C0[j]), fmaf(Tr[j], bc.bg[1], C1[j]),
-                          fmaf(Tr[j], bc.bg[2], C2[j])};
+      const float Tf = fabsf(sT[j]);
+      const float c[3] = {fmaf(Tf, bc.bg[0], C0[j]), fmaf(Tf, bc.bg[1], C1[j]), fmaf(Tf, bc.bg[2], C2[j])};
       if (STD) {
         float* dst = out + (((int64_t)v * bc.H + xr) * bc.W + yc) * 3;
         dst[0] = c[0];

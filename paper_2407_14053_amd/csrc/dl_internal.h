@@ -51,10 +51,17 @@ struct BlendConst {
   int64_t G;             // record stride per view
   float q_cut;  // in the scaled units of the record (q_cut log2(e)/2)
   float alpha_min, alpha_max, t_min;
+  float log2_alpha_min;
   float bg[3];
   unsigned long long* stats;  // optional work counters, kStatSlots x {evaluations, blends, rays}
 };
 constexpr int kStatSlots = 1024;
+
+// The blend's bound on the scaled quadratic form Q = q log2(e)/2 for a record of opacity o: a pair blends iff
+// Q <= min(Q_cut, log2 o - log2 alpha_min), i.e. q <= q_cut and o exp(-q/2) >= alpha_min.
+__device__ inline float blend_qlim(float o, const BlendConst& bc) {
+  return fminf(bc.q_cut, __builtin_amdgcn_logf(o) - bc.log2_alpha_min);
+}
 
 // Depth chunk: ranks [n_v num_lo / den, n_v num_hi / den) of every view; `stride` bounds its length.
 struct ChunkArgs {
@@ -80,8 +87,8 @@ hipError_t launch_interleave(const uint8_t* V, const float* views, float* out, i
 int64_t scan_partial_count(int64_t n);
 // exclusive scan of n uint32 (in may equal out); `partial` holds scan_partial_count(n) + 1 entries and
 // receives the grand total in partial[scan_partial_count(n)].
-// With n_dev, only the first min(n, *n_dev) entries are scanned (the grand total then lands in
-// partial[scan_partial_count(n)] only when *n_dev >= n).
+// With n_dev, only the first min(n, *n_dev) entries are scanned; the grand total of what was scanned lands in
+// partial[scan_partial_count(n)] either way.
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, hipStream_t s,
                               const uint32_t* n_dev = nullptr);
 int64_t radix_hist_size(int64_t seg_len, int n_seg);

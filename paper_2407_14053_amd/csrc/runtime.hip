@@ -458,6 +458,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   bc.alpha_min = o.alpha_min;
   bc.alpha_max = o.alpha_max;
   bc.t_min = o.t_min;
+  bc.log2_alpha_min = (float)std::log2((double)o.alpha_min);
   for (int k = 0; k < 3; ++k) bc.bg[k] = o.bg[k];
   bc.stats = C->prof >= 2 ? C->stats.as<unsigned long long>() : nullptr;
   unsigned long long* total = C->dtotal.as<unsigned long long>();

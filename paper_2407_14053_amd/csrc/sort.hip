@@ -68,24 +68,22 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* _
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kThreads) void scan_partials_kernel(uint32_t* __restrict__ partial, int64_t np) {
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < np; base += kThreads) {
-    const int64_t i = base + threadIdx.x;
-    const uint32_t x = i < np ? partial[i] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_excl_scan(x, &total);
-    if (i < np) partial[i] = carry + ex;
-    carry += total;
-  }
-  if (threadIdx.x == 0) partial[np] = carry;
-}
-
+// Second half of the scan: each tile adds the totals of the tiles before it (at most a few hundred, summed by
+// the workgroup) and scans its own items; the last tile writes the grand total to *grand.
 __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* in, uint32_t* out, int64_t n,
                                                                const uint32_t* __restrict__ n_dev,
-                                                               const uint32_t* __restrict__ partial) {
+                                                               const uint32_t* __restrict__ partial_in,
+                                                               uint32_t* __restrict__ grand) {
   if (n_dev) n = min(n, (int64_t)*n_dev);
-  if ((int64_t)blockIdx.x * kScanTile >= n) return;
+  const int64_t np = (n + kScanTile - 1) / kScanTile;
+  if ((int64_t)blockIdx.x >= np) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *grand = 0;  // nothing to scan
+    return;
+  }
+  uint32_t pre = 0;
+  for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kThreads) pre += partial_in[i];
+  uint32_t prefix;
+  block_excl_scan(pre, &prefix);
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
   uint32_t v[kScanIPT];
   uint32_t s = 0;
@@ -95,12 +93,13 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* in,
     s += v[i];
   }
   uint32_t total;
-  uint32_t run = block_excl_scan(s, &total) + partial[blockIdx.x];
+  uint32_t run = block_excl_scan(s, &total) + prefix;
 #pragma unroll
   for (int i = 0; i < kScanIPT; ++i) {
     if (base + i < n) out[base + i] = run;
     run += v[i];
   }
+  if ((int64_t)blockIdx.x == np - 1 && threadIdx.x == 0) *grand = prefix + total;
 }
 
 // Range [lo, hi) of block `bis` within a segment whose live length is n (ranges are whole tiles).
@@ -475,8 +474,8 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
   if (n <= 0) return hipSuccess;
   const int64_t np = scan_partial_count(n);
   hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, n, n_dev, partial);
-  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kThreads), 0, s, partial, np);
-  hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, out, n, n_dev, partial);
+  hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, out, n, n_dev, partial,
+                     partial + np);
   return hipGetLastError();
 }
 
