@@ -105,27 +105,33 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
   WaveBin& W = wb[w];
   const int v = blockIdx.y;
   const int64_t nv = vis_count[v];
-  const int64_t lo = nv * ch.num_lo / ch.den, hi = nv * ch.num_hi / ch.den;
+  const int64_t fv = ch.front ? (int64_t)ch.front[v] : 0;
+  int64_t lo, hi;
+  if (ch.front && ch.first) {
+    lo = 0;
+    hi = fv;
+  } else {
+    lo = max(fv, nv * ch.num_lo / ch.den);
+    hi = max(lo, nv * ch.num_hi / ch.den);
+  }
   const bool view_live = !live || live[v] != 0;
-  const int64_t groups = (ch.stride + 255) / 256;
+  // groups of 256 consecutive ranks of this chunk (none for a view without live tiles)
+  const int64_t groups = view_live ? (hi - lo + 255) / 256 : 0;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const uint8_t* al = alive ? alive + (int64_t)v * bc.T : nullptr;
-  if (!view_live) {
-    // no live tile: no keys; the count pass still owes a zero per wavefront slot
-    if (!EMIT)
-      for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < ch.wstride; j += (int64_t)gridDim.x * 256)
-        counts[(int64_t)v * ch.wstride + j] = 0;
-    return;
-  }
+  if (!EMIT)  // the count pass owes a zero to every wavefront slot no group covers
+    for (int64_t j = groups * 4 + (int64_t)blockIdx.x * 256 + threadIdx.x; j < ch.wstride;
+         j += (int64_t)gridDim.x * 256)
+      counts[(int64_t)v * ch.wstride + j] = 0;
   unsigned long long block_sum = 0;
-  // groups of 256 consecutive ranks, strided over the view's workgroups
+  // the chunk's groups, strided over the view's workgroups
   for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
     const int64_t idx = grp * 256 + threadIdx.x;
     const int64_t wslot = (int64_t)v * ch.wstride + (idx >> 6);
     const bool wave_in = (idx >> 6) < ch.wstride;
     const int64_t r = lo + idx;
     uint32_t nt = 0;
-    if (idx < ch.stride && r < hi) {
+    if (r < hi) {
       float rr[8];
       load_rec_geom(rec + ((int64_t)v * bc.G + r) * kRecF4, rr);
       TileRange tr;

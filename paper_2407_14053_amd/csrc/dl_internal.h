@@ -66,6 +66,10 @@ __device__ inline float blend_qlim(float o, const BlendConst& bc) {
 // Depth chunk: ranks [n_v num_lo / den, n_v num_hi / den) of every view; `stride` bounds its length.
 struct ChunkArgs {
   int64_t num_lo, num_hi, den;
+  // front[v]: size of view v's front (the first chunk); later chunks start no earlier.  The chunk of view v is
+  // ranks [0, front) for the first chunk, else [max(front, n lo), max(that, n hi)) of its n visible ranks.
+  const uint32_t* front;
+  int first;
   int64_t stride;   // item slots per view (a multiple of 64 is not required)
   int64_t wstride;  // wavefront slots per view: ceil(stride / 64)
   uint32_t cap;     // key capacity
@@ -108,11 +112,28 @@ const uint32_t* tile_partition(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_
 bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
                     const uint32_t* seg_n, uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial,
                     hipStream_t s, hipError_t* err);
-// As radix_sort_u64 over full segments, with the first pass leaving out items whose key is drop_key; kept[seg]
-// receives each segment's kept count (the sorted kept items occupy the front of the segment).
-bool radix_sort_u64_drop(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
-                         int bit_lo, int bit_hi, uint64_t drop_key, uint32_t* kept, uint32_t* hist, uint32_t* partial,
-                         hipStream_t s, hipError_t* err);
+// One stable pass over full segments [s seg_len, (s + 1) seg_len) that leaves out items whose key is drop_key and
+// splits the rest into keys < thr[s] (first) and keys >= thr[s]; results in (k1, v1).
+bool radix_split_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
+                     const uint64_t* thr, uint64_t drop_key, uint32_t* hist, uint32_t* partial, hipStream_t s,
+                     hipError_t* err);
+// Stable LSD sort of each device range [lo[s], hi[s]) in place (n_seg <= 256); returns whether the result is in
+// (k1, v1).  hist: depth_ranges_hist_size entries; layout: 2 n_seg + 1 entries.
+int64_t depth_ranges_hist_size(int64_t seg_len, int n_seg);
+bool depth_ranges_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
+                       const uint32_t* lo, const uint32_t* hi, int key_bits, uint32_t* hist, uint32_t* partial,
+                       uint32_t* layout, hipStream_t s, hipError_t* err);
+// The front of each view's depth order: n_vis[v] visible keys (not `culled`), thr[v] the smallest bin boundary of
+// the top 12 key bits with at least ceil(n_vis num / den) keys below it, n_front[v] that many.  hist:
+// front_hist_size(N) entries of scratch.
+int64_t front_hist_size(int N);
+hipError_t launch_front_select(const uint64_t* keys, int64_t G, int N, int key_bits, uint64_t culled, int64_t num,
+                               int64_t den, uint32_t* hist, uint64_t* thr, uint32_t* n_vis, uint32_t* n_front,
+                               hipStream_t s);
+// Ranges of the depth sorts: live == nullptr: the fronts [vG, vG + f); else the backs [vG + f, vG + n) of views
+// with a live tile (empty otherwise); rank_hi = end rank of the range.
+hipError_t launch_depth_ranges(int N, int64_t G, const uint32_t* n_vis, const uint32_t* n_front,
+                               const uint32_t* live, uint32_t* lo, uint32_t* hi, uint32_t* rank_hi, hipStream_t s);
 bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
                     const uint32_t* seg_n, uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial,
                     hipStream_t s, hipError_t* err);
@@ -123,11 +144,9 @@ hipError_t launch_lower_bounds(const uint32_t* keys, const uint32_t* n_dev, uint
 // ---- projection (project.hip) ----
 hipError_t launch_project(const float* soa, const double* cams, const ProjConst& pc, float4* rec, uint64_t* keys,
                           uint32_t* vals, double* depth_out, hipStream_t s);
-// rec_sorted[v][r] = rec[v][sorted[v][r]] for r < vis_count[v]
-hipError_t launch_gather_records(const float4* rec, const uint32_t* sorted, const uint32_t* vis_count, int64_t G,
-                                 int N, float4* out, hipStream_t s);
-// vis_count[v] = number of visible Gaussians of view v, from its depth-sorted keys
-hipError_t launch_count_visible(const uint64_t* sorted_keys, int64_t G, int N, uint32_t* vis_count, hipStream_t s);
+// rec_sorted[v][r] = rec[v][sorted[v][r]] for rank_lo[v] <= r < rank_hi[v] (rank_lo nullptr: 0)
+hipError_t launch_gather_records(const float4* rec, const uint32_t* sorted, const uint32_t* rank_lo,
+                                 const uint32_t* rank_hi, int64_t G, int N, float4* out, hipStream_t s);
 hipError_t launch_scene_transpose(const float* means, const float* log_scales, const float* quats,
                                   const float* logits, const float* sh, int64_t n, int64_t n_pad, float* soa,
                                   hipStream_t s);

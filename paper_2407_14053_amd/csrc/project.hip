@@ -164,36 +164,24 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
   }
 }
 
-// Records in depth order: rec_sorted[v][r] = rec[v][sorted[v][r]] for the n_v visible ranks of view v, so
-// that binning reads consecutive records and the blend's list entries are ranks.
+// Records in depth order: rec_sorted[v][r] = rec[v][sorted[v][r]] for the ranks r in [rank_lo[v], rank_hi[v]) of
+// view v (rank_lo nullptr: 0), so that binning reads consecutive records and the blend's list entries are ranks.
 __global__ __launch_bounds__(256) void gather_records_kernel(const float4* __restrict__ rec,
                                                              const uint32_t* __restrict__ sorted,
-                                                             const uint32_t* __restrict__ vis_count, int64_t G,
+                                                             const uint32_t* __restrict__ rank_lo,
+                                                             const uint32_t* __restrict__ rank_hi, int64_t G,
                                                              float4* __restrict__ out) {
   const int v = blockIdx.y;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= (int64_t)vis_count[v]) return;
   const int64_t o = (int64_t)v * G;
-  const float4* src = rec + (o + sorted[o + r]) * kRecF4;
-  float4* dst = out + (o + r) * kRecF4;
-  dst[0] = src[0];
-  dst[1] = src[1];
-  dst[2] = src[2];
-}
-
-// Visible Gaussians of view v = position of the first culled key in its sorted segment.
-__global__ __launch_bounds__(64) void count_visible_kernel(const uint64_t* __restrict__ sorted_keys, int64_t G, int N,
-                                                           uint32_t* __restrict__ vis_count) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= N) return;
-  const uint64_t* k = sorted_keys + (int64_t)v * G;
-  int64_t lo = 0, hi = G;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (k[mid] < kDepthCulled) lo = mid + 1;
-    else hi = mid;
+  const int64_t hi = rank_hi[v];
+  for (int64_t r = (rank_lo ? rank_lo[v] : 0) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < hi;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const float4* src = rec + (o + sorted[o + r]) * kRecF4;
+    float4* dst = out + (o + r) * kRecF4;
+    dst[0] = src[0];
+    dst[1] = src[1];
+    dst[2] = src[2];
   }
-  vis_count[v] = (uint32_t)lo;
 }
 
 __global__ __launch_bounds__(256) void scene_transpose_kernel(const float* __restrict__ means,
@@ -228,16 +216,11 @@ hipError_t launch_project(const float* soa, const double* cams, const ProjConst&
   return hipGetLastError();
 }
 
-hipError_t launch_gather_records(const float4* rec, const uint32_t* sorted, const uint32_t* vis_count, int64_t G,
-                                 int N, float4* out, hipStream_t s) {
-  hipLaunchKernelGGL(gather_records_kernel, dim3((unsigned)((G + 255) / 256), (unsigned)N), dim3(256), 0, s, rec, sorted,
-                     vis_count, G, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_count_visible(const uint64_t* sorted_keys, int64_t G, int N, uint32_t* vis_count, hipStream_t s) {
-  hipLaunchKernelGGL(count_visible_kernel, dim3((unsigned)((N + 63) / 64)), dim3(64), 0, s, sorted_keys, G, N,
-                     vis_count);
+hipError_t launch_gather_records(const float4* rec, const uint32_t* sorted, const uint32_t* rank_lo,
+                                 const uint32_t* rank_hi, int64_t G, int N, float4* out, hipStream_t s) {
+  const unsigned per_view = (unsigned)std::min<int64_t>((G + 255) / 256, 256);
+  hipLaunchKernelGGL(gather_records_kernel, dim3(per_view, (unsigned)N), dim3(256), 0, s, rec, sorted, rank_lo,
+                     rank_hi, G, out);
   return hipGetLastError();
 }
 

@@ -102,6 +102,7 @@ struct dl_ctx {
   int device = 0;
   DevBuf live;    // live tiles per view after the last blended chunk
   DevBuf vstart;  // start of each view's tile keys in the current chunk [N + 1]
+  DevBuf dord, thr, fhist;  // depth order: fronts and sort ranges, front thresholds, key histogram
   DevBuf cams, rec, srec, k64[2], v32[2], vis, counts, bk[2], bv[2], hist, partial, tstart, views, stats, alive,
       state, dtotal, nkeys, gacc;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
@@ -336,7 +337,11 @@ int depth_key_e0(float z_near) {
   return (int)(b >> 52);
 }
 
-int64_t chunk_stride(int64_t G, int c) { return G * (kChunkBounds[c + 1] - kChunkBounds[c]) / kChunkDen + 1; }
+// Item slots per view of chunk c: the first chunk is the view's front (at most all G ranks), the others a rank
+// fraction of the visible Gaussians.
+int64_t chunk_stride(int64_t G, int c) {
+  return c == 0 ? G + 1 : G * (kChunkBounds[c + 1] - kChunkBounds[c]) / kChunkDen + 1;
+}
 
 // How a frame is issued: eager frames upload their cameras and end with the overflow check; a frame being
 // captured into a graph does neither (the plan uploads the cameras before each launch and reads the overflow
@@ -373,7 +378,8 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   if (C->key_cap == 0) C->key_cap = (uint32_t)std::min<int64_t>(kMaxKeyCap, std::max<int64_t>(1 << 22, 2 * NG));
   const uint32_t cap = C->key_cap;
   const int64_t nstate = standard ? (int64_t)N * d.width * d.height : L->n_rays;
-  const int64_t max_stride = chunk_stride(G, kChunks - 1) + 64;
+  int64_t max_stride = 0;
+  for (int c = 0; c < kChunks; ++c) max_stride = std::max(max_stride, chunk_stride(G, c) + 64);
   HIP_TRY(C->cams.ensure((size_t)N * kCamDoubles * 8));
   HIP_TRY(C->rec.ensure((size_t)NG * kRecF4 * 16));
   HIP_TRY(C->srec.ensure((size_t)NG * kRecF4 * 16));
@@ -386,6 +392,9 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   HIP_TRY(C->counts.ensure((size_t)N * max_wstride * 4));
   HIP_TRY(C->live.ensure((size_t)N * 4));
   HIP_TRY(C->vstart.ensure((size_t)(3 * N + 2) * 4));  // view starts, then the partition layout
+  HIP_TRY(C->dord.ensure((size_t)(6 * N + 1) * 4));    // fronts, sort ranges, rank ends, sort layout
+  HIP_TRY(C->thr.ensure((size_t)N * 8));
+  HIP_TRY(C->fhist.ensure((size_t)front_hist_size(N) * 4));
   HIP_TRY(C->bk[0].ensure((size_t)cap * 4));
   HIP_TRY(C->bk[1].ensure((size_t)cap * 4));
   HIP_TRY(C->bv[0].ensure((size_t)cap * 4));
@@ -395,7 +404,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   HIP_TRY(C->state.ensure((size_t)std::max<int64_t>(nstate, 1) * 16));
   HIP_TRY(C->dtotal.ensure(2 * 8));
   HIP_TRY(C->nkeys.ensure(4));
-  const int64_t hs = std::max(radix_hist_size(G, N), tile_partition_hist_size(N));
+  const int64_t hs = std::max(std::max(radix_hist_size(G, N), depth_ranges_hist_size(G, N)), tile_partition_hist_size(N));
   HIP_TRY(C->hist.ensure((size_t)hs * 4));
   HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, N * max_wstride)) + 2) * 4));
   if (C->prof >= 2) HIP_TRY(C->stats.ensure((size_t)kStatSlots * 3 * 8));
@@ -434,14 +443,31 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                          C->v32[0].as<uint32_t>(), nullptr, s));
   C->end(mk, s);
   hipError_t e;
+  // Depth order.  The first chunk is each view's front (the nearest ~1/16 of its visible Gaussians, chosen on a
+  // histogram of the keys' top bits); one stable pass drops the culled items and puts the front before the
+  // back, the fronts are sorted now and the backs after the first chunk, only for views that still have a live
+  // tile.  Both sorts take the same number of passes, so the ranks of a view end in one buffer.
   mk = C->begin(DL_STAGE_DEPTH_SORT, s);
-  // culled items are left out by the first pass; vis[v] = visible Gaussians of view v
-  bool fl = radix_sort_u64_drop(C->k64[0].as<uint64_t>(), C->v32[0].as<uint32_t>(), C->k64[1].as<uint64_t>(),
-                                C->v32[1].as<uint32_t>(), G, N, 0, kDepthKeyBits, kDepthCulled,
-                                C->vis.as<uint32_t>(), C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s, &e);
+  uint32_t* vis = C->vis.as<uint32_t>();
+  uint32_t* front = C->dord.as<uint32_t>();
+  uint32_t* rlo = front + N;
+  uint32_t* rhi = rlo + N;
+  uint32_t* rank_hi = rhi + N;
+  uint32_t* dlayout = rank_hi + N;  // 2N + 1
+  uint64_t* thr = C->thr.as<uint64_t>();
+  HIP_TRY(launch_front_select(C->k64[0].as<uint64_t>(), G, N, kDepthKeyBits, kDepthCulled, kChunkBounds[1], kChunkDen,
+                              C->fhist.as<uint32_t>(), thr, vis, front, s));
+  radix_split_u64(C->k64[0].as<uint64_t>(), C->v32[0].as<uint32_t>(), C->k64[1].as<uint64_t>(),
+                  C->v32[1].as<uint32_t>(), G, N, thr, kDepthCulled, C->hist.as<uint32_t>(),
+                  C->partial.as<uint32_t>(), s, &e);
+  if (e != hipSuccess) return fail(DL_EHIP, std::string("depth split: ") + hipGetErrorString(e));
+  HIP_TRY(launch_depth_ranges(N, G, vis, front, nullptr, rlo, rhi, rank_hi, s));
+  const bool fl = depth_ranges_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), C->k64[0].as<uint64_t>(),
+                                    C->v32[0].as<uint32_t>(), G, N, rlo, rhi, kDepthKeyBits, C->hist.as<uint32_t>(),
+                                    C->partial.as<uint32_t>(), dlayout, s, &e);
   if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
-  const uint32_t* sorted = fl ? C->v32[1].as<uint32_t>() : C->v32[0].as<uint32_t>();
-  HIP_TRY(launch_gather_records(C->rec.as<float4>(), sorted, C->vis.as<uint32_t>(), G, N, C->srec.as<float4>(), s));
+  const uint32_t* sorted = fl ? C->v32[0].as<uint32_t>() : C->v32[1].as<uint32_t>();
+  HIP_TRY(launch_gather_records(C->rec.as<float4>(), sorted, nullptr, rank_hi, G, N, C->srec.as<float4>(), s));
   C->end(mk, s);
 
   BlendConst bc{};
@@ -468,6 +494,8 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     ch.num_lo = kChunkBounds[c];
     ch.num_hi = kChunkBounds[c + 1];
     ch.den = kChunkDen;
+    ch.front = front;
+    ch.first = c == 0;
     ch.stride = chunk_stride(G, c);
     ch.wstride = (ch.stride + 63) / 64;
     ch.cap = cap;
@@ -512,6 +540,18 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     }
     if (c + 1 < kChunks) HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), s));
     C->end(mk, s);
+    if (c == 0 && kChunks > 1) {
+      // the backs of the views that still have a live tile
+      mk = C->begin(DL_STAGE_DEPTH_SORT, s);
+      HIP_TRY(launch_depth_ranges(N, G, vis, front, C->live.as<uint32_t>(), rlo, rhi, rank_hi, s));
+      const bool fl2 = depth_ranges_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), C->k64[0].as<uint64_t>(),
+                                         C->v32[0].as<uint32_t>(), G, N, rlo, rhi, kDepthKeyBits,
+                                         C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), dlayout, s, &e);
+      if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
+      if (fl2 != fl) return fail(DL_EHIP, "depth sorts ended in different buffers");
+      HIP_TRY(launch_gather_records(C->rec.as<float4>(), sorted, front, rank_hi, G, N, C->srec.as<float4>(), s));
+      C->end(mk, s);
+    }
   }
   if (bwd) {
     mk = C->begin(DL_STAGE_PROJECT, s);
@@ -521,12 +561,12 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   }
   if (!mode.finish) return DL_OK;
   unsigned long long mx = 0;
-  std::vector<uint32_t> vis(N, 0);
+  std::vector<uint32_t> vis_host(N, 0);
   HIP_TRY(hipMemcpyAsync(&mx, total + 1, 8, hipMemcpyDeviceToHost, s));
-  if (C->prof) HIP_TRY(hipMemcpyAsync(vis.data(), C->vis.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
+  if (C->prof) HIP_TRY(hipMemcpyAsync(vis_host.data(), C->vis.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   C->keys = (int64_t)mx;
-  for (int v = 0; v < N; ++v) C->visible += vis[v];
+  for (int v = 0; v < N; ++v) C->visible += vis_host[v];
   if (mx > cap) {
     *need = mx;
     return DL_ECAP;
@@ -807,7 +847,7 @@ namespace {
 size_t ctx_bytes(const dl_ctx* C) {
   const DevBuf* b[] = {&C->cams, &C->rec, &C->srec, &C->k64[0], &C->k64[1], &C->v32[0], &C->v32[1], &C->vis,
                        &C->counts, &C->bk[0], &C->bk[1], &C->bv[0], &C->bv[1], &C->hist, &C->partial, &C->tstart,
-                       &C->views, &C->stats, &C->alive, &C->state, &C->dtotal, &C->nkeys, &C->gacc, &C->live, &C->vstart};
+                       &C->views, &C->stats, &C->alive, &C->state, &C->dtotal, &C->nkeys, &C->gacc, &C->live, &C->vstart, &C->dord, &C->thr, &C->fhist};
   size_t t = 0;
   for (const DevBuf* x : b) t += x->cap;
   return t;

@@ -114,21 +114,22 @@ template <typename K>
 struct SortArgs {
   const K* kin;
   const uint32_t* vin;
-  K* kout;
+  K* kout;                // nullptr: keys are not written (the last pass of a partition)
   uint32_t* vout;
   int64_t seg_len;
   const uint32_t* seg_n;  // device live lengths (nullptr: seg_len)
-  uint32_t cap;           // clamp of device lengths
-  int bps;                // blocks per segment
+  uint32_t cap;           // clamp of device lengths and range ends
+  int bps;                // blocks per segment (the maximum, with device ranges)
   int shift, bits;
   uint32_t* hist;
-  int drop;               // this pass leaves out items whose key equals drop_key (the first pass only)
+  int drop;               // this pass leaves out items whose key equals drop_key
   K drop_key;
-  // device segment ranges [seg_start[s], seg_start[s + 1]) (clamped to cap) of one array, written back to the
-  // same ranges at absolute positions; nullptr: segment s is [s * seg_len, s * seg_len + live length)
-  const uint32_t* seg_start;
-  // with seg_start: histogram layout [segment][digit < ndig][block < bpse[seg]] from offset hoff[seg]; empty
-  // segments take no entries and no blocks
+  const K* split;         // one-bit digit: key >= split[seg] (instead of a bit field of the key)
+  // device ranges: segment s is [seg_lo[s], seg_hi[s]) (clamped to cap) of one array, sorted in place; the
+  // histogram is laid out [segment][digit < ndig][block < bpse[s]] from hoff[s], so empty segments take no
+  // entries and no blocks.  nullptr: segment s is [s * seg_len, s * seg_len + live length).
+  const uint32_t* seg_lo;
+  const uint32_t* seg_hi;
   const uint32_t* hoff;
   const uint32_t* bpse;
   int ndig;
@@ -136,7 +137,7 @@ struct SortArgs {
 
 template <typename K>
 __device__ inline int64_t hist_at(const SortArgs<K>& a, int seg, int d, int bis, int bps, int radix) {
-  return a.seg_start ? (int64_t)a.hoff[seg] + (int64_t)d * bps + bis : ((int64_t)seg * radix + d) * a.bps + bis;
+  return a.seg_lo ? (int64_t)a.hoff[seg] + (int64_t)d * bps + bis : ((int64_t)seg * radix + d) * a.bps + bis;
 }
 
 template <typename K>
@@ -145,18 +146,22 @@ __device__ inline int64_t live_len(const SortArgs<K>& a, int seg) {
   return min((int64_t)min(a.seg_n[seg], a.cap), a.seg_len);
 }
 
-// Input range of segment `seg` and whether output positions are absolute.
+// Input range [base, base + n) of segment `seg`; output goes to the same range.
 template <typename K>
 __device__ inline void seg_range(const SortArgs<K>& a, int seg, int64_t& base, int64_t& n) {
-  if (a.seg_start) {
-    base = min(a.seg_start[seg], a.cap);
-    n = (int64_t)min(a.seg_start[seg + 1], a.cap) - base;
+  if (a.seg_lo) {
+    base = min(a.seg_lo[seg], a.cap);
+    n = max((int64_t)0, (int64_t)min(a.seg_hi[seg], a.cap) - base);
   } else {
     base = (int64_t)seg * a.seg_len;
     n = live_len(a, seg);
   }
 }
 
+template <typename K>
+__device__ inline uint32_t digit_of(const SortArgs<K>& a, int seg, K k, uint32_t dmask) {
+  return a.split ? (uint32_t)(k >= a.split[seg]) : (uint32_t)(k >> a.shift) & dmask;
+}
 
 template <typename K, int RB>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(SortArgs<K> a) {
@@ -170,9 +175,9 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(SortArgs<K> a) {
   __syncthreads();
   const int seg = blockIdx.x / a.bps;
   const int bis = blockIdx.x - seg * a.bps;
-  const int bps = a.seg_start ? (int)a.bpse[seg] : a.bps;
+  const int bps = a.seg_lo ? (int)a.bpse[seg] : a.bps;
   if (bis >= bps) return;
-  const int ndig = a.seg_start ? a.ndig : radix;
+  const int ndig = a.seg_lo ? a.ndig : radix;
   int64_t base, n, lo, hi;
   seg_range(a, seg, base, n);
   block_range(n, bps, bis, lo, hi);
@@ -180,8 +185,7 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(SortArgs<K> a) {
   for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
     const K k = kin[i];
     if (a.drop && k == a.drop_key) continue;
-    const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
-    atomicAdd(&h[w][d], 1u);
+    atomicAdd(&h[w][digit_of(a, seg, k, dmask)], 1u);
   }
   __syncthreads();
   for (int d = threadIdx.x; d < ndig; d += kThreads) {
@@ -205,20 +209,18 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int seg = blockIdx.x / a.bps;
   const int bis = blockIdx.x - seg * a.bps;
-  const int bps = a.seg_start ? (int)a.bpse[seg] : a.bps;
+  const int bps = a.seg_lo ? (int)a.bpse[seg] : a.bps;
   if (bis >= bps) return;
-  const int ndig = a.seg_start ? a.ndig : radix;
+  const int ndig = a.seg_lo ? a.ndig : radix;
   int64_t base, n, lo, hi;
   seg_range(a, seg, base, n);
   block_range(n, bps, bis, lo, hi);
   const K* kin = a.kin + base;
   const uint32_t* vin = a.vin + base;
-  // the scan runs over all segments: its values are absolute positions when segments are ranges of one
-  // array (seg_start), else subtract the segment's first offset so positions are segment-relative
-  const int64_t obase = a.seg_start ? 0 : base;
-  K* kout = a.kout ? a.kout + obase : nullptr;
-  uint32_t* vout = a.vout + obase;
-  const uint32_t seg0 = a.seg_start ? 0u : a.hist[(int64_t)seg * radix * a.bps];
+  K* kout = a.kout ? a.kout + base : nullptr;
+  uint32_t* vout = a.vout + base;
+  // the scan runs over all segments; subtract the segment's first offset so positions are segment-relative
+  const uint32_t seg0 = a.hist[a.seg_lo ? (int64_t)a.hoff[seg] : (int64_t)seg * radix * a.bps];
   for (int d = threadIdx.x; d < radix; d += kThreads)
     run[d] = d < ndig ? a.hist[hist_at(a, seg, d, bis, bps, radix)] - seg0 : 0u;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
       key[r] = valid ? kin[t0 + li] : (K)0;
       val[r] = valid ? vin[t0 + li] : 0u;
       if (a.drop && key[r] == a.drop_key) valid = false;
-      const uint32_t d = (uint32_t)(key[r] >> a.shift) & dmask;
+      const uint32_t d = digit_of(a, seg, key[r], dmask);
       dig[r] = d;
       uint64_t m = __ballot(valid);
       for (int b = 0; b < a.bits; ++b) {
@@ -297,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
     // contiguous runs per digit: consecutive lanes write consecutive addresses (`total` = kept items)
     for (int p = threadIdx.x; p < (int)total; p += kThreads) {
       const K k = skey[p];
-      const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
+      const uint32_t d = digit_of(a, seg, k, dmask);
       const uint32_t g = run[d] + (uint32_t)p - loff[d];
       if (kout) kout[g] = k;
       vout[g] = sval[p];
@@ -312,38 +314,42 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
   }
 }
 
-// List starts of a one-pass partition: the first output position of digit t in segment v is the scanned
-// histogram at [v][t][block 0] (an empty segment has no entries: its lists start at its range);
-// start[n_seg * n_dig] = end of the last segment.
+// List starts of a one-pass partition: the first output position of digit t in segment v is the segment's
+// start plus the scanned histogram at [v][t][block 0] less the segment's first entry (an empty segment has no
+// entries: its lists start at its range); start[n_seg * n_dig] = end of the last segment.
 __global__ __launch_bounds__(kThreads) void hist_starts_kernel(const uint32_t* __restrict__ hist,
                                                                  const uint32_t* __restrict__ hoff,
                                                                  const uint32_t* __restrict__ bpse, int n_dig,
-                                                                 int n_seg, const uint32_t* __restrict__ seg_start,
-                                                                 uint32_t cap, uint32_t* __restrict__ start) {
+                                                                 int n_seg, const uint32_t* __restrict__ seg_lo,
+                                                                 const uint32_t* __restrict__ seg_hi, uint32_t cap,
+                                                                 uint32_t* __restrict__ start) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t n = (int64_t)n_seg * n_dig;
   if (i > n) return;
   if (i == n) {
-    start[i] = min(seg_start[n_seg], cap);
+    start[i] = min(seg_hi[n_seg - 1], cap);
     return;
   }
   const int v = (int)(i / n_dig);
   const int t = (int)(i - (int64_t)v * n_dig);
   const uint32_t b = bpse[v];
-  start[i] = b ? hist[(int64_t)hoff[v] + (int64_t)t * b] : min(seg_start[v], cap);
+  const uint32_t lo = min(seg_lo[v], cap);
+  start[i] = b ? lo + (hist[(int64_t)hoff[v] + (int64_t)t * b] - hist[hoff[v]]) : lo;
 }
 
-// Histogram layout of a partition: blocks per segment = its tiles of kTile items (at most bps_max, none for an
-// empty segment), offsets = exclusive scan of n_dig x blocks; hoff[n_seg] = entries in use.  One workgroup;
-// n_seg <= kThreads.
-__global__ __launch_bounds__(kThreads) void part_layout_kernel(const uint32_t* __restrict__ seg_start, uint32_t cap,
+// Histogram layout over device ranges: blocks per segment = its tiles of kTile items (at most bps_max, none for
+// an empty segment), offsets = exclusive scan of n_dig x blocks; hoff[n_seg] = entries in use.  One workgroup
+// per kThreads segments is not needed: n_seg <= kThreads.
+__global__ __launch_bounds__(kThreads) void part_layout_kernel(const uint32_t* __restrict__ seg_lo,
+                                                                 const uint32_t* __restrict__ seg_hi, uint32_t cap,
                                                                  int n_seg, int n_dig, int bps_max,
                                                                  uint32_t* __restrict__ bpse,
                                                                  uint32_t* __restrict__ hoff) {
   const int v = threadIdx.x;
   uint32_t b = 0;
   if (v < n_seg) {
-    const uint32_t n = min(seg_start[v + 1], cap) - min(seg_start[v], cap);
+    const uint32_t lo = min(seg_lo[v], cap), hi = min(seg_hi[v], cap);
+    const uint32_t n = hi > lo ? hi - lo : 0u;
     b = (uint32_t)min((int64_t)bps_max, ((int64_t)n + kTile - 1) / kTile);
     bpse[v] = b;
   }
@@ -355,18 +361,19 @@ __global__ __launch_bounds__(kThreads) void part_layout_kernel(const uint32_t* _
 
 // List starts after a multi-pass partition: first position in segment v whose key is >= t.
 __global__ __launch_bounds__(kThreads) void segment_bounds_kernel(const uint32_t* __restrict__ keys, int n_dig,
-                                                                    int n_seg, const uint32_t* __restrict__ seg_start,
-                                                                    uint32_t cap, uint32_t* __restrict__ start) {
+                                                                    int n_seg, const uint32_t* __restrict__ seg_lo,
+                                                                    const uint32_t* __restrict__ seg_hi, uint32_t cap,
+                                                                    uint32_t* __restrict__ start) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t n = (int64_t)n_seg * n_dig;
   if (i > n) return;
   if (i == n) {
-    start[i] = min(seg_start[n_seg], cap);
+    start[i] = min(seg_hi[n_seg - 1], cap);
     return;
   }
   const int v = (int)(i / n_dig);
   const uint32_t t = (uint32_t)(i - (int64_t)v * n_dig);
-  uint32_t lo = min(seg_start[v], cap), hi = min(seg_start[v + 1], cap);
+  uint32_t lo = min(seg_lo[v], cap), hi = max(lo, min(seg_hi[v], cap));
   while (lo < hi) {
     const uint32_t mid = lo + ((hi - lo) >> 1);
     if (keys[mid] < t) lo = mid + 1;
@@ -375,15 +382,93 @@ __global__ __launch_bounds__(kThreads) void segment_bounds_kernel(const uint32_t
   start[i] = lo;
 }
 
-// Items kept per segment by a dropping pass, from its scanned histogram ([segment][digit][block], exclusive)
-// and the scan's grand total.
-__global__ void segment_counts_kernel(const uint32_t* __restrict__ hist, const uint32_t* __restrict__ grand_total,
-                                      int n_seg, int64_t per_seg, uint32_t* __restrict__ counts) {
-  const int seg = blockIdx.x * blockDim.x + threadIdx.x;
-  if (seg >= n_seg) return;
-  const uint32_t a = hist[(int64_t)seg * per_seg];
-  const uint32_t b = seg + 1 < n_seg ? hist[(int64_t)(seg + 1) * per_seg] : *grand_total;
-  counts[seg] = b - a;
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---- the front of each view's depth order ----
+// Visible keys per view binned on their top kFrontBits bits; one workgroup's counts are added to the view's
+// global histogram bin by bin (only the bins it saw).
+constexpr int kFrontBits = 12;
+constexpr int kFrontBins = 1 << kFrontBits;
+
+__global__ __launch_bounds__(kThreads) void front_hist_kernel(const uint64_t* __restrict__ keys, int64_t G,
+                                                                int key_bits, uint64_t culled,
+                                                                uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kFrontBins];
+  for (int b = threadIdx.x; b < kFrontBins; b += kThreads) h[b] = 0;
+  __syncthreads();
+  const int v = blockIdx.y;
+  const int64_t per = (G + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(G, lo + per);
+  const uint64_t* k = keys + (int64_t)v * G;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+    const uint64_t key = k[i];
+    if (key != culled) atomicAdd(&h[(uint32_t)(key >> (key_bits - kFrontBits))], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kFrontBins; b += kThreads)
+    if (h[b]) atomicAdd(&hist[(int64_t)v * kFrontBins + b], h[b]);
+}
+
+// Per view (one workgroup each): visible count n, and the smallest bin b whose cumulative count reaches
+// ceil(n num / den); the front is every key below thr = (b + 1) << (key_bits - kFrontBits), f its size.
+__global__ __launch_bounds__(kThreads) void front_select_kernel(const uint32_t* __restrict__ hist, int key_bits,
+                                                                  int64_t num, int64_t den, uint64_t* __restrict__ thr,
+                                                                  uint32_t* __restrict__ n_vis,
+                                                                  uint32_t* __restrict__ n_front) {
+  constexpr int kPer = kFrontBins / kThreads;
+  const int v = blockIdx.x;
+  const uint32_t* h = hist + (int64_t)v * kFrontBins;
+  uint32_t c[kPer];
+  uint32_t mine = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    c[i] = h[threadIdx.x * kPer + i];
+    mine += c[i];
+  }
+  uint32_t n;
+  uint32_t run = block_excl_scan(mine, &n);
+  const uint32_t target = (uint32_t)(((int64_t)n * num + den - 1) / den);
+  if (threadIdx.x == 0) {
+    n_vis[v] = n;
+    if (target == 0) {
+      thr[v] = 0;
+      n_front[v] = 0;
+    }
+  }
+  if (target == 0) return;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const uint32_t before = run;
+    run += c[i];
+    if (before < target && run >= target) {
+      thr[v] = (uint64_t)(threadIdx.x * kPer + i + 1) << (key_bits - kFrontBits);
+      n_front[v] = run;
+    }
+  }
+}
+
+// Device ranges of the depth sorts: front [v G, v G + f_v); back [v G + f_v, v G + n_v) for views with a live
+// tile, empty otherwise.  Also the back's rank bounds for the record gather.
+__global__ void depth_ranges_kernel(int N, int64_t G, const uint32_t* __restrict__ n_vis,
+                                    const uint32_t* __restrict__ n_front, const uint32_t* __restrict__ live,
+                                    uint32_t* __restrict__ lo, uint32_t* __restrict__ hi,
+                                    uint32_t* __restrict__ rank_hi) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const uint32_t base = (uint32_t)((int64_t)v * G);
+  if (!live) {
+    lo[v] = base;
+    hi[v] = base + n_front[v];
+    rank_hi[v] = n_front[v];
+  } else {
+    const uint32_t e = live[v] ? n_vis[v] : n_front[v];
+    lo[v] = base + n_front[v];
+    hi[v] = base + e;
+    rank_hi[v] = e;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void lower_bounds_kernel(const uint32_t* __restrict__ keys,
@@ -410,9 +495,32 @@ int blocks_per_seg(int64_t seg_len, int n_seg) {
 }
 
 template <typename K>
+SortArgs<K> base_args(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, uint32_t* hist) {
+  SortArgs<K> a{};
+  a.kin = kin;
+  a.vin = vin;
+  a.kout = kout;
+  a.vout = vout;
+  a.hist = hist;
+  a.cap = 0xffffffffu;
+  return a;
+}
+
+template <typename K, int RB>
+hipError_t launch_pass(const SortArgs<K>& a, int64_t nblocks, int64_t hsize, uint32_t* partial,
+                       const uint32_t* hsize_dev, hipStream_t s) {
+  hipLaunchKernelGGL((radix_hist_kernel<K, RB>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = exclusive_scan_u32(a.hist, a.hist, hsize, partial, s, hsize_dev)) != hipSuccess) return e;
+  hipLaunchKernelGGL((radix_scatter_kernel<K, RB>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename K>
 bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, int n_seg, const uint32_t* seg_n,
                      uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial, hipStream_t s,
-                     hipError_t* err, const K* drop_key = nullptr, uint32_t* kept = nullptr) {
+                     hipError_t* err) {
   *err = hipSuccess;
   if (seg_len == 0 || n_seg == 0 || bit_hi <= bit_lo) return false;
   const int bps = blocks_per_seg(seg_len, n_seg);
@@ -424,39 +532,16 @@ bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, 
   int shift = bit_lo;
   for (int p = 0; p < passes; ++p) {
     const int bits = (nbits - (shift - bit_lo) + (passes - p) - 1) / (passes - p);
-    SortArgs<K> a;
-    a.kin = flipped ? k1 : k0;
-    a.vin = flipped ? v1 : v0;
-    a.kout = flipped ? k0 : k1;
-    a.vout = flipped ? v0 : v1;
+    SortArgs<K> a = base_args<K>(flipped ? k1 : k0, flipped ? v1 : v0, flipped ? k0 : k1, flipped ? v0 : v1, hist);
     a.seg_len = seg_len;
     a.seg_n = seg_n;
     a.cap = cap;
     a.bps = bps;
     a.shift = shift;
     a.bits = bits;
-    a.hist = hist;
-    a.drop = (p == 0 && drop_key) ? 1 : 0;
-    a.drop_key = drop_key ? *drop_key : (K)0;
-    if (p > 0 && drop_key) {
-      // after the dropping pass every segment holds only its kept items
-      a.seg_n = kept;
-      a.cap = (uint32_t)std::min<int64_t>(seg_len, 0xffffffffll);
-    }
-    const int64_t hsize = (int64_t)n_seg * (1 << bits) * bps;
-    a.seg_start = nullptr;
-    a.hoff = a.bpse = nullptr;
     a.ndig = 1 << bits;
-    hipLaunchKernelGGL((radix_hist_kernel<K, kMaxBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
-    if ((*err = hipGetLastError()) != hipSuccess) return flipped;
-    if ((*err = exclusive_scan_u32(hist, hist, hsize, partial, s)) != hipSuccess) return flipped;
-    if (a.drop) {
-      hipLaunchKernelGGL(segment_counts_kernel, dim3((unsigned)((n_seg + 63) / 64)), dim3(64), 0, s, hist,
-                         partial + scan_partial_count(hsize), n_seg, (int64_t)(1 << bits) * bps, kept);
-      if ((*err = hipGetLastError()) != hipSuccess) return flipped;
-    }
-    hipLaunchKernelGGL((radix_scatter_kernel<K, kMaxBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
-    if ((*err = hipGetLastError()) != hipSuccess) return flipped;
+    if ((*err = launch_pass<K, kMaxBits>(a, nblocks, (int64_t)n_seg * (1 << bits) * bps, partial, nullptr, s)))
+      return flipped;
     flipped = !flipped;
     shift += bits;
   }
@@ -464,6 +549,43 @@ bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, 
 }
 
 int part_blocks_per_seg(int n_seg) { return std::max(1, (2048 + n_seg - 1) / n_seg); }
+
+// LSD passes over device ranges [lo[s], hi[s]) (clamped to cap) with the adaptive histogram layout.  n_dig_last
+// > 0 makes a single pass use only that many digits (a partition whose keys are below it); kout of the last
+// pass may be dropped.  Returns whether the result is in (k1, v1).
+template <typename K, int RB>
+bool ranges_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int n_seg, const uint32_t* lo, const uint32_t* hi,
+                 uint32_t cap, int bps, int bits_total, int n_dig_one_pass, bool keep_last_keys, uint32_t* hist,
+                 uint32_t* partial, uint32_t* layout, hipStream_t s, hipError_t* err) {
+  *err = hipSuccess;
+  uint32_t* bpse = layout;          // [n_seg]
+  uint32_t* hoff = layout + n_seg;  // [n_seg + 1]
+  const int64_t nblocks = (int64_t)bps * n_seg;
+  const int passes = (bits_total + RB - 1) / RB;
+  bool flipped = false;
+  int shift = 0;
+  for (int p = 0; p < passes; ++p) {
+    const int pb = (bits_total - shift + (passes - p) - 1) / (passes - p);
+    const bool last = p == passes - 1;
+    SortArgs<K> a = base_args<K>(flipped ? k1 : k0, flipped ? v1 : v0,
+                                 (last && !keep_last_keys) ? nullptr : (flipped ? k0 : k1), flipped ? v0 : v1, hist);
+    a.cap = cap;
+    a.bps = bps;
+    a.shift = shift;
+    a.bits = pb;
+    a.seg_lo = lo;
+    a.seg_hi = hi;
+    a.hoff = hoff;
+    a.bpse = bpse;
+    a.ndig = (passes == 1 && n_dig_one_pass > 0) ? n_dig_one_pass : (1 << pb);
+    hipLaunchKernelGGL(part_layout_kernel, dim3(1), dim3(kThreads), 0, s, lo, hi, cap, n_seg, a.ndig, bps, bpse, hoff);
+    if ((*err = launch_pass<K, RB>(a, nblocks, (int64_t)n_seg * a.ndig * bps, partial, hoff + n_seg, s)))
+      return flipped;
+    flipped = !flipped;
+    shift += pb;
+  }
+  return flipped;
+}
 
 }  // namespace
 
@@ -490,11 +612,58 @@ bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int6
                                    err);
 }
 
-bool radix_sort_u64_drop(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
-                         int bit_lo, int bit_hi, uint64_t drop_key, uint32_t* kept, uint32_t* hist, uint32_t* partial,
-                         hipStream_t s, hipError_t* err) {
-  return radix_sort_impl<uint64_t>(k0, v0, k1, v1, seg_len, n_seg, nullptr, 0, bit_lo, bit_hi, hist, partial, s, err,
-                                   &drop_key, kept);
+bool radix_split_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
+                     const uint64_t* thr, uint64_t drop_key, uint32_t* hist, uint32_t* partial, hipStream_t s,
+                     hipError_t* err) {
+  const int bps = blocks_per_seg(seg_len, n_seg);
+  SortArgs<uint64_t> a = base_args<uint64_t>(k0, v0, k1, v1, hist);
+  a.seg_len = seg_len;
+  a.bps = bps;
+  a.bits = 1;
+  a.ndig = 2;
+  a.split = thr;
+  a.drop = 1;
+  a.drop_key = drop_key;
+  *err = launch_pass<uint64_t, kMaxBits>(a, (int64_t)bps * n_seg, (int64_t)n_seg * 2 * bps, partial, nullptr, s);
+  return true;
+}
+
+int64_t depth_ranges_hist_size(int64_t seg_len, int n_seg) {
+  return (int64_t)blocks_per_seg(seg_len, n_seg) * n_seg * kMaxRadix;
+}
+
+bool depth_ranges_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
+                       const uint32_t* lo, const uint32_t* hi, int key_bits, uint32_t* hist, uint32_t* partial,
+                       uint32_t* layout, hipStream_t s, hipError_t* err) {
+  if (n_seg > kThreads) {
+    *err = hipErrorInvalidValue;
+    return false;
+  }
+  // the keys of the last pass are not needed: only the values (Gaussian indices) in depth order are
+  return ranges_sort<uint64_t, kMaxBits>(k0, v0, k1, v1, n_seg, lo, hi, 0xffffffffu, blocks_per_seg(seg_len, n_seg),
+                                         key_bits, 0, false, hist, partial, layout, s, err);
+}
+
+hipError_t launch_front_select(const uint64_t* keys, int64_t G, int N, int key_bits, uint64_t culled, int64_t num,
+                               int64_t den, uint32_t* hist, uint64_t* thr, uint32_t* n_vis, uint32_t* n_front,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)(((int64_t)N * kFrontBins + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, hist, (int64_t)N * kFrontBins, 0u);
+  const unsigned per_view = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (G + 8191) / 8192));
+  hipLaunchKernelGGL(front_hist_kernel, dim3(per_view, (unsigned)N), dim3(kThreads), 0, s, keys, G, key_bits, culled,
+                     hist);
+  hipLaunchKernelGGL(front_select_kernel, dim3((unsigned)N), dim3(kThreads), 0, s, hist, key_bits, num, den, thr,
+                     n_vis, n_front);
+  return hipGetLastError();
+}
+
+int64_t front_hist_size(int N) { return (int64_t)N * kFrontBins; }
+
+hipError_t launch_depth_ranges(int N, int64_t G, const uint32_t* n_vis, const uint32_t* n_front,
+                               const uint32_t* live, uint32_t* lo, uint32_t* hi, uint32_t* rank_hi, hipStream_t s) {
+  hipLaunchKernelGGL(depth_ranges_kernel, dim3((unsigned)((N + 63) / 64)), dim3(64), 0, s, N, G, n_vis, n_front, live,
+                     lo, hi, rank_hi);
+  return hipGetLastError();
 }
 
 bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
@@ -514,64 +683,30 @@ const uint32_t* tile_partition(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_
     *err = hipErrorInvalidValue;
     return nullptr;
   }
-  uint32_t* bpse = layout;               // [n_seg]
-  uint32_t* hoff = layout + n_seg;       // [n_seg + 1]
   int bits = 1;
   while ((1 << bits) < n_dig) ++bits;
   const int bps = part_blocks_per_seg(n_seg);
-  const int64_t nblocks = (int64_t)bps * n_seg;
+  const uint32_t* lo = seg_start;
+  const uint32_t* hi = seg_start + 1;  // consecutive ranges of one array
   const int passes = (bits + kPartBits - 1) / kPartBits;
-  bool flipped = false;
-  int shift = 0;
-  for (int p = 0; p < passes; ++p) {
-    const int pb = (bits - shift + (passes - p) - 1) / (passes - p);
-    const bool last = p == passes - 1;
-    SortArgs<uint32_t> a{};
-    a.kin = flipped ? k1 : k0;
-    a.vin = flipped ? v1 : v0;
-    a.kout = (last && passes == 1) ? nullptr : (flipped ? k0 : k1);  // keys are not needed after one pass
-    a.vout = flipped ? v0 : v1;
-    a.seg_len = 0;
-    a.seg_n = nullptr;
-    a.cap = cap;
-    a.bps = bps;
-    a.shift = shift;
-    a.bits = pb;
-    a.hist = hist;
-    a.drop = 0;
-    a.drop_key = 0;
-    a.seg_start = seg_start;
-    a.hoff = hoff;
-    a.bpse = bpse;
-    a.ndig = passes == 1 ? n_dig : (1 << pb);
-    const int64_t hsize = (int64_t)n_seg * a.ndig * bps;
-    hipLaunchKernelGGL(part_layout_kernel, dim3(1), dim3(kThreads), 0, s, seg_start, cap, n_seg, a.ndig, bps, bpse,
-                       hoff);
-    if (pb > kMaxBits)
-      hipLaunchKernelGGL((radix_hist_kernel<uint32_t, kPartBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
-    else
-      hipLaunchKernelGGL((radix_hist_kernel<uint32_t, kMaxBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
-    if ((*err = hipGetLastError()) != hipSuccess) return nullptr;
-    if ((*err = exclusive_scan_u32(hist, hist, hsize, partial, s, hoff + n_seg)) != hipSuccess) return nullptr;
-    if (pb > kMaxBits)
-      hipLaunchKernelGGL((radix_scatter_kernel<uint32_t, kPartBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
-    else
-      hipLaunchKernelGGL((radix_scatter_kernel<uint32_t, kMaxBits>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
-    if ((*err = hipGetLastError()) != hipSuccess) return nullptr;
-    if (last) {
-      const int64_t ns = (int64_t)n_seg * n_dig + 1;
-      if (passes == 1)
-        hipLaunchKernelGGL(hist_starts_kernel, dim3((unsigned)((ns + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
-                           hist, hoff, bpse, n_dig, n_seg, seg_start, cap, start);
-      else
-        hipLaunchKernelGGL(segment_bounds_kernel, dim3((unsigned)((ns + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                           s, (const uint32_t*)a.kout, n_dig, n_seg, seg_start, cap, start);
-      if ((*err = hipGetLastError()) != hipSuccess) return nullptr;
-    }
-    flipped = !flipped;
-    shift += pb;
-  }
-  return flipped ? v1 : v0;
+  bool fl;
+  if (bits > kMaxBits)
+    fl = ranges_sort<uint32_t, kPartBits>(k0, v0, k1, v1, n_seg, lo, hi, cap, bps, bits, n_dig, passes > 1, hist,
+                                          partial, layout, s, err);
+  else
+    fl = ranges_sort<uint32_t, kMaxBits>(k0, v0, k1, v1, n_seg, lo, hi, cap, bps, bits, n_dig, false, hist, partial,
+                                         layout, s, err);
+  if (*err != hipSuccess) return nullptr;
+  const int64_t ns = (int64_t)n_seg * n_dig + 1;
+  const unsigned g = (unsigned)((ns + kThreads - 1) / kThreads);
+  if (passes == 1)
+    hipLaunchKernelGGL(hist_starts_kernel, dim3(g), dim3(kThreads), 0, s, hist, layout + n_seg, layout, n_dig, n_seg,
+                       lo, hi, cap, start);
+  else
+    hipLaunchKernelGGL(segment_bounds_kernel, dim3(g), dim3(kThreads), 0, s, fl ? k1 : k0, n_dig, n_seg, lo, hi, cap,
+                       start);
+  if ((*err = hipGetLastError()) != hipSuccess) return nullptr;
+  return fl ? v1 : v0;
 }
 
 hipError_t launch_lower_bounds(const uint32_t* keys, const uint32_t* n_dev, uint32_t cap, int64_t n_static,
