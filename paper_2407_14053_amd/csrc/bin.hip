@@ -114,6 +114,7 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
     lo = max(fv, nv * ch.num_lo / ch.den);
     hi = max(lo, nv * ch.num_hi / ch.den);
   }
+  hi = min(hi, lo + ch.stride);  // the host sizes the stride to cover every chunk; never write past its slots
   const bool view_live = !live || live[v] != 0;
   // groups of 256 consecutive ranks of this chunk (none for a view without live tiles)
   const int64_t groups = view_live ? (hi - lo + 255) / 256 : 0;
@@ -204,25 +205,13 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
   }
 }
 
-// Start of each view's key range: the scanned wavefront counts at the view's first wavefront; the end of the
-// last view is the chunk's total.
-__global__ void view_starts_kernel(const uint32_t* __restrict__ scanned, int64_t wstride, int N,
-                                   const unsigned long long* __restrict__ total, uint32_t* __restrict__ start) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v > N) return;
-  if (v == N) {
-    const unsigned long long t = *total;
-    start[v] = (uint32_t)(t < 0xffffffffull ? t : 0xffffffffull);
-  } else {
-    start[v] = scanned[(int64_t)v * wstride];
-  }
-}
-
 // Live tiles of each view (one workgroup per view), read by the binning of the next depth chunk.
 __global__ __launch_bounds__(256) void view_live_kernel(const uint8_t* __restrict__ alive, int64_t T,
-                                                         uint32_t* __restrict__ live) {
+                                                         uint32_t* __restrict__ live,
+                                                         unsigned long long* __restrict__ total) {
   __shared__ uint32_t part[4];
   const int v = blockIdx.x;
+  if (v == 0 && threadIdx.x == 0) *total = 0;  // the next chunk's key count starts from zero
   uint32_t c = 0;
   for (int64_t t = threadIdx.x; t < T; t += 256) c += alive[(int64_t)v * T + t];
   for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
@@ -231,19 +220,15 @@ __global__ __launch_bounds__(256) void view_live_kernel(const uint8_t* __restric
   if (threadIdx.x == 0) live[v] = part[0] + part[1] + part[2] + part[3];
 }
 
-// n = min(total, cap); record the largest total seen and whether any chunk overflowed.
-__global__ void finalize_count_kernel(const unsigned long long* __restrict__ total, uint32_t cap,
-                                      uint32_t* __restrict__ n_out, unsigned long long* __restrict__ max_total) {
-  const unsigned long long t = *total;
-  *n_out = (uint32_t)(t < cap ? t : cap);
-  if (t > *max_total) *max_total = t;
-}
-
-__global__ __launch_bounds__(256) void init_alive_kernel(uint8_t* __restrict__ alive, const uint32_t* __restrict__ ray_off,
-                                                         int64_t n) {
+// Start of a frame: every (view, tile) with rays is live, the key totals and the front histogram are zero.
+__global__ __launch_bounds__(256) void frame_init_kernel(uint8_t* __restrict__ alive,
+                                                         const uint32_t* __restrict__ ray_off, int64_t n,
+                                                         uint32_t* __restrict__ zero32, int64_t n_zero,
+                                                         unsigned long long* __restrict__ totals) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  alive[i] = ray_off ? (uint8_t)(ray_off[i + 1] > ray_off[i]) : (uint8_t)1;
+  if (i < n) alive[i] = ray_off ? (uint8_t)(ray_off[i + 1] > ray_off[i]) : (uint8_t)1;
+  if (i < n_zero) zero32[i] = 0;
+  if (i < 2) totals[i] = 0;
 }
 
 __global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long v) {
@@ -275,26 +260,17 @@ hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const u
   return hipGetLastError();
 }
 
-hipError_t launch_view_starts(const uint32_t* scanned, int64_t wstride, int N, const unsigned long long* total,
-                              uint32_t* start, hipStream_t s) {
-  hipLaunchKernelGGL(view_starts_kernel, dim3((unsigned)((N + 1 + 63) / 64)), dim3(64), 0, s, scanned, wstride, N, total,
-                     start);
+hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, unsigned long long* total,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(view_live_kernel, dim3((unsigned)N), dim3(256), 0, s, alive, T, live, total);
   return hipGetLastError();
 }
 
-hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, hipStream_t s) {
-  hipLaunchKernelGGL(view_live_kernel, dim3((unsigned)N), dim3(256), 0, s, alive, T, live);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize_count(const unsigned long long* total, uint32_t cap, uint32_t* n_out,
-                                 unsigned long long* max_total, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_count_kernel, dim3(1), dim3(1), 0, s, total, cap, n_out, max_total);
-  return hipGetLastError();
-}
-
-hipError_t launch_init_alive(uint8_t* alive, const uint32_t* ray_off, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(init_alive_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, alive, ray_off, n);
+hipError_t launch_frame_init(uint8_t* alive, const uint32_t* ray_off, int64_t n, uint32_t* zero32, int64_t n_zero,
+                             unsigned long long* totals, hipStream_t s) {
+  const int64_t m = std::max<int64_t>(std::max<int64_t>(n, n_zero), 2);
+  hipLaunchKernelGGL(frame_init_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, alive, ray_off, n, zero32,
+                     n_zero, totals);
   return hipGetLastError();
 }
 

@@ -67,7 +67,8 @@ __device__ inline float blend_qlim(float o, const BlendConst& bc) {
 struct ChunkArgs {
   int64_t num_lo, num_hi, den;
   // front[v]: size of view v's front (the first chunk); later chunks start no earlier.  The chunk of view v is
-  // ranks [0, front) for the first chunk, else [max(front, n lo), max(that, n hi)) of its n visible ranks.
+  // ranks [0, front) for the first chunk, else [max(front, n lo), max(that, n hi)) of its n visible ranks (the
+  // second chunk has lo = 0, so that the chunks tile the ranks whatever the front's size).
   const uint32_t* front;
   int first;
   int64_t stride;   // item slots per view (a multiple of 64 is not required)
@@ -91,17 +92,17 @@ hipError_t launch_interleave(const uint8_t* V, const float* views, float* out, i
 int64_t scan_partial_count(int64_t n);
 // exclusive scan of n uint32 (in may equal out); `partial` holds scan_partial_count(n) + 1 entries and
 // receives the grand total in partial[scan_partial_count(n)].
-// With n_dev, only the first min(n, *n_dev) entries are scanned; the grand total of what was scanned lands in
+// With n_dev, only the first min(n, n_mul * *n_dev) entries are scanned; the grand total of what was scanned lands in
 // partial[scan_partial_count(n)] either way.
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, hipStream_t s,
-                              const uint32_t* n_dev = nullptr);
+                              const uint32_t* n_dev = nullptr, int n_mul = 1);
 int64_t radix_hist_size(int64_t seg_len, int n_seg);
 // Stable partition of (key = digit < n_dig, value) pairs within each of n_seg segments given as device ranges
 // [seg_start[s], seg_start[s + 1]) of one array (clamped to cap): afterwards every segment holds its values
 // grouped by digit, in input order within a digit.  start[s * n_dig + d] receives the first position of
 // digit d in segment s, start[n_seg * n_dig] the end.  Returns the buffer holding the partitioned values
-// (v0 or v1); keys k0/k1 are scratch.  hist: tile_partition_hist_size(n_seg) entries; layout: 2 n_seg + 1
-// entries; n_seg <= 256.
+// (v0 or v1); keys k0/k1 are scratch.  hist: tile_partition_hist_size(n_seg) entries; layout: the 2 n_seg + 1
+// entries launch_chunk_setup wrote for these ranges; n_seg <= 256.
 int64_t tile_partition_hist_size(int n_seg);
 const uint32_t* tile_partition(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int n_seg,
                                const uint32_t* seg_start, uint32_t cap, int n_dig, uint32_t* hist, uint32_t* partial,
@@ -112,28 +113,35 @@ const uint32_t* tile_partition(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_
 bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
                     const uint32_t* seg_n, uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial,
                     hipStream_t s, hipError_t* err);
-// One stable pass over full segments [s seg_len, (s + 1) seg_len) that leaves out items whose key is drop_key and
-// splits the rest into keys < thr[s] (first) and keys >= thr[s]; results in (k1, v1).
-bool radix_split_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
-                     const uint64_t* thr, uint64_t drop_key, uint32_t* hist, uint32_t* partial, hipStream_t s,
-                     hipError_t* err);
-// Stable LSD sort of each device range [lo[s], hi[s]) in place (n_seg <= 256); returns whether the result is in
-// (k1, v1).  hist: depth_ranges_hist_size entries; layout: 2 n_seg + 1 entries.
+// One stable pass over full segments [s seg_len, (s + 1) seg_len) of keys k0 that leaves out items whose key is
+// drop_key and splits the rest into keys < thr[s] (first) and keys >= thr[s]; values are the items' positions in
+// their segment.  Results in (k1, v1); n_vis[s] = items kept, n_front[s] = items below thr[s].
+bool radix_split_u64(uint64_t* k0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg, const uint64_t* thr,
+                     uint64_t drop_key, uint32_t* n_vis, uint32_t* n_front, uint32_t* hist, uint32_t* partial,
+                     hipStream_t s, hipError_t* err);
+// Stable LSD sort of each device range [lo[s], hi[s]) in place (n_seg <= 256), with the histogram layout that
+// launch_depth_ranges wrote to `layout`; returns whether the result is in (k1, v1).  hist: depth_ranges_hist_size
+// entries.
 int64_t depth_ranges_hist_size(int64_t seg_len, int n_seg);
 bool depth_ranges_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
                        const uint32_t* lo, const uint32_t* hi, int key_bits, uint32_t* hist, uint32_t* partial,
                        uint32_t* layout, hipStream_t s, hipError_t* err);
-// The front of each view's depth order: n_vis[v] visible keys (not `culled`), thr[v] the smallest bin boundary of
-// the top 12 key bits with at least ceil(n_vis num / den) keys below it, n_front[v] that many.  hist:
-// front_hist_size(N) entries of scratch.
+// The front of each view's depth order: thr[v] = the smallest bin boundary of the top 12 key bits with at least
+// a fraction num / den of a sample of the view's visible keys (not `culled`) below it.  hist: front_hist_size(N)
+// entries, zero on entry.
 int64_t front_hist_size(int N);
 hipError_t launch_front_select(const uint64_t* keys, int64_t G, int N, int key_bits, uint64_t culled, int64_t num,
-                               int64_t den, uint32_t* hist, uint64_t* thr, uint32_t* n_vis, uint32_t* n_front,
-                               hipStream_t s);
+                               int64_t den, uint32_t* hist, uint64_t* thr, hipStream_t s);
 // Ranges of the depth sorts: live == nullptr: the fronts [vG, vG + f); else the backs [vG + f, vG + n) of views
-// with a live tile (empty otherwise); rank_hi = end rank of the range.
+// with a live tile (empty otherwise); rank_hi = end rank of the range; layout (2N + 1 entries) for the sort.
 hipError_t launch_depth_ranges(int N, int64_t G, const uint32_t* n_vis, const uint32_t* n_front,
-                               const uint32_t* live, uint32_t* lo, uint32_t* hi, uint32_t* rank_hi, hipStream_t s);
+                               const uint32_t* live, uint32_t* lo, uint32_t* hi, uint32_t* rank_hi, uint32_t* layout,
+                               hipStream_t s);
+// Per depth chunk: start[v] = scanned[v * wstride] (v < N), start[N] = *total (saturated), *max_total =
+// max(*max_total, *total), and the tile partition's layout (2N + 1 entries) over the ranges of start.
+hipError_t launch_chunk_setup(const uint32_t* scanned, int64_t wstride, int N, const unsigned long long* total,
+                              unsigned long long* max_total, uint32_t cap, uint32_t* start, uint32_t* layout,
+                              hipStream_t s);
 bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
                     const uint32_t* seg_n, uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial,
                     hipStream_t s, hipError_t* err);
@@ -161,13 +169,14 @@ hipError_t launch_bin_count(const float4* rec, const uint32_t* vis_count, const 
 hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const uint32_t* live, const BlendConst& bc,
                            const ChunkArgs& ch, const uint8_t* alive, const uint32_t* offsets, uint32_t* keys,
                            uint32_t* vals, hipStream_t s);
-hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, hipStream_t s);
-// start[v] = scanned[v * wstride] for v < N, start[N] = *total (saturated to 32 bits)
-hipError_t launch_view_starts(const uint32_t* scanned, int64_t wstride, int N, const unsigned long long* total,
-                              uint32_t* start, hipStream_t s);
-hipError_t launch_finalize_count(const unsigned long long* total, uint32_t cap, uint32_t* n_out,
-                                 unsigned long long* max_total, hipStream_t s);
-hipError_t launch_init_alive(uint8_t* alive, const uint32_t* ray_off, int64_t n, hipStream_t s);
+// live[v] = live tiles of view v; *total = 0 (for the next chunk)
+hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, unsigned long long* total,
+                            hipStream_t s);
+
+
+// alive[i] = tile i has rays (ray_off nullptr: all); zero32[0, n_zero) = 0; totals[0..1] = 0
+hipError_t launch_frame_init(uint8_t* alive, const uint32_t* ray_off, int64_t n, uint32_t* zero32, int64_t n_zero,
+                             unsigned long long* totals, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
 
 // ---- blending (blend.hip) ----

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
     const int64_t o = (int64_t)v * pc.G + i;
     if (live) {
       keys[o] = key;
-      vals[o] = (uint32_t)i;
+      if (vals) vals[o] = (uint32_t)i;
       if (vis) {
         float4* dst = rec + o * kRecF4;
         dst[0] = make_float4(r[0], r[1], r[2], r[3]);

@@ -104,7 +104,7 @@ struct dl_ctx {
   DevBuf vstart;  // start of each view's tile keys in the current chunk [N + 1]
   DevBuf dord, thr, fhist;  // depth order: fronts and sort ranges, front thresholds, key histogram
   DevBuf cams, rec, srec, k64[2], v32[2], vis, counts, bk[2], bv[2], hist, partial, tstart, views, stats, alive,
-      state, dtotal, nkeys, gacc;
+      state, dtotal, gacc;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
   double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
   // profiling: 0 off, 1 HIP events around each stage of the last frame, 2 events and work counters
@@ -337,10 +337,13 @@ int depth_key_e0(float z_near) {
   return (int)(b >> 52);
 }
 
-// Item slots per view of chunk c: the first chunk is the view's front (at most all G ranks), the others a rank
-// fraction of the visible Gaussians.
+// Item slots per view of chunk c (a bound on its ranks): the first chunk is the view's front (at most all G
+// ranks), the second runs from the front's end to a rank fraction, the others between two rank fractions of the
+// visible Gaussians.
 int64_t chunk_stride(int64_t G, int c) {
-  return c == 0 ? G + 1 : G * (kChunkBounds[c + 1] - kChunkBounds[c]) / kChunkDen + 1;
+  if (c == 0) return G + 1;
+  if (c == 1) return G * kChunkBounds[2] / kChunkDen + 1;  // starts at the front's end, which may be rank 0
+  return G * (kChunkBounds[c + 1] - kChunkBounds[c]) / kChunkDen + 1;
 }
 
 // How a frame is issued: eager frames upload their cameras and end with the overflow check; a frame being
@@ -403,7 +406,6 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   HIP_TRY(C->alive.ensure((size_t)NT));
   HIP_TRY(C->state.ensure((size_t)std::max<int64_t>(nstate, 1) * 16));
   HIP_TRY(C->dtotal.ensure(2 * 8));
-  HIP_TRY(C->nkeys.ensure(4));
   const int64_t hs = std::max(std::max(radix_hist_size(G, N), depth_ranges_hist_size(G, N)), tile_partition_hist_size(N));
   HIP_TRY(C->hist.ensure((size_t)hs * 4));
   HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, N * max_wstride)) + 2) * 4));
@@ -417,9 +419,9 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   int mk = C->begin(DL_STAGE_UPLOAD, s);
   if (mode.upload)
     HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
-  HIP_TRY(launch_fill_u64(C->dtotal.as<unsigned long long>(), 2, 0ull, s));
   if (C->prof >= 2) HIP_TRY(launch_fill_u64(C->stats.as<unsigned long long>(), kStatSlots * 3, 0ull, s));
-  HIP_TRY(launch_init_alive(C->alive.as<uint8_t>(), standard ? nullptr : L->off.as<uint32_t>(), NT, s));
+  HIP_TRY(launch_frame_init(C->alive.as<uint8_t>(), standard ? nullptr : L->off.as<uint32_t>(), NT,
+                            C->fhist.as<uint32_t>(), front_hist_size(N), C->dtotal.as<unsigned long long>(), s));
   C->end(mk, s);
 
   ProjConst pc{};
@@ -440,7 +442,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   pc.key_e0 = depth_key_e0(o.z_near);
   mk = C->begin(DL_STAGE_PROJECT, s);
   HIP_TRY(launch_project(S->soa.as<float>(), C->cams.as<double>(), pc, C->rec.as<float4>(), C->k64[0].as<uint64_t>(),
-                         C->v32[0].as<uint32_t>(), nullptr, s));
+                         nullptr, nullptr, s));
   C->end(mk, s);
   hipError_t e;
   // Depth order.  The first chunk is each view's front (the nearest ~1/16 of its visible Gaussians, chosen on a
@@ -456,12 +458,11 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   uint32_t* dlayout = rank_hi + N;  // 2N + 1
   uint64_t* thr = C->thr.as<uint64_t>();
   HIP_TRY(launch_front_select(C->k64[0].as<uint64_t>(), G, N, kDepthKeyBits, kDepthCulled, kChunkBounds[1], kChunkDen,
-                              C->fhist.as<uint32_t>(), thr, vis, front, s));
-  radix_split_u64(C->k64[0].as<uint64_t>(), C->v32[0].as<uint32_t>(), C->k64[1].as<uint64_t>(),
-                  C->v32[1].as<uint32_t>(), G, N, thr, kDepthCulled, C->hist.as<uint32_t>(),
-                  C->partial.as<uint32_t>(), s, &e);
+                              C->fhist.as<uint32_t>(), thr, s));
+  radix_split_u64(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N, thr, kDepthCulled,
+                  vis, front, C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s, &e);
   if (e != hipSuccess) return fail(DL_EHIP, std::string("depth split: ") + hipGetErrorString(e));
-  HIP_TRY(launch_depth_ranges(N, G, vis, front, nullptr, rlo, rhi, rank_hi, s));
+  HIP_TRY(launch_depth_ranges(N, G, vis, front, nullptr, rlo, rhi, rank_hi, dlayout, s));
   const bool fl = depth_ranges_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), C->k64[0].as<uint64_t>(),
                                     C->v32[0].as<uint32_t>(), G, N, rlo, rhi, kDepthKeyBits, C->hist.as<uint32_t>(),
                                     C->partial.as<uint32_t>(), dlayout, s, &e);
@@ -491,7 +492,8 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   for (int c = 0; c < kChunks; ++c) {
     C->chunk = c;
     ChunkArgs ch;
-    ch.num_lo = kChunkBounds[c];
+    // the second chunk starts where the front ended, whatever fraction the front took
+    ch.num_lo = c == 1 ? 0 : kChunkBounds[c];
     ch.num_hi = kChunkBounds[c + 1];
     ch.den = kChunkDen;
     ch.front = front;
@@ -503,20 +505,19 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     // views with no live tile left produce no keys in this chunk (the first chunk has every tile live)
     const uint32_t* live = c > 0 ? C->live.as<uint32_t>() : nullptr;
     mk = C->begin(DL_STAGE_BIN_COUNT, s);
-    HIP_TRY(launch_fill_u64(total, 1, 0ull, s));
     HIP_TRY(launch_bin_count(C->srec.as<float4>(), C->vis.as<uint32_t>(), live, bc, ch, C->alive.as<uint8_t>(),
                              C->counts.as<uint32_t>(), total, s));
     C->end(mk, s);
     mk = C->begin(DL_STAGE_SCAN, s);
     HIP_TRY(exclusive_scan_u32(C->counts.as<uint32_t>(), C->counts.as<uint32_t>(), ncount, C->partial.as<uint32_t>(), s));
-    HIP_TRY(launch_finalize_count(total, cap, C->nkeys.as<uint32_t>(), total + 1, s));
     C->end(mk, s);
     mk = C->begin(DL_STAGE_BIN_EMIT, s);
     HIP_TRY(launch_bin_emit(C->srec.as<float4>(), C->vis.as<uint32_t>(), live, bc, ch, C->alive.as<uint8_t>(),
                             C->counts.as<uint32_t>(), C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), s));
     C->end(mk, s);
     mk = C->begin(DL_STAGE_TILE_SORT, s);
-    HIP_TRY(launch_view_starts(C->counts.as<uint32_t>(), ch.wstride, N, total, C->vstart.as<uint32_t>(), s));
+    HIP_TRY(launch_chunk_setup(C->counts.as<uint32_t>(), ch.wstride, N, total, total + 1, cap, C->vstart.as<uint32_t>(),
+                               C->vstart.as<uint32_t>() + (N + 1), s));
     const uint32_t* svals = tile_partition(C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), C->bk[1].as<uint32_t>(),
                                            C->bv[1].as<uint32_t>(), N, C->vstart.as<uint32_t>(), cap, tl.T,
                                            C->hist.as<uint32_t>(), C->partial.as<uint32_t>(),
@@ -538,12 +539,13 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                                    L->ent.as<uint32_t>(), L->max_rays, bc, bk, C->alive.as<uint8_t>(),
                                    C->state.as<float4>(), out, s));
     }
-    if (c + 1 < kChunks) HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), s));
+    if (c + 1 < kChunks)
+      HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), total, s));
     C->end(mk, s);
     if (c == 0 && kChunks > 1) {
       // the backs of the views that still have a live tile
       mk = C->begin(DL_STAGE_DEPTH_SORT, s);
-      HIP_TRY(launch_depth_ranges(N, G, vis, front, C->live.as<uint32_t>(), rlo, rhi, rank_hi, s));
+      HIP_TRY(launch_depth_ranges(N, G, vis, front, C->live.as<uint32_t>(), rlo, rhi, rank_hi, dlayout, s));
       const bool fl2 = depth_ranges_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), C->k64[0].as<uint64_t>(),
                                          C->v32[0].as<uint32_t>(), G, N, rlo, rhi, kDepthKeyBits,
                                          C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), dlayout, s, &e);
@@ -847,7 +849,7 @@ namespace {
 size_t ctx_bytes(const dl_ctx* C) {
   const DevBuf* b[] = {&C->cams, &C->rec, &C->srec, &C->k64[0], &C->k64[1], &C->v32[0], &C->v32[1], &C->vis,
                        &C->counts, &C->bk[0], &C->bk[1], &C->bv[0], &C->bv[1], &C->hist, &C->partial, &C->tstart,
-                       &C->views, &C->stats, &C->alive, &C->state, &C->dtotal, &C->nkeys, &C->gacc, &C->live, &C->vstart, &C->dord, &C->thr, &C->fhist};
+                       &C->views, &C->stats, &C->alive, &C->state, &C->dtotal, &C->gacc, &C->live, &C->vstart, &C->dord, &C->thr, &C->fhist};
   size_t t = 0;
   for (const DevBuf* x : b) t += x->cap;
   return t;

@@ -53,11 +53,11 @@ __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* total) {
   return before + inc - x;
 }
 
-// The scans take a static length n, or a device length *n_dev (<= n; grids are sized for n).
+// The scans take a static length n, or a device length n_mul * *n_dev (<= n; grids are sized for n).
 __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
-                                                                 const uint32_t* __restrict__ n_dev,
+                                                                 const uint32_t* __restrict__ n_dev, int n_mul,
                                                                  uint32_t* __restrict__ partial) {
-  if (n_dev) n = min(n, (int64_t)*n_dev);
+  if (n_dev) n = min(n, (int64_t)n_mul * *n_dev);
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
   uint32_t s = 0;
 #pragma unroll
@@ -71,10 +71,10 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* _
 // Second half of the scan: each tile adds the totals of the tiles before it (at most a few hundred, summed by
 // the workgroup) and scans its own items; the last tile writes the grand total to *grand.
 __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* in, uint32_t* out, int64_t n,
-                                                               const uint32_t* __restrict__ n_dev,
+                                                               const uint32_t* __restrict__ n_dev, int n_mul,
                                                                const uint32_t* __restrict__ partial_in,
                                                                uint32_t* __restrict__ grand) {
-  if (n_dev) n = min(n, (int64_t)*n_dev);
+  if (n_dev) n = min(n, (int64_t)n_mul * *n_dev);
   const int64_t np = (n + kScanTile - 1) / kScanTile;
   if ((int64_t)blockIdx.x >= np) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *grand = 0;  // nothing to scan
@@ -126,18 +126,20 @@ struct SortArgs {
   K drop_key;
   const K* split;         // one-bit digit: key >= split[seg] (instead of a bit field of the key)
   // device ranges: segment s is [seg_lo[s], seg_hi[s]) (clamped to cap) of one array, sorted in place; the
-  // histogram is laid out [segment][digit < ndig][block < bpse[s]] from hoff[s], so empty segments take no
-  // entries and no blocks.  nullptr: segment s is [s * seg_len, s * seg_len + live length).
+  // histogram is laid out [segment][digit < ndig][block < bpse[s]] from ndig * pb[s] (pb = exclusive prefix of
+  // bpse), so empty segments take no entries and no blocks.  nullptr: segment s is
+  // [s * seg_len, s * seg_len + live length).
   const uint32_t* seg_lo;
   const uint32_t* seg_hi;
-  const uint32_t* hoff;
+  const uint32_t* pb;
   const uint32_t* bpse;
   int ndig;
+  int iota;  // the values are the items' positions in their segment (vin is not read)
 };
 
 template <typename K>
 __device__ inline int64_t hist_at(const SortArgs<K>& a, int seg, int d, int bis, int bps, int radix) {
-  return a.seg_lo ? (int64_t)a.hoff[seg] + (int64_t)d * bps + bis : ((int64_t)seg * radix + d) * a.bps + bis;
+  return a.seg_lo ? (int64_t)a.ndig * a.pb[seg] + (int64_t)d * bps + bis : ((int64_t)seg * radix + d) * a.bps + bis;
 }
 
 template <typename K>
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
   K* kout = a.kout ? a.kout + base : nullptr;
   uint32_t* vout = a.vout + base;
   // the scan runs over all segments; subtract the segment's first offset so positions are segment-relative
-  const uint32_t seg0 = a.hist[a.seg_lo ? (int64_t)a.hoff[seg] : (int64_t)seg * radix * a.bps];
+  const uint32_t seg0 = a.hist[a.seg_lo ? (int64_t)a.ndig * a.pb[seg] : (int64_t)seg * radix * a.bps];
   for (int d = threadIdx.x; d < radix; d += kThreads)
     run[d] = d < ndig ? a.hist[hist_at(a, seg, d, bis, bps, radix)] - seg0 : 0u;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
       const int li = w * (kRows * 64) + r * 64 + lane;
       bool valid = li < tn;
       key[r] = valid ? kin[t0 + li] : (K)0;
-      val[r] = valid ? vin[t0 + li] : 0u;
+      val[r] = valid ? (a.iota ? (uint32_t)(t0 + li) : vin[t0 + li]) : 0u;
       if (a.drop && key[r] == a.drop_key) valid = false;
       const uint32_t d = digit_of(a, seg, key[r], dmask);
       dig[r] = d;
@@ -318,7 +320,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
 // start plus the scanned histogram at [v][t][block 0] less the segment's first entry (an empty segment has no
 // entries: its lists start at its range); start[n_seg * n_dig] = end of the last segment.
 __global__ __launch_bounds__(kThreads) void hist_starts_kernel(const uint32_t* __restrict__ hist,
-                                                                 const uint32_t* __restrict__ hoff,
+                                                                 const uint32_t* __restrict__ pb,
                                                                  const uint32_t* __restrict__ bpse, int n_dig,
                                                                  int n_seg, const uint32_t* __restrict__ seg_lo,
                                                                  const uint32_t* __restrict__ seg_hi, uint32_t cap,
@@ -334,17 +336,15 @@ __global__ __launch_bounds__(kThreads) void hist_starts_kernel(const uint32_t* _
   const int t = (int)(i - (int64_t)v * n_dig);
   const uint32_t b = bpse[v];
   const uint32_t lo = min(seg_lo[v], cap);
-  start[i] = b ? lo + (hist[(int64_t)hoff[v] + (int64_t)t * b] - hist[hoff[v]]) : lo;
+  const int64_t h0 = (int64_t)n_dig * pb[v];
+  start[i] = b ? lo + (hist[h0 + (int64_t)t * b] - hist[h0]) : lo;
 }
 
-// Histogram layout over device ranges: blocks per segment = its tiles of kTile items (at most bps_max, none for
-// an empty segment), offsets = exclusive scan of n_dig x blocks; hoff[n_seg] = entries in use.  One workgroup
-// per kThreads segments is not needed: n_seg <= kThreads.
-__global__ __launch_bounds__(kThreads) void part_layout_kernel(const uint32_t* __restrict__ seg_lo,
-                                                                 const uint32_t* __restrict__ seg_hi, uint32_t cap,
-                                                                 int n_seg, int n_dig, int bps_max,
-                                                                 uint32_t* __restrict__ bpse,
-                                                                 uint32_t* __restrict__ hoff) {
+// Histogram layout over device ranges (one workgroup, n_seg <= kThreads): blocks per segment = its tiles of kTile
+// items (at most bps_max, none for an empty segment) and their exclusive prefix pb (pb[n_seg] = total blocks).
+__device__ inline void range_layout(const uint32_t* __restrict__ seg_lo, const uint32_t* __restrict__ seg_hi,
+                                    uint32_t cap, int n_seg, int bps_max, uint32_t* __restrict__ bpse,
+                                    uint32_t* __restrict__ pb) {
   const int v = threadIdx.x;
   uint32_t b = 0;
   if (v < n_seg) {
@@ -354,9 +354,16 @@ __global__ __launch_bounds__(kThreads) void part_layout_kernel(const uint32_t* _
     bpse[v] = b;
   }
   uint32_t total;
-  const uint32_t off = block_excl_scan(b * (uint32_t)n_dig, &total);
-  if (v < n_seg) hoff[v] = off;
-  if (v == 0) hoff[n_seg] = total;
+  const uint32_t off = block_excl_scan(b, &total);
+  if (v < n_seg) pb[v] = off;
+  if (v == 0) pb[n_seg] = total;
+}
+
+__global__ __launch_bounds__(kThreads) void part_layout_kernel(const uint32_t* __restrict__ seg_lo,
+                                                                 const uint32_t* __restrict__ seg_hi, uint32_t cap,
+                                                                 int n_seg, int bps_max, uint32_t* __restrict__ bpse,
+                                                                 uint32_t* __restrict__ pb) {
+  range_layout(seg_lo, seg_hi, cap, n_seg, bps_max, bpse, pb);
 }
 
 // List starts after a multi-pass partition: first position in segment v whose key is >= t.
@@ -387,9 +394,31 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
+// Per depth chunk, one workgroup (N <= kThreads): the start of each view's key range (the scanned wavefront counts
+// at the view's first slot; the end of the last view is the chunk's total), the largest total seen (overflow
+// check), and the tile partition's histogram layout over these ranges.
+__global__ __launch_bounds__(kThreads) void chunk_setup_kernel(const uint32_t* __restrict__ scanned, int64_t wstride,
+                                                                 int N, const unsigned long long* __restrict__ total,
+                                                                 unsigned long long* __restrict__ max_total,
+                                                                 uint32_t cap, int bps_max,
+                                                                 uint32_t* __restrict__ start,
+                                                                 uint32_t* __restrict__ bpse,
+                                                                 uint32_t* __restrict__ pb) {
+  const int v = threadIdx.x;
+  const unsigned long long t = *total;
+  if (v < N) start[v] = scanned[(int64_t)v * wstride];
+  if (v == 0) {
+    start[N] = (uint32_t)(t < 0xffffffffull ? t : 0xffffffffull);
+    if (t > *max_total) *max_total = t;
+  }
+  __syncthreads();
+  range_layout(start, start + 1, cap, N, bps_max, bpse, pb);
+}
+
 // ---- the front of each view's depth order ----
-// Visible keys per view binned on their top kFrontBits bits; one workgroup's counts are added to the view's
-// global histogram bin by bin (only the bins it saw).
+// A sample of each view's visible keys (runs of 64 items, one in every 16) binned on their top kFrontBits bits;
+// one workgroup's counts are added to the view's global histogram bin by bin (only the bins it saw).  The
+// threshold only steers how much goes into the first chunk; the exact front sizes come from the split pass.
 constexpr int kFrontBits = 12;
 constexpr int kFrontBins = 1 << kFrontBits;
 
@@ -400,24 +429,25 @@ __global__ __launch_bounds__(kThreads) void front_hist_kernel(const uint64_t* __
   for (int b = threadIdx.x; b < kFrontBins; b += kThreads) h[b] = 0;
   __syncthreads();
   const int v = blockIdx.y;
-  const int64_t per = (G + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(G, lo + per);
   const uint64_t* k = keys + (int64_t)v * G;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-    const uint64_t key = k[i];
-    if (key != culled) atomicAdd(&h[(uint32_t)(key >> (key_bits - kFrontBits))], 1u);
+  // sampled runs: items [1024 j, 1024 j + 64) for j = blockIdx.x, blockIdx.x + gridDim.x, ...
+  for (int64_t j = blockIdx.x; j * 1024 < G; j += gridDim.x) {
+    const int64_t i = j * 1024 + threadIdx.x;
+    if (threadIdx.x < 64 && i < G) {
+      const uint64_t key = k[i];
+      if (key != culled) atomicAdd(&h[(uint32_t)(key >> (key_bits - kFrontBits))], 1u);
+    }
   }
   __syncthreads();
   for (int b = threadIdx.x; b < kFrontBins; b += kThreads)
     if (h[b]) atomicAdd(&hist[(int64_t)v * kFrontBins + b], h[b]);
 }
 
-// Per view (one workgroup each): visible count n, and the smallest bin b whose cumulative count reaches
-// ceil(n num / den); the front is every key below thr = (b + 1) << (key_bits - kFrontBits), f its size.
+// Per view (one workgroup each): the smallest bin b whose cumulative sample count reaches ceil(n_s num / den)
+// of the n_s sampled keys; the front is every key below thr = (b + 1) << (key_bits - kFrontBits) (0: none).
 __global__ __launch_bounds__(kThreads) void front_select_kernel(const uint32_t* __restrict__ hist, int key_bits,
-                                                                  int64_t num, int64_t den, uint64_t* __restrict__ thr,
-                                                                  uint32_t* __restrict__ n_vis,
-                                                                  uint32_t* __restrict__ n_front) {
+                                                                  int64_t num, int64_t den,
+                                                                  uint64_t* __restrict__ thr) {
   constexpr int kPer = kFrontBins / kThreads;
   const int v = blockIdx.x;
   const uint32_t* h = hist + (int64_t)v * kFrontBins;
@@ -431,44 +461,57 @@ __global__ __launch_bounds__(kThreads) void front_select_kernel(const uint32_t* 
   uint32_t n;
   uint32_t run = block_excl_scan(mine, &n);
   const uint32_t target = (uint32_t)(((int64_t)n * num + den - 1) / den);
-  if (threadIdx.x == 0) {
-    n_vis[v] = n;
-    if (target == 0) {
-      thr[v] = 0;
-      n_front[v] = 0;
-    }
+  if (target == 0) {
+    if (threadIdx.x == 0) thr[v] = 0;
+    return;
   }
-  if (target == 0) return;
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
     const uint32_t before = run;
     run += c[i];
-    if (before < target && run >= target) {
-      thr[v] = (uint64_t)(threadIdx.x * kPer + i + 1) << (key_bits - kFrontBits);
-      n_front[v] = run;
-    }
+    if (before < target && run >= target) thr[v] = (uint64_t)(threadIdx.x * kPer + i + 1) << (key_bits - kFrontBits);
   }
 }
 
-// Device ranges of the depth sorts: front [v G, v G + f_v); back [v G + f_v, v G + n_v) for views with a live
-// tile, empty otherwise.  Also the back's rank bounds for the record gather.
-__global__ void depth_ranges_kernel(int N, int64_t G, const uint32_t* __restrict__ n_vis,
-                                    const uint32_t* __restrict__ n_front, const uint32_t* __restrict__ live,
-                                    uint32_t* __restrict__ lo, uint32_t* __restrict__ hi,
-                                    uint32_t* __restrict__ rank_hi) {
+// Exact sizes after the split pass, from its scanned histogram ([segment][digit 0, 1][block], exclusive) and the
+// scan's grand total: n_vis = kept items, n_front = items of digit 0.
+__global__ void split_counts_kernel(const uint32_t* __restrict__ hist, const uint32_t* __restrict__ grand, int n_seg,
+                                    int bps, uint32_t* __restrict__ n_vis, uint32_t* __restrict__ n_front) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= N) return;
-  const uint32_t base = (uint32_t)((int64_t)v * G);
-  if (!live) {
-    lo[v] = base;
-    hi[v] = base + n_front[v];
-    rank_hi[v] = n_front[v];
-  } else {
-    const uint32_t e = live[v] ? n_vis[v] : n_front[v];
-    lo[v] = base + n_front[v];
-    hi[v] = base + e;
-    rank_hi[v] = e;
+  if (v >= n_seg) return;
+  const uint32_t a = hist[(int64_t)v * 2 * bps];
+  const uint32_t b = hist[((int64_t)v * 2 + 1) * bps];
+  const uint32_t c = v + 1 < n_seg ? hist[(int64_t)(v + 1) * 2 * bps] : *grand;
+  n_vis[v] = c - a;
+  n_front[v] = b - a;
+}
+
+// Device ranges of the depth sorts (one workgroup, N <= kThreads): front [v G, v G + f_v); back
+// [v G + f_v, v G + n_v) for views with a live tile, empty otherwise; rank_hi = end rank of the range; and the
+// sort's histogram layout over these ranges.
+__global__ __launch_bounds__(kThreads) void depth_ranges_kernel(int N, int64_t G, const uint32_t* __restrict__ n_vis,
+                                                                  const uint32_t* __restrict__ n_front,
+                                                                  const uint32_t* __restrict__ live,
+                                                                  uint32_t* __restrict__ lo, uint32_t* __restrict__ hi,
+                                                                  uint32_t* __restrict__ rank_hi, int bps_max,
+                                                                  uint32_t* __restrict__ bpse,
+                                                                  uint32_t* __restrict__ pb) {
+  const int v = threadIdx.x;
+  if (v < N) {
+    const uint32_t base = (uint32_t)((int64_t)v * G);
+    if (!live) {
+      lo[v] = base;
+      hi[v] = base + n_front[v];
+      rank_hi[v] = n_front[v];
+    } else {
+      const uint32_t e = live[v] ? n_vis[v] : n_front[v];
+      lo[v] = base + n_front[v];
+      hi[v] = base + e;
+      rank_hi[v] = e;
+    }
   }
+  __syncthreads();
+  range_layout(lo, hi, 0xffffffffu, N, bps_max, bpse, pb);
 }
 
 __global__ __launch_bounds__(kThreads) void lower_bounds_kernel(const uint32_t* __restrict__ keys,
@@ -506,13 +549,14 @@ SortArgs<K> base_args(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout
   return a;
 }
 
+// One pass: histogram, scan (of hsize entries, or of n_mul * *hsize_dev on the device), scatter.
 template <typename K, int RB>
 hipError_t launch_pass(const SortArgs<K>& a, int64_t nblocks, int64_t hsize, uint32_t* partial,
-                       const uint32_t* hsize_dev, hipStream_t s) {
+                       const uint32_t* hsize_dev, int n_mul, hipStream_t s) {
   hipLaunchKernelGGL((radix_hist_kernel<K, RB>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = exclusive_scan_u32(a.hist, a.hist, hsize, partial, s, hsize_dev)) != hipSuccess) return e;
+  if ((e = exclusive_scan_u32(a.hist, a.hist, hsize, partial, s, hsize_dev, n_mul)) != hipSuccess) return e;
   hipLaunchKernelGGL((radix_scatter_kernel<K, RB>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -540,7 +584,7 @@ bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, 
     a.shift = shift;
     a.bits = bits;
     a.ndig = 1 << bits;
-    if ((*err = launch_pass<K, kMaxBits>(a, nblocks, (int64_t)n_seg * (1 << bits) * bps, partial, nullptr, s)))
+    if ((*err = launch_pass<K, kMaxBits>(a, nblocks, (int64_t)n_seg * (1 << bits) * bps, partial, nullptr, 1, s)))
       return flipped;
     flipped = !flipped;
     shift += bits;
@@ -550,39 +594,41 @@ bool radix_sort_impl(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int64_t seg_len, 
 
 int part_blocks_per_seg(int n_seg) { return std::max(1, (2048 + n_seg - 1) / n_seg); }
 
-// LSD passes over device ranges [lo[s], hi[s]) (clamped to cap) with the adaptive histogram layout.  n_dig_last
-// > 0 makes a single pass use only that many digits (a partition whose keys are below it); kout of the last
-// pass may be dropped.  Returns whether the result is in (k1, v1).
+// LSD passes over device ranges [lo[s], hi[s]) (clamped to cap) with the adaptive histogram layout (bpse, pb),
+// computed here unless the caller has (layout_ready).  n_dig_one_pass > 0 makes a single pass use only that many
+// digits (a partition whose keys are below it); the keys of the last pass may be dropped.  Returns whether the
+// result is in (k1, v1).
 template <typename K, int RB>
 bool ranges_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int n_seg, const uint32_t* lo, const uint32_t* hi,
                  uint32_t cap, int bps, int bits_total, int n_dig_one_pass, bool keep_last_keys, uint32_t* hist,
-                 uint32_t* partial, uint32_t* layout, hipStream_t s, hipError_t* err) {
+                 uint32_t* partial, uint32_t* bpse, uint32_t* pb, bool layout_ready, hipStream_t s, hipError_t* err) {
   *err = hipSuccess;
-  uint32_t* bpse = layout;          // [n_seg]
-  uint32_t* hoff = layout + n_seg;  // [n_seg + 1]
+  if (!layout_ready) {
+    hipLaunchKernelGGL(part_layout_kernel, dim3(1), dim3(kThreads), 0, s, lo, hi, cap, n_seg, bps, bpse, pb);
+    if ((*err = hipGetLastError()) != hipSuccess) return false;
+  }
   const int64_t nblocks = (int64_t)bps * n_seg;
   const int passes = (bits_total + RB - 1) / RB;
   bool flipped = false;
   int shift = 0;
   for (int p = 0; p < passes; ++p) {
-    const int pb = (bits_total - shift + (passes - p) - 1) / (passes - p);
+    const int pbits = (bits_total - shift + (passes - p) - 1) / (passes - p);
     const bool last = p == passes - 1;
     SortArgs<K> a = base_args<K>(flipped ? k1 : k0, flipped ? v1 : v0,
                                  (last && !keep_last_keys) ? nullptr : (flipped ? k0 : k1), flipped ? v0 : v1, hist);
     a.cap = cap;
     a.bps = bps;
     a.shift = shift;
-    a.bits = pb;
+    a.bits = pbits;
     a.seg_lo = lo;
     a.seg_hi = hi;
-    a.hoff = hoff;
+    a.pb = pb;
     a.bpse = bpse;
-    a.ndig = (passes == 1 && n_dig_one_pass > 0) ? n_dig_one_pass : (1 << pb);
-    hipLaunchKernelGGL(part_layout_kernel, dim3(1), dim3(kThreads), 0, s, lo, hi, cap, n_seg, a.ndig, bps, bpse, hoff);
-    if ((*err = launch_pass<K, RB>(a, nblocks, (int64_t)n_seg * a.ndig * bps, partial, hoff + n_seg, s)))
+    a.ndig = (passes == 1 && n_dig_one_pass > 0) ? n_dig_one_pass : (1 << pbits);
+    if ((*err = launch_pass<K, RB>(a, nblocks, (int64_t)n_seg * a.ndig * bps, partial, pb + n_seg, a.ndig, s)))
       return flipped;
     flipped = !flipped;
-    shift += pb;
+    shift += pbits;
   }
   return flipped;
 }
@@ -592,11 +638,11 @@ bool ranges_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int n_seg, const uint
 int64_t scan_partial_count(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, hipStream_t s,
-                              const uint32_t* n_dev) {
+                              const uint32_t* n_dev, int n_mul) {
   if (n <= 0) return hipSuccess;
   const int64_t np = scan_partial_count(n);
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, n, n_dev, partial);
-  hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, out, n, n_dev, partial,
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, n, n_dev, n_mul, partial);
+  hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, out, n, n_dev, n_mul, partial,
                      partial + np);
   return hipGetLastError();
 }
@@ -612,11 +658,11 @@ bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int6
                                    err);
 }
 
-bool radix_split_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
-                     const uint64_t* thr, uint64_t drop_key, uint32_t* hist, uint32_t* partial, hipStream_t s,
-                     hipError_t* err) {
+bool radix_split_u64(uint64_t* k0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg, const uint64_t* thr,
+                     uint64_t drop_key, uint32_t* n_vis, uint32_t* n_front, uint32_t* hist, uint32_t* partial,
+                     hipStream_t s, hipError_t* err) {
   const int bps = blocks_per_seg(seg_len, n_seg);
-  SortArgs<uint64_t> a = base_args<uint64_t>(k0, v0, k1, v1, hist);
+  SortArgs<uint64_t> a = base_args<uint64_t>(k0, nullptr, k1, v1, hist);
   a.seg_len = seg_len;
   a.bps = bps;
   a.bits = 1;
@@ -624,7 +670,12 @@ bool radix_split_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int
   a.split = thr;
   a.drop = 1;
   a.drop_key = drop_key;
-  *err = launch_pass<uint64_t, kMaxBits>(a, (int64_t)bps * n_seg, (int64_t)n_seg * 2 * bps, partial, nullptr, s);
+  a.iota = 1;  // the values are the Gaussian indices: positions in the view's segment
+  const int64_t hsize = (int64_t)n_seg * 2 * bps;
+  if ((*err = launch_pass<uint64_t, kMaxBits>(a, (int64_t)bps * n_seg, hsize, partial, nullptr, 1, s))) return true;
+  hipLaunchKernelGGL(split_counts_kernel, dim3((unsigned)((n_seg + 63) / 64)), dim3(64), 0, s, hist,
+                     partial + scan_partial_count(hsize), n_seg, bps, n_vis, n_front);
+  *err = hipGetLastError();
   return true;
 }
 
@@ -639,30 +690,31 @@ bool depth_ranges_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, i
     *err = hipErrorInvalidValue;
     return false;
   }
-  // the keys of the last pass are not needed: only the values (Gaussian indices) in depth order are
+  // the layout comes with the ranges; the keys of the last pass are not needed, only the values (Gaussian
+  // indices) in depth order
   return ranges_sort<uint64_t, kMaxBits>(k0, v0, k1, v1, n_seg, lo, hi, 0xffffffffu, blocks_per_seg(seg_len, n_seg),
-                                         key_bits, 0, false, hist, partial, layout, s, err);
+                                         key_bits, 0, false, hist, partial, layout, layout + n_seg, true, s, err);
 }
 
+int depth_sort_blocks(int64_t seg_len, int n_seg) { return blocks_per_seg(seg_len, n_seg); }
+
 hipError_t launch_front_select(const uint64_t* keys, int64_t G, int N, int key_bits, uint64_t culled, int64_t num,
-                               int64_t den, uint32_t* hist, uint64_t* thr, uint32_t* n_vis, uint32_t* n_front,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)(((int64_t)N * kFrontBins + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, s, hist, (int64_t)N * kFrontBins, 0u);
-  const unsigned per_view = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (G + 8191) / 8192));
+                               int64_t den, uint32_t* hist, uint64_t* thr, hipStream_t s) {
+  const unsigned per_view = (unsigned)std::max<int64_t>(1, std::min<int64_t>(32, (G + 16383) / 16384));
   hipLaunchKernelGGL(front_hist_kernel, dim3(per_view, (unsigned)N), dim3(kThreads), 0, s, keys, G, key_bits, culled,
                      hist);
-  hipLaunchKernelGGL(front_select_kernel, dim3((unsigned)N), dim3(kThreads), 0, s, hist, key_bits, num, den, thr,
-                     n_vis, n_front);
+  hipLaunchKernelGGL(front_select_kernel, dim3((unsigned)N), dim3(kThreads), 0, s, hist, key_bits, num, den, thr);
   return hipGetLastError();
 }
 
 int64_t front_hist_size(int N) { return (int64_t)N * kFrontBins; }
 
 hipError_t launch_depth_ranges(int N, int64_t G, const uint32_t* n_vis, const uint32_t* n_front,
-                               const uint32_t* live, uint32_t* lo, uint32_t* hi, uint32_t* rank_hi, hipStream_t s) {
-  hipLaunchKernelGGL(depth_ranges_kernel, dim3((unsigned)((N + 63) / 64)), dim3(64), 0, s, N, G, n_vis, n_front, live,
-                     lo, hi, rank_hi);
+                               const uint32_t* live, uint32_t* lo, uint32_t* hi, uint32_t* rank_hi, uint32_t* layout,
+                               hipStream_t s) {
+  if (N > kThreads) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(depth_ranges_kernel, dim3(1), dim3(kThreads), 0, s, N, G, n_vis, n_front, live, lo, hi, rank_hi,
+                     blocks_per_seg(G, N), layout, layout + N);
   return hipGetLastError();
 }
 
@@ -674,6 +726,8 @@ bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int6
 }
 
 int64_t tile_partition_hist_size(int n_seg) { return (int64_t)part_blocks_per_seg(n_seg) * n_seg * kMaxRadix; }
+
+int tile_partition_blocks(int n_seg) { return part_blocks_per_seg(n_seg); }
 
 const uint32_t* tile_partition(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int n_seg,
                                const uint32_t* seg_start, uint32_t cap, int n_dig, uint32_t* hist, uint32_t* partial,
@@ -688,25 +742,36 @@ const uint32_t* tile_partition(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_
   const int bps = part_blocks_per_seg(n_seg);
   const uint32_t* lo = seg_start;
   const uint32_t* hi = seg_start + 1;  // consecutive ranges of one array
+  uint32_t* bpse = layout;
+  uint32_t* pb = layout + n_seg;
   const int passes = (bits + kPartBits - 1) / kPartBits;
   bool fl;
   if (bits > kMaxBits)
     fl = ranges_sort<uint32_t, kPartBits>(k0, v0, k1, v1, n_seg, lo, hi, cap, bps, bits, n_dig, passes > 1, hist,
-                                          partial, layout, s, err);
+                                          partial, bpse, pb, true, s, err);
   else
     fl = ranges_sort<uint32_t, kMaxBits>(k0, v0, k1, v1, n_seg, lo, hi, cap, bps, bits, n_dig, false, hist, partial,
-                                         layout, s, err);
+                                         bpse, pb, true, s, err);
   if (*err != hipSuccess) return nullptr;
   const int64_t ns = (int64_t)n_seg * n_dig + 1;
   const unsigned g = (unsigned)((ns + kThreads - 1) / kThreads);
   if (passes == 1)
-    hipLaunchKernelGGL(hist_starts_kernel, dim3(g), dim3(kThreads), 0, s, hist, layout + n_seg, layout, n_dig, n_seg,
-                       lo, hi, cap, start);
+    hipLaunchKernelGGL(hist_starts_kernel, dim3(g), dim3(kThreads), 0, s, hist, pb, bpse, n_dig, n_seg, lo, hi, cap,
+                       start);
   else
     hipLaunchKernelGGL(segment_bounds_kernel, dim3(g), dim3(kThreads), 0, s, fl ? k1 : k0, n_dig, n_seg, lo, hi, cap,
                        start);
   if ((*err = hipGetLastError()) != hipSuccess) return nullptr;
   return fl ? v1 : v0;
+}
+
+hipError_t launch_chunk_setup(const uint32_t* scanned, int64_t wstride, int N, const unsigned long long* total,
+                              unsigned long long* max_total, uint32_t cap, uint32_t* start, uint32_t* layout,
+                              hipStream_t s) {
+  if (N > kThreads) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(chunk_setup_kernel, dim3(1), dim3(kThreads), 0, s, scanned, wstride, N, total, max_total, cap,
+                     part_blocks_per_seg(N), start, layout, layout + N);
+  return hipGetLastError();
 }
 
 hipError_t launch_lower_bounds(const uint32_t* keys, const uint32_t* n_dev, uint32_t cap, int64_t n_static,
