@@ -225,8 +225,13 @@ hipError_t launch_rpt(int rpt, unsigned nblocks, const float4* rec, const uint32
   switch (rpt) {
     DL_BLEND_CASE(1)
     DL_BLEND_CASE(2)
+    DL_BLEND_CASE(3)
     DL_BLEND_CASE(4)
+    DL_BLEND_CASE(5)
+    DL_BLEND_CASE(6)
+    DL_BLEND_CASE(7)
     DL_BLEND_CASE(8)
+    DL_BLEND_CASE(12)
     DL_BLEND_CASE(16)
     default:
       return hipErrorInvalidValue;
@@ -235,10 +240,11 @@ hipError_t launch_rpt(int rpt, unsigned nblocks, const float4* rec, const uint32
   return hipGetLastError();
 }
 
+// Rays per lane: the fewest that hold the largest (view, tile) ray list (registers, and so occupancy, grow with
+// it; slots that a whole wavefront leaves empty cost nothing).
 int rpt_for(int max_rays) {
-  int r = 1;
-  while (r * kThreads < max_rays) r *= 2;
-  return r;
+  const int r = (max_rays + kThreads - 1) / kThreads;
+  return r <= 8 ? std::max(r, 1) : (r <= 12 ? 12 : 16);
 }
 
 }  // namespace

@@ -244,10 +244,13 @@ int check_opts(const dl_render_opts* o, dl_render_opts& out) {
 void auto_tile_directl(const dl_display_desc& d, int& tw, int& th) {
   // A view owns about 3/N of a tile's pixels.  Tiles of about 900 owned rays (3-4 per lane of a 256-lane
   // workgroup) amortise each LDS-staged record over many rays and keep the tile-key count low, while the
-  // extra per-ray evaluations of a larger tile stay small next to the splat sizes.
+  // extra per-ray evaluations of a larger tile stay small next to the splat sizes.  On large panels the tiles
+  // grow until a view has at most 1024 of them, so that the tile partition takes one radix pass.
   const double side = std::sqrt(300.0 * d.n_views);
   int s = (int)std::floor(side / 8.0) * 8;
   s = std::max(8, std::min(s, 256));
+  auto tiles = [&](int t) { return (int64_t)((d.width + t - 1) / t) * ((d.height + t - 1) / t); };
+  while (tiles(s) > 1024 && s < 256) s += 8;
   tw = th = s;
 }
 
