@@ -151,7 +151,8 @@ def run_gpu(args):
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload],
                    "gaussians": scene.n, "width": W, "height": H, "views": disp.n_views,
-                   "tile": [stages[0]["tile_w"], stages[0]["tile_h"]], "rays": D.num_rays()},
+                   "tile": [stages[0]["tile_w"], stages[0]["tile_h"]], "rays": D.num_rays(),
+                   "blend_lanes": stages[0]["lanes"], "rays_per_lane": stages[0]["rays_per_lane"]},
         "gsubpixel_per_s": round(fps * 3 * W * H / 1e9, 4),
         "p50_ms": round(percentile(frame_ms, 50), 3),
         "p99_ms": round(percentile(frame_ms, 99), 3),
@@ -170,7 +171,7 @@ def run_gpu(args):
     if dom == "blend":
         flops = (cnt["evaluations"] * FLOP_Q + cnt["blends"] * FLOP_BLEND) / launches
         ach = flops / (per_launch_ms * 1e-3) / 1e12
-        tr = measured_traffic("blend_kernel<false, %d, false>" % stages[0]["rays_per_lane"]) \
+        tr = measured_traffic("blend_kernel<false, %d, false, %d>" % (stages[0]["rays_per_lane"], stages[0]["lanes"])) \
             if args.workload == "uhd45" else None
         roof = {"kernel": "blend", "bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4),

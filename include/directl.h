@@ -223,6 +223,7 @@ typedef struct {
   int32_t batches, tile_w, tile_h, rays_per_lane;
   int32_t chunks;                               /* depth chunks of the frame */
   double chunk_ms[DL_MAX_CHUNKS][DL_NSTAGES];   /* stage_ms split by depth chunk (frame-level stages in 0) */
+  int32_t lanes;                                /* blend workgroup size (rays_per_lane rays per lane) */
 } dl_frame_stats;
 
 /* Profiling of subsequent frames of this context: 0 off; 1 per-stage HIP-event timing (a few events per

@@ -55,7 +55,7 @@ class dl_frame_stats(ctypes.Structure):
                 ("keys", ctypes.c_int64), ("visible", ctypes.c_int64), ("evaluations", ctypes.c_int64),
                 ("blends", ctypes.c_int64), ("rays", ctypes.c_int64), ("batches", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("rays_per_lane", ctypes.c_int32),
-                ("chunks", ctypes.c_int32), ("chunk_ms", (ctypes.c_double * NSTAGES) * 8)]
+                ("chunks", ctypes.c_int32), ("chunk_ms", (ctypes.c_double * NSTAGES) * 8), ("lanes", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -189,7 +189,7 @@ class Context:
         st = dl_frame_stats()
         _check(load().dl_frame_stats_get(self.h, ctypes.byref(st)))
         d = {k: getattr(st, k) for k in ("keys", "visible", "evaluations", "blends", "rays", "batches", "tile_w",
-                                         "tile_h", "rays_per_lane")}
+                                         "tile_h", "rays_per_lane", "lanes")}
         d["stage_ms"] = {STAGES[i]: st.stage_ms[i] for i in range(NSTAGES)}
         d["stage_launches"] = {STAGES[i]: st.stage_launches[i] for i in range(NSTAGES)}
         d["chunk_ms"] = [{STAGES[i]: st.chunk_ms[c][i] for i in range(NSTAGES) if st.chunk_ms[c][i] > 0}

@@ -29,15 +29,15 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   return x * q + min(x, rem) + k;
 }
 
-template <bool STD, int RPT, bool STATS>
-__global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restrict__ rec,
+template <bool STD, int RPT, bool STATS, int NT>
+__global__ __launch_bounds__(NT) void blend_kernel(const float4* __restrict__ rec,
                                                           const uint32_t* __restrict__ tile_start,
                                                           const uint32_t* __restrict__ gidx,
                                                           const uint32_t* __restrict__ ray_off,
                                                           const uint32_t* __restrict__ ray_ent, BlendConst bc,
                                                           BlendChunk bk, uint8_t* __restrict__ alive,
                                                           float4* __restrict__ state, float* __restrict__ out) {
-  __shared__ float4 sm[kThreads * kRecF4];
+  __shared__ float4 sm[NT * kRecF4];
   const uint32_t wi = xcd_remap(blockIdx.x, gridDim.x);
   const int v = (int)(wi / (uint32_t)bc.T);
   const int t = (int)(wi - (uint32_t)v * (uint32_t)bc.T);
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
   int64_t gid[RPT];
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int idx = threadIdx.x + j * kThreads;
+    const int idx = threadIdx.x + j * NT;
     const bool valid = idx < nr;
     int lx = 0, ly = 0;
     mask[j] = 0;
@@ -96,8 +96,8 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
   const uint32_t le = tile_start[vt + 1];
   const float4* vrec = rec + (int64_t)v * bc.G * kRecF4;
 
-  for (uint32_t base = ls; base < le; base += kThreads) {
-    const int n = (int)min((uint32_t)kThreads, le - base);
+  for (uint32_t base = ls; base < le; base += NT) {
+    const int n = (int)min((uint32_t)NT, le - base);
     if ((int)threadIdx.x < n) {
       const uint32_t g = gidx[base + threadIdx.x];
       const float4* src = vrec + (int64_t)g * kRecF4;
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
     for (int j = 0; j < RPT; ++j) {
       e += nev[j];
       b += nbl[j];
-      r += (bk.first && threadIdx.x + j * kThreads < nr) ? 1 : 0;
+      r += (bk.first && threadIdx.x + j * NT < nr) ? 1 : 0;
     }
     for (int d = 32; d >= 1; d >>= 1) {
       e += __shfl_xor(e, d, 64);
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
 
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int idx = threadIdx.x + j * kThreads;
+    const int idx = threadIdx.x + j * NT;
     if (idx >= nr) continue;
     if (!bk.last && tile_live) state[gid[j]] = make_float4(sT[j], C0[j], C1[j], C2[j]);
     if (bk.last || !tile_live) {
@@ -209,17 +209,17 @@ __global__ __launch_bounds__(kThreads) void blend_kernel(const float4* __restric
   }
 }
 
-template <bool STD>
+template <bool STD, int NT>
 hipError_t launch_rpt(int rpt, unsigned nblocks, const float4* rec, const uint32_t* tile_start, const uint32_t* gidx,
                       const uint32_t* ray_off, const uint32_t* ray_ent, const BlendConst& bc, BlendChunk bk,
                       uint8_t* alive, float4* state, float* out, hipStream_t s) {
 #define DL_BLEND_CASE(R)                                                                                        \
   case R:                                                                                                      \
     if (bc.stats)                                                                                              \
-      hipLaunchKernelGGL((blend_kernel<STD, R, true>), dim3(nblocks), dim3(kThreads), 0, s, rec, tile_start,  \
+      hipLaunchKernelGGL((blend_kernel<STD, R, true, NT>), dim3(nblocks), dim3(NT), 0, s, rec, tile_start,     \
                          gidx, ray_off, ray_ent, bc, bk, alive, state, out);                                   \
     else                                                                                                       \
-      hipLaunchKernelGGL((blend_kernel<STD, R, false>), dim3(nblocks), dim3(kThreads), 0, s, rec, tile_start, \
+      hipLaunchKernelGGL((blend_kernel<STD, R, false, NT>), dim3(nblocks), dim3(NT), 0, s, rec, tile_start,    \
                          gidx, ray_off, ray_ent, bc, bk, alive, state, out);                                   \
     break;
   switch (rpt) {
@@ -231,8 +231,6 @@ hipError_t launch_rpt(int rpt, unsigned nblocks, const float4* rec, const uint32
     DL_BLEND_CASE(6)
     DL_BLEND_CASE(7)
     DL_BLEND_CASE(8)
-    DL_BLEND_CASE(12)
-    DL_BLEND_CASE(16)
     default:
       return hipErrorInvalidValue;
   }
@@ -240,11 +238,18 @@ hipError_t launch_rpt(int rpt, unsigned nblocks, const float4* rec, const uint32
   return hipGetLastError();
 }
 
-// Rays per lane: the fewest that hold the largest (view, tile) ray list (registers, and so occupancy, grow with
-// it; slots that a whole wavefront leaves empty cost nothing).
-int rpt_for(int max_rays) {
-  const int r = (max_rays + kThreads - 1) / kThreads;
-  return r <= 8 ? std::max(r, 1) : (r <= 12 ? 12 : 16);
+// Workgroup shape for a tile's largest ray list: 256 lanes with up to 4 rays each, else 512 lanes with up to 8
+// (registers, and so occupancy, grow with the rays per lane; slots a whole wavefront leaves empty cost nothing).
+template <bool STD>
+hipError_t launch_blend(int max_rays, unsigned nblocks, const float4* rec, const uint32_t* tile_start,
+                        const uint32_t* gidx, const uint32_t* ray_off, const uint32_t* ray_ent, const BlendConst& bc,
+                        BlendChunk bk, uint8_t* alive, float4* state, float* out, hipStream_t s) {
+  if (max_rays <= 4 * 256)
+    return launch_rpt<STD, 256>(std::max(1, (max_rays + 255) / 256), nblocks, rec, tile_start, gidx, ray_off, ray_ent,
+                                bc, bk, alive, state, out, s);
+  if (max_rays > 8 * 512) return hipErrorInvalidValue;
+  return launch_rpt<STD, 512>((max_rays + 511) / 512, nblocks, rec, tile_start, gidx, ray_off, ray_ent, bc, bk, alive,
+                              state, out, s);
 }
 
 }  // namespace
@@ -255,8 +260,7 @@ hipError_t launch_blend_directl(const float4* rec, const uint32_t* tile_start, c
                                 hipStream_t s) {
   const unsigned nb = (unsigned)((int64_t)bc.N * bc.T);
   if (nb == 0) return hipSuccess;
-  return launch_rpt<false>(rpt_for(max_rays), nb, rec, tile_start, gidx, ray_off, ray_ent, bc, bk, alive, state, out,
-                           s);
+  return launch_blend<false>(max_rays, nb, rec, tile_start, gidx, ray_off, ray_ent, bc, bk, alive, state, out, s);
 }
 
 hipError_t launch_blend_standard(const float4* rec, const uint32_t* tile_start, const uint32_t* gidx,
@@ -264,8 +268,8 @@ hipError_t launch_blend_standard(const float4* rec, const uint32_t* tile_start, 
                                  hipStream_t s) {
   const unsigned nb = (unsigned)((int64_t)bc.N * bc.T);
   if (nb == 0) return hipSuccess;
-  return launch_rpt<true>(rpt_for(bc.tw * bc.th), nb, rec, tile_start, gidx, nullptr, nullptr, bc, bk, alive, state,
-                          views, s);
+  return launch_blend<true>(bc.tw * bc.th, nb, rec, tile_start, gidx, nullptr, nullptr, bc, bk, alive, state, views,
+                            s);
 }
 
 }  // namespace dl

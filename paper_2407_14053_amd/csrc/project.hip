@@ -47,7 +47,7 @@ __device__ inline void sh_basis(int deg, float x, float y, float z, float* Y) {
 }
 
 template <int DEG>
-__global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ soa, const double* __restrict__ cams,
+__global__ __launch_bounds__(256, 4) void project_kernel(const float* __restrict__ soa, const double* __restrict__ cams,
                                                       ProjConst pc, float4* __restrict__ rec,
                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                       double* __restrict__ depth_out) {
@@ -122,15 +122,17 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
       const double idet = 1.0 / (ca * cc - cb * cb);
       const double u = f * X * iz + pc.cx;
       const double w = f * Y * iz + pc.cy;
-      const double ex = sqrt(qlim * ca) * (1.0 + 1e-4) + 1e-3;
-      const double ey = sqrt(qlim * cc) * (1.0 + 1e-4) + 1e-3;
+      // conservative half-extents of the cutoff ellipse (FP32 square roots; the margins dwarf their error)
+      const float ex = sqrtf((float)(qlim * ca)) * (1.0f + 1e-4f) + 1e-3f;
+      const float ey = sqrtf((float)(qlim * cc)) * (1.0f + 1e-4f) + 1e-3f;
       // the ellipse must reach a pixel centre: centres span [0.5, W - 0.5] x [0.5, H - 0.5]
       vis = (u + ex >= 0.5) && (u - ex <= pc.W - 0.5) && (w + ey >= 0.5) && (w - ey <= pc.H - 0.5);
       if (vis) {
-        double dx = mx - cam[12], dy = my - cam[13], dz = mz - cam[14];
-        const double dn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+        // view direction for the colour, normalised in FP32 (the SH basis is evaluated in FP32)
+        const float dx = (float)(mx - cam[12]), dy = (float)(my - cam[13]), dz = (float)(mz - cam[14]);
+        const float dn = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
         float Yb[16];
-        sh_basis(DEG, (float)(dx * dn), (float)(dy * dn), (float)(dz * dn), Yb);
+        sh_basis(DEG, dx * dn, dy * dn, dz * dn, Yb);
         float rgb[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
         }
         r[0] = (float)u; r[1] = (float)w;
         r[2] = (float)(ks * cc * idet); r[3] = (float)(-2.0 * ks * cb * idet); r[4] = (float)(ks * ca * idet);
-        r[5] = (float)(ks * qlim); r[6] = (float)ex; r[7] = (float)ey;
+        r[5] = (float)(ks * qlim); r[6] = ex; r[7] = ey;
         r[8] = o32; r[9] = rgb[0]; r[10] = rgb[1]; r[11] = rgb[2];
         const uint64_t zb = (uint64_t)__double_as_longlong(Z);
         const int e = (int)(zb >> 52) - pc.key_e0;  // >= 0 since Z > z_near

@@ -118,7 +118,7 @@ struct dl_ctx {
   size_t evused = 0;
   std::vector<Mark> marks;
   int64_t keys = 0, visible = 0;
-  int batches = 0, tile_w = 0, tile_h = 0, rpt = 0;
+  int batches = 0, tile_w = 0, tile_h = 0, rpt = 0, lanes = 0;
   ~dl_ctx() {
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
   }
@@ -818,7 +818,8 @@ int dl_render(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* 
   Tiles tl = make_tiles(D->desc, tw, th);
   C->tile_w = tw;
   C->tile_h = th;
-  C->rpt = (L->max_rays + 255) / 256;
+  C->rpt = L->max_rays <= 1024 ? (L->max_rays + 255) / 256 : (L->max_rays + 511) / 512;
+  C->lanes = L->max_rays <= 1024 ? 256 : 512;
   return render_grow(C, S, D, pose, o, tl, false, L, out_dev, s);
 }
 
@@ -1020,6 +1021,7 @@ int dl_frame_stats_get(dl_ctx* C, dl_frame_stats* out) {
   out->tile_w = C->tile_w;
   out->tile_h = C->tile_h;
   out->rays_per_lane = C->rpt;
+  out->lanes = C->lanes;
   return DL_OK;
 }
 
@@ -1041,7 +1043,8 @@ int dl_render_backward(dl_ctx* C, const dl_scene* S, const dl_display* D, const 
   Tiles tl = make_tiles(D->desc, tw, th);
   C->tile_w = tw;
   C->tile_h = th;
-  C->rpt = (L->max_rays + 255) / 256;
+  C->rpt = L->max_rays <= 1024 ? (L->max_rays + 255) / 256 : (L->max_rays + 511) / 512;
+  C->lanes = L->max_rays <= 1024 ? 256 : 512;
   BwdArgs b{out_dev, grad_out_dev, g_means, g_log_scales, g_quats, g_opacity_logits, g_sh};
   return render_grow(C, S, D, pose, o, tl, false, L, nullptr, s, &b);
 }
@@ -1072,7 +1075,8 @@ int dl_render_standard(dl_ctx* C, const dl_scene* S, const dl_display* D, const 
   Tiles tl = make_tiles(d, tw, th);
   C->tile_w = tw;
   C->tile_h = th;
-  C->rpt = (tw * th + 255) / 256;
+  C->rpt = tw * th <= 1024 ? (tw * th + 255) / 256 : (tw * th + 511) / 512;
+  C->lanes = tw * th <= 1024 ? 256 : 512;
   if ((rc = render_grow(C, S, D, pose, o, tl, true, nullptr, views, s))) return rc;
   int mk = C->begin(DL_STAGE_INTERLEAVE, s);
   HIP_TRY(launch_interleave(D->V.as<uint8_t>(), views, out_dev, d.width, d.height, s));
