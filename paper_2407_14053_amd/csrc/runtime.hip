@@ -329,7 +329,7 @@ Tiles make_tiles(const dl_display_desc& d, int tw, int th) {
 // Depth chunks (fractions of each view's visible depth ranks, in 1/1024): front chunks are small so that most
 // tiles terminate before the bulk of the keys would be produced.
 constexpr int kChunkDen = 1024;
-constexpr int kChunkBounds[] = {0, 64, 128, 256, 512, 1024};
+constexpr int kChunkBounds[] = {0, 64, 256, 1024};
 constexpr int kChunks = sizeof(kChunkBounds) / sizeof(kChunkBounds[0]) - 1;
 constexpr uint32_t kMaxKeyCap = 0x7fffffffu;
 
