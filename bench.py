@@ -97,10 +97,10 @@ def run_gpu(args):
     torch.cuda.synchronize()
     print("warmup done", file=sys.stderr, flush=True)
 
-    # timed region: per-stage HIP events only (profiling level 1); each frame ends with the library's own
-    # overflow readback, so frames do not overlap
+    # timed region: HIP events around the blend launches only (profiling level 1: the dominant kernel's duration
+    # for the roofline); each frame ends with the library's own overflow readback, so frames do not overlap
     ctx.set_profiling(1)
-    frame_ms, stages = [], []
+    frame_ms, timed = [], []
     timed_poses = [poses[(args.warmup + i) % len(poses)] for i in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -110,7 +110,7 @@ def run_gpu(args):
         e0.record(stream)
         api.render(ctx, S, D, c2w, opts=opts, out=out)
         e1.record(stream)
-        stages.append(ctx.frame_stats())
+        timed.append(ctx.frame_stats())
         e1.synchronize()
         frame_ms.append(e0.elapsed_time(e1))
     torch.cuda.synchronize()
@@ -118,8 +118,13 @@ def run_gpu(args):
     wall = t1 - t0
     fps = args.steps / wall
     print("directl: %.2f frames/s" % fps, file=sys.stderr, flush=True)
-    # work counters of the same frames (level 2 adds atomics to the blend, so it is not timed)
+    # the same frames again, untimed: every stage's events (level 2), then the blend's work counters (level 3)
     ctx.set_profiling(2)
+    stages = []
+    for c2w in timed_poses:
+        api.render(ctx, S, D, c2w, opts=opts, out=out)
+        stages.append(ctx.frame_stats())
+    ctx.set_profiling(3)
     counted = []
     for c2w in timed_poses:
         api.render(ctx, S, D, c2w, opts=opts, out=out)
@@ -128,6 +133,33 @@ def run_gpu(args):
     for st, ct in zip(stages, counted):
         for k in ("evaluations", "blends", "rays"):
             st[k] = ct[k]
+    blend_timed_ms = sum(t["stage_ms"]["blend"] for t in timed) / len(timed)
+    blend_launches = timed[0]["stage_launches"]["blend"]
+
+    # the same frames as HIP graph launches of a plan (the serving path): queued back to back without a host
+    # synchronisation between frames, the overflow status checked once after the last
+    gstream = torch.cuda.Stream()
+    plan = api.Plan(ctx, S, D, timed_poses[0], opts=opts, stream=gstream)
+    for c2w in timed_poses[:2]:
+        plan.launch(c2w, stream=gstream)
+    gstream.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(timed_poses) + 1)]
+    tg0 = time.perf_counter()
+    evs[0].record(gstream)
+    for i, c2w in enumerate(timed_poses):
+        plan.launch(c2w, stream=gstream)
+        evs[i + 1].record(gstream)
+    gstream.synchronize()
+    tg1 = time.perf_counter()
+    g_ok, _ = plan.check()
+    graph_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(len(timed_poses))]
+    api.render(ctx, S, D, timed_poses[-1], opts=opts, out=out)
+    graph = {"frames_per_s": round(len(timed_poses) / (tg1 - tg0), 3),
+             "ms_per_frame": round(1000.0 * (tg1 - tg0) / len(timed_poses), 3),
+             "p50_ms": round(percentile(graph_ms, 50), 3), "p99_ms": round(percentile(graph_ms, 99), 3),
+             "no_overflow": bool(g_ok), "bit_identical_to_eager": bool(torch.equal(plan.out, out))}
+    plan.close()
+    print("directl as graph launches: %.2f frames/s" % graph["frames_per_s"], file=sys.stderr, flush=True)
 
     def mean_stats(sts):
         keys = sts[0]["stage_ms"].keys()
@@ -158,6 +190,7 @@ def run_gpu(args):
         "p99_ms": round(percentile(frame_ms, 99), 3),
         "stage_ms": {k: round(v, 4) for k, v in st_ms.items() if v > 0},
         "work": {k: int(v) for k, v in cnt.items()},
+        "graph": graph,
         "chunk_ms": [{k: round(sum(s_["chunk_ms"][c].get(k, 0.0) for s_ in stages) / len(stages), 4)
                       for k in stages[0]["chunk_ms"][c]} for c in range(len(stages[0]["chunk_ms"]))],
     }
@@ -167,6 +200,9 @@ def run_gpu(args):
     dom = "blend" if st_ms.get("blend", 0) > 0 else max(st_ms, key=lambda k: st_ms[k])
     launches = max(1, stages[0]["stage_launches"][dom])
     per_launch_ms = st_ms[dom] / launches
+    if dom == "blend":  # its duration as measured inside the timed region
+        launches = max(1, blend_launches)
+        per_launch_ms = blend_timed_ms / launches
     G, N = scene.n, disp.n_views
     if dom == "blend":
         flops = (cnt["evaluations"] * FLOP_Q + cnt["blends"] * FLOP_BLEND) / launches
@@ -202,8 +238,7 @@ def run_gpu(args):
         out_std = torch.empty_like(out)
         api.render_standard(ctx, S, D, poses[0], out=out_std)
         torch.cuda.synchronize()
-        ms, sst = [], []
-        ctx.set_profiling(1)
+        ms = []
         ts0 = time.perf_counter()
         for i in range(args.std_steps):
             e0 = torch.cuda.Event(enable_timing=True)
@@ -211,11 +246,13 @@ def run_gpu(args):
             e0.record(stream)
             api.render_standard(ctx, S, D, poses[(args.warmup + i) % len(poses)], out=out_std)
             e1.record(stream)
-            sst.append(ctx.frame_stats())
             e1.synchronize()
             ms.append(e0.elapsed_time(e1))
         torch.cuda.synchronize()
         ts1 = time.perf_counter()
+        ctx.set_profiling(2)  # stage breakdown of one more standard frame, untimed
+        api.render_standard(ctx, S, D, poses[args.warmup % len(poses)], out=out_std)
+        sst = [ctx.frame_stats()]
         ctx.set_profiling(0)
         std_stage, std_cnt = mean_stats(sst)
         std_fps = args.std_steps / (ts1 - ts0)

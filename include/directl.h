@@ -177,8 +177,10 @@ int dl_interleave(const dl_display* display, const float* views_dev, float* out_
  * cameras of `pose`, then launches that graph on `stream`; it does not synchronise.  Streams must not be the
  * null stream.  Launches of one plan must be
  * ordered (one stream, or the previous frame completed): they share the plan's buffers.  After a launch has
- * completed, dl_plan_check returns DL_OK, or DL_ECAP if a depth chunk overflowed the plan's capacity — the image
- * is then invalid and *need holds the keys that chunk required (render that request eagerly or with a new plan).
+ * completed, dl_plan_check returns DL_OK if no frame of the plan so far overflowed its capacity, else DL_ECAP
+ * (sticky: the overflowing frame's image, and any later one, is invalid) with *need = the most keys a depth
+ * chunk required — render those requests eagerly or with a new plan.  Many frames may be launched back to back
+ * and checked once after the last.
  * dl_plan_bytes: device bytes the plan holds.  dl_plan_free waits for the plan's work to finish. */
 int dl_plan_create(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_render_opts* opts,
                    const dl_pose* probe_pose, int64_t min_key_capacity, float* out_dev, void* stream,
@@ -214,7 +216,7 @@ enum {
  * keys: the largest number of (view, tile) list entries of one depth chunk; visible: (view, Gaussian) pairs
  * that reach the screen;
  * evaluations: (ray, list entry) pairs the blend examined; blends: pairs composited; rays: rays rendered
- * (these three are zero unless profiling is at level 2). */
+ * (these three are zero unless profiling is at level 3); stages without events read 0. */
 #define DL_MAX_CHUNKS 8
 typedef struct {
   double stage_ms[DL_NSTAGES];
@@ -226,9 +228,11 @@ typedef struct {
   int32_t lanes;                                /* blend workgroup size (rays_per_lane rays per lane) */
 } dl_frame_stats;
 
-/* Profiling of subsequent frames of this context: 0 off; 1 per-stage HIP-event timing (a few events per
- * stage, negligible cost); 2 timing plus the blend's work counters (evaluations, blends, rays), which cost
- * atomics in the blend kernel — time with level 1, count with level 2.  Other levels: DL_EINVAL. */
+/* Profiling of subsequent frames of this context: 0 off; 1 HIP events around the blend launches only (the
+ * dominant kernel; two events per depth chunk); 2 events around every stage (each event adds a few microseconds
+ * between kernels); 3 every stage plus the blend's work counters (evaluations, blends, rays), which cost
+ * atomics in the blend kernel — time with level 1, break down with level 2, count with level 3.  Other levels:
+ * DL_EINVAL. */
 int dl_set_profiling(dl_ctx* ctx, int level);
 /* Read the measurements of the last profiled frame (synchronises on its events). */
 int dl_frame_stats_get(dl_ctx* ctx, dl_frame_stats* out);

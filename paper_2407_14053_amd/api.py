@@ -181,8 +181,8 @@ class Context:
         return int(load().dl_key_capacity(self.h))
 
     def set_profiling(self, level):
-        """0/False off, 1 stage timing, 2/True timing and blend work counters."""
-        level = 2 if level is True else int(level)
+        """0/False off, 1 blend timing, 2 every stage, 3/True every stage and the blend's work counters."""
+        level = 3 if level is True else int(level)
         _check(load().dl_set_profiling(self.h, level))
 
     def frame_stats(self) -> dict:

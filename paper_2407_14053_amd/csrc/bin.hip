@@ -220,15 +220,16 @@ __global__ __launch_bounds__(256) void view_live_kernel(const uint8_t* __restric
   if (threadIdx.x == 0) live[v] = part[0] + part[1] + part[2] + part[3];
 }
 
-// Start of a frame: every (view, tile) with rays is live, the key totals and the front histogram are zero.
+// Start of a frame: every (view, tile) with rays is live, the front histogram and the first n_totals key totals
+// (the chunk's, then the frame's largest) are zero.
 __global__ __launch_bounds__(256) void frame_init_kernel(uint8_t* __restrict__ alive,
                                                          const uint32_t* __restrict__ ray_off, int64_t n,
                                                          uint32_t* __restrict__ zero32, int64_t n_zero,
-                                                         unsigned long long* __restrict__ totals) {
+                                                         unsigned long long* __restrict__ totals, int n_totals) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) alive[i] = ray_off ? (uint8_t)(ray_off[i + 1] > ray_off[i]) : (uint8_t)1;
   if (i < n_zero) zero32[i] = 0;
-  if (i < 2) totals[i] = 0;
+  if (i < n_totals) totals[i] = 0;
 }
 
 __global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long v) {
@@ -267,10 +268,10 @@ hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* li
 }
 
 hipError_t launch_frame_init(uint8_t* alive, const uint32_t* ray_off, int64_t n, uint32_t* zero32, int64_t n_zero,
-                             unsigned long long* totals, hipStream_t s) {
+                             unsigned long long* totals, int n_totals, hipStream_t s) {
   const int64_t m = std::max<int64_t>(std::max<int64_t>(n, n_zero), 2);
   hipLaunchKernelGGL(frame_init_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, alive, ray_off, n, zero32,
-                     n_zero, totals);
+                     n_zero, totals, n_totals);
   return hipGetLastError();
 }
 

@@ -174,9 +174,9 @@ hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* li
                             hipStream_t s);
 
 
-// alive[i] = tile i has rays (ray_off nullptr: all); zero32[0, n_zero) = 0; totals[0..1] = 0
+// alive[i] = tile i has rays (ray_off nullptr: all); zero32[0, n_zero) = 0; totals[0, n_totals) = 0
 hipError_t launch_frame_init(uint8_t* alive, const uint32_t* ray_off, int64_t n, uint32_t* zero32, int64_t n_zero,
-                             unsigned long long* totals, hipStream_t s);
+                             unsigned long long* totals, int n_totals, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
 
 // ---- blending (blend.hip) ----

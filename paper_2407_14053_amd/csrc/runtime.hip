@@ -107,7 +107,8 @@ struct dl_ctx {
       state, dtotal, gacc;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
   double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
-  // profiling: 0 off, 1 HIP events around each stage of the last frame, 2 events and work counters
+  // profiling: 0 off, 1 HIP events around the blend launches, 2 around every stage, 3 every stage and the
+  // blend's work counters
   int prof = 0;
   struct Mark {
     int stage, chunk;
@@ -138,7 +139,7 @@ struct dl_ctx {
     batches = 0;
   }
   int begin(int stage, hipStream_t s) {
-    if (!prof) return -1;
+    if (!prof || (prof == 1 && stage != DL_STAGE_BLEND)) return -1;
     Mark m{stage, chunk, ev(), ev()};
     if (!m.a || !m.b) return -1;
     (void)hipEventRecord(m.a, s);
@@ -355,6 +356,7 @@ int64_t chunk_stride(int64_t G, int c) {
 struct FrameMode {
   bool upload = true;
   bool finish = true;
+  bool keep_max = false;  // keep the largest chunk total of earlier frames (a plan's overflow status is sticky)
 };
 
 // Backward inputs/outputs of a frame (DirectL only).
@@ -412,7 +414,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   const int64_t hs = std::max(std::max(radix_hist_size(G, N), depth_ranges_hist_size(G, N)), tile_partition_hist_size(N));
   HIP_TRY(C->hist.ensure((size_t)hs * 4));
   HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, N * max_wstride)) + 2) * 4));
-  if (C->prof >= 2) HIP_TRY(C->stats.ensure((size_t)kStatSlots * 3 * 8));
+  if (C->prof >= 3) HIP_TRY(C->stats.ensure((size_t)kStatSlots * 3 * 8));
   if (bwd) {
     HIP_TRY(C->gacc.ensure((size_t)NG * 9 * 4));
     HIP_TRY(hipMemsetAsync(C->gacc.p, 0, (size_t)NG * 9 * 4, s));
@@ -422,9 +424,10 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   int mk = C->begin(DL_STAGE_UPLOAD, s);
   if (mode.upload)
     HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
-  if (C->prof >= 2) HIP_TRY(launch_fill_u64(C->stats.as<unsigned long long>(), kStatSlots * 3, 0ull, s));
+  if (C->prof >= 3) HIP_TRY(launch_fill_u64(C->stats.as<unsigned long long>(), kStatSlots * 3, 0ull, s));
   HIP_TRY(launch_frame_init(C->alive.as<uint8_t>(), standard ? nullptr : L->off.as<uint32_t>(), NT,
-                            C->fhist.as<uint32_t>(), front_hist_size(N), C->dtotal.as<unsigned long long>(), s));
+                            C->fhist.as<uint32_t>(), front_hist_size(N), C->dtotal.as<unsigned long long>(),
+                            mode.keep_max ? 1 : 2, s));
   C->end(mk, s);
 
   ProjConst pc{};
@@ -490,7 +493,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   bc.t_min = o.t_min;
   bc.log2_alpha_min = (float)std::log2((double)o.alpha_min);
   for (int k = 0; k < 3; ++k) bc.bg[k] = o.bg[k];
-  bc.stats = C->prof >= 2 ? C->stats.as<unsigned long long>() : nullptr;
+  bc.stats = C->prof >= 3 ? C->stats.as<unsigned long long>() : nullptr;
   unsigned long long* total = C->dtotal.as<unsigned long long>();
   for (int c = 0; c < kChunks; ++c) {
     C->chunk = c;
@@ -836,7 +839,7 @@ struct dl_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t copied = nullptr;                // after the last camera upload: the staging may be rewritten
-  unsigned long long* status_host = nullptr;  // pinned: largest chunk key total of the last launch
+  unsigned long long* status_host = nullptr;  // pinned: largest chunk key total of the plan's frames so far
   ~dl_plan() {
     if (copied) {
       (void)hipEventSynchronize(copied);
@@ -864,6 +867,8 @@ int plan_capture(dl_plan* P, hipStream_t s) {
   FrameMode m;
   m.upload = false;
   m.finish = false;
+  m.keep_max = true;
+  HIP_TRY(launch_fill_u64(P->C->dtotal.as<unsigned long long>(), 2, 0ull, s));  // status of the plan's frames
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   int rc = render_frame(P->C, P->S, P->D, nullptr, P->o, P->tl, false, P->L, P->out, s, &need, nullptr, m);
   hipGraph_t g = nullptr;
@@ -985,7 +990,7 @@ int64_t dl_key_capacity(const dl_ctx* C) { return C ? (int64_t)C->key_cap : -1; 
 
 int dl_set_profiling(dl_ctx* C, int level) {
   if (!C) return fail(DL_EINVAL, "NULL context");
-  if (level < 0 || level > 2) return fail(DL_EINVAL, "profiling level is 0, 1 or 2");
+  if (level < 0 || level > 3) return fail(DL_EINVAL, "profiling level is 0, 1, 2 or 3");
   C->prof = level;
   return DL_OK;
 }
@@ -1005,7 +1010,7 @@ int dl_frame_stats_get(dl_ctx* C, dl_frame_stats* out) {
     }
   }
   unsigned long long st[3] = {0, 0, 0};
-  if (C->prof >= 2 && C->stats.p) {
+  if (C->prof >= 3 && C->stats.p) {
     std::vector<unsigned long long> sl((size_t)kStatSlots * 3);
     HIP_TRY(hipMemcpy(sl.data(), C->stats.p, sl.size() * 8, hipMemcpyDeviceToHost));
     for (int i = 0; i < kStatSlots; ++i)
