@@ -22,8 +22,7 @@ namespace {
 constexpr int kThreads = 256;
 
 __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
-  // workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous range of work items so
-  // that the tiles sharing a view's records share an L2
+  // workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous range of work items
   const uint32_t q = nb / 8, rem = nb % 8;
   const uint32_t x = b % 8, k = b / 8;
   return x * q + min(x, rem) + k;
@@ -38,9 +37,11 @@ __global__ __launch_bounds__(NT) void blend_kernel(const float4* __restrict__ re
                                                           BlendChunk bk, uint8_t* __restrict__ alive,
                                                           float4* __restrict__ state, float* __restrict__ out) {
   __shared__ float4 sm[NT * kRecF4];
+  // work items in tile-major order, a contiguous range of them per XCD: all views of a tile run on one XCD
+  // at about the same time, so the partial writes of their interleaved subpixels meet in that XCD's L2
   const uint32_t wi = xcd_remap(blockIdx.x, gridDim.x);
-  const int v = (int)(wi / (uint32_t)bc.T);
-  const int t = (int)(wi - (uint32_t)v * (uint32_t)bc.T);
+  const int t = (int)(wi / (uint32_t)bc.N);
+  const int v = (int)(wi - (uint32_t)t * (uint32_t)bc.N);
   const int64_t vt = (int64_t)v * bc.T + t;
   if (!alive[vt]) return;
   const int tx = t % bc.ntx, ty = t / bc.ntx;
