@@ -188,6 +188,11 @@ int dl_plan_create(dl_ctx* ctx, const dl_scene* scene, const dl_display* display
 int dl_plan_render(dl_plan* plan, const dl_pose* pose, void* stream);
 int dl_plan_check(const dl_plan* plan, int64_t* need);
 int64_t dl_plan_bytes(const dl_plan* plan);
+/* Device bytes a plan of (scene, display, opts) would hold with a per-chunk tile-key capacity of key_capacity
+ * (a plan sizes its own capacity with its probe frame), for admission decisions before creating one; -1 on a
+ * NULL argument or invalid options. */
+int64_t dl_plan_estimate_bytes(const dl_scene* scene, const dl_display* display, const dl_render_opts* opts,
+                               int64_t key_capacity);
 void dl_plan_free(dl_plan* plan);
 
 /* Per-depth-chunk capacity of the context's tile-key buffers (0 until the first frame sizes it).  A frame

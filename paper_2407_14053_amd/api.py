@@ -90,6 +90,7 @@ _SIGS = {
     "dl_plan_render": (_I, [_P, ctypes.POINTER(dl_pose), _P]),
     "dl_plan_check": (_I, [_P, ctypes.POINTER(ctypes.c_int64)]),
     "dl_plan_bytes": (ctypes.c_int64, [_P]),
+    "dl_plan_estimate_bytes": (ctypes.c_int64, [_P, _P, ctypes.POINTER(dl_render_opts), ctypes.c_int64]),
     "dl_plan_free": (None, [_P]),
 }
 
@@ -361,6 +362,16 @@ def interleave(display, views, out=None, stream=None):
         out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     _check(load().dl_interleave(display.h, _ptr(views), _ptr(out), _stream(stream)))
     return out
+
+
+def plan_estimate_bytes(scene, display, opts=None, key_capacity: int = 0) -> int:
+    """Device bytes a plan would hold (plus its output image) at the given tile-key capacity."""
+    o = opts or default_opts()
+    n = int(load().dl_plan_estimate_bytes(scene.h, display.h, ctypes.byref(o), int(key_capacity)))
+    if n < 0:
+        raise DLError(DL_EINVAL, "cannot estimate a plan for these arguments")
+    h, w = display.shape
+    return n + 12 * h * w
 
 
 class Plan:

@@ -350,6 +350,52 @@ int64_t chunk_stride(int64_t G, int c) {
   return G * (kChunkBounds[c + 1] - kChunkBounds[c]) / kChunkDen + 1;
 }
 
+// Device bytes of every per-frame buffer, in the order render_frame ensures them.
+constexpr int kFrameBufs = 26;
+struct FrameSizes {
+  size_t bytes[kFrameBufs];
+  int64_t max_wstride;
+  size_t total() const {
+    size_t t = 0;
+    for (size_t b : bytes) t += b;
+    return t;
+  }
+};
+
+FrameSizes frame_sizes(int N, int64_t G, int64_t NT, int64_t nstate, uint32_t cap, bool stats, bool bwd) {
+  FrameSizes z{};
+  const int64_t NG = (int64_t)N * G;
+  int64_t max_stride = 0;
+  for (int c = 0; c < kChunks; ++c) max_stride = std::max(max_stride, chunk_stride(G, c) + 64);
+  z.max_wstride = (max_stride + 63) / 64;
+  const int64_t hs = std::max(std::max(radix_hist_size(G, N), depth_ranges_hist_size(G, N)), tile_partition_hist_size(N));
+  const size_t v[kFrameBufs] = {
+      (size_t)N * kCamDoubles * 8,                    // cameras
+      (size_t)NG * kRecF4 * 16,                       // records, projection order
+      (size_t)NG * kRecF4 * 16,                       // records, depth order
+      (size_t)NG * 8, (size_t)NG * 8,                 // depth keys (double-buffered)
+      (size_t)NG * 4, (size_t)NG * 4,                 // Gaussian indices (double-buffered)
+      256 * 4,                                        // visible counts
+      (size_t)N * z.max_wstride * 4,                  // per-wavefront key counts
+      (size_t)N * 4,                                  // live tiles per view
+      (size_t)(3 * N + 2) * 4,                        // view key ranges and the partition layout
+      (size_t)(6 * N + 1) * 4,                        // fronts, sort ranges, rank ends, sort layout
+      (size_t)N * 8,                                  // front thresholds
+      (size_t)front_hist_size(N) * 4,                 // front histogram
+      (size_t)cap * 4, (size_t)cap * 4,               // tile keys (double-buffered)
+      (size_t)cap * 4, (size_t)cap * 4,               // tile values (double-buffered)
+      (size_t)(NT + 1) * 4,                           // list starts
+      (size_t)NT,                                     // live tiles
+      (size_t)std::max<int64_t>(nstate, 1) * 16,      // ray state
+      2 * 8,                                          // key totals
+      (size_t)hs * 4,                                 // radix histograms
+      (size_t)(scan_partial_count(std::max<int64_t>(hs, N * z.max_wstride)) + 2) * 4,  // scan partials
+      stats ? (size_t)kStatSlots * 3 * 8 : 0,         // work counters
+      bwd ? (size_t)NG * 9 * 4 : 0};                  // backward accumulators
+  for (int b = 0; b < kFrameBufs; ++b) z.bytes[b] = v[b];
+  return z;
+}
+
 // How a frame is issued: eager frames upload their cameras and end with the overflow check; a frame being
 // captured into a graph does neither (the plan uploads the cameras before each launch and reads the overflow
 // flag after completion).
@@ -386,39 +432,15 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   if (C->key_cap == 0) C->key_cap = (uint32_t)std::min<int64_t>(kMaxKeyCap, std::max<int64_t>(1 << 22, 2 * NG));
   const uint32_t cap = C->key_cap;
   const int64_t nstate = standard ? (int64_t)N * d.width * d.height : L->n_rays;
-  int64_t max_stride = 0;
-  for (int c = 0; c < kChunks; ++c) max_stride = std::max(max_stride, chunk_stride(G, c) + 64);
-  HIP_TRY(C->cams.ensure((size_t)N * kCamDoubles * 8));
-  HIP_TRY(C->rec.ensure((size_t)NG * kRecF4 * 16));
-  HIP_TRY(C->srec.ensure((size_t)NG * kRecF4 * 16));
-  HIP_TRY(C->k64[0].ensure((size_t)NG * 8));
-  HIP_TRY(C->k64[1].ensure((size_t)NG * 8));
-  HIP_TRY(C->v32[0].ensure((size_t)NG * 4));
-  HIP_TRY(C->v32[1].ensure((size_t)NG * 4));
-  HIP_TRY(C->vis.ensure(256 * 4));
-  const int64_t max_wstride = (max_stride + 63) / 64;
-  HIP_TRY(C->counts.ensure((size_t)N * max_wstride * 4));
-  HIP_TRY(C->live.ensure((size_t)N * 4));
-  HIP_TRY(C->vstart.ensure((size_t)(3 * N + 2) * 4));  // view starts, then the partition layout
-  HIP_TRY(C->dord.ensure((size_t)(6 * N + 1) * 4));    // fronts, sort ranges, rank ends, sort layout
-  HIP_TRY(C->thr.ensure((size_t)N * 8));
-  HIP_TRY(C->fhist.ensure((size_t)front_hist_size(N) * 4));
-  HIP_TRY(C->bk[0].ensure((size_t)cap * 4));
-  HIP_TRY(C->bk[1].ensure((size_t)cap * 4));
-  HIP_TRY(C->bv[0].ensure((size_t)cap * 4));
-  HIP_TRY(C->bv[1].ensure((size_t)cap * 4));
-  HIP_TRY(C->tstart.ensure((size_t)(NT + 1) * 4));
-  HIP_TRY(C->alive.ensure((size_t)NT));
-  HIP_TRY(C->state.ensure((size_t)std::max<int64_t>(nstate, 1) * 16));
-  HIP_TRY(C->dtotal.ensure(2 * 8));
-  const int64_t hs = std::max(std::max(radix_hist_size(G, N), depth_ranges_hist_size(G, N)), tile_partition_hist_size(N));
-  HIP_TRY(C->hist.ensure((size_t)hs * 4));
-  HIP_TRY(C->partial.ensure((size_t)(scan_partial_count(std::max<int64_t>(hs, N * max_wstride)) + 2) * 4));
-  if (C->prof >= 3) HIP_TRY(C->stats.ensure((size_t)kStatSlots * 3 * 8));
-  if (bwd) {
-    HIP_TRY(C->gacc.ensure((size_t)NG * 9 * 4));
-    HIP_TRY(hipMemsetAsync(C->gacc.p, 0, (size_t)NG * 9 * 4, s));
-  }
+  const FrameSizes z = frame_sizes(N, G, NT, nstate, cap, C->prof >= 3, bwd != nullptr);
+  DevBuf* bufs[] = {&C->cams,   &C->rec,   &C->srec,  &C->k64[0], &C->k64[1], &C->v32[0], &C->v32[1],
+                    &C->vis,    &C->counts, &C->live, &C->vstart, &C->dord,   &C->thr,    &C->fhist,
+                    &C->bk[0],  &C->bk[1], &C->bv[0], &C->bv[1],  &C->tstart, &C->alive,  &C->state,
+                    &C->dtotal, &C->hist,  &C->partial, &C->stats, &C->gacc};
+  static_assert(sizeof(bufs) / sizeof(bufs[0]) == kFrameBufs, "one size per frame buffer");
+  for (int b = 0; b < kFrameBufs; ++b)
+    if (z.bytes[b]) HIP_TRY(bufs[b]->ensure(z.bytes[b]));
+  if (bwd) HIP_TRY(hipMemsetAsync(C->gacc.p, 0, (size_t)NG * 9 * 4, s));
 
   C->frame_begin();
   int mk = C->begin(DL_STAGE_UPLOAD, s);
@@ -952,6 +974,19 @@ int dl_plan_create(dl_ctx* ctx, const dl_scene* S, const dl_display* D, const dl
 }
 
 int64_t dl_plan_bytes(const dl_plan* P) { return P ? (int64_t)ctx_bytes(P->C) : -1; }
+
+int64_t dl_plan_estimate_bytes(const dl_scene* S, const dl_display* D, const dl_render_opts* opts,
+                               int64_t key_capacity) {
+  if (!S || !D || key_capacity < 0) return -1;
+  dl_render_opts o;
+  if (check_opts(opts, o)) return -1;
+  int tw = o.tile_w, th = o.tile_h;
+  if (tw == 0 || th == 0) auto_tile_directl(D->desc, tw, th);
+  const Tiles tl = make_tiles(D->desc, tw, th);
+  const int N = D->desc.n_views;
+  const uint32_t cap = (uint32_t)std::min<int64_t>(kMaxKeyCap, std::max<int64_t>(key_capacity, 1));
+  return (int64_t)frame_sizes(N, S->n, (int64_t)N * tl.T, D->n_rays, cap, false, false).total();
+}
 
 int dl_plan_render(dl_plan* P, const dl_pose* pose, void* stream) {
   if (!P) return fail(DL_EINVAL, "NULL plan");

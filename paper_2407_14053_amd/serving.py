@@ -177,16 +177,13 @@ class Server:
         return self.resident_bytes + self.plan_bytes
 
     def _estimate(self, key) -> int:
+        """Bytes of a new plan for the pair: the last plan made for it, else the library's estimate at a
+        tile-key capacity of twice the (view, Gaussian) pairs per depth chunk (a generous first guess)."""
         if key in self.est:
             return self.est[key]
-        # before the first plan of a pair: two record arrays, depth keys and values (double-buffered), chunk
-        # counts, the probe's first guess of the tile-key capacity (four buffers), ray state and the image
-        g = self.scenes[key[0]].n
-        disp = self.displays[key[1]]
-        ng = disp.n_views * g
-        h, w = disp.shape
-        cap = min(1 << 22, max(1 << 16, ng // 2))
-        return ng * (2 * 48 + 2 * 8 + 2 * 4) + 4 * ng // 2 + 16 * cap + 16 * 3 * h * w + 12 * h * w
+        scene, disp = self.scenes[key[0]], self.displays[key[1]]
+        cap = max(self.min_keys.get(key, 0), 2 * disp.n_views * scene.n)
+        return api.plan_estimate_bytes(scene, disp, self.opts, min(cap, 2**31 - 1))
 
     # ---- plans ----
     def _evict_for(self, need: int) -> bool:

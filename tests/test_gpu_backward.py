@@ -138,6 +138,6 @@ def test_autograd_function_and_l1_descent(ctx):
         loss = (rnd.render(params, c2w) - target).abs().mean()
         loss.backward()
         opt.step()
-        losses.append(float(loss))
+        losses.append(float(loss.detach()))
     log("  L1:", ["%.5f" % x for x in losses])
     assert losses[-1] < 0.9 * losses[0]

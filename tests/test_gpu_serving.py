@@ -108,6 +108,26 @@ def test_plan_overflow_is_reported_and_rebuilt_plan_is_exact(ctx):
     plan.close()
 
 
+def test_plan_memory_estimate(ctx):
+    import torch
+    from paper_2407_14053_amd import api
+    d = synth.make_named_display("tiny")
+    sc = synth.scene_uniform(20_000, 2.0, 1004)
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    e0 = api.plan_estimate_bytes(S, D)
+    assert api.plan_estimate_bytes(S, D, key_capacity=101_000) - api.plan_estimate_bytes(S, D, key_capacity=1000) \
+        == 16 * 100_000  # four 4-byte key buffers
+    stream = torch.cuda.Stream()
+    plan = api.Plan(ctx, S, D, synth.pose_front(3.0), stream=stream)
+    # the plan holds the estimate at its own capacity (a multiple of 16 bytes above the zero-capacity estimate),
+    # up to the allocator's minimum block for the smallest buffers
+    extra = plan.bytes - e0
+    assert 0 < extra
+    cap = extra // 16
+    assert abs(plan.bytes - api.plan_estimate_bytes(S, D, key_capacity=cap)) <= 16 * 256
+    plan.close()
+
+
 def test_plan_rejects_null_stream(ctx):
     from paper_2407_14053_amd import api
     d = synth.make_named_display("fd64")
