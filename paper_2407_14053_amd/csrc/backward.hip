@@ -30,10 +30,27 @@ __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
   return x * q + min(x, rem) + k;
 }
 
-__device__ inline float wave_sum(float x) {
+// Sums of 9 values over the 64 lanes of a wavefront, as a reduce-scatter: each exchange step halves the values a
+// lane carries (8 + 4 + 2 + 1 shuffles, then 2 to finish) instead of reducing every value separately.  On return
+// lane l holds the sum of value index(l) = (l5 l4 l3 l2) read as a binary number (bit k of l is lk); lanes with
+// l & 3 == 0 carry distinct indices 0..15, of which 0..8 are the values.
+__device__ inline float wave_reduce9(const float* g, int lane, int* index) {
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+  float x[8], y[4], z[2];
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-  return x;
+  for (int j = 0; j < 8; ++j) {
+    const float lo = g[j], hi = j == 0 ? g[8] : 0.0f;  // indices j and 8 + j
+    x[j] = (b5 ? hi : lo) + __shfl_xor(b5 ? lo : hi, 32, 64);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) y[j] = (b4 ? x[4 + j] : x[j]) + __shfl_xor(b4 ? x[j] : x[4 + j], 16, 64);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) z[j] = (b3 ? y[2 + j] : y[j]) + __shfl_xor(b3 ? y[j] : y[2 + j], 8, 64);
+  float w = (b2 ? z[1] : z[0]) + __shfl_xor(b2 ? z[0] : z[1], 4, 64);
+  w += __shfl_xor(w, 2, 64);
+  w += __shfl_xor(w, 1, 64);
+  *index = (b5 ? 8 : 0) | (b4 ? 4 : 0) | (b3 ? 2 : 0) | (b2 ? 1 : 0);
+  return w;
 }
 
 template <int RPT>
@@ -140,7 +157,8 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
           // the forward's arithmetic, operation for operation
           const float dx = px[j] - A.x, dy = py[j] - A.y;
           const float q = fmaf(A.z * dx, dx, fmaf(cC, dy, A.w * dx) * dy);
-          const float ga = B.x * __builtin_amdgcn_exp2f(-q);
+          const float e2 = __builtin_amdgcn_exp2f(-q);
+          const float ga = B.x * e2;
           const float alpha = fminf(a_max, ga);
           const bool ok = live[j] && (q <= CQ.y);
           const float tn = fmaf(-alpha, Tr[j], Tr[j]);
@@ -153,13 +171,13 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
             // dC/dc = alpha T ; dC/dalpha = T c - (C_end - C_<=j) / (1 - alpha)
             const float gc = g0[j] * B.y + g1[j] * B.z + g2[j] * B.w;
             const float gR = g0[j] * (F0[j] - n0) + g1[j] * (F1[j] - n1) + g2[j] * (F2[j] - n2);
-            const float da = Tr[j] * gc - gR / (1.0f - alpha);
+            const float da = Tr[j] * gc - gR * __builtin_amdgcn_rcpf(1.0f - alpha);
             gr[6] += g0[j] * w;
             gr[7] += g1[j] * w;
             gr[8] += g2[j] * w;
             if (ga <= a_max) {
               const float dQ = -da * ln2 * ga;  // alpha = o 2^-Q
-              gr[5] += da * (ga / B.x);
+              gr[5] += da * e2;
               gr[2] += dQ * dx * dx;
               gr[3] += dQ * dx * dy;
               gr[4] += dQ * dy * dy;
@@ -175,11 +193,9 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
           any_take |= take;
         }
         if (__ballot(any_take) != 0ull) {
-#pragma unroll
-          for (int c = 0; c < kG; ++c) {
-            const float s = wave_sum(gr[c]);
-            if (lane == 0) part[w][k][c] = s;
-          }
+          int c;
+          const float s = wave_reduce9(gr, lane, &c);
+          if ((lane & 3) == 0 && c < kG) part[w][k][c] = s;
         }
         if (__ballot(any_live) == 0ull) break;
       }
@@ -214,12 +230,12 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
 }
 
 // Real SH basis (as in the projection) and its gradient with respect to the unit direction (x, y, z).
-__device__ inline void sh_basis_grad(int deg, double x, double y, double z, double* Y, double* dYx, double* dYy,
-                                     double* dYz) {
-  const double k0 = 0.28209479177387814, k1 = 0.4886025119029199, k2 = 1.0925484305920792,
-               k3 = 0.31539156525252005, k4 = 0.5462742152960396, k5 = 0.5900435899266435,
-               k6 = 2.890611442640554, k7 = 0.4570457994644658, k8 = 0.3731763325901154, k9 = 1.445305721320277;
-  for (int l = 0; l < 16; ++l) Y[l] = dYx[l] = dYy[l] = dYz[l] = 0.0;
+template <typename F>
+__device__ inline void sh_basis_grad(int deg, F x, F y, F z, F* Y, F* dYx, F* dYy, F* dYz) {
+  const F k0 = (F)0.28209479177387814, k1 = (F)0.4886025119029199, k2 = (F)1.0925484305920792,
+          k3 = (F)0.31539156525252005, k4 = (F)0.5462742152960396, k5 = (F)0.5900435899266435,
+          k6 = (F)2.890611442640554, k7 = (F)0.4570457994644658, k8 = (F)0.3731763325901154, k9 = (F)1.445305721320277;
+  for (int l = 0; l < 16; ++l) Y[l] = dYx[l] = dYy[l] = dYz[l] = (F)0;
   Y[0] = k0;
   if (deg < 1) return;
   Y[1] = k1 * y; dYy[1] = k1;
@@ -306,8 +322,9 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(const float* __restric
   float shc[48];
   for (int k = 0; k < nb * 3; ++k) shc[k] = soa[(kRowSH + k) * np + i];
 
-  double gmu[3] = {0, 0, 0}, gSig[9] = {0}, glogit = 0, gsh[48];
-  for (int k = 0; k < 48; ++k) gsh[k] = 0.0;
+  double gmu[3] = {0, 0, 0}, gSig[9] = {0}, glogit = 0;
+  float gsh[48];  // FP32: the SH colour itself is FP32
+  for (int k = 0; k < 48; ++k) gsh[k] = 0.0f;
   const double ks = 0.72134752044448170368;
   const double f = pc.focal;
   for (int v = 0; v < pc.N; ++v) {
@@ -376,17 +393,19 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(const float* __restric
     for (int k = 0; k < 3; ++k) gmu[k] += W[k] * gX + W[3 + k] * gY + W[6 + k] * gZ;
     // opacity
     glogit += (double)ag[5] * opac * (1.0 - opac);
-    // colour: rgb = max(0, SH(dir) + 0.5), dir = (mu - eye) / |mu - eye|
-    const double d[3] = {mu[0] - cam[12], mu[1] - cam[13], mu[2] - cam[14]};
-    const double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    const double dir[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
-    double Yb[16], dYx[16], dYy[16], dYz[16];
-    sh_basis_grad(deg, dir[0], dir[1], dir[2], Yb, dYx, dYy, dYz);
-    double gdir[3] = {0, 0, 0};
+    // colour: rgb = max(0, SH(dir) + 0.5), dir = (mu - eye) / |mu - eye|, in FP32 with the forward's operations
+    // (the clamp decision must be the forward's)
+    const float dx = (float)(mu[0] - cam[12]), dy = (float)(mu[1] - cam[13]), dz = (float)(mu[2] - cam[14]);
+    const float dn = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float idn = 1.0f / dn;
+    const float dir[3] = {dx * idn, dy * idn, dz * idn};
+    float Yb[16], dYx[16], dYy[16], dYz[16];
+    sh_basis_grad<float>(deg, dir[0], dir[1], dir[2], Yb, dYx, dYy, dYz);
+    float gdir[3] = {0.0f, 0.0f, 0.0f};
     for (int c = 0; c < 3; ++c) {
-      const double gcol = ag[6 + c];
-      if (gcol == 0.0) continue;
-      if (!(raw_colour_f32(deg, (float)dir[0], (float)dir[1], (float)dir[2], shc, c) > 0.0f)) continue;
+      const float gcol = ag[6 + c];
+      if (gcol == 0.0f) continue;
+      if (!(raw_colour_f32(deg, dir[0], dir[1], dir[2], shc, c) > 0.0f)) continue;
       for (int l = 0; l < nb; ++l) {
         gsh[l * 3 + c] += gcol * Yb[l];
         gdir[0] += gcol * shc[l * 3 + c] * dYx[l];
@@ -394,8 +413,8 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(const float* __restric
         gdir[2] += gcol * shc[l * 3 + c] * dYz[l];
       }
     }
-    const double gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
-    for (int k = 0; k < 3; ++k) gmu[k] += (gdir[k] - gd * dir[k]) / dn;
+    const float gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+    for (int k = 0; k < 3; ++k) gmu[k] += (double)((gdir[k] - gd * dir[k]) / dn);
   }
   // Sigma = R diag(s^2) R^T: dL/dR = 2 G R S^2 (G symmetrised), dL/ds^2_k = (R^T G R)_kk
   double Gs[9];
@@ -427,7 +446,7 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(const float* __restric
   for (int k = 0; k < 4; ++k) g_quats[i * 4 + k] = (float)((dq[k] - dqh * qh[k]) / qnorm);
   for (int k = 0; k < 3; ++k) g_means[i * 3 + k] = (float)gmu[k];
   g_logits[i] = (float)glogit;
-  for (int k = 0; k < 48; ++k) g_sh[i * 48 + k] = (float)gsh[k];
+  for (int k = 0; k < 48; ++k) g_sh[i * 48 + k] = gsh[k];
 }
 
 }  // namespace
