@@ -21,7 +21,6 @@
 namespace dl {
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kG = 9;  // gradient components per (view, Gaussian): u, v, A, B, C, o, r, g, b
 
 __device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
@@ -53,8 +52,8 @@ __device__ inline float wave_reduce9(const float* g, int lane, int* index) {
   return w;
 }
 
-template <int RPT>
-__global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __restrict__ rec,
+template <int RPT, int NT>
+__global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict__ rec,
                                                              const uint32_t* __restrict__ tile_start,
                                                              const uint32_t* __restrict__ gidx,
                                                              const uint32_t* __restrict__ sorted,
@@ -63,9 +62,9 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
                                                              BlendChunk bk, uint8_t* __restrict__ alive,
                                                              float4* __restrict__ state, const float* __restrict__ fwd,
                                                              const float* __restrict__ gout, float* __restrict__ acc) {
-  __shared__ float4 sm[kThreads * kRecF4];
-  __shared__ uint32_t sg[kThreads];                 // Gaussian index of each staged entry
-  __shared__ float part[kThreads / 64][kThreads][kG];  // per-wavefront sums per staged entry
+  __shared__ float4 sm[NT * kRecF4];
+  __shared__ uint32_t sg[NT];          // Gaussian index of each staged entry
+  __shared__ float part[NT][kG];       // workgroup sums per staged entry (wavefront sums added in LDS)
   const uint32_t wi = xcd_remap(blockIdx.x, gridDim.x);
   const int v = (int)(wi / (uint32_t)bc.T);
   const int t = (int)(wi - (uint32_t)v * (uint32_t)bc.T);
@@ -84,7 +83,7 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
   bool live[RPT];
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int idx = threadIdx.x + j * kThreads;
+    const int idx = threadIdx.x + j * NT;
     const bool valid = idx < nr;
     int lx = 0, ly = 0;
     uint32_t mask = 0;
@@ -124,8 +123,8 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
   const int64_t NG = (int64_t)bc.N * bc.G;
   const float ln2 = 0.69314718055994531f;
 
-  for (uint32_t base = ls; base < le; base += kThreads) {
-    const int n = (int)min((uint32_t)kThreads, le - base);
+  for (uint32_t base = ls; base < le; base += NT) {
+    const int n = (int)min((uint32_t)NT, le - base);
     if ((int)threadIdx.x < n) {
       const uint32_t rk = gidx[base + threadIdx.x];
       const float4* src = vrec + (int64_t)rk * kRecF4;
@@ -137,7 +136,7 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
       sm[threadIdx.x * kRecF4 + 2] = r2;
       sg[threadIdx.x] = sorted[vG + rk];
     }
-    for (int i = threadIdx.x; i < (kThreads / 64) * kThreads * kG; i += kThreads) (&part[0][0][0])[i] = 0.0f;
+    for (int i = threadIdx.x; i < NT * kG; i += NT) (&part[0][0])[i] = 0.0f;
     __syncthreads();
     bool any = false;
 #pragma unroll
@@ -195,7 +194,7 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
         if (__ballot(any_take) != 0ull) {
           int c;
           const float s = wave_reduce9(gr, lane, &c);
-          if ((lane & 3) == 0 && c < kG) part[w][k][c] = s;
+          if ((lane & 3) == 0 && c < kG && s != 0.0f) atomicAdd(&part[k][c], s);
         }
         if (__ballot(any_live) == 0ull) break;
       }
@@ -206,9 +205,7 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
       const uint32_t g = sg[threadIdx.x];
 #pragma unroll
       for (int c = 0; c < kG; ++c) {
-        float s = 0.0f;
-#pragma unroll
-        for (int i = 0; i < kThreads / 64; ++i) s += part[i][threadIdx.x][c];
+        const float s = part[threadIdx.x][c];
         if (s != 0.0f) atomicAdd(&acc[(int64_t)c * NG + vG + g], s);
       }
     }
@@ -224,7 +221,7 @@ __global__ __launch_bounds__(kThreads) void blend_bwd_kernel(const float4* __res
   if (!tile_live && threadIdx.x == 0) alive[vt] = 0;
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int idx = threadIdx.x + j * kThreads;
+    const int idx = threadIdx.x + j * NT;
     if (idx < nr && !bk.last && tile_live) state[gid[j]] = make_float4(live[j] ? Tr[j] : -Tr[j], C0[j], C1[j], C2[j]);
   }
 }
@@ -457,21 +454,36 @@ hipError_t launch_blend_backward(const float4* rec, const uint32_t* tile_start, 
                                  const float* fwd, const float* gout, float* acc, hipStream_t s) {
   const unsigned nb = (unsigned)((int64_t)bc.N * bc.T);
   if (nb == 0) return hipSuccess;
-  int rpt = 1;
-  while (rpt * kThreads < max_rays) rpt *= 2;
-#define DL_BWD_CASE(R)                                                                                          \
+  // the forward blend's workgroup shape: 256 lanes with up to 4 rays each, else 512 lanes with up to 8
+  const bool wide = max_rays > 4 * 256;
+  const int lanes = wide ? 512 : 256;
+  const int rpt = std::max(1, (max_rays + lanes - 1) / lanes);
+#define DL_BWD_CASE(R, L)                                                                                       \
   case R:                                                                                                      \
-    hipLaunchKernelGGL((blend_bwd_kernel<R>), dim3(nb), dim3(kThreads), 0, s, rec, tile_start, gidx, sorted,  \
+    hipLaunchKernelGGL((blend_bwd_kernel<R, L>), dim3(nb), dim3(L), 0, s, rec, tile_start, gidx, sorted,      \
                        ray_off, ray_ent, bc, bk, alive, state, fwd, gout, acc);                                \
     break;
-  switch (rpt) {
-    DL_BWD_CASE(1)
-    DL_BWD_CASE(2)
-    DL_BWD_CASE(4)
-    DL_BWD_CASE(8)
-    DL_BWD_CASE(16)
-    default:
-      return hipErrorInvalidValue;
+  if (!wide) {
+    switch (rpt) {
+      DL_BWD_CASE(1, 256)
+      DL_BWD_CASE(2, 256)
+      DL_BWD_CASE(3, 256)
+      DL_BWD_CASE(4, 256)
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else {
+    switch (rpt) {
+      DL_BWD_CASE(2, 512)
+      DL_BWD_CASE(3, 512)
+      DL_BWD_CASE(4, 512)
+      DL_BWD_CASE(5, 512)
+      DL_BWD_CASE(6, 512)
+      DL_BWD_CASE(7, 512)
+      DL_BWD_CASE(8, 512)
+      default:
+        return hipErrorInvalidValue;
+    }
   }
 #undef DL_BWD_CASE
   return hipGetLastError();
