@@ -89,21 +89,48 @@ struct WaveBin {
 // tile rectangle, and then walks the flattened list of (Gaussian, tile of its rectangle) pairs 64 at a time,
 // so that a large splat is shared by all lanes instead of stalling one.  Pairs are visited Gaussian by
 // Gaussian in rank order, and the hits of each step are compacted with a ballot, so the wavefront's keys come
-// out in rank order within every tile.  COUNT stores the number of keys of each wavefront; EMIT writes them
-// from the wavefront's scanned offset.  A view none of whose tiles is live (`live`, chunks after the first)
+// out in rank order within every tile.  A view none of whose tiles is live (`live`, chunks after the first)
 // produces no keys and reads no records.
-template <bool EMIT>
+//
+// Two ways to turn the hits into (view, tile) lists:
+//   !TABLE: COUNT stores the number of keys of each wavefront; EMIT writes (tile, rank) pairs from the
+//           wavefront's scanned offset, in emission order, and a stable partition by tile follows.
+//   TABLE:  COUNT stores, for every wavefront w and tile t of view v, the number of its hits in t at
+//           table[base_v + t * nw_v + w] (nw_v = wavefronts of the view, a multiple of 4, base_v = T * sum of nw
+//           over earlier views); scanned in that order, the table gives each wavefront its first slot in every
+//           tile's final list, so EMIT writes the ranks straight into the lists: no partition.  Lanes of one step
+//           that hit the same tile take consecutive slots in lane order (found with one ballot per tile-index
+//           bit), which is rank order, since every Gaussian's tiles are distinct.  The tile counters of the four
+//           wavefronts of a workgroup live in LDS as [tile][wavefront] (T <= kTableMaxTiles), so that the
+//           workgroup moves them to and from the table as one 16-byte access per tile.
+template <bool EMIT, bool TABLE>
 __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ vis_count,
                                                   const uint32_t* __restrict__ live, BlendConst bc, ChunkArgs ch,
                                                   const uint8_t* __restrict__ alive, uint32_t* __restrict__ counts,
                                                   unsigned long long* __restrict__ total,
                                                   const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ vals) {
+                                                  uint32_t* __restrict__ vals, const uint32_t* __restrict__ tab_base) {
   __shared__ WaveBin wb[4];
   __shared__ unsigned long long part[4];
+  __shared__ uint4 tcnt_s[TABLE ? kTableMaxTiles : 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   WaveBin& W = wb[w];
-  const int v = blockIdx.y;
+  uint32_t* tc = reinterpret_cast<uint32_t*>(tcnt_s);  // tc[4 t + w]: wavefront w's counter of tile t
+  // TABLE: a one-dimensional grid in which all workgroups of view v have the same index modulo 8, so that they
+  // run on one XCD (workgroups are handed to the 8 XCDs in turn) and the scattered writes into the view's
+  // table and lists merge in that XCD's L2.  Otherwise blockIdx.y is the view.
+  int v, bx, gx;
+  if (TABLE) {
+    gx = (int)ch.tgx;
+    const int slot = (int)(blockIdx.x >> 3), q = slot / gx;
+    bx = slot - q * gx;
+    v = (int)(blockIdx.x & 7) + 8 * q;
+    if (v >= bc.N) return;
+  } else {
+    v = blockIdx.y;
+    bx = blockIdx.x;
+    gx = gridDim.x;
+  }
   const int64_t nv = vis_count[v];
   const int64_t fv = ch.front ? (int64_t)ch.front[v] : 0;
   int64_t lo, hi;
@@ -120,16 +147,80 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
   const int64_t groups = view_live ? (hi - lo + 255) / 256 : 0;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const uint8_t* al = alive ? alive + (int64_t)v * bc.T : nullptr;
-  if (!EMIT)  // the count pass owes a zero to every wavefront slot no group covers
-    for (int64_t j = groups * 4 + (int64_t)blockIdx.x * 256 + threadIdx.x; j < ch.wstride;
-         j += (int64_t)gridDim.x * 256)
+  const int T = bc.T;
+  const int64_t nw = 4 * groups;  // TABLE: wavefront slots of this view
+  const int64_t tbase = TABLE ? (int64_t)tab_base[v] : 0;
+  int tbits = 0;
+  while ((1 << tbits) < T) ++tbits;
+  if (!EMIT && !TABLE)  // the count pass owes a zero to every wavefront slot no group covers
+    for (int64_t j = groups * 4 + (int64_t)bx * 256 + threadIdx.x; j < ch.wstride; j += (int64_t)gx * 256)
       counts[(int64_t)v * ch.wstride + j] = 0;
   unsigned long long block_sum = 0;
+
+  // Pair p of the wavefront's flattened (Gaussian, tile) list: its Gaussian's lane i, tile t, and whether the
+  // Gaussian's cutoff ellipse reaches a pixel centre of the (live) tile.  Branch-free, so that the two pairs of
+  // a step are computed side by side.
+  auto locate = [&](uint32_t p, uint32_t S, int& i, int& t) -> bool {
+    const uint32_t pc = min(p, S - 1);
+    i = 0;
+    // the last lane i with pre[i] <= pc (it has a non-empty rectangle)
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+      const uint32_t pv = W.pre[i + step < 64 ? i + step : 63];
+      i = (i + step < 64 && pv <= pc) ? i + step : i;
+    }
+    const int q = (int)(pc - W.pre[i]);
+    const int wr = W.wr[i];
+    const int row = q / wr;
+    const int tx = W.tx0[i] + (q - row * wr), ty = W.ty0[i] + row;
+    t = ty * bc.ntx + tx;
+    const float xlo = tx * bc.tw + 0.5f, xhi = min((tx + 1) * bc.tw, bc.W) - 0.5f;
+    const float ylo = ty * bc.th + 0.5f, yhi = min((ty + 1) * bc.th, bc.H) - 0.5f;
+    const float rr[8] = {W.u[i], W.v[i], W.A[i], W.B[i], W.C[i], W.qlim[i], 0.f, 0.f};
+    bool hit = p < S && tile_touch(rr, W.hA[i], W.hC[i], xlo, xhi, ylo, yhi);
+    if (al) hit = hit && al[t];
+    return hit;
+  };
+  // One step's hits in lane order: keys (!TABLE) or ranks into the lists (TABLE EMIT), or counts.
+  uint32_t pos = 0;  // !TABLE: next key of this wavefront
+  auto record = [&](bool hit, int i, int t, int64_t r) {
+    const uint64_t bal = __ballot(hit);
+    if (TABLE) {
+      if (!EMIT) {
+        if (hit) atomicAdd(&tc[4 * t + w], 1u);
+      } else if (bal) {
+        // lanes hitting the same tile as this one
+        uint64_t m = bal;
+        for (int b = 0; b < tbits; ++b) {
+          const bool bit = (t >> b) & 1;
+          const uint64_t bb = __ballot(bit);
+          m &= bit ? bb : ~bb;
+        }
+        const uint32_t k = (uint32_t)__popcll(m & below);
+        if (hit) {
+          const uint32_t at = tc[4 * t + w] + k;
+          if (at < ch.cap) vals[at] = (uint32_t)(r - lane + i);  // depth rank of the Gaussian in lane i
+          if (k == 0) tc[4 * t + w] = at + (uint32_t)__popcll(m);
+        }
+      }
+    } else {
+      if (EMIT && hit) {
+        const uint32_t at = pos + (uint32_t)__popcll(bal & below);
+        if (at < ch.cap) {
+          keys[at] = (uint32_t)t;  // the view is the segment: keys of view v lie in its scanned range
+          vals[at] = (uint32_t)(r - lane + i);  // depth rank of the Gaussian in lane i
+        }
+      }
+      pos += (uint32_t)__popcll(bal);
+    }
+  };
+
   // the chunk's groups, strided over the view's workgroups
-  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+  for (int64_t grp = bx; grp < groups; grp += gx) {
     const int64_t idx = grp * 256 + threadIdx.x;
-    const int64_t wslot = (int64_t)v * ch.wstride + (idx >> 6);
-    const bool wave_in = (idx >> 6) < ch.wstride;
+    const int64_t wv = idx >> 6;  // wavefront index within the view's chunk
+    const int64_t wslot = (int64_t)v * ch.wstride + wv;
+    const bool wave_in = wv < ch.wstride;
     const int64_t r = lo + idx;
     uint32_t nt = 0;
     if (r < hi) {
@@ -154,48 +245,36 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
     const uint32_t incl = wave_incl_scan_u32(nt, lane);
     W.pre[lane] = incl - nt;
     const uint32_t S = __shfl(incl, 63, 64);
+    if (TABLE) {
+      // the workgroup's counters (COUNT: zero) or next list slots (EMIT: the scanned table), 16 bytes per tile
+      const int64_t at = tbase + 4 * grp;
+      for (int tt = threadIdx.x; tt < T; tt += 256)
+        tcnt_s[tt] = EMIT ? *reinterpret_cast<const uint4*>(offsets + at + (int64_t)tt * nw) : make_uint4(0, 0, 0, 0);
+    }
     __syncthreads();
 
-    uint32_t pos = EMIT && wave_in && S ? offsets[wslot] : 0u;  // next key of this wavefront
-    for (uint32_t s0 = 0; s0 < S; s0 += 64) {
-      const uint32_t p = s0 + (uint32_t)lane;
-      bool hit = false;
-      int i = 0, t = 0;
-      if (p < S) {
-        // the Gaussian owning pair p: the last lane i with pre[i] <= p (it has a non-empty rectangle)
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1)
-          if (i + step < 64 && W.pre[i + step] <= p) i += step;
-        const int q = (int)(p - W.pre[i]);
-        const int wr = W.wr[i];
-        const int row = q / wr;
-        const int tx = W.tx0[i] + (q - row * wr), ty = W.ty0[i] + row;
-        t = ty * bc.ntx + tx;
-        hit = !al || al[t];
-        if (hit) {
-          const float xlo = tx * bc.tw + 0.5f, xhi = min((tx + 1) * bc.tw, bc.W) - 0.5f;
-          const float ylo = ty * bc.th + 0.5f, yhi = min((ty + 1) * bc.th, bc.H) - 0.5f;
-          const float rr[8] = {W.u[i], W.v[i], W.A[i], W.B[i], W.C[i], W.qlim[i], 0.f, 0.f};
-          hit = tile_touch(rr, W.hA[i], W.hC[i], xlo, xhi, ylo, yhi);
-        }
-      }
-      const uint64_t bal = __ballot(hit);
-      if (EMIT && hit) {
-        const uint32_t at = pos + (uint32_t)__popcll(bal & below);
-        if (at < ch.cap) {
-          keys[at] = (uint32_t)t;  // the view is the segment: keys of view v lie in its scanned range
-          vals[at] = (uint32_t)(r - lane + i);  // depth rank of the Gaussian in lane i
-        }
-      }
-      pos += (uint32_t)__popcll(bal);
+    if (!TABLE) pos = EMIT && wave_in && S ? offsets[wslot] : 0u;
+    for (uint32_t s0 = 0; s0 < S; s0 += 128) {
+      // two steps of 64 pairs side by side, recorded in order
+      int i0, t0, i1, t1;
+      const bool h0 = locate(s0 + (uint32_t)lane, S, i0, t0);
+      const bool h1 = locate(s0 + 64 + (uint32_t)lane, S, i1, t1);
+      record(h0, i0, t0, r);
+      if (s0 + 64 < S) record(h1, i1, t1, r);
     }
-    if (!EMIT && lane == 0) {
+    if (!TABLE && !EMIT && lane == 0) {
       if (wave_in) counts[wslot] = pos;
       block_sum += pos;
     }
-    __syncthreads();  // the wavefront staging is rewritten by the next group
+    __syncthreads();  // the counters are complete; the wavefront staging is rewritten by the next group
+    if (TABLE && !EMIT) {
+      const int64_t at = tbase + 4 * grp;
+      for (int tt = threadIdx.x; tt < T; tt += 256)
+        *reinterpret_cast<uint4*>(counts + at + (int64_t)tt * nw) = tcnt_s[tt];
+      __syncthreads();
+    }
   }
-  if (!EMIT) {
+  if (!TABLE && !EMIT) {
     if (lane == 0) part[w] = block_sum;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -203,6 +282,56 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
       if (sum) atomicAdd(total, sum);
     }
   }
+}
+
+// Chunk-0 layout of the table form: e0[v] = min(front[v], fcap) (the first chunk's end, where the second
+// starts), base[v] = T * sum over earlier views of nw = 4 ceil(e0 / 256) (wavefront slots, whole workgroups),
+// base[N] = the table's length.
+__global__ __launch_bounds__(256) void table_setup_kernel(const uint32_t* __restrict__ front, int N, int T,
+                                                          uint32_t fcap, uint32_t* __restrict__ e0,
+                                                          uint32_t* __restrict__ base) {
+  __shared__ uint32_t wsum[4];
+  const int v = threadIdx.x, lane = v & 63, w = v >> 6;
+  const uint32_t e = v < N ? min(front[v], fcap) : 0u;
+  const uint32_t nw = 4 * ((e + 255) / 256);
+  const uint32_t inc = wave_incl_scan_u32(nw, lane);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+  for (int i = 0; i < 4; ++i) {
+    if (i < w) before += wsum[i];
+    tot += wsum[i];
+  }
+  if (v < N) {
+    e0[v] = e;
+    base[v] = (uint32_t)T * (before + inc - nw);
+  }
+  if (v == 0) base[N] = (uint32_t)T * tot;
+}
+
+// List starts from the scanned table: start[v T + t] = scanned[base_v + t nw_v] (the slot of the view's first
+// wavefront in tile t), start[N T] = the key total; *max_total = max(*max_total, key total).  Starts are clamped
+// to the key capacity, as emission drops keys beyond it: a frame that overflows reads only written slots (and
+// is reported and rendered again).
+__global__ __launch_bounds__(256) void table_starts_kernel(const uint32_t* __restrict__ scanned,
+                                                           const uint32_t* __restrict__ base,
+                                                           const uint32_t* __restrict__ e0, int N, int T,
+                                                           const uint32_t* __restrict__ grand, uint32_t cap,
+                                                           unsigned long long* __restrict__ max_total,
+                                                           uint32_t* __restrict__ start) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t NT = (int64_t)N * T;
+  if (i > NT) return;
+  const uint32_t g = *grand;
+  if (i == NT) {
+    start[NT] = min(g, cap);
+    if (g > *max_total) *max_total = g;
+    return;
+  }
+  const int v = (int)(i / T), t = (int)(i - (int64_t)v * T);
+  const int64_t nw = 4 * (((int64_t)e0[v] + 255) / 256);
+  const int64_t k = (int64_t)base[v] + t * nw;
+  start[i] = min(k < (int64_t)base[N] ? scanned[k] : g, cap);
 }
 
 // Live tiles of each view (one workgroup per view), read by the binning of the next depth chunk.
@@ -247,8 +376,8 @@ hipError_t launch_bin_count(const float4* rec, const uint32_t* vis_count, const 
                             const ChunkArgs& ch, const uint8_t* alive, uint32_t* counts, unsigned long long* total,
                             hipStream_t s) {
   const dim3 grid(bin_blocks(ch), (unsigned)bc.N);
-  hipLaunchKernelGGL(bin_kernel<false>, grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, counts, total,
-                     nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL((bin_kernel<false, false>), grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, counts,
+                     total, nullptr, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -256,8 +385,48 @@ hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const u
                            const ChunkArgs& ch, const uint8_t* alive, const uint32_t* offsets, uint32_t* keys,
                            uint32_t* vals, hipStream_t s) {
   const dim3 grid(bin_blocks(ch), (unsigned)bc.N);
-  hipLaunchKernelGGL(bin_kernel<true>, grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, nullptr, nullptr,
-                     offsets, keys, vals);
+  hipLaunchKernelGGL((bin_kernel<true, false>), grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, nullptr,
+                     nullptr, offsets, keys, vals, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_setup(const uint32_t* front, int N, int T, uint32_t fcap, uint32_t* e0, uint32_t* base,
+                              hipStream_t s) {
+  if (N > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(table_setup_kernel, dim3(1), dim3(256), 0, s, front, N, T, fcap, e0, base);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_table_count(const float4* rec, const uint32_t* vis_count, const BlendConst& bc,
+                                  const ChunkArgs& ch, const uint8_t* alive, const uint32_t* base, uint32_t* table,
+                                  hipStream_t s) {
+  if (bc.T > kTableMaxTiles || !ch.first || !ch.front) return hipErrorInvalidValue;
+  ChunkArgs c = ch;
+  c.tgx = bin_blocks(ch);
+  const dim3 grid((unsigned)(8 * ((bc.N + 7) / 8) * c.tgx));
+  hipLaunchKernelGGL((bin_kernel<false, true>), grid, dim3(256), 0, s, rec, vis_count, nullptr, bc, c, alive, table,
+                     nullptr, nullptr, nullptr, nullptr, base);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_table_emit(const float4* rec, const uint32_t* vis_count, const BlendConst& bc,
+                                 const ChunkArgs& ch, const uint8_t* alive, const uint32_t* base,
+                                 const uint32_t* scanned, uint32_t* vals, hipStream_t s) {
+  if (bc.T > kTableMaxTiles || !ch.first || !ch.front) return hipErrorInvalidValue;
+  ChunkArgs c = ch;
+  c.tgx = bin_blocks(ch);
+  const dim3 grid((unsigned)(8 * ((bc.N + 7) / 8) * c.tgx));
+  hipLaunchKernelGGL((bin_kernel<true, true>), grid, dim3(256), 0, s, rec, vis_count, nullptr, bc, c, alive, nullptr,
+                     nullptr, scanned, nullptr, vals, base);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_starts(const uint32_t* scanned, const uint32_t* base, const uint32_t* e0, int N, int T,
+                               const uint32_t* grand, uint32_t cap, unsigned long long* max_total, uint32_t* start,
+                               hipStream_t s) {
+  const int64_t n = (int64_t)N * T + 1;
+  hipLaunchKernelGGL(table_starts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, scanned, base, e0, N, T,
+                     grand, cap, max_total, start);
   return hipGetLastError();
 }
 

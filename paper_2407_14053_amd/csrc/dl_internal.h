@@ -74,6 +74,7 @@ struct ChunkArgs {
   int64_t stride;   // item slots per view (a multiple of 64 is not required)
   int64_t wstride;  // wavefront slots per view: ceil(stride / 64)
   uint32_t cap;     // key capacity
+  int64_t tgx;      // workgroups per view of the table-form binning (set by its launchers)
 };
 
 // Per-chunk blend flags
@@ -169,6 +170,24 @@ hipError_t launch_bin_count(const float4* rec, const uint32_t* vis_count, const 
 hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const uint32_t* live, const BlendConst& bc,
                            const ChunkArgs& ch, const uint8_t* alive, const uint32_t* offsets, uint32_t* keys,
                            uint32_t* vals, hipStream_t s);
+// Table form of the first chunk's binning (T <= kTableMaxTiles): no partition, ranks written into the final
+// (view, tile) lists.  launch_table_setup: e0[v] = min(front[v], fcap) ends the first chunk (the second starts
+// there), base[v] = T * sum_{u < v} ceil(e0[u] / 64), base[N] = table length (N <= 256).  Count writes the
+// table [v][t][wavefront] from base[v]; after an exclusive scan of base[N] entries, emit writes the ranks of
+// chunk ranks [0, e0[v]) into vals (slots below cap), and launch_table_starts writes start[NT + 1] (list
+// bounds clamped to cap, start[NT] = *grand, the scan's total) and raises *max_total to the key total.
+constexpr int kTableMaxTiles = 1024;
+hipError_t launch_table_setup(const uint32_t* front, int N, int T, uint32_t fcap, uint32_t* e0, uint32_t* base,
+                              hipStream_t s);
+hipError_t launch_bin_table_count(const float4* rec, const uint32_t* vis_count, const BlendConst& bc,
+                                  const ChunkArgs& ch, const uint8_t* alive, const uint32_t* base, uint32_t* table,
+                                  hipStream_t s);
+hipError_t launch_bin_table_emit(const float4* rec, const uint32_t* vis_count, const BlendConst& bc,
+                                 const ChunkArgs& ch, const uint8_t* alive, const uint32_t* base,
+                                 const uint32_t* scanned, uint32_t* vals, hipStream_t s);
+hipError_t launch_table_starts(const uint32_t* scanned, const uint32_t* base, const uint32_t* e0, int N, int T,
+                               const uint32_t* grand, uint32_t cap, unsigned long long* max_total, uint32_t* start,
+                               hipStream_t s);
 // live[v] = live tiles of view v; *total = 0 (for the next chunk)
 hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, unsigned long long* total,
                             hipStream_t s);

@@ -350,6 +350,20 @@ int64_t chunk_stride(int64_t G, int c) {
   return G * (kChunkBounds[c + 1] - kChunkBounds[c]) / kChunkDen + 1;
 }
 
+// The first chunk uses the table form of binning (no tile partition) when a view has at most kTableMaxTiles
+// tiles; its table holds one count per (view, tile, wavefront of 64 ranks), at most kTableMaxEntries, so the
+// first chunk of each view is capped at fcap ranks (the second chunk starts where it ended).  0: partition form.
+constexpr int64_t kTableMaxEntries = 32ll << 20;
+uint32_t table_fcap(int N, int64_t G, int64_t T) {
+  if (T > kTableMaxTiles || N <= 0 || T <= 0) return 0;
+  const int64_t waves = std::max<int64_t>(1, kTableMaxEntries / (T * N));
+  return (uint32_t)std::min<int64_t>(std::max<int64_t>(G, 1), 64 * waves);
+}
+int64_t table_entries(int N, int64_t G, int64_t T) {
+  const uint32_t f = table_fcap(N, G, T);
+  return f ? T * N * 4 * (((int64_t)f + 255) / 256) : 0;  // wavefront slots in whole workgroups
+}
+
 // Device bytes of every per-frame buffer, in the order render_frame ensures them.
 constexpr int kFrameBufs = 26;
 struct FrameSizes {
@@ -368,6 +382,8 @@ FrameSizes frame_sizes(int N, int64_t G, int64_t NT, int64_t nstate, uint32_t ca
   int64_t max_stride = 0;
   for (int c = 0; c < kChunks; ++c) max_stride = std::max(max_stride, chunk_stride(G, c) + 64);
   z.max_wstride = (max_stride + 63) / 64;
+  const int64_t tab = table_entries(N, G, N ? NT / N : 0);
+  const int64_t ncounts = std::max<int64_t>((int64_t)N * z.max_wstride, tab + 1);
   const int64_t hs = std::max(std::max(radix_hist_size(G, N), depth_ranges_hist_size(G, N)), tile_partition_hist_size(N));
   const size_t v[kFrameBufs] = {
       (size_t)N * kCamDoubles * 8,                    // cameras
@@ -376,10 +392,10 @@ FrameSizes frame_sizes(int N, int64_t G, int64_t NT, int64_t nstate, uint32_t ca
       (size_t)NG * 8, (size_t)NG * 8,                 // depth keys (double-buffered)
       (size_t)NG * 4, (size_t)NG * 4,                 // Gaussian indices (double-buffered)
       256 * 4,                                        // visible counts
-      (size_t)N * z.max_wstride * 4,                  // per-wavefront key counts
+      (size_t)ncounts * 4,                            // per-wavefront key counts, or the first chunk's table
       (size_t)N * 4,                                  // live tiles per view
       (size_t)(3 * N + 2) * 4,                        // view key ranges and the partition layout
-      (size_t)(6 * N + 1) * 4,                        // fronts, sort ranges, rank ends, sort layout
+      (size_t)(8 * N + 2) * 4,                        // fronts, sort ranges, rank ends, sort layout, table layout
       (size_t)N * 8,                                  // front thresholds
       (size_t)front_hist_size(N) * 4,                 // front histogram
       (size_t)cap * 4, (size_t)cap * 4,               // tile keys (double-buffered)
@@ -389,7 +405,7 @@ FrameSizes frame_sizes(int N, int64_t G, int64_t NT, int64_t nstate, uint32_t ca
       (size_t)std::max<int64_t>(nstate, 1) * 16,      // ray state
       2 * 8,                                          // key totals
       (size_t)hs * 4,                                 // radix histograms
-      (size_t)(scan_partial_count(std::max<int64_t>(hs, N * z.max_wstride)) + 2) * 4,  // scan partials
+      (size_t)(scan_partial_count(std::max<int64_t>(hs, ncounts)) + 2) * 4,  // scan partials
       stats ? (size_t)kStatSlots * 3 * 8 : 0,         // work counters
       bwd ? (size_t)NG * 9 * 4 : 0};                  // backward accumulators
   for (int b = 0; b < kFrameBufs; ++b) z.bytes[b] = v[b];
@@ -497,6 +513,13 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
   const uint32_t* sorted = fl ? C->v32[0].as<uint32_t>() : C->v32[1].as<uint32_t>();
   HIP_TRY(launch_gather_records(C->rec.as<float4>(), sorted, nullptr, rank_hi, G, N, C->srec.as<float4>(), s));
+  // the first chunk's end per view (the table form caps it) and the table layout
+  const uint32_t fcap = table_fcap(N, G, tl.T);
+  const int64_t tab_n = table_entries(N, G, tl.T);
+  uint32_t* e0 = dlayout + 2 * N + 1;
+  uint32_t* tbase = e0 + N;
+  if (fcap) HIP_TRY(launch_table_setup(front, N, tl.T, fcap, e0, tbase, s));
+  const uint32_t* chunk_front = fcap ? e0 : front;
   C->end(mk, s);
 
   BlendConst bc{};
@@ -519,12 +542,12 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   unsigned long long* total = C->dtotal.as<unsigned long long>();
   for (int c = 0; c < kChunks; ++c) {
     C->chunk = c;
-    ChunkArgs ch;
+    ChunkArgs ch{};
     // the second chunk starts where the front ended, whatever fraction the front took
     ch.num_lo = c == 1 ? 0 : kChunkBounds[c];
     ch.num_hi = kChunkBounds[c + 1];
     ch.den = kChunkDen;
-    ch.front = front;
+    ch.front = chunk_front;
     ch.first = c == 0;
     ch.stride = chunk_stride(G, c);
     ch.wstride = (ch.stride + 63) / 64;
@@ -532,26 +555,49 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     const int64_t ncount = (int64_t)N * ch.wstride;
     // views with no live tile left produce no keys in this chunk (the first chunk has every tile live)
     const uint32_t* live = c > 0 ? C->live.as<uint32_t>() : nullptr;
-    mk = C->begin(DL_STAGE_BIN_COUNT, s);
-    HIP_TRY(launch_bin_count(C->srec.as<float4>(), C->vis.as<uint32_t>(), live, bc, ch, C->alive.as<uint8_t>(),
-                             C->counts.as<uint32_t>(), total, s));
-    C->end(mk, s);
-    mk = C->begin(DL_STAGE_SCAN, s);
-    HIP_TRY(exclusive_scan_u32(C->counts.as<uint32_t>(), C->counts.as<uint32_t>(), ncount, C->partial.as<uint32_t>(), s));
-    C->end(mk, s);
-    mk = C->begin(DL_STAGE_BIN_EMIT, s);
-    HIP_TRY(launch_bin_emit(C->srec.as<float4>(), C->vis.as<uint32_t>(), live, bc, ch, C->alive.as<uint8_t>(),
-                            C->counts.as<uint32_t>(), C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), s));
-    C->end(mk, s);
-    mk = C->begin(DL_STAGE_TILE_SORT, s);
-    HIP_TRY(launch_chunk_setup(C->counts.as<uint32_t>(), ch.wstride, N, total, total + 1, cap, C->vstart.as<uint32_t>(),
-                               C->vstart.as<uint32_t>() + (N + 1), s));
-    const uint32_t* svals = tile_partition(C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), C->bk[1].as<uint32_t>(),
-                                           C->bv[1].as<uint32_t>(), N, C->vstart.as<uint32_t>(), cap, tl.T,
-                                           C->hist.as<uint32_t>(), C->partial.as<uint32_t>(),
-                                           C->vstart.as<uint32_t>() + (N + 1), C->tstart.as<uint32_t>(), s, &e);
-    if (e != hipSuccess) return fail(DL_EHIP, std::string("tile partition: ") + hipGetErrorString(e));
-    C->end(mk, s);
+    const uint32_t* svals;
+    if (c == 0 && fcap) {
+      // table form: counts per (view, tile, wavefront), scan, ranks written into the final lists
+      uint32_t* table = C->counts.as<uint32_t>();
+      mk = C->begin(DL_STAGE_BIN_COUNT, s);
+      // every tile with rays is live in the first chunk (tiles without rays have empty blend work)
+      HIP_TRY(launch_bin_table_count(C->srec.as<float4>(), C->vis.as<uint32_t>(), bc, ch, nullptr, tbase, table, s));
+      C->end(mk, s);
+      mk = C->begin(DL_STAGE_SCAN, s);
+      HIP_TRY(exclusive_scan_u32(table, table, tab_n, C->partial.as<uint32_t>(), s, tbase + N, 1));
+      C->end(mk, s);
+      mk = C->begin(DL_STAGE_BIN_EMIT, s);
+      HIP_TRY(launch_bin_table_emit(C->srec.as<float4>(), C->vis.as<uint32_t>(), bc, ch, nullptr, tbase, table,
+                                    C->bv[0].as<uint32_t>(), s));
+      C->end(mk, s);
+      mk = C->begin(DL_STAGE_TILE_SORT, s);
+      HIP_TRY(launch_table_starts(table, tbase, e0, N, tl.T, C->partial.as<uint32_t>() + scan_partial_count(tab_n),
+                                  cap, total + 1, C->tstart.as<uint32_t>(), s));
+      C->end(mk, s);
+      svals = C->bv[0].as<uint32_t>();
+    } else {
+      mk = C->begin(DL_STAGE_BIN_COUNT, s);
+      HIP_TRY(launch_bin_count(C->srec.as<float4>(), C->vis.as<uint32_t>(), live, bc, ch, C->alive.as<uint8_t>(),
+                               C->counts.as<uint32_t>(), total, s));
+      C->end(mk, s);
+      mk = C->begin(DL_STAGE_SCAN, s);
+      HIP_TRY(exclusive_scan_u32(C->counts.as<uint32_t>(), C->counts.as<uint32_t>(), ncount, C->partial.as<uint32_t>(),
+                                 s));
+      C->end(mk, s);
+      mk = C->begin(DL_STAGE_BIN_EMIT, s);
+      HIP_TRY(launch_bin_emit(C->srec.as<float4>(), C->vis.as<uint32_t>(), live, bc, ch, C->alive.as<uint8_t>(),
+                              C->counts.as<uint32_t>(), C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), s));
+      C->end(mk, s);
+      mk = C->begin(DL_STAGE_TILE_SORT, s);
+      HIP_TRY(launch_chunk_setup(C->counts.as<uint32_t>(), ch.wstride, N, total, total + 1, cap,
+                                 C->vstart.as<uint32_t>(), C->vstart.as<uint32_t>() + (N + 1), s));
+      svals = tile_partition(C->bk[0].as<uint32_t>(), C->bv[0].as<uint32_t>(), C->bk[1].as<uint32_t>(),
+                             C->bv[1].as<uint32_t>(), N, C->vstart.as<uint32_t>(), cap, tl.T, C->hist.as<uint32_t>(),
+                             C->partial.as<uint32_t>(), C->vstart.as<uint32_t>() + (N + 1), C->tstart.as<uint32_t>(),
+                             s, &e);
+      if (e != hipSuccess) return fail(DL_EHIP, std::string("tile partition: ") + hipGetErrorString(e));
+      C->end(mk, s);
+    }
     BlendChunk bk{c == 0, c == kChunks - 1};
     mk = C->begin(DL_STAGE_BLEND, s);
     if (bwd) {

@@ -53,27 +53,37 @@ __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* total) {
   return before + inc - x;
 }
 
-// The scans take a static length n, or a device length n_mul * *n_dev (<= n; grids are sized for n).
+// The scans take a static length n, or a device length n_mul * *n_dev (<= n; grids are sized for n).  Each
+// workgroup owns a tile of kScanTile items, read and written with consecutive lanes on consecutive items.
 __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
                                                                  const uint32_t* __restrict__ n_dev, int n_mul,
                                                                  uint32_t* __restrict__ partial) {
   if (n_dev) n = min(n, (int64_t)n_mul * *n_dev);
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n) {  // beyond a device length: nothing to sum
+    if (threadIdx.x == 0) partial[blockIdx.x] = 0;
+    return;
+  }
   uint32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanIPT; ++i)
-    if (base + i < n) s += in[base + i];
+  for (int i = 0; i < kScanIPT; ++i) {
+    const int64_t k = base + i * kThreads + threadIdx.x;
+    if (k < n) s += in[k];
+  }
   uint32_t total;
   block_excl_scan(s, &total);
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-// Second half of the scan: each tile adds the totals of the tiles before it (at most a few hundred, summed by
-// the workgroup) and scans its own items; the last tile writes the grand total to *grand.
+// Second half of the scan: each tile adds the totals of the tiles before it (at most a few thousand, summed by
+// the workgroup) and scans its own items, staged in LDS so that thread j scans items [16 j, 16 j + 16) of the
+// tile (one padding word every 16 keeps those reads free of bank conflicts); the last tile writes the grand
+// total to *grand.
 __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* in, uint32_t* out, int64_t n,
                                                                const uint32_t* __restrict__ n_dev, int n_mul,
                                                                const uint32_t* __restrict__ partial_in,
                                                                uint32_t* __restrict__ grand) {
+  __shared__ uint32_t st[kScanTile + kScanTile / kScanIPT];
   if (n_dev) n = min(n, (int64_t)n_mul * *n_dev);
   const int64_t np = (n + kScanTile - 1) / kScanTile;
   if ((int64_t)blockIdx.x >= np) {
@@ -84,20 +94,33 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* in,
   for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kThreads) pre += partial_in[i];
   uint32_t prefix;
   block_excl_scan(pre, &prefix);
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  auto pad = [](int j) { return j + (j >> 4); };
+#pragma unroll
+  for (int i = 0; i < kScanIPT; ++i) {
+    const int j = i * kThreads + threadIdx.x;
+    st[pad(j)] = base + j < n ? in[base + j] : 0u;
+  }
+  __syncthreads();
   uint32_t v[kScanIPT];
   uint32_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanIPT; ++i) {
-    v[i] = base + i < n ? in[base + i] : 0u;
+    v[i] = st[pad(threadIdx.x * kScanIPT + i)];
     s += v[i];
   }
   uint32_t total;
   uint32_t run = block_excl_scan(s, &total) + prefix;
 #pragma unroll
   for (int i = 0; i < kScanIPT; ++i) {
-    if (base + i < n) out[base + i] = run;
+    st[pad(threadIdx.x * kScanIPT + i)] = run;
     run += v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kScanIPT; ++i) {
+    const int j = i * kThreads + threadIdx.x;
+    if (base + j < n) out[base + j] = st[pad(j)];
   }
   if ((int64_t)blockIdx.x == np - 1 && threadIdx.x == 0) *grand = prefix + total;
 }
