@@ -35,31 +35,22 @@ __device__ inline bool tile_range(const float* r, const BlendConst& bc, TileRang
 }
 
 // Minimum over the tile's pixel centres (a rectangle) of Q = A dx^2 + B dx dy + C dy^2 about (u, v).
-// Zero when the centre lies inside; otherwise the minimum of the convex quadratic sits on an edge, where
-// it is a 1D quadratic minimised at the clamped stationary point (-B dx / 2C along a vertical edge,
-// -B dy / 2A along a horizontal one).  hA = 1 / 2A and hC = 1 / 2C are precomputed per Gaussian.
-__device__ inline bool tile_touch(const float* r, float hA, float hC, float xlo, float xhi, float ylo, float yhi) {
-  const float u = r[0], v = r[1], A = r[2], B = r[3], C = r[4], qlim = r[5];
+// Zero when the centre lies inside.  Otherwise the minimum of the convex quadratic lies on an edge that faces
+// the centre — the nearer of the two vertical edges or the nearer of the two horizontal ones — where it is a
+// 1D quadratic minimised at the clamped stationary point (-B dx / 2C along a vertical edge, -B dy / 2A along a
+// horizontal one).  Evaluating both facing edges (one may not face the centre: its value is still a value of
+// Q on the rectangle) gives the minimum without branches.  hA = 1 / 2A and hC = 1 / 2C per Gaussian.
+__device__ inline bool tile_touch(float u, float v, float A, float B, float C, float qlim, float hA, float hC,
+                                  float xlo, float xhi, float ylo, float yhi) {
   const float dxl = xlo - u, dxh = xhi - u, dyl = ylo - v, dyh = yhi - v;
-  if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) return true;
-  float qmin = 3.0e38f;
-  {
-    float dx = dxl;
-    float dy = fminf(fmaxf(-B * dx * hC, dyl), dyh);
-    qmin = fminf(qmin, A * dx * dx + B * dx * dy + C * dy * dy);
-    dx = dxh;
-    dy = fminf(fmaxf(-B * dx * hC, dyl), dyh);
-    qmin = fminf(qmin, A * dx * dx + B * dx * dy + C * dy * dy);
-  }
-  {
-    float dy = dyl;
-    float dx = fminf(fmaxf(-B * dy * hA, dxl), dxh);
-    qmin = fminf(qmin, A * dx * dx + B * dx * dy + C * dy * dy);
-    dy = dyh;
-    dx = fminf(fmaxf(-B * dy * hA, dxl), dxh);
-    qmin = fminf(qmin, A * dx * dx + B * dx * dy + C * dy * dy);
-  }
-  return qmin <= qlim * 1.001f + 1e-3f;
+  const bool inside = (dxl <= 0.0f) & (dxh >= 0.0f) & (dyl <= 0.0f) & (dyh >= 0.0f);
+  const float ex = dxl > 0.0f ? dxl : dxh;  // the facing vertical edge
+  const float ey = dyl > 0.0f ? dyl : dyh;  // the facing horizontal edge
+  const float dy1 = fminf(fmaxf(-B * ex * hC, dyl), dyh);
+  const float q1 = A * ex * ex + B * ex * dy1 + C * dy1 * dy1;
+  const float dx2 = fminf(fmaxf(-B * ey * hA, dxl), dxh);
+  const float q2 = A * dx2 * dx2 + B * dx2 * ey + C * ey * ey;
+  return inside | (fminf(q1, q2) <= qlim * 1.001f + 1e-3f);
 }
 
 // The geometric half of a record: u, v, A, B, C, Q_limit, ext_x, ext_y.
@@ -80,10 +71,32 @@ __device__ inline uint32_t wave_incl_scan_u32(uint32_t x, int lane) {
 
 // Per-wavefront staging of its 64 Gaussians.
 struct WaveBin {
-  float u[64], v[64], A[64], B[64], C[64], qlim[64], hA[64], hC[64];
+  float u[64], v[64], A[64], B[64], C[64], qlim[64], hA[64], hC[64], rw[64];
   int tx0[64], ty0[64], wr[64];
-  uint32_t pre[64];
+  uint32_t pre[64], nt[64];
+  int mark[128];  // per pair of a two-step window: the lane of the Gaussian whose pairs start there, or -1
 };
+
+// Orders the wavefront's LDS accesses: what a lane wrote before is seen by every lane of the wavefront after
+// (without it the compiler may take a lane's own earlier store as the value of its load).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Inclusive maximum over lanes 0..lane of the wavefront: DPP row shifts within each row of 16 lanes, then
+// the maxima of the rows below, read from lanes 15, 31 and 47; values are >= -1.
+__device__ inline int wave_max_scan(int x, int lane) {
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+  const int r0 = __builtin_amdgcn_readlane(x, 15);
+  const int r1 = max(r0, __builtin_amdgcn_readlane(x, 31));
+  const int r2 = max(r1, __builtin_amdgcn_readlane(x, 47));
+  return max(x, lane >= 48 ? r2 : lane >= 32 ? r1 : lane >= 16 ? r0 : -1);
+}
 
 // Each wavefront takes 64 consecutive depth ranks of one view (one per lane), computes every Gaussian's
 // tile rectangle, and then walks the flattened list of (Gaussian, tile of its rectangle) pairs 64 at a time,
@@ -99,8 +112,8 @@ struct WaveBin {
 //           table[base_v + t * nw_v + w] (nw_v = wavefronts of the view, a multiple of 4, base_v = T * sum of nw
 //           over earlier views); scanned in that order, the table gives each wavefront its first slot in every
 //           tile's final list, so EMIT writes the ranks straight into the lists: no partition.  Lanes of one step
-//           that hit the same tile take consecutive slots in lane order (found with one ballot per tile-index
-//           bit), which is rank order, since every Gaussian's tiles are distinct.  The tile counters of the four
+//           that hit the same tile take consecutive slots in lane order, which is rank order, since every
+//           Gaussian's tiles are distinct.  The tile counters of the four
 //           wavefronts of a workgroup live in LDS as [tile][wavefront] (T <= kTableMaxTiles), so that the
 //           workgroup moves them to and from the table as one 16-byte access per tile.
 template <bool EMIT, bool TABLE>
@@ -157,50 +170,64 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
       counts[(int64_t)v * ch.wstride + j] = 0;
   unsigned long long block_sum = 0;
 
-  // Pair p of the wavefront's flattened (Gaussian, tile) list: its Gaussian's lane i, tile t, and whether the
-  // Gaussian's cutoff ellipse reaches a pixel centre of the (live) tile.  Branch-free, so that the two pairs of
-  // a step are computed side by side.
-  auto locate = [&](uint32_t p, uint32_t S, int& i, int& t) -> bool {
-    const uint32_t pc = min(p, S - 1);
-    i = 0;
-    // the last lane i with pre[i] <= pc (it has a non-empty rectangle)
-#pragma unroll
-    for (int step = 32; step >= 1; step >>= 1) {
-      const uint32_t pv = W.pre[i + step < 64 ? i + step : 63];
-      i = (i + step < 64 && pv <= pc) ? i + step : i;
-    }
-    const int q = (int)(pc - W.pre[i]);
+  // Pair p of the wavefront's flattened (Gaussian, tile) list, owned by the Gaussian of lane i: its tile t
+  // (column tx, row ty of the Gaussian's rectangle, row-major), and whether the Gaussian's cutoff ellipse
+  // reaches a pixel centre of the (live) tile.  Branch-free, so that the two pairs of a step are computed side
+  // by side; pairs beyond the list are misses.
+  auto locate = [&](uint32_t p, int i, uint32_t S, int& t, int& tx, int& ty) -> bool {
+    const uint32_t q = p - W.pre[i];
     const int wr = W.wr[i];
-    const int row = q / wr;
-    const int tx = W.tx0[i] + (q - row * wr), ty = W.ty0[i] + row;
-    t = ty * bc.ntx + tx;
+    // row = q / wr from the rounded reciprocal, then one correction step
+    int row = (int)(((float)q + 0.5f) * W.rw[i]);
+    const int rem0 = (int)q - row * wr;
+    row += (rem0 >= wr ? 1 : 0) - (rem0 < 0 ? 1 : 0);
+    tx = W.tx0[i] + ((int)q - row * wr);
+    ty = W.ty0[i] + row;
+    const bool valid = (p < S) & (q < W.nt[i]);
+    t = valid ? ty * bc.ntx + tx : 0;
     const float xlo = tx * bc.tw + 0.5f, xhi = min((tx + 1) * bc.tw, bc.W) - 0.5f;
     const float ylo = ty * bc.th + 0.5f, yhi = min((ty + 1) * bc.th, bc.H) - 0.5f;
-    const float rr[8] = {W.u[i], W.v[i], W.A[i], W.B[i], W.C[i], W.qlim[i], 0.f, 0.f};
-    bool hit = p < S && tile_touch(rr, W.hA[i], W.hC[i], xlo, xhi, ylo, yhi);
+    bool hit = valid & tile_touch(W.u[i], W.v[i], W.A[i], W.B[i], W.C[i], W.qlim[i], W.hA[i], W.hC[i], xlo, xhi,
+                                  ylo, yhi);
     if (al) hit = hit && al[t];
     return hit;
   };
   // One step's hits in lane order: keys (!TABLE) or ranks into the lists (TABLE EMIT), or counts.
   uint32_t pos = 0;  // !TABLE: next key of this wavefront
-  auto record = [&](bool hit, int i, int t, int64_t r) {
+  auto record = [&](bool hit, int i, int t, int tx, int ty, uint32_t s0, uint32_t S, int64_t r) {
     const uint64_t bal = __ballot(hit);
     if (TABLE) {
       if (!EMIT) {
         if (hit) atomicAdd(&tc[4 * t + w], 1u);
       } else if (bal) {
-        // lanes hitting the same tile as this one
-        uint64_t m = bal;
-        for (int b = 0; b < tbits; ++b) {
-          const bool bit = (t >> b) & 1;
-          const uint64_t bb = __ballot(bit);
-          m &= bit ? bb : ~bb;
+        // k = hits of this step in the same tile on earlier lanes.  Those belong to earlier Gaussians of the
+        // step; when the step spans few Gaussians, each is tested for holding this tile within the step (its
+        // pair index and hit bit), else lanes are matched on the tile index, one ballot per bit.
+        uint32_t k = 0;
+        const int ia = __builtin_amdgcn_readlane(i, 0), ib = __builtin_amdgcn_readlane(i, 63);
+        if (ib - ia <= 4) {
+          for (int j = ia; j < ib; ++j) {
+            const int wrj = W.wr[j], dx = tx - W.tx0[j], dy = ty - W.ty0[j];
+            const uint32_t prej = W.pre[j];
+            const uint32_t ntj = W.pre[j + 1] - prej;  // j < ib <= 63
+            const uint32_t q = (uint32_t)dy * (uint32_t)wrj + (uint32_t)dx;
+            const uint32_t pp = prej + q - s0;  // the step offset of pair (j, this tile)
+            k += (j < i && (uint32_t)dx < (uint32_t)wrj && q < ntj && pp < 64u && ((bal >> (pp & 63u)) & 1ull))
+                     ? 1u : 0u;
+          }
+        } else {
+          uint64_t m = bal;
+          for (int b = 0; b < tbits; ++b) {
+            const bool bit = (t >> b) & 1;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+          }
+          k = (uint32_t)__popcll(m & below);
         }
-        const uint32_t k = (uint32_t)__popcll(m & below);
         if (hit) {
           const uint32_t at = tc[4 * t + w] + k;
           if (at < ch.cap) vals[at] = (uint32_t)(r - lane + i);  // depth rank of the Gaussian in lane i
-          if (k == 0) tc[4 * t + w] = at + (uint32_t)__popcll(m);
+          atomicAdd(&tc[4 * t + w], 1u);  // after every lane's read: the tile's slots advance by its hits
         }
       }
     } else {
@@ -239,11 +266,14 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
         W.tx0[lane] = tr.tx0;
         W.ty0[lane] = tr.ty0;
         W.wr[lane] = tr.tx1 - tr.tx0 + 1;
+        W.rw[lane] = 1.0f / (float)(tr.tx1 - tr.tx0 + 1);
         nt = (uint32_t)((tr.tx1 - tr.tx0 + 1) * (tr.ty1 - tr.ty0 + 1));
       }
     }
     const uint32_t incl = wave_incl_scan_u32(nt, lane);
-    W.pre[lane] = incl - nt;
+    const uint32_t my_pre = incl - nt;
+    W.pre[lane] = my_pre;
+    W.nt[lane] = nt;
     const uint32_t S = __shfl(incl, 63, 64);
     if (TABLE) {
       // the workgroup's counters (COUNT: zero) or next list slots (EMIT: the scanned table), 16 bytes per tile
@@ -254,13 +284,24 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
     __syncthreads();
 
     if (!TABLE) pos = EMIT && wave_in && S ? offsets[wslot] : 0u;
+    int carry = 0;  // owner of the pair before the window
     for (uint32_t s0 = 0; s0 < S; s0 += 128) {
-      // two steps of 64 pairs side by side, recorded in order
-      int i0, t0, i1, t1;
-      const bool h0 = locate(s0 + (uint32_t)lane, S, i0, t0);
-      const bool h1 = locate(s0 + 64 + (uint32_t)lane, S, i1, t1);
-      record(h0, i0, t0, r);
-      if (s0 + 64 < S) record(h1, i1, t1, r);
+      // two steps of 64 pairs side by side, recorded in order.  Owners: each Gaussian marks the pair where its
+      // list starts, and a running maximum over the window's pairs carries it to the pairs that follow.
+      wave_lds_sync();  // the previous window's reads of the marks are done
+      W.mark[lane] = -1;
+      W.mark[64 + lane] = -1;
+      wave_lds_sync();
+      if (nt > 0 && my_pre - s0 < 128u) W.mark[my_pre - s0] = lane;
+      wave_lds_sync();
+      const int i0 = max(wave_max_scan(W.mark[lane], lane), carry);
+      const int i1 = max(wave_max_scan(W.mark[64 + lane], lane), __builtin_amdgcn_readlane(i0, 63));
+      carry = __builtin_amdgcn_readlane(i1, 63);
+      int t0, x0, y0, t1, x1, y1;
+      const bool h0 = locate(s0 + (uint32_t)lane, i0, S, t0, x0, y0);
+      const bool h1 = locate(s0 + 64 + (uint32_t)lane, i1, S, t1, x1, y1);
+      record(h0, i0, t0, x0, y0, s0, S, r);
+      if (s0 + 64 < S) record(h1, i1, t1, x1, y1, s0 + 64, S, r);
     }
     if (!TABLE && !EMIT && lane == 0) {
       if (wave_in) counts[wslot] = pos;
