@@ -23,6 +23,10 @@ constexpr int kScanIPT = 16;
 constexpr int kScanTile = kThreads * kScanIPT;
 constexpr int kRows = 16;                        // rows of 64 items per wavefront per tile
 constexpr int kTile = kThreads * kRows;          // 4096 items per tile
+// The depth-order range sorts work on views' fronts of a few thousand items: smaller tiles give them more
+// workgroups (and less LDS each).
+constexpr int kDepthRows = 4;
+constexpr int kDepthTile = kThreads * kDepthRows;
 constexpr int kMaxBits = 9;    // digit width of the general sorts
 constexpr int kPartBits = 10;  // digit width of the tile partition (one pass for up to 1024 tiles per view)
 constexpr int kMaxRadix = 1 << kPartBits;
@@ -126,9 +130,9 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* in,
 }
 
 // Range [lo, hi) of block `bis` within a segment whose live length is n (ranges are whole tiles).
-__device__ inline void block_range(int64_t n, int bps, int bis, int64_t& lo, int64_t& hi) {
+__device__ inline void block_range(int64_t n, int bps, int bis, int64_t& lo, int64_t& hi, int tile) {
   int64_t per = (n + bps - 1) / bps;
-  per = (per + kTile - 1) / kTile * kTile;
+  per = (per + tile - 1) / tile * tile;
   lo = min((int64_t)bis * per, n);
   hi = min(lo + per, n);
 }
@@ -188,7 +192,7 @@ __device__ inline uint32_t digit_of(const SortArgs<K>& a, int seg, K k, uint32_t
   return a.split ? (uint32_t)(k >= a.split[seg]) : (uint32_t)(k >> a.shift) & dmask;
 }
 
-template <typename K, int RB>
+template <typename K, int RB, int ROWS>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(SortArgs<K> a) {
   __shared__ uint32_t h[kWaves][1 << RB];
   const int radix = 1 << a.bits;
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(SortArgs<K> a) {
   const int ndig = a.seg_lo ? a.ndig : radix;
   int64_t base, n, lo, hi;
   seg_range(a, seg, base, n);
-  block_range(n, bps, bis, lo, hi);
+  block_range(n, bps, bis, lo, hi, kThreads * ROWS);
   const K* kin = a.kin + base;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
     const K k = kin[i];
@@ -221,8 +225,11 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(SortArgs<K> a) {
   }
 }
 
-template <typename K, int RB>
+// ROWS rows of 64 items per wavefront make a tile of kThreads * ROWS items (the unit of the block ranges).
+template <typename K, int RB, int ROWS>
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) {
+  constexpr int kTile = kThreads * ROWS;
+  constexpr int kRows = ROWS;
   constexpr int DPT = (1 << RB) / kThreads;     // digits owned by each thread in the tile-local scan
   __shared__ uint32_t run[1 << RB];             // next output position per digit
   __shared__ uint32_t wc[kWaves][1 << RB];      // per-wavefront digit counts within the tile
@@ -239,7 +246,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(SortArgs<K> a) 
   const int ndig = a.seg_lo ? a.ndig : radix;
   int64_t base, n, lo, hi;
   seg_range(a, seg, base, n);
-  block_range(n, bps, bis, lo, hi);
+  block_range(n, bps, bis, lo, hi, kTile);
   const K* kin = a.kin + base;
   const uint32_t* vin = a.vin + base;
   K* kout = a.kout ? a.kout + base : nullptr;
@@ -367,13 +374,13 @@ __global__ __launch_bounds__(kThreads) void hist_starts_kernel(const uint32_t* _
 // items (at most bps_max, none for an empty segment) and their exclusive prefix pb (pb[n_seg] = total blocks).
 __device__ inline void range_layout(const uint32_t* __restrict__ seg_lo, const uint32_t* __restrict__ seg_hi,
                                     uint32_t cap, int n_seg, int bps_max, uint32_t* __restrict__ bpse,
-                                    uint32_t* __restrict__ pb) {
+                                    uint32_t* __restrict__ pb, int tile = kTile) {
   const int v = threadIdx.x;
   uint32_t b = 0;
   if (v < n_seg) {
     const uint32_t lo = min(seg_lo[v], cap), hi = min(seg_hi[v], cap);
     const uint32_t n = hi > lo ? hi - lo : 0u;
-    b = (uint32_t)min((int64_t)bps_max, ((int64_t)n + kTile - 1) / kTile);
+    b = (uint32_t)min((int64_t)bps_max, ((int64_t)n + tile - 1) / tile);
     bpse[v] = b;
   }
   uint32_t total;
@@ -385,8 +392,8 @@ __device__ inline void range_layout(const uint32_t* __restrict__ seg_lo, const u
 __global__ __launch_bounds__(kThreads) void part_layout_kernel(const uint32_t* __restrict__ seg_lo,
                                                                  const uint32_t* __restrict__ seg_hi, uint32_t cap,
                                                                  int n_seg, int bps_max, uint32_t* __restrict__ bpse,
-                                                                 uint32_t* __restrict__ pb) {
-  range_layout(seg_lo, seg_hi, cap, n_seg, bps_max, bpse, pb);
+                                                                 uint32_t* __restrict__ pb, int tile) {
+  range_layout(seg_lo, seg_hi, cap, n_seg, bps_max, bpse, pb, tile);
 }
 
 // List starts after a multi-pass partition: first position in segment v whose key is >= t.
@@ -534,7 +541,7 @@ __global__ __launch_bounds__(kThreads) void depth_ranges_kernel(int N, int64_t G
     }
   }
   __syncthreads();
-  range_layout(lo, hi, 0xffffffffu, N, bps_max, bpse, pb);
+  range_layout(lo, hi, 0xffffffffu, N, bps_max, bpse, pb, kDepthTile);
 }
 
 __global__ __launch_bounds__(kThreads) void lower_bounds_kernel(const uint32_t* __restrict__ keys,
@@ -560,6 +567,12 @@ int blocks_per_seg(int64_t seg_len, int n_seg) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, want));
 }
 
+int depth_blocks_per_seg(int64_t seg_len, int n_seg) {
+  int64_t tiles = (seg_len + kDepthTile - 1) / kDepthTile;
+  int64_t want = (4096 + n_seg - 1) / n_seg;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, want));
+}
+
 template <typename K>
 SortArgs<K> base_args(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, uint32_t* hist) {
   SortArgs<K> a{};
@@ -573,14 +586,14 @@ SortArgs<K> base_args(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout
 }
 
 // One pass: histogram, scan (of hsize entries, or of n_mul * *hsize_dev on the device), scatter.
-template <typename K, int RB>
+template <typename K, int RB, int ROWS = kRows>
 hipError_t launch_pass(const SortArgs<K>& a, int64_t nblocks, int64_t hsize, uint32_t* partial,
                        const uint32_t* hsize_dev, int n_mul, hipStream_t s) {
-  hipLaunchKernelGGL((radix_hist_kernel<K, RB>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((radix_hist_kernel<K, RB, ROWS>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = exclusive_scan_u32(a.hist, a.hist, hsize, partial, s, hsize_dev, n_mul)) != hipSuccess) return e;
-  hipLaunchKernelGGL((radix_scatter_kernel<K, RB>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((radix_scatter_kernel<K, RB, ROWS>), dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -621,13 +634,14 @@ int part_blocks_per_seg(int n_seg) { return std::max(1, (2048 + n_seg - 1) / n_s
 // computed here unless the caller has (layout_ready).  n_dig_one_pass > 0 makes a single pass use only that many
 // digits (a partition whose keys are below it); the keys of the last pass may be dropped.  Returns whether the
 // result is in (k1, v1).
-template <typename K, int RB>
+template <typename K, int RB, int ROWS = kRows>
 bool ranges_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int n_seg, const uint32_t* lo, const uint32_t* hi,
                  uint32_t cap, int bps, int bits_total, int n_dig_one_pass, bool keep_last_keys, uint32_t* hist,
                  uint32_t* partial, uint32_t* bpse, uint32_t* pb, bool layout_ready, hipStream_t s, hipError_t* err) {
   *err = hipSuccess;
   if (!layout_ready) {
-    hipLaunchKernelGGL(part_layout_kernel, dim3(1), dim3(kThreads), 0, s, lo, hi, cap, n_seg, bps, bpse, pb);
+    hipLaunchKernelGGL(part_layout_kernel, dim3(1), dim3(kThreads), 0, s, lo, hi, cap, n_seg, bps, bpse, pb,
+                       kThreads * ROWS);
     if ((*err = hipGetLastError()) != hipSuccess) return false;
   }
   const int64_t nblocks = (int64_t)bps * n_seg;
@@ -648,7 +662,8 @@ bool ranges_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int n_seg, const uint
     a.pb = pb;
     a.bpse = bpse;
     a.ndig = (passes == 1 && n_dig_one_pass > 0) ? n_dig_one_pass : (1 << pbits);
-    if ((*err = launch_pass<K, RB>(a, nblocks, (int64_t)n_seg * a.ndig * bps, partial, pb + n_seg, a.ndig, s)))
+    if ((*err = launch_pass<K, RB, ROWS>(a, nblocks, (int64_t)n_seg * a.ndig * bps, partial, pb + n_seg, a.ndig,
+                                         s)))
       return flipped;
     flipped = !flipped;
     shift += pbits;
@@ -703,7 +718,7 @@ bool radix_split_u64(uint64_t* k0, uint64_t* k1, uint32_t* v1, int64_t seg_len, 
 }
 
 int64_t depth_ranges_hist_size(int64_t seg_len, int n_seg) {
-  return (int64_t)blocks_per_seg(seg_len, n_seg) * n_seg * kMaxRadix;
+  return (int64_t)depth_blocks_per_seg(seg_len, n_seg) * n_seg * kMaxRadix;
 }
 
 bool depth_ranges_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
@@ -715,8 +730,9 @@ bool depth_ranges_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, i
   }
   // the layout comes with the ranges; the keys of the last pass are not needed, only the values (Gaussian
   // indices) in depth order
-  return ranges_sort<uint64_t, kMaxBits>(k0, v0, k1, v1, n_seg, lo, hi, 0xffffffffu, blocks_per_seg(seg_len, n_seg),
-                                         key_bits, 0, false, hist, partial, layout, layout + n_seg, true, s, err);
+  return ranges_sort<uint64_t, kMaxBits, kDepthRows>(k0, v0, k1, v1, n_seg, lo, hi, 0xffffffffu,
+                                                     depth_blocks_per_seg(seg_len, n_seg), key_bits, 0, false, hist,
+                                                     partial, layout, layout + n_seg, true, s, err);
 }
 
 int depth_sort_blocks(int64_t seg_len, int n_seg) { return blocks_per_seg(seg_len, n_seg); }
@@ -737,7 +753,7 @@ hipError_t launch_depth_ranges(int N, int64_t G, const uint32_t* n_vis, const ui
                                hipStream_t s) {
   if (N > kThreads) return hipErrorInvalidValue;
   hipLaunchKernelGGL(depth_ranges_kernel, dim3(1), dim3(kThreads), 0, s, N, G, n_vis, n_front, live, lo, hi, rank_hi,
-                     blocks_per_seg(G, N), layout, layout + N);
+                     depth_blocks_per_seg(G, N), layout, layout + N);
   return hipGetLastError();
 }
 
