@@ -116,7 +116,9 @@ bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int6
                     hipStream_t s, hipError_t* err);
 // One stable pass over full segments [s seg_len, (s + 1) seg_len) of keys k0 that leaves out items whose key is
 // drop_key and splits the rest into keys < thr[s] (first) and keys >= thr[s]; values are the items' positions in
-// their segment.  Results in (k1, v1); n_vis[s] = items kept, n_front[s] = items below thr[s].
+// their segment.  Results in (k1, v1); n_vis[s] = items kept, n_front[s] = items below thr[s].  hist holds
+// split_hist_size(seg_len, n_seg) entries.
+int64_t split_hist_size(int64_t seg_len, int n_seg);
 bool radix_split_u64(uint64_t* k0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg, const uint64_t* thr,
                      uint64_t drop_key, uint32_t* n_vis, uint32_t* n_front, uint32_t* hist, uint32_t* partial,
                      hipStream_t s, hipError_t* err);

@@ -384,7 +384,9 @@ FrameSizes frame_sizes(int N, int64_t G, int64_t NT, int64_t nstate, uint32_t ca
   z.max_wstride = (max_stride + 63) / 64;
   const int64_t tab = table_entries(N, G, N ? NT / N : 0);
   const int64_t ncounts = std::max<int64_t>((int64_t)N * z.max_wstride, tab + 1);
-  const int64_t hs = std::max(std::max(radix_hist_size(G, N), depth_ranges_hist_size(G, N)), tile_partition_hist_size(N));
+  const int64_t hs = std::max(std::max(std::max(radix_hist_size(G, N), depth_ranges_hist_size(G, N)),
+                                        tile_partition_hist_size(N)),
+                               split_hist_size(G, N));
   const size_t v[kFrameBufs] = {
       (size_t)N * kCamDoubles * 8,                    // cameras
       (size_t)NG * kRecF4 * 16,                       // records, projection order

@@ -505,6 +505,98 @@ __global__ __launch_bounds__(kThreads) void front_select_kernel(const uint32_t* 
 
 // Exact sizes after the split pass, from its scanned histogram ([segment][digit 0, 1][block], exclusive) and the
 // scan's grand total: n_vis = kept items, n_front = items of digit 0.
+// ---- the depth split ----
+// One stable pass drops each view's culled items and puts its front (keys below the view's threshold) before
+// its back.  Each wavefront owns a contiguous run of its view's items, runs in view order; the histogram holds,
+// per view, the kept fronts of every wavefront, then the kept backs ([view][2][wavefront]), so that after one
+// scan each wavefront streams its items straight into the two output runs, ranked by ballots: stable, with no
+// LDS staging.  The values are the items' positions in their view (Gaussian indices).
+__device__ inline void split_range(int64_t G, int wps, int k, int64_t& lo, int64_t& hi) {
+  int64_t per = (G + wps - 1) / wps;
+  per = (per + 63) / 64 * 64;
+  lo = min((int64_t)k * per, G);
+  hi = min(lo + per, G);
+}
+
+__device__ inline uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+__global__ __launch_bounds__(kThreads) void split_hist_kernel(const uint64_t* __restrict__ keys, int64_t G, int wps,
+                                                                const uint64_t* __restrict__ thr, uint64_t drop,
+                                                                uint32_t* __restrict__ hist) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int v = (int)(gw / wps), k = (int)(gw - (int64_t)v * wps);
+  int64_t lo, hi;
+  split_range(G, wps, k, lo, hi);
+  const uint64_t* kin = keys + (int64_t)v * G;
+  const uint64_t th = thr[v];
+  uint32_t c0 = 0, c1 = 0;
+  int64_t i = lo + lane;
+  for (; i + 192 < hi; i += 256) {  // four independent loads in flight
+    const uint64_t k0 = kin[i], k1 = kin[i + 64], k2 = kin[i + 128], k3 = kin[i + 192];
+    c0 += (k0 != drop && k0 < th) + (k1 != drop && k1 < th) + (k2 != drop && k2 < th) + (k3 != drop && k3 < th);
+    c1 += (k0 != drop && k0 >= th) + (k1 != drop && k1 >= th) + (k2 != drop && k2 >= th) + (k3 != drop && k3 >= th);
+  }
+  for (; i < hi; i += 64) {
+    const uint64_t k0 = kin[i];
+    c0 += k0 != drop && k0 < th;
+    c1 += k0 != drop && k0 >= th;
+  }
+  c0 = wave_sum_u32(c0);
+  c1 = wave_sum_u32(c1);
+  if (lane == 0) {
+    hist[(int64_t)v * 2 * wps + k] = c0;
+    hist[((int64_t)v * 2 + 1) * wps + k] = c1;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void split_scatter_kernel(const uint64_t* __restrict__ keys, int64_t G,
+                                                                   int wps, const uint64_t* __restrict__ thr,
+                                                                   uint64_t drop, const uint32_t* __restrict__ hist,
+                                                                   uint64_t* __restrict__ kout,
+                                                                   uint32_t* __restrict__ vout) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int v = (int)(gw / wps), k = (int)(gw - (int64_t)v * wps);
+  int64_t lo, hi;
+  split_range(G, wps, k, lo, hi);
+  const uint64_t* kin = keys + (int64_t)v * G;
+  uint64_t* ko = kout + (int64_t)v * G;
+  uint32_t* vo = vout + (int64_t)v * G;
+  const uint64_t th = thr[v];
+  // the scan runs over all views: positions are relative to the view's first entry
+  const uint32_t seg0 = hist[(int64_t)v * 2 * wps];
+  uint32_t p0 = hist[(int64_t)v * 2 * wps + k] - seg0;        // next front slot
+  uint32_t p1 = hist[((int64_t)v * 2 + 1) * wps + k] - seg0;  // next back slot
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int64_t i0 = lo; i0 < hi; i0 += 128) {
+    // two rows of 64 items side by side, written in order
+    const int64_t ia = i0 + lane, ib = i0 + 64 + lane;
+    const uint64_t ka = ia < hi ? kin[ia] : drop, kb = ib < hi ? kin[ib] : drop;
+    const bool fa = ka != drop && ka < th, ba = ka != drop && ka >= th;
+    const bool fb = kb != drop && kb < th, bb = kb != drop && kb >= th;
+    const uint64_t mfa = __ballot(fa), mba = __ballot(ba), mfb = __ballot(fb), mbb = __ballot(bb);
+    if (fa | ba) {
+      const uint32_t at = fa ? p0 + (uint32_t)__popcll(mfa & below) : p1 + (uint32_t)__popcll(mba & below);
+      ko[at] = ka;
+      vo[at] = (uint32_t)ia;
+    }
+    p0 += (uint32_t)__popcll(mfa);
+    p1 += (uint32_t)__popcll(mba);
+    if (fb | bb) {
+      const uint32_t at = fb ? p0 + (uint32_t)__popcll(mfb & below) : p1 + (uint32_t)__popcll(mbb & below);
+      ko[at] = kb;
+      vo[at] = (uint32_t)ib;
+    }
+    p0 += (uint32_t)__popcll(mfb);
+    p1 += (uint32_t)__popcll(mbb);
+  }
+}
+
 __global__ void split_counts_kernel(const uint32_t* __restrict__ hist, const uint32_t* __restrict__ grand, int n_seg,
                                     int bps, uint32_t* __restrict__ n_vis, uint32_t* __restrict__ n_front) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -696,23 +788,28 @@ bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int6
                                    err);
 }
 
+int split_waves_per_seg(int64_t seg_len, int n_seg) {
+  // about 8192 wavefronts in all, a multiple of the wavefronts of a workgroup, at most one per 64 items
+  int64_t w = std::max<int64_t>(1, std::min<int64_t>((8192 + n_seg - 1) / n_seg, (seg_len + 63) / 64));
+  return (int)((w + kWaves - 1) / kWaves * kWaves);
+}
+
+int64_t split_hist_size(int64_t seg_len, int n_seg) { return (int64_t)n_seg * 2 * split_waves_per_seg(seg_len, n_seg); }
+
 bool radix_split_u64(uint64_t* k0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg, const uint64_t* thr,
                      uint64_t drop_key, uint32_t* n_vis, uint32_t* n_front, uint32_t* hist, uint32_t* partial,
                      hipStream_t s, hipError_t* err) {
-  const int bps = blocks_per_seg(seg_len, n_seg);
-  SortArgs<uint64_t> a = base_args<uint64_t>(k0, nullptr, k1, v1, hist);
-  a.seg_len = seg_len;
-  a.bps = bps;
-  a.bits = 1;
-  a.ndig = 2;
-  a.split = thr;
-  a.drop = 1;
-  a.drop_key = drop_key;
-  a.iota = 1;  // the values are the Gaussian indices: positions in the view's segment
-  const int64_t hsize = (int64_t)n_seg * 2 * bps;
-  if ((*err = launch_pass<uint64_t, kMaxBits>(a, (int64_t)bps * n_seg, hsize, partial, nullptr, 1, s))) return true;
+  const int wps = split_waves_per_seg(seg_len, n_seg);
+  const int64_t hsize = split_hist_size(seg_len, n_seg);
+  const unsigned blocks = (unsigned)((int64_t)n_seg * wps / kWaves);
+  hipLaunchKernelGGL(split_hist_kernel, dim3(blocks), dim3(kThreads), 0, s, k0, seg_len, wps, thr, drop_key, hist);
+  if ((*err = hipGetLastError()) != hipSuccess) return true;
+  if ((*err = exclusive_scan_u32(hist, hist, hsize, partial, s)) != hipSuccess) return true;
+  hipLaunchKernelGGL(split_scatter_kernel, dim3(blocks), dim3(kThreads), 0, s, k0, seg_len, wps, thr, drop_key, hist,
+                     k1, v1);
+  if ((*err = hipGetLastError()) != hipSuccess) return true;
   hipLaunchKernelGGL(split_counts_kernel, dim3((unsigned)((n_seg + 63) / 64)), dim3(64), 0, s, hist,
-                     partial + scan_partial_count(hsize), n_seg, bps, n_vis, n_front);
+                     partial + scan_partial_count(hsize), n_seg, wps, n_vis, n_front);
   *err = hipGetLastError();
   return true;
 }
