@@ -122,10 +122,18 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
                                                   const uint8_t* __restrict__ alive, uint32_t* __restrict__ counts,
                                                   unsigned long long* __restrict__ total,
                                                   const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ vals, const uint32_t* __restrict__ tab_base) {
+                                                  uint32_t* __restrict__ vals, const uint32_t* __restrict__ tab_base,
+                                                  const uint32_t* __restrict__ grand) {
   __shared__ WaveBin wb[4];
   __shared__ unsigned long long part[4];
-  __shared__ uint4 tcnt_s[TABLE ? kTableMaxTiles : 1];
+  // TABLE (dynamic LDS, sized by the launch): the tile counters, [T] x 16 bytes; for EMIT also each tile's
+  // first slot of the workgroup's run in the lists, [T] x 4 bytes, and the workgroup's hits staged in list order
+  // as ranks relative to its first rank (below 256), kTableStage bytes, copied out run by run per group
+  extern __shared__ __align__(16) uint8_t bin_dyn[];
+  uint4* tcnt_s = reinterpret_cast<uint4*>(bin_dyn);
+  uint32_t* ppos = reinterpret_cast<uint32_t*>(bin_dyn + 16 * bc.T);
+  uint8_t* stage = bin_dyn + 20 * bc.T;
+  __shared__ uint32_t ssum[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   WaveBin& W = wb[w];
   uint32_t* tc = reinterpret_cast<uint32_t*>(tcnt_s);  // tc[4 t + w]: wavefront w's counter of tile t
@@ -192,9 +200,13 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
     if (al) hit = hit && al[t];
     return hit;
   };
+  // this lane's Gaussian's rectangle (first column and row, width), first pair and pair count, for other lanes
+  // to read with readlane
+  int g_tx0 = 0, g_ty0 = 0, g_wr = 1;
+  uint32_t g_pre = 0, g_nt = 0;
   // One step's hits in lane order: keys (!TABLE) or ranks into the lists (TABLE EMIT), or counts.
   uint32_t pos = 0;  // !TABLE: next key of this wavefront
-  auto record = [&](bool hit, int i, int t, int tx, int ty, uint32_t s0, uint32_t S, int64_t r) {
+  auto record = [&](bool hit, int i, int t, int tx, int ty, uint32_t s0, uint32_t S, int64_t r, bool staged) {
     const uint64_t bal = __ballot(hit);
     if (TABLE) {
       if (!EMIT) {
@@ -207,9 +219,10 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
         const int ia = __builtin_amdgcn_readlane(i, 0), ib = __builtin_amdgcn_readlane(i, 63);
         if (ib - ia <= 4) {
           for (int j = ia; j < ib; ++j) {
-            const int wrj = W.wr[j], dx = tx - W.tx0[j], dy = ty - W.ty0[j];
-            const uint32_t prej = W.pre[j];
-            const uint32_t ntj = W.pre[j + 1] - prej;  // j < ib <= 63
+            const int wrj = __builtin_amdgcn_readlane(g_wr, j);
+            const int dx = tx - __builtin_amdgcn_readlane(g_tx0, j), dy = ty - __builtin_amdgcn_readlane(g_ty0, j);
+            const uint32_t prej = __builtin_amdgcn_readlane(g_pre, j);
+            const uint32_t ntj = __builtin_amdgcn_readlane(g_nt, j);
             const uint32_t q = (uint32_t)dy * (uint32_t)wrj + (uint32_t)dx;
             const uint32_t pp = prej + q - s0;  // the step offset of pair (j, this tile)
             k += (j < i && (uint32_t)dx < (uint32_t)wrj && q < ntj && pp < 64u && ((bal >> (pp & 63u)) & 1ull))
@@ -226,7 +239,8 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
         }
         if (hit) {
           const uint32_t at = tc[4 * t + w] + k;
-          if (at < ch.cap) vals[at] = (uint32_t)(r - lane + i);  // depth rank of the Gaussian in lane i
+          if (staged) stage[at] = (uint8_t)(64 * w + i);  // the Gaussian in lane i, relative to the group
+          else if (at < ch.cap) vals[at] = (uint32_t)(r - lane + i);  // depth rank of the Gaussian in lane i
           atomicAdd(&tc[4 * t + w], 1u);  // after every lane's read: the tile's slots advance by its hits
         }
       }
@@ -268,18 +282,67 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
         W.wr[lane] = tr.tx1 - tr.tx0 + 1;
         W.rw[lane] = 1.0f / (float)(tr.tx1 - tr.tx0 + 1);
         nt = (uint32_t)((tr.tx1 - tr.tx0 + 1) * (tr.ty1 - tr.ty0 + 1));
+        g_tx0 = tr.tx0;
+        g_ty0 = tr.ty0;
+        g_wr = tr.tx1 - tr.tx0 + 1;
       }
     }
     const uint32_t incl = wave_incl_scan_u32(nt, lane);
     const uint32_t my_pre = incl - nt;
     W.pre[lane] = my_pre;
     W.nt[lane] = nt;
+    g_pre = my_pre;
+    g_nt = nt;
     const uint32_t S = __shfl(incl, 63, 64);
-    if (TABLE) {
-      // the workgroup's counters (COUNT: zero) or next list slots (EMIT: the scanned table), 16 bytes per tile
+    bool staged = false;
+    if (TABLE && !EMIT) {
+      // the workgroup's counters, 16 bytes per tile
+      for (int tt = threadIdx.x; tt < T; tt += 256) tcnt_s[tt] = make_uint4(0, 0, 0, 0);
+    }
+    if (TABLE && EMIT) {
+      // The workgroup's four wavefronts own consecutive slots of every tile's list: its run.  The scanned table
+      // gives each wavefront's first slot; the next entry (the next workgroup's, or the next tile's first) ends
+      // the run.  When all runs fit in LDS they are laid out back to back there (local slots), else the
+      // counters hold the list slots themselves.
       const int64_t at = tbase + 4 * grp;
-      for (int tt = threadIdx.x; tt < T; tt += 256)
-        tcnt_s[tt] = EMIT ? *reinterpret_cast<const uint4*>(offsets + at + (int64_t)tt * nw) : make_uint4(0, 0, 0, 0);
+      const int64_t tab_len = (int64_t)tab_base[bc.N];
+      uint32_t cnt[4];
+      uint32_t mine = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int tt = 4 * (int)threadIdx.x + q;
+        cnt[q] = 0;
+        if (tt < T) {
+          const uint4 o = *reinterpret_cast<const uint4*>(offsets + at + (int64_t)tt * nw);
+          const int64_t nx = at + (int64_t)tt * nw + 4;
+          const uint32_t e = nx < tab_len ? offsets[nx] : *grand;
+          tcnt_s[tt] = o;
+          ppos[tt] = o.x;
+          cnt[q] = e - o.x;
+        }
+        mine += cnt[q];
+      }
+      const uint32_t inc = wave_incl_scan_u32(mine, lane);
+      if (lane == 63) ssum[w] = inc;
+      __syncthreads();
+      uint32_t run = inc - mine, total = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q < w) run += ssum[q];
+        total += ssum[q];
+      }
+      staged = total <= (uint32_t)kTableStage;
+      if (staged) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int tt = 4 * (int)threadIdx.x + q;
+          if (tt < T) {
+            const uint4 o = tcnt_s[tt];
+            tcnt_s[tt] = make_uint4(run, run + (o.y - o.x), run + (o.z - o.x), run + (o.w - o.x));
+          }
+          run += cnt[q];
+        }
+      }
     }
     __syncthreads();
 
@@ -300,14 +363,25 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
       int t0, x0, y0, t1, x1, y1;
       const bool h0 = locate(s0 + (uint32_t)lane, i0, S, t0, x0, y0);
       const bool h1 = locate(s0 + 64 + (uint32_t)lane, i1, S, t1, x1, y1);
-      record(h0, i0, t0, x0, y0, s0, S, r);
-      if (s0 + 64 < S) record(h1, i1, t1, x1, y1, s0 + 64, S, r);
+      record(h0, i0, t0, x0, y0, s0, S, r, staged);
+      if (s0 + 64 < S) record(h1, i1, t1, x1, y1, s0 + 64, S, r, staged);
     }
     if (!TABLE && !EMIT && lane == 0) {
       if (wave_in) counts[wslot] = pos;
       block_sum += pos;
     }
     __syncthreads();  // the counters are complete; the wavefront staging is rewritten by the next group
+    if (TABLE && EMIT && staged) {
+      // copy the runs out: tile t's run is [end of tile t - 1's, the last wavefront's counter of tile t)
+      const uint32_t rank0 = (uint32_t)(lo + grp * 256);
+      for (int tt = threadIdx.x; tt < T; tt += 256) {
+        const uint32_t a = tt ? tc[4 * (tt - 1) + 3] : 0u, b = tc[4 * tt + 3];
+        const uint32_t p0 = ppos[tt];
+        for (uint32_t k = a; k < b; ++k)
+          if (p0 + (k - a) < ch.cap) vals[p0 + (k - a)] = rank0 + stage[k];
+      }
+      __syncthreads();
+    }
     if (TABLE && !EMIT) {
       const int64_t at = tbase + 4 * grp;
       for (int tt = threadIdx.x; tt < T; tt += 256)
@@ -418,7 +492,7 @@ hipError_t launch_bin_count(const float4* rec, const uint32_t* vis_count, const 
                             hipStream_t s) {
   const dim3 grid(bin_blocks(ch), (unsigned)bc.N);
   hipLaunchKernelGGL((bin_kernel<false, false>), grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, counts,
-                     total, nullptr, nullptr, nullptr, nullptr);
+                     total, nullptr, nullptr, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -427,7 +501,7 @@ hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const u
                            uint32_t* vals, hipStream_t s) {
   const dim3 grid(bin_blocks(ch), (unsigned)bc.N);
   hipLaunchKernelGGL((bin_kernel<true, false>), grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, nullptr,
-                     nullptr, offsets, keys, vals, nullptr);
+                     nullptr, offsets, keys, vals, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -445,20 +519,20 @@ hipError_t launch_bin_table_count(const float4* rec, const uint32_t* vis_count, 
   ChunkArgs c = ch;
   c.tgx = bin_blocks(ch);
   const dim3 grid((unsigned)(8 * ((bc.N + 7) / 8) * c.tgx));
-  hipLaunchKernelGGL((bin_kernel<false, true>), grid, dim3(256), 0, s, rec, vis_count, nullptr, bc, c, alive, table,
-                     nullptr, nullptr, nullptr, nullptr, base);
+  hipLaunchKernelGGL((bin_kernel<false, true>), grid, dim3(256), (size_t)16 * bc.T, s, rec, vis_count, nullptr, bc, c,
+                     alive, table, nullptr, nullptr, nullptr, nullptr, base, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_table_emit(const float4* rec, const uint32_t* vis_count, const BlendConst& bc,
                                  const ChunkArgs& ch, const uint8_t* alive, const uint32_t* base,
-                                 const uint32_t* scanned, uint32_t* vals, hipStream_t s) {
+                                 const uint32_t* scanned, const uint32_t* grand, uint32_t* vals, hipStream_t s) {
   if (bc.T > kTableMaxTiles || !ch.first || !ch.front) return hipErrorInvalidValue;
   ChunkArgs c = ch;
   c.tgx = bin_blocks(ch);
   const dim3 grid((unsigned)(8 * ((bc.N + 7) / 8) * c.tgx));
-  hipLaunchKernelGGL((bin_kernel<true, true>), grid, dim3(256), 0, s, rec, vis_count, nullptr, bc, c, alive, nullptr,
-                     nullptr, scanned, nullptr, vals, base);
+  hipLaunchKernelGGL((bin_kernel<true, true>), grid, dim3(256), (size_t)20 * bc.T + kTableStage, s, rec, vis_count,
+                     nullptr, bc, c, alive, nullptr, nullptr, scanned, nullptr, vals, base, grand);
   return hipGetLastError();
 }
 

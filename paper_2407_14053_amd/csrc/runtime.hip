@@ -570,7 +570,8 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
       C->end(mk, s);
       mk = C->begin(DL_STAGE_BIN_EMIT, s);
       HIP_TRY(launch_bin_table_emit(C->srec.as<float4>(), C->vis.as<uint32_t>(), bc, ch, nullptr, tbase, table,
-                                    C->bv[0].as<uint32_t>(), s));
+                                    C->partial.as<uint32_t>() + scan_partial_count(tab_n), C->bv[0].as<uint32_t>(),
+                                    s));
       C->end(mk, s);
       mk = C->begin(DL_STAGE_TILE_SORT, s);
       HIP_TRY(launch_table_starts(table, tbase, e0, N, tl.T, C->partial.as<uint32_t>() + scan_partial_count(tab_n),

@@ -94,6 +94,7 @@ class Report:
     plans_created: int
     plans_evicted: int
     hbm_high_water: int
+    budget_high_water: int
     budget: int
     resident_bytes: int
     per_display: dict = field(default_factory=dict)
@@ -114,7 +115,10 @@ class Report:
             "replans": self.replans,
             "plans_created": self.plans_created,
             "plans_evicted": self.plans_evicted,
+            # device-wide use (everything on the GPU, incl. memory in use before the server started)
             "hbm_high_water_gb": self.hbm_high_water / 2**30,
+            # what the budget bounds: resident scenes + plans
+            "budget_high_water_gb": self.budget_high_water / 2**30,
             "budget_gb": self.budget / 2**30,
             "resident_scene_gb": self.resident_bytes / 2**30,
         }
@@ -151,6 +155,7 @@ class Server:
         self.total = total
         self.budget = int(budget_bytes) if budget_bytes is not None else int(0.9 * free)
         self.high_water = total - free
+        self.used_high_water = 0
         self.created = self.evicted = 0
 
     # ---- residency ----
@@ -172,6 +177,7 @@ class Server:
     def _sample_memory(self):
         free, total = self.torch.cuda.mem_get_info()
         self.high_water = max(self.high_water, total - free)
+        self.used_high_water = max(self.used_high_water, self._used())
 
     def _used(self) -> int:
         return self.resident_bytes + self.plan_bytes
@@ -334,7 +340,8 @@ class Server:
         return Report(done=sorted(done, key=lambda d: d.rid), wall_s=wall, admitted=admitted,
                       deferred=len(deferred_ids), waited=len(waited_ids), replans=sum(replans.values()),
                       plans_created=self.created - created0,
-                      plans_evicted=self.evicted - evicted0, hbm_high_water=self.high_water, budget=self.budget,
+                      plans_evicted=self.evicted - evicted0, hbm_high_water=self.high_water,
+                      budget_high_water=self.used_high_water, budget=self.budget,
                       resident_bytes=self.resident_bytes)
 
     def close(self):
