@@ -327,10 +327,12 @@ Tiles make_tiles(const dl_display_desc& d, int tw, int th) {
   return t;
 }
 
-// Depth chunks (fractions of each view's visible depth ranks, in 1/1024): front chunks are small so that most
-// tiles terminate before the bulk of the keys would be produced.
+// Depth chunks (fractions of each view's visible depth ranks, in 1/1024): the front (about 1/16, chosen on a
+// key histogram) is small so that most tiles terminate before the bulk of the keys would be produced; the rest
+// of each view follows in one chunk (more boundaries add launches to every frame and only pay off in scenes
+// whose tiles stay unsaturated through a large part of the depth order).
 constexpr int kChunkDen = 1024;
-constexpr int kChunkBounds[] = {0, 64, 256, 1024};
+constexpr int kChunkBounds[] = {0, 64, 1024};
 constexpr int kChunks = sizeof(kChunkBounds) / sizeof(kChunkBounds[0]) - 1;
 constexpr uint32_t kMaxKeyCap = 0x7fffffffu;
 
