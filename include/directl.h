@@ -55,10 +55,14 @@ typedef struct {
  * width/height: panel pixels (each has 3 subpixels, R G B left to right).  n_views: N in [1, 255].
  * tan_slant: tan(alpha) of the lens tilt (clockwise positive).  pitch: line count L_x in subpixel widths
  * (> 0).  offset: K_offset in subpixel widths.  baseline: distance between the outermost cameras (world
- * units, >= 0).  focal_px: focal length in pixels (> 0), square pixels. */
+ * units, >= 0).  focal_px: focal length in pixels (> 0), square pixels.
+ * repurpose_pw: 0 = every subpixel shows its own pixel of its view (Alg. 1, the identity map); P_w >= 1 =
+ * subpixel repurposing (Sec. "Subpixel Repurposing", Alg. 2) in areas of P_w grating units: a subpixel may show
+ * its channel of a nearby pixel of its view, so fewer rays are rendered (dl_display_num_rays, dl_display_
+ * source_map).  At most 4096. */
 typedef struct {
   int32_t width, height, n_views;
-  int32_t reserved;
+  int32_t repurpose_pw;
   dl_rational tan_slant, pitch, offset;
   double baseline;
   double focal_px;
@@ -122,6 +126,10 @@ void dl_display_free(dl_display* display);
 int dl_display_view_map(const dl_display* display, uint8_t* out_dev, void* stream);
 /* Number of distinct rays (v, x, y) the panel needs (Sec. 5: wh <= n <= 3wh). */
 int64_t dl_display_num_rays(const dl_display* display);
+/* Source pixel of every subpixel (the index matrix M_i of Alg. 2 without its view and channel, which are
+ * V(x, 3y + k) and k): out_dev[(x W + y) 3 + k] = x' W + y' (int32), the pixel of view V(x, 3y + k) whose
+ * channel k the subpixel shows; its own pixel unless the panel repurposes subpixels.  Stream-ordered. */
+int dl_display_source_map(const dl_display* display, int32_t* out_dev, void* stream);
 
 /* Per-view cameras of the rig for `pose` (Eq. (17)), in FP64 on the host: out_host[N][16] =
  * world-to-camera rotation rows (9), translation (3), camera centre (3), 0. */

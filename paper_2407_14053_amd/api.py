@@ -30,7 +30,7 @@ class dl_rational(ctypes.Structure):
 
 class dl_display_desc(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("n_views", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("tan_slant", dl_rational), ("pitch", dl_rational),
+                ("repurpose_pw", ctypes.c_int32), ("tan_slant", dl_rational), ("pitch", dl_rational),
                 ("offset", dl_rational), ("baseline", ctypes.c_double), ("focal_px", ctypes.c_double)]
 
 
@@ -73,6 +73,7 @@ _SIGS = {
     "dl_display_free": (None, [_P]),
     "dl_display_view_map": (_I, [_P, _P, _P]),
     "dl_display_num_rays": (ctypes.c_int64, [_P]),
+    "dl_display_source_map": (_I, [_P, _P, _P]),
     "dl_cameras": (_I, [_P, ctypes.POINTER(dl_pose), _P]),
     "dl_project": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P, _P]),
     "dl_render": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P]),
@@ -163,6 +164,7 @@ def make_desc(display) -> dl_display_desc:
     d.width, d.height, d.n_views = display.width, display.height, display.n_views
     d.tan_slant, d.pitch, d.offset = _rat(display.tan_slant), _rat(display.pitch), _rat(display.offset)
     d.baseline, d.focal_px = float(display.baseline), float(display.focal_px)
+    d.repurpose_pw = int(getattr(display, "repurpose_pw", 0))
     return d
 
 
@@ -276,6 +278,13 @@ class Display:
         torch = _torch()
         out = torch.empty((self.desc.height, 3 * self.desc.width), dtype=torch.uint8, device="cuda")
         _check(load().dl_display_view_map(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def source_map(self, stream=None):
+        """[H][W][3] int32: the pixel x' W + y' whose channel k subpixel (x, y, k) shows (Alg. 2's M_i)."""
+        torch = _torch()
+        out = torch.empty((self.desc.height, self.desc.width, 3), dtype=torch.int32, device="cuda")
+        _check(load().dl_display_source_map(self.h, _ptr(out), _stream(stream)))
         return out
 
     def cameras(self, c2w, converge_dist=None) -> np.ndarray:

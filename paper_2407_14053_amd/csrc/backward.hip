@@ -86,23 +86,28 @@ __global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict_
     const int idx = threadIdx.x + j * NT;
     const bool valid = idx < nr;
     int lx = 0, ly = 0;
-    uint32_t mask = 0;
+    uint32_t mask = 0, slot = 0;
     if (valid) {
       const uint32_t e = ray_ent[r0 + idx];
       lx = (int)(e & 0xfffu);
       ly = (int)((e >> 12) & 0xfffu);
-      mask = e >> 24;
+      mask = (e >> 24) & 7u;
+      slot = (e >> 27) & 3u;
     }
     px[j] = (float)(ox + lx) + 0.5f;
     py[j] = (float)(oy + ly) + 0.5f;
     gid[j] = (int64_t)r0 + idx;
-    const int64_t pix = ((int64_t)(oy + ly) * bc.W + ox + lx) * 3;
-    g0[j] = (valid && (mask & 1u)) ? gout[pix + 0] : 0.0f;
-    g1[j] = (valid && (mask & 2u)) ? gout[pix + 1] : 0.0f;
-    g2[j] = (valid && (mask & 4u)) ? gout[pix + 2] : 0.0f;
-    F0[j] = (valid && (mask & 1u)) ? fwd[pix + 0] : 0.0f;
-    F1[j] = (valid && (mask & 2u)) ? fwd[pix + 1] : 0.0f;
-    F2[j] = (valid && (mask & 4u)) ? fwd[pix + 2] : 0.0f;
+    // the subpixel each channel of the ray fills: its own pixel's, or on a repurposed panel the listed one
+    const int64_t pix = (int64_t)(oy + ly) * bc.W + ox + lx;
+    int64_t at[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) at[k] = bc.tgt ? (int64_t)max(bc.tgt[(3 * pix + slot) * 3 + k], 0) : 3 * pix + k;
+    g0[j] = (valid && (mask & 1u)) ? gout[at[0]] : 0.0f;
+    g1[j] = (valid && (mask & 2u)) ? gout[at[1]] : 0.0f;
+    g2[j] = (valid && (mask & 4u)) ? gout[at[2]] : 0.0f;
+    F0[j] = (valid && (mask & 1u)) ? fwd[at[0]] : 0.0f;
+    F1[j] = (valid && (mask & 2u)) ? fwd[at[1]] : 0.0f;
+    F2[j] = (valid && (mask & 4u)) ? fwd[at[2]] : 0.0f;
     Tr[j] = 1.0f;
     C0[j] = C1[j] = C2[j] = 0.0f;
     live[j] = valid;

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(NT) void blend_kernel(const float4* __restrict__ re
         const uint32_t e = ray_ent[r0 + idx];
         lx = (int)(e & 0xfffu);
         ly = (int)((e >> 12) & 0xfffu);
-        mask[j] = e >> 24;
+        mask[j] = (e >> 24) & 7u;
       }
     }
     px[j] = (float)(ox + lx) + 0.5f;
@@ -201,10 +201,19 @@ __global__ __launch_bounds__(NT) void blend_kernel(const float4* __restrict__ re
         dst[1] = c[1];
         dst[2] = c[2];
       } else {
-        float* dst = out + ((int64_t)xr * bc.W + yc) * 3;
+        if (bc.tgt) {
+          // repurposed panel: channel k of the ray fills the subpixel listed for it
+          const uint32_t slot = (ray_ent[r0 + idx] >> 27) & 3u;
+          const int32_t* tg = bc.tgt + ((int64_t)3 * ((int64_t)xr * bc.W + yc) + slot) * 3;
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-          if (mask[j] & (1u << k)) dst[k] = c[k];
+          for (int k = 0; k < 3; ++k)
+            if (mask[j] & (1u << k)) out[tg[k]] = c[k];
+        } else {
+          float* dst = out + ((int64_t)xr * bc.W + yc) * 3;
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            if (mask[j] & (1u << k)) dst[k] = c[k];
+        }
       }
     }
   }

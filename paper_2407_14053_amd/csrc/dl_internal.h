@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <string>
+
 #include <cstdint>
 
 #include "../../include/directl.h"
@@ -54,6 +56,9 @@ struct BlendConst {
   float log2_alpha_min;
   float bg[3];
   unsigned long long* stats;  // optional work counters, kStatSlots x {evaluations, blends, rays}
+  // repurposed panel (nullptr: every ray fills channels of its own pixel): tgt[(3 p + j) * 3 + k] = the subpixel
+  // filled by channel k of the ray of pixel p whose entry carries slot j (bits 27-28), or -1
+  const int32_t* tgt;
 };
 constexpr int kStatSlots = 1024;
 
@@ -88,6 +93,22 @@ hipError_t launch_view_map(uint8_t* V, int W, int H, int N, int64_t As, int64_t 
 hipError_t launch_rays_emit(const uint8_t* V, int W, int H, int tw, int th, int ntx, int T, uint32_t* keys,
                             uint32_t* vals, hipStream_t s);
 hipError_t launch_interleave(const uint8_t* V, const float* views, float* out, int W, int H, hipStream_t s);
+
+// ---- subpixel repurposing (repurpose.hip) ----
+// Host: src[(x W + y) 3 + k] = source pixel x' W + y' of subpixel (x, y, k) for the panel d with P_w = pw, from
+// the view map V[H][3W] (host copy).  Returns a DL_ code (message in *why).
+int repurpose_sources(const dl_display_desc& d, int pw, const uint8_t* V, int32_t* src, std::string* why);
+// tgt[9 W H] from src (see BlendConst::tgt); *err = 1 if a source pixel does not show its subpixel's view.
+hipError_t launch_tgt_build(const uint8_t* V, const int32_t* src, int W, int H, int32_t* tgt, int32_t* err,
+                            hipStream_t s);
+// Ray entries of a repurposed panel (as launch_rays_emit, with the target slot in bits 27-28).
+hipError_t launch_rays_emit_sr(const uint8_t* V, const int32_t* tgt, int W, int H, int tw, int th, int ntx, int T,
+                               uint32_t* keys, uint32_t* vals, hipStream_t s);
+// Alg. 1 through a repurposed map: out[s] = views[V[s]][src[s]][s mod 3].
+hipError_t launch_interleave_sr(const uint8_t* V, const int32_t* src, const float* views, float* out, int W, int H,
+                                hipStream_t s);
+// out[s] = s / 3 (every subpixel's own pixel), [3 W H].
+hipError_t launch_own_pixel(int32_t* out, int W, int H, hipStream_t s);
 
 // ---- scans, radix sort, ranges (sort.hip) ----
 int64_t scan_partial_count(int64_t n);

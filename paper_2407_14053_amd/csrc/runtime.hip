@@ -161,6 +161,7 @@ struct dl_display {
   dl_ctx* ctx = nullptr;
   dl_display_desc desc{};
   DevBuf V;
+  DevBuf src, tgt;  // repurposed panels only: source pixel per subpixel, target subpixel per (ray, channel)
   int64_t n_rays = 0;
   std::map<std::pair<int, int>, RayLists*> lists;
   ~dl_display() {
@@ -181,6 +182,7 @@ int check_desc(const dl_display_desc* d, dl_display_desc& o) {
   if (o.pitch.num <= 0) return fail(DL_EINVAL, "pitch must be > 0");
   if (!(o.focal_px > 0) || !std::isfinite(o.focal_px)) return fail(DL_EINVAL, "focal_px must be finite and > 0");
   if (!(o.baseline >= 0) || !std::isfinite(o.baseline)) return fail(DL_EINVAL, "baseline must be finite and >= 0");
+  if (o.repurpose_pw < 0 || o.repurpose_pw > 4096) return fail(DL_EINVAL, "repurpose_pw must be in [0, 4096]");
   return DL_OK;
 }
 
@@ -287,8 +289,10 @@ int build_ray_lists(dl_display* D, int tw, int th, hipStream_t s, RayLists** out
   const int64_t hs = radix_hist_size(n, 1);
   if (hist.ensure(hs * 4) || part.ensure((scan_partial_count(hs) + 2) * 4) || L->off.ensure((NT + 1) * 4))
     return cleanup_fail(DL_ENOMEM, "ray list buffers");
-  hipError_t e = launch_rays_emit(D->V.as<uint8_t>(), d.width, d.height, tw, th, L->ntx, L->T, k0.as<uint32_t>(),
-                                  v0.as<uint32_t>(), s);
+  hipError_t e = D->tgt.p ? launch_rays_emit_sr(D->V.as<uint8_t>(), D->tgt.as<int32_t>(), d.width, d.height, tw, th,
+                                                L->ntx, L->T, k0.as<uint32_t>(), v0.as<uint32_t>(), s)
+                          : launch_rays_emit(D->V.as<uint8_t>(), d.width, d.height, tw, th, L->ntx, L->T,
+                                             k0.as<uint32_t>(), v0.as<uint32_t>(), s);
   if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
   bool fl = radix_sort_u32(k0.as<uint32_t>(), v0.as<uint32_t>(), k1.as<uint32_t>(), v1.as<uint32_t>(), n, 1, nullptr,
                            0, 0, bits, hist.as<uint32_t>(), part.as<uint32_t>(), s, &e);
@@ -543,6 +547,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   bc.log2_alpha_min = (float)std::log2((double)o.alpha_min);
   for (int k = 0; k < 3; ++k) bc.bg[k] = o.bg[k];
   bc.stats = C->prof >= 3 ? C->stats.as<unsigned long long>() : nullptr;
+  bc.tgt = (!standard && D->tgt.p) ? D->tgt.as<int32_t>() : nullptr;
   unsigned long long* total = C->dtotal.as<unsigned long long>();
   for (int c = 0; c < kChunks; ++c) {
     C->chunk = c;
@@ -809,6 +814,40 @@ int dl_display_create(dl_ctx* ctx, const dl_display_desc* desc, void* stream, dl
     delete D;
     return fail(DL_EHIP, std::string("view map: ") + hipGetErrorString(e));
   }
+  if (d.repurpose_pw > 0) {
+    // subpixel repurposing (Alg. 2) on the host from the view map, then the rays' targets on the device
+    const size_t nsub = nV;
+    std::vector<uint8_t> Vh(nsub);
+    std::vector<int32_t> srch(nsub);
+    e = hipMemcpy(Vh.data(), D->V.p, nsub, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      delete D;
+      return fail(DL_EHIP, std::string("view map copy: ") + hipGetErrorString(e));
+    }
+    std::string why;
+    rc = repurpose_sources(d, d.repurpose_pw, Vh.data(), srch.data(), &why);
+    if (rc) {
+      delete D;
+      return fail(rc, why);
+    }
+    DevBuf err;
+    if (D->src.ensure(nsub * 4) || D->tgt.ensure(nsub * 3 * 4) || err.ensure(4)) {
+      delete D;
+      return fail(DL_ENOMEM, "repurposing buffers");
+    }
+    int32_t errh = 0;
+    e = hipMemcpyAsync(D->src.p, srch.data(), nsub * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = launch_tgt_build(D->V.as<uint8_t>(), D->src.as<int32_t>(), d.width, d.height, D->tgt.as<int32_t>(),
+                           err.as<int32_t>(), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&errh, err.p, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess || errh) {
+      delete D;
+      return fail(DL_EHIP, e != hipSuccess ? std::string("repurposing: ") + hipGetErrorString(e)
+                                           : std::string("repurposing: a source pixel does not show its view"));
+    }
+  }
   // number of distinct rays via the ray lists of a 64x64 tiling (cached for later use)
   RayLists* L = nullptr;
   rc = build_ray_lists(D, 64, 64, s, &L);
@@ -831,6 +870,16 @@ int dl_display_view_map(const dl_display* D, uint8_t* out_dev, void* stream) {
 }
 
 int64_t dl_display_num_rays(const dl_display* D) { return D ? D->n_rays : -1; }
+
+int dl_display_source_map(const dl_display* D, int32_t* out_dev, void* stream) {
+  if (!D || !out_dev) return fail(DL_EINVAL, "NULL display or output");
+  const size_t n = (size_t)3 * D->desc.width * D->desc.height;
+  if (D->src.p)
+    HIP_TRY(hipMemcpyAsync(out_dev, D->src.p, n * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  else
+    HIP_TRY(launch_own_pixel(out_dev, D->desc.width, D->desc.height, (hipStream_t)stream));
+  return DL_OK;
+}
 
 int dl_cameras(const dl_display* D, const dl_pose* pose, double* out_host) {
   if (!D || !out_host) return fail(DL_EINVAL, "NULL display or output");
@@ -1142,8 +1191,12 @@ int dl_render_backward(dl_ctx* C, const dl_scene* S, const dl_display* D, const 
 
 int dl_interleave(const dl_display* D, const float* views_dev, float* out_dev, void* stream) {
   if (!D || !views_dev || !out_dev) return fail(DL_EINVAL, "NULL argument");
-  HIP_TRY(launch_interleave(D->V.as<uint8_t>(), views_dev, out_dev, D->desc.width, D->desc.height,
-                            (hipStream_t)stream));
+  if (D->src.p)
+    HIP_TRY(launch_interleave_sr(D->V.as<uint8_t>(), D->src.as<int32_t>(), views_dev, out_dev, D->desc.width,
+                                 D->desc.height, (hipStream_t)stream));
+  else
+    HIP_TRY(launch_interleave(D->V.as<uint8_t>(), views_dev, out_dev, D->desc.width, D->desc.height,
+                              (hipStream_t)stream));
   return DL_OK;
 }
 
@@ -1170,7 +1223,10 @@ int dl_render_standard(dl_ctx* C, const dl_scene* S, const dl_display* D, const 
   C->lanes = tw * th <= 1024 ? 256 : 512;
   if ((rc = render_grow(C, S, D, pose, o, tl, true, nullptr, views, s))) return rc;
   int mk = C->begin(DL_STAGE_INTERLEAVE, s);
-  HIP_TRY(launch_interleave(D->V.as<uint8_t>(), views, out_dev, d.width, d.height, s));
+  if (D->src.p)
+    HIP_TRY(launch_interleave_sr(D->V.as<uint8_t>(), D->src.as<int32_t>(), views, out_dev, d.width, d.height, s));
+  else
+    HIP_TRY(launch_interleave(D->V.as<uint8_t>(), views, out_dev, d.width, d.height, s));
   C->end(mk, s);
   return DL_OK;
 }

@@ -68,6 +68,7 @@ class Display:
     focal_px: float = 0.0
     name: str = ""
     extra: dict = field(default_factory=dict)
+    repurpose_pw: int = 0  # 0: identity map (Alg. 1); P_w >= 1: subpixel repurposing (Alg. 2)
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -118,9 +119,9 @@ def focal_from_fov_y(height: int, fov_y_deg: float) -> float:
 
 
 def make_display(width, height, n_views, tan_slant, pitch, offset=0, baseline=0.3, fov_y_deg=40.0,
-                 name="") -> Display:
+                 name="", repurpose_pw=0) -> Display:
     return Display(width, height, n_views, Fraction(tan_slant), Fraction(pitch), Fraction(offset),
-                   float(baseline), focal_from_fov_y(height, fov_y_deg), name)
+                   float(baseline), focal_from_fov_y(height, fov_y_deg), name, repurpose_pw=int(repurpose_pw))
 
 
 # Display descriptors of the workloads (rational forms of the stated slants and pitches).

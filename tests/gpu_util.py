@@ -29,13 +29,16 @@ def sample_subpixels(h, w, n, seed):
     return np.r_[xs, ex], np.r_[ys, ey], np.r_[ks, ek]
 
 
-def check_subpixels(scene, display, c2w, img, xs, ys, ks, opts=None, V=None, label=""):
-    """GPU image values at subpixels (xs, ys, ks) against the oracle's admissible outcomes of their rays.
-    Returns (max error over rays within budget, number of over-budget rays, number of fragile rays)."""
+def check_subpixels(scene, display, c2w, img, xs, ys, ks, opts=None, V=None, label="", src=None):
+    """GPU image values at subpixels (xs, ys, ks) against the oracle's admissible outcomes of their rays: the
+    ray of view V(x, 3y + k) through pixel (x, y), or through the pixel src = (src_x, src_y)[x, y, k] of a
+    repurposed panel.  Returns (max error over rays within budget, number of over-budget rays, number of
+    fragile rays)."""
     if V is None:
         V = orender.view_map_of(display)
     vs = V[xs, 3 * ys + ks].astype(np.int64)
-    code = (vs * display.height + xs) * display.width + ys
+    px, py = (xs, ys) if src is None else (src[0][xs, ys, ks], src[1][xs, ys, ks])
+    code = (vs * display.height + px) * display.width + py
     uniq, inv = np.unique(code, return_inverse=True)
     rv = uniq // (display.width * display.height)
     rx = (uniq // display.width) % display.height
