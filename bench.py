@@ -322,6 +322,55 @@ def run_backward(args):
             "steps_per_s": round(1000.0 / tot, 3)}
 
 
+def run_repurposed(args, identity_fps):
+    """Subpixel repurposing (Alg. 2) on the same workload: the panel's rays with P_w grating units per area
+    (built once per display, offline), the same scene and pose sweep, eager frames."""
+    import numpy as np
+    import torch
+
+    from paper_2407_14053_amd import api, synth
+
+    disp = synth.make_named_display(args.workload, repurpose_pw=args.repurpose_pw)
+    scene = synth.make_scene(args.workload)
+    poses = synth.pose_sweep(200) if args.workload == "uhd45" else synth.pose_orbit(120)
+    ctx = api.Context(0)
+    S = api.Scene(ctx, scene.arrays())
+    t0 = time.perf_counter()
+    D = api.Display(ctx, disp)
+    build_s = time.perf_counter() - t0
+    rays = D.num_rays()
+    out = torch.empty((disp.height, disp.width, 3), dtype=torch.float32, device="cuda")
+    for i in range(args.warmup):
+        api.render(ctx, S, D, poses[i % len(poses)], out=out)
+    torch.cuda.synchronize()
+    ms = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        api.render(ctx, S, D, poses[(args.warmup + i) % len(poses)], out=out)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    wall = time.perf_counter() - t0
+    ctx.set_profiling(2)
+    api.render(ctx, S, D, poses[args.warmup % len(poses)], out=out)
+    st = ctx.frame_stats()
+    ctx.set_profiling(0)
+    D.close()
+    S.close()
+    ctx.close()
+    fps = args.steps / wall
+    print("directl, repurposed subpixels (P_w = %d): %.2f frames/s, %d rays (beta %.4f)"
+          % (args.repurpose_pw, fps, rays, rays / (disp.width * disp.height)), file=sys.stderr, flush=True)
+    return {"repurpose_pw": args.repurpose_pw, "rays": int(rays), "beta": round(rays / (disp.width * disp.height), 4),
+            "panel_build_s": round(build_s, 3), "frames_per_s": round(fps, 3),
+            "ms_per_frame": round(1000 * wall / args.steps, 3), "p50_ms": round(float(np.percentile(ms, 50)), 3),
+            "p99_ms": round(float(np.percentile(ms, 99)), 3),
+            "stage_ms": {k: round(v, 4) for k, v in st["stage_ms"].items() if v},
+            "speedup_vs_identity_map": round(fps / identity_fps, 3) if identity_fps else None}
+
+
 WORKLOADS = {
     "uhd45": "directl_uhd45: 300k Gaussians (uniform [-2,2]^3, SH3), 3840x2160 panel x 3 subpixels, N=45 views, "
              "slant atan(1/6), pitch 37/5 subpixels, baseline 0.6, FOV 40 deg, 200-pose +-10 deg sweep",
@@ -436,6 +485,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--bwd-steps", type=int, default=5)
+    ap.add_argument("--repurpose-pw", type=int, default=2,
+                    help="also time the workload with subpixel repurposing in areas of this many grating units "
+                         "(0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (calibrates HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -450,6 +502,8 @@ def main():
     if args.copy_probe:
         copy_probe()
     res, scene, disp, poses = run_gpu(args)
+    if args.repurpose_pw > 0:
+        res["repurposed"] = run_repurposed(args, res["value"])
     if not args.no_backward:
         res["training_step"] = run_backward(args)
     if not args.no_serve:

@@ -244,12 +244,15 @@ int check_opts(const dl_render_opts* o, dl_render_opts& out) {
   return DL_OK;
 }
 
-void auto_tile_directl(const dl_display_desc& d, int& tw, int& th) {
-  // A view owns about 3/N of a tile's pixels.  Tiles of about 900 owned rays (3-4 per lane of a 256-lane
-  // workgroup) amortise each LDS-staged record over many rays and keep the tile-key count low, while the
-  // extra per-ray evaluations of a larger tile stay small next to the splat sizes.  On large panels the tiles
-  // grow until a view has at most 1024 of them, so that the tile partition takes one radix pass.
-  const double side = std::sqrt(300.0 * d.n_views);
+void auto_tile_directl(const dl_display_desc& d, int64_t n_rays, int& tw, int& th) {
+  // A view owns about r/N of a tile's pixels (r = rays per pixel: 3 without repurposing).  Tiles of about 900
+  // owned rays (3-4 per lane of a 256-lane workgroup) amortise each LDS-staged record over many rays and keep
+  // the tile-key count low, while the extra per-ray evaluations of a larger tile stay small next to the splat
+  // sizes; with fewer rays per pixel the best side grows only as (3 / r)^(1/4) (measured: the evaluations per
+  // ray grow with the tile).  On large panels the tiles grow until a view has at most 1024 of them, so that
+  // the first chunk's binning takes the table form.
+  const double r = n_rays > 0 ? std::min(3.0, (double)n_rays / ((double)d.width * d.height)) : 3.0;
+  const double side = std::sqrt(300.0 * d.n_views) * std::pow(3.0 / r, 0.25);
   int s = (int)std::floor(side / 8.0) * 8;
   s = std::max(8, std::min(s, 256));
   auto tiles = [&](int t) { return (int64_t)((d.width + t - 1) / t) * ((d.height + t - 1) / t); };
@@ -936,7 +939,7 @@ int dl_render(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* 
   if ((rc = check_opts(opts, o))) return rc;
   hipStream_t s = (hipStream_t)stream;
   int tw = o.tile_w, th = o.tile_h;
-  if (tw == 0 || th == 0) auto_tile_directl(D->desc, tw, th);
+  if (tw == 0 || th == 0) auto_tile_directl(D->desc, D->n_rays, tw, th);
   RayLists* L = nullptr;
   if ((rc = build_ray_lists(const_cast<dl_display*>(D), tw, th, s, &L))) return rc;
   if (L->max_rays > 16 * 256) return fail(DL_EINVAL, "tile too large: more than 4096 rays of one view");
@@ -1029,7 +1032,7 @@ int dl_plan_create(dl_ctx* ctx, const dl_scene* S, const dl_display* D, const dl
   P->o = o;
   P->out = out_dev;
   int tw = o.tile_w, th = o.tile_h;
-  if (tw == 0 || th == 0) auto_tile_directl(D->desc, tw, th);
+  if (tw == 0 || th == 0) auto_tile_directl(D->desc, D->n_rays, tw, th);
   P->tl = make_tiles(D->desc, tw, th);
   // first guess of the per-chunk key capacity; the probe grows it to what the pose needs
   P->C->key_cap = (uint32_t)std::min<int64_t>(1 << 22, std::max<int64_t>(1 << 16, (int64_t)D->desc.n_views * S->n / 2));
@@ -1081,7 +1084,7 @@ int64_t dl_plan_estimate_bytes(const dl_scene* S, const dl_display* D, const dl_
   dl_render_opts o;
   if (check_opts(opts, o)) return -1;
   int tw = o.tile_w, th = o.tile_h;
-  if (tw == 0 || th == 0) auto_tile_directl(D->desc, tw, th);
+  if (tw == 0 || th == 0) auto_tile_directl(D->desc, D->n_rays, tw, th);
   const Tiles tl = make_tiles(D->desc, tw, th);
   const int N = D->desc.n_views;
   const uint32_t cap = (uint32_t)std::min<int64_t>(kMaxKeyCap, std::max<int64_t>(key_capacity, 1));
@@ -1176,7 +1179,7 @@ int dl_render_backward(dl_ctx* C, const dl_scene* S, const dl_display* D, const 
   if ((rc = check_opts(opts, o))) return rc;
   hipStream_t s = (hipStream_t)stream;
   int tw = o.tile_w, th = o.tile_h;
-  if (tw == 0 || th == 0) auto_tile_directl(D->desc, tw, th);
+  if (tw == 0 || th == 0) auto_tile_directl(D->desc, D->n_rays, tw, th);
   RayLists* L = nullptr;
   if ((rc = build_ray_lists(const_cast<dl_display*>(D), tw, th, s, &L))) return rc;
   if (L->max_rays > 16 * 256) return fail(DL_EINVAL, "tile too large: more than 4096 rays of one view");
