@@ -322,6 +322,40 @@ def run_backward(args):
             "steps_per_s": round(1000.0 / tot, 3)}
 
 
+def run_grid(args):
+    """The paper's multi-view rows on the same workload: the N views at the low and medium view sizes the
+    display table gives for its 3840x2160 panel (800x450, 1920x1080), bilinear Resize, Alg. 1."""
+    import torch
+
+    from paper_2407_14053_amd import api, synth
+
+    disp = synth.make_named_display(args.workload)
+    scene = synth.make_scene(args.workload)
+    poses = synth.pose_sweep(200) if args.workload == "uhd45" else synth.pose_orbit(120)
+    sizes = {"LR": (800, 450), "MR": (1920, 1080)} if args.workload == "uhd45" else \
+        {"LR": (1600, 900), "MR": (3840, 2160)}
+    ctx = api.Context(0)
+    S = api.Scene(ctx, scene.arrays())
+    D = api.Display(ctx, disp)
+    out = torch.empty((disp.height, disp.width, 3), dtype=torch.float32, device="cuda")
+    res = {}
+    for name, (vw, vh) in sizes.items():
+        for i in range(2):
+            api.render_multiview(ctx, S, D, poses[i], vw, vh, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.std_steps):
+            api.render_multiview(ctx, S, D, poses[(2 + i) % len(poses)], vw, vh, out=out)
+        torch.cuda.synchronize()
+        fps = args.std_steps / (time.perf_counter() - t0)
+        print("multi-view %s (%dx%d views): %.2f frames/s" % (name, vw, vh, fps), file=sys.stderr, flush=True)
+        res["%s_%dx%d" % (name, vw, vh)] = {"frames_per_s": round(fps, 3), "ms_per_frame": round(1000 / fps, 3)}
+    D.close()
+    S.close()
+    ctx.close()
+    return res
+
+
 def run_repurposed(args, identity_fps):
     """Subpixel repurposing (Alg. 2) on the same workload: the panel's rays with P_w grating units per area
     (built once per display, offline), the same scene and pose sweep, eager frames."""
@@ -504,6 +538,8 @@ def main():
     res, scene, disp, poses = run_gpu(args)
     if args.repurpose_pw > 0:
         res["repurposed"] = run_repurposed(args, res["value"])
+    if not args.no_standard:
+        res["multiview"] = run_grid(args)
     if not args.no_backward:
         res["training_step"] = run_backward(args)
     if not args.no_serve:

@@ -158,6 +158,16 @@ int dl_render(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, con
 int dl_render_standard(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
                        const dl_render_opts* opts, float* out_dev, float* views_dev, void* stream);
 
+/* The paper's multi-view baselines (Alg. 1 with its Resize): the N views rendered at view_w x view_h pixels
+ * (the panel's rig and vertical field of view: focal_px scaled by view_h / height), each upsampled to the
+ * panel by bilinear interpolation (half-pixel centres, edges clamped), then interlaced into out_dev[H][W][3]
+ * (through the source map on a repurposed panel).  The LR and MR rows of the paper's comparison; with the
+ * panel's own size the views are the standard paradigm's.  views_dev: NULL or [N][view_h][view_w][3] to keep
+ * the views.  tile_w/tile_h of opts as for dl_render_standard. */
+int dl_render_multiview(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
+                        const dl_render_opts* opts, int32_t view_w, int32_t view_h, float* out_dev,
+                        float* views_dev, void* stream);
+
 /* Backward of dl_render (the paper names backpropagation as future work, Sec. 9; here the rasterized
  * DirectL forward is differentiated): given the forward's encoded image out_dev[H][W][3] for the same scene,
  * display, pose and options, and grad_out_dev = d loss / d out_dev, writes d loss / d parameters in the

@@ -71,6 +71,29 @@ def view_map(width: int, height: int, n_views: int, tan_slant, pitch, offset=0) 
     return V.astype(np.uint8 if n_views <= 256 else np.int64)
 
 
+def resize_bilinear(img: np.ndarray, out_h: int, out_w: int) -> np.ndarray:
+    """Alg. 1's Resize (the paper names no filter; this build reads it as bilinear): img[h, w, c] ->
+    [out_h, out_w, c] in FP64 with half-pixel centres: output row i samples input row (i + 1/2) h / out_h - 1/2,
+    clamped at 0, between its floor and the next row (the last row repeats); columns alike."""
+    h, w = img.shape[:2]
+
+    def axis(n_out, n_in):
+        src = np.maximum((np.arange(n_out) + 0.5) * (n_in / n_out) - 0.5, 0.0)
+        i0 = np.minimum(np.floor(src).astype(np.int64), n_in - 1)
+        i1 = np.minimum(i0 + 1, n_in - 1)
+        return i0, i1, src - i0
+
+    r0, r1, ly = axis(out_h, h)
+    c0, c1, lx = axis(out_w, w)
+    a = img[r0][:, c0].astype(np.float64)
+    b = img[r0][:, c1].astype(np.float64)
+    c = img[r1][:, c0].astype(np.float64)
+    d = img[r1][:, c1].astype(np.float64)
+    ly = ly[:, None, None]
+    lx = lx[None, :, None]
+    return (1 - ly) * ((1 - lx) * a + lx * b) + ly * ((1 - lx) * c + lx * d)
+
+
 def interleave(views: np.ndarray, V: np.ndarray) -> np.ndarray:
     """Alg. 1: views[N, h, w, 3] and V[h, 3w] -> encoded image M_e[h, w, 3]."""
     n, h, w, _ = views.shape

@@ -79,6 +79,8 @@ _SIGS = {
     "dl_render": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P]),
     "dl_render_standard": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P,
                                 _P]),
+    "dl_render_multiview": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), ctypes.c_int32,
+                                 ctypes.c_int32, _P, _P, _P]),
     "dl_interleave": (_I, [_P, _P, _P, _P]),
     "dl_render_backward": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P, _P, _P,
                                 _P, _P, _P, _P]),
@@ -344,6 +346,24 @@ def render_standard(ctx, scene, display, c2w, converge_dist=None, opts=None, out
     o = opts or default_opts()
     _check(load().dl_render_standard(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(out),
                                      _ptr(views) if views is not None else None, _stream(stream)))
+    return out, views
+
+
+def render_multiview(ctx, scene, display, c2w, view_w, view_h, converge_dist=None, opts=None, out=None, views=None,
+                     keep_views=False, stream=None):
+    """The multi-view baselines: N views at view_w x view_h, bilinear Resize to the panel, Alg. 1.  Returns
+    (encoded image, views [N, view_h, view_w, 3] or None)."""
+    torch = _torch()
+    H, W = display.shape
+    if out is None:
+        out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    if views is None and keep_views:
+        views = torch.empty((display.n_views, view_h, view_w, 3), dtype=torch.float32, device="cuda")
+    pose = make_pose(c2w, converge_dist)
+    o = opts or default_opts()
+    _check(load().dl_render_multiview(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), int(view_w),
+                                      int(view_h), _ptr(out), _ptr(views) if views is not None else None,
+                                      _stream(stream)))
     return out, views
 
 

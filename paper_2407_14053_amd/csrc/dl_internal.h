@@ -93,6 +93,9 @@ hipError_t launch_view_map(uint8_t* V, int W, int H, int N, int64_t As, int64_t 
 hipError_t launch_rays_emit(const uint8_t* V, int W, int H, int tw, int th, int ntx, int T, uint32_t* keys,
                             uint32_t* vals, hipStream_t s);
 hipError_t launch_interleave(const uint8_t* V, const float* views, float* out, int W, int H, hipStream_t s);
+// Alg. 1 with a bilinear Resize of views[N][vh][vw][3] to the panel (src: source pixels of a repurposed panel)
+hipError_t launch_interleave_resize(const uint8_t* V, const int32_t* src, const float* views, float* out, int W,
+                                   int H, int vw, int vh, hipStream_t s);
 
 // ---- subpixel repurposing (repurpose.hip) ----
 // Host: src[(x W + y) 3 + k] = source pixel x' W + y' of subpixel (x, y, k) for the panel d with P_w = pw, from

@@ -951,6 +951,44 @@ int dl_render(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* 
   return render_grow(C, S, D, pose, o, tl, false, L, out_dev, s);
 }
 
+int dl_render_multiview(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose,
+                        const dl_render_opts* opts, int32_t view_w, int32_t view_h, float* out_dev, float* views_dev,
+                        void* stream) {
+  int rc = check_common(C, S, D);
+  if (rc) return rc;
+  if (!out_dev) return fail(DL_EINVAL, "NULL output");
+  if (view_w < 1 || view_h < 1 || view_w > 65536 || view_h > 65536) return fail(DL_EINVAL, "view size out of range");
+  dl_render_opts o;
+  if ((rc = check_opts(opts, o))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int tw = o.tile_w ? o.tile_w : 32, th = o.tile_h ? o.tile_h : 32;
+  if (tw * th > 16 * 256) return fail(DL_EINVAL, "standard tile larger than 4096 pixels");
+  const dl_display_desc& d = D->desc;
+  // the views: the same rig and vertical field of view at view_w x view_h pixels
+  dl_display Dv;
+  Dv.ctx = D->ctx;
+  Dv.desc = d;
+  Dv.desc.width = view_w;
+  Dv.desc.height = view_h;
+  Dv.desc.focal_px = d.focal_px * (double)view_h / (double)d.height;
+  float* views = views_dev;
+  if (!views) {
+    HIP_TRY(C->views.ensure((size_t)d.n_views * view_w * view_h * 12));
+    views = C->views.as<float>();
+  }
+  Tiles tl = make_tiles(Dv.desc, tw, th);
+  C->tile_w = tw;
+  C->tile_h = th;
+  C->rpt = tw * th <= 1024 ? (tw * th + 255) / 256 : (tw * th + 511) / 512;
+  C->lanes = tw * th <= 1024 ? 256 : 512;
+  if ((rc = render_grow(C, S, &Dv, pose, o, tl, true, nullptr, views, s))) return rc;
+  int mk = C->begin(DL_STAGE_INTERLEAVE, s);
+  HIP_TRY(launch_interleave_resize(D->V.as<uint8_t>(), D->src.p ? D->src.as<int32_t>() : nullptr, views, out_dev,
+                                   d.width, d.height, view_w, view_h, s));
+  C->end(mk, s);
+  return DL_OK;
+}
+
 }  // extern "C"
 
 struct dl_plan {

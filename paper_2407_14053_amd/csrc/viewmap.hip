@@ -58,6 +58,30 @@ __global__ __launch_bounds__(256) void interleave_kernel(const uint8_t* __restri
   out[idx] = views[v * n + idx];
 }
 
+// Alg. 1 with its Resize: out[s] = view V[s] at panel pixel (x, y) of subpixel s (or its source pixel on a
+// repurposed panel), upsampled from vh x vw by bilinear interpolation with half-pixel centres (source
+// coordinate (i + 1/2) in / out - 1/2, clamped at 0, neighbours clamped to the last row / column).
+__global__ __launch_bounds__(256) void interleave_resize_kernel(const uint8_t* __restrict__ V,
+                                                                const int32_t* __restrict__ src,
+                                                                const float* __restrict__ views,
+                                                                float* __restrict__ out, int W, int H, int vw, int vh) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)3 * W * H;
+  if (s >= n) return;
+  const int k = (int)(s % 3);
+  const int64_t p = src ? (int64_t)src[s] : s / 3;
+  const int x = (int)(p / W), y = (int)(p - (int64_t)x * W);
+  const float fy = fmaxf(((float)x + 0.5f) * ((float)vh / (float)H) - 0.5f, 0.0f);
+  const float fx = fmaxf(((float)y + 0.5f) * ((float)vw / (float)W) - 0.5f, 0.0f);
+  const int r0 = min((int)fy, vh - 1), c0 = min((int)fx, vw - 1);
+  const int r1 = min(r0 + 1, vh - 1), c1 = min(c0 + 1, vw - 1);
+  const float ly = fy - (float)r0, lx = fx - (float)c0;
+  const float* img = views + (int64_t)V[s] * vh * vw * 3;
+  const float a = img[((int64_t)r0 * vw + c0) * 3 + k], b = img[((int64_t)r0 * vw + c1) * 3 + k];
+  const float c = img[((int64_t)r1 * vw + c0) * 3 + k], d = img[((int64_t)r1 * vw + c1) * 3 + k];
+  out[s] = (1.0f - ly) * ((1.0f - lx) * a + lx * b) + ly * ((1.0f - lx) * c + lx * d);
+}
+
 inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -74,6 +98,14 @@ hipError_t launch_rays_emit(const uint8_t* V, int W, int H, int tw, int th, int 
   const int64_t n = (int64_t)W * H;
   hipLaunchKernelGGL(rays_emit_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, V, W, H, tw, th, ntx, T, keys,
                      vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_interleave_resize(const uint8_t* V, const int32_t* src, const float* views, float* out, int W,
+                                   int H, int vw, int vh, hipStream_t s) {
+  const int64_t n = (int64_t)3 * W * H;
+  hipLaunchKernelGGL(interleave_resize_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, V, src, views, out, W, H, vw,
+                     vh);
   return hipGetLastError();
 }
 

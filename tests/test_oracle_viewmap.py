@@ -145,3 +145,17 @@ def test_literal_fp64_formula_misassigns_lens_boundaries():
     xo = np.mod(doff, float(d.pitch))
     Vf = np.floor(d.n_views * xo / float(d.pitch)).astype(np.int64)
     assert (Vf != V).sum() > 0
+
+
+def test_resize_bilinear_matches_torch_interpolate():
+    """Alg. 1's Resize read as bilinear: the oracle's FP64 definition equals torch's bilinear interpolation with
+    half-pixel centres (align_corners=False), a library routine, for up- and down-sampling and odd sizes."""
+    import torch
+    from oracle.viewmap import resize_bilinear
+    rng = np.random.default_rng(4)
+    for (h, w, oh, ow) in [(9, 16, 36, 64), (45, 80, 216, 384), (7, 5, 3, 11), (10, 10, 10, 10)]:
+        img = rng.uniform(0, 1, (h, w, 3))
+        ref = torch.nn.functional.interpolate(torch.tensor(img).permute(2, 0, 1)[None], size=(oh, ow),
+                                              mode="bilinear", align_corners=False)[0].permute(1, 2, 0).numpy()
+        got = resize_bilinear(img, oh, ow)
+        assert np.abs(got - ref).max() < 1e-12, (h, w, oh, ow)
