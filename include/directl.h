@@ -45,6 +45,7 @@ typedef struct dl_ctx dl_ctx;
 typedef struct dl_scene dl_scene;
 typedef struct dl_display dl_display;
 typedef struct dl_plan dl_plan;
+typedef struct dl_bvh dl_bvh;
 
 /* Exact rational num/den, den > 0. */
 typedef struct {
@@ -183,6 +184,42 @@ int dl_render_backward(dl_ctx* ctx, const dl_scene* scene, const dl_display* dis
 
 /* Alg. 1 alone: out_dev[x][y][k] = views_dev[V(x, 3y + k)][x][y][k]. */
 int dl_interleave(const dl_display* display, const float* views_dev, float* out_dev, void* stream);
+
+/* ---- ray-order 3DGS (Sec. "Ray-Order 3DGS", Alg. 3, Eq. (21)-(23)) ----
+ * A second renderer for the same rays as dl_render: every ray (its view's camera centre o, unit direction d
+ * through the pixel centre) is cast through a BVH over the Gaussians; a Gaussian is hit where its response
+ * along the ray peaks, t_j = (mu - o)^T Sigma^-1 d / (d^T Sigma^-1 d) (Eq. (22)), if there t_j >= z_near,
+ * q_j <= q_cut and alpha_j = o_j G(o + t_j d) >= alpha_min (Eq. (23)); the c_h hits of smallest (t_j, j) are
+ * blended front to back (alpha clamped at alpha_max, stop before the transmittance would fall below t_min,
+ * background with the final transmittance) with SH colours in direction d.  This computes a different image
+ * from the rasterizer (peak response along the ray instead of the projected 2D Gaussian). */
+typedef struct {
+  int64_t n_gaussians;  /* scene size */
+  int64_t n_prims;      /* Gaussians in the BVH (opacity >= alpha_min) */
+  int64_t n_nodes;      /* 8-wide nodes */
+  int64_t n_leaves;     /* leaf children (at most 4 Gaussians each) */
+  int32_t depth;        /* wide levels */
+  int32_t stack_bound;  /* traversal stack entries per ray */
+  double sah_cost;      /* Eq. (21) of the binary SAH tree, c_node = c_prim = 1, areas relative to the root */
+  double build_ms;      /* host build time (copy-back, build, upload) */
+} dl_bvh_stats;
+
+/* Build the BVH of a scene (Eq. (21): binned SAH, collapsed to 8-wide nodes) on the host from the scene's
+ * current parameters; q_cut and alpha_min of opts (NULL: defaults) fix the hit rule's bounds, baked into the
+ * boxes.  The BVH holds its own copy of what it needs (records and SH in leaf order): later dl_scene_update calls
+ * do not reach it (build again).  Synchronises `stream`.  DL_ERANGE if the tree needs a traversal stack deeper
+ * than 256 entries. */
+int dl_bvh_build(dl_ctx* ctx, const dl_scene* scene, const dl_render_opts* opts, void* stream, dl_bvh** out);
+int dl_bvh_get_stats(const dl_bvh* bvh, dl_bvh_stats* out);
+void dl_bvh_free(dl_bvh* bvh);
+
+/* Render the display's rays (repurposed panels included) in ray order with heap capacity heap_cap = c_h in
+ * [1, 2^24] into out_dev[H][W][3] (every subpixel written).  opts: z_near, alpha_max, t_min, bg, sh_degree;
+ * tile_w/tile_h choose the (view, tile) ray lists that a 64-lane workgroup walks (0: about 128 rays per list);
+ * q_cut and alpha_min are the BVH's.  Asynchronous on `stream`; profiling level >= 1 records the kernel as the
+ * blend stage, level 3 counts Gaussian tests (evaluations), blends and rays. */
+int dl_render_rayorder(dl_ctx* ctx, const dl_bvh* bvh, const dl_display* display, const dl_pose* pose,
+                       const dl_render_opts* opts, int32_t heap_cap, float* out_dev, void* stream);
 
 /* ---- plans: fixed-buffer frames replayed as HIP graphs (serving) ----
  * A plan owns every per-frame buffer of one (scene, display, options) at fixed capacity, sized by an eager

@@ -23,8 +23,9 @@ Readings of what the paper leaves open (each one a line of the design notes):
   at image point (y + 1/2, x + 1/2)) of that view's pinhole camera.
 
 Decisions that FP32 arithmetic can take differently from FP64 (q at q_cut, alpha at alpha_min, t at z_near,
-near-equal t among the kept Gaussians or at the heap's capacity, the transmittance at t_min) mark the ray
-"fragile"; tests compare only rays without such a decision.
+near-equal t among the blended Gaussians or at the heap's capacity, the transmittance at t_min) mark the ray
+"fragile" when they can change the result: a threshold decision only for a Gaussian nearer than where the walk
+ended.  Tests compare only rays without such a decision.
 """
 from __future__ import annotations
 
@@ -36,7 +37,7 @@ import numpy as np
 from . import render as orender
 
 # relative bands of the fragile decisions (FP32 error of the GPU's peak, quadratic form and blend, with margin)
-BAND_Q = 1e-3
+BAND_Q = 1e-4
 BAND_T = 1e-5
 BAND_STOP = 1e-3
 
@@ -117,10 +118,8 @@ def trace(scene, origins, dirs, heap_cap: int, opts: orender.Opts = None) -> Ray
         o, d = np.asarray(origins[r], np.float64), np.asarray(dirs[r], np.float64)
         t, q = peak(mu, inv, o, d)
         a = op * np.exp(-0.5 * q)
-        hit = (t >= opts.z_near) & (q <= q_cut) & (a >= a_min)                    # IntersectsBVH
-        fr = bool(np.any((np.abs(q - q_cut) <= BAND_Q * q_cut) & (t >= opts.z_near) & (a >= a_min * (1 - BAND_Q)))
-                  or np.any((np.abs(a / a_min - 1) <= BAND_Q) & (t >= opts.z_near) & (q <= q_cut * (1 + BAND_Q)))
-                  or np.any((np.abs(t - opts.z_near) <= BAND_T * opts.z_near) & (q <= q_cut) & (a >= a_min)))
+        front = t >= opts.z_near
+        hit = front & (q <= q_cut) & (a >= a_min)                                 # IntersectsBVH
         heap = []                                                                 # max-heap of (t, j) via negation
         for j in np.nonzero(hit)[0]:
             key = (float(t[j]), int(j))
@@ -131,27 +130,39 @@ def trace(scene, origins, dirs, heap_cap: int, opts: orender.Opts = None) -> Ray
                 heapq.heappush(heap, (-key[0], -key[1]))
         kept = sorted((-a_, -b_) for a_, b_ in heap)                              # Sort(h)
         hits[r] = int(hit.sum())
-        ts = np.array([k[0] for k in kept])
-        if len(ts) > 1 and np.any(np.diff(ts) <= BAND_T * np.abs(ts[1:])):
-            fr = True
-        if hits[r] > heap_cap:                                                    # near-tie at the capacity
-            rest = np.sort(t[hit])
-            if rest[heap_cap] - rest[heap_cap - 1] <= BAND_T * abs(rest[heap_cap]):
-                fr = True
         T = 1.0
         C = np.zeros(3)
-        for tj, j in kept:                                                        # AlphaBlending
+        fr = False
+        t_end = np.inf            # hits beyond this distance cannot change the result
+        for i, (tj, j) in enumerate(kept):                                        # AlphaBlending
             alpha = min(opts.alpha_max, float(a[j]))
             nt = T * (1.0 - alpha)
             if abs(nt - opts.t_min) <= BAND_STOP * opts.t_min:
                 fr = True
             if nt < opts.t_min:
+                t_end = tj
                 break
             col = np.maximum(Y[r] @ sh[j] + 0.5, 0.0)                             # CalculateFromSHS(d, g)
             C += T * alpha * col
             T = nt
             blended[r] += 1
+        else:
+            if len(kept) == heap_cap:                                             # the capacity ended the walk
+                t_end = kept[-1][0]
+                if hits[r] > heap_cap:
+                    rest = np.sort(t[hit])
+                    if rest[heap_cap] - rest[heap_cap - 1] <= BAND_T * abs(rest[heap_cap]):
+                        fr = True
         rgb[r] = C + T * np.asarray([orender.f32(b) for b in opts.bg])
+        # threshold decisions FP32 could take the other way, on Gaussians that would change the blended prefix
+        near = t <= t_end * (1 + BAND_T)
+        fr = fr or bool(np.any(near & front & (np.abs(q - q_cut) <= BAND_Q * q_cut) & (a >= a_min * (1 - BAND_Q)))
+                        or np.any(near & front & (np.abs(a / a_min - 1) <= BAND_Q) & (q <= q_cut * (1 + BAND_Q)))
+                        or np.any(near & (np.abs(t - opts.z_near) <= BAND_T * opts.z_near) & (q <= q_cut)
+                                  & (a >= a_min)))
+        ts = np.array([k[0] for k in kept[:blended[r] + 1]])
+        if len(ts) > 1 and np.any(np.diff(ts) <= BAND_T * np.abs(ts[1:])):
+            fr = True
         fragile[r] = fr
     return RayOut(rgb, hits, blended, fragile)
 

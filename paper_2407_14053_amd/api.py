@@ -58,6 +58,12 @@ class dl_frame_stats(ctypes.Structure):
                 ("chunks", ctypes.c_int32), ("chunk_ms", (ctypes.c_double * NSTAGES) * 8), ("lanes", ctypes.c_int32)]
 
 
+class dl_bvh_stats(ctypes.Structure):
+    _fields_ = [("n_gaussians", ctypes.c_int64), ("n_prims", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("n_leaves", ctypes.c_int64), ("depth", ctypes.c_int32), ("stack_bound", ctypes.c_int32),
+                ("sah_cost", ctypes.c_double), ("build_ms", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _SIGS = {
@@ -95,6 +101,11 @@ _SIGS = {
     "dl_plan_bytes": (ctypes.c_int64, [_P]),
     "dl_plan_estimate_bytes": (ctypes.c_int64, [_P, _P, ctypes.POINTER(dl_render_opts), ctypes.c_int64]),
     "dl_plan_free": (None, [_P]),
+    "dl_bvh_build": (_I, [_P, _P, ctypes.POINTER(dl_render_opts), _P, ctypes.POINTER(_P)]),
+    "dl_bvh_get_stats": (_I, [_P, ctypes.POINTER(dl_bvh_stats)]),
+    "dl_bvh_free": (None, [_P]),
+    "dl_render_rayorder": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), ctypes.c_int32,
+                                _P, _P]),
 }
 
 _lib = None
@@ -365,6 +376,47 @@ def render_multiview(ctx, scene, display, c2w, view_w, view_h, converge_dist=Non
                                       int(view_h), _ptr(out), _ptr(views) if views is not None else None,
                                       _stream(stream)))
     return out, views
+
+
+class BVH:
+    """The scene's 8-wide SAH BVH for ray-order rendering (built on the host from the scene's current
+    parameters; q_cut and alpha_min of ``opts`` are baked into its boxes)."""
+
+    def __init__(self, ctx: Context, scene: Scene, opts=None, stream=None):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        o = opts or default_opts()
+        _check(load().dl_bvh_build(ctx.h, scene.h, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def stats(self) -> dict:
+        st = dl_bvh_stats()
+        _check(load().dl_bvh_get_stats(self.h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def close(self):
+        if self.h:
+            load().dl_bvh_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def render_rayorder(ctx, bvh, display, c2w, heap_cap=128, converge_dist=None, opts=None, out=None, stream=None):
+    """Ray-order 3DGS (Alg. 3) of the display's rays with heap capacity c_h = heap_cap: the encoded image."""
+    torch = _torch()
+    H, W = display.shape
+    if out is None:
+        out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    pose = make_pose(c2w, converge_dist)
+    o = opts or default_opts()
+    _check(load().dl_render_rayorder(ctx.h, bvh.h, display.h, ctypes.byref(pose), ctypes.byref(o), int(heap_cap),
+                                     _ptr(out), _stream(stream)))
+    return out
 
 
 def render_backward(ctx, scene, display, c2w, out, grad_out, converge_dist=None, opts=None, stream=None):

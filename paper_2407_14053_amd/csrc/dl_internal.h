@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include <cstdint>
 
@@ -81,6 +82,38 @@ struct ChunkArgs {
   uint32_t cap;     // key capacity
   int64_t tgx;      // workgroups per view of the table-form binning (set by its launchers)
 };
+
+// Real spherical harmonics without the Condon-Shortley phase, index l*l + l + m, m = -l..l, written as
+// polynomials of the unit direction (x, y, z):
+//   l=0: 1/(2 sqrt(pi))
+//   l=1: sqrt(3/(4pi)) * (y, z, x)
+//   l=2: (1/2)sqrt(15/pi) xy, (1/2)sqrt(15/pi) yz, (1/4)sqrt(5/pi)(3z^2 - 1), (1/2)sqrt(15/pi) xz,
+//        (1/4)sqrt(15/pi)(x^2 - y^2)
+//   l=3: (1/4)sqrt(35/(2pi)) y(3x^2 - y^2), (1/2)sqrt(105/pi) xyz, (1/4)sqrt(21/(2pi)) y(5z^2 - 1),
+//        (1/4)sqrt(7/pi) z(5z^2 - 3), (1/4)sqrt(21/(2pi)) x(5z^2 - 1), (1/4)sqrt(105/pi) z(x^2 - y^2),
+//        (1/4)sqrt(35/(2pi)) x(x^2 - 3y^2)
+__device__ inline void sh_basis(int deg, float x, float y, float z, float* Y) {
+  Y[0] = 0.28209479177387814f;
+  if (deg < 1) return;
+  Y[1] = 0.4886025119029199f * y;
+  Y[2] = 0.4886025119029199f * z;
+  Y[3] = 0.4886025119029199f * x;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = 1.0925484305920792f * (x * y);
+  Y[5] = 1.0925484305920792f * (y * z);
+  Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
+  Y[7] = 1.0925484305920792f * (x * z);
+  Y[8] = 0.5462742152960396f * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = 0.5900435899266435f * y * (3.0f * xx - yy);
+  Y[10] = 2.890611442640554f * (x * y) * z;
+  Y[11] = 0.4570457994644658f * y * (5.0f * zz - 1.0f);
+  Y[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
+  Y[13] = 0.4570457994644658f * x * (5.0f * zz - 1.0f);
+  Y[14] = 1.445305721320277f * z * (xx - yy);
+  Y[15] = 0.5900435899266435f * x * (xx - 3.0f * yy);
+}
 
 // Per-chunk blend flags
 struct BlendChunk {
@@ -236,6 +269,44 @@ hipError_t launch_blend_directl(const float4* rec, const uint32_t* tile_start, c
 hipError_t launch_blend_standard(const float4* rec, const uint32_t* tile_start, const uint32_t* gidx,
                                  const BlendConst& bc, BlendChunk bk, uint8_t* alive, float4* state, float* views,
                                  hipStream_t s);
+
+// ---- ray-order rendering (bvh.hip, rayorder.hip) ----
+// 8-wide BVH node: 64 floats = child boxes lo x[8], lo y[8], lo z[8], hi x[8], hi y[8], hi z[8], child refs
+// (uint32 bits) [8], the node's own box (lo xyz, hi xyz) and 2 unused.  A ref is a node index, or
+// kBvhLeafBit | (count - 1) << 28 | first Gaussian (in leaf order), or kBvhEmpty.
+constexpr int kBvhNodeFloats = 64;
+constexpr int kBvhLeafMax = 4;
+constexpr uint32_t kBvhLeafBit = 0x80000000u;
+constexpr uint32_t kBvhEmpty = 0xffffffffu;
+constexpr int kBvhStackMax = 256;  // stack entries per lane the traversal supports
+struct BvhHost {
+  std::vector<float> nodes;   // n_nodes * kBvhNodeFloats, root first
+  std::vector<float> rec;     // per Gaussian in leaf order: [mu, o], [a00 a01 a02 a11], [a12 a22 q_lim, index]
+  std::vector<int32_t> perm;  // leaf order -> scene index
+  int64_t n_prims = 0, n_nodes = 0, n_leaves = 0;
+  int depth = 0, stack_bound = 1;
+  double sah_cost = 0.0;
+};
+// Host build from the scene's structure-of-arrays rows (host copy); DL_ code, message in *why.
+int bvh_build_host(const float* soa, int64_t n, int64_t n_pad, float q_cut, float alpha_min, BvhHost* out,
+                   std::string* why);
+
+struct RoConst {
+  int W, H, N, T, tw, th, ntx;
+  int sh_degree;
+  int heap_cap;    // c_h
+  int stack_cap;   // stack entries per lane (the BVH's bound)
+  double focal, cx, cy;
+  float z_near, alpha_max, t_min;
+  float bg[3];
+  const int32_t* tgt;  // repurposed panel's targets (see BlendConst::tgt), or nullptr
+  unsigned long long* stats;  // optional: kStatSlots x {Gaussian tests, blends, rays}
+};
+// One ray per lane over the (view, tile) ray lists: BVH traversal, the c_h nearest hits by peak distance, their
+// blend; writes the owned channels of out[H][W][3].
+hipError_t launch_rayorder(const float* nodes, const float4* rec, const float4* sh, const double* cams,
+                           const uint32_t* ray_off, const uint32_t* ray_ent, const RoConst& rc, float* out,
+                           hipStream_t s);
 
 // ---- backward (backward.hip) ----
 // Replays the DirectL blend of one depth chunk and accumulates d loss / d (u, v, A, B, C, o, r, g, b) per

@@ -14,38 +14,6 @@
 namespace dl {
 namespace {
 
-// Real spherical harmonics without the Condon-Shortley phase, index l*l + l + m, m = -l..l, written as
-// polynomials of the unit direction (x, y, z):
-//   l=0: 1/(2 sqrt(pi))
-//   l=1: sqrt(3/(4pi)) * (y, z, x)
-//   l=2: (1/2)sqrt(15/pi) xy, (1/2)sqrt(15/pi) yz, (1/4)sqrt(5/pi)(3z^2 - 1), (1/2)sqrt(15/pi) xz,
-//        (1/4)sqrt(15/pi)(x^2 - y^2)
-//   l=3: (1/4)sqrt(35/(2pi)) y(3x^2 - y^2), (1/2)sqrt(105/pi) xyz, (1/4)sqrt(21/(2pi)) y(5z^2 - 1),
-//        (1/4)sqrt(7/pi) z(5z^2 - 3), (1/4)sqrt(21/(2pi)) x(5z^2 - 1), (1/4)sqrt(105/pi) z(x^2 - y^2),
-//        (1/4)sqrt(35/(2pi)) x(x^2 - 3y^2)
-__device__ inline void sh_basis(int deg, float x, float y, float z, float* Y) {
-  Y[0] = 0.28209479177387814f;
-  if (deg < 1) return;
-  Y[1] = 0.4886025119029199f * y;
-  Y[2] = 0.4886025119029199f * z;
-  Y[3] = 0.4886025119029199f * x;
-  if (deg < 2) return;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  Y[4] = 1.0925484305920792f * (x * y);
-  Y[5] = 1.0925484305920792f * (y * z);
-  Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
-  Y[7] = 1.0925484305920792f * (x * z);
-  Y[8] = 0.5462742152960396f * (xx - yy);
-  if (deg < 3) return;
-  Y[9] = 0.5900435899266435f * y * (3.0f * xx - yy);
-  Y[10] = 2.890611442640554f * (x * y) * z;
-  Y[11] = 0.4570457994644658f * y * (5.0f * zz - 1.0f);
-  Y[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
-  Y[13] = 0.4570457994644658f * x * (5.0f * zz - 1.0f);
-  Y[14] = 1.445305721320277f * z * (xx - yy);
-  Y[15] = 0.5900435899266435f * x * (xx - 3.0f * yy);
-}
-
 template <int DEG>
 __global__ __launch_bounds__(256, 4) void project_kernel(const float* __restrict__ soa, const double* __restrict__ cams,
                                                       ProjConst pc, float4* __restrict__ rec,

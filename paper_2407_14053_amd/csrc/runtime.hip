@@ -9,6 +9,7 @@
 // Every launch has a static grid; data-dependent sizes (visible counts, key counts) stay on the device.  The
 // only host synchronisation is the end-of-frame check that no chunk overflowed the key capacity.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -155,6 +156,12 @@ struct dl_scene {
   dl_ctx* ctx = nullptr;
   int64_t n = 0, n_pad = 0;
   DevBuf soa;
+};
+
+struct dl_bvh {
+  dl_ctx* ctx = nullptr;
+  DevBuf nodes, rec, sh;  // wide nodes; records and SH [3][16] per Gaussian in leaf order
+  dl_bvh_stats st{};
 };
 
 struct dl_display {
@@ -1271,5 +1278,123 @@ int dl_render_standard(dl_ctx* C, const dl_scene* S, const dl_display* D, const 
   C->end(mk, s);
   return DL_OK;
 }
+
+int dl_bvh_build(dl_ctx* C, const dl_scene* S, const dl_render_opts* opts, void* stream, dl_bvh** out) {
+  if (!C || !S || !out) return fail(DL_EINVAL, "NULL context, scene or out");
+  if (S->ctx->device != C->device) return fail(DL_EINVAL, "scene lives on another device");
+  dl_render_opts o;
+  int rc = check_opts(opts, o);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t np = S->n_pad;
+  std::vector<float> h((size_t)kSceneRows * np);
+  HIP_TRY(hipMemcpyAsync(h.data(), S->soa.p, h.size() * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  BvhHost bh;
+  std::string why;
+  if ((rc = bvh_build_host(h.data(), S->n, np, o.q_cut, o.alpha_min, &bh, &why))) return fail(rc, why);
+  if (bh.stack_bound > kBvhStackMax) return fail(DL_ERANGE, "BVH needs a traversal stack deeper than 256");
+  const int64_t m = bh.n_prims;
+  std::vector<float> sh((size_t)m * 48);
+  for (int64_t r = 0; r < m; ++r)
+    for (int c = 0; c < 3; ++c)
+      for (int l = 0; l < 16; ++l) sh[((size_t)r * 3 + c) * 16 + l] = h[(size_t)(kRowSH + 3 * l + c) * np + bh.perm[r]];
+  dl_bvh* B = new dl_bvh();
+  B->ctx = C;
+  if (B->nodes.ensure(bh.nodes.size() * 4) || B->rec.ensure(bh.rec.size() * 4) || B->sh.ensure(sh.size() * 4)) {
+    delete B;
+    return fail(DL_ENOMEM, "BVH buffers");
+  }
+  hipError_t e = hipMemcpyAsync(B->nodes.p, bh.nodes.data(), bh.nodes.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && m)
+    e = hipMemcpyAsync(B->rec.p, bh.rec.data(), bh.rec.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && m) e = hipMemcpyAsync(B->sh.p, sh.data(), sh.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete B;
+    return fail(DL_EHIP, hipGetErrorString(e));
+  }
+  B->st.n_gaussians = S->n;
+  B->st.n_prims = m;
+  B->st.n_nodes = bh.n_nodes;
+  B->st.n_leaves = bh.n_leaves;
+  B->st.depth = bh.depth;
+  B->st.stack_bound = bh.stack_bound;
+  B->st.sah_cost = bh.sah_cost;
+  B->st.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = B;
+  return DL_OK;
+}
+
+int dl_bvh_get_stats(const dl_bvh* B, dl_bvh_stats* out) {
+  if (!B || !out) return fail(DL_EINVAL, "NULL argument");
+  *out = B->st;
+  return DL_OK;
+}
+
+void dl_bvh_free(dl_bvh* B) { delete B; }
+
+int dl_render_rayorder(dl_ctx* C, const dl_bvh* B, const dl_display* D, const dl_pose* pose,
+                       const dl_render_opts* opts, int32_t heap_cap, float* out_dev, void* stream) {
+  if (!C || !B || !D) return fail(DL_EINVAL, "NULL context, BVH or display");
+  if (B->ctx->device != C->device || D->ctx->device != C->device)
+    return fail(DL_EINVAL, "BVH/display live on another device");
+  if (!out_dev) return fail(DL_EINVAL, "NULL output");
+  if (heap_cap < 1 || heap_cap > (1 << 24)) return fail(DL_EINVAL, "heap_cap must be in [1, 2^24]");
+  dl_render_opts o;
+  int rc = check_opts(opts, o);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const dl_display_desc& d = D->desc;
+  int tw = o.tile_w, th = o.tile_h;
+  if (tw == 0 || th == 0) {
+    // about 128 rays of one view per (view, tile) list: two batches of a 64-lane workgroup
+    const double r = D->n_rays > 0 ? std::min(3.0, (double)D->n_rays / ((double)d.width * d.height)) : 3.0;
+    int side = (int)std::ceil(std::sqrt(128.0 * d.n_views / r) / 8.0) * 8;
+    tw = th = std::max(8, std::min(side, 256));
+  }
+  RayLists* L = nullptr;
+  if ((rc = build_ray_lists(const_cast<dl_display*>(D), tw, th, s, &L))) return rc;
+  C->frame_begin();
+  C->tile_w = tw;
+  C->tile_h = th;
+  C->rpt = 1;
+  C->lanes = 64;
+  if ((rc = make_cameras(d, pose, C->cams_host))) return rc;
+  HIP_TRY(C->cams.ensure((size_t)d.n_views * kCamDoubles * 8));
+  HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)d.n_views * kCamDoubles * 8, hipMemcpyHostToDevice, s));
+  RoConst rcs{};
+  rcs.W = d.width;
+  rcs.H = d.height;
+  rcs.N = d.n_views;
+  rcs.T = L->T;
+  rcs.tw = tw;
+  rcs.th = th;
+  rcs.ntx = L->ntx;
+  rcs.sh_degree = o.sh_degree;
+  rcs.heap_cap = heap_cap;
+  rcs.stack_cap = B->st.stack_bound;
+  rcs.focal = d.focal_px;
+  rcs.cx = d.width / 2.0;
+  rcs.cy = d.height / 2.0;
+  rcs.z_near = o.z_near;
+  rcs.alpha_max = o.alpha_max;
+  rcs.t_min = o.t_min;
+  for (int k = 0; k < 3; ++k) rcs.bg[k] = o.bg[k];
+  rcs.tgt = D->tgt.p ? D->tgt.as<int32_t>() : nullptr;
+  rcs.stats = nullptr;
+  if (C->prof >= 3) {
+    HIP_TRY(C->stats.ensure((size_t)kStatSlots * 3 * 8));
+    HIP_TRY(launch_fill_u64(C->stats.as<unsigned long long>(), kStatSlots * 3, 0ull, s));
+    rcs.stats = C->stats.as<unsigned long long>();
+  }
+  const int mk = C->begin(DL_STAGE_BLEND, s);
+  HIP_TRY(launch_rayorder(B->nodes.as<float>(), B->rec.as<float4>(), B->sh.as<float4>(), C->cams.as<double>(),
+                          L->off.as<uint32_t>(), L->ent.as<uint32_t>(), rcs, out_dev, s));
+  C->end(mk, s);
+  return DL_OK;
+}
+
 
 }  // extern "C"

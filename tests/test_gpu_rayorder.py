@@ -1,0 +1,170 @@
+"""Ray-order 3DGS (Alg. 3) on the GPU path against the FP64 oracle: sampled subpixels of the encoded image
+equal channel k of the oracle's ray (view V(x, 3y + k), its pixel or its repurposed source pixel) for several
+heap capacities, on sparse and dense scenes (rays with more hits than c_h), a single-view camera, a repurposed
+panel, an empty BVH and the full-size single-view workload (C ABI)."""
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+from oracle import rayorder as oro
+from oracle import render as orender
+from oracle import repurpose as orep
+from paper_2407_14053_amd import synth
+from tests.gpu_util import TOL, log, sample_subpixels
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2407_14053_amd import api
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _dense_scene(n=20000):
+    return synth.make_scene("uhd45").subset(np.arange(n))
+
+
+def _check(sc, d, c2w, img, cap, n, seed, src=None, opts=None, min_clean=None):
+    """Sampled subpixels against the oracle; returns (worst error on rays without a fragile decision, rays,
+    fragile rays, mean hits)."""
+    V = orender.view_map_of(d)
+    xs, ys, ks = sample_subpixels(d.height, d.width, n, seed)
+    n = len(xs)
+    vs = V[xs, 3 * ys + ks].astype(np.int64)
+    px, py = (xs, ys) if src is None else (src[0][xs, ys, ks], src[1][xs, ys, ks])
+    out = oro.render_rays(sc, d, c2w, vs, px, py, cap, opts)
+    got = img[xs, ys, ks].astype(np.float64)
+    exp = out.rgb[np.arange(n), ks]
+    clean = ~out.fragile
+    err = np.abs(got - exp)
+    worst = float(err[clean].max()) if clean.any() else 0.0
+    if worst > TOL:
+        i = int(np.argmax(np.where(clean, err, -1)))
+        log("  worst subpixel (x=%d y=%d k=%d v=%d): gpu %.7f oracle %.7f hits %d blended %d" % (
+            xs[i], ys[i], ks[i], vs[i], got[i], exp[i], out.hits[i], out.blended[i]))
+    assert clean.sum() >= (min_clean if min_clean is not None else 0.8 * n)
+    return worst, n, int((~clean).sum()), float(out.hits.mean())
+
+
+def test_bvh_stats(ctx):
+    from paper_2407_14053_amd import api
+    sc = synth.make_scene("tiny")
+    S = api.Scene(ctx, sc.arrays())
+    B = api.BVH(ctx, S)
+    st = B.stats()
+    lg = np.asarray(sc.opacity_logits, np.float32).astype(np.float64).ravel()
+    op = 1.0 / (1.0 + np.exp(-lg))
+    log("bvh", st)
+    assert st["n_gaussians"] == sc.n
+    assert st["n_prims"] == int((2.0 * np.log(op) + 2.0 * np.log(255.0) > 0).sum())
+    assert 1 <= st["stack_bound"] <= 256 and st["depth"] >= 2 and st["n_leaves"] >= st["n_prims"] / 4
+    B.close()
+    S.close()
+
+
+@pytest.mark.parametrize("cap", [1, 5, 16, 17, 40, 128])
+def test_rayorder_tiny_matches_oracle(ctx, cap):
+    from paper_2407_14053_amd import api
+    log("ray-order tiny c_h=%d" % cap)
+    d = synth.make_named_display("tiny")
+    sc = synth.make_scene("tiny")
+    c2w = synth.pose_sweep(8)[3]
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    B = api.BVH(ctx, S)
+    img = api.render_rayorder(ctx, B, D, c2w, cap).cpu().numpy()
+    assert np.isfinite(img).all()
+    again = api.render_rayorder(ctx, B, D, c2w, cap).cpu().numpy()
+    assert np.array_equal(img, again)
+    worst, n, fr, hits = _check(sc, d, c2w, img, cap, 400, 100 + cap)
+    log("  worst %.2e over %d subpixels (%d fragile), mean hits %.1f" % (worst, n, fr, hits))
+    assert worst <= TOL
+    for x in (B, D, S):
+        x.close()
+
+
+@pytest.mark.parametrize("cap", [8, 33, 128])
+def test_rayorder_dense_truncates_like_the_heap(ctx, cap):
+    """20000 Gaussians of the 300k scene: rays meet about 120 Gaussians, so small c_h cut the blend."""
+    from paper_2407_14053_amd import api
+    log("ray-order dense c_h=%d" % cap)
+    d = synth.make_display(96, 64, 6, F(1, 3), F(53, 10))
+    sc = _dense_scene()
+    c2w = synth.pose_sweep(8)[1]
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    B = api.BVH(ctx, S)
+    img = api.render_rayorder(ctx, B, D, c2w, cap).cpu().numpy()
+    worst, n, fr, hits = _check(sc, d, c2w, img, cap, 200, 7 + cap)
+    log("  worst %.2e over %d subpixels (%d fragile), mean hits %.1f" % (worst, n, fr, hits))
+    assert worst <= TOL and hits > cap / 2
+    for x in (B, D, S):
+        x.close()
+
+
+def test_rayorder_single_view(ctx):
+    from paper_2407_14053_amd import api
+    log("ray-order single view")
+    d = synth.make_display(160, 106, 1, F(1, 3), F(53, 10), baseline=0.0)
+    sc = _dense_scene(5000)
+    c2w = synth.pose_sweep(8)[6]
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    B = api.BVH(ctx, S)
+    img = api.render_rayorder(ctx, B, D, c2w, 64).cpu().numpy()
+    worst, n, fr, hits = _check(sc, d, c2w, img, 64, 300, 3)
+    log("  worst %.2e over %d subpixels (%d fragile), mean hits %.1f" % (worst, n, fr, hits))
+    assert worst <= TOL
+    for x in (B, D, S):
+        x.close()
+
+
+def test_rayorder_repurposed_panel(ctx):
+    from paper_2407_14053_amd import api
+    log("ray-order repurposed")
+    d = synth.make_display(64, 48, 45, F(1, 6), F(37, 5), repurpose_pw=2)
+    sc = synth.make_scene("tiny")
+    c2w = synth.pose_sweep(8)[2]
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    B = api.BVH(ctx, S)
+    img = api.render_rayorder(ctx, B, D, c2w, 32).cpu().numpy()
+    src = orep.repurpose_map(d.width, d.height, d.n_views, d.tan_slant, d.pitch, d.offset, d.repurpose_pw)
+    worst, n, fr, hits = _check(sc, d, c2w, img, 32, 300, 5, src=src)
+    log("  worst %.2e over %d subpixels (%d fragile)" % (worst, n, fr))
+    assert worst <= TOL
+    for x in (B, D, S):
+        x.close()
+
+
+def test_rayorder_empty_bvh_is_background(ctx):
+    from paper_2407_14053_amd import api
+    sc = synth.make_scene("fd64")
+    sc.opacity_logits[:] = -8.0          # opacity below 1/255: never hit, left out of the BVH
+    d = synth.make_named_display("fd64")
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    B = api.BVH(ctx, S)
+    assert B.stats()["n_prims"] == 0
+    bg = (0.1, 0.2, 0.3)
+    img = api.render_rayorder(ctx, B, D, synth.pose_front(), 16, opts=api.default_opts(bg=bg)).cpu().numpy()
+    assert np.array_equal(img, np.broadcast_to(np.float32(bg), img.shape))
+    for x in (B, D, S):
+        x.close()
+
+
+def test_rayorder_full_size_single_view_sampled(ctx):
+    """The benchmark's ray-order workload: 1600 x 1060 single view, 300k Gaussians, c_h = 128; sampled rays."""
+    from paper_2407_14053_amd import api
+    log("ray-order 1600x1060, 300k")
+    d = synth.make_display(1600, 1060, 1, F(1, 3), F(53, 10), baseline=0.0)
+    sc = synth.make_scene("uhd45")
+    c2w = synth.pose_sweep(8)[0]
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    B = api.BVH(ctx, S)
+    log("  bvh", B.stats())
+    img = api.render_rayorder(ctx, B, D, c2w, 128).cpu().numpy()
+    worst, n, fr, hits = _check(sc, d, c2w, img, 128, 40, 9, min_clean=30)
+    log("  worst %.2e over %d subpixels (%d fragile), mean hits %.1f" % (worst, n, fr, hits))
+    assert worst <= TOL
+    for x in (B, D, S):
+        x.close()
