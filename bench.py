@@ -405,6 +405,72 @@ def run_repurposed(args, identity_fps):
             "speedup_vs_identity_map": round(fps / identity_fps, 3) if identity_fps else None}
 
 
+def run_rayorder(args):
+    """Ray-order 3DGS (Alg. 3): the paper's heap-capacity study (one 1600 x 1060 view, c_h from 16 to 256) on the
+    workload's scene, then the panel's own rays at c_h = 128.  The BVH is built once per scene (host, offline)."""
+    import numpy as np
+    import torch
+
+    from paper_2407_14053_amd import api, synth
+
+    scene = synth.make_scene(args.workload)
+    disp = synth.make_named_display(args.workload)
+    single = synth.make_display(1600, 1060, 1, disp.tan_slant, disp.pitch, baseline=0.0)
+    poses = synth.pose_sweep(200) if args.workload == "uhd45" else synth.pose_orbit(120)
+    ctx = api.Context(0)
+    S = api.Scene(ctx, scene.arrays())
+    B = api.BVH(ctx, S)
+    bst = B.stats()
+    S.close()
+
+    def timed(D, cap, steps):
+        H, W = D.shape
+        out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+        for i in range(2):
+            api.render_rayorder(ctx, B, D, poses[i], cap, out=out)
+        torch.cuda.synchronize()
+        ms = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            api.render_rayorder(ctx, B, D, poses[(2 + i) % len(poses)], cap, out=out)
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        wall = time.perf_counter() - t0
+        ctx.set_profiling(3)
+        api.render_rayorder(ctx, B, D, poses[2], cap, out=out)
+        st = ctx.frame_stats()
+        ctx.set_profiling(1)
+        api.render_rayorder(ctx, B, D, poses[2], cap, out=out)
+        kern = ctx.frame_stats()["stage_ms"]["blend"]
+        ctx.set_profiling(0)
+        rays = max(st["rays"], 1)
+        return {"c_h": cap, "frames_per_s": round(steps / wall, 3), "p50_ms": round(float(np.percentile(ms, 50)), 3),
+                "kernel_ms": round(kern, 3), "rays": int(st["rays"]),
+                "gaussian_tests_per_ray": round(st["evaluations"] / rays, 2),
+                "blended_per_ray": round(st["blends"] / rays, 2),
+                "rays_per_s": round(st["rays"] / (kern * 1e-3), 1) if kern > 0 else None}
+
+    D1 = api.Display(ctx, single)
+    rows = [timed(D1, cap, args.rayorder_steps) for cap in (16, 32, 64, 128, 256)]
+    D1.close()
+    for r in rows:
+        print("ray-order 1600x1060, c_h %3d: %.2f frames/s (kernel %.3f ms, %.1f Gaussian tests and %.1f blends per "
+              "ray)" % (r["c_h"], r["frames_per_s"], r["kernel_ms"], r["gaussian_tests_per_ray"], r["blended_per_ray"]),
+              file=sys.stderr, flush=True)
+    D = api.Display(ctx, disp)
+    panel = timed(D, 128, max(2, args.rayorder_steps // 2))
+    D.close()
+    print("ray-order %s panel rays, c_h 128: %.2f frames/s (kernel %.3f ms)" % (
+        args.workload, panel["frames_per_s"], panel["kernel_ms"]), file=sys.stderr, flush=True)
+    B.close()
+    ctx.close()
+    return {"bvh": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in bst.items()},
+            "single_view_1600x1060": rows, "panel_c_h_128": panel}
+
+
 WORKLOADS = {
     "uhd45": "directl_uhd45: 300k Gaussians (uniform [-2,2]^3, SH3), 3840x2160 panel x 3 subpixels, N=45 views, "
              "slant atan(1/6), pitch 37/5 subpixels, baseline 0.6, FOV 40 deg, 200-pose +-10 deg sweep",
@@ -524,6 +590,8 @@ def main():
                          "(0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (calibrates HBM byte counters)")
+    ap.add_argument("--rayorder-steps", type=int, default=4,
+                    help="frames per ray-order configuration (0: skip the ray-order rows)")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -540,6 +608,8 @@ def main():
         res["repurposed"] = run_repurposed(args, res["value"])
     if not args.no_standard:
         res["multiview"] = run_grid(args)
+    if args.rayorder_steps > 0:
+        res["rayorder"] = run_rayorder(args)
     if not args.no_backward:
         res["training_step"] = run_backward(args)
     if not args.no_serve:

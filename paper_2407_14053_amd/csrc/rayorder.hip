@@ -19,7 +19,6 @@
 namespace dl {
 namespace {
 
-constexpr int kRoundKeys = 16;
 constexpr float kLog2e = 1.4426950408889634f;
 
 __device__ inline void cswap(float& ta, uint32_t& ra, float& tb, uint32_t& rb) {
@@ -62,7 +61,7 @@ __device__ inline void peak(const float4& r0, const float4& r1, const float4& r2
   q = rx * arx + ry * ary + rz * arz;
 }
 
-template <bool STATS>
+template <bool STATS, int kRoundKeys>
 __global__ __launch_bounds__(64) void rayorder_kernel(const float* __restrict__ nodes, const float4* __restrict__ rec,
                                                       const float4* __restrict__ shl, const double* __restrict__ cams,
                                                       const uint32_t* __restrict__ ray_off,
@@ -177,14 +176,18 @@ __global__ __launch_bounds__(64) void rayorder_kernel(const float* __restrict__ 
               ++sp;
             }
         }
-        // blend this round's keys in order
+        // blend this round's keys in order (taken from the front of the buffer, which shifts down: no dynamic
+        // register indexing)
+        const bool full = kb[kRoundKeys - 1] != ~0ull;
+#pragma unroll 1
+        for (int i = 0; i < kRoundKeys && !done; ++i) {
+          const uint64_t key = kb[0];
 #pragma unroll
-        for (int i = 0; i < kRoundKeys; ++i) {
-          if (done) continue;
-          const uint64_t key = kb[i];
+          for (int k = 0; k < kRoundKeys - 1; ++k) kb[k] = kb[k + 1];
+          kb[kRoundKeys - 1] = ~0ull;
           if (key == ~0ull) {
             done = true;
-            continue;
+            break;
           }
           const uint32_t j = (uint32_t)key;
           const float t = __uint_as_float((uint32_t)(key >> 32));
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(64) void rayorder_kernel(const float* __restrict__ 
           const float nt = T * (1.0f - alpha);
           if (nt < rc.t_min) {
             done = true;
-            continue;
+            break;
           }
           float Y[16];
 #pragma unroll
@@ -224,6 +227,7 @@ __global__ __launch_bounds__(64) void rayorder_kernel(const float* __restrict__ 
           lo_key = key + 1;
           if (used >= rc.heap_cap) done = true;
         }
+        if (!full) done = true;  // the round found every remaining hit
       }
       if (STATS) ++n_rays;
       const float c3[3] = {fmaf(T, rc.bg[0], C0), fmaf(T, rc.bg[1], C1), fmaf(T, rc.bg[2], C2)};
@@ -266,12 +270,19 @@ hipError_t launch_rayorder(const float* nodes, const float4* rec, const float4* 
   if (nb == 0) return hipSuccess;
   if (rc.stack_cap < 1 || rc.stack_cap > kBvhStackMax || nb >= (1ll << 31)) return hipErrorInvalidValue;
   const size_t lds = (size_t)rc.stack_cap * 64 * 4;
-  if (rc.stats)
-    hipLaunchKernelGGL(rayorder_kernel<true>, dim3((unsigned)nb), dim3(64), lds, s, nodes, rec, sh, cams, ray_off,
-                       ray_ent, rc, out);
-  else
-    hipLaunchKernelGGL(rayorder_kernel<false>, dim3((unsigned)nb), dim3(64), lds, s, nodes, rec, sh, cams, ray_off,
-                       ray_ent, rc, out);
+#define DL_RO_LAUNCH(K)                                                                                          \
+  if (rc.stats)                                                                                                  \
+    hipLaunchKernelGGL((rayorder_kernel<true, K>), dim3((unsigned)nb), dim3(64), lds, s, nodes, rec, sh, cams,  \
+                       ray_off, ray_ent, rc, out);                                                               \
+  else                                                                                                           \
+    hipLaunchKernelGGL((rayorder_kernel<false, K>), dim3((unsigned)nb), dim3(64), lds, s, nodes, rec, sh, cams, \
+                       ray_off, ray_ent, rc, out);
+  if (rc.heap_cap <= 16) {
+    DL_RO_LAUNCH(16)
+  } else {
+    DL_RO_LAUNCH(32)
+  }
+#undef DL_RO_LAUNCH
   return hipGetLastError();
 }
 
