@@ -134,11 +134,11 @@ __global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict_
       const uint32_t rk = gidx[base + threadIdx.x];
       const float4* src = vrec + (int64_t)rk * kRecF4;
       const float4 r1 = src[1], r2 = src[2];
+      const float lo = __builtin_amdgcn_logf(r2.x);
       sm[threadIdx.x * kRecF4 + 0] = src[0];
-      // the LDS copy carries, in place of the binning's Q limit, the blend's own: Q <= min(Q_cut, log2(o / a_min))
-      // holds exactly when q <= q_cut and o exp(-q/2) >= alpha_min (up to the rounding of the logarithm)
-      sm[threadIdx.x * kRecF4 + 1] = make_float4(r1.x, blend_qlim(r2.x, bc), r1.z, r1.w);
-      sm[threadIdx.x * kRecF4 + 2] = r2;
+      // the forward's staging (log2(o) and the bound on E = log2(o) - Q), with o itself in the unused slot
+      sm[threadIdx.x * kRecF4 + 1] = make_float4(r1.x, blend_elim(lo, bc), r2.x, r1.w);
+      sm[threadIdx.x * kRecF4 + 2] = make_float4(lo, r2.y, r2.z, r2.w);
       sg[threadIdx.x] = sorted[vG + rk];
     }
     for (int i = threadIdx.x; i < NT * kG; i += NT) (&part[0][0])[i] = 0.0f;
@@ -149,9 +149,9 @@ __global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict_
     if (__ballot(any) != 0ull) {
       for (int k = 0; k < n; ++k) {
         const float4 A = sm[k * kRecF4 + 0];
-        const float2 CQ = *reinterpret_cast<const float2*>(&sm[k * kRecF4 + 1]);
+        const float4 CQ = sm[k * kRecF4 + 1];  // conic C (scaled), E limit, opacity
         const float cC = CQ.x;
-        const float4 B = sm[k * kRecF4 + 2];
+        const float4 B = sm[k * kRecF4 + 2];    // log2(opacity), r, g, b
         float gr[kG];
 #pragma unroll
         for (int c = 0; c < kG; ++c) gr[c] = 0.0f;
@@ -160,11 +160,10 @@ __global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict_
         for (int j = 0; j < RPT; ++j) {
           // the forward's arithmetic, operation for operation
           const float dx = px[j] - A.x, dy = py[j] - A.y;
-          const float q = fmaf(A.z * dx, dx, fmaf(cC, dy, A.w * dx) * dy);
-          const float e2 = __builtin_amdgcn_exp2f(-q);
-          const float ga = B.x * e2;
+          const float E = fmaf(-fmaf(A.w, dy, A.z * dx), dx, fmaf(-(cC * dy), dy, B.x));
+          const float ga = __builtin_amdgcn_exp2f(E);  // o 2^-Q
           const float alpha = fminf(a_max, ga);
-          const bool ok = live[j] && (q <= CQ.y);
+          const bool ok = live[j] && (E >= CQ.y);
           const float tn = fmaf(-alpha, Tr[j], Tr[j]);
           const bool stop = ok && (tn < t_min);
           const bool take = ok && !stop;
@@ -181,7 +180,7 @@ __global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict_
             gr[8] += g2[j] * w;
             if (ga <= a_max) {
               const float dQ = -da * ln2 * ga;  // alpha = o 2^-Q
-              gr[5] += da * e2;
+              gr[5] += da * ga * __builtin_amdgcn_rcpf(CQ.z);  // d alpha / d o = 2^-Q
               gr[2] += dQ * dx * dx;
               gr[3] += dQ * dx * dy;
               gr[4] += dQ * dy * dy;

@@ -8,7 +8,9 @@
 //   q = d^T Sigma'^{-1} d,  alpha = min(alpha_max, o exp(-q/2)),  blend iff q <= q_cut and alpha >= alpha_min
 //   (tested as one bound on q per record),
 //   stop (without blending) when T (1 - alpha) < t_min,
-// with q held as Q = q log2(e)/2 (the record's conic is pre-scaled) and exp(-q/2) = 2^-Q (one v_exp_f32).
+// with q held as Q = q log2(e)/2 (the record's conic is pre-scaled) and o exp(-q/2) = 2^(log2(o) - Q): the
+// staged record carries log2(o), so the exponent comes out of the quadratic form's FMAs and alpha costs one
+// v_exp_f32 and a min.
 // A wavefront leaves the LDS chunk as soon as a ballot shows all its rays finished, and the workgroup
 // leaves the list when none of its lanes has a live ray.  The epilogue writes C + T bg into the owned
 // subpixels of the encoded image (DirectL) or into all three channels of the view image (standard).
@@ -103,11 +105,12 @@ __global__ __launch_bounds__(NT) void blend_kernel(const float4* __restrict__ re
       const uint32_t g = gidx[base + threadIdx.x];
       const float4* src = vrec + (int64_t)g * kRecF4;
       const float4 r1 = src[1], r2 = src[2];
+      const float lo = __builtin_amdgcn_logf(r2.x);  // log2(o)
       sm[threadIdx.x * kRecF4 + 0] = src[0];
-      // the LDS copy carries, in place of the binning's Q limit, the blend's own: Q <= min(Q_cut, log2(o / a_min))
-      // holds exactly when q <= q_cut and o exp(-q/2) >= alpha_min (up to the rounding of the logarithm)
-      sm[threadIdx.x * kRecF4 + 1] = make_float4(r1.x, blend_qlim(r2.x, bc), r1.z, r1.w);
-      sm[threadIdx.x * kRecF4 + 2] = r2;
+      // the LDS copy carries log2(o) in place of o and, in place of the binning's Q limit, the blend's bound on
+      // E = log2(o) - Q (see blend_elim)
+      sm[threadIdx.x * kRecF4 + 1] = make_float4(r1.x, blend_elim(lo, bc), r1.z, r1.w);
+      sm[threadIdx.x * kRecF4 + 2] = make_float4(lo, r2.y, r2.z, r2.w);
     }
     __syncthreads();
     bool any = false;
@@ -120,37 +123,43 @@ __global__ __launch_bounds__(NT) void blend_kernel(const float4* __restrict__ re
     if (__ballot(any) != 0ull) {
       for (int k = 0; k < n; ++k) {
         const float4 A = sm[k * kRecF4 + 0];    // u, v, conic A, B (scaled)
-        const float2 CQ = *reinterpret_cast<const float2*>(&sm[k * kRecF4 + 1]);  // conic C (scaled), Q limit
+        const float2 CQ = *reinterpret_cast<const float2*>(&sm[k * kRecF4 + 1]);  // conic C (scaled), E limit
         const float cC = CQ.x;
-        const float4 B = sm[k * kRecF4 + 2];    // opacity, r, g, b
-        bool any_live = false;
+        const float4 B = sm[k * kRecF4 + 2];    // log2(opacity), r, g, b
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
           if (j > 0 && !slot[j]) continue;
           // per-pixel rule and front-to-back update, without branches:
+          //   E = log2(o) - Q = log2(o) - C dy^2 - (A dx + B dy) dx, alpha = min(alpha_max, 2^E)
           //   T' = T (1 - alpha) as one FMA, the colour weight as T - T' (alpha T up to one rounding of T')
+          // A finished ray keeps T < 0: then T' < 0 < t_min, so an accepted record only "stops" it again, and
+          // the stop writes -|T|, which leaves it unchanged; no liveness test is needed per pair.
           const float dx = px[j] - A.x, dy = py[j] - A.y;
-          const float q = fmaf(A.z * dx, dx, fmaf(cC, dy, A.w * dx) * dy);
-          const float alpha = fminf(a_max, B.x * __builtin_amdgcn_exp2f(-q));
+          const float E = fmaf(-fmaf(A.w, dy, A.z * dx), dx, fmaf(-(cC * dy), dy, B.x));
+          const float alpha = fminf(a_max, __builtin_amdgcn_exp2f(E));
           const float T = sT[j];
           const float tn = fmaf(-alpha, T, T);
-          const bool live = T > 0.0f;
-          const bool ok = live && (q <= CQ.y);
+          const bool ok = E >= CQ.y;
           const bool stop = ok && (tn < t_min);
-          const bool take = ok && !stop;
+          const bool take = ok != stop;  // ok and not stop (stop implies ok): one scalar mask operation
           const float Tt = take ? tn : T;
           const float w = T - Tt;
           if (STATS) {
-            nev[j] += live ? 1u : 0u;
+            nev[j] += T > 0.0f ? 1u : 0u;
             nbl[j] += take ? 1u : 0u;
           }
           C0[j] = fmaf(w, B.y, C0[j]);
           C1[j] = fmaf(w, B.z, C1[j]);
           C2[j] = fmaf(w, B.w, C2[j]);
-          sT[j] = stop ? -T : Tt;
-          any_live |= live && !stop;
+          sT[j] = stop ? -fabsf(T) : Tt;
         }
-        if (__ballot(any_live) == 0ull) break;
+        // leave the chunk once no ray of the wavefront is live (checked every 4 records)
+        if ((k & 3) == 3) {
+          bool any_live = false;
+#pragma unroll
+          for (int j = 0; j < RPT; ++j) any_live |= sT[j] > 0.0f;
+          if (__ballot(any_live) == 0ull) break;
+        }
       }
     }
     bool mine = false;

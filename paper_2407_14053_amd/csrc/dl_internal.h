@@ -63,10 +63,11 @@ struct BlendConst {
 };
 constexpr int kStatSlots = 1024;
 
-// The blend's bound on the scaled quadratic form Q = q log2(e)/2 for a record of opacity o: a pair blends iff
-// Q <= min(Q_cut, log2 o - log2 alpha_min), i.e. q <= q_cut and o exp(-q/2) >= alpha_min.
-__device__ inline float blend_qlim(float o, const BlendConst& bc) {
-  return fminf(bc.q_cut, __builtin_amdgcn_logf(o) - bc.log2_alpha_min);
+// The blend's bound on E = log2(o) - Q (Q = q log2(e)/2, the scaled quadratic form) for a record with
+// lo = log2(o): a pair blends iff E >= max(lo - Q_cut, log2 alpha_min), i.e. q <= q_cut and
+// o exp(-q/2) >= alpha_min.
+__device__ inline float blend_elim(float lo, const BlendConst& bc) {
+  return fmaxf(lo - bc.q_cut, bc.log2_alpha_min);
 }
 
 // Depth chunk: ranks [n_v num_lo / den, n_v num_hi / den) of every view; `stride` bounds its length.
