@@ -77,7 +77,7 @@ class Opts:
     # fragile-decision bands (relative), derived from the FP32 error of the GPU's blend
     band_q: float = 2e-4
     band_a: float = 2e-4
-    band_z: float = 2.0 ** -35
+    band_z: float = 2.0 ** -30
     band_znear: float = 1e-9
     eps_alpha: float = 3e-5
     eps_mul: float = 1e-6

@@ -40,9 +40,11 @@ struct ProjConst {
   int key_e0;  // biased FP64 exponent of z_near: depth keys count exponents from it
 };
 
-// Depth keys: (exponent of z - key_e0, saturated at kDepthExpMax) << 36 | top 36 mantissa bits of the FP64 z.
-// Monotone in z (strictly, to 2^-36 relative, below 2^kDepthExpMax z_near); culled items carry kDepthCulled.
-constexpr int kDepthKeyBits = 41;
+// Depth keys: (exponent of z - key_e0, saturated at kDepthExpMax) << 31 | top 31 mantissa bits of the FP64 z.
+// Monotone in z (strictly, to 2^-31 relative, below 2^kDepthExpMax z_near); culled items carry kDepthCulled.
+// 36 bits: four radix passes of 9 bits.
+constexpr int kDepthMantBits = 31;
+constexpr int kDepthKeyBits = 5 + kDepthMantBits;
 constexpr int kDepthExpMax = 30;
 constexpr uint64_t kDepthCulled = (1ull << kDepthKeyBits) - 1;
 

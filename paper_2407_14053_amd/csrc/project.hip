@@ -5,8 +5,8 @@
 // perspective map, Sigma' = J W Sigma W^T J^T + h I, its inverse (the conic), the projected mean and the
 // cutoff ellipse, the depth key and the view-dependent colour.  Geometry runs in FP64 (the chip's vector
 // FP64 rate makes this free next to the memory traffic) and the record is rounded to FP32 once, so the
-// FP32 blend starts from correctly rounded inputs; depth keys keep 36 mantissa bits of the FP64 z and its
-// exponent counted from that of z_near (41 bits: five radix passes).
+// FP32 blend starts from correctly rounded inputs; depth keys keep 31 mantissa bits of the FP64 z and its
+// exponent counted from that of z_near (36 bits: four radix passes of 9 bits).
 // The conic is stored pre-multiplied by log2(e)/2 (A, C) and log2(e) (B), so that the blend evaluates
 // alpha = o * 2^-(A dx^2 + B dx dy + C dy^2) with one hardware exp2.
 #include "dl_internal.h"
@@ -115,8 +115,9 @@ __global__ __launch_bounds__(256, 4) void project_kernel(const float* __restrict
         r[8] = o32; r[9] = rgb[0]; r[10] = rgb[1]; r[11] = rgb[2];
         const uint64_t zb = (uint64_t)__double_as_longlong(Z);
         const int e = (int)(zb >> 52) - pc.key_e0;  // >= 0 since Z > z_near
-        key = e > kDepthExpMax ? (((uint64_t)(kDepthExpMax + 1) << 36) - 1)
-                               : (((uint64_t)e << 36) | ((zb >> 16) & ((1ull << 36) - 1)));
+        key = e > kDepthExpMax ? (((uint64_t)(kDepthExpMax + 1) << kDepthMantBits) - 1)
+                               : (((uint64_t)e << kDepthMantBits) |
+                                  ((zb >> (52 - kDepthMantBits)) & ((1ull << kDepthMantBits) - 1)));
       }
     }
     const int64_t o = (int64_t)v * pc.G + i;

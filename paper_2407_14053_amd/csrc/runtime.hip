@@ -1,7 +1,7 @@
 // Host runtime of the light-field renderer: the C ABI of include/directl.h on top of the gfx950 kernels.
 //
 // Frame (both paths):
-//   cameras (FP64, host) -> project (all views) -> per-view depth sort (segmented radix sort, 48-bit keys)
+//   cameras (FP64, host) -> project (all views) -> per-view depth sort (segmented radix sort, 36-bit keys)
 //   -> for each depth chunk, front to back: count keys of live (view, tile) pairs -> scan -> emit
 //      (view, tile) keys -> stable radix partition by key -> list bounds -> blend (carrying per-ray state,
 //      retiring tiles whose rays have all terminated)
