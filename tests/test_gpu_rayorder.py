@@ -168,3 +168,25 @@ def test_rayorder_full_size_single_view_sampled(ctx):
     assert worst <= TOL
     for x in (B, D, S):
         x.close()
+
+
+def test_rayorder_clustered_3m_sampled(ctx):
+    """3M Gaussians, 80% in 64 tight blobs: the BVH over dense clusters (depth, stack bound) and sampled rays of a
+    640x360 single view at c_h = 64 against the oracle."""
+    from paper_2407_14053_amd import api
+    log("ray-order clustered 3M")
+    d = synth.make_display(640, 360, 1, F(1, 3), F(53, 10), baseline=0.0)
+    sc = synth.make_scene("8k60")
+    c2w = synth.pose_orbit(120)[0]
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    B = api.BVH(ctx, S)
+    st = B.stats()
+    log("  bvh", st)
+    assert st["stack_bound"] <= 256 and st["n_prims"] > 0.9 * sc.n
+    img = api.render_rayorder(ctx, B, D, c2w, 64).cpu().numpy()
+    assert np.isfinite(img).all()
+    worst, n, fr, hits = _check(sc, d, c2w, img, 64, 16, 17, min_clean=28)
+    log("  worst %.2e over %d subpixels (%d fragile), mean hits %.1f" % (worst, n, fr, hits))
+    assert worst <= TOL
+    for x in (B, D, S):
+        x.close()
