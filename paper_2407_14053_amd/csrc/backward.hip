@@ -290,6 +290,8 @@ __device__ inline float raw_colour_f32(int deg, float x, float y, float z, const
   return a;
 }
 
+// DEG: SH degree as a compile-time constant, so that the coefficient and gradient arrays stay in registers
+template <int DEG>
 __global__ __launch_bounds__(128) void project_bwd_kernel(const float* __restrict__ soa, const double* __restrict__ cams,
                                                           ProjConst pc, const float* __restrict__ acc,
                                                           float* __restrict__ g_means, float* __restrict__ g_log_scales,
@@ -299,8 +301,8 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(const float* __restric
   if (i >= pc.G) return;
   const int64_t np = pc.n_pad, G = pc.G;
   const int64_t NG = (int64_t)pc.N * G;
-  const int deg = pc.sh_degree;
-  const int nb = (deg + 1) * (deg + 1);
+  constexpr int deg = DEG;
+  constexpr int nb = (DEG + 1) * (DEG + 1);
   const double mu[3] = {soa[kRowMean * np + i], soa[(kRowMean + 1) * np + i], soa[(kRowMean + 2) * np + i]};
   double q4[4] = {soa[kRowQuat * np + i], soa[(kRowQuat + 1) * np + i], soa[(kRowQuat + 2) * np + i],
                   soa[(kRowQuat + 3) * np + i]};
@@ -321,10 +323,12 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(const float* __restric
                       R[a * 3 + 2] * s2[2] * R[b * 3 + 2];
   const double opac = 1.0 / (1.0 + exp(-(double)soa[kRowLogit * np + i]));
   float shc[48];
-  for (int k = 0; k < nb * 3; ++k) shc[k] = soa[(kRowSH + k) * np + i];
+#pragma unroll
+  for (int k = 0; k < 48; ++k) shc[k] = k < nb * 3 ? soa[(kRowSH + k) * np + i] : 0.0f;
 
   double gmu[3] = {0, 0, 0}, gSig[9] = {0}, glogit = 0;
   float gsh[48];  // FP32: the SH colour itself is FP32
+#pragma unroll
   for (int k = 0; k < 48; ++k) gsh[k] = 0.0f;
   const double ks = 0.72134752044448170368;
   const double f = pc.focal;
@@ -403,10 +407,12 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(const float* __restric
     float Yb[16], dYx[16], dYy[16], dYz[16];
     sh_basis_grad<float>(deg, dir[0], dir[1], dir[2], Yb, dYx, dYy, dYz);
     float gdir[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
       const float gcol = ag[6 + c];
       if (gcol == 0.0f) continue;
       if (!(raw_colour_f32(deg, dir[0], dir[1], dir[2], shc, c) > 0.0f)) continue;
+#pragma unroll
       for (int l = 0; l < nb; ++l) {
         gsh[l * 3 + c] += gcol * Yb[l];
         gdir[0] += gcol * shc[l * 3 + c] * dYx[l];
@@ -447,6 +453,7 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(const float* __restric
   for (int k = 0; k < 4; ++k) g_quats[i * 4 + k] = (float)((dq[k] - dqh * qh[k]) / qnorm);
   for (int k = 0; k < 3; ++k) g_means[i * 3 + k] = (float)gmu[k];
   g_logits[i] = (float)glogit;
+#pragma unroll
   for (int k = 0; k < 48; ++k) g_sh[i * 48 + k] = gsh[k];
 }
 
@@ -496,8 +503,25 @@ hipError_t launch_blend_backward(const float4* rec, const uint32_t* tile_start, 
 hipError_t launch_project_backward(const float* soa, const double* cams, const ProjConst& pc, const float* acc,
                                    float* g_means, float* g_log_scales, float* g_quats, float* g_logits, float* g_sh,
                                    hipStream_t s) {
-  hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)((pc.G + 127) / 128)), dim3(128), 0, s, soa, cams, pc, acc,
-                     g_means, g_log_scales, g_quats, g_logits, g_sh);
+  const dim3 grid((unsigned)((pc.G + 127) / 128));
+  switch (pc.sh_degree) {
+    case 0:
+      hipLaunchKernelGGL(project_bwd_kernel<0>, grid, dim3(128), 0, s, soa, cams, pc, acc, g_means, g_log_scales,
+                         g_quats, g_logits, g_sh);
+      break;
+    case 1:
+      hipLaunchKernelGGL(project_bwd_kernel<1>, grid, dim3(128), 0, s, soa, cams, pc, acc, g_means, g_log_scales,
+                         g_quats, g_logits, g_sh);
+      break;
+    case 2:
+      hipLaunchKernelGGL(project_bwd_kernel<2>, grid, dim3(128), 0, s, soa, cams, pc, acc, g_means, g_log_scales,
+                         g_quats, g_logits, g_sh);
+      break;
+    default:
+      hipLaunchKernelGGL(project_bwd_kernel<3>, grid, dim3(128), 0, s, soa, cams, pc, acc, g_means, g_log_scales,
+                         g_quats, g_logits, g_sh);
+      break;
+  }
   return hipGetLastError();
 }
 
