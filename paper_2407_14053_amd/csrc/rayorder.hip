@@ -62,7 +62,7 @@ __device__ inline void peak(const float4& r0, const float4& r1, const float4& r2
 }
 
 template <bool STATS, int kRoundKeys>
-__global__ __launch_bounds__(64) void rayorder_kernel(const float* __restrict__ nodes, const float4* __restrict__ rec,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void rayorder_kernel(const float* __restrict__ nodes, const float4* __restrict__ rec,
                                                       const float4* __restrict__ shl, const double* __restrict__ cams,
                                                       const uint32_t* __restrict__ ray_off,
                                                       const uint32_t* __restrict__ ray_ent, RoConst rc,
@@ -139,23 +139,25 @@ __global__ __launch_bounds__(64) void rayorder_kernel(const float* __restrict__ 
           const float4 own0 = nd[14], own1 = nd[15];
           if (slab(own0.x, own0.y, own0.z, own0.w, own1.x, own1.y, ox, oy, oz, ix, iy, iz, tlo, thi) == INFINITY)
             continue;
-          const float4 lx0 = nd[0], lx1 = nd[1], ly0 = nd[2], ly1 = nd[3], lz0 = nd[4], lz1 = nd[5];
-          const float4 hx0 = nd[6], hx1 = nd[7], hy0 = nd[8], hy1 = nd[9], hz0 = nd[10], hz1 = nd[11];
-          const float4 rf0 = nd[12], rf1 = nd[13];
-          const float lx[8] = {lx0.x, lx0.y, lx0.z, lx0.w, lx1.x, lx1.y, lx1.z, lx1.w};
-          const float ly[8] = {ly0.x, ly0.y, ly0.z, ly0.w, ly1.x, ly1.y, ly1.z, ly1.w};
-          const float lz[8] = {lz0.x, lz0.y, lz0.z, lz0.w, lz1.x, lz1.y, lz1.z, lz1.w};
-          const float hx[8] = {hx0.x, hx0.y, hx0.z, hx0.w, hx1.x, hx1.y, hx1.z, hx1.w};
-          const float hy[8] = {hy0.x, hy0.y, hy0.z, hy0.w, hy1.x, hy1.y, hy1.z, hy1.w};
-          const float hz[8] = {hz0.x, hz0.y, hz0.z, hz0.w, hz1.x, hz1.y, hz1.z, hz1.w};
+          // the child boxes in two halves of four (fewer registers live at once)
           float tn[8];
-          uint32_t cr[8] = {__float_as_uint(rf0.x), __float_as_uint(rf0.y), __float_as_uint(rf0.z),
-                            __float_as_uint(rf0.w), __float_as_uint(rf1.x), __float_as_uint(rf1.y),
-                            __float_as_uint(rf1.z), __float_as_uint(rf1.w)};
+          uint32_t cr[8];
 #pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            const float tt = slab(lx[c], ly[c], lz[c], hx[c], hy[c], hz[c], ox, oy, oz, ix, iy, iz, tlo, thi);
-            tn[c] = cr[c] == kBvhEmpty ? INFINITY : tt;
+          for (int h = 0; h < 2; ++h) {
+            const float4 lx = nd[0 + h], ly = nd[2 + h], lz = nd[4 + h];
+            const float4 hx = nd[6 + h], hy = nd[8 + h], hz = nd[10 + h], rf = nd[12 + h];
+            const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, lya[4] = {ly.x, ly.y, ly.z, ly.w};
+            const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
+            const float hya[4] = {hy.x, hy.y, hy.z, hy.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
+            const uint32_t ra[4] = {__float_as_uint(rf.x), __float_as_uint(rf.y), __float_as_uint(rf.z),
+                                    __float_as_uint(rf.w)};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const float tt = slab(lxa[c], lya[c], lza[c], hxa[c], hya[c], hza[c], ox, oy, oz, ix, iy, iz, tlo, thi);
+              tn[4 * h + c] = ra[c] == kBvhEmpty ? INFINITY : tt;
+              cr[4 * h + c] = ra[c];
+            }
+            if (h == 0) __builtin_amdgcn_sched_barrier(0);  // keep the second half's loads after the first's use
           }
           // sort the 8 children by entry distance (19 compare-exchanges)
           cswap(tn[0], cr[0], tn[1], cr[1]); cswap(tn[2], cr[2], tn[3], cr[3]);
