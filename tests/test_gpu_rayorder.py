@@ -190,3 +190,29 @@ def test_rayorder_clustered_3m_sampled(ctx):
     assert worst <= TOL
     for x in (B, D, S):
         x.close()
+
+
+def test_rayorder_rejects_bad_arguments(ctx):
+    import ctypes
+
+    from paper_2407_14053_amd import api
+    d = synth.make_named_display("fd64")
+    sc = synth.make_scene("fd64")
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    B = api.BVH(ctx, S)
+    for cap in (0, -3, (1 << 24) + 1):
+        with pytest.raises(api.DLError) as e:
+            api.render_rayorder(ctx, B, D, synth.pose_front(), cap)
+        assert e.value.code == api.DL_EINVAL
+    lib = api.load()
+    pose = api.make_pose(synth.pose_front())
+    o = api.default_opts()
+    out = ctypes.c_void_p(0)
+    assert lib.dl_render_rayorder(ctx.h, B.h, D.h, ctypes.byref(pose), ctypes.byref(o), 16, out, None) == api.DL_EINVAL
+    assert lib.dl_render_rayorder(ctx.h, None, D.h, ctypes.byref(pose), ctypes.byref(o), 16, out, None) == api.DL_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.dl_bvh_build(ctx.h, None, None, None, ctypes.byref(h)) == api.DL_EINVAL
+    st = api.dl_bvh_stats()
+    assert lib.dl_bvh_get_stats(None, ctypes.byref(st)) == api.DL_EINVAL
+    for x in (B, D, S):
+        x.close()
