@@ -108,6 +108,7 @@ struct dl_ctx {
       state, dtotal, gacc;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
   double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
+  uint32_t* live_host = nullptr;  // pinned: live tiles per view after the first depth chunk (eager frames)
   // profiling: 0 off, 1 HIP events around the blend launches, 2 around every stage, 3 every stage and the
   // blend's work counters
   int prof = 0;
@@ -636,6 +637,16 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     if (c + 1 < kChunks)
       HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), total, s));
     C->end(mk, s);
+    if (c == 0 && kChunks > 1 && mode.finish) {
+      // an eager frame (it synchronises at its end anyway) reads the live tiles after the first chunk: when every
+      // tile's rays have terminated, every tile has written its pixels and the later chunks would only launch
+      // empty kernels, so they are skipped (a captured frame keeps them: its launches are fixed)
+      HIP_TRY(hipMemcpyAsync(C->live_host, C->live.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      uint64_t nlive = 0;
+      for (int v = 0; v < N; ++v) nlive += C->live_host[v];
+      if (nlive == 0) break;
+    }
     if (c == 0 && kChunks > 1) {
       // the backs of the views that still have a live tile
       mk = C->begin(DL_STAGE_DEPTH_SORT, s);
@@ -725,7 +736,10 @@ int dl_create(int device, dl_ctx** out) {
   HIP_TRY(hipSetDevice(device));
   dl_ctx* c = new dl_ctx();
   c->device = device;
-  if (hipHostMalloc((void**)&c->cams_host, 256 * kCamDoubles * 8, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&c->cams_host, 256 * kCamDoubles * 8, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->live_host, 256 * 4, hipHostMallocDefault) != hipSuccess) {
+    if (c->cams_host) (void)hipHostFree(c->cams_host);
+    if (c->live_host) (void)hipHostFree(c->live_host);
     delete c;
     return fail(DL_ENOMEM, "pinned camera staging");
   }
@@ -738,6 +752,7 @@ void dl_destroy(dl_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   if (c->cams_host) (void)hipHostFree(c->cams_host);
+  if (c->live_host) (void)hipHostFree(c->live_host);
   delete c;
 }
 
