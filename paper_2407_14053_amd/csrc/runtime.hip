@@ -7,7 +7,9 @@
 //      retiring tiles whose rays have all terminated)
 //   ; the standard path then interlaces its N views (Alg. 1).
 // Every launch has a static grid; data-dependent sizes (visible counts, key counts) stay on the device.  The
-// only host synchronisation is the end-of-frame check that no chunk overflowed the key capacity.
+// host synchronisations of an eager frame are the end-of-frame check that no chunk overflowed the key capacity and,
+// after the first depth chunk, the read of the live tiles that lets it skip later chunks with nothing left to
+// blend; a frame captured into a graph has neither.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
