@@ -1,6 +1,6 @@
 """Oracle (test infrastructure only): ray-order 3DGS, Alg. 3 of the paper (Sec. "Ray-Order 3DGS"), in FP64.
 
-Nothing in the product imports this module; only tests and the benchmark's CPU-baseline leg use it.
+Nothing in the product imports this module; only tests use it.
 
 For a ray with origin o and unit direction d, and a Gaussian j with mean mu, covariance
 Sigma = R S S^T R^T (R from the normalised quaternion (w, x, y, z), S = diag(exp(log-scale)), Eq. (8)) and
