@@ -421,7 +421,6 @@ def run_rayorder(args):
     S = api.Scene(ctx, scene.arrays())
     B = api.BVH(ctx, S)
     bst = B.stats()
-    S.close()
 
     def timed(D, cap, steps):
         H, W = D.shape
@@ -454,11 +453,26 @@ def run_rayorder(args):
                 "rays_per_s": round(st["rays"] / (kern * 1e-3), 1) if kern > 0 else None}
 
     D1 = api.Display(ctx, single)
-    rows = [timed(D1, cap, args.rayorder_steps) for cap in (16, 32, 64, 128, 256)]
+    caps = (16, 32, 64, 128, 256)
+    rows = [timed(D1, cap, args.rayorder_steps) for cap in caps]
+    # image quality against c_h (the other column of the paper's heap-capacity table), on this synthetic scene:
+    # PSNR of each c_h's image against c_h = 256 (what truncating the heap loses) and against the rasterized
+    # render of the same view (a different image by construction); colours clamped to [0, 1]
+    def psnr(a, b):
+        mse = float(torch.mean((a.clamp(0, 1) - b.clamp(0, 1)) ** 2))
+        return round(10.0 * np.log10(1.0 / mse), 2) if mse > 0 else None
+    imgs = {cap: api.render_rayorder(ctx, B, D1, poses[2], cap).clone() for cap in caps}
+    raster = api.render(ctx, S, D1, poses[2]).clone()
+    for r in rows:
+        r["psnr_vs_c_h_256_db"] = psnr(imgs[r["c_h"]], imgs[256])
+        r["psnr_vs_raster_db"] = psnr(imgs[r["c_h"]], raster)
     D1.close()
+    S.close()
     for r in rows:
         print("ray-order 1600x1060, c_h %3d: %.2f frames/s (kernel %.3f ms, %.1f Gaussian tests and %.1f blends per "
-              "ray)" % (r["c_h"], r["frames_per_s"], r["kernel_ms"], r["gaussian_tests_per_ray"], r["blended_per_ray"]),
+              "ray; PSNR %s dB vs c_h 256, %s dB vs raster)" % (r["c_h"], r["frames_per_s"], r["kernel_ms"],
+                                                                 r["gaussian_tests_per_ray"], r["blended_per_ray"],
+                                                                 r["psnr_vs_c_h_256_db"], r["psnr_vs_raster_db"]),
               file=sys.stderr, flush=True)
     D = api.Display(ctx, disp)
     panel = timed(D, 128, max(2, args.rayorder_steps // 2))
