@@ -136,7 +136,8 @@ int dl_display_source_map(const dl_display* display, int32_t* out_dev, void* str
  * world-to-camera rotation rows (9), translation (3), camera centre (3), 0. */
 int dl_cameras(const dl_display* display, const dl_pose* pose, double* out_host);
 
-/* Projection only (Eq. (8)-(9) and the SH colour), for inspection: out_dev[N][n][12] float32 =
+/* Projection only (Eq. (8)-(9) and the SH colour), for inspection: out_dev[N][n][12] float32 (all zeros where
+ * the Gaussian is culled in that view) =
  * (u, v, A, B, C, Q_limit, ext_x, ext_y, opacity, r, g, b) where (u, v) is the projected mean in image
  * coordinates and A = a log2(e)/2, B = b log2(e), C = c log2(e)/2 for the conic [[a, b], [b, c]] = Sigma'^-1
  * (so that exp(-q/2) = 2^-(A dx^2 + B dx dy + C dy^2)); Q_limit is the tile-test cutoff on the same scale

@@ -63,33 +63,38 @@ __global__ __launch_bounds__(256, 4) void project_kernel(const float* __restrict
   const double ks = 0.72134752044448170368;  // log2(e) / 2
   for (int v = 0; v < pc.N; ++v) {
     const double* cam = cams + v * kCamDoubles;
-    const double X = cam[0] * mx + cam[1] * my + cam[2] * mz + cam[9];
-    const double Y = cam[3] * mx + cam[4] * my + cam[5] * mz + cam[10];
-    const double Z = cam[6] * mx + cam[7] * my + cam[8] * mz + cam[11];
+    // FP64 chain as explicit FMAs (one rounding per multiply-add)
+    const double X = fma(cam[0], mx, fma(cam[1], my, fma(cam[2], mz, cam[9])));
+    const double Y = fma(cam[3], mx, fma(cam[4], my, fma(cam[5], mz, cam[10])));
+    const double Z = fma(cam[6], mx, fma(cam[7], my, fma(cam[8], mz, cam[11])));
     bool vis = live && (Z > (double)pc.z_near) && (o32 >= pc.alpha_min);
     uint64_t key = kDepthCulled;
-    float r[12];
+    float r[12] = {};
     if (vis) {
       // T = J W, rows of the 2x3 product
       const double iz = 1.0 / Z;
       const double f = pc.focal;
+      const double fz = f * iz, xz = X * iz, yz = Y * iz;
       double T0[3], T1[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        T0[k] = f * iz * (cam[k] - X * iz * cam[6 + k]);
-        T1[k] = f * iz * (cam[3 + k] - Y * iz * cam[6 + k]);
+        T0[k] = fz * fma(-xz, cam[6 + k], cam[k]);
+        T1[k] = fz * fma(-yz, cam[6 + k], cam[3 + k]);
       }
       // Sigma' = T Sigma T^T + h I
-      const double S0[3] = {Sg[0] * T0[0] + Sg[1] * T0[1] + Sg[2] * T0[2], Sg[1] * T0[0] + Sg[3] * T0[1] + Sg[4] * T0[2],
-                            Sg[2] * T0[0] + Sg[4] * T0[1] + Sg[5] * T0[2]};
-      const double S1[3] = {Sg[0] * T1[0] + Sg[1] * T1[1] + Sg[2] * T1[2], Sg[1] * T1[0] + Sg[3] * T1[1] + Sg[4] * T1[2],
-                            Sg[2] * T1[0] + Sg[4] * T1[1] + Sg[5] * T1[2]};
-      const double ca = T0[0] * S0[0] + T0[1] * S0[1] + T0[2] * S0[2] + (double)pc.dilation;
-      const double cb = T1[0] * S0[0] + T1[1] * S0[1] + T1[2] * S0[2];
-      const double cc = T1[0] * S1[0] + T1[1] * S1[1] + T1[2] * S1[2] + (double)pc.dilation;
-      const double idet = 1.0 / (ca * cc - cb * cb);
-      const double u = f * X * iz + pc.cx;
-      const double w = f * Y * iz + pc.cy;
+      const double S0[3] = {fma(Sg[0], T0[0], fma(Sg[1], T0[1], Sg[2] * T0[2])),
+                            fma(Sg[1], T0[0], fma(Sg[3], T0[1], Sg[4] * T0[2])),
+                            fma(Sg[2], T0[0], fma(Sg[4], T0[1], Sg[5] * T0[2]))};
+      const double S1[3] = {fma(Sg[0], T1[0], fma(Sg[1], T1[1], Sg[2] * T1[2])),
+                            fma(Sg[1], T1[0], fma(Sg[3], T1[1], Sg[4] * T1[2])),
+                            fma(Sg[2], T1[0], fma(Sg[4], T1[1], Sg[5] * T1[2]))};
+      const double dil = (double)pc.dilation;
+      const double ca = fma(T0[0], S0[0], fma(T0[1], S0[1], fma(T0[2], S0[2], dil)));
+      const double cb = fma(T1[0], S0[0], fma(T1[1], S0[1], T1[2] * S0[2]));
+      const double cc = fma(T1[0], S1[0], fma(T1[1], S1[1], fma(T1[2], S1[2], dil)));
+      const double idet = 1.0 / fma(ca, cc, -(cb * cb));
+      const double u = fma(f, xz, pc.cx);
+      const double w = fma(f, yz, pc.cy);
       // conservative half-extents of the cutoff ellipse (FP32 square roots; the margins dwarf their error)
       const float ex = sqrtf((float)(qlim * ca)) * (1.0f + 1e-4f) + 1e-3f;
       const float ey = sqrtf((float)(qlim * cc)) * (1.0f + 1e-4f) + 1e-3f;
@@ -124,7 +129,9 @@ __global__ __launch_bounds__(256, 4) void project_kernel(const float* __restrict
     if (live) {
       keys[o] = key;
       if (vals) vals[o] = (uint32_t)i;
-      if (vis) {
+      {
+        // every live lane writes its record (zeros when culled): full 128-byte lines reach HBM, where the
+        // visible records alone, with holes in most lines, were written 20% slower despite 40% fewer bytes
         float4* dst = rec + o * kRecF4;
         dst[0] = make_float4(r[0], r[1], r[2], r[3]);
         dst[1] = make_float4(r[4], r[5], r[6], r[7]);
