@@ -40,6 +40,7 @@ def test_projected_records_match_oracle(ctx, case):
     for v in sorted({0, d.n_views // 2, d.n_views - 1}):
         o = orender.project(sc, R[v], t[v], eye[v], f, cx, cy, opts)
         vis = np.isfinite(depth[v])
+        assert not np.any(rec[v][~vis])  # a culled Gaussian's record is all zeros
         # visible on the GPU only in front of the near plane and with opacity able to reach alpha_min
         assert np.all(o[vis, 9] > opts.z_near)
         # every Gaussian whose cutoff ellipse certainly reaches a pixel centre must be visible
