@@ -6,10 +6,11 @@
 //      (view, tile) keys -> stable radix partition by key -> list bounds -> blend (carrying per-ray state,
 //      retiring tiles whose rays have all terminated)
 //   ; the standard path then interlaces its N views (Alg. 1).
-// Every launch has a static grid; data-dependent sizes (visible counts, key counts) stay on the device.  The
-// host synchronisations of an eager frame are the end-of-frame check that no chunk overflowed the key capacity and,
-// after the first depth chunk, the read of the live tiles that lets it skip later chunks with nothing left to
-// blend; a frame captured into a graph has neither.
+// Every launch has a static grid; data-dependent sizes (visible counts, key counts) stay on the device.  An
+// eager frame synchronises with the host after the first depth chunk, to read the live tiles (later chunks with
+// nothing left to blend are skipped) together with the key count; when later chunks run, or for the backward,
+// a second synchronisation at the end of the frame checks that no chunk overflowed the key capacity.  A frame
+// captured into a graph has neither.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -110,7 +111,9 @@ struct dl_ctx {
       state, dtotal, gacc;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
   double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
-  uint32_t* live_host = nullptr;  // pinned: live tiles per view after the first depth chunk (eager frames)
+  // pinned, read after the first depth chunk of eager frames: live tiles per view [256], that chunk's key count
+  // (8 bytes), visible Gaussians per view [256]
+  uint32_t* live_host = nullptr;
   // profiling: 0 off, 1 HIP events around the blend launches, 2 around every stage, 3 every stage and the
   // blend's work counters
   int prof = 0;
@@ -645,12 +648,28 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     if (c == 0 && kChunks > 1 && mode.finish) {
       // an eager frame (it synchronises at its end anyway) reads the live tiles after the first chunk: when every
       // tile's rays have terminated, every tile has written its pixels and the later chunks would only launch
-      // empty kernels, so they are skipped (a captured frame keeps them: its launches are fixed)
+      // empty kernels, so they are skipped (a captured frame keeps them: its launches are fixed).  The same
+      // readback brings the first chunk's key count: a frame that skips the later chunks is complete here, and
+      // its overflow check needs nothing more (a backward frame goes on to the projection's backward).
+      unsigned long long* keys_host = reinterpret_cast<unsigned long long*>(C->live_host + 256);
+      uint32_t* vis_counts = C->live_host + 258;
       HIP_TRY(hipMemcpyAsync(C->live_host, C->live.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(keys_host, total + 1, 8, hipMemcpyDeviceToHost, s));
+      if (C->prof) HIP_TRY(hipMemcpyAsync(vis_counts, C->vis.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       uint64_t nlive = 0;
       for (int v = 0; v < N; ++v) nlive += C->live_host[v];
-      if (nlive == 0) break;
+      if (nlive == 0) {
+        if (bwd) break;
+        C->keys = (int64_t)*keys_host;
+        if (C->prof)
+          for (int v = 0; v < N; ++v) C->visible += vis_counts[v];
+        if (*keys_host > cap) {
+          *need = *keys_host;
+          return DL_ECAP;
+        }
+        return DL_OK;
+      }
     }
     if (c == 0 && kChunks > 1) {
       // the backs of the views that still have a live tile
@@ -742,7 +761,7 @@ int dl_create(int device, dl_ctx** out) {
   dl_ctx* c = new dl_ctx();
   c->device = device;
   if (hipHostMalloc((void**)&c->cams_host, 256 * kCamDoubles * 8, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->live_host, 256 * 4, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->live_host, 256 * 4 + 8 + 256 * 4, hipHostMallocDefault) != hipSuccess) {
     if (c->cams_host) (void)hipHostFree(c->cams_host);
     if (c->live_host) (void)hipHostFree(c->live_host);
     delete c;
