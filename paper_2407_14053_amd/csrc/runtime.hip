@@ -646,7 +646,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
       HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), total, s));
     C->end(mk, s);
     if (c == 0 && kChunks > 1 && mode.finish) {
-      // an eager frame (it synchronises at its end anyway) reads the live tiles after the first chunk: when every
+      // an eager frame (its caller waits for it anyway) reads the live tiles after the first chunk: when every
       // tile's rays have terminated, every tile has written its pixels and the later chunks would only launch
       // empty kernels, so they are skipped (a captured frame keeps them: its launches are fixed).  The same
       // readback brings the first chunk's key count: a frame that skips the later chunks is complete here, and
