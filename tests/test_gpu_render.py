@@ -97,6 +97,30 @@ def test_key_capacity_overflow_regrows(ctx):
     assert np.array_equal(std.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("case", ["tiny", "uhd45"])
+def test_frame_stats_count_visible_pairs(ctx, case):
+    """A profiled frame reports as visible exactly the (view, Gaussian) pairs the projection gives a depth, and a
+    key count, whether the frame ends after its first depth chunk (no tile live) or runs the later one."""
+    from paper_2407_14053_amd import api
+    log("frame stats", case)
+    d = synth.make_named_display(case)
+    sc = synth.make_scene(case)
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    c2w = synth.pose_sweep(8)[2]
+    _, depth = api.project(ctx, S, D, c2w)
+    n_vis = int(np.isfinite(depth.cpu().numpy()).sum())
+    ctx.set_profiling(2)
+    api.render(ctx, S, D, c2w)
+    st = ctx.frame_stats()
+    ctx.set_profiling(0)
+    later = len(st["chunk_ms"]) > 1 and bool(st["chunk_ms"][1])
+    log("  visible %d (projection %d), keys %d, later chunk ran: %s" % (st["visible"], n_vis, st["keys"], later))
+    assert st["visible"] == n_vis
+    assert 0 < st["keys"] <= ctx.key_capacity()
+    S.close()
+    D.close()
+
+
 def test_deterministic(ctx):
     from paper_2407_14053_amd import api
     d = synth.make_named_display("tiny")
