@@ -26,6 +26,7 @@ constexpr int kSceneRows = 59;
 // with A = a log2(e)/2, B = b log2(e), C = c log2(e)/2 for the conic [[a, b], [b, c]] = Sigma'^{-1}, so that
 // Q = A dx^2 + B dx dy + C dy^2 = q log2(e)/2 and o exp(-q/2) = o 2^-Q.
 constexpr int kRecF4 = 3;
+constexpr int kGaussBlockF4 = 18;  // per-Gaussian block of the projection's view-independent terms (288 B)
 
 // Per-view camera block uploaded for every frame: 16 doubles = rotation rows (9), t (3), eye (3), 0.
 constexpr int kCamDoubles = 16;
@@ -215,9 +216,14 @@ hipError_t launch_lower_bounds(const uint32_t* keys, const uint32_t* n_dev, uint
 // ---- projection (project.hip) ----
 hipError_t launch_project(const float* soa, const double* cams, const ProjConst& pc, float4* rec, uint64_t* keys,
                           uint32_t* vals, double* depth_out, hipStream_t s);
-// rec_sorted[v][r] = rec[v][sorted[v][r]] for rank_lo[v] <= r < rank_hi[v] (rank_lo nullptr: 0)
-hipError_t launch_gather_records(const float4* rec, const uint32_t* sorted, const uint32_t* rank_lo,
-                                 const uint32_t* rank_hi, int64_t G, int N, float4* out, hipStream_t s);
+// Depth keys of every (view, Gaussian) and each Gaussian's block of view-independent terms (blocks[G][18]).
+hipError_t launch_project_keys(const float* soa, const double* cams, const ProjConst& pc, float4* blocks,
+                               uint64_t* keys, hipStream_t s);
+// out[v][r] = record of (view v, Gaussian sorted[v][r]) for rank_lo[v] <= r < rank_hi[v] (rank_lo nullptr: 0),
+// from the blocks, with the arithmetic of launch_project
+hipError_t launch_project_ranks(const float4* blocks, const double* cams, const ProjConst& pc,
+                                const uint32_t* sorted, const uint32_t* rank_lo, const uint32_t* rank_hi,
+                                float4* out, hipStream_t s);
 hipError_t launch_scene_transpose(const float* means, const float* log_scales, const float* quats,
                                   const float* logits, const float* sh, int64_t n, int64_t n_pad, float* soa,
                                   hipStream_t s);

@@ -414,7 +414,7 @@ FrameSizes frame_sizes(int N, int64_t G, int64_t NT, int64_t nstate, uint32_t ca
                                split_hist_size(G, N));
   const size_t v[kFrameBufs] = {
       (size_t)N * kCamDoubles * 8,                    // cameras
-      (size_t)NG * kRecF4 * 16,                       // records, projection order
+      (size_t)G * kGaussBlockF4 * 16,                 // per-Gaussian blocks of the projection
       (size_t)NG * kRecF4 * 16,                       // records, depth order
       (size_t)NG * 8, (size_t)NG * 8,                 // depth keys (double-buffered)
       (size_t)NG * 4, (size_t)NG * 4,                 // Gaussian indices (double-buffered)
@@ -512,8 +512,8 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   pc.dilation = o.dilation;
   pc.key_e0 = depth_key_e0(o.z_near);
   mk = C->begin(DL_STAGE_PROJECT, s);
-  HIP_TRY(launch_project(S->soa.as<float>(), C->cams.as<double>(), pc, C->rec.as<float4>(), C->k64[0].as<uint64_t>(),
-                         nullptr, nullptr, s));
+  HIP_TRY(launch_project_keys(S->soa.as<float>(), C->cams.as<double>(), pc, C->rec.as<float4>(),
+                              C->k64[0].as<uint64_t>(), s));
   C->end(mk, s);
   hipError_t e;
   // Depth order.  The first chunk is each view's front (the nearest ~1/16 of its visible Gaussians, chosen on a
@@ -539,7 +539,8 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                                     C->partial.as<uint32_t>(), dlayout, s, &e);
   if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
   const uint32_t* sorted = fl ? C->v32[0].as<uint32_t>() : C->v32[1].as<uint32_t>();
-  HIP_TRY(launch_gather_records(C->rec.as<float4>(), sorted, nullptr, rank_hi, G, N, C->srec.as<float4>(), s));
+  HIP_TRY(launch_project_ranks(C->rec.as<float4>(), C->cams.as<double>(), pc, sorted, nullptr, rank_hi,
+                               C->srec.as<float4>(), s));
   // the first chunk's end per view (the table form caps it) and the table layout
   const uint32_t fcap = table_fcap(N, G, tl.T);
   const int64_t tab_n = table_entries(N, G, tl.T);
@@ -680,7 +681,8 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                                          C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), dlayout, s, &e);
       if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
       if (fl2 != fl) return fail(DL_EHIP, "depth sorts ended in different buffers");
-      HIP_TRY(launch_gather_records(C->rec.as<float4>(), sorted, front, rank_hi, G, N, C->srec.as<float4>(), s));
+      HIP_TRY(launch_project_ranks(C->rec.as<float4>(), C->cams.as<double>(), pc, sorted, front, rank_hi,
+                                   C->srec.as<float4>(), s));
       C->end(mk, s);
     }
   }
