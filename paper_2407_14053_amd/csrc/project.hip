@@ -3,7 +3,10 @@
 // One thread per Gaussian reads its 59 parameters once (coalesced structure-of-arrays rows), builds
 // Sigma = R S S^T R^T once, then loops over the N views of the rig: camera transform, Jacobian J of the
 // perspective map, Sigma' = J W Sigma W^T J^T + h I, its inverse (the conic), the projected mean and the
-// cutoff ellipse, the depth key and the view-dependent colour.  Geometry runs in FP64 (the chip's vector
+// cutoff ellipse, the depth key and the view-dependent colour.  The render path keeps only the keys from that
+// loop, plus one block of each Gaussian's view-independent terms; the records of the ranks the depth order
+// keeps are then built from the blocks by the same device functions (most (view, Gaussian) records of a
+// dense scene are never read).  Geometry runs in FP64 (the chip's vector
 // FP64 rate makes this free next to the memory traffic) and the record is rounded to FP32 once, so the
 // FP32 blend starts from correctly rounded inputs; depth keys keep 31 mantissa bits of the FP64 z and its
 // exponent counted from that of z_near (36 bits: four radix passes of 9 bits).
