@@ -298,6 +298,20 @@ int dl_set_profiling(dl_ctx* ctx, int level);
 /* Read the measurements of the last profiled frame (synchronises on its events). */
 int dl_frame_stats_get(dl_ctx* ctx, dl_frame_stats* out);
 
+/* Vector-ALU issue rates of the device (the ceilings against which the blend's arithmetic is measured): short
+ * kernels of independent dependent-chain steps, 8 wavefronts per SIMD on every compute unit, timed with HIP
+ * events (best of three after one warm-up launch).  Synchronous; makes `device` current.  Writes
+ * min(n_out, 16) doubles: [0] v_fma_f32 lane operations per second, [1] v_exp_f32 lane operations per second,
+ * [2] steps of (4 v_fma_f32 + 1 v_exp_f32) per second and lane, [3] (ray, record) pairs per second of the
+ * blend's per-pair instruction sequence for a ray that fills one channel (lanes), [4] the same for a ray that
+ * fills three channels, with the clamp at alpha_max, [5] the engine clock measured over the FMA kernel (Hz,
+ * shader clock counter against the 100 MHz constant clock), [6] compute units, [7]-[10] lane operations per
+ * second of single instruction classes: v_add_f32, v_fmac_f32, v_mul_f32 with a negated operand, v_fma_f32 with
+ * three VGPR operands, [11] v_cndmask_b32 with an SGPR-pair mask, [12] steps of (v_cmp_gt_f32 into an SGPR pair
+ * + v_add_f32), [13] v_fmac_f32 with three distinct registers, [14] v_fma_f32 with an SGPR operand, [15] steps of
+ * (1 v_exp_f32 + 4 independent v_fma_f32).  Errors: DL_EINVAL (out NULL, n_out < 1, no such device), DL_EHIP. */
+int dl_probe_issue_rates(int device, double* out, int n_out);
+
 #ifdef __cplusplus
 }
 #endif

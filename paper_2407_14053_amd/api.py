@@ -94,6 +94,7 @@ _SIGS = {
     "dl_set_key_capacity": (_I, [_P, ctypes.c_int64]),
     "dl_key_capacity": (ctypes.c_int64, [_P]),
     "dl_frame_stats_get": (_I, [_P, ctypes.POINTER(dl_frame_stats)]),
+    "dl_probe_issue_rates": (_I, [_I, ctypes.POINTER(ctypes.c_double), _I]),
     "dl_plan_create": (_I, [_P, _P, _P, ctypes.POINTER(dl_render_opts), ctypes.POINTER(dl_pose), ctypes.c_int64,
                             _P, _P, ctypes.POINTER(_P)]),
     "dl_plan_render": (_I, [_P, ctypes.POINTER(dl_pose), _P]),
@@ -179,6 +180,20 @@ def make_desc(display) -> dl_display_desc:
     d.baseline, d.focal_px = float(display.baseline), float(display.focal_px)
     d.repurpose_pw = int(getattr(display, "repurpose_pw", 0))
     return d
+
+
+def probe_issue_rates(device: int = 0) -> dict:
+    """Vector-ALU issue rates measured on the device (dl_probe_issue_rates)."""
+    _torch()
+    out = (ctypes.c_double * 16)()
+    _check(load().dl_probe_issue_rates(int(device), out, 16))
+    return {"fma_lane_ops_per_s": out[0], "exp_lane_ops_per_s": out[1], "fma4_exp1_steps_per_s": out[2],
+            "blend_pairs_1ch_per_s": out[3], "blend_pairs_3ch_per_s": out[4], "engine_clock_hz": out[5],
+            "compute_units": int(out[6]), "add_lane_ops_per_s": out[7], "fmac_lane_ops_per_s": out[8],
+            "negmul_lane_ops_per_s": out[9], "fma3v_lane_ops_per_s": out[10],
+            "cndmask_sgpr_lane_ops_per_s": out[11], "cmp_sgpr_add_steps_per_s": out[12],
+            "fmac3r_lane_ops_per_s": out[13], "fma_sgpr_lane_ops_per_s": out[14],
+            "exp1_fma4_steps_per_s": out[15]}
 
 
 class Context:

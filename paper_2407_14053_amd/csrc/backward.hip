@@ -8,7 +8,7 @@
 //   dC/dalpha_j = T_j c_j - (C - C_<=j) / (1 - alpha_j)        (C_<=j: colour accumulated up to j)
 // because C - C_<=j = sum_{k>j} alpha_k T_k c_k + T_end bg is exactly what 1 - alpha_j scales.  This walks
 // front to back with no stored per-pixel blend state and no division by a transmittance.  Through
-// alpha = min(alpha_max, o 2^-Q) (zero gradient when clamped) and Q = A dx^2 + B dx dy + C dy^2 the pair gives
+// alpha = min(cap, o 2^-Q) (the forward's clamp, blend_cap; zero gradient when clamped) and Q = A dx^2 + B dx dy + C dy^2 the pair gives
 // gradients of the record (u, v, A, B, C, o, r, g, b); they are summed over the wavefront, then over the
 // workgroup, and added to a per-(view, Gaussian) accumulator with one atomic per component per tile.
 //
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict_
       C2[j] = st.w;
     }
   }
-  const float a_max = bc.alpha_max, t_min = bc.t_min;
+  const float t_min = bc.t_min;
   const uint32_t ls = tile_start[vt];
   const uint32_t le = tile_start[vt + 1];
   const int64_t vG = (int64_t)v * bc.G;
@@ -136,8 +136,8 @@ __global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict_
       const float4 r1 = src[1], r2 = src[2];
       const float lo = __builtin_amdgcn_logf(r2.x);
       sm[threadIdx.x * kRecF4 + 0] = src[0];
-      // the forward's staging (log2(o) and the bound on E = log2(o) - Q), with o itself in the unused slot
-      sm[threadIdx.x * kRecF4 + 1] = make_float4(r1.x, blend_elim(lo, bc), r2.x, r1.w);
+      // the forward's staging (log2(o), the bound on E = log2(o) - Q and the clamp of alpha), with o itself
+      sm[threadIdx.x * kRecF4 + 1] = make_float4(r1.x, blend_elim(lo, bc), r2.x, blend_cap(r2.x, bc));
       sm[threadIdx.x * kRecF4 + 2] = make_float4(lo, r2.y, r2.z, r2.w);
       sg[threadIdx.x] = sorted[vG + rk];
     }
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict_
     if (__ballot(any) != 0ull) {
       for (int k = 0; k < n; ++k) {
         const float4 A = sm[k * kRecF4 + 0];
-        const float4 CQ = sm[k * kRecF4 + 1];  // conic C (scaled), E limit, opacity
+        const float4 CQ = sm[k * kRecF4 + 1];  // conic C (scaled), E limit, opacity, clamp of alpha
         const float cC = CQ.x;
         const float4 B = sm[k * kRecF4 + 2];    // log2(opacity), r, g, b
         float gr[kG];
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict_
           const float dx = px[j] - A.x, dy = py[j] - A.y;
           const float E = fmaf(-fmaf(A.w, dy, A.z * dx), dx, fmaf(-(cC * dy), dy, B.x));
           const float ga = __builtin_amdgcn_exp2f(E);  // o 2^-Q
-          const float alpha = fminf(a_max, ga);
+          const float alpha = fminf(CQ.w, ga);
           const bool ok = live[j] && (E >= CQ.y);
           const float tn = fmaf(-alpha, Tr[j], Tr[j]);
           const bool stop = ok && (tn < t_min);
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict_
             gr[6] += g0[j] * w;
             gr[7] += g1[j] * w;
             gr[8] += g2[j] * w;
-            if (ga <= a_max) {
+            if (ga <= CQ.w) {
               const float dQ = -da * ln2 * ga;  // alpha = o 2^-Q
               gr[5] += da * ga * __builtin_amdgcn_rcpf(CQ.z);  // d alpha / d o = 2^-Q
               gr[2] += dQ * dx * dx;

@@ -63,6 +63,8 @@ struct BlendConst {
   // repurposed panel (nullptr: every ray fills channels of its own pixel): tgt[(3 p + j) * 3 + k] = the subpixel
   // filled by channel k of the ray of pixel p whose entry carries slot j (bits 27-28), or -1
   const int32_t* tgt;
+  // DirectL: every ray of the panel fills exactly one channel (its three subpixels belong to three views)
+  int single_channel;
 };
 constexpr int kStatSlots = 1024;
 
@@ -71,6 +73,14 @@ constexpr int kStatSlots = 1024;
 // o exp(-q/2) >= alpha_min.
 __device__ inline float blend_elim(float lo, const BlendConst& bc) {
   return fmaxf(lo - bc.q_cut, bc.log2_alpha_min);
+}
+
+// The clamp of a record's alpha, alpha = min(cap, o 2^-Q): alpha_max for a Gaussian whose opacity comes within
+// 2^-10 of alpha_max, else +inf (then o 2^-Q <= o stays below alpha_max and min(alpha_max, .) never applies, so
+// alpha = min(alpha_max, o exp(-q/2)) either way; a rounding excess of the computed 2^-Q above 1 would have to
+// exceed 2^-10 to make the two differ).
+__device__ inline float blend_cap(float o, const BlendConst& bc) {
+  return o > bc.alpha_max * (1.0f - 1.0f / 1024.0f) ? bc.alpha_max : __builtin_inff();
 }
 
 // Depth chunk: ranks [n_v num_lo / den, n_v num_hi / den) of every view; `stride` bounds its length.
@@ -130,6 +140,8 @@ hipError_t launch_view_map(uint8_t* V, int W, int H, int N, int64_t As, int64_t 
 hipError_t launch_rays_emit(const uint8_t* V, int W, int H, int tw, int th, int ntx, int T, uint32_t* keys,
                             uint32_t* vals, hipStream_t s);
 hipError_t launch_interleave(const uint8_t* V, const float* views, float* out, int W, int H, hipStream_t s);
+// *count += ray entries ent[0, n) whose channel mask holds more than one channel (count zeroed by the caller)
+hipError_t launch_count_multichannel(const uint32_t* ent, int64_t n, uint32_t* count, hipStream_t s);
 // Alg. 1 with a bilinear Resize of views[N][vh][vw][3] to the panel (src: source pixels of a repurposed panel)
 hipError_t launch_interleave_resize(const uint8_t* V, const int32_t* src, const float* views, float* out, int W,
                                    int H, int vw, int vh, hipStream_t s);
@@ -328,5 +340,11 @@ hipError_t launch_blend_backward(const float4* rec, const uint32_t* tile_start, 
 hipError_t launch_project_backward(const float* soa, const double* cams, const ProjConst& pc, const float* acc,
                                    float* g_means, float* g_log_scales, float* g_quats, float* g_logits, float* g_sh,
                                    hipStream_t s);
+
+// ---- issue-rate probe (probe.hip) ----
+// Synchronous, on the current device: out[0..6] = FMA lane-ops/s, exp lane-ops/s, (4 FMA + 1 exp) steps/s, blend
+// pairs/s of one-channel and of three-channel rays (per lane), measured engine clock (Hz), compute units; out[7..10]
+// = v_add_f32, v_fmac_f32, negated v_mul_f32, three-VGPR v_fma_f32 lane-ops/s; DL_ code, message in *why.
+int probe_issue_rates(double* out, int n_out, std::string* why);
 
 }  // namespace dl

@@ -98,6 +98,7 @@ struct RayLists {
   DevBuf ent;  // [n_rays] uint32
   int max_rays = 0;
   int64_t n_rays = 0;
+  bool single_channel = false;  // every ray fills exactly one channel
 };
 
 }  // namespace
@@ -325,6 +326,15 @@ int build_ray_lists(dl_display* D, int tw, int th, hipStream_t s, RayLists** out
   int mx = 0;
   for (int64_t k = 0; k < NT; ++k) mx = std::max<int>(mx, (int)(off[k + 1] - off[k]));
   L->max_rays = mx;
+  {
+    uint32_t multi = 0;
+    e = hipMemsetAsync(part.p, 0, 4, s);
+    if (e == hipSuccess) e = launch_count_multichannel(sv.as<uint32_t>(), L->n_rays, part.as<uint32_t>(), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&multi, part.p, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
+    L->single_channel = multi == 0;
+  }
   // keep the sorted entries (first n_rays values)
   std::swap(L->ent.p, sv.p);
   std::swap(L->ent.cap, sv.cap);
@@ -568,6 +578,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   for (int k = 0; k < 3; ++k) bc.bg[k] = o.bg[k];
   bc.stats = C->prof >= 3 ? C->stats.as<unsigned long long>() : nullptr;
   bc.tgt = (!standard && D->tgt.p) ? D->tgt.as<int32_t>() : nullptr;
+  bc.single_channel = (!standard && L && L->single_channel) ? 1 : 0;
   unsigned long long* total = C->dtotal.as<unsigned long long>();
   for (int c = 0; c < kChunks; ++c) {
     C->chunk = c;
@@ -1211,6 +1222,18 @@ int dl_set_key_capacity(dl_ctx* C, int64_t keys) {
 }
 
 int64_t dl_key_capacity(const dl_ctx* C) { return C ? (int64_t)C->key_cap : -1; }
+
+int dl_probe_issue_rates(int device, double* out, int n_out) {
+  if (!out || n_out < 1) return fail(DL_EINVAL, "out is NULL or n_out < 1");
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(DL_EINVAL, "no such device");
+  HIP_TRY(hipSetDevice(device));
+  std::string why;
+  const int rc = probe_issue_rates(out, n_out, &why);
+  if (rc != DL_OK) return fail(rc, why);
+  return DL_OK;
+}
 
 int dl_set_profiling(dl_ctx* C, int level) {
   if (!C) return fail(DL_EINVAL, "NULL context");

@@ -47,6 +47,16 @@ __global__ __launch_bounds__(256) void rays_emit_kernel(const uint8_t* __restric
   }
 }
 
+// *count += entries whose channel mask (bits 24-26) has more than one channel; one thread per entry.
+__global__ __launch_bounds__(256) void count_multichannel_kernel(const uint32_t* __restrict__ ent, int64_t n,
+                                                                 uint32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t m = i < n ? (ent[i] >> 24) & 7u : 0u;
+  const bool multi = (m & (m - 1u)) != 0u;
+  const unsigned long long b = __ballot(multi);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (uint32_t)__popcll(b));
+}
+
 // Alg. 1: out[x][y][k] = views[V[x][3y + k]][x][y][k]; one thread per subpixel.
 __global__ __launch_bounds__(256) void interleave_kernel(const uint8_t* __restrict__ V,
                                                          const float* __restrict__ views, float* __restrict__ out,
@@ -98,6 +108,12 @@ hipError_t launch_rays_emit(const uint8_t* V, int W, int H, int tw, int th, int 
   const int64_t n = (int64_t)W * H;
   hipLaunchKernelGGL(rays_emit_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, V, W, H, tw, th, ntx, T, keys,
                      vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_multichannel(const uint32_t* ent, int64_t n, uint32_t* count, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(count_multichannel_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, ent, n, count);
   return hipGetLastError();
 }
 
