@@ -5,16 +5,18 @@
 // of the ray (v, x', y').  A pixel rendered for one of its channels lends its two other channels to later
 // subpixels of the same view found along the lens direction (Eq. (14) search window), so fewer distinct rays
 // are rendered.  The heuristic's open points are resolved as follows:
-//   - area of a subpixel: floor(d_offset / (P_w L_x)) with d_offset of Eq. (1) (slanted strips of P_w grating
-//     units); areas in increasing order, each area's subpixels in row-major order (x, y, k);
+//   - area of a subpixel: that of its pixel, floor(d_offset(x, y, 0) / (P_w L_x)) with d_offset of Eq. (1) at the
+//     pixel's left edge (slanted strips of P_w grating units); areas in increasing order, each area's subpixels
+//     in row-major order (x, y, k);
 //   - one waiting pixel per (view, channel), empty at the start of an area; sampling a subpixel anew (Eq. (11))
 //     lends its pixel to the view's two other channels (Eq. (12)), overwriting; repurposing (Eq. (13)) takes
 //     and empties the slot of (view, channel);
 //   - search window (Eq. (14), parentheses unbalanced in print): rows min(x + 2, h - 1) .. min(x +
 //     floor(5 N / (2 L_x)), h - 1), columns max(y - floor(N / (3 L_x)), 0) .. y;
-//   - next subpixel: unassigned, same view, same area, inside the window; one whose channel has a waiting pixel
-//     if any, else any; first in row-major order (row, column, channel).  None: the chain ends and the view's
-//     slots are emptied.
+//   - next subpixel: unassigned, same view, inside the window; one whose channel has a waiting pixel if any,
+//     else any; first in row-major order (row, column, channel).  The search does not look at areas: the chain
+//     goes on only while the subpixel found lies in the chain's area.  None, or one outside the area: the chain
+//     ends and the view's slots are emptied.
 // Device part: the (view, pixel) rays and, per ray and channel, the subpixel it fills (at most one, since
 // each (v, x', y', k) is used once), so the blend writes every ray's channels where they belong.
 #include "dl_internal.h"
@@ -106,13 +108,14 @@ int repurpose_sources(const dl_display_desc& d, int pw, const uint8_t* V, int32_
     *why = "repurpose_pw must be >= 1";
     return DL_EINVAL;
   }
-  // area(x, s) = floor(d_offset / (pw L)) = floor(D q / (b c pw p)), D = s b c + 3 x a c - r b
+  // area(x, s) = floor(d_offset(x, y, 0) / (pw L)) = floor(D q / (b c pw p)), D = 3 y b c + 3 x a c - r b for
+  // the subpixel s = 3 y + k (all three subpixels of a pixel share its area)
   const __int128 den = b * c * (__int128)pw * p;
   std::vector<int32_t> area((size_t)H * W3);
   int64_t amin = INT64_MAX, amax = INT64_MIN;
   for (int x = 0; x < H; ++x)
     for (int s = 0; s < W3; ++s) {
-      const __int128 D = (__int128)s * b * c + (__int128)3 * x * a * c - r * b;
+      const __int128 D = (__int128)(s - s % 3) * b * c + (__int128)3 * x * a * c - r * b;
       const int64_t A = floor_div(D * q, den);
       if (A < INT32_MIN || A > INT32_MAX) {
         *why = "repurposing area index out of range";
@@ -153,7 +156,7 @@ int repurpose_sources(const dl_display_desc& d, int pw, const uint8_t* V, int32_
             for (int yy = ylo; yy <= yhi; ++yy)
               for (int kk = 0; kk < 3; ++kk) {
                 const size_t sidx = (size_t)xx * W3 + 3 * yy + kk;
-                if (V[sidx] != v || src[sidx] >= 0 || area[sidx] != A) continue;
+                if (V[sidx] != v || src[sidx] >= 0) continue;
                 if (fx < 0) {
                   fx = xx; fy = yy; fk = kk;
                 }
