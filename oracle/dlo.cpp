@@ -249,21 +249,26 @@ struct Cand {
   bool truth;
 };
 
+constexpr int kMaxVar = 32;      // admissible outcomes kept per ray
+constexpr int kMaxOrders = 24;   // depth orders of near-tie groups explored per ray
+
 struct RayOut {
   double prim[3];
-  double var[16][3];
+  double var[kMaxVar][3];
   int nvar;
-  int over;       // more fragile decisions than the budget on some path
+  int over;       // more fragile decisions or near-tie orders than explored on some path
   int nfrag;      // fragile decisions met on the primary path
   int nblend;     // Gaussians blended on the primary path
+  int nties;      // near-tie groups among the candidates the walks reach
   double t_final;
 };
 
 struct Walker {
   const dlo_opts* o;
   RayOut* out;
+  size_t reach;   // furthest candidate position any path examined (a stop there, or the list's end)
   void emit(const double C[3], double T) {
-    if (out->nvar >= 16) { out->over = 1; return; }
+    if (out->nvar >= kMaxVar) { out->over = 1; return; }
     for (int c = 0; c < 3; ++c) out->var[out->nvar][c] = C[c] + T * o->bg[c];
     out->nvar++;
   }
@@ -295,17 +300,19 @@ struct Walker {
             for (int k = 0; k < 3; ++k) C2[k] = C[k] + a * T * c.rgb[k];
             walk(cs, j + 1, Tn, C2, errTn, budget);
           } else {
+            reach = std::max(reach, j);
             emit(C, T);  // variant: stop here
           }
         } else {
           out->over = 1;
         }
       }
-      if (stop) { emit(C, T); return; }
+      if (stop) { reach = std::max(reach, j); emit(C, T); return; }
       for (int k = 0; k < 3; ++k) C[k] += a * T * c.rgb[k];
       T = Tn;
       errT = errTn;
     }
+    reach = std::max(reach, cs.size());
     emit(C, T);
   }
 };
@@ -374,6 +381,28 @@ void collect(const std::vector<Proj<double>>& P, double px, double py, const dlo
   });
 }
 
+// Near-tie groups: maximal runs cs[a..b] (b > a) of consecutive candidates whose adjacent depths differ by
+// at most the band (but are not equal: equal FP64 depths come from equal means, which both sides order by
+// index).  Within a group the depth order is not defined at the GPU's precision, so every permutation of it is
+// an admissible order.  Only groups that start at or before `reach` can change the composite: a walk never
+// examines a candidate after the position where it stopped.
+struct TieGroup { size_t a, n; };
+
+void tie_groups(const std::vector<Cand>& cs, size_t reach, double band, std::vector<TieGroup>& gs) {
+  gs.clear();
+  size_t j = 0;
+  while (j + 1 < cs.size() && j <= reach) {
+    size_t b = j;
+    while (b + 1 < cs.size()) {
+      const double dz = std::fabs(cs[b + 1].z - cs[b].z);
+      if (dz == 0.0 || dz > band * std::max(cs[b].z, 1.0)) break;
+      ++b;
+    }
+    if (b > j) gs.push_back({j, b - j + 1});
+    j = b + 1;
+  }
+}
+
 void render_ray(const std::vector<Proj<double>>& P, double px, double py, const dlo_opts& o, std::vector<Cand>& cs,
                 RayOut& out) {
   collect(P, px, py, o, cs);
@@ -383,25 +412,56 @@ void render_ray(const std::vector<Proj<double>>& P, double px, double py, const 
   out.t_final = T;
   out.nvar = 0;
   out.over = 0;
-  // near-tie depth pairs among adjacent candidates: explore swapped orders
-  std::vector<size_t> ties;
-  for (size_t j = 0; j + 1 < cs.size(); ++j)
-    if (std::fabs(cs[j + 1].z - cs[j].z) <= o.band_z * std::max(cs[j].z, 1.0)) ties.push_back(j);
+  out.nties = 0;
   const int budget = std::min(o.budget, 4);
-  if (ties.size() > 2) { out.over = 1; ties.resize(2); }
-  Walker w{&o, &out};
+  Walker w{&o, &out, 0};
   const double C0[3] = {0, 0, 0};
-  for (unsigned mask = 0; mask < (1u << ties.size()); ++mask) {
-    int used = __builtin_popcount(mask);
-    if (used > budget) { out.over = 1; continue; }
-    if (mask == 0) {
-      w.walk(cs, 0, 1.0, C0, 0.0, budget);
-    } else {
-      std::vector<Cand> alt(cs);
-      for (size_t b = 0; b < ties.size(); ++b)
-        if (mask & (1u << b)) std::swap(alt[ties[b]], alt[ties[b] + 1]);
-      w.walk(alt, 0, 1.0, C0, 0.0, budget - used);
+  w.walk(cs, 0, 1.0, C0, 0.0, budget);  // the exact order, fragile thresholds both ways
+  // orders of the near-tie groups the walks reach; a permuted order can carry a walk past the first reach,
+  // so the groups are taken again up to the new reach until they no longer change
+  std::vector<TieGroup> gs, seen;
+  std::vector<Cand> alt;
+  size_t done_reach = 0;
+  for (int round = 0; round < 4; ++round) {
+    tie_groups(cs, w.reach, o.band_z, gs);
+    if (round > 0 && w.reach == done_reach) break;
+    done_reach = w.reach;
+    if (gs.size() == seen.size()) break;   // groups are found in order: same count = same groups
+    seen = gs;
+    out.nties = (int)gs.size();
+    // mixed-radix enumeration of one permutation per group (index 0 = the exact order)
+    long total = 1;
+    for (const TieGroup& g : gs) {
+      long f = 1;
+      for (size_t i = 2; i <= g.n; ++i) f *= (long)i;
+      total *= f;
+      if (total > kMaxOrders) break;
     }
+    if (total > kMaxOrders) { out.over = 1; return; }
+    out.nvar = 0;
+    w.walk(cs, 0, 1.0, C0, 0.0, budget);
+    for (long code = 1; code < total; ++code) {
+      alt = cs;
+      long c = code;
+      int used = 0;
+      for (const TieGroup& g : gs) {
+        long f = 1;
+        for (size_t i = 2; i <= g.n; ++i) f *= (long)i;
+        long pc = c % f;
+        c /= f;
+        if (pc == 0) continue;
+        used++;
+        std::vector<size_t> perm(g.n);
+        for (size_t i = 0; i < g.n; ++i) perm[i] = i;
+        for (long r = 0; r < pc; ++r) std::next_permutation(perm.begin(), perm.end());
+        for (size_t i = 0; i < g.n; ++i) alt[g.a + i] = cs[g.a + perm[i]];
+      }
+      w.walk(alt, 0, 1.0, C0, 0.0, std::max(0, budget - used));
+    }
+  }
+  if (w.reach != done_reach) {
+    tie_groups(cs, w.reach, o.band_z, gs);
+    if (gs.size() != seen.size()) out.over = 1;  // still growing after the last round: not explored
   }
 }
 
@@ -469,9 +529,9 @@ void dlo_sh_basis(int64_t n, int32_t degree, const double* dirs, double* Y) {
   }
 }
 
-// Render rays (v, x = row, y = column).  out_prim[n][3]: FP64 truth; out_var[n][16][3] with out_nvar[n]
+// Render rays (v, x = row, y = column).  out_prim[n][3]: FP64 truth; out_var[n][32][3] with out_nvar[n]
 // admissible outcomes; out_info[n][4] = (over-budget flag, fragile decisions on the primary path,
-// Gaussians blended, 0).
+// Gaussians blended, near-tie groups explored).
 int dlo_render_rays(int64_t G, const float* means, const float* log_scales, const float* quats, const float* logits,
                     const float* sh, int32_t N, const double* R, const double* t, const double* eye,
                     const dlo_opts* o, int64_t n_rays, const int32_t* ray_v, const int32_t* ray_x,
@@ -497,13 +557,13 @@ int dlo_render_rays(int64_t G, const float* means, const float* log_scales, cons
         for (int c = 0; c < 3; ++c) out_prim[r * 3 + c] = ro.prim[c];
         if (out_var) {
           out_nvar[r] = ro.nvar;
-          std::memcpy(out_var + r * 48, ro.var, sizeof(double) * 3 * std::min(ro.nvar, 16));
+          std::memcpy(out_var + r * 3 * kMaxVar, ro.var, sizeof(double) * 3 * std::min(ro.nvar, kMaxVar));
         }
         if (out_info) {
           out_info[r * 4 + 0] = ro.over;
           out_info[r * 4 + 1] = ro.nfrag;
           out_info[r * 4 + 2] = ro.nblend;
-          out_info[r * 4 + 3] = 0;
+          out_info[r * 4 + 3] = ro.nties;
         }
       }
     }

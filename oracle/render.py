@@ -42,6 +42,7 @@ class _COpts(ctypes.Structure):
 
 
 _lib = None
+MAX_VAR = 32   # admissible outcomes per ray (kMaxVar in dlo.cpp)
 
 
 def lib():
@@ -132,14 +133,14 @@ def project(scene, R, t, eye, focal, cx, cy, opts: Opts = None) -> np.ndarray:
 class RayResult:
     prim: np.ndarray      # [n, 3] FP64 truth
     nvar: np.ndarray      # [n]
-    var: np.ndarray       # [n, 16, 3] admissible outcomes
-    info: np.ndarray      # [n, 4]: over-budget flag, fragile decisions, Gaussians blended, 0
+    var: np.ndarray       # [n, MAX_VAR, 3] admissible outcomes
+    info: np.ndarray      # [n, 4]: over-budget flag, fragile decisions, Gaussians blended, near-tie groups
 
     def admissible_err(self, gpu: np.ndarray) -> np.ndarray:
         """Per ray: min over admissible outcomes of max_c |gpu[r, c] - outcome[c]|."""
         gpu = np.asarray(gpu, dtype=np.float64)
         d = np.abs(self.var - gpu[:, None, :]).max(axis=2)
-        d = np.where(np.arange(16)[None, :] < self.nvar[:, None], d, np.inf)
+        d = np.where(np.arange(MAX_VAR)[None, :] < self.nvar[:, None], d, np.inf)
         return np.minimum(d.min(axis=1), np.abs(self.prim - gpu).max(axis=1))
 
     def admissible_err_sub(self, gpu_vals, ray_idx, ch) -> np.ndarray:
@@ -148,9 +149,9 @@ class RayResult:
         gpu_vals = np.asarray(gpu_vals, dtype=np.float64)
         ray_idx = np.asarray(ray_idx)
         ch = np.asarray(ch)
-        v = self.var[ray_idx[:, None], np.arange(16)[None, :], ch[:, None]]
+        v = self.var[ray_idx[:, None], np.arange(MAX_VAR)[None, :], ch[:, None]]
         d = np.abs(v - gpu_vals[:, None])
-        d = np.where(np.arange(16)[None, :] < self.nvar[ray_idx][:, None], d, np.inf)
+        d = np.where(np.arange(MAX_VAR)[None, :] < self.nvar[ray_idx][:, None], d, np.inf)
         return np.minimum(d.min(axis=1), np.abs(self.prim[ray_idx, ch] - gpu_vals))
 
 
@@ -168,7 +169,7 @@ def render_rays(scene, display, c2w, ray_v, ray_x, ray_y, opts: Opts = None, con
     n = len(rv)
     prim = np.zeros((n, 3))
     nvar = np.zeros(n, dtype=np.int32)
-    var = np.zeros((n, 16, 3))
+    var = np.zeros((n, MAX_VAR, 3))
     info = np.zeros((n, 4), dtype=np.int32)
     co = opts.c(*intrinsics(display))
     lib().dlo_render_rays(scene.n, _ptr(m), _ptr(ls), _ptr(q), _ptr(lg), _ptr(sh), display.n_views, _ptr(R),

@@ -205,14 +205,6 @@ def test_depth_order_cases_match_oracle_and_standard(ctx, name):
     std, _ = api.render_standard(ctx, S, D, c2w)
     assert np.array_equal(img, std.cpu().numpy())
     ref, res, index = full_oracle_image(sc, d, c2w)
-    if name == "twins":
-        # exact depth ties exceed the oracle's branching budget on most rays; its primary outcome orders ties by
-        # index, as the GPU does
-        ch = np.broadcast_to(np.arange(3)[None, None, :], index.shape)
-        err_prim = np.abs(img.astype(np.float64) - res.prim[index, ch])
-        log("  subpixels off the oracle's primary outcome: %d" % (err_prim > TOL).sum())
-        assert (err_prim > TOL).mean() <= 1e-3
-        return
     err, over = admissible_image_err(res, index, img)
     log("  max err %.3g, over-budget %d" % (err[~over].max(), over.sum()))
     assert err[~over].max() <= TOL
@@ -231,8 +223,9 @@ def test_uhd45_full_size_sampled(ctx):
     worst, over, frag = check_subpixels(sc, d, c2w, img, xs, ys, ks, label="uhd45")
     log("  uhd45 worst %.3g over %d fragile %d" % (worst, over, frag))
     assert worst <= TOL
-    # rays with more near-threshold decisions than the oracle explores are counted, not checked
-    assert over <= 0.003 * len(xs)
+    # rays with more near-threshold decisions or near-tie orders than the oracle explores are counted, not
+    # checked: at most 0.1% of the sample
+    assert over <= 0.001 * len(xs)
 
 
 def test_8k60_full_size_sampled(ctx):
@@ -248,9 +241,8 @@ def test_8k60_full_size_sampled(ctx):
         worst, over, frag = check_subpixels(sc, d, c2w, img, xs, ys, ks, label="8k60")
         log("  8k60 worst %.3g over %d fragile %d" % (worst, over, frag))
         assert worst <= TOL
-        # the clustered scene packs hundreds of Gaussians into each blob's narrow depth range, so some rays have
-        # more depth near-ties (within the key's 2^-31 relative resolution) than the oracle explores: counted,
-        # not checked (1.6% of the sample at one pose)
-        assert over <= 0.03 * len(xs)
+        # near-tie groups in the clustered blobs' narrow depth ranges are explored where a walk reaches them;
+        # rays beyond the oracle's exploration limits are counted, not checked: at most 0.1% of the sample
+        assert over <= 0.001 * len(xs)
         S.close()
         D.close()

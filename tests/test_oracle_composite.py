@@ -178,3 +178,53 @@ def test_directl_equals_views_then_interleave(name):
     enc = viewmap.interleave(views, render.view_map_of(d))
     assert np.array_equal(img, enc)
     assert res.info[:, 0].sum() == 0
+
+
+def _alpha_at(rec, i, px, py):
+    dx, dy = px - rec[i, 0], py - rec[i, 1]
+    q = rec[i, 2] * dx * dx + 2 * rec[i, 3] * dx * dy + rec[i, 4] * dy * dy
+    return min(float(np.float32(0.99)), rec[i, 5] * np.exp(-0.5 * q))
+
+
+def test_near_tie_group_admits_every_order():
+    """Three Gaussians whose depths differ by less than the depth band (2^-30 relative) form one near-tie group:
+    the order among them is not defined at the renderer's depth precision, so the composite of each of the 3!
+    orders is among the admissible outcomes, and the exact FP64 order gives the primary one."""
+    from itertools import permutations
+    d = _one_view_display()
+    mz = [0.0, 2e-9, 4e-9]            # camera depths 3, 3 - 2e-9, 3 - 4e-9: adjacent gaps below 2^-30 * 3
+    sc = _scene([[0, 0, z] for z in mz], np.log(0.2), [_logit(0.5), _logit(0.6), _logit(0.7)],
+                [[0.9, 0.1, 0.1], [0.1, 0.9, 0.1], [0.1, 0.1, 0.9]])
+    rec = _rec(sc, d)
+    assert len(set(rec[:, 9])) == 3
+    res = _ray(sc, d, 7, 7)
+    assert res.info[0, 0] == 0 and res.info[0, 3] == 1
+    outs = res.var[0, :res.nvar[0]]
+    a = [_alpha_at(rec, i, 7.5, 7.5) for i in range(3)]
+    comps = []
+    for perm in permutations(range(3)):
+        T, C = 1.0, np.zeros(3)
+        for i in perm:
+            C += a[i] * T * rec[i, 6:9]
+            T *= 1 - a[i]
+        comps.append(C)
+        assert np.abs(outs - C[None, :]).max(axis=1).min() < 1e-12, perm
+    exact = comps[list(permutations(range(3))).index(tuple(np.argsort(rec[:, 9], kind="stable")))]
+    assert np.allclose(res.prim[0], exact, atol=1e-12)
+    # the six orders give six different colours, so the check above is not vacuous
+    assert min(np.abs(comps[i] - comps[j]).max() for i in range(6) for j in range(i)) > 1e-3
+
+
+def test_near_tie_behind_terminated_walk_is_not_explored():
+    """A near-tie pair behind three opaque Gaussians that end the walk (T would fall below t_min) cannot change
+    the composite, so it is neither explored nor counted; in front of them it is."""
+    d = _one_view_display()
+    rgb = [[0.9, 0.1, 0.1], [0.1, 0.9, 0.1], [0.5, 0.5, 0.5], [0.3, 0.2, 0.1], [0.2, 0.3, 0.4]]
+    for stack_z, explored in [(0.5, False), (-0.5, True)]:
+        # the pair at camera depths 3 and 3 - 2e-9, the stack at 2.5-2.7 (in front) or 3.3-3.5 (behind)
+        mz = [stack_z, stack_z * 0.8, stack_z * 0.6, 0.0, 2e-9]
+        sc = _scene([[0, 0, z] for z in mz], np.log(0.3), [_logit(0.98)] * 3 + [_logit(0.5)] * 2, rgb)
+        res = _ray(sc, d, 7, 7)
+        assert res.info[0, 0] == 0
+        assert res.info[0, 3] == (1 if explored else 0), stack_z
+        assert (res.nvar[0] >= 2) == explored
