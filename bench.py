@@ -30,8 +30,14 @@ if ROOT not in sys.path:
 
 METRIC = "LF frames/s & Gsubpixel/s vs 45-view render+interleave; p50/p99 frame ms"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector, non-packed: 256 CUs x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
-VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# MI355X's published FP32 vector peak (256 CUs x 128 FP32 lanes per clock x 2 FLOP (FMA) x 2.4 GHz): the SIMDs
+# issue two VALU instructions per cycle when their operands are VGPRs (the issue-rate probe,
+# paper_2407_14053_amd/probe.py, measures v_fma_f32 with three VGPR operands at ~118 lanes per CU and clock)
+VALU_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6   # published FP64 vector peak
+# FP64 FLOPs of one (view, Gaussian) projection: the view transform (18), the EWA Jacobian (8), J W (36),
+# Sigma' = (J W) Sigma (J W)^T (54), dilation, inverse and cutoff extent (~25), depth key (~5)
+FLOP_PROJECT = 146
 # FLOPs of one (ray, list entry) evaluation in the blend: offset and q (11), and for a candidate inside the
 # cutoff alpha (4: scale, exp, opacity, clamp), transmittance (2) and colour (7)
 FLOP_Q = 11
@@ -60,6 +66,41 @@ def percentile(xs, p):
     k = (len(xs) - 1) * p / 100.0
     f, c = math.floor(k), math.ceil(k)
     return xs[f] if f == c else xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def frame_roofline(st_ms: dict, cnt: dict, G: int, N: int, W: int, H: int, frame_ms: float) -> dict:
+    """Frame-level roofline: per stage the time its algorithmic bytes need at the HBM peak or its algorithmic
+    FLOPs at the vector peak (whichever is longer), summed over the stages and divided by the measured frame
+    time.  Algorithmic work per unit (the front of each view's depth order is taken as 1/32 of its visible
+    Gaussians, the fraction the depth chunks are built for):
+      project     read 236 B of parameters and write a 288 B block per Gaussian, write an 8 B depth key per
+                  (view, Gaussian); FLOP_PROJECT FP64 FLOPs per (view, Gaussian)
+      depth_sort  read every key (8 B) and write every visible (view, Gaussian) as key + index (12 B); 4 radix
+                  passes over the fronts (24 B each); per front rank a block read and a 48 B record written
+      bin_count   read each front record (48 B)
+      bin_emit    read each front record (48 B), write each tile key (4 B)
+      blend       FLOP_Q per (ray, list entry) evaluation and FLOP_BLEND per blend at the FP32 peak; read each
+                  tile key's record (48 B) and the ray list (4 B per ray), write the image (4 B per subpixel)
+    """
+    front = cnt["visible"] / 32.0
+    model = {
+        "project": (236.0 * G + 288.0 * G + 8.0 * N * G, FLOP_PROJECT * N * G / (FP64_PEAK_TFLOPS * 1e12)),
+        "depth_sort": (8.0 * N * G + 12.0 * cnt["visible"] + front * (4 * 24 + 288 + 48), 0.0),
+        "bin_count": (48.0 * front, 0.0),
+        "bin_emit": (48.0 * front + 4.0 * cnt["keys"], 0.0),
+        "blend": (48.0 * cnt["keys"] + 4.0 * cnt["rays"] + 12.0 * W * H,
+                  (cnt["evaluations"] * FLOP_Q + cnt["blends"] * FLOP_BLEND) / (VALU_PEAK_TFLOPS * 1e12)),
+    }
+    stages, bound = {}, 0.0
+    for k, (nbytes, t_alu) in model.items():
+        t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+        t = max(t_hbm, t_alu) * 1e3
+        bound += t
+        stages[k] = {"bound": "hbm" if t_hbm >= t_alu else "alu", "min_ms": round(t, 4),
+                     "measured_ms": round(st_ms.get(k, 0.0), 4),
+                     "frac": round(t / st_ms[k], 3) if st_ms.get(k, 0.0) > 0 else None}
+    return {"bound_ms": round(bound, 4), "frame_ms": round(frame_ms, 4), "frac": round(bound / frame_ms, 4),
+            "stages": stages}
 
 
 def copy_probe(nbytes: int = 256 << 20):
@@ -232,6 +273,7 @@ def run_gpu(args):
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "per_launch_ms": round(per_launch_ms, 4)}
     res["roofline"] = roof
+    res["frame_roofline"] = frame_roofline(st_ms, cnt, G, N, W, H, 1000.0 * wall / args.steps)
 
     if not args.no_standard:
         # the standard paradigm on the same kernels: all 45 full views at its best tile (32x32), then Alg. 1
@@ -260,7 +302,9 @@ def run_gpu(args):
         api.render(ctx, S, D, poses[args.warmup % len(poses)], opts=opts, out=out)
         same = bool(torch.equal(out, out_std))
         res["standard"] = {"frames_per_s": round(std_fps, 4), "ms_per_frame": round(1000 * (ts1 - ts0) / args.std_steps, 2),
-                           "steps": args.std_steps, "tile": [sst[0]["tile_w"], sst[0]["tile_h"]],
+                           "steps": args.std_steps, "gsubpixel_per_s": round(std_fps * 3 * W * H / 1e9, 4),
+                           "p50_ms": round(percentile(ms, 50), 3), "p99_ms": round(percentile(ms, 99), 3),
+                           "tile": [sst[0]["tile_w"], sst[0]["tile_h"]],
                            "bit_identical_to_directl": same,
                            "stage_ms": {k: round(v, 3) for k, v in std_stage.items() if v > 0},
                            "work": {k: int(v) for k, v in std_cnt.items()}}
@@ -479,10 +523,167 @@ def run_rayorder(args):
     D.close()
     print("ray-order %s panel rays, c_h 128: %.2f frames/s (kernel %.3f ms)" % (
         args.workload, panel["frames_per_s"], panel["kernel_ms"]), file=sys.stderr, flush=True)
+    res = {"bvh": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in bst.items()},
+           "single_view_1600x1060": rows, "panel_c_h_128": panel}
+    if args.repurpose_pw > 0:
+        # the paper's DirectL-3DGS ("Ours" in its comparison table): Alg. 3 on the repurposed panel's rays
+        D = api.Display(ctx, synth.make_named_display(args.workload, repurpose_pw=args.repurpose_pw))
+        ours = timed(D, 128, max(2, args.rayorder_steps // 2))
+        ours["repurpose_pw"] = args.repurpose_pw
+        D.close()
+        res["panel_repurposed_c_h_128"] = ours
+        print("ray-order %s repurposed rays (P_w = %d), c_h 128: %.2f frames/s (kernel %.3f ms)" % (
+            args.workload, args.repurpose_pw, ours["frames_per_s"], ours["kernel_ms"]), file=sys.stderr, flush=True)
     B.close()
     ctx.close()
-    return {"bvh": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in bst.items()},
-            "single_view_1600x1060": rows, "panel_c_h_128": panel}
+    return res
+
+
+def _timed_frames(render, steps, warmup=2):
+    """Eager frames: (frames/s over the wall clock, per-frame HIP-event milliseconds)."""
+    import torch
+    for i in range(warmup):
+        render(i)
+    torch.cuda.synchronize()
+    ms = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        render(warmup + i)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return steps / (time.perf_counter() - t0), ms
+
+
+def _row(fps, ms, W, H, extra=None):
+    r = {"frames_per_s": round(fps, 3), "ms_per_frame": round(1000.0 / fps, 3),
+         "p50_ms": round(percentile(ms, 50), 3), "p99_ms": round(percentile(ms, 99), 3),
+         "gsubpixel_per_s": round(fps * 3 * W * H / 1e9, 4), "steps": len(ms)}
+    r.update(extra or {})
+    return r
+
+
+def run_variants(args):
+    """More rows on the display-scale workload's panel and poses:
+    - required_only_16x16: the paper's "Required Only" multi-view row (Table 3): every view blends only the pixels
+      the panel needs, at the standard 16x16 tiles of 3DGS (the DirectL path with the tile forced to 16x16);
+    - faint: the same Gaussians with opacity logits lowered by 4 (opacities mostly below 0.1), so that rays
+      survive the front depth chunk and the later chunk (the back of every live view's depth order) runs."""
+    import torch
+
+    from paper_2407_14053_amd import api, synth
+
+    disp = synth.make_named_display(args.workload)
+    scene = synth.make_scene(args.workload)
+    poses = synth.pose_sweep(200) if args.workload == "uhd45" else synth.pose_orbit(120)
+    W, H = disp.width, disp.height
+    ctx = api.Context(0)
+    D = api.Display(ctx, disp)
+    out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    res = {}
+    S = api.Scene(ctx, scene.arrays())
+    o16 = api.default_opts(tile_w=16, tile_h=16)
+    fps, ms = _timed_frames(lambda i: api.render(ctx, S, D, poses[i % len(poses)], opts=o16, out=out),
+                            max(2, args.std_steps // 2))
+    res["required_only_16x16"] = _row(fps, ms, W, H, {"tile": [16, 16]})
+    print("required only (16x16 tiles): %.2f frames/s" % fps, file=sys.stderr, flush=True)
+    S.close()
+    faint = synth.Scene(*[a.copy() for a in scene.arrays()])
+    faint.opacity_logits -= 4.0
+    S = api.Scene(ctx, faint.arrays())
+    fps, ms = _timed_frames(lambda i: api.render(ctx, S, D, poses[i % len(poses)], out=out), args.steps)
+    ctx.set_profiling(2)
+    api.render(ctx, S, D, poses[0], out=out)
+    st = ctx.frame_stats()
+    ctx.set_profiling(0)
+    res["faint"] = _row(fps, ms, W, H, {
+        "workload": "the same 300k Gaussians with opacity logits - 4",
+        "later_chunk_ran": len(st["chunk_ms"]) > 1 and bool(st["chunk_ms"][1]),
+        "chunk_ms": [{k: round(v, 4) for k, v in c.items()} for c in st["chunk_ms"]]})
+    print("faint scene: %.2f frames/s" % fps, file=sys.stderr, flush=True)
+    S.close()
+    D.close()
+    ctx.close()
+    return res
+
+
+def run_large(args):
+    """The large configuration: 3M clustered Gaussians, 7680x4320 panel, N = 60, the 120-frame orbit; and a few
+    frames of the standard paradigm (60 full 7680x4320 views + Alg. 1) on the same poses."""
+    import torch
+
+    from paper_2407_14053_amd import api, synth
+
+    disp = synth.make_named_display("8k60")
+    scene = synth.make_scene("8k60")
+    poses = synth.pose_orbit(120)
+    W, H = disp.width, disp.height
+    ctx = api.Context(0)
+    S = api.Scene(ctx, scene.arrays())
+    D = api.Display(ctx, disp)
+    out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    fps, ms = _timed_frames(lambda i: api.render(ctx, S, D, poses[i % len(poses)], out=out), len(poses))
+    ctx.set_profiling(2)
+    api.render(ctx, S, D, poses[7], out=out)
+    st = ctx.frame_stats()
+    ctx.set_profiling(0)
+    res = _row(fps, ms, W, H, {"workload": WORKLOADS["8k60"], "tile": [st["tile_w"], st["tile_h"]],
+                               "stage_ms": {k: round(v, 4) for k, v in st["stage_ms"].items() if v > 0}})
+    print("large 8k60: %.2f frames/s (p50 %.2f ms)" % (fps, res["p50_ms"]), file=sys.stderr, flush=True)
+    if args.large_std_steps > 0:
+        # the standard paradigm's 32x32 tiles need more than 2^31 tile keys in a depth chunk here (60 full views of
+        # 3M Gaussians in one frame); larger tiles are tried in turn
+        errs = []
+        for t in (32, 48, 64):
+            ot = api.default_opts(tile_w=t, tile_h=t)
+            try:
+                sfps, sms = _timed_frames(
+                    lambda i: api.render_standard(ctx, S, D, poses[i % len(poses)], opts=ot, out=out),
+                    args.large_std_steps, warmup=1)
+            except RuntimeError as e:
+                errs.append("tile %d: %s" % (t, e))
+                continue
+            res["standard"] = _row(sfps, sms, W, H, {"tile": [t, t], "failed": errs})
+            res["speedup_vs_standard"] = round(fps / sfps, 2)
+            print("large 8k60 standard (%dx%d tiles): %.3f frames/s" % (t, t, sfps), file=sys.stderr, flush=True)
+            break
+        else:
+            res["standard"] = {"error": errs}
+    S.close()
+    D.close()
+    ctx.close()
+    return res
+
+
+# The paper's Table 6: rendered pixel ratio beta at P_w = 1..4 on the display table's panels (context: the
+# reading of Alg. 2 is this build's, see the design notes)
+TABLE6 = {"7.9in": (1.4764, 1.4467, 1.3044, 1.0790), "15.6in": (1.3701, 1.3694, 1.2868, 1.1109),
+          "65in": (1.5613, 1.3708, 1.2440, 1.2222)}
+
+
+def run_table6(args):
+    """beta = rays / (w h) of the display table's panels under subpixel repurposing, from the library's own
+    Alg. 2 walk (display creation, offline); all P_w for the 7.9- and 15.6-inch panels, P_w = 2 for the 65-inch."""
+    from paper_2407_14053_amd import api, synth
+
+    ctx = api.Context(0)
+    res = {}
+    for name, pws in (("7.9in", (1, 2, 3, 4)), ("15.6in", (1, 2, 3, 4)), ("65in", (2,))):
+        row = {}
+        for pw in pws:
+            d = synth.table1_display(name, repurpose_pw=pw)
+            t0 = time.perf_counter()
+            D = api.Display(ctx, d)
+            row["P_w=%d" % pw] = {"beta": round(D.num_rays() / (d.width * d.height), 4),
+                                  "paper": TABLE6[name][pw - 1], "build_s": round(time.perf_counter() - t0, 2)}
+            D.close()
+        res[name] = row
+        print("beta %s: %s" % (name, ", ".join("%s %.3f (paper %.3f)" % (k, v["beta"], v["paper"])
+                                                for k, v in row.items())), file=sys.stderr, flush=True)
+    ctx.close()
+    return res
 
 
 WORKLOADS = {
@@ -589,7 +790,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--std-steps", type=int, default=2)
+    ap.add_argument("--std-steps", type=int, default=20,
+                    help="frames of the standard paradigm and of the multi-view rows")
     ap.add_argument("--tile", type=int, default=0, help="DirectL tile side (0 = automatic)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="uhd45",
                     help="uhd45: the display-scale configuration the metric is quoted on; 8k60: the large one")
@@ -606,6 +808,11 @@ def main():
                     help="first copy 256 MiB device-to-device 3 times (calibrates HBM byte counters)")
     ap.add_argument("--rayorder-steps", type=int, default=4,
                     help="frames per ray-order configuration (0: skip the ray-order rows)")
+    ap.add_argument("--no-variants", action="store_true", help="skip the Required Only (16x16) and faint rows")
+    ap.add_argument("--no-large", action="store_true", help="skip the 7680x4320 N=60 row")
+    ap.add_argument("--large-std-steps", type=int, default=2,
+                    help="standard-paradigm frames in the 7680x4320 N=60 row (0: skip)")
+    ap.add_argument("--no-table6", action="store_true", help="skip beta of the display table's panels")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -622,6 +829,12 @@ def main():
         res["repurposed"] = run_repurposed(args, res["value"])
     if not args.no_standard:
         res["multiview"] = run_grid(args)
+    if not args.no_variants:
+        res["variants"] = run_variants(args)
+    if args.workload == "uhd45" and not args.no_large:
+        res["large_8k60"] = run_large(args)
+    if not args.no_table6:
+        res["table6_beta"] = run_table6(args)
     if args.rayorder_steps > 0:
         res["rayorder"] = run_rayorder(args)
     if not args.no_backward:

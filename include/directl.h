@@ -120,7 +120,8 @@ void dl_scene_free(dl_scene* scene);
 
 /* Display: validates the descriptor and builds the view map V[H][3W] (uint8) on the device by exact
  * integer arithmetic on the rationals (Eq. (1)-(3) with the floored modulo of Eq. (2)).  Returns DL_ERANGE if
- * the exact arithmetic would not fit 64-bit integers.  Synchronises `stream`. */
+ * the exact arithmetic would not fit 64-bit integers: with tan(alpha) = a/b, L_x = p/q, K_offset = r/c in
+ * lowest terms, Q = b c p must be below 2^61, N Q below 2^62, 3W and H below 2^20.  Synchronises `stream`. */
 int dl_display_create(dl_ctx* ctx, const dl_display_desc* desc, void* stream, dl_display** out);
 void dl_display_free(dl_display* display);
 /* Copy V[H][3W] (uint8, view of subpixel column 3y + k in row x) into out_dev. */

@@ -135,7 +135,7 @@ struct BlendChunk {
 };
 
 // ---- view map and ray lists (viewmap.hip) ----
-hipError_t launch_view_map(uint8_t* V, int W, int H, int N, int64_t As, int64_t Ax, int64_t C, int64_t Q,
+hipError_t launch_view_map(uint8_t* V, int W, int H, int N, int64_t As, int64_t Ax, int64_t C, int64_t Q, int wide,
                            hipStream_t s);
 hipError_t launch_rays_emit(const uint8_t* V, int W, int H, int tw, int th, int ntx, int T, uint32_t* keys,
                             uint32_t* vals, hipStream_t s);

@@ -669,6 +669,12 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
       HIP_TRY(hipMemcpyAsync(keys_host, total + 1, 8, hipMemcpyDeviceToHost, s));
       if (C->prof) HIP_TRY(hipMemcpyAsync(vis_counts, C->vis.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
+      if (*keys_host > cap) {
+        // the first chunk overflowed: its blend saw truncated lists, so the live tiles (and the later chunks'
+        // key counts) mean nothing; grow to what this chunk needs and render again
+        *need = *keys_host;
+        return DL_ECAP;
+      }
       uint64_t nlive = 0;
       for (int v = 0; v < N; ++v) nlive += C->live_host[v];
       if (nlive == 0) {
@@ -676,10 +682,6 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
         C->keys = (int64_t)*keys_host;
         if (C->prof)
           for (int v = 0; v < N; ++v) C->visible += vis_counts[v];
-        if (*keys_host > cap) {
-          *need = *keys_host;
-          return DL_ECAP;
-        }
         return DL_OK;
       }
     }
@@ -736,6 +738,27 @@ int render_grow(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose
     C->key_cap = (uint32_t)want;
   }
   return fail(DL_ECAP, "tile key capacity kept overflowing");
+}
+
+// Projection constants of a scene on a display under options o.
+ProjConst proj_const(const dl_scene* S, const dl_display_desc& d, const dl_render_opts& o) {
+  ProjConst pc{};
+  pc.G = S->n;
+  pc.n_pad = S->n_pad;
+  pc.N = d.n_views;
+  pc.W = d.width;
+  pc.H = d.height;
+  pc.sh_degree = o.sh_degree;
+  pc.focal = d.focal_px;
+  pc.cx = d.width / 2.0;
+  pc.cy = d.height / 2.0;
+  pc.z_near = o.z_near;
+  pc.q_cut = o.q_cut;
+  pc.alpha_min = o.alpha_min;
+  pc.alpha_max = o.alpha_max;
+  pc.dilation = o.dilation;
+  pc.key_e0 = depth_key_e0(o.z_near);
+  return pc;
 }
 
 int check_common(dl_ctx* C, const dl_scene* S, const dl_display* D) {
@@ -856,10 +879,13 @@ int dl_display_create(dl_ctx* ctx, const dl_display_desc* desc, void* stream, dl
                  c = d.offset.den;
   const __int128 Q = b * c * p;
   const __int128 lim = (__int128)1 << 62;
-  if (Q <= 0 || Q >= lim) return fail(DL_ERANGE, "view map modulus b*c*p out of range");
-  const __int128 As = mod_floor(b * c * q, Q), Ax = mod_floor(3 * a * c * q, Q), Cc = mod_floor(-r * b * q, Q);
-  if (Q * (__int128)(3 * (int64_t)d.width + d.height + 1) >= lim || Q * d.n_views >= lim)
+  // the device reduces each product modulo Q on its own when the direct sum would not fit (below 2^61 and with
+  // row and column indices below 2^20, see view_map_kernel); N rho < N Q must fit as well
+  if (Q <= 0 || Q >= ((__int128)1 << 61)) return fail(DL_ERANGE, "view map modulus b*c*p out of range");
+  if (Q * d.n_views >= lim || 3 * (int64_t)d.width >= (1 << 20) || d.height >= (1 << 20))
     return fail(DL_ERANGE, "view map exceeds 64-bit exact arithmetic");
+  const __int128 As = mod_floor(b * c * q, Q), Ax = mod_floor(3 * a * c * q, Q), Cc = mod_floor(-r * b * q, Q);
+  const int wide = Q * (__int128)(3 * (int64_t)d.width + d.height + 1) >= lim ? 1 : 0;
   dl_display* D = new dl_display();
   D->ctx = ctx;
   D->desc = d;
@@ -870,7 +896,7 @@ int dl_display_create(dl_ctx* ctx, const dl_display_desc* desc, void* stream, dl
     return fail(DL_ENOMEM, "view map buffer");
   }
   hipError_t e = launch_view_map(D->V.as<uint8_t>(), d.width, d.height, d.n_views, (int64_t)As, (int64_t)Ax,
-                                 (int64_t)Cc, (int64_t)Q, s);
+                                 (int64_t)Cc, (int64_t)Q, wide, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     delete D;
@@ -967,22 +993,7 @@ int dl_project(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose*
   HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(C->vis.p, 0, 256 * 4, s));
   HIP_TRY(hipMemsetAsync(out_dev, 0, (size_t)NG * 48, s));
-  ProjConst pc{};
-  pc.G = S->n;
-  pc.n_pad = S->n_pad;
-  pc.N = N;
-  pc.W = d.width;
-  pc.H = d.height;
-  pc.sh_degree = o.sh_degree;
-  pc.focal = d.focal_px;
-  pc.cx = d.width / 2.0;
-  pc.cy = d.height / 2.0;
-  pc.z_near = o.z_near;
-  pc.q_cut = o.q_cut;
-  pc.alpha_min = o.alpha_min;
-  pc.alpha_max = o.alpha_max;
-  pc.dilation = o.dilation;
-  pc.key_e0 = depth_key_e0(o.z_near);
+  const ProjConst pc = proj_const(S, d, o);
   HIP_TRY(launch_project(S->soa.as<float>(), C->cams.as<double>(), pc, (float4*)out_dev, C->k64[0].as<uint64_t>(),
                          C->v32[0].as<uint32_t>(), depth_dev, s));
   HIP_TRY(hipStreamSynchronize(s));

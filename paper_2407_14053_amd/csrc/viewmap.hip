@@ -4,18 +4,43 @@
 namespace dl {
 namespace {
 
+// (a b) mod m for 0 <= a < 2^20 and 0 <= b < m < 2^61, by binary expansion of a: no intermediate value reaches 2m,
+// so the product never leaves 64-bit integers whatever the size of b.
+__device__ inline int64_t mul_mod(int64_t a, int64_t b, int64_t m) {
+  int64_t r = 0;
+#pragma unroll
+  for (int i = 19; i >= 0; --i) {
+    r += r;
+    if (r >= m) r -= m;
+    if ((a >> i) & 1) {
+      r += b;
+      if (r >= m) r -= m;
+    }
+  }
+  return r;
+}
+
 // V[x][s], s = 3y + k.  With tan(alpha) = a/b, L_x = p/q, K_offset = r/c the view is
 // v = floor(N * frac(d_offset / L_x)), and d_offset / L_x = (s b c + 3 x a c - r b) q / (b c p).  The host
 // reduces the three integer coefficients modulo Q = b c p, so that rho = (s As + x Ax + C) mod Q is the
 // numerator of frac(d_offset / L_x) exactly (the floored modulo of Eq. (2) since every term is >= 0), and
-// v = N rho / Q with integer division (the floor of Eq. (3)).
+// v = N rho / Q with integer division (the floor of Eq. (3)).  When Q (3W + H + 1) fits 63 bits the sum is
+// formed directly; otherwise each product is reduced modulo Q on its own (mul_mod).
 __global__ __launch_bounds__(256) void view_map_kernel(uint8_t* __restrict__ V, int W3, int H, int N,
-                                                       int64_t As, int64_t Ax, int64_t C, int64_t Q) {
+                                                       int64_t As, int64_t Ax, int64_t C, int64_t Q, int wide) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)W3 * H) return;
   const int64_t x = idx / W3;
   const int64_t s = idx - x * W3;
-  const int64_t rho = (s * As + x * Ax + C) % Q;
+  int64_t rho;
+  if (wide) {
+    rho = mul_mod(s, As, Q) + mul_mod(x, Ax, Q);
+    if (rho >= Q) rho -= Q;
+    rho += C;
+    if (rho >= Q) rho -= Q;
+  } else {
+    rho = (s * As + x * Ax + C) % Q;
+  }
   V[idx] = (uint8_t)((N * rho) / Q);
 }
 
@@ -96,10 +121,10 @@ inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b);
 
 }  // namespace
 
-hipError_t launch_view_map(uint8_t* V, int W, int H, int N, int64_t As, int64_t Ax, int64_t C, int64_t Q,
+hipError_t launch_view_map(uint8_t* V, int W, int H, int N, int64_t As, int64_t Ax, int64_t C, int64_t Q, int wide,
                            hipStream_t s) {
   const int64_t n = (int64_t)3 * W * H;
-  hipLaunchKernelGGL(view_map_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, V, 3 * W, H, N, As, Ax, C, Q);
+  hipLaunchKernelGGL(view_map_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, V, 3 * W, H, N, As, Ax, C, Q, wide);
   return hipGetLastError();
 }
 

@@ -150,6 +150,24 @@ DISPLAYS = {
 }
 
 
+# The three panels of the paper's display table (Table 1): (w, h, L_x, tilt angle in degrees, K_offset, N_v).
+# Tilt angles become tan(alpha) rounded to a denominator of 10^6; four-decimal pitches and offsets are exact
+# decimals.
+TABLE1_PANELS = {
+    "7.9in": (1536, 2048, "6.2221", 10.8232, "4.2077", 48),
+    "15.6in": (3840, 2160, "5.3344", 6.8526, "1.2547", 60),
+    "65in": (7680, 4320, "9.3597", 8.6517, "23.6677", 96),
+}
+
+
+def table1_display(name: str, repurpose_pw: int = 0, baseline: float = 0.6) -> Display:
+    import math
+    w, h, pitch, deg, off, n = TABLE1_PANELS[name]
+    tan = Fraction(round(math.tan(math.radians(deg)) * 10 ** 6), 10 ** 6)
+    return make_display(w, h, n, tan, Fraction(pitch), Fraction(off), baseline=baseline, name=name,
+                        repurpose_pw=repurpose_pw)
+
+
 def make_named_display(name: str, **over) -> Display:
     kw = dict(DISPLAYS[name])
     kw.update(over)
