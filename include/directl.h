@@ -148,6 +148,23 @@ int dl_cameras(const dl_display* display, const dl_pose* pose, double* out_host)
 int dl_project(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
                const dl_render_opts* opts, float* out_dev, double* depth_dev, void* stream);
 
+/* Bytes of the fixed device array behind dl_project_noalloc (held on every device the library runs on until the
+ * process ends). */
+#define DL_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/* dl_project without any allocation, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same records out_dev[N][n][12] and depths
+ * depth_dev[N][n] as dl_project, from the same kernel; its scratch (the N cameras, 256-byte aligned, then the
+ * N x n depth keys, 8 bytes each) lives in a fixed device array of DL_NOALLOC_SCRATCH_BYTES per device, whose
+ * address dl_create takes.  Calls no hipMalloc, hipFree or other allocating routine; the cameras are staged
+ * through the context's pinned buffer (allocated by dl_create).  Errors: DL_ERANGE (nothing launched) when
+ * round_up(128 N, 256) + 8 N n exceeds DL_NOALLOC_SCRATCH_BYTES; DL_EINVAL for NULL arguments or when the
+ * context's device is not the current device; DL_EHIP.  Every call on a device shares that device's array and
+ * finds the previous call's contents there (nothing in it needs to start at zero): calls that overlap on one
+ * device (other streams, other threads) race; calls ordered on one stream do not.  Synchronises `stream`. */
+int dl_project_noalloc(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_pose* pose,
+                       const dl_render_opts* opts, float* out_dev, double* depth_dev, void* stream);
+
 /* DirectL forward: the encoded image out_dev[H][W][3] (every subpixel written).  The visible Gaussians of
  * each view are binned and blended in depth chunks, front to back; tiles whose rays have all terminated take
  * no further keys.  Synchronises `stream` at the end of the frame to check the library-owned key buffers

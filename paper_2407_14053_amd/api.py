@@ -82,6 +82,7 @@ _SIGS = {
     "dl_display_source_map": (_I, [_P, _P, _P]),
     "dl_cameras": (_I, [_P, ctypes.POINTER(dl_pose), _P]),
     "dl_project": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P, _P]),
+    "dl_project_noalloc": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P, _P]),
     "dl_render": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P]),
     "dl_render_standard": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P,
                                 _P]),
@@ -344,6 +345,22 @@ def project(ctx, scene, display, c2w, converge_dist=None, opts=None, stream=None
     _check(load().dl_project(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(rec), _ptr(depth),
                              _stream(stream)))
     return rec, depth
+
+
+def project_noalloc(ctx, scene, display, c2w, out, depth, converge_dist=None, opts=None, stream=None):
+    """dl_project_noalloc into caller-owned out[N, G, 12] float32 and depth[N, G] float64 (the library allocates
+    nothing; its scratch is a fixed device array)."""
+    torch = _torch()
+    N, G = display.n_views, scene.n
+    if tuple(out.shape) != (N, G, 12) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of shape (%d, %d, 12)" % (N, G))
+    if tuple(depth.shape) != (N, G) or depth.dtype != torch.float64 or not depth.is_contiguous():
+        raise ValueError("depth must be a contiguous float64 tensor of shape (%d, %d)" % (N, G))
+    pose = make_pose(c2w, converge_dist)
+    o = opts or default_opts()
+    _check(load().dl_project_noalloc(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(out),
+                                     _ptr(depth), _stream(stream)))
+    return out, depth
 
 
 def render(ctx, scene, display, c2w, converge_dist=None, opts=None, out=None, stream=None):

@@ -41,6 +41,33 @@ int fail(int code, const std::string& msg) {
     if (_e != hipSuccess) return fail(DL_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));     \
   } while (0)
 
+// Scratch of dl_project_noalloc: a fixed device array that every GPU the library runs on holds until the process
+// ends (a HIP module's device variable), so that entry point allocates nothing.  In host code `scratch` names a
+// host-side stand-in, not device memory: its device address is taken once per device, with that device current,
+// by scratch_setup (from dl_create), and only that address is ever passed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[DL_NOALLOC_SCRATCH_BYTES];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kScratchDevices] = {};
+
+int scratch_setup(int device) {
+  if (device < 0 || device >= kScratchDevices) return fail(DL_EINVAL, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return DL_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(DL_EHIP, std::string("device address of the no-allocation scratch: ") + hipGetErrorString(e));
+  g_scratch_dev[device] = p;
+  return DL_OK;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
@@ -794,6 +821,8 @@ int dl_create(int device, dl_ctx** out) {
   HIP_TRY(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return fail(DL_EINVAL, "no such HIP device");
   HIP_TRY(hipSetDevice(device));
+  int rc = scratch_setup(device);
+  if (rc) return rc;
   dl_ctx* c = new dl_ctx();
   c->device = device;
   if (hipHostMalloc((void**)&c->cams_host, 256 * kCamDoubles * 8, hipHostMallocDefault) != hipSuccess ||
@@ -996,6 +1025,40 @@ int dl_project(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose*
   const ProjConst pc = proj_const(S, d, o);
   HIP_TRY(launch_project(S->soa.as<float>(), C->cams.as<double>(), pc, (float4*)out_dev, C->k64[0].as<uint64_t>(),
                          C->v32[0].as<uint32_t>(), depth_dev, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DL_OK;
+}
+
+int dl_project_noalloc(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pose* pose,
+                       const dl_render_opts* opts, float* out_dev, double* depth_dev, void* stream) {
+  int rc = check_common(C, S, D);
+  if (rc) return rc;
+  if (!out_dev || !depth_dev) return fail(DL_EINVAL, "NULL output");
+  dl_render_opts o;
+  if ((rc = check_opts(opts, o))) return rc;
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != C->device) return fail(DL_EINVAL, "the context's device is not the current device");
+  const dl_display_desc& d = D->desc;
+  const int N = d.n_views;
+  const int64_t NG = (int64_t)N * S->n;
+  // scratch layout: the N cameras, then the N x G depth keys the projection kernel writes (read by nobody here)
+  const size_t cam_bytes = ((size_t)N * kCamDoubles * 8 + 255) / 256 * 256;
+  const unsigned long long need = (unsigned long long)cam_bytes + (unsigned long long)NG * 8ull;
+  if (need > (unsigned long long)DL_NOALLOC_SCRATCH_BYTES)
+    return fail(DL_ERANGE, "projection of " + std::to_string(NG) + " (view, Gaussian) pairs needs " +
+                               std::to_string(need) + " bytes of scratch, more than the fixed " +
+                               std::to_string((long long)DL_NOALLOC_SCRATCH_BYTES));
+  unsigned char* base = static_cast<unsigned char*>(scratch_of(C->device));
+  if (!base) return fail(DL_EHIP, "no scratch address for this device");
+  if ((rc = make_cameras(d, pose, C->cams_host))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  double* cams = reinterpret_cast<double*>(base);
+  uint64_t* keys = reinterpret_cast<uint64_t*>(base + cam_bytes);
+  HIP_TRY(hipMemcpyAsync(cams, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
+  const ProjConst pc = proj_const(S, d, o);
+  // every (view, Gaussian) record and depth is written by the kernel (culled records as zeros): nothing to clear
+  HIP_TRY(launch_project(S->soa.as<float>(), cams, pc, (float4*)out_dev, keys, nullptr, depth_dev, s));
   HIP_TRY(hipStreamSynchronize(s));
   return DL_OK;
 }
