@@ -707,7 +707,10 @@ def run_serving(args):
     from paper_2407_14053_amd import api, serving, synth
 
     ctx = api.Context(0)
-    srv = serving.Server(ctx, n_slots=args.serve_slots)
+    # plans are made before timing (grow_in_loop=False): a pair's requests wait for one of its plans; a watchdog
+    # reports frames not completed within 2 s
+    srv = serving.Server(ctx, n_slots=args.serve_slots, grow_in_loop=False, watchdog_s=2.0,
+                         batch_max=args.serve_batch)
     tb = time.perf_counter()
     for name, (n, seed) in SERVING_SCENES.items():
         srv.add_scene(name, synth.serving_scene(n, seed))
@@ -717,7 +720,8 @@ def run_serving(args):
     tb = time.perf_counter()
     # one plan per pair, checked at eight orbit angles
     probes = [synth.look_at_c2w((3.0 * math.sin(a), 0.0, 3.0 * math.cos(a))) for a in np.arange(8) * math.pi / 4]
-    srv.warm(log=lambda m: print("serving: " + m, file=sys.stderr, flush=True), probe_poses=probes)
+    srv.warm(log=lambda m: print("serving: " + m, file=sys.stderr, flush=True), probe_poses=probes,
+             copies=args.serve_copies)
     t_warm = time.perf_counter() - tb
     print("serving: resident in %.1f s, %d plans in %.1f s" % (t_res, len(srv.plans), t_warm), file=sys.stderr,
           flush=True)
@@ -735,18 +739,34 @@ def run_serving(args):
             summ["rate_req_per_s"], summ["frames_per_s"], summ["p50_ms"], summ["p99_ms"]), file=sys.stderr, flush=True)
         return summ
 
+    # capacity: every request of the stream present at once (the loop always has work queued), with batched
+    # launches of queued same-pair requests and with one frame per launch
+    cap_reqs = serving.poisson_requests(args.serve_requests // 2, args.serve_rate, list(SERVING_SCENES),
+                                        list(SERVING_DISPLAYS), seed=2003)
+    cap = srv.run(cap_reqs, realtime=False).summary()
+    srv.batch_max = 1
+    cap1 = srv.run(cap_reqs, realtime=False).summary()
+    srv.batch_max = args.serve_batch
+    capacity = cap["frames_per_s"]
+    print("serving capacity: %.1f frames/s with batched launches (mean batch %.2f), %.1f with one frame per launch"
+          % (capacity, cap["mean_batch"], cap1["frames_per_s"]), file=sys.stderr, flush=True)
     rep = srv.run(reqs, realtime=True)
     summ = rep.summary()
     summ.update({"rate_req_per_s": args.serve_rate, "slots": args.serve_slots, "plans_warm_s": round(t_warm, 2),
+                 "plans": len(srv.plans), "plans_per_pair": args.serve_copies,
                  "scenes": {k: v[0] for k, v in SERVING_SCENES.items()}, "displays": list(SERVING_DISPLAYS)})
     tidy(summ)
-    # the same mix offered at 70% of the throughput just measured, where latency is not dominated by the queue
-    rate2 = round(0.7 * summ["frames_per_s"], 1)
+    summ["capacity_frames_per_s"] = round(capacity, 2)
+    summ["capacity_mean_batch"] = round(cap["mean_batch"], 3)
+    summ["capacity_one_frame_per_launch"] = round(cap1["frames_per_s"], 2)
+    summ["batching_gain"] = round(capacity / cap1["frames_per_s"], 3) if cap1["frames_per_s"] > 0 else None
+    # the same mix offered at 85% of the measured capacity, where latency is not dominated by the queue
+    rate2 = round(0.85 * capacity, 1)
     reqs2 = serving.poisson_requests(args.serve_requests // 2, rate2, list(SERVING_SCENES), list(SERVING_DISPLAYS),
                                      seed=2001)
     s2 = srv.run(reqs2, realtime=True).summary()
     s2["rate_req_per_s"] = rate2
-    summ["below_saturation"] = tidy(s2)
+    summ["sustainable"] = tidy(s2)
     srv.close()
     ctx.close()
     torch.cuda.synchronize()
@@ -816,6 +836,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-copies", type=int, default=2, help="plans per (scene, display) pair made before timing")
+    ap.add_argument("--serve-batch", type=int, default=4, help="requests of one pair per batched launch (1: none)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

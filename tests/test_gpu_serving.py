@@ -108,6 +108,34 @@ def test_plan_overflow_is_reported_and_rebuilt_plan_is_exact(ctx):
     plan.close()
 
 
+def test_plan_batched_launch_equals_eager_frames(ctx):
+    """One launch of a plan's batch graph renders several poses in a row, each into its own image, bit for bit as
+    the eager frames of those poses; batches of other sizes and single launches interleave with it."""
+    import torch
+    from paper_2407_14053_amd import api
+    log("plan batched launches")
+    d = synth.make_named_display("tiny")
+    sc = synth.make_scene("tiny")
+    S, D = api.Scene(ctx, sc.arrays()), api.Display(ctx, d)
+    stream = torch.cuda.Stream()
+    poses = synth.pose_sweep(12)
+    plan = api.Plan(ctx, S, D, poses[0], stream=stream)
+    plan.prepare_batch(4, stream=stream)
+    for chosen in ([1, 5, 9], [2, 3, 4, 11], [7]):
+        outs = plan.launch_batch([poses[k] for k in chosen], stream=stream)
+        stream.synchronize()
+        assert plan.check()[0]
+        for k, img in zip(chosen, outs):
+            ref = api.render(ctx, S, D, poses[k]).cpu().numpy()
+            assert np.array_equal(img.cpu().numpy(), ref), k
+        single = plan.launch(poses[6], stream=stream)
+        stream.synchronize()
+        assert np.array_equal(single.cpu().numpy(), api.render(ctx, S, D, poses[6]).cpu().numpy())
+    with pytest.raises(api.DLError):
+        plan.launch_batch(poses[:5], stream=stream)          # more than prepared
+    plan.close()
+
+
 def test_plan_memory_estimate(ctx):
     import torch
     from paper_2407_14053_amd import api
@@ -212,6 +240,56 @@ def test_serving_recovers_from_plan_overflow(ctx):
     rep = srv.run(reqs, realtime=False)
     assert rep.replans > 0
     _check_alone(ctx, srv, rep, scenes, displays, reqs, n_oracle=0)
+    srv.close()
+
+
+def test_serving_cancel_watchdog_and_prewarmed_plans(ctx):
+    """Plans made before timing (two per pair) serve the stream without a plan being made in the loop; a request
+    cancelled from the first completion is dropped before launch; a watchdog deadline shorter than any frame
+    reports launched frames that had not completed, and they still complete; completion times come from the
+    frames' GPU events (after each launch, before the loop saw them)."""
+    from paper_2407_14053_amd import serving
+    log("serving cancel / watchdog")
+    srv, scenes, displays = _server(ctx)
+    srv.grow_in_loop = False
+    srv.watchdog_s = 1e-6
+    srv.warm(copies=2)
+    n_plans = len(srv.plans)
+    reqs = serving.poisson_requests(16, 200.0, list(scenes), list(displays), seed=2004)
+    last = max(reqs, key=lambda r: r.arrival).rid
+    fired = []
+
+    def first_done(d):
+        if not fired:
+            fired.append(d.rid)
+            srv.cancel(last)
+
+    rep = srv.run(reqs, realtime=True, on_done=first_done)
+    log("  ", {k: v for k, v in rep.summary().items() if k != "per_display"})
+    assert rep.cancelled == [last]
+    assert sorted(d.rid for d in rep.done) == sorted(r.rid for r in reqs if r.rid != last)
+    assert rep.plans_created == 0 and len(srv.plans) == n_plans
+    assert len(rep.stalled) > 0 and {rid for rid, _ in rep.stalled} <= {d.rid for d in rep.done}
+    for d in rep.done:
+        assert d.launched <= d.finished and d.arrival <= d.launched
+    _check_alone(ctx, srv, rep, scenes, displays, [r for r in reqs if r.rid != last], n_oracle=0)
+    srv.close()
+
+
+def test_serving_batches_queued_requests_of_one_pair(ctx):
+    """With every request queued at once, requests of the same (scene, display) are served by batched launches
+    (several frames per launch); each image equals the same request rendered alone."""
+    from paper_2407_14053_amd import serving
+    log("serving batched")
+    srv, scenes, displays = _server(ctx)
+    srv.batch_max = 3
+    srv.warm()
+    reqs = serving.poisson_requests(30, 1000.0, list(scenes), list(displays), seed=2005)
+    rep = srv.run(reqs, realtime=False)
+    s = rep.summary()
+    log("  ", {k: v for k, v in s.items() if k != "per_display"})
+    assert rep.admitted == 30 and max(d.batch for d in rep.done) > 1 and s["mean_batch"] > 1.0
+    _check_alone(ctx, srv, rep, scenes, displays, reqs, n_oracle=1)
     srv.close()
 
 
