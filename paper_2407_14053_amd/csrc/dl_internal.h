@@ -210,6 +210,13 @@ hipError_t launch_front_select(const uint64_t* keys, int64_t G, int N, int key_b
                                int64_t den, uint32_t* hist, uint64_t* thr, hipStream_t s);
 // Ranges of the depth sorts: live == nullptr: the fronts [vG, vG + f); else the backs [vG + f, vG + n) of views
 // with a live tile (empty otherwise); rank_hi = end rank of the range; layout (2N + 1 entries) for the sort.
+// The fronts of the views sorted in LDS, one workgroup per view (Gaussians per view at most kFrontSortMaxG): the
+// values of each view's front [v G, v G + n_front[v]) of (keys, vals) are put in depth order in place; a front of
+// more than 12288 items is first cut (n_front lowered, the rest moved in order to the start of the back, through
+// tmp_keys / tmp_vals); rank_hi[v] = n_front[v].
+constexpr int64_t kFrontSortMaxG = 400000;
+hipError_t launch_front_sort(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals, int64_t G, int N,
+                             uint32_t* n_front, uint32_t* rank_hi, hipStream_t s);
 hipError_t launch_depth_ranges(int N, int64_t G, const uint32_t* n_vis, const uint32_t* n_front,
                                const uint32_t* live, uint32_t* lo, uint32_t* hi, uint32_t* rank_hi, uint32_t* layout,
                                hipStream_t s);

@@ -570,11 +570,18 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   radix_split_u64(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N, thr, kDepthCulled,
                   vis, front, C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s, &e);
   if (e != hipSuccess) return fail(DL_EHIP, std::string("depth split: ") + hipGetErrorString(e));
-  HIP_TRY(launch_depth_ranges(N, G, vis, front, nullptr, rlo, rhi, rank_hi, dlayout, s));
-  const bool fl = depth_ranges_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), C->k64[0].as<uint64_t>(),
-                                    C->v32[0].as<uint32_t>(), G, N, rlo, rhi, kDepthKeyBits, C->hist.as<uint32_t>(),
-                                    C->partial.as<uint32_t>(), dlayout, s, &e);
-  if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
+  bool fl = false;
+  if (G <= kFrontSortMaxG) {
+    // small scenes: every view's front sorted in LDS by one workgroup (one launch instead of the passes below)
+    HIP_TRY(launch_front_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), C->k64[0].as<uint64_t>(),
+                              C->v32[0].as<uint32_t>(), G, N, front, rank_hi, s));
+  } else {
+    HIP_TRY(launch_depth_ranges(N, G, vis, front, nullptr, rlo, rhi, rank_hi, dlayout, s));
+    fl = depth_ranges_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), C->k64[0].as<uint64_t>(),
+                           C->v32[0].as<uint32_t>(), G, N, rlo, rhi, kDepthKeyBits, C->hist.as<uint32_t>(),
+                           C->partial.as<uint32_t>(), dlayout, s, &e);
+    if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
+  }
   const uint32_t* sorted = fl ? C->v32[0].as<uint32_t>() : C->v32[1].as<uint32_t>();
   HIP_TRY(launch_project_ranks(C->rec.as<float4>(), C->cams.as<double>(), pc, sorted, nullptr, rank_hi,
                                C->srec.as<float4>(), s));

@@ -652,6 +652,215 @@ __global__ __launch_bounds__(kThreads) void lower_bounds_kernel(const uint32_t* 
   start[k] = (uint32_t)lo;
 }
 
+// ---- depth order of small fronts: one workgroup per view sorts the view's front in LDS ----
+// The front of a view (its f_v nearest visible Gaussians after the split, in Gaussian index order) is packed as
+// key << 24 | index (36 + 24 bits) and sorted by four stable LSD passes of 9 bits over the key bits in LDS, which
+// gives the order by (depth key, index) of the device passes in one launch.  Wavefront w owns the contiguous items
+// [w R, (w + 1) R) (R a multiple of 64), visited in slots of 64 consecutive items; a lane's rank among the equal
+// digits of its slot comes from a match mask of nine ballots, its rank in the wavefront from a running count per
+// (digit, wavefront), and the scatter position from the exclusive scan of those counts in (digit, wavefront)
+// order.  A front larger than the LDS holds is first cut at a bin of the key's top 12 bits (an exact histogram of
+// the front): the items at or above that bin move, in order, to the start of the view's back (a stable partition
+// through the other key buffer), and the view's front count is lowered to what remains.
+__device__ inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kFsThreads = 1024;
+constexpr int kFsWaves = kFsThreads / 64;
+constexpr int kFsSlots = 12;
+constexpr int kFsCap = kFsThreads * kFsSlots;  // 12288 items
+constexpr int kFsBits = 9;
+constexpr int kFsBins = 1 << kFsBits;
+constexpr int kFsCutBins = 4096;  // the top 12 bits of the 36-bit key
+static_assert(kFsBins * kFsWaves >= kFsCutBins, "the cut histogram shares the count array");
+static_assert(kDepthKeyBits == 4 * kFsBits, "four passes cover the depth key");
+
+struct FrontSortSmem {
+  unsigned long long items[kFsCap];
+  uint32_t cnt[kFsBins * kFsWaves];
+  uint32_t wsum[kFsWaves];
+  uint32_t misc[2];
+};
+
+// Exclusive prefix over the workgroup of one value per thread, in thread order (all threads must call it).
+__device__ inline uint32_t fs_block_scan(uint32_t x, uint32_t* wsum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += y;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int k = 0; k < w; ++k) base += wsum[k];
+  __syncthreads();
+  return base + inc - x;
+}
+
+// Cut a front of f > kFsCap items (see above); returns the new front size.
+__device__ uint32_t fs_cut_front(FrontSortSmem& sm, uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys,
+                                 uint32_t* tmp_vals, int64_t base, uint32_t f) {
+  const int t = threadIdx.x;
+  for (int b = t; b < kFsCutBins; b += kFsThreads) sm.cnt[b] = 0;
+  if (t == 0) sm.misc[0] = sm.misc[1] = 0;
+  __syncthreads();
+  for (uint32_t i = t; i < f; i += kFsThreads) atomicAdd(&sm.cnt[(uint32_t)(keys[base + i] >> 24) & 4095u], 1u);
+  __syncthreads();
+  // bin b holds cnt[b]; thread t owns bins 4t .. 4t + 3; `below` = items in the bins below the current one
+  uint32_t c[4], loc = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    c[k] = sm.cnt[4 * t + k];
+    loc += c[k];
+  }
+  uint32_t below = fs_block_scan(loc, sm.wsum);
+  uint32_t best = 0, best_n = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (below <= (uint32_t)kFsCap) {  // keeping the bins below 4t + k keeps `below` items
+      best = 4 * t + k;
+      best_n = below;
+    }
+    below += c[k];
+  }
+  // the largest such bin (the item counts below are non-decreasing in the bin)
+  atomicMax(&sm.misc[0], best);
+  __syncthreads();
+  const uint32_t cut = sm.misc[0];
+  if (best == cut && best_n <= (uint32_t)kFsCap) sm.misc[1] = best_n;  // the owner of bin `cut` (one thread)
+  __syncthreads();
+  const uint32_t kept_total = sm.misc[1];
+  __syncthreads();
+  // stable partition: items of the bins below `cut` to [0, kept_total), the others after them, in order
+  uint32_t kept = 0, moved = 0;
+  for (uint32_t r0 = 0; r0 < f; r0 += kFsThreads) {
+    const uint32_t i = r0 + t;
+    const bool in = i < f;
+    const uint64_t k = in ? keys[base + i] : 0ull;
+    const uint32_t val = in ? vals[base + i] : 0u;
+    const bool keep = in && ((uint32_t)(k >> 24) & 4095u) < cut;
+    const bool move = in && !keep;
+    const uint32_t pk = fs_block_scan(keep ? 1u : 0u, sm.wsum);
+    const uint32_t pm = fs_block_scan(move ? 1u : 0u, sm.wsum);
+    if (t == kFsThreads - 1) {
+      sm.misc[0] = pk + (keep ? 1u : 0u);
+      sm.misc[1] = pm + (move ? 1u : 0u);
+    }
+    __syncthreads();
+    const int64_t dst = keep ? base + kept + pk : base + kept_total + moved + pm;
+    if (in) {
+      tmp_keys[dst] = k;
+      tmp_vals[dst] = val;
+    }
+    kept += sm.misc[0];
+    moved += sm.misc[1];
+    __syncthreads();
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (uint32_t i = t; i < f; i += kFsThreads) {
+    keys[base + i] = tmp_keys[base + i];
+    vals[base + i] = tmp_vals[base + i];
+  }
+  __threadfence_block();
+  __syncthreads();
+  return kept_total;
+}
+
+__global__ __launch_bounds__(kFsThreads) void front_sort_kernel(uint64_t* __restrict__ keys,
+                                                                 uint32_t* __restrict__ vals,
+                                                                 uint64_t* __restrict__ tmp_keys,
+                                                                 uint32_t* __restrict__ tmp_vals, int64_t G,
+                                                                 uint32_t* __restrict__ n_front,
+                                                                 uint32_t* __restrict__ rank_hi) {
+  __shared__ FrontSortSmem sm;
+  const int v = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t base = (int64_t)v * G;
+  uint32_t f = n_front[v];
+  if (f > (uint32_t)kFsCap) f = fs_cut_front(sm, keys, vals, tmp_keys, tmp_vals, base, f);
+  const uint32_t R = (f + kFsThreads - 1) / kFsThreads * 64;  // items per wavefront, a multiple of 64
+  const int nslot = (int)(R / 64);                             // <= kFsSlots
+  unsigned long long it[kFsSlots];
+  uint32_t rank[kFsSlots];
+#pragma unroll
+  for (int j = 0; j < kFsSlots; ++j) {
+    const uint32_t i = w * R + j * 64 + lane;
+    it[j] = (j < nslot && i < f) ? ((keys[base + i] << 24) | (unsigned long long)vals[base + i]) : 0ull;
+    rank[j] = 0;
+  }
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int p = 0; p < 4; ++p) {
+    const int sh = 24 + kFsBits * p;
+    for (int b = t; b < kFsBins * kFsWaves; b += kFsThreads) sm.cnt[b] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kFsSlots; ++j) {
+      if (j >= nslot) break;
+      const bool valid = w * R + j * 64 + lane < f;
+      const uint32_t d = (uint32_t)(it[j] >> sh) & (kFsBins - 1);
+      uint64_t m = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < kFsBits; ++b) {
+        const uint64_t bb = __ballot((d >> b) & 1u);
+        m &= ((d >> b) & 1u) ? bb : ~bb;
+      }
+      const int leader = valid ? __ffsll((long long)m) - 1 : lane;
+      uint32_t before = 0;
+      if (valid && lane == leader) {
+        before = sm.cnt[d * kFsWaves + w];
+        sm.cnt[d * kFsWaves + w] = before + (uint32_t)__popcll(m);
+      }
+      before = __shfl(before, leader, 64);
+      rank[j] = before + (uint32_t)__popcll(m & lt);
+      wave_lds_fence();
+    }
+    __syncthreads();
+    // exclusive scan of the counts in (digit, wavefront) order: thread t owns entries 8t .. 8t + 7
+    uint32_t e[8], loc = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      e[k] = sm.cnt[8 * t + k];
+      loc += e[k];
+    }
+    uint32_t run = fs_block_scan(loc, sm.wsum);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      sm.cnt[8 * t + k] = run;
+      run += e[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kFsSlots; ++j) {
+      if (j >= nslot) break;
+      if (w * R + j * 64 + lane < f) {
+        const uint32_t d = (uint32_t)(it[j] >> sh) & (kFsBins - 1);
+        sm.items[sm.cnt[d * kFsWaves + w] + rank[j]] = it[j];
+      }
+    }
+    __syncthreads();
+    if (p < 3) {
+#pragma unroll
+      for (int j = 0; j < kFsSlots; ++j) {
+        if (j >= nslot) break;
+        const uint32_t i = w * R + j * 64 + lane;
+        if (i < f) it[j] = sm.items[i];
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = t; i < f; i += kFsThreads) vals[base + i] = (uint32_t)(sm.items[i] & 0xffffffull);
+  if (t == 0) {
+    n_front[v] = f;
+    rank_hi[v] = f;
+  }
+}
+
 int blocks_per_seg(int64_t seg_len, int n_seg) {
   // enough blocks to fill the chip (~2048 in flight), never more than one per tile of the segment
   int64_t tiles = (seg_len + kTile - 1) / kTile;
@@ -851,6 +1060,15 @@ hipError_t launch_depth_ranges(int N, int64_t G, const uint32_t* n_vis, const ui
   if (N > kThreads) return hipErrorInvalidValue;
   hipLaunchKernelGGL(depth_ranges_kernel, dim3(1), dim3(kThreads), 0, s, N, G, n_vis, n_front, live, lo, hi, rank_hi,
                      depth_blocks_per_seg(G, N), layout, layout + N);
+  return hipGetLastError();
+}
+
+hipError_t launch_front_sort(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals, int64_t G, int N,
+                             uint32_t* n_front, uint32_t* rank_hi, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  if (G > kFrontSortMaxG) return hipErrorInvalidValue;  // indices must fit the packed item's 24 bits
+  hipLaunchKernelGGL(front_sort_kernel, dim3((unsigned)N), dim3(kFsThreads), 0, s, keys, vals, tmp_keys, tmp_vals, G,
+                     n_front, rank_hi);
   return hipGetLastError();
 }
 

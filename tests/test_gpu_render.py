@@ -211,6 +211,45 @@ def test_depth_order_cases_match_oracle_and_standard(ctx, name):
     assert over.sum() <= 0.001 * over.size
 
 
+def _front_cut_case(name):
+    """Scenes whose first depth chunk (each view's nearest ~1/32, chosen on bins of the depth key's top bits)
+    holds more Gaussians than the LDS front sort takes, so that the front is cut at a key bin: 14000 Gaussians at
+    one depth (everything in one bin: the cut leaves the front empty) and 100 Gaussians in front of 14000 at one
+    depth (the cut keeps the 100)."""
+    rng = np.random.default_rng(91)
+    n_far = 14000
+    near = 100 if name == "front_cut_partial" else 0
+    n = n_far + near
+    sc = synth.scene_uniform(n, 1.0, 92)
+    sc.means[:, 0] = rng.uniform(-1.2, 1.2, n)
+    sc.means[:, 1] = rng.uniform(-0.8, 0.8, n)
+    sc.means[:, 2] = 0.0
+    sc.means[:near, 2] = 0.5
+    sc.opacity_logits[:] = rng.normal(-1.0, 1.0, n).astype(np.float32)
+    return sc
+
+
+@pytest.mark.parametrize("name", ["front_cut_all", "front_cut_partial"])
+def test_front_larger_than_the_lds_sort_is_cut(ctx, name):
+    from paper_2407_14053_amd import api
+    log("front cut", name)
+    d = synth.make_named_display("tiny")
+    sc = _front_cut_case(name)
+    c2w = synth.pose_front(3.0)
+    S = api.Scene(ctx, sc.arrays())
+    D = api.Display(ctx, d)
+    img = api.render(ctx, S, D, c2w).cpu().numpy()
+    std, _ = api.render_standard(ctx, S, D, c2w)
+    assert np.array_equal(img, std.cpu().numpy())
+    xs, ys, ks = sample_subpixels(d.height, d.width, 3000, 17)
+    worst, over, frag = check_subpixels(sc, d, c2w, img, xs, ys, ks, label=name)
+    log("  worst %.3g over %d fragile %d" % (worst, over, frag))
+    assert worst <= TOL
+    assert over <= 0.001 * len(xs)
+    S.close()
+    D.close()
+
+
 def test_uhd45_full_size_sampled(ctx):
     """3840x2160, N = 45, 300k Gaussians: sampled subpixels against the oracle."""
     log("uhd45 full size")
