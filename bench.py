@@ -248,7 +248,9 @@ def run_gpu(args):
     if dom == "blend":
         flops = (cnt["evaluations"] * FLOP_Q + cnt["blends"] * FLOP_BLEND) / launches
         ach = flops / (per_launch_ms * 1e-3) / 1e12
-        tr = measured_traffic("blend_kernel<false, %d, false, %d>" % (stages[0]["rays_per_lane"], stages[0]["lanes"])) \
+        # the identity map's rays each fill one channel here (three views per pixel): the single-channel kernel
+        tr = measured_traffic("blend_kernel<false, true, %d, false, %d>" % (stages[0]["rays_per_lane"],
+                                                                            stages[0]["lanes"])) \
             if args.workload == "uhd45" else None
         roof = {"kernel": "blend", "bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4),

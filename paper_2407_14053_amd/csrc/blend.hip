@@ -152,35 +152,41 @@ __global__ __launch_bounds__(NT, (blend_min_waves<RPT>())) void blend_kernel(con
 
   // sT: the ray's transmittance, its sign carrying the ray's state (negative once terminated or absent)
   // (single-channel rays accumulate their one channel in C0; ch is that channel)
+  // (the ray's state slot and channel mask are not kept across the record loop: they are recomputed from the pixel
+  // position, the ray list and the thread index where needed, so that the loop's registers stay within the
+  // occupancy bound without spilling)
   float px[RPT], py[RPT], sT[RPT], C0[RPT], C1[RPT], C2[RPT];
-  uint32_t mask[RPT], ch[RPT], nev[RPT], nbl[RPT];
-  int64_t gid[RPT];
+  uint32_t ch[RPT], nev[RPT], nbl[RPT];
+  const auto state_slot = [&](int j) -> int64_t {
+    if (STD)
+      return ((int64_t)v * bc.H + (int)(py[j] - 0.5f)) * bc.W + (int)(px[j] - 0.5f);
+    return (int64_t)r0 + threadIdx.x + j * NT;
+  };
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int idx = threadIdx.x + j * NT;
     const bool valid = idx < nr;
     int lx = 0, ly = 0;
-    mask[j] = 0;
+    uint32_t mask = 0;
     if (valid) {
       if (STD) {
         ly = idx / cw;
         lx = idx - ly * cw;
-        mask[j] = 7u;
+        mask = 7u;
       } else {
         const uint32_t e = ray_ent[r0 + idx];
         lx = (int)(e & 0xfffu);
         ly = (int)((e >> 12) & 0xfffu);
-        mask[j] = (e >> 24) & 7u;
+        mask = (e >> 24) & 7u;
       }
     }
-    ch[j] = min(mask[j] >> 1, 2u);  // the channel of a one-channel mask (1, 2, 4 -> 0, 1, 2)
+    ch[j] = min(mask >> 1, 2u);  // the channel of a one-channel mask (1, 2, 4 -> 0, 1, 2)
     px[j] = (float)(ox + lx) + 0.5f;
     py[j] = (float)(oy + ly) + 0.5f;
-    gid[j] = STD ? ((int64_t)v * bc.H + oy + ly) * bc.W + ox + lx : (int64_t)r0 + idx;
     sT[j] = valid ? 1.0f : -1.0f;
     C0[j] = C1[j] = C2[j] = 0.0f;
     if (valid && !bk.first) {
-      const float4 st = state[gid[j]];
+      const float4 st = state[state_slot(j)];
       sT[j] = st.x;
       if (SC) {
         C0[j] = ch[j] == 0 ? st.y : (ch[j] == 1 ? st.z : st.w);
@@ -284,7 +290,7 @@ __global__ __launch_bounds__(NT, (blend_min_waves<RPT>())) void blend_kernel(con
       const uint32_t k = ch[j];
       if (!bk.last && tile_live) {
         const float c[3] = {k == 0 ? C0[j] : 0.0f, k == 1 ? C0[j] : 0.0f, k == 2 ? C0[j] : 0.0f};
-        state[gid[j]] = make_float4(sT[j], c[0], c[1], c[2]);
+        state[state_slot(j)] = make_float4(sT[j], c[0], c[1], c[2]);
       }
       if (bk.last || !tile_live) {
         const int xr = (int)(py[j] - 0.5f), yc = (int)(px[j] - 0.5f);
@@ -293,7 +299,7 @@ __global__ __launch_bounds__(NT, (blend_min_waves<RPT>())) void blend_kernel(con
       }
       continue;
     }
-    if (!bk.last && tile_live) state[gid[j]] = make_float4(sT[j], C0[j], C1[j], C2[j]);
+    if (!bk.last && tile_live) state[state_slot(j)] = make_float4(sT[j], C0[j], C1[j], C2[j]);
     if (bk.last || !tile_live) {
       const int xr = (int)(py[j] - 0.5f), yc = (int)(px[j] - 0.5f);
       const float Tf = fabsf(sT[j]);
@@ -304,18 +310,20 @@ __global__ __launch_bounds__(NT, (blend_min_waves<RPT>())) void blend_kernel(con
         dst[1] = c[1];
         dst[2] = c[2];
       } else {
+        const uint32_t e = ray_ent[r0 + idx];
+        const uint32_t mask = (e >> 24) & 7u;
         if (bc.tgt) {
           // repurposed panel: channel k of the ray fills the subpixel listed for it
-          const uint32_t sl = (ray_ent[r0 + idx] >> 27) & 3u;
+          const uint32_t sl = (e >> 27) & 3u;
           const int32_t* tg = bc.tgt + ((int64_t)3 * ((int64_t)xr * bc.W + yc) + sl) * 3;
 #pragma unroll
           for (int k = 0; k < 3; ++k)
-            if (mask[j] & (1u << k)) out[tg[k]] = c[k];
+            if (mask & (1u << k)) out[tg[k]] = c[k];
         } else {
           float* dst = out + ((int64_t)xr * bc.W + yc) * 3;
 #pragma unroll
           for (int k = 0; k < 3; ++k)
-            if (mask[j] & (1u << k)) dst[k] = c[k];
+            if (mask & (1u << k)) dst[k] = c[k];
         }
       }
     }
