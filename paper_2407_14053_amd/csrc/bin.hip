@@ -138,8 +138,8 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
   WaveBin& W = wb[w];
   uint32_t* tc = reinterpret_cast<uint32_t*>(tcnt_s);  // tc[4 t + w]: wavefront w's counter of tile t
   // TABLE: a one-dimensional grid in which all workgroups of view v have the same index modulo 8, so that they
-  // run on one XCD (workgroups are handed to the 8 XCDs in turn) and the scattered writes into the view's
-  // table and lists merge in that XCD's L2.  Otherwise blockIdx.y is the view.
+  // run on one XCD (workgroups are handed to the 8 XCDs in turn) and the view's table and lists are touched by
+  // one L2.  Otherwise blockIdx.y is the view.
   int v, bx, gx;
   if (TABLE) {
     gx = (int)ch.tgx;

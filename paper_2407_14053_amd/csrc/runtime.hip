@@ -553,10 +553,11 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                               C->k64[0].as<uint64_t>(), s));
   C->end(mk, s);
   hipError_t e;
-  // Depth order.  The first chunk is each view's front (the nearest ~1/16 of its visible Gaussians, chosen on a
+  // Depth order.  The first chunk is each view's front (the nearest ~1/32 of its visible Gaussians, chosen on a
   // histogram of the keys' top bits); one stable pass drops the culled items and puts the front before the
-  // back, the fronts are sorted now and the backs after the first chunk, only for views that still have a live
-  // tile.  Both sorts take the same number of passes, so the ranks of a view end in one buffer.
+  // back, the fronts are sorted now (in LDS, one workgroup per view, for scenes of at most kFrontSortMaxG
+  // Gaussians; else by device passes) and the backs after the first chunk, only for views that still have a live
+  // tile.  Every view's ranks end in one buffer.
   mk = C->begin(DL_STAGE_DEPTH_SORT, s);
   uint32_t* vis = C->vis.as<uint32_t>();
   uint32_t* front = C->dord.as<uint32_t>();

@@ -293,6 +293,47 @@ def test_serving_batches_queued_requests_of_one_pair(ctx):
     srv.close()
 
 
+def test_serving_at_workload_scale_equals_eager_and_oracle(ctx):
+    """The serving workload's own scenes and panels (0.5M and 1M Gaussians uniform in [-2, 2]^3; 1920x1080 N=16,
+    3840x2160 N=45, 7680x4320 N=60), plans made before the run, batched launches: every served frame equals the
+    eager frame of the same request bit for bit, and sampled subpixels of one frame per panel match the oracle."""
+    from paper_2407_14053_amd import serving
+    log("serving at workload scale")
+    srv = serving.Server(ctx, n_slots=4, keep_images=True, grow_in_loop=False, batch_max=2)
+    scenes = {"g500k": synth.serving_scene(500_000, 1004), "g1m": synth.serving_scene(1_000_000, 1005)}
+    for k, v in scenes.items():
+        srv.add_scene(k, v)
+    displays = {k: synth.make_named_display(k) for k in ("fhd16", "uhd45", "8k60")}
+    for k, v in displays.items():
+        srv.add_display(k, v)
+    import math
+    probes = [synth.look_at_c2w((3.0 * math.sin(a), 0.0, 3.0 * math.cos(a))) for a in np.arange(8) * math.pi / 4]
+    srv.warm(probe_poses=probes)
+    reqs = serving.poisson_requests(12, 200.0, list(scenes), list(displays), seed=2006)
+    rep = srv.run(reqs, realtime=True)
+    log("  ", {k: v for k, v in rep.summary().items() if k != "per_display"})
+    # every request served once; a plan is made in the loop only to replace one whose capacity a pose overflowed
+    assert sorted(d.rid for d in rep.done) == sorted(r.rid for r in reqs)
+    assert rep.admitted == len(reqs) + rep.replans and rep.plans_created <= rep.replans
+    assert (rep.plans_created == 0) == (rep.replans == 0)
+    by_id = {r.rid: r for r in reqs}
+    checked = set()
+    from paper_2407_14053_amd import api
+    for dn in rep.done:
+        r = by_id[dn.rid]
+        got = dn.image.cpu().numpy()
+        alone = api.render(ctx, srv.scenes[r.scene], srv.displays[r.display], r.c2w).cpu().numpy()
+        assert np.array_equal(got, alone), (dn.rid, r.scene, r.display)
+        if r.display not in checked:
+            checked.add(r.display)
+            d = displays[r.display]
+            xs, ys, ks = sample_subpixels(d.height, d.width, 150, 50 + dn.rid)
+            worst, over, _ = check_subpixels(scenes[r.scene], d, r.c2w, got, xs, ys, ks, label="serving " + r.display)
+            log("   %s/%s worst %.3g over %d" % (r.scene, r.display, worst, over))
+            assert worst <= TOL and over <= 0.001 * len(xs)
+    srv.close()
+
+
 def test_serving_rejects_request_larger_than_budget(ctx):
     from paper_2407_14053_amd import serving
     srv, scenes, displays = _server(ctx)
