@@ -190,11 +190,18 @@ bool radix_sort_u64(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int6
 // One stable pass over full segments [s seg_len, (s + 1) seg_len) of keys k0 that leaves out items whose key is
 // drop_key and splits the rest into keys < thr[s] (first) and keys >= thr[s]; values are the items' positions in
 // their segment.  Results in (k1, v1); n_vis[s] = items kept, n_front[s] = items below thr[s].  hist holds
-// split_hist_size(seg_len, n_seg) entries.
+// split_hist_size(seg_len, n_seg) entries.  With `live`, segments s with live[s] == 0 are left alone (nothing
+// written, counts kept); with back_only, only the items >= thr[s] are written (at the same places).
 int64_t split_hist_size(int64_t seg_len, int n_seg);
+int split_waves_per_seg(int64_t seg_len, int n_seg);
 bool radix_split_u64(uint64_t* k0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg, const uint64_t* thr,
                      uint64_t drop_key, uint32_t* n_vis, uint32_t* n_front, uint32_t* hist, uint32_t* partial,
-                     hipStream_t s, hipError_t* err);
+                     hipStream_t s, hipError_t* err, const uint32_t* live = nullptr, bool back_only = false);
+// The front part of that split alone: each of the split's runs (split_waves_per_seg runs per segment) keeps its
+// items that are not drop_key and below thr[s], in order, at the run's start in (kout, vout), and cnt
+// (split_hist_size entries) receives per run the count of those and of all kept items, [segment][2][run].
+hipError_t launch_front_gather(const uint64_t* keys, uint64_t* kout, uint32_t* vout, int64_t G, int N,
+                               const uint64_t* thr, uint64_t drop_key, uint32_t* cnt, hipStream_t s);
 // Stable LSD sort of each device range [lo[s], hi[s]) in place (n_seg <= 256), with the histogram layout that
 // launch_depth_ranges wrote to `layout`; returns whether the result is in (k1, v1).  hist: depth_ranges_hist_size
 // entries.
@@ -210,13 +217,16 @@ hipError_t launch_front_select(const uint64_t* keys, int64_t G, int N, int key_b
                                int64_t den, uint32_t* hist, uint64_t* thr, hipStream_t s);
 // Ranges of the depth sorts: live == nullptr: the fronts [vG, vG + f); else the backs [vG + f, vG + n) of views
 // with a live tile (empty otherwise); rank_hi = end rank of the range; layout (2N + 1 entries) for the sort.
-// The fronts of the views sorted in LDS, one workgroup per view (Gaussians per view at most kFrontSortMaxG): the
-// values of each view's front [v G, v G + n_front[v]) of (keys, vals) are put in depth order in place; a front of
-// more than 12288 items is first cut (n_front lowered, the rest moved in order to the start of the back, through
-// tmp_keys / tmp_vals); rank_hi[v] = n_front[v].
+// The fronts of the views sorted in LDS, one workgroup per view, from the runs that launch_front_gather left in
+// (keys, vals) with its counts cnt: vals[v G, v G + n_front[v]) receives the front's Gaussian indices in depth
+// order, n_vis[v] the view's kept items, rank_hi[v] = n_front[v].  A front of more than 12288 items is cut at a
+// bin of the key's top 12 bits, thr[v] lowered to that bin's start and n_front to the items below it; the rest
+// belongs to the back (a back-only split with the lowered thr puts it after the front).  Usable when
+// front_sort_fits(G, N): Gaussians per view at most kFrontSortMaxG.
 constexpr int64_t kFrontSortMaxG = 400000;
-hipError_t launch_front_sort(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals, int64_t G, int N,
-                             uint32_t* n_front, uint32_t* rank_hi, hipStream_t s);
+bool front_sort_fits(int64_t G, int N);
+hipError_t launch_front_sort(const uint64_t* keys, uint32_t* vals, int64_t G, int N, const uint32_t* cnt,
+                             uint64_t* thr, uint32_t* n_vis, uint32_t* n_front, uint32_t* rank_hi, hipStream_t s);
 hipError_t launch_depth_ranges(int N, int64_t G, const uint32_t* n_vis, const uint32_t* n_front,
                                const uint32_t* live, uint32_t* lo, uint32_t* hi, uint32_t* rank_hi, uint32_t* layout,
                                hipStream_t s);

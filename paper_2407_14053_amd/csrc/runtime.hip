@@ -554,10 +554,11 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   C->end(mk, s);
   hipError_t e;
   // Depth order.  The first chunk is each view's front (the nearest ~1/32 of its visible Gaussians, chosen on a
-  // histogram of the keys' top bits); one stable pass drops the culled items and puts the front before the
-  // back, the fronts are sorted now (in LDS, one workgroup per view, for scenes of at most kFrontSortMaxG
-  // Gaussians; else by device passes) and the backs after the first chunk, only for views that still have a live
-  // tile.  Every view's ranks end in one buffer.
+  // histogram of the keys' top bits).  Scenes of at most kFrontSortMaxG Gaussians: one pass gathers the fronts
+  // (culled items dropped) and one workgroup per view sorts its front in LDS; the backs are split off and sorted
+  // after the first chunk, only for views that still have a live tile.  Larger scenes: one stable pass drops the
+  // culled items and puts each front before its back, and device passes sort the fronts now and the live backs
+  // later.  Every view's ranks end in one buffer.
   mk = C->begin(DL_STAGE_DEPTH_SORT, s);
   uint32_t* vis = C->vis.as<uint32_t>();
   uint32_t* front = C->dord.as<uint32_t>();
@@ -568,15 +569,17 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   uint64_t* thr = C->thr.as<uint64_t>();
   HIP_TRY(launch_front_select(C->k64[0].as<uint64_t>(), G, N, kDepthKeyBits, kDepthCulled, kChunkBounds[1], kChunkDen,
                               C->fhist.as<uint32_t>(), thr, s));
-  radix_split_u64(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N, thr, kDepthCulled,
-                  vis, front, C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s, &e);
-  if (e != hipSuccess) return fail(DL_EHIP, std::string("depth split: ") + hipGetErrorString(e));
   bool fl = false;
-  if (G <= kFrontSortMaxG) {
-    // small scenes: every view's front sorted in LDS by one workgroup (one launch instead of the passes below)
-    HIP_TRY(launch_front_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), C->k64[0].as<uint64_t>(),
-                              C->v32[0].as<uint32_t>(), G, N, front, rank_hi, s));
+  const bool lds_front = front_sort_fits(G, N);
+  if (lds_front) {
+    HIP_TRY(launch_front_gather(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N,
+                                thr, kDepthCulled, C->hist.as<uint32_t>(), s));
+    HIP_TRY(launch_front_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N, C->hist.as<uint32_t>(), thr,
+                              vis, front, rank_hi, s));
   } else {
+    radix_split_u64(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N, thr,
+                    kDepthCulled, vis, front, C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s, &e);
+    if (e != hipSuccess) return fail(DL_EHIP, std::string("depth split: ") + hipGetErrorString(e));
     HIP_TRY(launch_depth_ranges(N, G, vis, front, nullptr, rlo, rhi, rank_hi, dlayout, s));
     fl = depth_ranges_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), C->k64[0].as<uint64_t>(),
                            C->v32[0].as<uint32_t>(), G, N, rlo, rhi, kDepthKeyBits, C->hist.as<uint32_t>(),
@@ -721,8 +724,15 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
       }
     }
     if (c == 0 && kChunks > 1) {
-      // the backs of the views that still have a live tile
+      // the backs of the views that still have a live tile (split off the projection's keys first when only the
+      // fronts were gathered)
       mk = C->begin(DL_STAGE_DEPTH_SORT, s);
+      if (lds_front) {
+        radix_split_u64(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N, thr,
+                        kDepthCulled, vis, front, C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s, &e,
+                        C->live.as<uint32_t>(), true);
+        if (e != hipSuccess) return fail(DL_EHIP, std::string("depth split: ") + hipGetErrorString(e));
+      }
       HIP_TRY(launch_depth_ranges(N, G, vis, front, C->live.as<uint32_t>(), rlo, rhi, rank_hi, dlayout, s));
       const bool fl2 = depth_ranges_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), C->k64[0].as<uint64_t>(),
                                          C->v32[0].as<uint32_t>(), G, N, rlo, rhi, kDepthKeyBits,

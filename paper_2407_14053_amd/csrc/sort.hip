@@ -526,12 +526,14 @@ __device__ inline uint32_t wave_sum_u32(uint32_t x) {
 
 __global__ __launch_bounds__(kThreads) void split_hist_kernel(const uint64_t* __restrict__ keys, int64_t G, int wps,
                                                                 const uint64_t* __restrict__ thr, uint64_t drop,
+                                                                const uint32_t* __restrict__ live,
                                                                 uint32_t* __restrict__ hist) {
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   const int v = (int)(gw / wps), k = (int)(gw - (int64_t)v * wps);
   int64_t lo, hi;
   split_range(G, wps, k, lo, hi);
+  if (live && !live[v]) hi = lo;  // a view left out: no items
   const uint64_t* kin = keys + (int64_t)v * G;
   const uint64_t th = thr[v];
   uint32_t c0 = 0, c1 = 0;
@@ -556,12 +558,14 @@ __global__ __launch_bounds__(kThreads) void split_hist_kernel(const uint64_t* __
 
 __global__ __launch_bounds__(kThreads) void split_scatter_kernel(const uint64_t* __restrict__ keys, int64_t G,
                                                                    int wps, const uint64_t* __restrict__ thr,
-                                                                   uint64_t drop, const uint32_t* __restrict__ hist,
+                                                                   uint64_t drop, const uint32_t* __restrict__ live,
+                                                                   bool back_only, const uint32_t* __restrict__ hist,
                                                                    uint64_t* __restrict__ kout,
                                                                    uint32_t* __restrict__ vout) {
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   const int v = (int)(gw / wps), k = (int)(gw - (int64_t)v * wps);
+  if (live && !live[v]) return;
   int64_t lo, hi;
   split_range(G, wps, k, lo, hi);
   const uint64_t* kin = keys + (int64_t)v * G;
@@ -580,14 +584,14 @@ __global__ __launch_bounds__(kThreads) void split_scatter_kernel(const uint64_t*
     const bool fa = ka != drop && ka < th, ba = ka != drop && ka >= th;
     const bool fb = kb != drop && kb < th, bb = kb != drop && kb >= th;
     const uint64_t mfa = __ballot(fa), mba = __ballot(ba), mfb = __ballot(fb), mbb = __ballot(bb);
-    if (fa | ba) {
+    if ((fa && !back_only) || ba) {
       const uint32_t at = fa ? p0 + (uint32_t)__popcll(mfa & below) : p1 + (uint32_t)__popcll(mba & below);
       ko[at] = ka;
       vo[at] = (uint32_t)ia;
     }
     p0 += (uint32_t)__popcll(mfa);
     p1 += (uint32_t)__popcll(mba);
-    if (fb | bb) {
+    if ((fb && !back_only) || bb) {
       const uint32_t at = fb ? p0 + (uint32_t)__popcll(mfb & below) : p1 + (uint32_t)__popcll(mbb & below);
       ko[at] = kb;
       vo[at] = (uint32_t)ib;
@@ -598,14 +602,61 @@ __global__ __launch_bounds__(kThreads) void split_scatter_kernel(const uint64_t*
 }
 
 __global__ void split_counts_kernel(const uint32_t* __restrict__ hist, const uint32_t* __restrict__ grand, int n_seg,
-                                    int bps, uint32_t* __restrict__ n_vis, uint32_t* __restrict__ n_front) {
+                                    int bps, const uint32_t* __restrict__ live, uint32_t* __restrict__ n_vis,
+                                    uint32_t* __restrict__ n_front) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n_seg) return;
+  if (v >= n_seg || (live && !live[v])) return;
   const uint32_t a = hist[(int64_t)v * 2 * bps];
   const uint32_t b = hist[((int64_t)v * 2 + 1) * bps];
   const uint32_t c = v + 1 < n_seg ? hist[(int64_t)(v + 1) * 2 * bps] : *grand;
   n_vis[v] = c - a;
   n_front[v] = b - a;
+}
+
+// The first chunk's part of the split: each wavefront keeps its run's front items (not dropped, key below the
+// view's threshold), in order, at the start of that run in (kout, vout), values = positions in the view, and
+// counts them and its kept items: cnt[2 v wps + k] = fronts, cnt[(2 v + 1) wps + k] = kept, for run k of view v.
+// The front sort gathers the runs; the backs are split only when a later chunk needs them.
+__global__ __launch_bounds__(kThreads) void front_gather_kernel(const uint64_t* __restrict__ keys, int64_t G, int wps,
+                                                                  const uint64_t* __restrict__ thr, uint64_t drop,
+                                                                  uint64_t* __restrict__ kout,
+                                                                  uint32_t* __restrict__ vout,
+                                                                  uint32_t* __restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int v = (int)(gw / wps), k = (int)(gw - (int64_t)v * wps);
+  int64_t lo, hi;
+  split_range(G, wps, k, lo, hi);
+  const uint64_t* kin = keys + (int64_t)v * G;
+  uint64_t* ko = kout + (int64_t)v * G + lo;
+  uint32_t* vo = vout + (int64_t)v * G + lo;
+  const uint64_t th = thr[v];
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint32_t p = 0, kept = 0;
+  for (int64_t i0 = lo; i0 < hi; i0 += 256) {
+    uint64_t kk[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {  // four independent loads in flight
+      const int64_t i = i0 + 64 * r + lane;
+      kk[r] = i < hi ? kin[i] : drop;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool in = kk[r] != drop, fr = in && kk[r] < th;
+      const uint64_t m = __ballot(fr);
+      if (fr) {
+        const uint32_t at = p + (uint32_t)__popcll(m & below);
+        ko[at] = kk[r];
+        vo[at] = (uint32_t)(i0 + 64 * r + lane);
+      }
+      p += (uint32_t)__popcll(m);
+      kept += (uint32_t)__popcll(__ballot(in));
+    }
+  }
+  if (lane == 0) {
+    cnt[(int64_t)v * 2 * wps + k] = p;
+    cnt[((int64_t)v * 2 + 1) * wps + k] = kept;
+  }
 }
 
 // Device ranges of the depth sorts (one workgroup, N <= kThreads): front [v G, v G + f_v); back
@@ -653,15 +704,16 @@ __global__ __launch_bounds__(kThreads) void lower_bounds_kernel(const uint32_t* 
 }
 
 // ---- depth order of small fronts: one workgroup per view sorts the view's front in LDS ----
-// The front of a view (its f_v nearest visible Gaussians after the split, in Gaussian index order) is packed as
-// key << 24 | index (36 + 24 bits) and sorted by four stable LSD passes of 9 bits over the key bits in LDS, which
-// gives the order by (depth key, index) of the device passes in one launch.  Wavefront w owns the contiguous items
-// [w R, (w + 1) R) (R a multiple of 64), visited in slots of 64 consecutive items; a lane's rank among the equal
-// digits of its slot comes from a match mask of nine ballots, its rank in the wavefront from a running count per
-// (digit, wavefront), and the scatter position from the exclusive scan of those counts in (digit, wavefront)
-// order.  A front larger than the LDS holds is first cut at a bin of the key's top 12 bits (an exact histogram of
-// the front): the items at or above that bin move, in order, to the start of the view's back (a stable partition
-// through the other key buffer), and the view's front count is lowered to what remains.
+// The front of a view (its nearest visible Gaussians, left by the gather pass at the starts of the view's runs,
+// each run in Gaussian index order) is collected run by run into LDS in index order, packed as key << 24 | index
+// (36 + 24 bits), and sorted by four stable LSD passes of 9 bits over the key bits, which gives the order by
+// (depth key, index) of the device passes in one launch.  Wavefront w owns the contiguous items [w R, (w + 1) R)
+// (R a multiple of 64), visited in slots of 64 consecutive items; a lane's rank among the equal digits of its slot
+// comes from a match mask of nine ballots, its rank in the wavefront from a running count per (digit, wavefront),
+// and the scatter position from the exclusive scan of those counts in (digit, wavefront) order.  A front larger
+// than the LDS holds is first cut at a bin of the key's top 12 bits (an exact histogram of the front): only the
+// items below that bin are collected, the view's threshold is lowered to the bin's start, and the others belong
+// to the back, which a later split pass takes from the projection's keys with that threshold.
 __device__ inline void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -675,7 +727,10 @@ constexpr int kFsCap = kFsThreads * kFsSlots;  // 12288 items
 constexpr int kFsBits = 9;
 constexpr int kFsBins = 1 << kFsBits;
 constexpr int kFsCutBins = 4096;  // the top 12 bits of the 36-bit key
+constexpr int kFsMaxRuns = kFsBins * kFsWaves;  // gather runs per view (their offsets live in the count array)
+constexpr int kFsRunsPerThread = kFsMaxRuns / kFsThreads;
 static_assert(kFsBins * kFsWaves >= kFsCutBins, "the cut histogram shares the count array");
+static_assert(kFsCutBins == 4 * kFsThreads, "four cut bins per thread");
 static_assert(kDepthKeyBits == 4 * kFsBits, "four passes cover the depth key");
 
 struct FrontSortSmem {
@@ -685,8 +740,9 @@ struct FrontSortSmem {
   uint32_t misc[2];
 };
 
-// Exclusive prefix over the workgroup of one value per thread, in thread order (all threads must call it).
-__device__ inline uint32_t fs_block_scan(uint32_t x, uint32_t* wsum) {
+// Exclusive prefix over the workgroup of one value per thread, in thread order (all threads must call it);
+// *total (if given) receives the workgroup's sum.
+__device__ inline uint32_t fs_block_scan(uint32_t x, uint32_t* wsum, uint32_t* total = nullptr) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint32_t inc = x;
 #pragma unroll
@@ -696,27 +752,44 @@ __device__ inline uint32_t fs_block_scan(uint32_t x, uint32_t* wsum) {
   }
   if (lane == 63) wsum[w] = inc;
   __syncthreads();
-  uint32_t base = 0;
-  for (int k = 0; k < w; ++k) base += wsum[k];
+  uint32_t base = 0, all = 0;
+  for (int k = 0; k < kFsWaves; ++k) {
+    base += k < w ? wsum[k] : 0u;
+    all += wsum[k];
+  }
   __syncthreads();
+  if (total) *total = all;
   return base + inc - x;
 }
 
-// Cut a front of f > kFsCap items (see above); returns the new front size.
-__device__ uint32_t fs_cut_front(FrontSortSmem& sm, uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys,
-                                 uint32_t* tmp_vals, int64_t base, uint32_t f) {
-  const int t = threadIdx.x;
+// Item i of run k of the view (base = v G): the gather pass left the run's fronts at the run's start.
+__device__ inline int64_t fs_run_start(int64_t G, int wps, int k) {
+  int64_t lo, hi;
+  split_range(G, wps, k, lo, hi);
+  return lo;
+}
+
+// A front of f > kFsCap items (runs of cf[k] items): the largest bin `cut` of the top 12 key bits such that the
+// items of the bins below it fit; those are written to sm.items in index order and their count returned, and
+// *thr_v becomes cut << 24.
+__device__ uint32_t fs_cut_runs(FrontSortSmem& sm, const uint64_t* keys, const uint32_t* vals, int64_t base,
+                                int64_t G, int wps, const uint32_t* cf, uint64_t* thr_v) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   for (int b = t; b < kFsCutBins; b += kFsThreads) sm.cnt[b] = 0;
   if (t == 0) sm.misc[0] = sm.misc[1] = 0;
   __syncthreads();
-  for (uint32_t i = t; i < f; i += kFsThreads) atomicAdd(&sm.cnt[(uint32_t)(keys[base + i] >> 24) & 4095u], 1u);
+  for (int k = w; k < wps; k += kFsWaves) {
+    const int64_t r0 = base + fs_run_start(G, wps, k);
+    const uint32_t c = cf[k];
+    for (uint32_t i = lane; i < c; i += 64) atomicAdd(&sm.cnt[(uint32_t)(keys[r0 + i] >> 24) & 4095u], 1u);
+  }
   __syncthreads();
   // bin b holds cnt[b]; thread t owns bins 4t .. 4t + 3; `below` = items in the bins below the current one
-  uint32_t c[4], loc = 0;
+  uint32_t c4[4], loc = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    c[k] = sm.cnt[4 * t + k];
-    loc += c[k];
+    c4[k] = sm.cnt[4 * t + k];
+    loc += c4[k];
   }
   uint32_t below = fs_block_scan(loc, sm.wsum);
   uint32_t best = 0, best_n = 0;
@@ -726,7 +799,7 @@ __device__ uint32_t fs_cut_front(FrontSortSmem& sm, uint64_t* keys, uint32_t* va
       best = 4 * t + k;
       best_n = below;
     }
-    below += c[k];
+    below += c4[k];
   }
   // the largest such bin (the item counts below are non-decreasing in the bin)
   atomicMax(&sm.misc[0], best);
@@ -735,55 +808,96 @@ __device__ uint32_t fs_cut_front(FrontSortSmem& sm, uint64_t* keys, uint32_t* va
   if (best == cut && best_n <= (uint32_t)kFsCap) sm.misc[1] = best_n;  // the owner of bin `cut` (one thread)
   __syncthreads();
   const uint32_t kept_total = sm.misc[1];
-  __syncthreads();
-  // stable partition: items of the bins below `cut` to [0, kept_total), the others after them, in order
-  uint32_t kept = 0, moved = 0;
-  for (uint32_t r0 = 0; r0 < f; r0 += kFsThreads) {
-    const uint32_t i = r0 + t;
-    const bool in = i < f;
-    const uint64_t k = in ? keys[base + i] : 0ull;
-    const uint32_t val = in ? vals[base + i] : 0u;
-    const bool keep = in && ((uint32_t)(k >> 24) & 4095u) < cut;
-    const bool move = in && !keep;
-    const uint32_t pk = fs_block_scan(keep ? 1u : 0u, sm.wsum);
-    const uint32_t pm = fs_block_scan(move ? 1u : 0u, sm.wsum);
-    if (t == kFsThreads - 1) {
-      sm.misc[0] = pk + (keep ? 1u : 0u);
-      sm.misc[1] = pm + (move ? 1u : 0u);
+  // kept items per run (the histogram is no longer read), then their offsets in run order
+  for (int k = w; k < wps; k += kFsWaves) {
+    const int64_t r0 = base + fs_run_start(G, wps, k);
+    const uint32_t c = cf[k];
+    uint32_t n = 0;
+    for (uint32_t i0 = 0; i0 < c; i0 += 64) {
+      const uint32_t i = i0 + lane;
+      n += (uint32_t)__popcll(__ballot(i < c && ((uint32_t)(keys[r0 + i] >> 24) & 4095u) < cut));
     }
-    __syncthreads();
-    const int64_t dst = keep ? base + kept + pk : base + kept_total + moved + pm;
-    if (in) {
-      tmp_keys[dst] = k;
-      tmp_vals[dst] = val;
-    }
-    kept += sm.misc[0];
-    moved += sm.misc[1];
-    __syncthreads();
+    if (lane == 0) sm.cnt[k] = n;
   }
-  __threadfence_block();
   __syncthreads();
-  for (uint32_t i = t; i < f; i += kFsThreads) {
-    keys[base + i] = tmp_keys[base + i];
-    vals[base + i] = tmp_vals[base + i];
+  uint32_t e[kFsRunsPerThread], mine = 0;
+#pragma unroll
+  for (int q = 0; q < kFsRunsPerThread; ++q) {
+    const int k = t * kFsRunsPerThread + q;
+    e[q] = k < wps ? sm.cnt[k] : 0u;
+    mine += e[q];
   }
-  __threadfence_block();
+  uint32_t run = fs_block_scan(mine, sm.wsum);
+#pragma unroll
+  for (int q = 0; q < kFsRunsPerThread; ++q) {
+    const int k = t * kFsRunsPerThread + q;
+    if (k < wps) sm.cnt[k] = run;
+    run += e[q];
+  }
+  __syncthreads();
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int k = w; k < wps; k += kFsWaves) {
+    const int64_t r0 = base + fs_run_start(G, wps, k);
+    const uint32_t c = cf[k];
+    uint32_t o = sm.cnt[k];
+    for (uint32_t i0 = 0; i0 < c; i0 += 64) {
+      const uint32_t i = i0 + lane;
+      const uint64_t key = i < c ? keys[r0 + i] : 0ull;
+      const bool keep = i < c && ((uint32_t)(key >> 24) & 4095u) < cut;
+      const uint64_t m = __ballot(keep);
+      if (keep) sm.items[o + (uint32_t)__popcll(m & lt)] = (key << 24) | (unsigned long long)vals[r0 + i];
+      o += (uint32_t)__popcll(m);
+    }
+  }
+  if (t == 0) *thr_v = (uint64_t)cut << 24;
   __syncthreads();
   return kept_total;
 }
 
-__global__ __launch_bounds__(kFsThreads) void front_sort_kernel(uint64_t* __restrict__ keys,
-                                                                 uint32_t* __restrict__ vals,
-                                                                 uint64_t* __restrict__ tmp_keys,
-                                                                 uint32_t* __restrict__ tmp_vals, int64_t G,
+__global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* __restrict__ keys,
+                                                                 uint32_t* __restrict__ vals, int64_t G, int wps,
+                                                                 const uint32_t* __restrict__ cnt,
+                                                                 uint64_t* __restrict__ thr,
+                                                                 uint32_t* __restrict__ n_vis,
                                                                  uint32_t* __restrict__ n_front,
                                                                  uint32_t* __restrict__ rank_hi) {
   __shared__ FrontSortSmem sm;
   const int v = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t base = (int64_t)v * G;
-  uint32_t f = n_front[v];
-  if (f > (uint32_t)kFsCap) f = fs_cut_front(sm, keys, vals, tmp_keys, tmp_vals, base, f);
+  const uint32_t* cf = cnt + (int64_t)v * 2 * wps;  // fronts per run
+  const uint32_t* cv = cf + wps;                    // kept items per run
+  // the runs' offsets in the front (thread t owns runs t R', ..., t R' + R' - 1), the front and visible counts
+  uint32_t e[kFsRunsPerThread], mine = 0, vis = 0;
+#pragma unroll
+  for (int q = 0; q < kFsRunsPerThread; ++q) {
+    const int k = t * kFsRunsPerThread + q;
+    e[q] = k < wps ? cf[k] : 0u;
+    mine += e[q];
+    vis += k < wps ? cv[k] : 0u;
+  }
+  uint32_t f = 0, nv = 0;
+  uint32_t run = fs_block_scan(mine, sm.wsum, &f);
+  fs_block_scan(vis, sm.wsum, &nv);
+  if (f <= (uint32_t)kFsCap) {
+#pragma unroll
+    for (int q = 0; q < kFsRunsPerThread; ++q) {
+      const int k = t * kFsRunsPerThread + q;
+      if (k < wps) sm.cnt[k] = run;
+      run += e[q];
+    }
+    __syncthreads();
+    // wavefront w collects runs w, w + 16, ...
+    for (int k = w; k < wps; k += kFsWaves) {
+      const int64_t r0 = base + fs_run_start(G, wps, k);
+      const uint32_t c = cf[k], o = sm.cnt[k];
+      for (uint32_t i = lane; i < c; i += 64)
+        sm.items[o + i] = (keys[r0 + i] << 24) | (unsigned long long)vals[r0 + i];
+    }
+    __syncthreads();
+  } else {
+    f = fs_cut_runs(sm, keys, vals, base, G, wps, cf, thr + v);
+  }
   const uint32_t R = (f + kFsThreads - 1) / kFsThreads * 64;  // items per wavefront, a multiple of 64
   const int nslot = (int)(R / 64);                             // <= kFsSlots
   unsigned long long it[kFsSlots];
@@ -791,7 +905,7 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(uint64_t* __rest
 #pragma unroll
   for (int j = 0; j < kFsSlots; ++j) {
     const uint32_t i = w * R + j * 64 + lane;
-    it[j] = (j < nslot && i < f) ? ((keys[base + i] << 24) | (unsigned long long)vals[base + i]) : 0ull;
+    it[j] = (j < nslot && i < f) ? sm.items[i] : 0ull;
     rank[j] = 0;
   }
   const uint64_t lt = (1ull << lane) - 1ull;
@@ -856,6 +970,7 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(uint64_t* __rest
   }
   for (uint32_t i = t; i < f; i += kFsThreads) vals[base + i] = (uint32_t)(sm.items[i] & 0xffffffull);
   if (t == 0) {
+    n_vis[v] = nv;
     n_front[v] = f;
     rank_hi[v] = f;
   }
@@ -1007,20 +1122,30 @@ int64_t split_hist_size(int64_t seg_len, int n_seg) { return (int64_t)n_seg * 2 
 
 bool radix_split_u64(uint64_t* k0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg, const uint64_t* thr,
                      uint64_t drop_key, uint32_t* n_vis, uint32_t* n_front, uint32_t* hist, uint32_t* partial,
-                     hipStream_t s, hipError_t* err) {
+                     hipStream_t s, hipError_t* err, const uint32_t* live, bool back_only) {
   const int wps = split_waves_per_seg(seg_len, n_seg);
   const int64_t hsize = split_hist_size(seg_len, n_seg);
   const unsigned blocks = (unsigned)((int64_t)n_seg * wps / kWaves);
-  hipLaunchKernelGGL(split_hist_kernel, dim3(blocks), dim3(kThreads), 0, s, k0, seg_len, wps, thr, drop_key, hist);
+  hipLaunchKernelGGL(split_hist_kernel, dim3(blocks), dim3(kThreads), 0, s, k0, seg_len, wps, thr, drop_key, live,
+                     hist);
   if ((*err = hipGetLastError()) != hipSuccess) return true;
   if ((*err = exclusive_scan_u32(hist, hist, hsize, partial, s)) != hipSuccess) return true;
-  hipLaunchKernelGGL(split_scatter_kernel, dim3(blocks), dim3(kThreads), 0, s, k0, seg_len, wps, thr, drop_key, hist,
-                     k1, v1);
+  hipLaunchKernelGGL(split_scatter_kernel, dim3(blocks), dim3(kThreads), 0, s, k0, seg_len, wps, thr, drop_key, live,
+                     back_only, hist, k1, v1);
   if ((*err = hipGetLastError()) != hipSuccess) return true;
   hipLaunchKernelGGL(split_counts_kernel, dim3((unsigned)((n_seg + 63) / 64)), dim3(64), 0, s, hist,
-                     partial + scan_partial_count(hsize), n_seg, wps, n_vis, n_front);
+                     partial + scan_partial_count(hsize), n_seg, wps, live, n_vis, n_front);
   *err = hipGetLastError();
   return true;
+}
+
+hipError_t launch_front_gather(const uint64_t* keys, uint64_t* kout, uint32_t* vout, int64_t G, int N,
+                               const uint64_t* thr, uint64_t drop_key, uint32_t* cnt, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  const int wps = split_waves_per_seg(G, N);
+  hipLaunchKernelGGL(front_gather_kernel, dim3((unsigned)((int64_t)N * wps / kWaves)), dim3(kThreads), 0, s, keys, G,
+                     wps, thr, drop_key, kout, vout, cnt);
+  return hipGetLastError();
 }
 
 int64_t depth_ranges_hist_size(int64_t seg_len, int n_seg) {
@@ -1063,12 +1188,15 @@ hipError_t launch_depth_ranges(int N, int64_t G, const uint32_t* n_vis, const ui
   return hipGetLastError();
 }
 
-hipError_t launch_front_sort(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals, int64_t G, int N,
-                             uint32_t* n_front, uint32_t* rank_hi, hipStream_t s) {
+bool front_sort_fits(int64_t G, int N) { return G <= kFrontSortMaxG && split_waves_per_seg(G, N) <= kFsMaxRuns; }
+
+hipError_t launch_front_sort(const uint64_t* keys, uint32_t* vals, int64_t G, int N, const uint32_t* cnt,
+                             uint64_t* thr, uint32_t* n_vis, uint32_t* n_front, uint32_t* rank_hi, hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  if (G > kFrontSortMaxG) return hipErrorInvalidValue;  // indices must fit the packed item's 24 bits
-  hipLaunchKernelGGL(front_sort_kernel, dim3((unsigned)N), dim3(kFsThreads), 0, s, keys, vals, tmp_keys, tmp_vals, G,
-                     n_front, rank_hi);
+  // indices must fit the packed item's 24 bits, and the runs' offsets the count array
+  if (!front_sort_fits(G, N)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(front_sort_kernel, dim3((unsigned)N), dim3(kFsThreads), 0, s, keys, vals, G,
+                     split_waves_per_seg(G, N), cnt, thr, n_vis, n_front, rank_hi);
   return hipGetLastError();
 }
 
