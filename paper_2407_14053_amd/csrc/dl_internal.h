@@ -209,12 +209,15 @@ int64_t depth_ranges_hist_size(int64_t seg_len, int n_seg);
 bool depth_ranges_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
                        const uint32_t* lo, const uint32_t* hi, int key_bits, uint32_t* hist, uint32_t* partial,
                        uint32_t* layout, hipStream_t s, hipError_t* err);
-// The front of each view's depth order: thr[v] = the smallest bin boundary of the top 12 key bits with at least
-// a fraction num / den of a sample of the view's visible keys (not `culled`) below it.  hist: front_hist_size(N)
-// entries, zero on entry.
+// The front of each view's depth order: thr[v] = the smallest bin boundary of the top kFrontBits key bits with at
+// least a fraction num / den of the sampled visible keys below it, from hist ([view][2^kFrontBits] counts, which
+// launch_project_keys fills: front_hist_size(N) entries, zero before it).
+constexpr int kFrontBits = 12;
+constexpr int kFrontSamplePeriod = 1024;  // Gaussians i with i mod kFrontSamplePeriod < kFrontSampleRun are sampled
+constexpr int kFrontSampleRun = 64;
 int64_t front_hist_size(int N);
-hipError_t launch_front_select(const uint64_t* keys, int64_t G, int N, int key_bits, uint64_t culled, int64_t num,
-                               int64_t den, uint32_t* hist, uint64_t* thr, hipStream_t s);
+hipError_t launch_front_select(int N, int key_bits, int64_t num, int64_t den, const uint32_t* hist, uint64_t* thr,
+                               hipStream_t s);
 // Ranges of the depth sorts: live == nullptr: the fronts [vG, vG + f); else the backs [vG + f, vG + n) of views
 // with a live tile (empty otherwise); rank_hi = end rank of the range; layout (2N + 1 entries) for the sort.
 // The fronts of the views sorted in LDS, one workgroup per view, from the runs that launch_front_gather left in
@@ -224,6 +227,7 @@ hipError_t launch_front_select(const uint64_t* keys, int64_t G, int N, int key_b
 // belongs to the back (a back-only split with the lowered thr puts it after the front).  Usable when
 // front_sort_fits(G, N): Gaussians per view at most kFrontSortMaxG.
 constexpr int64_t kFrontSortMaxG = 400000;
+constexpr int kFrontSortCap = 12288;  // the largest front sorted in LDS (larger ones are cut)
 bool front_sort_fits(int64_t G, int N);
 hipError_t launch_front_sort(const uint64_t* keys, uint32_t* vals, int64_t G, int N, const uint32_t* cnt,
                              uint64_t* thr, uint32_t* n_vis, uint32_t* n_front, uint32_t* rank_hi, hipStream_t s);
@@ -245,14 +249,15 @@ hipError_t launch_lower_bounds(const uint32_t* keys, const uint32_t* n_dev, uint
 // ---- projection (project.hip) ----
 hipError_t launch_project(const float* soa, const double* cams, const ProjConst& pc, float4* rec, uint64_t* keys,
                           uint32_t* vals, double* depth_out, hipStream_t s);
-// Depth keys of every (view, Gaussian) and each Gaussian's block of view-independent terms (blocks[G][18]).
+// Depth keys of every (view, Gaussian) and each Gaussian's block of view-independent terms (blocks[G][18]); the
+// sampled visible keys are added to the front histogram fhist (see launch_front_select).
 hipError_t launch_project_keys(const float* soa, const double* cams, const ProjConst& pc, float4* blocks,
-                               uint64_t* keys, hipStream_t s);
+                               uint64_t* keys, uint32_t* fhist, hipStream_t s);
 // out[v][r] = record of (view v, Gaussian sorted[v][r]) for rank_lo[v] <= r < rank_hi[v] (rank_lo nullptr: 0),
-// from the blocks, with the arithmetic of launch_project
+// from the blocks, with the arithmetic of launch_project; max_ranks bounds rank_hi - rank_lo (sizes the grid)
 hipError_t launch_project_ranks(const float4* blocks, const double* cams, const ProjConst& pc,
                                 const uint32_t* sorted, const uint32_t* rank_lo, const uint32_t* rank_hi,
-                                float4* out, hipStream_t s);
+                                int64_t max_ranks, float4* out, hipStream_t s);
 hipError_t launch_scene_transpose(const float* means, const float* log_scales, const float* quats,
                                   const float* logits, const float* sh, int64_t n, int64_t n_pad, float* soa,
                                   hipStream_t s);

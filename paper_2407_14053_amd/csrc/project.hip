@@ -182,7 +182,7 @@ template <int DEG, bool RECORDS>
 __global__ __launch_bounds__(256, 4) void project_kernel(const float* __restrict__ soa, const double* __restrict__ cams,
                                                       ProjConst pc, float4* __restrict__ rec,
                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                      double* __restrict__ depth_out) {
+                                                      double* __restrict__ depth_out, uint32_t* __restrict__ fhist) {
   constexpr int NB = (DEG + 1) * (DEG + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < pc.G;
@@ -191,6 +191,7 @@ __global__ __launch_bounds__(256, 4) void project_kernel(const float* __restrict
   float shc[NB * 3];
   gaussian_terms<DEG>(soa, pc.n_pad, ii, pc, g, shc);
   if (!RECORDS && live) store_block<NB * 3>(rec + i * kGaussBlockF4, g, shc);
+  const bool sampled = fhist && (i % kFrontSamplePeriod) < kFrontSampleRun;
   for (int v = 0; v < pc.N; ++v) {
     const double* cam = cams + v * kCamDoubles;
     float r[12] = {};
@@ -201,6 +202,8 @@ __global__ __launch_bounds__(256, 4) void project_kernel(const float* __restrict
     const int64_t o = (int64_t)v * pc.G + i;
     if (live) {
       keys[o] = vis ? key : kDepthCulled;
+      if (sampled && vis)
+        atomicAdd(&fhist[((int64_t)v << kFrontBits) + (uint32_t)(key >> (kDepthKeyBits - kFrontBits))], 1u);
       if (vals) vals[o] = (uint32_t)i;
       if (RECORDS) {
         float4* dst = rec + o * kRecF4;
@@ -271,30 +274,31 @@ hipError_t launch_project(const float* soa, const double* cams, const ProjConst&
                           uint32_t* vals, double* depth_out, hipStream_t s) {
   const dim3 grid((unsigned)((pc.G + 255) / 256));
   switch (pc.sh_degree) {
-    case 0: hipLaunchKernelGGL((project_kernel<0, true>), grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out); break;
-    case 1: hipLaunchKernelGGL((project_kernel<1, true>), grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out); break;
-    case 2: hipLaunchKernelGGL((project_kernel<2, true>), grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out); break;
-    default: hipLaunchKernelGGL((project_kernel<3, true>), grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out); break;
+    case 0: hipLaunchKernelGGL((project_kernel<0, true>), grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, nullptr); break;
+    case 1: hipLaunchKernelGGL((project_kernel<1, true>), grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, nullptr); break;
+    case 2: hipLaunchKernelGGL((project_kernel<2, true>), grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, nullptr); break;
+    default: hipLaunchKernelGGL((project_kernel<3, true>), grid, dim3(256), 0, s, soa, cams, pc, rec, keys, vals, depth_out, nullptr); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_project_keys(const float* soa, const double* cams, const ProjConst& pc, float4* blocks,
-                               uint64_t* keys, hipStream_t s) {
+                               uint64_t* keys, uint32_t* fhist, hipStream_t s) {
   const dim3 grid((unsigned)((pc.G + 255) / 256));
   switch (pc.sh_degree) {
-    case 0: hipLaunchKernelGGL((project_kernel<0, false>), grid, dim3(256), 0, s, soa, cams, pc, blocks, keys, nullptr, nullptr); break;
-    case 1: hipLaunchKernelGGL((project_kernel<1, false>), grid, dim3(256), 0, s, soa, cams, pc, blocks, keys, nullptr, nullptr); break;
-    case 2: hipLaunchKernelGGL((project_kernel<2, false>), grid, dim3(256), 0, s, soa, cams, pc, blocks, keys, nullptr, nullptr); break;
-    default: hipLaunchKernelGGL((project_kernel<3, false>), grid, dim3(256), 0, s, soa, cams, pc, blocks, keys, nullptr, nullptr); break;
+    case 0: hipLaunchKernelGGL((project_kernel<0, false>), grid, dim3(256), 0, s, soa, cams, pc, blocks, keys, nullptr, nullptr, fhist); break;
+    case 1: hipLaunchKernelGGL((project_kernel<1, false>), grid, dim3(256), 0, s, soa, cams, pc, blocks, keys, nullptr, nullptr, fhist); break;
+    case 2: hipLaunchKernelGGL((project_kernel<2, false>), grid, dim3(256), 0, s, soa, cams, pc, blocks, keys, nullptr, nullptr, fhist); break;
+    default: hipLaunchKernelGGL((project_kernel<3, false>), grid, dim3(256), 0, s, soa, cams, pc, blocks, keys, nullptr, nullptr, fhist); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_project_ranks(const float4* blocks, const double* cams, const ProjConst& pc,
                                 const uint32_t* sorted, const uint32_t* rank_lo, const uint32_t* rank_hi,
-                                float4* out, hipStream_t s) {
-  const dim3 grid((unsigned)std::min<int64_t>((pc.G + 255) / 256, 256), (unsigned)pc.N);
+                                int64_t max_ranks, float4* out, hipStream_t s) {
+  const int64_t m = std::max<int64_t>(1, std::min<int64_t>(max_ranks, pc.G));
+  const dim3 grid((unsigned)std::min<int64_t>((m + 255) / 256, 256), (unsigned)pc.N);
   switch (pc.sh_degree) {
     case 0: hipLaunchKernelGGL(project_ranks_kernel<0>, grid, dim3(256), 0, s, blocks, cams, pc, sorted, rank_lo, rank_hi, out); break;
     case 1: hipLaunchKernelGGL(project_ranks_kernel<1>, grid, dim3(256), 0, s, blocks, cams, pc, sorted, rank_lo, rank_hi, out); break;

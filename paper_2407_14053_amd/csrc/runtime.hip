@@ -550,7 +550,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   pc.key_e0 = depth_key_e0(o.z_near);
   mk = C->begin(DL_STAGE_PROJECT, s);
   HIP_TRY(launch_project_keys(S->soa.as<float>(), C->cams.as<double>(), pc, C->rec.as<float4>(),
-                              C->k64[0].as<uint64_t>(), s));
+                              C->k64[0].as<uint64_t>(), C->fhist.as<uint32_t>(), s));
   C->end(mk, s);
   hipError_t e;
   // Depth order.  The first chunk is each view's front (the nearest ~1/32 of its visible Gaussians, chosen on a
@@ -567,8 +567,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   uint32_t* rank_hi = rhi + N;
   uint32_t* dlayout = rank_hi + N;  // 2N + 1
   uint64_t* thr = C->thr.as<uint64_t>();
-  HIP_TRY(launch_front_select(C->k64[0].as<uint64_t>(), G, N, kDepthKeyBits, kDepthCulled, kChunkBounds[1], kChunkDen,
-                              C->fhist.as<uint32_t>(), thr, s));
+  HIP_TRY(launch_front_select(N, kDepthKeyBits, kChunkBounds[1], kChunkDen, C->fhist.as<uint32_t>(), thr, s));
   bool fl = false;
   const bool lds_front = front_sort_fits(G, N);
   if (lds_front) {
@@ -588,7 +587,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   }
   const uint32_t* sorted = fl ? C->v32[0].as<uint32_t>() : C->v32[1].as<uint32_t>();
   HIP_TRY(launch_project_ranks(C->rec.as<float4>(), C->cams.as<double>(), pc, sorted, nullptr, rank_hi,
-                               C->srec.as<float4>(), s));
+                               lds_front ? kFrontSortCap : G, C->srec.as<float4>(), s));
   // the first chunk's end per view (the table form caps it) and the table layout
   const uint32_t fcap = table_fcap(N, G, tl.T);
   const int64_t tab_n = table_entries(N, G, tl.T);
@@ -739,7 +738,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                                          C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), dlayout, s, &e);
       if (e != hipSuccess) return fail(DL_EHIP, std::string("depth sort: ") + hipGetErrorString(e));
       if (fl2 != fl) return fail(DL_EHIP, "depth sorts ended in different buffers");
-      HIP_TRY(launch_project_ranks(C->rec.as<float4>(), C->cams.as<double>(), pc, sorted, front, rank_hi,
+      HIP_TRY(launch_project_ranks(C->rec.as<float4>(), C->cams.as<double>(), pc, sorted, front, rank_hi, G,
                                    C->srec.as<float4>(), s));
       C->end(mk, s);
     }

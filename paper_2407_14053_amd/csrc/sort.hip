@@ -446,32 +446,10 @@ __global__ __launch_bounds__(kThreads) void chunk_setup_kernel(const uint32_t* _
 }
 
 // ---- the front of each view's depth order ----
-// A sample of each view's visible keys (runs of 64 items, one in every 16) binned on their top kFrontBits bits;
-// one workgroup's counts are added to the view's global histogram bin by bin (only the bins it saw).  The
-// threshold only steers how much goes into the first chunk; the exact front sizes come from the split pass.
-constexpr int kFrontBits = 12;
+// The projection counts a sample of each view's visible keys (Gaussians i with i mod kFrontSamplePeriod <
+// kFrontSampleRun) on their top kFrontBits bits.  The threshold only steers how much goes into the first chunk;
+// the exact front sizes come from the gather (or split) pass.
 constexpr int kFrontBins = 1 << kFrontBits;
-
-__global__ __launch_bounds__(kThreads) void front_hist_kernel(const uint64_t* __restrict__ keys, int64_t G,
-                                                                int key_bits, uint64_t culled,
-                                                                uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kFrontBins];
-  for (int b = threadIdx.x; b < kFrontBins; b += kThreads) h[b] = 0;
-  __syncthreads();
-  const int v = blockIdx.y;
-  const uint64_t* k = keys + (int64_t)v * G;
-  // sampled runs: items [1024 j, 1024 j + 64) for j = blockIdx.x, blockIdx.x + gridDim.x, ...
-  for (int64_t j = blockIdx.x; j * 1024 < G; j += gridDim.x) {
-    const int64_t i = j * 1024 + threadIdx.x;
-    if (threadIdx.x < 64 && i < G) {
-      const uint64_t key = k[i];
-      if (key != culled) atomicAdd(&h[(uint32_t)(key >> (key_bits - kFrontBits))], 1u);
-    }
-  }
-  __syncthreads();
-  for (int b = threadIdx.x; b < kFrontBins; b += kThreads)
-    if (h[b]) atomicAdd(&hist[(int64_t)v * kFrontBins + b], h[b]);
-}
 
 // Per view (one workgroup each): the smallest bin b whose cumulative sample count reaches ceil(n_s num / den)
 // of the n_s sampled keys; the front is every key below thr = (b + 1) << (key_bits - kFrontBits) (0: none).
@@ -724,6 +702,7 @@ constexpr int kFsThreads = 1024;
 constexpr int kFsWaves = kFsThreads / 64;
 constexpr int kFsSlots = 12;
 constexpr int kFsCap = kFsThreads * kFsSlots;  // 12288 items
+static_assert(kFsCap == kFrontSortCap, "the declared front capacity");
 constexpr int kFsBits = 9;
 constexpr int kFsBins = 1 << kFsBits;
 constexpr int kFsCutBins = 4096;  // the top 12 bits of the 36-bit key
@@ -762,11 +741,20 @@ __device__ inline uint32_t fs_block_scan(uint32_t x, uint32_t* wsum, uint32_t* t
   return base + inc - x;
 }
 
-// Item i of run k of the view (base = v G): the gather pass left the run's fronts at the run's start.
+// First item of run k of a view (relative to the view's first item): the gather pass left the run's fronts there.
 __device__ inline int64_t fs_run_start(int64_t G, int wps, int k) {
   int64_t lo, hi;
   split_range(G, wps, k, lo, hi);
   return lo;
+}
+
+// The run holding item i of the front, given the runs' exclusive offsets off[0 .. wps): the last run whose offset
+// is at most i (empty runs share their successor's offset and are passed over).  Fixed step count.
+__device__ inline int fs_find_run(const uint32_t* off, int wps, uint32_t i) {
+  int k = 0;
+  for (int step = 1 << (31 - __clz(wps)); step > 0; step >>= 1)
+    if (k + step < wps && off[k + step] <= i) k += step;
+  return k;
 }
 
 // A front of f > kFsCap items (runs of cf[k] items): the largest bin `cut` of the top 12 key bits such that the
@@ -879,20 +867,13 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* 
   uint32_t f = 0, nv = 0;
   uint32_t run = fs_block_scan(mine, sm.wsum, &f);
   fs_block_scan(vis, sm.wsum, &nv);
-  if (f <= (uint32_t)kFsCap) {
+  const bool cut = f > (uint32_t)kFsCap;
+  if (!cut) {
 #pragma unroll
     for (int q = 0; q < kFsRunsPerThread; ++q) {
       const int k = t * kFsRunsPerThread + q;
       if (k < wps) sm.cnt[k] = run;
       run += e[q];
-    }
-    __syncthreads();
-    // wavefront w collects runs w, w + 16, ...
-    for (int k = w; k < wps; k += kFsWaves) {
-      const int64_t r0 = base + fs_run_start(G, wps, k);
-      const uint32_t c = cf[k], o = sm.cnt[k];
-      for (uint32_t i = lane; i < c; i += 64)
-        sm.items[o + i] = (keys[r0 + i] << 24) | (unsigned long long)vals[r0 + i];
     }
     __syncthreads();
   } else {
@@ -902,12 +883,23 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* 
   const int nslot = (int)(R / 64);                             // <= kFsSlots
   unsigned long long it[kFsSlots];
   uint32_t rank[kFsSlots];
+  // each lane finds its items' runs and loads them, all loads in flight together (a cut front is in LDS)
 #pragma unroll
   for (int j = 0; j < kFsSlots; ++j) {
     const uint32_t i = w * R + j * 64 + lane;
-    it[j] = (j < nslot && i < f) ? sm.items[i] : 0ull;
+    it[j] = 0ull;
     rank[j] = 0;
+    if (j < nslot && i < f) {
+      if (cut) {
+        it[j] = sm.items[i];
+      } else {
+        const int k = fs_find_run(sm.cnt, wps, i);
+        const int64_t r = base + fs_run_start(G, wps, k) + (i - sm.cnt[k]);
+        it[j] = (keys[r] << 24) | (unsigned long long)vals[r];
+      }
+    }
   }
+  __syncthreads();  // the run offsets are read before the first pass clears the counts
   const uint64_t lt = (1ull << lane) - 1ull;
   for (int p = 0; p < 4; ++p) {
     const int sh = 24 + kFsBits * p;
@@ -1168,11 +1160,8 @@ bool depth_ranges_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, i
 
 int depth_sort_blocks(int64_t seg_len, int n_seg) { return blocks_per_seg(seg_len, n_seg); }
 
-hipError_t launch_front_select(const uint64_t* keys, int64_t G, int N, int key_bits, uint64_t culled, int64_t num,
-                               int64_t den, uint32_t* hist, uint64_t* thr, hipStream_t s) {
-  const unsigned per_view = (unsigned)std::max<int64_t>(1, std::min<int64_t>(32, (G + 16383) / 16384));
-  hipLaunchKernelGGL(front_hist_kernel, dim3(per_view, (unsigned)N), dim3(kThreads), 0, s, keys, G, key_bits, culled,
-                     hist);
+hipError_t launch_front_select(int N, int key_bits, int64_t num, int64_t den, const uint32_t* hist, uint64_t* thr,
+                               hipStream_t s) {
   hipLaunchKernelGGL(front_select_kernel, dim3((unsigned)N), dim3(kThreads), 0, s, hist, key_bits, num, den, thr);
   return hipGetLastError();
 }
