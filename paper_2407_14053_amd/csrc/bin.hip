@@ -372,12 +372,20 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
     }
     __syncthreads();  // the counters are complete; the wavefront staging is rewritten by the next group
     if (TABLE && EMIT && staged) {
-      // copy the runs out: tile t's run is [end of tile t - 1's, the last wavefront's counter of tile t)
+      // copy the runs out: tile t's run is [end of tile t - 1's, the last wavefront's counter of tile t).  Sixteen
+      // lanes copy one run, consecutive lanes to consecutive slots, so that the list lines are written in pieces
+      // of up to 64 bytes, not word by word.
       const uint32_t rank0 = (uint32_t)(lo + grp * 256);
-      for (int tt = threadIdx.x; tt < T; tt += 256) {
-        const uint32_t a = tt ? tc[4 * (tt - 1) + 3] : 0u, b = tc[4 * tt + 3];
-        const uint32_t p0 = ppos[tt];
-        for (uint32_t k = a; k < b; ++k)
+      const int sub = lane >> 4, sl = lane & 15;
+      for (int tb = 4 * w; tb < T; tb += 16) {
+        const int tt = tb + sub;
+        uint32_t a = 0u, b = 0u, p0 = 0u;
+        if (tt < T) {
+          a = tt ? tc[4 * (tt - 1) + 3] : 0u;
+          b = tc[4 * tt + 3];
+          p0 = ppos[tt];
+        }
+        for (uint32_t k = a + (uint32_t)sl; k < b; k += 16u)
           if (p0 + (k - a) < ch.cap) vals[p0 + (k - a)] = rank0 + stage[k];
       }
       __syncthreads();

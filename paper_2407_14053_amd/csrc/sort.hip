@@ -741,33 +741,27 @@ __device__ inline uint32_t fs_block_scan(uint32_t x, uint32_t* wsum, uint32_t* t
   return base + inc - x;
 }
 
-// First item of run k of a view (relative to the view's first item): the gather pass left the run's fronts there.
-__device__ inline int64_t fs_run_start(int64_t G, int wps, int k) {
+// The runs of a view: run k starts at item min(k per, G) (as split_range has it); the gather pass left the run's
+// fronts there.
+__device__ inline int64_t fs_run_len(int64_t G, int wps) {
   int64_t lo, hi;
-  split_range(G, wps, k, lo, hi);
-  return lo;
+  split_range(G, wps, 1, lo, hi);
+  return lo;  // min(per, G): either way min(k lo, G) is run k's start
 }
+__device__ inline int64_t fs_run_start(int64_t G, int64_t per, int k) { return min((int64_t)k * per, G); }
 
-// The run holding item i of the front, given the runs' exclusive offsets off[0 .. wps): the last run whose offset
-// is at most i (empty runs share their successor's offset and are passed over).  Fixed step count.
-__device__ inline int fs_find_run(const uint32_t* off, int wps, uint32_t i) {
-  int k = 0;
-  for (int step = 1 << (31 - __clz(wps)); step > 0; step >>= 1)
-    if (k + step < wps && off[k + step] <= i) k += step;
-  return k;
-}
 
 // A front of f > kFsCap items (runs of cf[k] items): the largest bin `cut` of the top 12 key bits such that the
 // items of the bins below it fit; those are written to sm.items in index order and their count returned, and
 // *thr_v becomes cut << 24.
 __device__ uint32_t fs_cut_runs(FrontSortSmem& sm, const uint64_t* keys, const uint32_t* vals, int64_t base,
-                                int64_t G, int wps, const uint32_t* cf, uint64_t* thr_v) {
+                                int64_t G, int wps, int64_t per, const uint32_t* cf, uint64_t* thr_v) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   for (int b = t; b < kFsCutBins; b += kFsThreads) sm.cnt[b] = 0;
   if (t == 0) sm.misc[0] = sm.misc[1] = 0;
   __syncthreads();
   for (int k = w; k < wps; k += kFsWaves) {
-    const int64_t r0 = base + fs_run_start(G, wps, k);
+    const int64_t r0 = base + fs_run_start(G, per, k);
     const uint32_t c = cf[k];
     for (uint32_t i = lane; i < c; i += 64) atomicAdd(&sm.cnt[(uint32_t)(keys[r0 + i] >> 24) & 4095u], 1u);
   }
@@ -798,7 +792,7 @@ __device__ uint32_t fs_cut_runs(FrontSortSmem& sm, const uint64_t* keys, const u
   const uint32_t kept_total = sm.misc[1];
   // kept items per run (the histogram is no longer read), then their offsets in run order
   for (int k = w; k < wps; k += kFsWaves) {
-    const int64_t r0 = base + fs_run_start(G, wps, k);
+    const int64_t r0 = base + fs_run_start(G, per, k);
     const uint32_t c = cf[k];
     uint32_t n = 0;
     for (uint32_t i0 = 0; i0 < c; i0 += 64) {
@@ -825,7 +819,7 @@ __device__ uint32_t fs_cut_runs(FrontSortSmem& sm, const uint64_t* keys, const u
   __syncthreads();
   const uint64_t lt = (1ull << lane) - 1ull;
   for (int k = w; k < wps; k += kFsWaves) {
-    const int64_t r0 = base + fs_run_start(G, wps, k);
+    const int64_t r0 = base + fs_run_start(G, per, k);
     const uint32_t c = cf[k];
     uint32_t o = sm.cnt[k];
     for (uint32_t i0 = 0; i0 < c; i0 += 64) {
@@ -853,6 +847,7 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* 
   const int v = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t base = (int64_t)v * G;
+  const int64_t per = fs_run_len(G, wps);
   const uint32_t* cf = cnt + (int64_t)v * 2 * wps;  // fronts per run
   const uint32_t* cv = cf + wps;                    // kept items per run
   // the runs' offsets in the front (thread t owns runs t R', ..., t R' + R' - 1), the front and visible counts
@@ -877,24 +872,42 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* 
     }
     __syncthreads();
   } else {
-    f = fs_cut_runs(sm, keys, vals, base, G, wps, cf, thr + v);
+    f = fs_cut_runs(sm, keys, vals, base, G, wps, per, cf, thr + v);
   }
   const uint32_t R = (f + kFsThreads - 1) / kFsThreads * 64;  // items per wavefront, a multiple of 64
   const int nslot = (int)(R / 64);                             // <= kFsSlots
   unsigned long long it[kFsSlots];
   uint32_t rank[kFsSlots];
-  // each lane finds its items' runs and loads them, all loads in flight together (a cut front is in LDS)
 #pragma unroll
   for (int j = 0; j < kFsSlots; ++j) {
-    const uint32_t i = w * R + j * 64 + lane;
     it[j] = 0ull;
     rank[j] = 0;
-    if (j < nslot && i < f) {
-      if (cut) {
-        it[j] = sm.items[i];
-      } else {
-        const int k = fs_find_run(sm.cnt, wps, i);
-        const int64_t r = base + fs_run_start(G, wps, k) + (i - sm.cnt[k]);
+  }
+  if (cut) {
+#pragma unroll
+    for (int j = 0; j < kFsSlots; ++j) {
+      const uint32_t i = w * R + j * 64 + lane;
+      if (j < nslot && i < f) it[j] = sm.items[i];
+    }
+  } else {
+    // each lane finds its items' runs (the last run whose offset is at most the item; empty runs share their
+    // successor's offset), the searches of all slots in step, then loads them, all loads in flight together
+    int k[kFsSlots];
+#pragma unroll
+    for (int j = 0; j < kFsSlots; ++j) k[j] = 0;
+    for (int step = 1 << (31 - __clz(wps)); step > 0; step >>= 1) {
+#pragma unroll
+      for (int j = 0; j < kFsSlots; ++j) {
+        const uint32_t i = w * R + j * 64 + lane;
+        const int kk = min(k[j] + step, wps - 1);
+        k[j] = (k[j] + step < wps && sm.cnt[kk] <= i) ? k[j] + step : k[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kFsSlots; ++j) {
+      const uint32_t i = w * R + j * 64 + lane;
+      if (j < nslot && i < f) {
+        const int64_t r = base + fs_run_start(G, per, k[j]) + (i - sm.cnt[k[j]]);
         it[j] = (keys[r] << 24) | (unsigned long long)vals[r];
       }
     }
