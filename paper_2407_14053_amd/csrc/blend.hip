@@ -47,7 +47,7 @@ struct BlendSmem {
 // One staged chunk's records [0, n4) for every ray of the lane (n4 a multiple of kUnroll; records past the
 // chunk's end are neutral: their bound on E is +inf).
 template <bool SC, bool CLAMP, int RPT, bool STATS, int NT>
-__device__ __forceinline__ void blend_records(const BlendSmem<NT>& sm, int n4, const bool (&slot)[RPT],
+__device__ __forceinline__ void blend_records(const BlendSmem<NT>& sm, int n4, uint32_t slots,
                                               const float (&px)[RPT], const float (&py)[RPT], float (&sT)[RPT],
                                               float (&C0)[RPT], float (&C1)[RPT], float (&C2)[RPT],
                                               const uint32_t (&ch)[RPT], uint32_t (&nev)[RPT],
@@ -74,35 +74,39 @@ __device__ __forceinline__ void blend_records(const BlendSmem<NT>& sm, int n4, c
       }
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
-        if (j > 0 && !slot[j]) continue;
-        // per-pixel rule and front-to-back update, without branches:
-        //   E = log2(o) - Q = log2(o) - C dy^2 - (A dx + B dy) dx, alpha = min(cap, 2^E)
-        //   T' = T (1 - alpha) as one FMA, the colour weight as T - T' (alpha T up to one rounding of T')
-        // A finished ray keeps T < 0: then T' < 0 < t_min, so an accepted record only "stops" it again, and
-        // the stop writes -|T|, which leaves it unchanged; no liveness test is needed per pair.
-        const float dx = px[j] - A.x, dy = py[j] - A.y;
-        const float E = fmaf(-fmaf(A.w, dy, A.z * dx), dx, fmaf(-(cC * dy), dy, lo));
-        const float ga = __builtin_amdgcn_exp2f(E);
-        const float alpha = CLAMP ? fminf(cap, ga) : ga;
-        const float T = sT[j];
-        const float tn = fmaf(-alpha, T, T);
-        const bool ok = E >= CQ.y;
-        const bool stop = ok && (tn < t_min);
-        const bool take = ok != stop;  // ok and not stop (stop implies ok): one scalar mask operation
-        const float Tt = take ? tn : T;
-        const float w = T - Tt;
-        if (STATS) {
-          nev[j] += T > 0.0f ? 1u : 0u;
-          nbl[j] += take ? 1u : 0u;
+        if (j == 0 || ((slots >> j) & 1u)) {
+          // per-pixel rule and front-to-back update, without branches per lane:
+          //   E = log2(o) - Q = log2(o) - C dy^2 - (A dx + B dy) dx, alpha = min(cap, 2^E)
+          //   T' = T (1 - alpha) as one FMA, the colour weight as T - T' (alpha T up to one rounding of T')
+          // A finished ray keeps T < 0: then T' < 0 < t_min, so an accepted record only "stops" it again, and
+          // the stop writes -|T|, which leaves it unchanged; no liveness test is needed per pair.
+          const float dx = px[j] - A.x, dy = py[j] - A.y;
+          const float E = fmaf(-fmaf(A.w, dy, A.z * dx), dx, fmaf(-(cC * dy), dy, lo));
+          const bool ok = E >= CQ.y;
+          const float T = sT[j];
+          if (STATS) nev[j] += T > 0.0f ? 1u : 0u;
+          // a record that no lane of the wavefront accepts changes nothing (T' = T, weight 0): the rest is
+          // skipped by a scalar branch on the compare's lane mask (about a third of the (record, 64-ray slot)
+          // pairs at 3840x2160, N = 45)
+          if (__ballot(ok) != 0ull) {
+            const float ga = __builtin_amdgcn_exp2f(E);
+            const float alpha = CLAMP ? fminf(cap, ga) : ga;
+            const float tn = fmaf(-alpha, T, T);
+            const bool stop = ok && (tn < t_min);
+            const bool take = ok != stop;  // ok and not stop (stop implies ok): one scalar mask operation
+            const float Tt = take ? tn : T;
+            const float w = T - Tt;
+            if (STATS) nbl[j] += take ? 1u : 0u;
+            if (SC) {
+              C0[j] = fmaf(w, colj[j][u], C0[j]);
+            } else {
+              C0[j] = fmaf(w, cr, C0[j]);
+              C1[j] = fmaf(w, cg, C1[j]);
+              C2[j] = fmaf(w, cb, C2[j]);
+            }
+            sT[j] = stop ? -fabsf(T) : Tt;
+          }
         }
-        if (SC) {
-          C0[j] = fmaf(w, colj[j][u], C0[j]);
-        } else {
-          C0[j] = fmaf(w, cr, C0[j]);
-          C1[j] = fmaf(w, cg, C1[j]);
-          C2[j] = fmaf(w, cb, C2[j]);
-        }
-        sT[j] = stop ? -fabsf(T) : Tt;
       }
     }
     // leave the chunk once no ray of the wavefront is live
@@ -235,18 +239,16 @@ __global__ __launch_bounds__(NT, (blend_min_waves<RPT>())) void blend_kernel(con
         sm.rgb[threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     const bool clamp = __syncthreads_or(need_clamp);
-    bool any = false;
-    bool slot[RPT];  // wavefront has a live ray in slot j (slots other than the first are often empty)
+    // bit j: the wavefront has a live ray in slot j (slots other than the first are often empty); wave-uniform
+    uint32_t slots = 0;
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      any |= sT[j] > 0.0f;
-      slot[j] = __ballot(sT[j] > 0.0f) != 0ull;
-    }
-    if (__ballot(any) != 0ull) {
+    for (int j = 0; j < RPT; ++j) slots |= (__ballot(sT[j] > 0.0f) != 0ull ? 1u : 0u) << j;
+    slots = __builtin_amdgcn_readfirstlane(slots);
+    if (slots) {
       if (clamp)
-        blend_records<SC, true, RPT, STATS, NT>(sm, n4, slot, px, py, sT, C0, C1, C2, ch, nev, nbl, t_min);
+        blend_records<SC, true, RPT, STATS, NT>(sm, n4, slots, px, py, sT, C0, C1, C2, ch, nev, nbl, t_min);
       else
-        blend_records<SC, false, RPT, STATS, NT>(sm, n4, slot, px, py, sT, C0, C1, C2, ch, nev, nbl, t_min);
+        blend_records<SC, false, RPT, STATS, NT>(sm, n4, slots, px, py, sT, C0, C1, C2, ch, nev, nbl, t_min);
     }
     bool mine = false;
 #pragma unroll
