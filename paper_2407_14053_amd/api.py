@@ -152,6 +152,19 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+_DEFAULT_OPTS = None
+
+
+def _opts(opts):
+    """opts, or the library's defaults (made once; the library only reads them)."""
+    global _DEFAULT_OPTS
+    if opts is not None:
+        return opts
+    if _DEFAULT_OPTS is None:
+        _DEFAULT_OPTS = default_opts()
+    return _DEFAULT_OPTS
+
+
 def default_opts(**over) -> dl_render_opts:
     o = dl_render_opts()
     load().dl_default_opts(ctypes.byref(o))
@@ -164,6 +177,10 @@ def default_opts(**over) -> dl_render_opts:
 
 
 def make_pose(c2w, converge_dist=None) -> dl_pose:
+    """The C pose of a camera-to-world matrix (converge_dist defaults to the camera's distance from the origin);
+    a dl_pose is returned as it is, so that callers can build poses once."""
+    if isinstance(c2w, dl_pose):
+        return c2w
     c2w = np.asarray(c2w, dtype=np.float64).reshape(4, 4)
     p = dl_pose()
     p.c2w = (ctypes.c_double * 16)(*c2w.ravel().tolist())
@@ -220,8 +237,16 @@ class Context:
         _check(load().dl_set_profiling(self.h, level))
 
     def frame_stats(self) -> dict:
+        return self.stats_dict(self.frame_stats_raw())
+
+    def frame_stats_raw(self) -> "dl_frame_stats":
+        """The last frame's statistics as the C struct (cheap to take inside a timed loop; see stats_dict)."""
         st = dl_frame_stats()
         _check(load().dl_frame_stats_get(self.h, ctypes.byref(st)))
+        return st
+
+    @staticmethod
+    def stats_dict(st) -> dict:
         d = {k: getattr(st, k) for k in ("keys", "visible", "evaluations", "blends", "rays", "batches", "tile_w",
                                          "tile_h", "rays_per_lane", "lanes")}
         d["stage_ms"] = {STAGES[i]: st.stage_ms[i] for i in range(NSTAGES)}
@@ -343,7 +368,7 @@ def project(ctx, scene, display, c2w, converge_dist=None, opts=None, stream=None
     rec = torch.empty((N, G, 12), dtype=torch.float32, device="cuda")
     depth = torch.empty((N, G), dtype=torch.float64, device="cuda")
     pose = make_pose(c2w, converge_dist)
-    o = opts or default_opts()
+    o = _opts(opts)
     _check(load().dl_project(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(rec), _ptr(depth),
                              _stream(stream)))
     return rec, depth
@@ -359,7 +384,7 @@ def project_noalloc(ctx, scene, display, c2w, out, depth, converge_dist=None, op
     if tuple(depth.shape) != (N, G) or depth.dtype != torch.float64 or not depth.is_contiguous():
         raise ValueError("depth must be a contiguous float64 tensor of shape (%d, %d)" % (N, G))
     pose = make_pose(c2w, converge_dist)
-    o = opts or default_opts()
+    o = _opts(opts)
     _check(load().dl_project_noalloc(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(out),
                                      _ptr(depth), _stream(stream)))
     return out, depth
@@ -372,7 +397,7 @@ def render(ctx, scene, display, c2w, converge_dist=None, opts=None, out=None, st
     if out is None:
         out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     pose = make_pose(c2w, converge_dist)
-    o = opts or default_opts()
+    o = _opts(opts)
     _check(load().dl_render(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(out),
                             _stream(stream)))
     return out
@@ -388,7 +413,7 @@ def render_standard(ctx, scene, display, c2w, converge_dist=None, opts=None, out
     if views is None and keep_views:
         views = torch.empty((display.n_views, H, W, 3), dtype=torch.float32, device="cuda")
     pose = make_pose(c2w, converge_dist)
-    o = opts or default_opts()
+    o = _opts(opts)
     _check(load().dl_render_standard(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(out),
                                      _ptr(views) if views is not None else None, _stream(stream)))
     return out, views
@@ -405,7 +430,7 @@ def render_multiview(ctx, scene, display, c2w, view_w, view_h, converge_dist=Non
     if views is None and keep_views:
         views = torch.empty((display.n_views, view_h, view_w, 3), dtype=torch.float32, device="cuda")
     pose = make_pose(c2w, converge_dist)
-    o = opts or default_opts()
+    o = _opts(opts)
     _check(load().dl_render_multiview(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), int(view_w),
                                       int(view_h), _ptr(out), _ptr(views) if views is not None else None,
                                       _stream(stream)))
@@ -419,7 +444,7 @@ class BVH:
     def __init__(self, ctx: Context, scene: Scene, opts=None, stream=None):
         self.ctx = ctx
         h = ctypes.c_void_p()
-        o = opts or default_opts()
+        o = _opts(opts)
         _check(load().dl_bvh_build(ctx.h, scene.h, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
         self.h = h
 
@@ -447,7 +472,7 @@ def render_rayorder(ctx, bvh, display, c2w, heap_cap=128, converge_dist=None, op
     if out is None:
         out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     pose = make_pose(c2w, converge_dist)
-    o = opts or default_opts()
+    o = _opts(opts)
     _check(load().dl_render_rayorder(ctx.h, bvh.h, display.h, ctypes.byref(pose), ctypes.byref(o), int(heap_cap),
                                      _ptr(out), _stream(stream)))
     return out
@@ -464,7 +489,7 @@ def render_backward(ctx, scene, display, c2w, out, grad_out, converge_dist=None,
     out = out.contiguous()
     grad_out = grad_out.to(torch.float32).contiguous()
     pose = make_pose(c2w, converge_dist)
-    o = opts or default_opts()
+    o = _opts(opts)
     _check(load().dl_render_backward(ctx.h, scene.h, display.h, ctypes.byref(pose), ctypes.byref(o), _ptr(out),
                                      _ptr(grad_out), *[_ptr(x) for x in g], _stream(stream)))
     return g
@@ -481,7 +506,7 @@ def interleave(display, views, out=None, stream=None):
 
 def plan_estimate_bytes(scene, display, opts=None, key_capacity: int = 0) -> int:
     """Device bytes a plan would hold (plus its output image) at the given tile-key capacity."""
-    o = opts or default_opts()
+    o = _opts(opts)
     n = int(load().dl_plan_estimate_bytes(scene.h, display.h, ctypes.byref(o), int(key_capacity)))
     if n < 0:
         raise DLError(DL_EINVAL, "cannot estimate a plan for these arguments")
