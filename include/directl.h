@@ -38,7 +38,8 @@ enum {
   DL_ERANGE = -2, /* exact view-map integer arithmetic would overflow */
   DL_ENOMEM = -3, /* device or host allocation failed */
   DL_EHIP = -4,   /* a HIP runtime call failed */
-  DL_ECAP = -5    /* a fixed-capacity plan overflowed (nothing valid was written to the output) */
+  DL_ECAP = -5,   /* a fixed-capacity plan overflowed (nothing valid was written to the output) */
+  DL_ELATER = -6  /* a frame of a first-chunk plan needed a later depth chunk (its image is incomplete) */
 };
 
 typedef struct dl_ctx dl_ctx;
@@ -255,12 +256,22 @@ int dl_render_rayorder(dl_ctx* ctx, const dl_bvh* bvh, const dl_display* display
  * (sticky: the overflowing frame's image, and any later one, is invalid) with *need = the most keys a depth
  * chunk required — render those requests eagerly or with a new plan.  Many frames may be launched back to back
  * and checked once after the last.
+ * Depth chunks (as for dl_render: each view's nearest Gaussians first, the rest only for tiles whose rays are
+ * still live): when the probe frame finished in its first chunk, the plan's graphs
+ * hold that chunk alone, which saves the later chunk's (then empty) launches.  A frame that leaves a tile live
+ * after it is incomplete; dl_plan_check then returns DL_ELATER (sticky, after any DL_ECAP) — the caller renders
+ * that pose eagerly, or calls dl_plan_use_all_chunks and launches it again.  dl_plan_first_chunk_only: 1 for
+ * such a plan, 0 otherwise (DL_EINVAL for NULL).  dl_plan_use_all_chunks recaptures the plan's graphs (the
+ * batched ones too) with every chunk and clears its status; it waits for the plan's last launch; DL_OK at once
+ * for a plan that has every chunk.
  * dl_plan_bytes: device bytes the plan holds.  dl_plan_free waits for the plan's work to finish. */
 int dl_plan_create(dl_ctx* ctx, const dl_scene* scene, const dl_display* display, const dl_render_opts* opts,
                    const dl_pose* probe_pose, int64_t min_key_capacity, float* out_dev, void* stream,
                    dl_plan** out);
 int dl_plan_render(dl_plan* plan, const dl_pose* pose, void* stream);
 int dl_plan_check(const dl_plan* plan, int64_t* need);
+int dl_plan_first_chunk_only(const dl_plan* plan);
+int dl_plan_use_all_chunks(dl_plan* plan, void* stream);
 int64_t dl_plan_bytes(const dl_plan* plan);
 /* Device bytes a plan of (scene, display, opts) would hold with a per-chunk tile-key capacity of key_capacity
  * (a plan sizes its own capacity with its probe frame), for admission decisions before creating one; -1 on a

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdirectl.so")
 
-DL_OK, DL_EINVAL, DL_ERANGE, DL_ENOMEM, DL_EHIP, DL_ECAP = 0, -1, -2, -3, -4, -5
+DL_OK, DL_EINVAL, DL_ERANGE, DL_ENOMEM, DL_EHIP, DL_ECAP, DL_ELATER = 0, -1, -2, -3, -4, -5, -6
 
 
 class DLError(RuntimeError):
@@ -102,6 +102,8 @@ _SIGS = {
                             _P, _P, ctypes.POINTER(_P)]),
     "dl_plan_render": (_I, [_P, ctypes.POINTER(dl_pose), _P]),
     "dl_plan_check": (_I, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "dl_plan_first_chunk_only": (_I, [_P]),
+    "dl_plan_use_all_chunks": (_I, [_P, _P]),
     "dl_plan_bytes": (ctypes.c_int64, [_P]),
     "dl_plan_estimate_bytes": (ctypes.c_int64, [_P, _P, ctypes.POINTER(dl_render_opts), ctypes.c_int64]),
     "dl_plan_free": (None, [_P]),
@@ -534,6 +536,7 @@ class Plan:
                                      int(min_key_capacity), _ptr(self.out), _stream(stream), ctypes.byref(h)))
         self.h = h
         self.batch_max = 1
+        self.needs_all_chunks = False
         self.bytes = int(load().dl_plan_bytes(self.h)) + self.out.numel() * 4
 
     def launch(self, c2w, stream=None, converge_dist=None):
@@ -562,11 +565,25 @@ class Plan:
         return self.outs[:n]
 
     def check(self):
+        """(ok, keys_needed) once the plan's launches have completed.  ok is False when a frame overflowed the
+        key capacity, or when a frame of a first-chunk plan needed a later depth chunk: then `needs_all_chunks`
+        is True, and use_all_chunks() makes the plan render such frames (launch them again)."""
         need = ctypes.c_int64(0)
         rc = load().dl_plan_check(self.h, ctypes.byref(need))
-        if rc not in (DL_OK, DL_ECAP):
+        if rc not in (DL_OK, DL_ECAP, DL_ELATER):
             _check(rc)
+        self.needs_all_chunks = rc == DL_ELATER
         return rc == DL_OK, int(need.value)
+
+    @property
+    def first_chunk_only(self) -> bool:
+        """The plan's graphs hold the first depth chunk only (its probe frame finished in it)."""
+        return load().dl_plan_first_chunk_only(self.h) == 1
+
+    def use_all_chunks(self, stream=None):
+        """Recapture the plan's graphs with every depth chunk (waits for the plan's last launch)."""
+        _check(load().dl_plan_use_all_chunks(self.h, _stream(stream)))
+        self.needs_all_chunks = False
 
     def close(self):
         if getattr(self, "h", None):

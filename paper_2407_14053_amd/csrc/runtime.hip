@@ -155,6 +155,7 @@ struct dl_ctx {
   std::vector<Mark> marks;
   int64_t keys = 0, visible = 0;
   int batches = 0, tile_w = 0, tile_h = 0, rpt = 0, lanes = 0;
+  bool later_ran = false;  // the last eager frame had a live tile after its first depth chunk
   ~dl_ctx() {
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
   }
@@ -467,7 +468,7 @@ FrameSizes frame_sizes(int N, int64_t G, int64_t NT, int64_t nstate, uint32_t ca
       (size_t)(NT + 1) * 4,                           // list starts
       (size_t)NT,                                     // live tiles
       (size_t)std::max<int64_t>(nstate, 1) * 16,      // ray state
-      2 * 8,                                          // key totals
+      3 * 8,                                          // key totals: chunk, largest, later chunk needed
       (size_t)hs * 4,                                 // radix histograms
       (size_t)(scan_partial_count(std::max<int64_t>(hs, ncounts)) + 2) * 4,  // scan partials
       stats ? (size_t)kStatSlots * 3 * 8 : 0,         // work counters
@@ -483,6 +484,9 @@ struct FrameMode {
   bool upload = true;
   bool finish = true;
   bool keep_max = false;  // keep the largest chunk total of earlier frames (a plan's overflow status is sticky)
+  // the first depth chunk only (a plan whose probe frame finished in it): a tile still live after it sets the
+  // third key total, so that the caller learns the frame's image is incomplete
+  bool first_only = false;
 };
 
 // Backward inputs/outputs of a frame (DirectL only).
@@ -692,8 +696,10 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                                    C->state.as<float4>(), out, s));
     }
     if (c + 1 < kChunks)
-      HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), total, s));
+      HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), total,
+                               mode.first_only ? total + 2 : nullptr, s));
     C->end(mk, s);
+    if (mode.first_only) break;
     if (c == 0 && kChunks > 1 && mode.finish) {
       // an eager frame (its caller waits for it anyway) reads the live tiles after the first chunk: when every
       // tile's rays have terminated, every tile has written its pixels and the later chunks would only launch
@@ -714,6 +720,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
       }
       uint64_t nlive = 0;
       for (int v = 0; v < N; ++v) nlive += C->live_host[v];
+      C->later_ran = nlive != 0;
       if (nlive == 0) {
         if (bwd) break;
         C->keys = (int64_t)*keys_host;
@@ -1152,7 +1159,10 @@ struct dl_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t copied = nullptr;                // after the last camera upload: the staging may be rewritten
-  unsigned long long* status_host = nullptr;  // pinned: largest chunk key total of the plan's frames so far
+  hipEvent_t done = nullptr;                  // after the last launch's status copy
+  // pinned: largest chunk key total of the plan's frames so far, and whether one of them needed a later chunk
+  unsigned long long* status_host = nullptr;
+  bool first_only = false;  // the graphs hold the first depth chunk only (the probe frame finished in it)
   // batched launches: graphs of 1..batch_max frames in a row, frame k reading camera set k of batch_cams and
   // writing batch_out[k]; the camera sets of a launch are uploaded together from pinned staging
   int batch_max = 0;
@@ -1165,6 +1175,10 @@ struct dl_plan {
     if (copied) {
       (void)hipEventSynchronize(copied);
       (void)hipEventDestroy(copied);
+    }
+    if (done) {
+      (void)hipEventSynchronize(done);
+      (void)hipEventDestroy(done);
     }
     for (hipGraphExec_t x : batch_exec) (void)hipGraphExecDestroy(x);
     for (hipGraph_t g : batch_graph) (void)hipGraphDestroy(g);
@@ -1192,7 +1206,8 @@ int plan_capture(dl_plan* P, hipStream_t s) {
   m.upload = false;
   m.finish = false;
   m.keep_max = true;
-  HIP_TRY(launch_fill_u64(P->C->dtotal.as<unsigned long long>(), 2, 0ull, s));  // status of the plan's frames
+  m.first_only = P->first_only;
+  HIP_TRY(launch_fill_u64(P->C->dtotal.as<unsigned long long>(), 3, 0ull, s));  // status of the plan's frames
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   int rc = render_frame(P->C, P->S, P->D, nullptr, P->o, P->tl, false, P->L, P->out, s, &need, nullptr, m);
   hipGraph_t g = nullptr;
@@ -1215,6 +1230,7 @@ int plan_capture_batch(dl_plan* P, int n, hipStream_t s, hipGraph_t* graph, hipG
   m.upload = false;
   m.finish = false;
   m.keep_max = true;
+  m.first_only = P->first_only;
   const size_t cam_bytes = (size_t)P->D->desc.n_views * kCamDoubles * 8;
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   int rc = DL_OK;
@@ -1274,7 +1290,7 @@ int dl_plan_create(dl_ctx* ctx, const dl_scene* S, const dl_display* D, const dl
     delete P;
     return fail(DL_EINVAL, "tile too large: more than 4096 rays of one view");
   }
-  if (hipHostMalloc((void**)&P->status_host, 8, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&P->status_host, 16, hipHostMallocDefault) != hipSuccess) {
     delete P;
     return fail(DL_ENOMEM, "plan status word");
   }
@@ -1293,15 +1309,18 @@ int dl_plan_create(dl_ctx* ctx, const dl_scene* S, const dl_display* D, const dl
     delete P;
     return rc;
   }
-  if (hipEventCreateWithFlags(&P->copied, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&P->copied, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess) {
     delete P;
     return fail(DL_EHIP, "plan event");
   }
+  // a probe frame that finished in its first depth chunk gives a plan of that chunk alone
+  P->first_only = kChunks > 1 && !P->C->later_ran;
   if ((rc = plan_capture(P, s))) {
     delete P;
     return rc;
   }
-  *P->status_host = 0;
+  P->status_host[0] = P->status_host[1] = 0;
   *out = P;
   return DL_OK;
 }
@@ -1333,15 +1352,45 @@ int dl_plan_render(dl_plan* P, const dl_pose* pose, void* stream) {
   HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(P->copied, s));
   HIP_TRY(hipGraphLaunch(P->exec, s));
-  HIP_TRY(hipMemcpyAsync(P->status_host, C->dtotal.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(P->status_host, C->dtotal.as<unsigned long long>() + 1, 16, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(P->done, s));
   return DL_OK;
 }
 
 int dl_plan_check(const dl_plan* P, int64_t* need) {
   if (!P) return fail(DL_EINVAL, "NULL plan");
-  const unsigned long long mx = *P->status_host;
+  const unsigned long long mx = P->status_host[0];
   if (need) *need = (int64_t)mx;
   if (mx > P->C->key_cap) return fail(DL_ECAP, "a depth chunk overflowed the plan's key capacity");
+  if (P->status_host[1]) return fail(DL_ELATER, "a frame of a first-chunk plan needed a later depth chunk");
+  return DL_OK;
+}
+
+int dl_plan_first_chunk_only(const dl_plan* P) { return P ? (P->first_only ? 1 : 0) : DL_EINVAL; }
+
+int dl_plan_use_all_chunks(dl_plan* P, void* stream) {
+  if (!P) return fail(DL_EINVAL, "NULL plan");
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(DL_EINVAL, "plans are captured on a created stream, not the null stream");
+  if (!P->first_only) return DL_OK;
+  // the plan's graphs are replaced once its last launch has completed
+  HIP_TRY(hipEventSynchronize(P->done));
+  P->first_only = false;
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  P->exec = nullptr;
+  P->graph = nullptr;
+  int rc = plan_capture(P, s);
+  if (rc) return rc;
+  for (int n = 1; n <= P->batch_max; ++n) {
+    (void)hipGraphExecDestroy(P->batch_exec[n - 1]);
+    (void)hipGraphDestroy(P->batch_graph[n - 1]);
+    P->batch_exec[n - 1] = nullptr;
+    P->batch_graph[n - 1] = nullptr;
+    if ((rc = plan_capture_batch(P, n, s, &P->batch_graph[n - 1], &P->batch_exec[n - 1]))) return rc;
+  }
+  HIP_TRY(hipStreamSynchronize(s));  // the status reset of the capture has run
+  P->status_host[0] = P->status_host[1] = 0;
   return DL_OK;
 }
 
@@ -1386,7 +1435,8 @@ int dl_plan_render_batch(dl_plan* P, const dl_pose* poses, int32_t n, void* stre
   HIP_TRY(hipMemcpyAsync(P->batch_cams.p, P->batch_cams_host, n * cam_doubles * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(P->copied, s));
   HIP_TRY(hipGraphLaunch(P->batch_exec[n - 1], s));
-  HIP_TRY(hipMemcpyAsync(P->status_host, P->C->dtotal.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(P->status_host, P->C->dtotal.as<unsigned long long>() + 1, 16, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(P->done, s));
   return DL_OK;
 }
 

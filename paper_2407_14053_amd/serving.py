@@ -186,6 +186,7 @@ class Server:
         self.plan_bytes = 0
         self.est: dict = {}  # (scene, display) -> bytes of the last plan made for it
         self.min_keys: dict = {}  # (scene, display) -> capacity a previous overflow asked for
+        self.all_chunks: set = set()  # (scene, display) pairs a frame of which needed a later depth chunk
         self.slots = [_Slot(torch) for _ in range(n_slots)]
         free, total = torch.cuda.mem_get_info()
         self.total = total
@@ -289,16 +290,22 @@ class Server:
                 e = self._new_plan(k, s) if copy > 0 else self._get_plan(k, s)[0]
                 if e is None:
                     break
-                for attempt in range(2):
-                    worst_ok = True
+                for attempt in range(3):
+                    worst_ok, later = True, False
                     for c2w in probe_poses:
                         e.plan.launch(c2w, stream=s)
                         s.synchronize()
                         ok, need = e.plan.check()
                         self.min_keys[k] = max(self.min_keys.get(k, 0), need + need * 3 // 10 + 4096)
                         worst_ok &= ok
+                        later |= e.plan.needs_all_chunks
                     if worst_ok:
                         break
+                    if later:
+                        # a probe pose needs a later depth chunk: the pair's plans keep every chunk
+                        self.all_chunks.add(k)
+                        e.plan.use_all_chunks(stream=s)
+                        continue
                     del self.plans[id(e)]
                     self.plan_bytes -= e.bytes
                     e.plan.close()
@@ -314,6 +321,8 @@ class Server:
                         min_key_capacity=self.min_keys.get(key, 0), stream=stream)
         if self.batch_max > 1:
             plan.prepare_batch(self.batch_max, stream=stream)
+        if key in self.all_chunks:
+            plan.use_all_chunks(stream=stream)
         e = _PlanEntry(key, plan)
         self.est[key] = e.bytes
         self.plans[id(e)] = e
@@ -380,6 +389,16 @@ class Server:
                 sl.reqs, sl.entry = [], None
                 # plans made later for this pair get 30% headroom over the largest chunk seen so far
                 self.min_keys[e.key] = max(self.min_keys.get(e.key, 0), need + need * 3 // 10 + 4096)
+                if not ok and e.plan.needs_all_chunks:
+                    # a frame of a first-chunk plan needed a later depth chunk: the plan keeps every chunk from
+                    # now on, and the requests are served again
+                    self.all_chunks.add(e.key)
+                    e.plan.use_all_chunks(stream=sl.stream)
+                    for r in reversed(rs):
+                        replans[r.rid] = replans.get(r.rid, 0) + 1
+                        queue.appendleft(r)
+                    sl.images = []
+                    continue
                 if not ok:
                     # a frame overflowed the plan's tile-key capacity: replace the plan and serve the requests again
                     del self.plans[id(e)]

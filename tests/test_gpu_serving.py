@@ -24,6 +24,20 @@ def _eager(ctx, S, D, c2w):
     return api.render(ctx, S, D, c2w).cpu().numpy()
 
 
+def _launch_checked(plan, launch, stream):
+    """launch() on the plan, wait, check; a first-chunk plan whose frame needed a later depth chunk is switched to
+    every chunk and launched again.  Returns launch()'s result and the (ok, need) status."""
+    out = launch()
+    stream.synchronize()
+    ok, need = plan.check()
+    if not ok and plan.needs_all_chunks:
+        plan.use_all_chunks(stream=stream)
+        out = launch()
+        stream.synchronize()
+        ok, need = plan.check()
+    return out, (ok, need)
+
+
 def test_plan_replays_equal_eager_frames(ctx):
     import torch
     from paper_2407_14053_amd import api
@@ -39,9 +53,7 @@ def test_plan_replays_equal_eager_frames(ctx):
     plan = api.Plan(ctx, S, D, poses[0], stream=stream)
     for rep in range(3):
         for i in (0, 3, 1, 4):
-            out = plan.launch(poses[i], stream=stream)
-            stream.synchronize()
-            ok, need = plan.check()
+            out, (ok, need) = _launch_checked(plan, lambda: plan.launch(poses[i], stream=stream), stream)
             assert ok, need
             got = out.cpu().numpy()
             assert np.array_equal(got, ref[i]), (rep, i, float(np.abs(got - ref[i]).max()))
@@ -62,12 +74,17 @@ def test_plan_back_to_back_launches_on_one_stream(ctx):
     ref = [_eager(ctx, S, D, p) for p in poses]
     stream = torch.cuda.Stream()
     plan = api.Plan(ctx, S, D, poses[0], stream=stream)
-    outs = []
-    with torch.cuda.stream(stream):
-        for p in poses:
-            plan.launch(p, stream=stream)
-            outs.append(plan.out.clone())
-    stream.synchronize()
+
+    def all_poses():
+        outs = []
+        with torch.cuda.stream(stream):
+            for p in poses:
+                plan.launch(p, stream=stream)
+                outs.append(plan.out.clone())
+        return outs
+
+    outs, (ok, _) = _launch_checked(plan, all_poses, stream)
+    assert ok
     for i, o in enumerate(outs):
         assert np.array_equal(o.cpu().numpy(), ref[i]), i
     plan.close()
@@ -101,9 +118,8 @@ def test_plan_overflow_is_reported_and_rebuilt_plan_is_exact(ctx):
     assert not ok and need == keys[1]
     plan.close()
     plan = api.Plan(ctx, S, D, probe, min_key_capacity=need + need // 4, stream=stream)
-    out = plan.launch(req, stream=stream)
-    stream.synchronize()
-    assert plan.check()[0]
+    out, (ok, _) = _launch_checked(plan, lambda: plan.launch(req, stream=stream), stream)
+    assert ok
     assert np.array_equal(out.cpu().numpy(), _eager(ctx, S, D, req))
     plan.close()
 
@@ -122,17 +138,112 @@ def test_plan_batched_launch_equals_eager_frames(ctx):
     plan = api.Plan(ctx, S, D, poses[0], stream=stream)
     plan.prepare_batch(4, stream=stream)
     for chosen in ([1, 5, 9], [2, 3, 4, 11], [7]):
-        outs = plan.launch_batch([poses[k] for k in chosen], stream=stream)
-        stream.synchronize()
-        assert plan.check()[0]
+        outs, (ok, _) = _launch_checked(plan, lambda: plan.launch_batch([poses[k] for k in chosen], stream=stream),
+                                        stream)
+        assert ok
         for k, img in zip(chosen, outs):
             ref = api.render(ctx, S, D, poses[k]).cpu().numpy()
             assert np.array_equal(img.cpu().numpy(), ref), k
-        single = plan.launch(poses[6], stream=stream)
-        stream.synchronize()
+        single, (ok, _) = _launch_checked(plan, lambda: plan.launch(poses[6], stream=stream), stream)
+        assert ok
         assert np.array_equal(single.cpu().numpy(), api.render(ctx, S, D, poses[6]).cpu().numpy())
     with pytest.raises(api.DLError):
         plan.launch_batch(poses[:5], stream=stream)          # more than prepared
+    plan.close()
+
+
+def _wall_scene(n_cloud=12_000, seed=5):
+    """Three opaque layers of large Gaussians on planes z = -1.3, -1.4, -1.5 (first in index order) in front of a
+    faint cloud in [-1, 1]^3: seen from z = -3 the wall is each view's nearest 1/32 and ends every ray in the first
+    depth chunk; seen from z = +3 the faint cloud comes first and rays survive it."""
+    rng = np.random.default_rng(seed)
+    g = np.linspace(-3.0, 3.0, 10)
+    wx, wy = np.meshgrid(g, g)
+    walls = [np.stack([wx.ravel(), wy.ravel(), np.full(wx.size, z)], 1) for z in (-1.3, -1.4, -1.5)]
+    wall = np.concatenate(walls).astype(np.float32)
+    cloud = rng.uniform(-1.0, 1.0, (n_cloud, 3)).astype(np.float32)
+    means = np.concatenate([wall, cloud])
+    n = means.shape[0]
+    log_scales = np.full((n, 3), np.log(0.05), np.float32)
+    log_scales[: len(wall)] = np.log(0.6)
+    quats = np.tile(np.array([1.0, 0.0, 0.0, 0.0], np.float32), (n, 1))
+    logits = np.full(n, -4.0, np.float32)
+    logits[: len(wall)] = 7.0
+    sh = np.zeros((n, 16, 3), np.float32)
+    sh[:, 0, :] = rng.uniform(-1.0, 1.0, (n, 3)).astype(np.float32)
+    return synth.Scene(means, log_scales, quats, logits, sh)
+
+
+def test_first_chunk_plan_reports_a_frame_that_needs_a_later_chunk(ctx):
+    """A plan probed where every ray ends in the first depth chunk holds that chunk alone; a pose whose rays
+    survive it is reported (DL_ELATER, sticky), and after use_all_chunks the same launches equal eager frames."""
+    import torch
+    from paper_2407_14053_amd import api
+    log("first-chunk plan")
+    d = synth.make_named_display("tiny")
+    S, D = api.Scene(ctx, _wall_scene().arrays()), api.Display(ctx, d)
+    near = synth.look_at_c2w((0.0, 0.0, -3.0))
+    far = synth.look_at_c2w((0.0, 0.0, 3.0))
+    probe = api.Context(0)
+    probe.set_profiling(True)
+    later, keys = [], []
+    for p in (near, far):
+        _eager(probe, S, D, p)
+        st = probe.frame_stats()
+        later.append(len(st["chunk_ms"]) > 1 and bool(st["chunk_ms"][1]))
+        keys.append(st["keys"])
+    probe.close()
+    log("  later depth chunk ran: near %s, far %s" % tuple(later))
+    assert not later[0] and later[1]
+    ref = {k: _eager(ctx, S, D, p) for k, p in (("near", near), ("far", far))}
+    stream = torch.cuda.Stream()
+
+    def images(outs):
+        stream.synchronize()
+        return [o.cpu().numpy() for o in outs]
+
+    # single launches
+    plan = api.Plan(ctx, S, D, near, stream=stream)
+    assert plan.first_chunk_only
+    got = images([plan.launch(near, stream=stream)])
+    assert plan.check()[0] and np.array_equal(got[0], ref["near"])
+    plan.launch(far, stream=stream)
+    stream.synchronize()
+    ok, _ = plan.check()
+    assert not ok and plan.needs_all_chunks
+    plan.launch(near, stream=stream)  # the status stays set
+    stream.synchronize()
+    assert not plan.check()[0] and plan.needs_all_chunks
+    plan.use_all_chunks(stream=stream)
+    assert not plan.first_chunk_only
+    plan.launch(far, stream=stream)
+    stream.synchronize()
+    ok, need = plan.check()
+    if not ok:
+        # the back chunk of the far pose outgrows the capacity the near probe sized: a new plan with room for it
+        assert not plan.needs_all_chunks and need > 0
+        plan.close()
+        plan = api.Plan(ctx, S, D, near, min_key_capacity=need + need // 4, stream=stream)
+        plan.use_all_chunks(stream=stream)
+    with torch.cuda.stream(stream):  # the copies run after each launch on the plan's stream
+        got = images([plan.launch(far, stream=stream).clone(), plan.launch(near, stream=stream).clone()])
+    assert plan.check()[0]
+    assert np.array_equal(got[0], ref["far"]) and np.array_equal(got[1], ref["near"])
+    plan.close()
+    # batched launches (capacity for the far pose from the start)
+    plan = api.Plan(ctx, S, D, near, min_key_capacity=max(keys) * 13 // 10 + 4096, stream=stream)
+    plan.prepare_batch(3, stream=stream)
+    assert plan.first_chunk_only
+    got = images(plan.launch_batch([near, near], stream=stream))
+    assert plan.check()[0] and all(np.array_equal(g, ref["near"]) for g in got)
+    plan.launch_batch([near, far, near], stream=stream)
+    stream.synchronize()
+    assert not plan.check()[0] and plan.needs_all_chunks
+    plan.use_all_chunks(stream=stream)
+    got = images(plan.launch_batch([near, far, near], stream=stream))
+    assert plan.check()[0]
+    for g, w in zip(got, ("near", "far", "near")):
+        assert np.array_equal(g, ref[w]), w
     plan.close()
 
 
