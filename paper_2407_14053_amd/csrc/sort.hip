@@ -706,15 +706,21 @@ static_assert(kFsCap == kFrontSortCap, "the declared front capacity");
 constexpr int kFsBits = 9;
 constexpr int kFsBins = 1 << kFsBits;
 constexpr int kFsCutBins = 4096;  // the top 12 bits of the 36-bit key
+// The pass counters of (digit d, wavefront w) live at d kFsStride + w: rows padded to an odd stride, so that the
+// leaders of different digits and the scan's threads reach different LDS banks (a stride of 16 put every digit
+// on two banks).
+constexpr int kFsStride = kFsWaves + 1;
+constexpr int kFsCntSize = kFsBins * kFsStride;
 constexpr int kFsMaxRuns = kFsBins * kFsWaves;  // gather runs per view (their offsets live in the count array)
 constexpr int kFsRunsPerThread = kFsMaxRuns / kFsThreads;
 static_assert(kFsBins * kFsWaves >= kFsCutBins, "the cut histogram shares the count array");
+static_assert(kFsWaves == 16 && kFsThreads * 8 == kFsBins * kFsWaves, "eight (digit, wavefront) counters per thread");
 static_assert(kFsCutBins == 4 * kFsThreads, "four cut bins per thread");
 static_assert(kDepthKeyBits == 4 * kFsBits, "four passes cover the depth key");
 
 struct FrontSortSmem {
   unsigned long long items[kFsCap];
-  uint32_t cnt[kFsBins * kFsWaves];
+  uint32_t cnt[kFsCntSize];
   uint32_t wsum[kFsWaves];
   uint32_t misc[2];
 };
@@ -916,7 +922,7 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* 
   const uint64_t lt = (1ull << lane) - 1ull;
   for (int p = 0; p < 4; ++p) {
     const int sh = 24 + kFsBits * p;
-    for (int b = t; b < kFsBins * kFsWaves; b += kFsThreads) sm.cnt[b] = 0;
+    for (int b = t; b < kFsCntSize; b += kFsThreads) sm.cnt[b] = 0;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kFsSlots; ++j) {
@@ -932,25 +938,26 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* 
       const int leader = valid ? __ffsll((long long)m) - 1 : lane;
       uint32_t before = 0;
       if (valid && lane == leader) {
-        before = sm.cnt[d * kFsWaves + w];
-        sm.cnt[d * kFsWaves + w] = before + (uint32_t)__popcll(m);
+        before = sm.cnt[d * kFsStride + w];
+        sm.cnt[d * kFsStride + w] = before + (uint32_t)__popcll(m);
       }
       before = __shfl(before, leader, 64);
       rank[j] = before + (uint32_t)__popcll(m & lt);
       wave_lds_fence();
     }
     __syncthreads();
-    // exclusive scan of the counts in (digit, wavefront) order: thread t owns entries 8t .. 8t + 7
+    // exclusive scan of the counts in (digit, wavefront) order: thread t owns the 8 entries 8t .. 8t + 7 of that
+    // order, which are digit t / 2's counters of wavefronts 8 (t % 2) .. 8 (t % 2) + 7
     uint32_t e[8], loc = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      e[k] = sm.cnt[8 * t + k];
+      e[k] = sm.cnt[(t >> 1) * kFsStride + 8 * (t & 1) + k];  // digit t / 2, wavefronts 8 (t % 2) + k
       loc += e[k];
     }
     uint32_t run = fs_block_scan(loc, sm.wsum);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      sm.cnt[8 * t + k] = run;
+      sm.cnt[(t >> 1) * kFsStride + 8 * (t & 1) + k] = run;
       run += e[k];
     }
     __syncthreads();
@@ -959,7 +966,7 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* 
       if (j >= nslot) break;
       if (w * R + j * 64 + lane < f) {
         const uint32_t d = (uint32_t)(it[j] >> sh) & (kFsBins - 1);
-        sm.items[sm.cnt[d * kFsWaves + w] + rank[j]] = it[j];
+        sm.items[sm.cnt[d * kFsStride + w] + rank[j]] = it[j];
       }
     }
     __syncthreads();
