@@ -70,10 +70,11 @@ __device__ inline uint32_t wave_incl_scan_u32(uint32_t x, int lane) {
 }
 
 // Per-wavefront staging of its 64 Gaussians.
+template <int GPW>
 struct WaveBin {
-  float u[64], v[64], A[64], B[64], C[64], qlim[64], hA[64], hC[64], rw[64];
-  int tx0[64], ty0[64], wr[64];
-  uint32_t pre[64], nt[64];
+  float u[GPW], v[GPW], A[GPW], B[GPW], C[GPW], qlim[GPW], hA[GPW], hC[GPW], rw[GPW];
+  int tx0[GPW], ty0[GPW], wr[GPW];
+  uint32_t pre[GPW], nt[GPW];
   int mark[128];  // per pair of a two-step window: the lane of the Gaussian whose pairs start there, or -1
 };
 
@@ -124,18 +125,23 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
                                                   const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys,
                                                   uint32_t* __restrict__ vals, const uint32_t* __restrict__ tab_base,
                                                   const uint32_t* __restrict__ grand) {
-  __shared__ WaveBin wb[4];
+  // Gaussians per wavefront: the table form takes 32 (lanes 32-63 own none; the pair walk still runs 64 pairs a
+  // step), so that the first chunk's few hundred Gaussians per view spread over twice the wavefronts and each
+  // wavefront's serial walk is half as long
+  constexpr int GPW = TABLE ? kTableWaveRanks : 64;
+  constexpr int GPG = 4 * GPW;  // per workgroup (a group)
+  __shared__ WaveBin<GPW> wb[4];
   __shared__ unsigned long long part[4];
   // TABLE (dynamic LDS, sized by the launch): the tile counters, [T] x 16 bytes; for EMIT also each tile's
   // first slot of the workgroup's run in the lists, [T] x 4 bytes, and the workgroup's hits staged in list order
-  // as ranks relative to its first rank (below 256), kTableStage bytes, copied out run by run per group
+  // as ranks relative to its first rank (below GPG), kTableStage bytes, copied out run by run per group
   extern __shared__ __align__(16) uint8_t bin_dyn[];
   uint4* tcnt_s = reinterpret_cast<uint4*>(bin_dyn);
   uint32_t* ppos = reinterpret_cast<uint32_t*>(bin_dyn + 16 * bc.T);
   uint8_t* stage = bin_dyn + 20 * bc.T;
   __shared__ uint32_t ssum[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  WaveBin& W = wb[w];
+  WaveBin<GPW>& W = wb[w];
   uint32_t* tc = reinterpret_cast<uint32_t*>(tcnt_s);  // tc[4 t + w]: wavefront w's counter of tile t
   // TABLE: a one-dimensional grid in which all workgroups of view v have the same index modulo 8, so that they
   // run on one XCD (workgroups are handed to the 8 XCDs in turn) and the view's table and lists are touched by
@@ -164,8 +170,8 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
   }
   hi = min(hi, lo + ch.stride);  // the host sizes the stride to cover every chunk; never write past its slots
   const bool view_live = !live || live[v] != 0;
-  // groups of 256 consecutive ranks of this chunk (none for a view without live tiles)
-  const int64_t groups = view_live ? (hi - lo + 255) / 256 : 0;
+  // groups of GPG consecutive ranks of this chunk (none for a view without live tiles)
+  const int64_t groups = view_live ? (hi - lo + GPG - 1) / GPG : 0;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const uint8_t* al = alive ? alive + (int64_t)v * bc.T : nullptr;
   const int T = bc.T;
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
   int tbits = 0;
   while ((1 << tbits) < T) ++tbits;
   if (!EMIT && !TABLE)  // the count pass owes a zero to every wavefront slot no group covers
-    for (int64_t j = groups * 4 + (int64_t)bx * 256 + threadIdx.x; j < ch.wstride; j += (int64_t)gx * 256)
+    for (int64_t j = groups * 4 + (int64_t)bx * 256 + threadIdx.x; j < ch.wstride; j += (int64_t)gx * 256)  // GPG = 256
       counts[(int64_t)v * ch.wstride + j] = 0;
   unsigned long long block_sum = 0;
 
@@ -239,7 +245,7 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
         }
         if (hit) {
           const uint32_t at = tc[4 * t + w] + k;
-          if (staged) stage[at] = (uint8_t)(64 * w + i);  // the Gaussian in lane i, relative to the group
+          if (staged) stage[at] = (uint8_t)(GPW * w + i);  // the Gaussian in lane i, relative to the group
           else if (at < ch.cap) vals[at] = (uint32_t)(r - lane + i);  // depth rank of the Gaussian in lane i
           atomicAdd(&tc[4 * t + w], 1u);  // after every lane's read: the tile's slots advance by its hits
         }
@@ -258,13 +264,13 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
 
   // the chunk's groups, strided over the view's workgroups
   for (int64_t grp = bx; grp < groups; grp += gx) {
-    const int64_t idx = grp * 256 + threadIdx.x;
-    const int64_t wv = idx >> 6;  // wavefront index within the view's chunk
+    const int64_t idx = grp * GPG + (int64_t)w * GPW + lane;  // this lane's rank in the chunk (lanes < GPW)
+    const int64_t wv = grp * 4 + w;  // wavefront index within the view's chunk
     const int64_t wslot = (int64_t)v * ch.wstride + wv;
     const bool wave_in = wv < ch.wstride;
     const int64_t r = lo + idx;
     uint32_t nt = 0;
-    if (r < hi) {
+    if (lane < GPW && r < hi) {
       float rr[8];
       load_rec_geom(rec + ((int64_t)v * bc.G + r) * kRecF4, rr);
       TileRange tr;
@@ -289,8 +295,10 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
     }
     const uint32_t incl = wave_incl_scan_u32(nt, lane);
     const uint32_t my_pre = incl - nt;
-    W.pre[lane] = my_pre;
-    W.nt[lane] = nt;
+    if (lane < GPW) {
+      W.pre[lane] = my_pre;
+      W.nt[lane] = nt;
+    }
     g_pre = my_pre;
     g_nt = nt;
     const uint32_t S = __shfl(incl, 63, 64);
@@ -375,7 +383,7 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
       // copy the runs out: tile t's run is [end of tile t - 1's, the last wavefront's counter of tile t).  Sixteen
       // lanes copy one run, consecutive lanes to consecutive slots, so that the list lines are written in pieces
       // of up to 64 bytes, not word by word.
-      const uint32_t rank0 = (uint32_t)(lo + grp * 256);
+      const uint32_t rank0 = (uint32_t)(lo + grp * GPG);
       const int sub = lane >> 4, sl = lane & 15;
       for (int tb = 4 * w; tb < T; tb += 16) {
         const int tt = tb + sub;
@@ -408,7 +416,7 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
 }
 
 // Chunk-0 layout of the table form: e0[v] = min(front[v], fcap) (the first chunk's end, where the second
-// starts), base[v] = T * sum over earlier views of nw = 4 ceil(e0 / 256) (wavefront slots, whole workgroups),
+// starts), base[v] = T * sum over earlier views of nw = 4 ceil(e0 / kTableGroup) (wavefront slots, whole workgroups),
 // base[N] = the table's length.
 __global__ __launch_bounds__(256) void table_setup_kernel(const uint32_t* __restrict__ front, int N, int T,
                                                           uint32_t fcap, uint32_t* __restrict__ e0,
@@ -416,7 +424,7 @@ __global__ __launch_bounds__(256) void table_setup_kernel(const uint32_t* __rest
   __shared__ uint32_t wsum[4];
   const int v = threadIdx.x, lane = v & 63, w = v >> 6;
   const uint32_t e = v < N ? min(front[v], fcap) : 0u;
-  const uint32_t nw = 4 * ((e + 255) / 256);
+  const uint32_t nw = 4 * ((e + kTableGroup - 1) / kTableGroup);
   const uint32_t inc = wave_incl_scan_u32(nw, lane);
   if (lane == 63) wsum[w] = inc;
   __syncthreads();
@@ -452,7 +460,7 @@ __global__ __launch_bounds__(256) void table_starts_kernel(const uint32_t* __res
     return;
   }
   const int v = (int)(i / T), t = (int)(i - (int64_t)v * T);
-  const int64_t nw = 4 * (((int64_t)e0[v] + 255) / 256);
+  const int64_t nw = 4 * (((int64_t)e0[v] + kTableGroup - 1) / kTableGroup);
   const int64_t k = (int64_t)base[v] + t * nw;
   start[i] = min(k < (int64_t)base[N] ? scanned[k] : g, cap);
 }
@@ -499,6 +507,11 @@ __global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long
 // Workgroups per view: enough to fill the chip for one chunk of a large scene, few enough that a chunk whose
 // views are dead costs little more than its launch.
 unsigned bin_blocks(const ChunkArgs& ch) { return (unsigned)std::min<int64_t>((ch.stride + 255) / 256, 96); }
+// workgroups per view of the table form: one per group of the largest first chunk a view can have
+unsigned table_blocks(const ChunkArgs& ch) {
+  const int64_t m = ch.front_max > 0 ? ch.front_max : ch.stride;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((m + kTableGroup - 1) / kTableGroup, 256));
+}
 
 hipError_t launch_bin_count(const float4* rec, const uint32_t* vis_count, const uint32_t* live, const BlendConst& bc,
                             const ChunkArgs& ch, const uint8_t* alive, uint32_t* counts, unsigned long long* total,
@@ -530,7 +543,7 @@ hipError_t launch_bin_table_count(const float4* rec, const uint32_t* vis_count, 
                                   hipStream_t s) {
   if (bc.T > kTableMaxTiles || !ch.first || !ch.front) return hipErrorInvalidValue;
   ChunkArgs c = ch;
-  c.tgx = bin_blocks(ch);
+  c.tgx = table_blocks(ch);
   const dim3 grid((unsigned)(8 * ((bc.N + 7) / 8) * c.tgx));
   hipLaunchKernelGGL((bin_kernel<false, true>), grid, dim3(256), (size_t)16 * bc.T, s, rec, vis_count, nullptr, bc, c,
                      alive, table, nullptr, nullptr, nullptr, nullptr, base, nullptr);
@@ -542,7 +555,7 @@ hipError_t launch_bin_table_emit(const float4* rec, const uint32_t* vis_count, c
                                  const uint32_t* scanned, const uint32_t* grand, uint32_t* vals, hipStream_t s) {
   if (bc.T > kTableMaxTiles || !ch.first || !ch.front) return hipErrorInvalidValue;
   ChunkArgs c = ch;
-  c.tgx = bin_blocks(ch);
+  c.tgx = table_blocks(ch);
   const dim3 grid((unsigned)(8 * ((bc.N + 7) / 8) * c.tgx));
   hipLaunchKernelGGL((bin_kernel<true, true>), grid, dim3(256), (size_t)20 * bc.T + kTableStage, s, rec, vis_count,
                      nullptr, bc, c, alive, nullptr, nullptr, scanned, nullptr, vals, base, grand);

@@ -95,6 +95,7 @@ struct ChunkArgs {
   int64_t wstride;  // wavefront slots per view: ceil(stride / 64)
   uint32_t cap;     // key capacity
   int64_t tgx;      // workgroups per view of the table-form binning (set by its launchers)
+  int64_t front_max;  // table form: an upper bound of any view's first-chunk ranks (sizes the grid; 0: stride)
 };
 
 // Real spherical harmonics without the Condon-Shortley phase, index l*l + l + m, m = -l..l, written as
@@ -279,7 +280,9 @@ hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const u
 // chunk ranks [0, e0[v]) into vals (slots below cap), and launch_table_starts writes start[NT + 1] (list
 // bounds clamped to cap, start[NT] = *grand, the scan's total) and raises *max_total to the key total.
 constexpr int kTableMaxTiles = 1024;
-constexpr int kTableStage = 12288;  // hits of one emit workgroup staged in LDS (more: written directly)
+constexpr int kTableWaveRanks = 32;                   // ranks (Gaussians) per wavefront slot of the table
+constexpr int kTableGroup = 4 * kTableWaveRanks;      // ranks per workgroup of the table form
+constexpr int kTableStage = 8192;  // hits of one emit workgroup staged in LDS (more: written directly)
 hipError_t launch_table_setup(const uint32_t* front, int N, int T, uint32_t fcap, uint32_t* e0, uint32_t* base,
                               hipStream_t s);
 hipError_t launch_bin_table_count(const float4* rec, const uint32_t* vis_count, const BlendConst& bc,

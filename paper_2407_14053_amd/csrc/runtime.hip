@@ -414,17 +414,18 @@ int64_t chunk_stride(int64_t G, int c) {
 }
 
 // The first chunk uses the table form of binning (no tile partition) when a view has at most kTableMaxTiles
-// tiles; its table holds one count per (view, tile, wavefront of 64 ranks), at most kTableMaxEntries, so the
-// first chunk of each view is capped at fcap ranks (the second chunk starts where it ended).  0: partition form.
-constexpr int64_t kTableMaxEntries = 32ll << 20;
+// tiles; its table holds one count per (view, tile, wavefront slot of kTableWaveRanks ranks), at most
+// kTableMaxEntries, so the first chunk of each view is capped at fcap ranks (the second chunk starts where it
+// ended).  0: partition form.
+constexpr int64_t kTableMaxEntries = 64ll << 20;
 uint32_t table_fcap(int N, int64_t G, int64_t T) {
   if (T > kTableMaxTiles || N <= 0 || T <= 0) return 0;
   const int64_t waves = std::max<int64_t>(1, kTableMaxEntries / (T * N));
-  return (uint32_t)std::min<int64_t>(std::max<int64_t>(G, 1), 64 * waves);
+  return (uint32_t)std::min<int64_t>(std::max<int64_t>(G, 1), (int64_t)kTableWaveRanks * waves);
 }
 int64_t table_entries(int N, int64_t G, int64_t T) {
   const uint32_t f = table_fcap(N, G, T);
-  return f ? T * N * 4 * (((int64_t)f + 255) / 256) : 0;  // wavefront slots in whole workgroups
+  return f ? T * N * 4 * (((int64_t)f + kTableGroup - 1) / kTableGroup) : 0;  // slots in whole workgroups
 }
 
 // Device bytes of every per-frame buffer, in the order render_frame ensures them.
@@ -633,6 +634,8 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     ch.stride = chunk_stride(G, c);
     ch.wstride = (ch.stride + 63) / 64;
     ch.cap = cap;
+    // the first chunk's ranks per view: the LDS-sorted front (at most kFrontSortCap), within the table's cap
+    ch.front_max = fcap ? (lds_front ? std::min<int64_t>(kFrontSortCap, fcap) : (int64_t)fcap) : 0;
     const int64_t ncount = (int64_t)N * ch.wstride;
     // views with no live tile left produce no keys in this chunk (the first chunk has every tile live)
     const uint32_t* live = c > 0 ? C->live.as<uint32_t>() : nullptr;
