@@ -386,14 +386,15 @@ Tiles make_tiles(const dl_display_desc& d, int tw, int th) {
 }
 
 // Depth chunks (fractions of each view's visible depth ranks, in 1/1024): the front (about 1/32, chosen on a
-// key histogram) is small so that most tiles terminate before the bulk of the keys would be produced; the rest
-// of each view follows in one chunk (more boundaries add launches to every frame and only pay off in scenes
-// whose tiles stay unsaturated through a large part of the depth order).  An eager frame skips the second chunk
-// when no tile is live after the front; a front too small for the scene's rays to saturate costs the sort of
-// every live view's back (measured on 300k Gaussians at 3840x2160 N=45: 1/64 leaves tiles live, 3.6 ms per
-// frame; 1/32 none, 1.91 ms; 1/16 1.99 ms).
+// sampled histogram of the depth keys), the ranks up to 1/8, then the rest.  An eager frame skips the later
+// chunks when no tile is live after the front (a plan whose probe frame finished there holds the front alone);
+// when tiles stay live, the middle chunk gives them a second chance to saturate before the whole back is binned.
+// A front too small for the scene's rays to saturate costs the sort of every live view's back (measured on 300k
+// Gaussians at 3840x2160 N=45: 1/64 leaves tiles live, 3.6 ms per frame; 1/32 none, 1.91 ms; 1/16 1.99 ms; a
+// front of 1/43 was 1% faster there but left tiles live at some poses of 500k Gaussians at 1920x1080 N=16 and
+// 7680x4320 N=60, where 1/32 does not).
 constexpr int kChunkDen = 1024;
-constexpr int kChunkBounds[] = {0, 32, 1024};
+constexpr int kChunkBounds[] = {0, 32, 128, 1024};
 constexpr int kChunks = sizeof(kChunkBounds) / sizeof(kChunkBounds[0]) - 1;
 constexpr uint32_t kMaxKeyCap = 0x7fffffffu;
 

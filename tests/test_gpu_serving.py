@@ -423,10 +423,13 @@ def test_serving_at_workload_scale_equals_eager_and_oracle(ctx):
     reqs = serving.poisson_requests(12, 200.0, list(scenes), list(displays), seed=2006)
     rep = srv.run(reqs, realtime=True)
     log("  ", {k: v for k, v in rep.summary().items() if k != "per_display"})
-    # every request served once; a plan is made in the loop only to replace one whose capacity a pose overflowed
+    # every request served once; a plan is made in the loop only to replace one whose capacity a pose overflowed,
+    # and a request is also served again when its pose needed a later depth chunk than its first-chunk plan holds
+    # (that plan then keeps every chunk)
     assert sorted(d.rid for d in rep.done) == sorted(r.rid for r in reqs)
     assert rep.admitted == len(reqs) + rep.replans and rep.plans_created <= rep.replans
-    assert (rep.plans_created == 0) == (rep.replans == 0)
+    assert rep.replans == rep.plans_created or srv.all_chunks
+    log("   pairs switched to every chunk: %s" % sorted(srv.all_chunks))
     by_id = {r.rid: r for r in reqs}
     checked = set()
     from paper_2407_14053_amd import api
