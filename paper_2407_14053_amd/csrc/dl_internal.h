@@ -243,9 +243,13 @@ hipError_t launch_chunk_setup(const uint32_t* scanned, int64_t wstride, int N, c
 bool radix_sort_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t seg_len, int n_seg,
                     const uint32_t* seg_n, uint32_t cap, int bit_lo, int bit_hi, uint32_t* hist, uint32_t* partial,
                     hipStream_t s, hipError_t* err);
-// start[k] = first index j < n with keys[j] >= k, for k in [0, n_keys]; n = min(*n_dev, cap) or n_static
+// start[k] = first index j < n with keys[j] >= k << shift, for k in [0, n_keys]; n = min(*n_dev, cap) or n_static
 hipError_t launch_lower_bounds(const uint32_t* keys, const uint32_t* n_dev, uint32_t cap, int64_t n_static,
-                               uint32_t* start, int64_t n_keys, hipStream_t s);
+                               uint32_t* start, int64_t n_keys, hipStream_t s, int shift = 0);
+// Ray-list keys (view T + tile, or ~0u for none) widened by four bits, (key << 4) | block, where block =
+// 4 (4 row / th) + (4 column / tw) is the ray's sub-block of its tile (4 x 4 sub-blocks; the local column and row
+// are the entry's bits 0-11 and 12-23), so that a stable sort lists each (view, tile)'s rays block by block.
+hipError_t launch_ray_key_blocks(uint32_t* keys, const uint32_t* vals, int64_t n, int tw, int th, hipStream_t s);
 
 // ---- projection (project.hip) ----
 hipError_t launch_project(const float* soa, const double* cams, const ProjConst& pc, float4* rec, uint64_t* keys,

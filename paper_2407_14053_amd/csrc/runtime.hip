@@ -339,12 +339,19 @@ int build_ray_lists(dl_display* D, int tw, int th, hipStream_t s, RayLists** out
                           : launch_rays_emit(D->V.as<uint8_t>(), d.width, d.height, tw, th, L->ntx, L->T,
                                              k0.as<uint32_t>(), v0.as<uint32_t>(), s);
   if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
+  // each list's rays block by block (4 x 4 sub-blocks of the tile, row-major within a block), so that the blend's
+  // 64-ray slots cover compact areas (more records that no ray of a slot accepts, and rays that end together)
+  const int shift = bits + 4 <= 32 ? 4 : 0;
+  if (shift) {
+    e = launch_ray_key_blocks(k0.as<uint32_t>(), v0.as<uint32_t>(), n, tw, th, s);
+    if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
+  }
   bool fl = radix_sort_u32(k0.as<uint32_t>(), v0.as<uint32_t>(), k1.as<uint32_t>(), v1.as<uint32_t>(), n, 1, nullptr,
-                           0, 0, bits, hist.as<uint32_t>(), part.as<uint32_t>(), s, &e);
+                           0, 0, bits + shift, hist.as<uint32_t>(), part.as<uint32_t>(), s, &e);
   if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
   uint32_t* sk = fl ? k1.as<uint32_t>() : k0.as<uint32_t>();
   DevBuf& sv = fl ? v1 : v0;
-  e = launch_lower_bounds(sk, nullptr, 0, n, L->off.as<uint32_t>(), NT, s);
+  e = launch_lower_bounds(sk, nullptr, 0, n, L->off.as<uint32_t>(), NT, s, shift);
   if (e != hipSuccess) return cleanup_fail(DL_EHIP, hipGetErrorString(e));
   std::vector<uint32_t> off(NT + 1);
   e = hipMemcpyAsync(off.data(), L->off.p, (NT + 1) * 4, hipMemcpyDeviceToHost, s);

@@ -668,14 +668,15 @@ __global__ __launch_bounds__(kThreads) void depth_ranges_kernel(int N, int64_t G
 __global__ __launch_bounds__(kThreads) void lower_bounds_kernel(const uint32_t* __restrict__ keys,
                                                                   const uint32_t* __restrict__ n_dev, uint32_t cap,
                                                                   int64_t n_static, uint32_t* __restrict__ start,
-                                                                  int64_t n_keys) {
+                                                                  int64_t n_keys, int shift) {
   const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (k > n_keys) return;
   const int64_t n = n_dev ? (int64_t)min(*n_dev, cap) : n_static;
+  const int64_t ks = k << shift;
   int64_t lo = 0, hi = n;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)keys[mid] < k) lo = mid + 1;
+    if ((int64_t)keys[mid] < ks) lo = mid + 1;
     else hi = mid;
   }
   start[k] = (uint32_t)lo;
@@ -1266,9 +1267,9 @@ hipError_t launch_chunk_setup(const uint32_t* scanned, int64_t wstride, int N, c
 }
 
 hipError_t launch_lower_bounds(const uint32_t* keys, const uint32_t* n_dev, uint32_t cap, int64_t n_static,
-                               uint32_t* start, int64_t n_keys, hipStream_t s) {
+                               uint32_t* start, int64_t n_keys, hipStream_t s, int shift) {
   hipLaunchKernelGGL(lower_bounds_kernel, dim3((unsigned)((n_keys + 1 + kThreads - 1) / kThreads)), dim3(kThreads),
-                     0, s, keys, n_dev, cap, n_static, start, n_keys);
+                     0, s, keys, n_dev, cap, n_static, start, n_keys, shift);
   return hipGetLastError();
 }
 

@@ -72,6 +72,19 @@ __global__ __launch_bounds__(256) void rays_emit_kernel(const uint8_t* __restric
   }
 }
 
+// Ray-list keys widened by the ray's 4 x 4 sub-block of its tile (see launch_ray_key_blocks); one thread per entry.
+__global__ __launch_bounds__(256) void ray_key_blocks_kernel(uint32_t* __restrict__ keys,
+                                                             const uint32_t* __restrict__ vals, int64_t n, int tw,
+                                                             int th) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = keys[i];
+  if (k == 0xffffffffu) return;
+  const uint32_t e = vals[i];
+  const uint32_t bx = (4u * (e & 0xfffu)) / (uint32_t)tw, by = (4u * ((e >> 12) & 0xfffu)) / (uint32_t)th;
+  keys[i] = (k << 4) | (by * 4u + bx);
+}
+
 // *count += entries whose channel mask (bits 24-26) has more than one channel; one thread per entry.
 __global__ __launch_bounds__(256) void count_multichannel_kernel(const uint32_t* __restrict__ ent, int64_t n,
                                                                  uint32_t* __restrict__ count) {
@@ -133,6 +146,12 @@ hipError_t launch_rays_emit(const uint8_t* V, int W, int H, int tw, int th, int 
   const int64_t n = (int64_t)W * H;
   hipLaunchKernelGGL(rays_emit_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, V, W, H, tw, th, ntx, T, keys,
                      vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_ray_key_blocks(uint32_t* keys, const uint32_t* vals, int64_t n, int tw, int th, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ray_key_blocks_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, keys, vals, n, tw, th);
   return hipGetLastError();
 }
 
