@@ -199,10 +199,11 @@ bool radix_split_u64(uint64_t* k0, uint64_t* k1, uint32_t* v1, int64_t seg_len, 
                      uint64_t drop_key, uint32_t* n_vis, uint32_t* n_front, uint32_t* hist, uint32_t* partial,
                      hipStream_t s, hipError_t* err, const uint32_t* live = nullptr, bool back_only = false);
 // The front part of that split alone: each of the split's runs (split_waves_per_seg runs per segment) keeps its
-// items that are not drop_key and below thr[s], in order, at the run's start in (kout, vout), and cnt
-// (split_hist_size entries) receives per run the count of those and of all kept items, [segment][2][run].
-hipError_t launch_front_gather(const uint64_t* keys, uint64_t* kout, uint32_t* vout, int64_t G, int N,
-                               const uint64_t* thr, uint64_t drop_key, uint32_t* cnt, hipStream_t s);
+// items that are not drop_key and below thr[s], in order, at the run's start in kout, each packed as
+// key << 24 | position in the segment, and cnt (split_hist_size entries) receives per run the count of those and
+// of all kept items, [segment][2][run].  Segments of at most kFrontSortMaxG items.
+hipError_t launch_front_gather(const uint64_t* keys, uint64_t* kout, int64_t G, int N, const uint64_t* thr,
+                               uint64_t drop_key, uint32_t* cnt, hipStream_t s);
 // Stable LSD sort of each device range [lo[s], hi[s]) in place (n_seg <= 256), with the histogram layout that
 // launch_depth_ranges wrote to `layout`; returns whether the result is in (k1, v1).  hist: depth_ranges_hist_size
 // entries.
@@ -221,17 +222,21 @@ hipError_t launch_front_select(int N, int key_bits, int64_t num, int64_t den, co
                                hipStream_t s);
 // Ranges of the depth sorts: live == nullptr: the fronts [vG, vG + f); else the backs [vG + f, vG + n) of views
 // with a live tile (empty otherwise); rank_hi = end rank of the range; layout (2N + 1 entries) for the sort.
-// The fronts of the views sorted in LDS, one workgroup per view, from the runs that launch_front_gather left in
-// (keys, vals) with its counts cnt: vals[v G, v G + n_front[v]) receives the front's Gaussian indices in depth
-// order, n_vis[v] the view's kept items, rank_hi[v] = n_front[v].  A front of more than 12288 items is cut at a
-// bin of the key's top 12 bits, thr[v] lowered to that bin's start and n_front to the items below it; the rest
-// belongs to the back (a back-only split with the lowered thr puts it after the front).  Usable when
-// front_sort_fits(G, N): Gaussians per view at most kFrontSortMaxG.
+// The fronts of the views sorted in LDS, front_sort_parts(N) workgroups per view (each a range of the key's top
+// 12 bits, at quantiles of fhist, the projection's sampled histogram below thr[v]), from the runs that
+// launch_front_gather left in `items` with its counts cnt: vals[v G, v G + n_front[v]) receives the front's
+// Gaussian indices in depth order, n_vis[v] the view's kept items, rank_hi[v] = n_front[v].  A front of more
+// than 12288 items is sorted by one workgroup after a cut at a bin of the key's top 12 bits, thr[v] lowered to
+// that bin's start and n_front to the items below it; the rest belongs to the back (a back-only split with the
+// lowered thr puts it after the front).  Usable when front_sort_fits(G, N): Gaussians per view at most
+// kFrontSortMaxG.
 constexpr int64_t kFrontSortMaxG = 400000;
 constexpr int kFrontSortCap = 12288;  // the largest front sorted in LDS (larger ones are cut)
 bool front_sort_fits(int64_t G, int N);
-hipError_t launch_front_sort(const uint64_t* keys, uint32_t* vals, int64_t G, int N, const uint32_t* cnt,
-                             uint64_t* thr, uint32_t* n_vis, uint32_t* n_front, uint32_t* rank_hi, hipStream_t s);
+int front_sort_parts(int N);
+hipError_t launch_front_sort(const uint64_t* items, uint32_t* vals, int64_t G, int N, const uint32_t* cnt,
+                             const uint32_t* fhist, uint64_t* thr, uint32_t* n_vis, uint32_t* n_front,
+                             uint32_t* rank_hi, hipStream_t s);
 hipError_t launch_depth_ranges(int N, int64_t G, const uint32_t* n_vis, const uint32_t* n_front,
                                const uint32_t* live, uint32_t* lo, uint32_t* hi, uint32_t* rank_hi, uint32_t* layout,
                                hipStream_t s);

@@ -584,10 +584,10 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   bool fl = false;
   const bool lds_front = front_sort_fits(G, N);
   if (lds_front) {
-    HIP_TRY(launch_front_gather(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N,
-                                thr, kDepthCulled, C->hist.as<uint32_t>(), s));
-    HIP_TRY(launch_front_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N, C->hist.as<uint32_t>(), thr,
-                              vis, front, rank_hi, s));
+    HIP_TRY(launch_front_gather(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), G, N, thr, kDepthCulled,
+                                C->hist.as<uint32_t>(), s));
+    HIP_TRY(launch_front_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N, C->hist.as<uint32_t>(),
+                              C->fhist.as<uint32_t>(), thr, vis, front, rank_hi, s));
   } else {
     radix_split_u64(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N, thr,
                     kDepthCulled, vis, front, C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s, &e);

@@ -592,13 +592,12 @@ __global__ void split_counts_kernel(const uint32_t* __restrict__ hist, const uin
 }
 
 // The first chunk's part of the split: each wavefront keeps its run's front items (not dropped, key below the
-// view's threshold), in order, at the start of that run in (kout, vout), values = positions in the view, and
-// counts them and its kept items: cnt[2 v wps + k] = fronts, cnt[(2 v + 1) wps + k] = kept, for run k of view v.
-// The front sort gathers the runs; the backs are split only when a later chunk needs them.
+// view's threshold), in order, at the start of that run in `kout`, each packed as key << 24 | position in the view
+// (36 + 24 bits), and counts them and its kept items: cnt[2 v wps + k] = fronts, cnt[(2 v + 1) wps + k] = kept,
+// for run k of view v.  The front sort gathers the runs; the backs are split only when a later chunk needs them.
 __global__ __launch_bounds__(kThreads) void front_gather_kernel(const uint64_t* __restrict__ keys, int64_t G, int wps,
                                                                   const uint64_t* __restrict__ thr, uint64_t drop,
                                                                   uint64_t* __restrict__ kout,
-                                                                  uint32_t* __restrict__ vout,
                                                                   uint32_t* __restrict__ cnt) {
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
@@ -607,7 +606,6 @@ __global__ __launch_bounds__(kThreads) void front_gather_kernel(const uint64_t* 
   split_range(G, wps, k, lo, hi);
   const uint64_t* kin = keys + (int64_t)v * G;
   uint64_t* ko = kout + (int64_t)v * G + lo;
-  uint32_t* vo = vout + (int64_t)v * G + lo;
   const uint64_t th = thr[v];
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   uint32_t p = 0, kept = 0;
@@ -622,11 +620,7 @@ __global__ __launch_bounds__(kThreads) void front_gather_kernel(const uint64_t* 
     for (int r = 0; r < 4; ++r) {
       const bool in = kk[r] != drop, fr = in && kk[r] < th;
       const uint64_t m = __ballot(fr);
-      if (fr) {
-        const uint32_t at = p + (uint32_t)__popcll(m & below);
-        ko[at] = kk[r];
-        vo[at] = (uint32_t)(i0 + 64 * r + lane);
-      }
+      if (fr) ko[p + (uint32_t)__popcll(m & below)] = (kk[r] << 24) | (uint64_t)(i0 + 64 * r + lane);
       p += (uint32_t)__popcll(m);
       kept += (uint32_t)__popcll(__ballot(in));
     }
@@ -682,17 +676,19 @@ __global__ __launch_bounds__(kThreads) void lower_bounds_kernel(const uint32_t* 
   start[k] = (uint32_t)lo;
 }
 
-// ---- depth order of small fronts: one workgroup per view sorts the view's front in LDS ----
-// The front of a view (its nearest visible Gaussians, left by the gather pass at the starts of the view's runs,
-// each run in Gaussian index order) is collected run by run into LDS in index order, packed as key << 24 | index
-// (36 + 24 bits), and sorted by four stable LSD passes of 9 bits over the key bits, which gives the order by
-// (depth key, index) of the device passes in one launch.  Wavefront w owns the contiguous items [w R, (w + 1) R)
-// (R a multiple of 64), visited in slots of 64 consecutive items; a lane's rank among the equal digits of its slot
-// comes from a match mask of nine ballots, its rank in the wavefront from a running count per (digit, wavefront),
-// and the scatter position from the exclusive scan of those counts in (digit, wavefront) order.  A front larger
-// than the LDS holds is first cut at a bin of the key's top 12 bits (an exact histogram of the front): only the
-// items below that bin are collected, the view's threshold is lowered to the bin's start, and the others belong
-// to the back, which a later split pass takes from the projection's keys with that threshold.
+// ---- depth order of small fronts: a few workgroups per view sort the view's front in LDS ----
+// The front of a view (its nearest visible Gaussians, left by the gather pass at the starts of the view's runs as
+// key << 24 | index, each run in Gaussian index order) is split into `parts` ranges of the key's top 12 bits at
+// quantiles of the projection's sampled histogram; each part's workgroup loads the front in index order, keeps its
+// range's items (also in index order) in LDS, sorts them by four stable LSD passes of 9 bits over the key bits,
+// and writes them after the items of the lower ranges, which gives the order by (depth key, index) of the device
+// passes.  Wavefront w owns the contiguous items [w R, (w + 1) R) (R a multiple of 64), visited in slots of 64
+// consecutive items; a lane's rank among the equal digits of its slot comes from a match mask of nine ballots, its
+// rank in the wavefront from a running count per (digit, wavefront), and the scatter position from the exclusive
+// scan of those counts in (digit, wavefront) order.  A front larger than the LDS holds is sorted by its first
+// part alone, after a cut at a bin of the key's top 12 bits (an exact histogram of the front): only the items
+// below that bin are collected, the view's threshold is lowered to the bin's start, and the others belong to the
+// back, which a later split pass takes from the projection's keys with that threshold.
 __device__ inline void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -717,6 +713,7 @@ constexpr int kFsRunsPerThread = kFsMaxRuns / kFsThreads;
 static_assert(kFsBins * kFsWaves >= kFsCutBins, "the cut histogram shares the count array");
 static_assert(kFsWaves == 16 && kFsThreads * 8 == kFsBins * kFsWaves, "eight (digit, wavefront) counters per thread");
 static_assert(kFsCutBins == 4 * kFsThreads, "four cut bins per thread");
+static_assert(kFsCutBins == kFrontBins, "the parts' bins are the sampled histogram's");
 static_assert(kDepthKeyBits == 4 * kFsBits, "four passes cover the depth key");
 
 struct FrontSortSmem {
@@ -758,11 +755,14 @@ __device__ inline int64_t fs_run_len(int64_t G, int wps) {
 __device__ inline int64_t fs_run_start(int64_t G, int64_t per, int k) { return min((int64_t)k * per, G); }
 
 
+// The bin of a packed item (key << 24 | index): the key's top 12 bits.
+__device__ inline uint32_t fs_bin(uint64_t it) { return (uint32_t)(it >> 48) & (kFsCutBins - 1); }
+
 // A front of f > kFsCap items (runs of cf[k] items): the largest bin `cut` of the top 12 key bits such that the
 // items of the bins below it fit; those are written to sm.items in index order and their count returned, and
 // *thr_v becomes cut << 24.
-__device__ uint32_t fs_cut_runs(FrontSortSmem& sm, const uint64_t* keys, const uint32_t* vals, int64_t base,
-                                int64_t G, int wps, int64_t per, const uint32_t* cf, uint64_t* thr_v) {
+__device__ uint32_t fs_cut_runs(FrontSortSmem& sm, const uint64_t* items, int64_t base, int64_t G, int wps,
+                                int64_t per, const uint32_t* cf, uint64_t* thr_v) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   for (int b = t; b < kFsCutBins; b += kFsThreads) sm.cnt[b] = 0;
   if (t == 0) sm.misc[0] = sm.misc[1] = 0;
@@ -770,7 +770,7 @@ __device__ uint32_t fs_cut_runs(FrontSortSmem& sm, const uint64_t* keys, const u
   for (int k = w; k < wps; k += kFsWaves) {
     const int64_t r0 = base + fs_run_start(G, per, k);
     const uint32_t c = cf[k];
-    for (uint32_t i = lane; i < c; i += 64) atomicAdd(&sm.cnt[(uint32_t)(keys[r0 + i] >> 24) & 4095u], 1u);
+    for (uint32_t i = lane; i < c; i += 64) atomicAdd(&sm.cnt[fs_bin(items[r0 + i])], 1u);
   }
   __syncthreads();
   // bin b holds cnt[b]; thread t owns bins 4t .. 4t + 3; `below` = items in the bins below the current one
@@ -804,7 +804,7 @@ __device__ uint32_t fs_cut_runs(FrontSortSmem& sm, const uint64_t* keys, const u
     uint32_t n = 0;
     for (uint32_t i0 = 0; i0 < c; i0 += 64) {
       const uint32_t i = i0 + lane;
-      n += (uint32_t)__popcll(__ballot(i < c && ((uint32_t)(keys[r0 + i] >> 24) & 4095u) < cut));
+      n += (uint32_t)__popcll(__ballot(i < c && fs_bin(items[r0 + i]) < cut));
     }
     if (lane == 0) sm.cnt[k] = n;
   }
@@ -831,10 +831,10 @@ __device__ uint32_t fs_cut_runs(FrontSortSmem& sm, const uint64_t* keys, const u
     uint32_t o = sm.cnt[k];
     for (uint32_t i0 = 0; i0 < c; i0 += 64) {
       const uint32_t i = i0 + lane;
-      const uint64_t key = i < c ? keys[r0 + i] : 0ull;
-      const bool keep = i < c && ((uint32_t)(key >> 24) & 4095u) < cut;
+      const uint64_t it = i < c ? items[r0 + i] : 0ull;
+      const bool keep = i < c && fs_bin(it) < cut;
       const uint64_t m = __ballot(keep);
-      if (keep) sm.items[o + (uint32_t)__popcll(m & lt)] = (key << 24) | (unsigned long long)vals[r0 + i];
+      if (keep) sm.items[o + (uint32_t)__popcll(m & lt)] = it;
       o += (uint32_t)__popcll(m);
     }
   }
@@ -843,15 +843,19 @@ __device__ uint32_t fs_cut_runs(FrontSortSmem& sm, const uint64_t* keys, const u
   return kept_total;
 }
 
-__global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* __restrict__ keys,
+__global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* __restrict__ items,
                                                                  uint32_t* __restrict__ vals, int64_t G, int wps,
-                                                                 const uint32_t* __restrict__ cnt,
+                                                                 int N, int parts, const uint32_t* __restrict__ cnt,
+                                                                 const uint32_t* __restrict__ fhist,
                                                                  uint64_t* __restrict__ thr,
                                                                  uint32_t* __restrict__ n_vis,
                                                                  uint32_t* __restrict__ n_front,
                                                                  uint32_t* __restrict__ rank_hi) {
   __shared__ FrontSortSmem sm;
-  const int v = blockIdx.x;
+  // the parts of a view run on one XCD (workgroups are dealt to the 8 XCDs in turn), whose L2 holds its runs
+  const int kk = (int)(blockIdx.x >> 3);
+  const int v = (kk / parts) * 8 + (int)(blockIdx.x & 7u), q = kk % parts;
+  if (v >= N) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t base = (int64_t)v * G;
   const int64_t per = fs_run_len(G, wps);
@@ -860,29 +864,63 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* 
   // the runs' offsets in the front (thread t owns runs t R', ..., t R' + R' - 1), the front and visible counts
   uint32_t e[kFsRunsPerThread], mine = 0, vis = 0;
 #pragma unroll
-  for (int q = 0; q < kFsRunsPerThread; ++q) {
-    const int k = t * kFsRunsPerThread + q;
-    e[q] = k < wps ? cf[k] : 0u;
-    mine += e[q];
+  for (int qq = 0; qq < kFsRunsPerThread; ++qq) {
+    const int k = t * kFsRunsPerThread + qq;
+    e[qq] = k < wps ? cf[k] : 0u;
+    mine += e[qq];
     vis += k < wps ? cv[k] : 0u;
   }
   uint32_t f = 0, nv = 0;
   uint32_t run = fs_block_scan(mine, sm.wsum, &f);
   fs_block_scan(vis, sm.wsum, &nv);
   const bool cut = f > (uint32_t)kFsCap;
+  if (cut && q != 0) return;  // a cut front is sorted by its first part alone
+  const bool split = parts > 1 && !cut;
+  uint32_t lo_bin = 0, hi_bin = kFsCutBins;  // this part's bins of the key's top 12 bits
   if (!cut) {
 #pragma unroll
-    for (int q = 0; q < kFsRunsPerThread; ++q) {
-      const int k = t * kFsRunsPerThread + q;
+    for (int qq = 0; qq < kFsRunsPerThread; ++qq) {
+      const int k = t * kFsRunsPerThread + qq;
       if (k < wps) sm.cnt[k] = run;
-      run += e[q];
+      run += e[qq];
+    }
+    if (split) {
+      // boundary j of the parts: the bin after the one where the sampled count of the front's bins (those below
+      // the threshold's) reaches ceil(j S / parts), S the samples in the front; 4096 when no bin does (S = 0)
+      const uint32_t tb = (uint32_t)(thr[v] >> (kDepthKeyBits - kFrontBits));
+      const uint32_t* h = fhist + (int64_t)v * kFrontBins;
+      uint32_t c4[4], loc = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t b = 4 * t + k;
+        c4[k] = b < tb ? h[b] : 0u;
+        loc += c4[k];
+      }
+      uint32_t S = 0;
+      uint32_t before = fs_block_scan(loc, sm.wsum, &S);
+      if (t == 0) sm.misc[0] = sm.misc[1] = kFsCutBins;
+      __syncthreads();
+      const uint32_t t0 = (uint32_t)(((uint64_t)S * q + parts - 1) / parts);
+      const uint32_t t1 = (uint32_t)(((uint64_t)S * (q + 1) + parts - 1) / parts);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t b0 = before;
+        before += c4[k];
+        if (b0 < t0 && before >= t0) sm.misc[0] = 4 * t + k + 1;  // one thread each (the count is monotone)
+        if (b0 < t1 && before >= t1) sm.misc[1] = 4 * t + k + 1;
+      }
     }
     __syncthreads();
+    if (split) {
+      lo_bin = q > 0 ? sm.misc[0] : 0u;
+      hi_bin = q + 1 < parts ? sm.misc[1] : (uint32_t)kFsCutBins;
+    }
   } else {
-    f = fs_cut_runs(sm, keys, vals, base, G, wps, per, cf, thr + v);
+    f = fs_cut_runs(sm, items, base, G, wps, per, cf, thr + v);
   }
-  const uint32_t R = (f + kFsThreads - 1) / kFsThreads * 64;  // items per wavefront, a multiple of 64
-  const int nslot = (int)(R / 64);                             // <= kFsSlots
+  const uint32_t f_all = f;
+  uint32_t R = (f + kFsThreads - 1) / kFsThreads * 64;  // items per wavefront, a multiple of 64
+  int nslot = (int)(R / 64);                             // <= kFsSlots
   unsigned long long it[kFsSlots];
   uint32_t rank[kFsSlots];
 #pragma unroll
@@ -890,6 +928,8 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* 
     it[j] = 0ull;
     rank[j] = 0;
   }
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t out0 = 0;  // the part's first rank in the view's front
   if (cut) {
 #pragma unroll
     for (int j = 0; j < kFsSlots; ++j) {
@@ -906,21 +946,47 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* 
 #pragma unroll
       for (int j = 0; j < kFsSlots; ++j) {
         const uint32_t i = w * R + j * 64 + lane;
-        const int kk = min(k[j] + step, wps - 1);
-        k[j] = (k[j] + step < wps && sm.cnt[kk] <= i) ? k[j] + step : k[j];
+        const int kk2 = min(k[j] + step, wps - 1);
+        k[j] = (k[j] + step < wps && sm.cnt[kk2] <= i) ? k[j] + step : k[j];
       }
     }
 #pragma unroll
     for (int j = 0; j < kFsSlots; ++j) {
       const uint32_t i = w * R + j * 64 + lane;
-      if (j < nslot && i < f) {
-        const int64_t r = base + fs_run_start(G, per, k[j]) + (i - sm.cnt[k[j]]);
-        it[j] = (keys[r] << 24) | (unsigned long long)vals[r];
+      if (j < nslot && i < f) it[j] = items[base + fs_run_start(G, per, k[j]) + (i - sm.cnt[k[j]])];
+    }
+    if (split) {
+      // keep the part's items, in front order, at the start of the LDS array; count the items of the lower parts
+      uint64_t m[kFsSlots];
+      uint32_t own = 0, low = 0;
+#pragma unroll
+      for (int j = 0; j < kFsSlots; ++j) {
+        const bool valid = j < nslot && w * R + j * 64 + lane < f;
+        const uint32_t b = fs_bin(it[j]);
+        m[j] = __ballot(valid && b >= lo_bin && b < hi_bin);
+        own += (uint32_t)__popcll(m[j]);
+        low += (uint32_t)__popcll(__ballot(valid && b < lo_bin));
+      }
+      uint32_t fq = 0;
+      uint32_t o = __shfl(fs_block_scan(lane == 0 ? own : 0u, sm.wsum, &fq), 0, 64);
+      fs_block_scan(lane == 0 ? low : 0u, sm.wsum, &out0);
+#pragma unroll
+      for (int j = 0; j < kFsSlots; ++j) {
+        if ((m[j] >> lane) & 1ull) sm.items[o + (uint32_t)__popcll(m[j] & lt)] = it[j];
+        o += (uint32_t)__popcll(m[j]);
+      }
+      __syncthreads();
+      f = fq;
+      R = (f + kFsThreads - 1) / kFsThreads * 64;
+      nslot = (int)(R / 64);
+#pragma unroll
+      for (int j = 0; j < kFsSlots; ++j) {
+        const uint32_t i = w * R + j * 64 + lane;
+        it[j] = (j < nslot && i < f) ? sm.items[i] : 0ull;
       }
     }
   }
-  __syncthreads();  // the run offsets are read before the first pass clears the counts
-  const uint64_t lt = (1ull << lane) - 1ull;
+  __syncthreads();  // the run offsets (and the kept items) are read before the first pass clears the counts
   for (int p = 0; p < 4; ++p) {
     const int sh = 24 + kFsBits * p;
     for (int b = t; b < kFsCntSize; b += kFsThreads) sm.cnt[b] = 0;
@@ -981,11 +1047,11 @@ __global__ __launch_bounds__(kFsThreads) void front_sort_kernel(const uint64_t* 
       __syncthreads();
     }
   }
-  for (uint32_t i = t; i < f; i += kFsThreads) vals[base + i] = (uint32_t)(sm.items[i] & 0xffffffull);
-  if (t == 0) {
+  for (uint32_t i = t; i < f; i += kFsThreads) vals[base + out0 + i] = (uint32_t)(sm.items[i] & 0xffffffull);
+  if (t == 0 && q == 0) {
     n_vis[v] = nv;
-    n_front[v] = f;
-    rank_hi[v] = f;
+    n_front[v] = f_all;
+    rank_hi[v] = f_all;
   }
 }
 
@@ -1152,12 +1218,14 @@ bool radix_split_u64(uint64_t* k0, uint64_t* k1, uint32_t* v1, int64_t seg_len, 
   return true;
 }
 
-hipError_t launch_front_gather(const uint64_t* keys, uint64_t* kout, uint32_t* vout, int64_t G, int N,
-                               const uint64_t* thr, uint64_t drop_key, uint32_t* cnt, hipStream_t s) {
+hipError_t launch_front_gather(const uint64_t* keys, uint64_t* kout, int64_t G, int N, const uint64_t* thr,
+                               uint64_t drop_key, uint32_t* cnt, hipStream_t s) {
   if (N <= 0) return hipSuccess;
+  // positions must fit the packed item's 24 bits
+  if (G > kFrontSortMaxG) return hipErrorInvalidValue;
   const int wps = split_waves_per_seg(G, N);
   hipLaunchKernelGGL(front_gather_kernel, dim3((unsigned)((int64_t)N * wps / kWaves)), dim3(kThreads), 0, s, keys, G,
-                     wps, thr, drop_key, kout, vout, cnt);
+                     wps, thr, drop_key, kout, cnt);
   return hipGetLastError();
 }
 
@@ -1200,13 +1268,19 @@ hipError_t launch_depth_ranges(int N, int64_t G, const uint32_t* n_vis, const ui
 
 bool front_sort_fits(int64_t G, int N) { return G <= kFrontSortMaxG && split_waves_per_seg(G, N) <= kFsMaxRuns; }
 
-hipError_t launch_front_sort(const uint64_t* keys, uint32_t* vals, int64_t G, int N, const uint32_t* cnt,
-                             uint64_t* thr, uint32_t* n_vis, uint32_t* n_front, uint32_t* rank_hi, hipStream_t s) {
+int front_sort_parts(int N) { return (int)std::max(1, std::min(8, 256 / std::max(N, 1))); }
+
+hipError_t launch_front_sort(const uint64_t* items, uint32_t* vals, int64_t G, int N, const uint32_t* cnt,
+                             const uint32_t* fhist, uint64_t* thr, uint32_t* n_vis, uint32_t* n_front,
+                             uint32_t* rank_hi, hipStream_t s) {
   if (N <= 0) return hipSuccess;
   // indices must fit the packed item's 24 bits, and the runs' offsets the count array
   if (!front_sort_fits(G, N)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(front_sort_kernel, dim3((unsigned)N), dim3(kFsThreads), 0, s, keys, vals, G,
-                     split_waves_per_seg(G, N), cnt, thr, n_vis, n_front, rank_hi);
+  // one workgroup per (view, part) in enough groups of 8 for the views, the parts of a view 8 apart
+  const int parts = front_sort_parts(N);
+  const int64_t nb = (int64_t)8 * parts * ((N + 7) / 8);
+  hipLaunchKernelGGL(front_sort_kernel, dim3((unsigned)nb), dim3(kFsThreads), 0, s, items, vals, G,
+                     split_waves_per_seg(G, N), N, parts, cnt, fhist, thr, n_vis, n_front, rank_hi);
   return hipGetLastError();
 }
 
