@@ -469,7 +469,9 @@ __global__ __launch_bounds__(256) void table_starts_kernel(const uint32_t* __res
 __global__ __launch_bounds__(256) void view_live_kernel(const uint8_t* __restrict__ alive, int64_t T,
                                                          uint32_t* __restrict__ live,
                                                          unsigned long long* __restrict__ total,
-                                                         unsigned long long* __restrict__ later) {
+                                                         unsigned long long* __restrict__ later,
+                                                         const uint32_t* __restrict__ vis,
+                                                         unsigned long long* __restrict__ vis_sum) {
   __shared__ uint32_t part[4];
   const int v = blockIdx.x;
   if (v == 0 && threadIdx.x == 0) *total = 0;  // the next chunk's key count starts from zero
@@ -482,11 +484,12 @@ __global__ __launch_bounds__(256) void view_live_kernel(const uint8_t* __restric
     const uint32_t n = part[0] + part[1] + part[2] + part[3];
     live[v] = n;
     if (later && n) *later = 1ull;  // every writer stores the same value
+    if (vis) atomicAdd(vis_sum, (unsigned long long)vis[v]);
   }
 }
 
-// Start of a frame: every (view, tile) with rays is live, the front histogram and the first n_totals key totals
-// (the chunk's, then the frame's largest) are zero.
+// Start of a frame: every (view, tile) with rays is live, the front histogram and the first n_totals frame totals
+// (the chunk's key count, the frame's largest, whether a later chunk is needed, the visible items) are zero.
 __global__ __launch_bounds__(256) void frame_init_kernel(uint8_t* __restrict__ alive,
                                                          const uint32_t* __restrict__ ray_off, int64_t n,
                                                          uint32_t* __restrict__ zero32, int64_t n_zero,
@@ -572,14 +575,16 @@ hipError_t launch_table_starts(const uint32_t* scanned, const uint32_t* base, co
 }
 
 hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, unsigned long long* total,
-                            unsigned long long* later, hipStream_t s) {
-  hipLaunchKernelGGL(view_live_kernel, dim3((unsigned)N), dim3(256), 0, s, alive, T, live, total, later);
+                            unsigned long long* later, const uint32_t* vis, unsigned long long* vis_sum,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(view_live_kernel, dim3((unsigned)N), dim3(256), 0, s, alive, T, live, total, later, vis,
+                     vis_sum);
   return hipGetLastError();
 }
 
 hipError_t launch_frame_init(uint8_t* alive, const uint32_t* ray_off, int64_t n, uint32_t* zero32, int64_t n_zero,
                              unsigned long long* totals, int n_totals, hipStream_t s) {
-  const int64_t m = std::max<int64_t>(std::max<int64_t>(n, n_zero), 2);
+  const int64_t m = std::max<int64_t>(std::max<int64_t>(n, n_zero), n_totals);
   hipLaunchKernelGGL(frame_init_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, alive, ray_off, n, zero32,
                      n_zero, totals, n_totals);
   return hipGetLastError();

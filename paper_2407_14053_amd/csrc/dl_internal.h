@@ -303,9 +303,11 @@ hipError_t launch_bin_table_emit(const float4* rec, const uint32_t* vis_count, c
 hipError_t launch_table_starts(const uint32_t* scanned, const uint32_t* base, const uint32_t* e0, int N, int T,
                                const uint32_t* grand, uint32_t cap, unsigned long long* max_total, uint32_t* start,
                                hipStream_t s);
-// live[v] = live tiles of view v; *total = 0 (for the next chunk); *later = 1 if any tile is live (later given)
+// live[v] = live tiles of view v; *total = 0 (for the next chunk); *later = 1 if any tile is live (later given);
+// *vis_sum += the sum of vis[0, N) (vis given)
 hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, unsigned long long* total,
-                            unsigned long long* later, hipStream_t s);
+                            unsigned long long* later, const uint32_t* vis, unsigned long long* vis_sum,
+                            hipStream_t s);
 
 
 // alive[i] = tile i has rays (ray_off nullptr: all); zero32[0, n_zero) = 0; totals[0, n_totals) = 0

@@ -139,9 +139,9 @@ struct dl_ctx {
       state, dtotal, gacc;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
   double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
-  // pinned, read after the first depth chunk of eager frames: live tiles per view [256], that chunk's key count
-  // (8 bytes), visible Gaussians per view [256]
-  uint32_t* live_host = nullptr;
+  // pinned, read after the first depth chunk of eager frames: that chunk's key count, whether a tile is still
+  // live, the visible Gaussians of all views
+  unsigned long long* frame_host = nullptr;
   // profiling: 0 off, 1 HIP events around the blend launches, 2 around every stage, 3 every stage and the
   // blend's work counters
   int prof = 0;
@@ -477,7 +477,7 @@ FrameSizes frame_sizes(int N, int64_t G, int64_t NT, int64_t nstate, uint32_t ca
       (size_t)(NT + 1) * 4,                           // list starts
       (size_t)NT,                                     // live tiles
       (size_t)std::max<int64_t>(nstate, 1) * 16,      // ray state
-      3 * 8,                                          // key totals: chunk, largest, later chunk needed
+      4 * 8,                                          // key totals: chunk, largest; later chunk needed; visible
       (size_t)hs * 4,                                 // radix histograms
       (size_t)(scan_partial_count(std::max<int64_t>(hs, ncounts)) + 2) * 4,  // scan partials
       stats ? (size_t)kStatSlots * 3 * 8 : 0,         // work counters
@@ -542,7 +542,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   if (C->prof >= 3) HIP_TRY(launch_fill_u64(C->stats.as<unsigned long long>(), kStatSlots * 3, 0ull, s));
   HIP_TRY(launch_frame_init(C->alive.as<uint8_t>(), standard ? nullptr : L->off.as<uint32_t>(), NT,
                             C->fhist.as<uint32_t>(), front_hist_size(N), C->dtotal.as<unsigned long long>(),
-                            mode.keep_max ? 1 : 2, s));
+                            mode.keep_max ? 1 : 4, s));
   C->end(mk, s);
 
   ProjConst pc{};
@@ -706,37 +706,36 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                                    L->ent.as<uint32_t>(), L->max_rays, bc, bk, C->alive.as<uint8_t>(),
                                    C->state.as<float4>(), out, s));
     }
+    // after the first chunk an eager frame reads the later flag and the visible total, a first-chunk plan keeps the
+    // flag as its status
+    const bool readback = c == 0 && kChunks > 1 && mode.finish;
     if (c + 1 < kChunks)
       HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), total,
-                               mode.first_only ? total + 2 : nullptr, s));
+                               (mode.first_only || readback) ? total + 2 : nullptr, readback ? vis : nullptr,
+                               total + 3, s));
     C->end(mk, s);
     if (mode.first_only) break;
-    if (c == 0 && kChunks > 1 && mode.finish) {
-      // an eager frame (its caller waits for it anyway) reads the live tiles after the first chunk: when every
-      // tile's rays have terminated, every tile has written its pixels and the later chunks would only launch
-      // empty kernels, so they are skipped (a captured frame keeps them: its launches are fixed).  The same
-      // readback brings the first chunk's key count: a frame that skips the later chunks is complete here, and
-      // its overflow check needs nothing more (a backward frame goes on to the projection's backward).
-      unsigned long long* keys_host = reinterpret_cast<unsigned long long*>(C->live_host + 256);
-      uint32_t* vis_counts = C->live_host + 258;
-      HIP_TRY(hipMemcpyAsync(C->live_host, C->live.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(keys_host, total + 1, 8, hipMemcpyDeviceToHost, s));
-      if (C->prof) HIP_TRY(hipMemcpyAsync(vis_counts, C->vis.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
+    if (readback) {
+      // an eager frame (its caller waits for it anyway) reads whether a tile is still live after the first chunk:
+      // when every tile's rays have terminated, every tile has written its pixels and the later chunks would only
+      // launch empty kernels, so they are skipped (a captured frame keeps them: its launches are fixed).  The same
+      // copy brings the first chunk's key count and the views' visible total: a frame that skips the later chunks
+      // is complete here, and its overflow check needs nothing more (a backward frame goes on to the
+      // projection's backward).
+      unsigned long long* rb = C->frame_host;
+      HIP_TRY(hipMemcpyAsync(rb, total + 1, 3 * 8, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      if (*keys_host > cap) {
+      if (rb[0] > cap) {
         // the first chunk overflowed: its blend saw truncated lists, so the live tiles (and the later chunks'
         // key counts) mean nothing; grow to what this chunk needs and render again
-        *need = *keys_host;
+        *need = rb[0];
         return DL_ECAP;
       }
-      uint64_t nlive = 0;
-      for (int v = 0; v < N; ++v) nlive += C->live_host[v];
-      C->later_ran = nlive != 0;
-      if (nlive == 0) {
+      C->later_ran = rb[1] != 0;
+      if (!C->later_ran) {
         if (bwd) break;
-        C->keys = (int64_t)*keys_host;
-        if (C->prof)
-          for (int v = 0; v < N; ++v) C->visible += vis_counts[v];
+        C->keys = (int64_t)rb[0];
+        if (C->prof) C->visible += (int64_t)rb[2];
         return DL_OK;
       }
     }
@@ -861,9 +860,9 @@ int dl_create(int device, dl_ctx** out) {
   dl_ctx* c = new dl_ctx();
   c->device = device;
   if (hipHostMalloc((void**)&c->cams_host, 256 * kCamDoubles * 8, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->live_host, 256 * 4 + 8 + 256 * 4, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->frame_host, 4 * 8, hipHostMallocDefault) != hipSuccess) {
     if (c->cams_host) (void)hipHostFree(c->cams_host);
-    if (c->live_host) (void)hipHostFree(c->live_host);
+    if (c->frame_host) (void)hipHostFree(c->frame_host);
     delete c;
     return fail(DL_ENOMEM, "pinned camera staging");
   }
@@ -876,7 +875,7 @@ void dl_destroy(dl_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   if (c->cams_host) (void)hipHostFree(c->cams_host);
-  if (c->live_host) (void)hipHostFree(c->live_host);
+  if (c->frame_host) (void)hipHostFree(c->frame_host);
   delete c;
 }
 
