@@ -109,22 +109,23 @@ __device__ inline int wave_max_scan(int x, int lane) {
 // Two ways to turn the hits into (view, tile) lists:
 //   !TABLE: COUNT stores the number of keys of each wavefront; EMIT writes (tile, rank) pairs from the
 //           wavefront's scanned offset, in emission order, and a stable partition by tile follows.
-//   TABLE:  COUNT stores, for every wavefront w and tile t of view v, the number of its hits in t at
-//           table[base_v + t * nw_v + w] (nw_v = wavefronts of the view, a multiple of 4, base_v = T * sum of nw
-//           over earlier views); scanned in that order, the table gives each wavefront its first slot in every
-//           tile's final list, so EMIT writes the ranks straight into the lists: no partition.  Lanes of one step
-//           that hit the same tile take consecutive slots in lane order, which is rank order, since every
-//           Gaussian's tiles are distinct.  The tile counters of the four
-//           wavefronts of a workgroup live in LDS as [tile][wavefront] (T <= kTableMaxTiles), so that the
-//           workgroup moves them to and from the table as one 16-byte access per tile.
+//   TABLE:  COUNT stores, for every workgroup (group of four wavefronts) g and tile t of view v, the numbers of
+//           its four wavefronts' hits in t, one byte each (at most kTableWaveRanks), in the word
+//           table[base_v + t * ng_v + g] (ng_v = groups of the view, base_v = T * sum of ng over earlier views);
+//           the exclusive scan of the words' byte sums in that order gives each group its first slot in every
+//           tile's final list, and the bytes its wavefronts' slots after it, so EMIT writes the ranks straight
+//           into the lists: no partition.  Lanes of one step that hit the same tile take consecutive slots in
+//           lane order, which is rank order, since every Gaussian's tiles are distinct.  The tile counters of
+//           the four wavefronts of a workgroup live in LDS as [tile][wavefront] (T <= kTableMaxTiles).
+static_assert(kTableWaveRanks <= 255, "a wavefront's hits in one tile fit the table's byte");
+
 template <bool EMIT, bool TABLE>
 __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec, const uint32_t* __restrict__ vis_count,
                                                   const uint32_t* __restrict__ live, BlendConst bc, ChunkArgs ch,
                                                   const uint8_t* __restrict__ alive, uint32_t* __restrict__ counts,
                                                   unsigned long long* __restrict__ total,
                                                   const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ vals, const uint32_t* __restrict__ tab_base,
-                                                  const uint32_t* __restrict__ grand) {
+                                                  uint32_t* __restrict__ vals, const uint32_t* __restrict__ tab_base) {
   // Gaussians per wavefront: the table form takes 32 (lanes 32-63 own none; the pair walk still runs 64 pairs a
   // step), so that the first chunk's few hundred Gaussians per view spread over twice the wavefronts and each
   // wavefront's serial walk is half as long
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const uint8_t* al = alive ? alive + (int64_t)v * bc.T : nullptr;
   const int T = bc.T;
-  const int64_t nw = 4 * groups;  // TABLE: wavefront slots of this view
+  const int64_t ng = groups;  // TABLE: group slots of this view
   const int64_t tbase = TABLE ? (int64_t)tab_base[v] : 0;
   int tbits = 0;
   while ((1 << tbits) < T) ++tbits;
@@ -308,12 +309,10 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
       for (int tt = threadIdx.x; tt < T; tt += 256) tcnt_s[tt] = make_uint4(0, 0, 0, 0);
     }
     if (TABLE && EMIT) {
-      // The workgroup's four wavefronts own consecutive slots of every tile's list: its run.  The scanned table
-      // gives each wavefront's first slot; the next entry (the next workgroup's, or the next tile's first) ends
-      // the run.  When all runs fit in LDS they are laid out back to back there (local slots), else the
-      // counters hold the list slots themselves.
-      const int64_t at = tbase + 4 * grp;
-      const int64_t tab_len = (int64_t)tab_base[bc.N];
+      // The workgroup's four wavefronts own consecutive slots of every tile's list: its run, which starts at the
+      // scanned offset and holds the counts of the table word, wavefront after wavefront.  When all runs fit in
+      // LDS they are laid out back to back there (local slots), else the counters hold the list slots themselves.
+      const int64_t at = tbase + grp;
       uint32_t cnt[4];
       uint32_t mine = 0;
 #pragma unroll
@@ -321,12 +320,11 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
         const int tt = 4 * (int)threadIdx.x + q;
         cnt[q] = 0;
         if (tt < T) {
-          const uint4 o = *reinterpret_cast<const uint4*>(offsets + at + (int64_t)tt * nw);
-          const int64_t nx = at + (int64_t)tt * nw + 4;
-          const uint32_t e = nx < tab_len ? offsets[nx] : *grand;
-          tcnt_s[tt] = o;
-          ppos[tt] = o.x;
-          cnt[q] = e - o.x;
+          const uint32_t c = counts[at + (int64_t)tt * ng], o = offsets[at + (int64_t)tt * ng];
+          const uint32_t c0 = c & 255u, c1 = (c >> 8) & 255u, c2 = (c >> 16) & 255u, c3 = c >> 24;
+          tcnt_s[tt] = make_uint4(o, o + c0, o + c0 + c1, o + c0 + c1 + c2);
+          ppos[tt] = o;
+          cnt[q] = c0 + c1 + c2 + c3;
         }
         mine += cnt[q];
       }
@@ -399,9 +397,11 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
       __syncthreads();
     }
     if (TABLE && !EMIT) {
-      const int64_t at = tbase + 4 * grp;
-      for (int tt = threadIdx.x; tt < T; tt += 256)
-        *reinterpret_cast<uint4*>(counts + at + (int64_t)tt * nw) = tcnt_s[tt];
+      const int64_t at = tbase + grp;
+      for (int tt = threadIdx.x; tt < T; tt += 256) {
+        const uint4 c = tcnt_s[tt];
+        counts[at + (int64_t)tt * ng] = c.x | (c.y << 8) | (c.z << 16) | (c.w << 24);
+      }
       __syncthreads();
     }
   }
@@ -416,16 +416,16 @@ __global__ __launch_bounds__(256) void bin_kernel(const float4* __restrict__ rec
 }
 
 // Chunk-0 layout of the table form: e0[v] = min(front[v], fcap) (the first chunk's end, where the second
-// starts), base[v] = T * sum over earlier views of nw = 4 ceil(e0 / kTableGroup) (wavefront slots, whole workgroups),
-// base[N] = the table's length.
+// starts), base[v] = T * sum over earlier views of ng = ceil(e0 / kTableGroup) (workgroup slots), base[N] = the
+// table's length.
 __global__ __launch_bounds__(256) void table_setup_kernel(const uint32_t* __restrict__ front, int N, int T,
                                                           uint32_t fcap, uint32_t* __restrict__ e0,
                                                           uint32_t* __restrict__ base) {
   __shared__ uint32_t wsum[4];
   const int v = threadIdx.x, lane = v & 63, w = v >> 6;
   const uint32_t e = v < N ? min(front[v], fcap) : 0u;
-  const uint32_t nw = 4 * ((e + kTableGroup - 1) / kTableGroup);
-  const uint32_t inc = wave_incl_scan_u32(nw, lane);
+  const uint32_t ng = (e + kTableGroup - 1) / kTableGroup;
+  const uint32_t inc = wave_incl_scan_u32(ng, lane);
   if (lane == 63) wsum[w] = inc;
   __syncthreads();
   uint32_t before = 0, tot = 0;
@@ -435,13 +435,13 @@ __global__ __launch_bounds__(256) void table_setup_kernel(const uint32_t* __rest
   }
   if (v < N) {
     e0[v] = e;
-    base[v] = (uint32_t)T * (before + inc - nw);
+    base[v] = (uint32_t)T * (before + inc - ng);
   }
   if (v == 0) base[N] = (uint32_t)T * tot;
 }
 
-// List starts from the scanned table: start[v T + t] = scanned[base_v + t nw_v] (the slot of the view's first
-// wavefront in tile t), start[N T] = the key total; *max_total = max(*max_total, key total).  Starts are clamped
+// List starts from the scanned table: start[v T + t] = scanned[base_v + t ng_v] (the slot of the view's first
+// group in tile t), start[N T] = the key total; *max_total = max(*max_total, key total).  Starts are clamped
 // to the key capacity, as emission drops keys beyond it: a frame that overflows reads only written slots (and
 // is reported and rendered again).
 __global__ __launch_bounds__(256) void table_starts_kernel(const uint32_t* __restrict__ scanned,
@@ -460,8 +460,8 @@ __global__ __launch_bounds__(256) void table_starts_kernel(const uint32_t* __res
     return;
   }
   const int v = (int)(i / T), t = (int)(i - (int64_t)v * T);
-  const int64_t nw = 4 * (((int64_t)e0[v] + kTableGroup - 1) / kTableGroup);
-  const int64_t k = (int64_t)base[v] + t * nw;
+  const int64_t ng = ((int64_t)e0[v] + kTableGroup - 1) / kTableGroup;
+  const int64_t k = (int64_t)base[v] + t * ng;
   start[i] = min(k < (int64_t)base[N] ? scanned[k] : g, cap);
 }
 
@@ -521,7 +521,7 @@ hipError_t launch_bin_count(const float4* rec, const uint32_t* vis_count, const 
                             hipStream_t s) {
   const dim3 grid(bin_blocks(ch), (unsigned)bc.N);
   hipLaunchKernelGGL((bin_kernel<false, false>), grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, counts,
-                     total, nullptr, nullptr, nullptr, nullptr, nullptr);
+                     total, nullptr, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -530,7 +530,7 @@ hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const u
                            uint32_t* vals, hipStream_t s) {
   const dim3 grid(bin_blocks(ch), (unsigned)bc.N);
   hipLaunchKernelGGL((bin_kernel<true, false>), grid, dim3(256), 0, s, rec, vis_count, live, bc, ch, alive, nullptr,
-                     nullptr, offsets, keys, vals, nullptr, nullptr);
+                     nullptr, offsets, keys, vals, nullptr);
   return hipGetLastError();
 }
 
@@ -549,19 +549,19 @@ hipError_t launch_bin_table_count(const float4* rec, const uint32_t* vis_count, 
   c.tgx = table_blocks(ch);
   const dim3 grid((unsigned)(8 * ((bc.N + 7) / 8) * c.tgx));
   hipLaunchKernelGGL((bin_kernel<false, true>), grid, dim3(256), (size_t)16 * bc.T, s, rec, vis_count, nullptr, bc, c,
-                     alive, table, nullptr, nullptr, nullptr, nullptr, base, nullptr);
+                     alive, table, nullptr, nullptr, nullptr, nullptr, base);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_table_emit(const float4* rec, const uint32_t* vis_count, const BlendConst& bc,
-                                 const ChunkArgs& ch, const uint8_t* alive, const uint32_t* base,
-                                 const uint32_t* scanned, const uint32_t* grand, uint32_t* vals, hipStream_t s) {
+                                 const ChunkArgs& ch, const uint8_t* alive, const uint32_t* base, uint32_t* table,
+                                 const uint32_t* scanned, uint32_t* vals, hipStream_t s) {
   if (bc.T > kTableMaxTiles || !ch.first || !ch.front) return hipErrorInvalidValue;
   ChunkArgs c = ch;
   c.tgx = table_blocks(ch);
   const dim3 grid((unsigned)(8 * ((bc.N + 7) / 8) * c.tgx));
   hipLaunchKernelGGL((bin_kernel<true, true>), grid, dim3(256), (size_t)20 * bc.T + kTableStage, s, rec, vis_count,
-                     nullptr, bc, c, alive, nullptr, nullptr, scanned, nullptr, vals, base, grand);
+                     nullptr, bc, c, alive, table, nullptr, scanned, nullptr, vals, base);
   return hipGetLastError();
 }
 

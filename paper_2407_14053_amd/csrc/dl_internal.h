@@ -168,9 +168,9 @@ int64_t scan_partial_count(int64_t n);
 // exclusive scan of n uint32 (in may equal out); `partial` holds scan_partial_count(n) + 1 entries and
 // receives the grand total in partial[scan_partial_count(n)].
 // With n_dev, only the first min(n, n_mul * *n_dev) entries are scanned; the grand total of what was scanned lands in
-// partial[scan_partial_count(n)] either way.
+// partial[scan_partial_count(n)] either way.  byte_sums: each input word counts as the sum of its four bytes.
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, hipStream_t s,
-                              const uint32_t* n_dev = nullptr, int n_mul = 1);
+                              const uint32_t* n_dev = nullptr, int n_mul = 1, bool byte_sums = false);
 int64_t radix_hist_size(int64_t seg_len, int n_seg);
 // Stable partition of (key = digit < n_dig, value) pairs within each of n_seg segments given as device ranges
 // [seg_start[s], seg_start[s + 1]) of one array (clamped to cap): afterwards every segment holds its values
@@ -284,10 +284,11 @@ hipError_t launch_bin_emit(const float4* rec, const uint32_t* vis_count, const u
                            uint32_t* vals, hipStream_t s);
 // Table form of the first chunk's binning (T <= kTableMaxTiles): no partition, ranks written into the final
 // (view, tile) lists.  launch_table_setup: e0[v] = min(front[v], fcap) ends the first chunk (the second starts
-// there), base[v] = T * sum_{u < v} ceil(e0[u] / 64), base[N] = table length (N <= 256).  Count writes the
-// table [v][t][wavefront] from base[v]; after an exclusive scan of base[N] entries, emit writes the ranks of
-// chunk ranks [0, e0[v]) into vals (slots below cap), and launch_table_starts writes start[NT + 1] (list
-// bounds clamped to cap, start[NT] = *grand, the scan's total) and raises *max_total to the key total.
+// there), base[v] = T * sum_{u < v} ceil(e0[u] / kTableGroup), base[N] = table length (N <= 256).  Count writes
+// the table [v][t][workgroup] from base[v], one word of four byte counts (its wavefronts' hits) per entry; after
+// an exclusive scan of the base[N] words' byte sums into `scanned`, emit writes the ranks of chunk ranks
+// [0, e0[v]) into vals (slots below cap), and launch_table_starts writes start[NT + 1] (list bounds clamped to
+// cap, start[NT] = *grand, the scan's total) and raises *max_total to the key total.
 constexpr int kTableMaxTiles = 1024;
 constexpr int kTableWaveRanks = 32;                   // ranks (Gaussians) per wavefront slot of the table
 constexpr int kTableGroup = 4 * kTableWaveRanks;      // ranks per workgroup of the table form
@@ -298,8 +299,8 @@ hipError_t launch_bin_table_count(const float4* rec, const uint32_t* vis_count, 
                                   const ChunkArgs& ch, const uint8_t* alive, const uint32_t* base, uint32_t* table,
                                   hipStream_t s);
 hipError_t launch_bin_table_emit(const float4* rec, const uint32_t* vis_count, const BlendConst& bc,
-                                 const ChunkArgs& ch, const uint8_t* alive, const uint32_t* base,
-                                 const uint32_t* scanned, const uint32_t* grand, uint32_t* vals, hipStream_t s);
+                                 const ChunkArgs& ch, const uint8_t* alive, const uint32_t* base, uint32_t* table,
+                                 const uint32_t* scanned, uint32_t* vals, hipStream_t s);
 hipError_t launch_table_starts(const uint32_t* scanned, const uint32_t* base, const uint32_t* e0, int N, int T,
                                const uint32_t* grand, uint32_t cap, unsigned long long* max_total, uint32_t* start,
                                hipStream_t s);

@@ -422,9 +422,9 @@ int64_t chunk_stride(int64_t G, int c) {
 }
 
 // The first chunk uses the table form of binning (no tile partition) when a view has at most kTableMaxTiles
-// tiles; its table holds one count per (view, tile, wavefront slot of kTableWaveRanks ranks), at most
-// kTableMaxEntries, so the first chunk of each view is capped at fcap ranks (the second chunk starts where it
-// ended).  0: partition form.
+// tiles; its table holds one byte count per (view, tile, wavefront slot of kTableWaveRanks ranks), four to a
+// word, at most kTableMaxEntries counts, so the first chunk of each view is capped at fcap ranks (the second
+// chunk starts where it ended).  0: partition form.
 constexpr int64_t kTableMaxEntries = 64ll << 20;
 uint32_t table_fcap(int N, int64_t G, int64_t T) {
   if (T > kTableMaxTiles || N <= 0 || T <= 0) return 0;
@@ -433,7 +433,7 @@ uint32_t table_fcap(int N, int64_t G, int64_t T) {
 }
 int64_t table_entries(int N, int64_t G, int64_t T) {
   const uint32_t f = table_fcap(N, G, T);
-  return f ? T * N * 4 * (((int64_t)f + kTableGroup - 1) / kTableGroup) : 0;  // slots in whole workgroups
+  return f ? T * N * (((int64_t)f + kTableGroup - 1) / kTableGroup) : 0;  // one word per workgroup slot
 }
 
 // Device bytes of every per-frame buffer, in the order render_frame ensures them.
@@ -455,7 +455,7 @@ FrameSizes frame_sizes(int N, int64_t G, int64_t NT, int64_t nstate, uint32_t ca
   for (int c = 0; c < kChunks; ++c) max_stride = std::max(max_stride, chunk_stride(G, c) + 64);
   z.max_wstride = (max_stride + 63) / 64;
   const int64_t tab = table_entries(N, G, N ? NT / N : 0);
-  const int64_t ncounts = std::max<int64_t>((int64_t)N * z.max_wstride, tab + 1);
+  const int64_t ncounts = std::max<int64_t>((int64_t)N * z.max_wstride, 2 * tab + 1);
   const int64_t hs = std::max(std::max(std::max(radix_hist_size(G, N), depth_ranges_hist_size(G, N)),
                                         tile_partition_hist_size(N)),
                                split_hist_size(G, N));
@@ -466,7 +466,7 @@ FrameSizes frame_sizes(int N, int64_t G, int64_t NT, int64_t nstate, uint32_t ca
       (size_t)NG * 8, (size_t)NG * 8,                 // depth keys (double-buffered)
       (size_t)NG * 4, (size_t)NG * 4,                 // Gaussian indices (double-buffered)
       256 * 4,                                        // visible counts
-      (size_t)ncounts * 4,                            // per-wavefront key counts, or the first chunk's table
+      (size_t)ncounts * 4,                            // per-wavefront key counts, or the first chunk's table, scanned
       (size_t)N * 4,                                  // live tiles per view
       (size_t)(3 * N + 2) * 4,                        // view key ranges and the partition layout
       (size_t)(8 * N + 2) * 4,                        // fronts, sort ranges, rank ends, sort layout, table layout
@@ -649,22 +649,23 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     const uint32_t* live = c > 0 ? C->live.as<uint32_t>() : nullptr;
     const uint32_t* svals;
     if (c == 0 && fcap) {
-      // table form: counts per (view, tile, wavefront), scan, ranks written into the final lists
+      // table form: counts per (view, tile, wavefront), scan, ranks written into the final lists; the scanned
+      // table follows the counts
       uint32_t* table = C->counts.as<uint32_t>();
+      uint32_t* scanned = table + tab_n;
       mk = C->begin(DL_STAGE_BIN_COUNT, s);
       // every tile with rays is live in the first chunk (tiles without rays have empty blend work)
       HIP_TRY(launch_bin_table_count(C->srec.as<float4>(), C->vis.as<uint32_t>(), bc, ch, nullptr, tbase, table, s));
       C->end(mk, s);
       mk = C->begin(DL_STAGE_SCAN, s);
-      HIP_TRY(exclusive_scan_u32(table, table, tab_n, C->partial.as<uint32_t>(), s, tbase + N, 1));
+      HIP_TRY(exclusive_scan_u32(table, scanned, tab_n, C->partial.as<uint32_t>(), s, tbase + N, 1, true));
       C->end(mk, s);
       mk = C->begin(DL_STAGE_BIN_EMIT, s);
       HIP_TRY(launch_bin_table_emit(C->srec.as<float4>(), C->vis.as<uint32_t>(), bc, ch, nullptr, tbase, table,
-                                    C->partial.as<uint32_t>() + scan_partial_count(tab_n), C->bv[0].as<uint32_t>(),
-                                    s));
+                                    scanned, C->bv[0].as<uint32_t>(), s));
       C->end(mk, s);
       mk = C->begin(DL_STAGE_TILE_SORT, s);
-      HIP_TRY(launch_table_starts(table, tbase, e0, N, tl.T, C->partial.as<uint32_t>() + scan_partial_count(tab_n),
+      HIP_TRY(launch_table_starts(scanned, tbase, e0, N, tl.T, C->partial.as<uint32_t>() + scan_partial_count(tab_n),
                                   cap, total + 1, C->tstart.as<uint32_t>(), s));
       C->end(mk, s);
       svals = C->bv[0].as<uint32_t>();

@@ -59,6 +59,12 @@ __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* total) {
 
 // The scans take a static length n, or a device length n_mul * *n_dev (<= n; grids are sized for n).  Each
 // workgroup owns a tile of kScanTile items, read and written with consecutive lanes on consecutive items.
+// BYTES: each input word stands for the sum of its four bytes.
+__device__ inline uint32_t scan_item(uint32_t x, bool bytes) {
+  return bytes ? (x & 255u) + ((x >> 8) & 255u) + ((x >> 16) & 255u) + (x >> 24) : x;
+}
+
+template <bool BYTES>
 __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
                                                                  const uint32_t* __restrict__ n_dev, int n_mul,
                                                                  uint32_t* __restrict__ partial) {
@@ -72,7 +78,7 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* _
 #pragma unroll
   for (int i = 0; i < kScanIPT; ++i) {
     const int64_t k = base + i * kThreads + threadIdx.x;
-    if (k < n) s += in[k];
+    if (k < n) s += scan_item(in[k], BYTES);
   }
   uint32_t total;
   block_excl_scan(s, &total);
@@ -83,6 +89,7 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* _
 // the workgroup) and scans its own items, staged in LDS so that thread j scans items [16 j, 16 j + 16) of the
 // tile (one padding word every 16 keeps those reads free of bank conflicts); the last tile writes the grand
 // total to *grand.
+template <bool BYTES>
 __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* in, uint32_t* out, int64_t n,
                                                                const uint32_t* __restrict__ n_dev, int n_mul,
                                                                const uint32_t* __restrict__ partial_in,
@@ -103,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* in,
 #pragma unroll
   for (int i = 0; i < kScanIPT; ++i) {
     const int j = i * kThreads + threadIdx.x;
-    st[pad(j)] = base + j < n ? in[base + j] : 0u;
+    st[pad(j)] = base + j < n ? scan_item(in[base + j], BYTES) : 0u;
   }
   __syncthreads();
   uint32_t v[kScanIPT];
@@ -1171,12 +1178,20 @@ bool ranges_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, int n_seg, const uint
 int64_t scan_partial_count(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial, hipStream_t s,
-                              const uint32_t* n_dev, int n_mul) {
+                              const uint32_t* n_dev, int n_mul, bool byte_sums) {
   if (n <= 0) return hipSuccess;
   const int64_t np = scan_partial_count(n);
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, n, n_dev, n_mul, partial);
-  hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)np), dim3(kThreads), 0, s, in, out, n, n_dev, n_mul, partial,
-                     partial + np);
+  if (byte_sums) {
+    hipLaunchKernelGGL(scan_reduce_kernel<true>, dim3((unsigned)np), dim3(kThreads), 0, s, in, n, n_dev, n_mul,
+                       partial);
+    hipLaunchKernelGGL(scan_down_kernel<true>, dim3((unsigned)np), dim3(kThreads), 0, s, in, out, n, n_dev, n_mul,
+                       partial, partial + np);
+  } else {
+    hipLaunchKernelGGL(scan_reduce_kernel<false>, dim3((unsigned)np), dim3(kThreads), 0, s, in, n, n_dev, n_mul,
+                       partial);
+    hipLaunchKernelGGL(scan_down_kernel<false>, dim3((unsigned)np), dim3(kThreads), 0, s, in, out, n, n_dev, n_mul,
+                       partial, partial + np);
+  }
   return hipGetLastError();
 }
 
