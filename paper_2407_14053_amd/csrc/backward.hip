@@ -223,6 +223,7 @@ __global__ __launch_bounds__(NT) void blend_bwd_kernel(const float4* __restrict_
   for (int j = 0; j < RPT; ++j) mine |= live[j];
   const bool tile_live = __syncthreads_or(mine);
   if (!tile_live && threadIdx.x == 0) alive[vt] = 0;
+  if (tile_live && threadIdx.x == 0 && bk.later) *bk.later = 1ull;  // every writer stores the same value
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int idx = threadIdx.x + j * NT;

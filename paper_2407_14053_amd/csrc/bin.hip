@@ -468,10 +468,7 @@ __global__ __launch_bounds__(256) void table_starts_kernel(const uint32_t* __res
 // Live tiles of each view (one workgroup per view), read by the binning of the next depth chunk.
 __global__ __launch_bounds__(256) void view_live_kernel(const uint8_t* __restrict__ alive, int64_t T,
                                                          uint32_t* __restrict__ live,
-                                                         unsigned long long* __restrict__ total,
-                                                         unsigned long long* __restrict__ later,
-                                                         const uint32_t* __restrict__ vis,
-                                                         unsigned long long* __restrict__ vis_sum) {
+                                                         unsigned long long* __restrict__ total) {
   __shared__ uint32_t part[4];
   const int v = blockIdx.x;
   if (v == 0 && threadIdx.x == 0) *total = 0;  // the next chunk's key count starts from zero
@@ -480,16 +477,11 @@ __global__ __launch_bounds__(256) void view_live_kernel(const uint8_t* __restric
   for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t n = part[0] + part[1] + part[2] + part[3];
-    live[v] = n;
-    if (later && n) *later = 1ull;  // every writer stores the same value
-    if (vis) atomicAdd(vis_sum, (unsigned long long)vis[v]);
-  }
+  if (threadIdx.x == 0) live[v] = part[0] + part[1] + part[2] + part[3];
 }
 
 // Start of a frame: every (view, tile) with rays is live, the front histogram and the first n_totals frame totals
-// (the chunk's key count, the frame's largest, whether a later chunk is needed, the visible items) are zero.
+// (the chunk's key count, the frame's largest, whether a later chunk is needed) are zero.
 __global__ __launch_bounds__(256) void frame_init_kernel(uint8_t* __restrict__ alive,
                                                          const uint32_t* __restrict__ ray_off, int64_t n,
                                                          uint32_t* __restrict__ zero32, int64_t n_zero,
@@ -575,10 +567,8 @@ hipError_t launch_table_starts(const uint32_t* scanned, const uint32_t* base, co
 }
 
 hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, unsigned long long* total,
-                            unsigned long long* later, const uint32_t* vis, unsigned long long* vis_sum,
                             hipStream_t s) {
-  hipLaunchKernelGGL(view_live_kernel, dim3((unsigned)N), dim3(256), 0, s, alive, T, live, total, later, vis,
-                     vis_sum);
+  hipLaunchKernelGGL(view_live_kernel, dim3((unsigned)N), dim3(256), 0, s, alive, T, live, total);
   return hipGetLastError();
 }
 

@@ -257,6 +257,7 @@ __global__ __launch_bounds__(NT, (blend_min_waves<RPT>())) void blend_kernel(con
   for (int j = 0; j < RPT; ++j) mine |= sT[j] > 0.0f;
   const bool tile_live = __syncthreads_or(mine);
   if (!tile_live && threadIdx.x == 0) alive[vt] = 0;
+  if (tile_live && threadIdx.x == 0 && bk.later) *bk.later = 1ull;  // every writer stores the same value
 
   if (STATS) {
     unsigned long long e = 0, b = 0, r = 0;

@@ -133,6 +133,7 @@ __device__ inline void sh_basis(int deg, float x, float y, float z, float* Y) {
 // Per-chunk blend flags
 struct BlendChunk {
   int first, last;
+  unsigned long long* later;  // given: set to 1 by every workgroup whose tile keeps a live ray
 };
 
 // ---- view map and ray lists (viewmap.hip) ----
@@ -198,12 +199,14 @@ int split_waves_per_seg(int64_t seg_len, int n_seg);
 bool radix_split_u64(uint64_t* k0, uint64_t* k1, uint32_t* v1, int64_t seg_len, int n_seg, const uint64_t* thr,
                      uint64_t drop_key, uint32_t* n_vis, uint32_t* n_front, uint32_t* hist, uint32_t* partial,
                      hipStream_t s, hipError_t* err, const uint32_t* live = nullptr, bool back_only = false);
-// The front part of that split alone: each of the split's runs (split_waves_per_seg runs per segment) keeps its
-// items that are not drop_key and below thr[s], in order, at the run's start in kout, each packed as
-// key << 24 | position in the segment, and cnt (split_hist_size entries) receives per run the count of those and
-// of all kept items, [segment][2][run].  Segments of at most kFrontSortMaxG items.
-hipError_t launch_front_gather(const uint64_t* keys, uint64_t* kout, int64_t G, int N, const uint64_t* thr,
-                               uint64_t drop_key, uint32_t* cnt, hipStream_t s);
+// The front part of that split alone: thr[s] is picked from the sampled histogram `hist` as launch_front_select
+// does, and each of the split's runs (split_waves_per_seg runs per segment) keeps its items that are not drop_key
+// and below thr[s], in order, at the run's start in kout, each packed as key << 24 | position in the segment;
+// cnt (split_hist_size entries) receives per run the count of those and of all kept items, [segment][2][run].
+// Segments of at most kFrontSortMaxG items.
+hipError_t launch_front_gather(const uint64_t* keys, uint64_t* kout, int64_t G, int N, const uint32_t* hist,
+                               int key_bits, int64_t num, int64_t den, uint64_t* thr, uint64_t drop_key,
+                               uint32_t* cnt, hipStream_t s);
 // Stable LSD sort of each device range [lo[s], hi[s]) in place (n_seg <= 256), with the histogram layout that
 // launch_depth_ranges wrote to `layout`; returns whether the result is in (k1, v1).  hist: depth_ranges_hist_size
 // entries.
@@ -304,10 +307,8 @@ hipError_t launch_bin_table_emit(const float4* rec, const uint32_t* vis_count, c
 hipError_t launch_table_starts(const uint32_t* scanned, const uint32_t* base, const uint32_t* e0, int N, int T,
                                const uint32_t* grand, uint32_t cap, unsigned long long* max_total, uint32_t* start,
                                hipStream_t s);
-// live[v] = live tiles of view v; *total = 0 (for the next chunk); *later = 1 if any tile is live (later given);
-// *vis_sum += the sum of vis[0, N) (vis given)
+// live[v] = live tiles of view v; *total = 0 (for the next chunk)
 hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, unsigned long long* total,
-                            unsigned long long* later, const uint32_t* vis, unsigned long long* vis_sum,
                             hipStream_t s);
 
 

@@ -140,7 +140,7 @@ struct dl_ctx {
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
   double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
   // pinned, read after the first depth chunk of eager frames: that chunk's key count, whether a tile is still
-  // live, the visible Gaussians of all views
+  // live, then (profiled frames) the visible Gaussians of each view [256]
   unsigned long long* frame_host = nullptr;
   // profiling: 0 off, 1 HIP events around the blend launches, 2 around every stage, 3 every stage and the
   // blend's work counters
@@ -477,7 +477,7 @@ FrameSizes frame_sizes(int N, int64_t G, int64_t NT, int64_t nstate, uint32_t ca
       (size_t)(NT + 1) * 4,                           // list starts
       (size_t)NT,                                     // live tiles
       (size_t)std::max<int64_t>(nstate, 1) * 16,      // ray state
-      4 * 8,                                          // key totals: chunk, largest; later chunk needed; visible
+      3 * 8,                                          // key totals: chunk, largest, later chunk needed
       (size_t)hs * 4,                                 // radix histograms
       (size_t)(scan_partial_count(std::max<int64_t>(hs, ncounts)) + 2) * 4,  // scan partials
       stats ? (size_t)kStatSlots * 3 * 8 : 0,         // work counters
@@ -542,7 +542,7 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   if (C->prof >= 3) HIP_TRY(launch_fill_u64(C->stats.as<unsigned long long>(), kStatSlots * 3, 0ull, s));
   HIP_TRY(launch_frame_init(C->alive.as<uint8_t>(), standard ? nullptr : L->off.as<uint32_t>(), NT,
                             C->fhist.as<uint32_t>(), front_hist_size(N), C->dtotal.as<unsigned long long>(),
-                            mode.keep_max ? 1 : 4, s));
+                            mode.keep_max ? 1 : 3, s));
   C->end(mk, s);
 
   ProjConst pc{};
@@ -568,7 +568,8 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   hipError_t e;
   // Depth order.  The first chunk is each view's front (the nearest ~1/32 of its visible Gaussians, chosen on a
   // histogram of the keys' top bits).  Scenes of at most kFrontSortMaxG Gaussians: one pass gathers the fronts
-  // (culled items dropped) and one workgroup per view sorts its front in LDS; the backs are split off and sorted
+  // (culled items dropped; each of its workgroups picks its view's threshold) and a few workgroups per view sort
+  // its front in LDS, each a range of the keys' top bits; the backs are split off and sorted
   // after the first chunk, only for views that still have a live tile.  Larger scenes: one stable pass drops the
   // culled items and puts each front before its back, and device passes sort the fronts now and the live backs
   // later.  Every view's ranks end in one buffer.
@@ -580,15 +581,16 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   uint32_t* rank_hi = rhi + N;
   uint32_t* dlayout = rank_hi + N;  // 2N + 1
   uint64_t* thr = C->thr.as<uint64_t>();
-  HIP_TRY(launch_front_select(N, kDepthKeyBits, kChunkBounds[1], kChunkDen, C->fhist.as<uint32_t>(), thr, s));
   bool fl = false;
   const bool lds_front = front_sort_fits(G, N);
   if (lds_front) {
-    HIP_TRY(launch_front_gather(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), G, N, thr, kDepthCulled,
-                                C->hist.as<uint32_t>(), s));
+    HIP_TRY(launch_front_gather(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), G, N, C->fhist.as<uint32_t>(),
+                                kDepthKeyBits, kChunkBounds[1], kChunkDen, thr, kDepthCulled, C->hist.as<uint32_t>(),
+                                s));
     HIP_TRY(launch_front_sort(C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N, C->hist.as<uint32_t>(),
                               C->fhist.as<uint32_t>(), thr, vis, front, rank_hi, s));
   } else {
+    HIP_TRY(launch_front_select(N, kDepthKeyBits, kChunkBounds[1], kChunkDen, C->fhist.as<uint32_t>(), thr, s));
     radix_split_u64(C->k64[0].as<uint64_t>(), C->k64[1].as<uint64_t>(), C->v32[1].as<uint32_t>(), G, N, thr,
                     kDepthCulled, vis, front, C->hist.as<uint32_t>(), C->partial.as<uint32_t>(), s, &e);
     if (e != hipSuccess) return fail(DL_EHIP, std::string("depth split: ") + hipGetErrorString(e));
@@ -692,7 +694,10 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
       if (e != hipSuccess) return fail(DL_EHIP, std::string("tile partition: ") + hipGetErrorString(e));
       C->end(mk, s);
     }
-    BlendChunk bk{c == 0, c == kChunks - 1};
+    // after the first chunk an eager frame reads whether a tile is still live (the blend's workgroups raise the
+    // flag), and a first-chunk plan keeps that flag as its status
+    const bool readback = c == 0 && kChunks > 1 && mode.finish;
+    BlendChunk bk{c == 0, c == kChunks - 1, (readback || (c == 0 && mode.first_only)) ? total + 2 : nullptr};
     mk = C->begin(DL_STAGE_BLEND, s);
     if (bwd) {
       HIP_TRY(launch_blend_backward(C->srec.as<float4>(), C->tstart.as<uint32_t>(), svals, sorted,
@@ -707,24 +712,23 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
                                    L->ent.as<uint32_t>(), L->max_rays, bc, bk, C->alive.as<uint8_t>(),
                                    C->state.as<float4>(), out, s));
     }
-    // after the first chunk an eager frame reads the later flag and the visible total, a first-chunk plan keeps the
-    // flag as its status
-    const bool readback = c == 0 && kChunks > 1 && mode.finish;
-    if (c + 1 < kChunks)
-      HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), total,
-                               (mode.first_only || readback) ? total + 2 : nullptr, readback ? vis : nullptr,
-                               total + 3, s));
+    // the live tiles per view for the next chunk (an eager frame counts them only once it knows a later chunk
+    // runs; a first-chunk plan has none)
+    if (c + 1 < kChunks && !readback && !mode.first_only)
+      HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), total, s));
     C->end(mk, s);
     if (mode.first_only) break;
     if (readback) {
       // an eager frame (its caller waits for it anyway) reads whether a tile is still live after the first chunk:
       // when every tile's rays have terminated, every tile has written its pixels and the later chunks would only
       // launch empty kernels, so they are skipped (a captured frame keeps them: its launches are fixed).  The same
-      // copy brings the first chunk's key count and the views' visible total: a frame that skips the later chunks
-      // is complete here, and its overflow check needs nothing more (a backward frame goes on to the
-      // projection's backward).
+      // copy brings the first chunk's key count: a frame that skips the later chunks is complete here, and its
+      // overflow check needs nothing more (a backward frame goes on to the projection's backward).  Profiled
+      // frames also bring the views' visible counts.
       unsigned long long* rb = C->frame_host;
-      HIP_TRY(hipMemcpyAsync(rb, total + 1, 3 * 8, hipMemcpyDeviceToHost, s));
+      uint32_t* vis_host = reinterpret_cast<uint32_t*>(C->frame_host + 2);
+      HIP_TRY(hipMemcpyAsync(rb, total + 1, 2 * 8, hipMemcpyDeviceToHost, s));
+      if (C->prof) HIP_TRY(hipMemcpyAsync(vis_host, vis, (size_t)N * 4, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       if (rb[0] > cap) {
         // the first chunk overflowed: its blend saw truncated lists, so the live tiles (and the later chunks'
@@ -736,9 +740,11 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
       if (!C->later_ran) {
         if (bwd) break;
         C->keys = (int64_t)rb[0];
-        if (C->prof) C->visible += (int64_t)rb[2];
+        if (C->prof)
+          for (int v = 0; v < N; ++v) C->visible += vis_host[v];
         return DL_OK;
       }
+      HIP_TRY(launch_view_live(C->alive.as<uint8_t>(), tl.T, N, C->live.as<uint32_t>(), total, s));
     }
     if (c == 0 && kChunks > 1) {
       // the backs of the views that still have a live tile (split off the projection's keys first when only the
@@ -861,7 +867,7 @@ int dl_create(int device, dl_ctx** out) {
   dl_ctx* c = new dl_ctx();
   c->device = device;
   if (hipHostMalloc((void**)&c->cams_host, 256 * kCamDoubles * 8, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->frame_host, 4 * 8, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->frame_host, 2 * 8 + 256 * 4, hipHostMallocDefault) != hipSuccess) {
     if (c->cams_host) (void)hipHostFree(c->cams_host);
     if (c->frame_host) (void)hipHostFree(c->frame_host);
     delete c;

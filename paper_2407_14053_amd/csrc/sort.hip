@@ -458,14 +458,12 @@ __global__ __launch_bounds__(kThreads) void chunk_setup_kernel(const uint32_t* _
 // the exact front sizes come from the gather (or split) pass.
 constexpr int kFrontBins = 1 << kFrontBits;
 
-// Per view (one workgroup each): the smallest bin b whose cumulative sample count reaches ceil(n_s num / den)
-// of the n_s sampled keys; the front is every key below thr = (b + 1) << (key_bits - kFrontBits) (0: none).
-__global__ __launch_bounds__(kThreads) void front_select_kernel(const uint32_t* __restrict__ hist, int key_bits,
-                                                                  int64_t num, int64_t den,
-                                                                  uint64_t* __restrict__ thr) {
+// The threshold of one view (a whole workgroup of kThreads calls it): the smallest bin b whose cumulative sample
+// count reaches ceil(n_s num / den) of the n_s sampled keys; the front is every key below
+// thr = (b + 1) << (key_bits - kFrontBits) (0: none).
+__device__ uint64_t front_threshold(const uint32_t* __restrict__ h, int key_bits, int64_t num, int64_t den) {
   constexpr int kPer = kFrontBins / kThreads;
-  const int v = blockIdx.x;
-  const uint32_t* h = hist + (int64_t)v * kFrontBins;
+  __shared__ unsigned long long th_s;
   uint32_t c[kPer];
   uint32_t mine = 0;
 #pragma unroll
@@ -473,19 +471,32 @@ __global__ __launch_bounds__(kThreads) void front_select_kernel(const uint32_t* 
     c[i] = h[threadIdx.x * kPer + i];
     mine += c[i];
   }
+  if (threadIdx.x == 0) th_s = 0;
   uint32_t n;
-  uint32_t run = block_excl_scan(mine, &n);
+  uint32_t run = block_excl_scan(mine, &n);  // its barriers order the reset before the store below
   const uint32_t target = (uint32_t)(((int64_t)n * num + den - 1) / den);
-  if (target == 0) {
-    if (threadIdx.x == 0) thr[v] = 0;
-    return;
-  }
+  if (target > 0) {
 #pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    const uint32_t before = run;
-    run += c[i];
-    if (before < target && run >= target) thr[v] = (uint64_t)(threadIdx.x * kPer + i + 1) << (key_bits - kFrontBits);
+    for (int i = 0; i < kPer; ++i) {
+      const uint32_t before = run;
+      run += c[i];
+      if (before < target && run >= target)  // one thread: the count is monotone
+        th_s = (unsigned long long)(threadIdx.x * kPer + i + 1) << (key_bits - kFrontBits);
+    }
   }
+  __syncthreads();
+  const uint64_t th = th_s;
+  __syncthreads();  // every thread has read it before a later call resets it
+  return th;
+}
+
+// Per view (one workgroup each): thr[v] = front_threshold of its histogram.
+__global__ __launch_bounds__(kThreads) void front_select_kernel(const uint32_t* __restrict__ hist, int key_bits,
+                                                                  int64_t num, int64_t den,
+                                                                  uint64_t* __restrict__ thr) {
+  const int v = blockIdx.x;
+  const uint64_t th = front_threshold(hist + (int64_t)v * kFrontBins, key_bits, num, den);
+  if (threadIdx.x == 0) thr[v] = th;
 }
 
 // Exact sizes after the split pass, from its scanned histogram ([segment][digit 0, 1][block], exclusive) and the
@@ -601,19 +612,24 @@ __global__ void split_counts_kernel(const uint32_t* __restrict__ hist, const uin
 // The first chunk's part of the split: each wavefront keeps its run's front items (not dropped, key below the
 // view's threshold), in order, at the start of that run in `kout`, each packed as key << 24 | position in the view
 // (36 + 24 bits), and counts them and its kept items: cnt[2 v wps + k] = fronts, cnt[(2 v + 1) wps + k] = kept,
-// for run k of view v.  The front sort gathers the runs; the backs are split only when a later chunk needs them.
+// for run k of view v.  Every workgroup (four runs of one view, wps a multiple of four) picks the view's
+// threshold from its sampled histogram itself, and the view's first writes it to thr[v].  The front sort gathers
+// the runs; the backs are split only when a later chunk needs them.
 __global__ __launch_bounds__(kThreads) void front_gather_kernel(const uint64_t* __restrict__ keys, int64_t G, int wps,
-                                                                  const uint64_t* __restrict__ thr, uint64_t drop,
+                                                                  const uint32_t* __restrict__ hist, int key_bits,
+                                                                  int64_t num, int64_t den,
+                                                                  uint64_t* __restrict__ thr, uint64_t drop,
                                                                   uint64_t* __restrict__ kout,
                                                                   uint32_t* __restrict__ cnt) {
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   const int v = (int)(gw / wps), k = (int)(gw - (int64_t)v * wps);
+  const uint64_t th = front_threshold(hist + (int64_t)v * kFrontBins, key_bits, num, den);
+  if (k == 0 && lane == 0) thr[v] = th;
   int64_t lo, hi;
   split_range(G, wps, k, lo, hi);
   const uint64_t* kin = keys + (int64_t)v * G;
   uint64_t* ko = kout + (int64_t)v * G + lo;
-  const uint64_t th = thr[v];
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   uint32_t p = 0, kept = 0;
   for (int64_t i0 = lo; i0 < hi; i0 += 256) {
@@ -1233,14 +1249,15 @@ bool radix_split_u64(uint64_t* k0, uint64_t* k1, uint32_t* v1, int64_t seg_len, 
   return true;
 }
 
-hipError_t launch_front_gather(const uint64_t* keys, uint64_t* kout, int64_t G, int N, const uint64_t* thr,
-                               uint64_t drop_key, uint32_t* cnt, hipStream_t s) {
+hipError_t launch_front_gather(const uint64_t* keys, uint64_t* kout, int64_t G, int N, const uint32_t* hist,
+                               int key_bits, int64_t num, int64_t den, uint64_t* thr, uint64_t drop_key,
+                               uint32_t* cnt, hipStream_t s) {
   if (N <= 0) return hipSuccess;
   // positions must fit the packed item's 24 bits
   if (G > kFrontSortMaxG) return hipErrorInvalidValue;
   const int wps = split_waves_per_seg(G, N);
   hipLaunchKernelGGL(front_gather_kernel, dim3((unsigned)((int64_t)N * wps / kWaves)), dim3(kThreads), 0, s, keys, G,
-                     wps, thr, drop_key, kout, cnt);
+                     wps, hist, key_bits, num, den, thr, drop_key, kout, cnt);
   return hipGetLastError();
 }
 
