@@ -211,6 +211,28 @@ def test_depth_order_cases_match_oracle_and_standard(ctx, name):
     assert over.sum() <= 0.001 * over.size
 
 
+@pytest.mark.parametrize("n_views,case", [(40, "plain"), (40, "one_depth"), (130, "plain"), (130, "one_depth")])
+def test_front_sort_parts_match_oracle_and_standard(ctx, n_views, case):
+    """The LDS front sort splits each view's front into min(8, 256 // N) key ranges: 6 uneven parts at N = 40, one
+    part (no split) at N = 130; with every Gaussian at one depth all of a view's front falls in one part."""
+    from paper_2407_14053_amd import api
+    log("front sort parts", n_views, case)
+    d = synth.make_display(96, 48, n_views, Fraction(1, 3), Fraction(53, 10), baseline=0.3)
+    sc = _depth_case(case) if case != "plain" else synth.make_scene("tiny")
+    c2w = synth.pose_front(3.0)
+    S = api.Scene(ctx, sc.arrays())
+    D = api.Display(ctx, d)
+    img = api.render(ctx, S, D, c2w).cpu().numpy()
+    std, _ = api.render_standard(ctx, S, D, c2w)
+    assert np.array_equal(img, std.cpu().numpy())
+    ref, res, index = full_oracle_image(sc, d, c2w)
+    err, over = admissible_image_err(res, index, img)
+    log("  max err %.3g, over-budget %d" % (err[~over].max(), over.sum()))
+    assert err[~over].max() <= TOL
+    assert over.sum() <= 0.001 * over.size
+    assert img.max() > 0.05
+
+
 def _front_cut_case(name):
     """Scenes whose first depth chunk (each view's nearest ~1/32, chosen on bins of the depth key's top bits)
     holds more Gaussians than the LDS front sort takes, so that the front is cut at a key bin: 14000 Gaussians at
