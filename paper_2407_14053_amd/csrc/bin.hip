@@ -441,7 +441,8 @@ __global__ __launch_bounds__(256) void table_setup_kernel(const uint32_t* __rest
 }
 
 // List starts from the scanned table: start[v T + t] = scanned[base_v + t ng_v] (the slot of the view's first
-// group in tile t), start[N T] = the key total; *max_total = max(*max_total, key total).  Starts are clamped
+// group in tile t), start[N T] = the key total; *max_total = max(*max_total, key total), and *host_total = the key
+// total when given (a word of host memory the host reads after synchronising).  Starts are clamped
 // to the key capacity, as emission drops keys beyond it: a frame that overflows reads only written slots (and
 // is reported and rendered again).
 __global__ __launch_bounds__(256) void table_starts_kernel(const uint32_t* __restrict__ scanned,
@@ -449,6 +450,7 @@ __global__ __launch_bounds__(256) void table_starts_kernel(const uint32_t* __res
                                                            const uint32_t* __restrict__ e0, int N, int T,
                                                            const uint32_t* __restrict__ grand, uint32_t cap,
                                                            unsigned long long* __restrict__ max_total,
+                                                           unsigned long long* host_total,
                                                            uint32_t* __restrict__ start) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t NT = (int64_t)N * T;
@@ -457,6 +459,7 @@ __global__ __launch_bounds__(256) void table_starts_kernel(const uint32_t* __res
   if (i == NT) {
     start[NT] = min(g, cap);
     if (g > *max_total) *max_total = g;
+    if (host_total) *host_total = g;
     return;
   }
   const int v = (int)(i / T), t = (int)(i - (int64_t)v * T);
@@ -558,11 +561,11 @@ hipError_t launch_bin_table_emit(const float4* rec, const uint32_t* vis_count, c
 }
 
 hipError_t launch_table_starts(const uint32_t* scanned, const uint32_t* base, const uint32_t* e0, int N, int T,
-                               const uint32_t* grand, uint32_t cap, unsigned long long* max_total, uint32_t* start,
-                               hipStream_t s) {
+                               const uint32_t* grand, uint32_t cap, unsigned long long* max_total,
+                               unsigned long long* host_total, uint32_t* start, hipStream_t s) {
   const int64_t n = (int64_t)N * T + 1;
   hipLaunchKernelGGL(table_starts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, scanned, base, e0, N, T,
-                     grand, cap, max_total, start);
+                     grand, cap, max_total, host_total, start);
   return hipGetLastError();
 }
 

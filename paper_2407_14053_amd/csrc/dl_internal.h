@@ -305,8 +305,8 @@ hipError_t launch_bin_table_emit(const float4* rec, const uint32_t* vis_count, c
                                  const ChunkArgs& ch, const uint8_t* alive, const uint32_t* base, uint32_t* table,
                                  const uint32_t* scanned, uint32_t* vals, hipStream_t s);
 hipError_t launch_table_starts(const uint32_t* scanned, const uint32_t* base, const uint32_t* e0, int N, int T,
-                               const uint32_t* grand, uint32_t cap, unsigned long long* max_total, uint32_t* start,
-                               hipStream_t s);
+                               const uint32_t* grand, uint32_t cap, unsigned long long* max_total,
+                               unsigned long long* host_total, uint32_t* start, hipStream_t s);
 // live[v] = live tiles of view v; *total = 0 (for the next chunk)
 hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* live, unsigned long long* total,
                             hipStream_t s);

@@ -139,9 +139,11 @@ struct dl_ctx {
       state, dtotal, gacc;
   uint32_t key_cap = 0;  // current per-chunk key capacity (grows on overflow)
   double* cams_host = nullptr;  // pinned staging, 255 * 16 doubles
-  // pinned, read after the first depth chunk of eager frames: that chunk's key count, whether a tile is still
-  // live, then (profiled frames) the visible Gaussians of each view [256]
+  // pinned and coherent (kernels write it directly), read after the first depth chunk of eager frames: that
+  // chunk's key count, whether a tile is still live, then (profiled frames) the visible Gaussians of each view
+  // [256]; frame_dev is its device address
   unsigned long long* frame_host = nullptr;
+  unsigned long long* frame_dev = nullptr;
   // profiling: 0 off, 1 HIP events around the blend launches, 2 around every stage, 3 every stage and the
   // blend's work counters
   int prof = 0;
@@ -632,8 +634,12 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
   bc.tgt = (!standard && D->tgt.p) ? D->tgt.as<int32_t>() : nullptr;
   bc.single_channel = (!standard && L && L->single_channel) ? 1 : 0;
   unsigned long long* total = C->dtotal.as<unsigned long long>();
+  // an eager frame's first-chunk status words in host memory start at zero (the frame before has finished)
+  if (mode.finish) C->frame_host[0] = C->frame_host[1] = 0;
   for (int c = 0; c < kChunks; ++c) {
     C->chunk = c;
+    // after the first chunk an eager frame reads its key count and whether a tile is still live
+    const bool readback = c == 0 && kChunks > 1 && mode.finish;
     ChunkArgs ch{};
     // the second chunk starts where the front ended, whatever fraction the front took
     ch.num_lo = c == 1 ? 0 : kChunkBounds[c];
@@ -668,7 +674,8 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
       C->end(mk, s);
       mk = C->begin(DL_STAGE_TILE_SORT, s);
       HIP_TRY(launch_table_starts(scanned, tbase, e0, N, tl.T, C->partial.as<uint32_t>() + scan_partial_count(tab_n),
-                                  cap, total + 1, C->tstart.as<uint32_t>(), s));
+                                  cap, total + 1, readback ? C->frame_dev : nullptr, C->tstart.as<uint32_t>(),
+                                  s));
       C->end(mk, s);
       svals = C->bv[0].as<uint32_t>();
     } else {
@@ -694,10 +701,10 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
       if (e != hipSuccess) return fail(DL_EHIP, std::string("tile partition: ") + hipGetErrorString(e));
       C->end(mk, s);
     }
-    // after the first chunk an eager frame reads whether a tile is still live (the blend's workgroups raise the
-    // flag), and a first-chunk plan keeps that flag as its status
-    const bool readback = c == 0 && kChunks > 1 && mode.finish;
-    BlendChunk bk{c == 0, c == kChunks - 1, (readback || (c == 0 && mode.first_only)) ? total + 2 : nullptr};
+    // the blend's workgroups raise the later-chunk flag: in host memory for an eager frame, as the status of a
+    // first-chunk plan
+    BlendChunk bk{c == 0, c == kChunks - 1,
+                  readback ? C->frame_dev + 1 : (c == 0 && mode.first_only) ? total + 2 : nullptr};
     mk = C->begin(DL_STAGE_BLEND, s);
     if (bwd) {
       HIP_TRY(launch_blend_backward(C->srec.as<float4>(), C->tstart.as<uint32_t>(), svals, sorted,
@@ -721,13 +728,14 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
     if (readback) {
       // an eager frame (its caller waits for it anyway) reads whether a tile is still live after the first chunk:
       // when every tile's rays have terminated, every tile has written its pixels and the later chunks would only
-      // launch empty kernels, so they are skipped (a captured frame keeps them: its launches are fixed).  The same
-      // copy brings the first chunk's key count: a frame that skips the later chunks is complete here, and its
-      // overflow check needs nothing more (a backward frame goes on to the projection's backward).  Profiled
-      // frames also bring the views' visible counts.
-      unsigned long long* rb = C->frame_host;
+      // launch empty kernels, so they are skipped (a captured frame keeps them: its launches are fixed).  It also
+      // reads the first chunk's key count: a frame that skips the later chunks is complete here, and its overflow
+      // check needs nothing more (a backward frame goes on to the projection's backward).  The blend and (table
+      // form) the list-bounds kernel wrote both words into host memory; the partition form's count comes by copy,
+      // and profiled frames copy the views' visible counts.
+      volatile unsigned long long* rb = C->frame_host;
       uint32_t* vis_host = reinterpret_cast<uint32_t*>(C->frame_host + 2);
-      HIP_TRY(hipMemcpyAsync(rb, total + 1, 2 * 8, hipMemcpyDeviceToHost, s));
+      if (!fcap) HIP_TRY(hipMemcpyAsync(C->frame_host, total + 1, 8, hipMemcpyDeviceToHost, s));
       if (C->prof) HIP_TRY(hipMemcpyAsync(vis_host, vis, (size_t)N * 4, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       if (rb[0] > cap) {
@@ -867,7 +875,8 @@ int dl_create(int device, dl_ctx** out) {
   dl_ctx* c = new dl_ctx();
   c->device = device;
   if (hipHostMalloc((void**)&c->cams_host, 256 * kCamDoubles * 8, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->frame_host, 2 * 8 + 256 * 4, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->frame_host, 2 * 8 + 256 * 4, hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&c->frame_dev, c->frame_host, 0) != hipSuccess) {
     if (c->cams_host) (void)hipHostFree(c->cams_host);
     if (c->frame_host) (void)hipHostFree(c->frame_host);
     delete c;
