@@ -484,15 +484,18 @@ __global__ __launch_bounds__(256) void view_live_kernel(const uint8_t* __restric
 }
 
 // Start of a frame: every (view, tile) with rays is live, the front histogram and the first n_totals frame totals
-// (the chunk's key count, the frame's largest, whether a later chunk is needed) are zero.
+// (the chunk's key count, the frame's largest, whether a later chunk is needed) are zero, and (cams given) the
+// rig's cameras are built.
 __global__ __launch_bounds__(256) void frame_init_kernel(uint8_t* __restrict__ alive,
                                                          const uint32_t* __restrict__ ray_off, int64_t n,
                                                          uint32_t* __restrict__ zero32, int64_t n_zero,
-                                                         unsigned long long* __restrict__ totals, int n_totals) {
+                                                         unsigned long long* __restrict__ totals, int n_totals,
+                                                         CamRig rig, double* __restrict__ cams) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) alive[i] = ray_off ? (uint8_t)(ray_off[i + 1] > ray_off[i]) : (uint8_t)1;
   if (i < n_zero) zero32[i] = 0;
   if (i < n_totals) totals[i] = 0;
+  if (cams && i < rig.n) (void)rig_camera(rig, (int)i, cams + i * kCamDoubles);
 }
 
 __global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long v) {
@@ -576,10 +579,11 @@ hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* li
 }
 
 hipError_t launch_frame_init(uint8_t* alive, const uint32_t* ray_off, int64_t n, uint32_t* zero32, int64_t n_zero,
-                             unsigned long long* totals, int n_totals, hipStream_t s) {
-  const int64_t m = std::max<int64_t>(std::max<int64_t>(n, n_zero), n_totals);
+                             unsigned long long* totals, int n_totals, const CamRig& rig, double* cams,
+                             hipStream_t s) {
+  const int64_t m = std::max<int64_t>(std::max<int64_t>(std::max<int64_t>(n, n_zero), n_totals), cams ? rig.n : 0);
   hipLaunchKernelGGL(frame_init_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, alive, ray_off, n, zero32,
-                     n_zero, totals, n_totals);
+                     n_zero, totals, n_totals, rig, cams);
   return hipGetLastError();
 }
 

@@ -31,6 +31,52 @@ constexpr int kGaussBlockF4 = 18;  // per-Gaussian block of the projection's vie
 // Per-view camera block uploaded for every frame: 16 doubles = rotation rows (9), t (3), eye (3), 0.
 constexpr int kCamDoubles = 16;
 
+// The camera rig of a frame (Sec. 3.1, the light-field centre extrinsic): the centre camera-to-world pose, the
+// convergence distance, the baseline and the view count.  rig_camera writes view v's camera (kCamDoubles: the
+// world-to-camera rotation rows right, down, forward, the translation, the eye, 0): the eye at
+// eye_0 + baseline (v / (N - 1) - 1/2) right_0, aimed at eye_0 + converge_dist forward_0 with down_0 as the
+// reference down axis.  Host and device run this one function (IEEE division and square root, no contraction),
+// so the cameras an eager frame builds on the device equal those the host validates and stages for plans.
+// Returns 1 if the forward axis vanishes or is parallel to down_0 (the host rejects such poses).
+struct CamRig {
+  double c2w[16];
+  double converge_dist, baseline;
+  int n;
+};
+__host__ __device__ inline int rig_camera(const CamRig& r, int v, double* c) {
+  const double* m = r.c2w;
+  const double right0[3] = {m[0], m[4], m[8]}, down0[3] = {m[1], m[5], m[9]}, fwd0[3] = {m[2], m[6], m[10]};
+  const double eye0[3] = {m[3], m[7], m[11]};
+  double target[3];
+  for (int k = 0; k < 3; ++k) target[k] = eye0[k] + r.converge_dist * fwd0[k];
+  const double s = r.n > 1 ? r.baseline * ((double)v / (double)(r.n - 1) - 0.5) : 0.0;
+  double eye[3], f[3], rt[3], dn[3];
+  for (int k = 0; k < 3; ++k) eye[k] = eye0[k] + s * right0[k];
+  for (int k = 0; k < 3; ++k) f[k] = target[k] - eye[k];
+  const double nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  if (!(nf > 0)) return 1;
+  for (int k = 0; k < 3; ++k) f[k] /= nf;
+  // right = down0 x forward, down = forward x right
+  rt[0] = down0[1] * f[2] - down0[2] * f[1];
+  rt[1] = down0[2] * f[0] - down0[0] * f[2];
+  rt[2] = down0[0] * f[1] - down0[1] * f[0];
+  const double nr = sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+  if (!(nr > 0)) return 1;
+  for (int k = 0; k < 3; ++k) rt[k] /= nr;
+  dn[0] = f[1] * rt[2] - f[2] * rt[1];
+  dn[1] = f[2] * rt[0] - f[0] * rt[2];
+  dn[2] = f[0] * rt[1] - f[1] * rt[0];
+  for (int k = 0; k < 3; ++k) {
+    c[k] = rt[k];
+    c[3 + k] = dn[k];
+    c[6 + k] = f[k];
+  }
+  for (int a = 0; a < 3; ++a) c[9 + a] = -(c[a * 3] * eye[0] + c[a * 3 + 1] * eye[1] + c[a * 3 + 2] * eye[2]);
+  for (int k = 0; k < 3; ++k) c[12 + k] = eye[k];
+  c[15] = 0.0;
+  return 0;
+}
+
 struct ProjConst {
   int64_t G;        // Gaussians
   int64_t n_pad;    // scene row stride
@@ -313,8 +359,10 @@ hipError_t launch_view_live(const uint8_t* alive, int64_t T, int N, uint32_t* li
 
 
 // alive[i] = tile i has rays (ray_off nullptr: all); zero32[0, n_zero) = 0; totals[0, n_totals) = 0
+// (cams given: cams[v kCamDoubles ...] = rig_camera(rig, v) for v < rig.n)
 hipError_t launch_frame_init(uint8_t* alive, const uint32_t* ray_off, int64_t n, uint32_t* zero32, int64_t n_zero,
-                             unsigned long long* totals, int n_totals, hipStream_t s);
+                             unsigned long long* totals, int n_totals, const CamRig& rig, double* cams,
+                             hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
 
 // ---- blending (blend.hip) ----

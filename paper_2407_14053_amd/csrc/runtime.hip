@@ -231,6 +231,16 @@ int check_desc(const dl_display_desc* d, dl_display_desc& o) {
 }
 
 // Cameras of the rig (Eq. (17) with a horizontal toe-in rig), FP64.
+// The rig of a display and pose (rig_camera builds its cameras).
+CamRig make_rig(const dl_display_desc& d, const dl_pose* pose) {
+  CamRig r{};
+  for (int k = 0; k < 16; ++k) r.c2w[k] = pose->c2w[k];
+  r.converge_dist = pose->converge_dist;
+  r.baseline = d.baseline;
+  r.n = d.n_views;
+  return r;
+}
+
 int make_cameras(const dl_display_desc& d, const dl_pose* pose, double* out) {
   if (!pose) return fail(DL_EINVAL, "pose is NULL");
   const double* m = pose->c2w;
@@ -238,39 +248,10 @@ int make_cameras(const dl_display_desc& d, const dl_pose* pose, double* out) {
     if (!std::isfinite(m[k])) return fail(DL_EINVAL, "pose has non-finite entries");
   if (!(pose->converge_dist > 0) || !std::isfinite(pose->converge_dist))
     return fail(DL_EINVAL, "converge_dist must be finite and > 0");
-  const double right0[3] = {m[0], m[4], m[8]}, down0[3] = {m[1], m[5], m[9]}, fwd0[3] = {m[2], m[6], m[10]};
-  const double eye0[3] = {m[3], m[7], m[11]};
-  double target[3];
-  for (int k = 0; k < 3; ++k) target[k] = eye0[k] + pose->converge_dist * fwd0[k];
-  const int N = d.n_views;
-  for (int v = 0; v < N; ++v) {
-    const double s = N > 1 ? d.baseline * ((double)v / (double)(N - 1) - 0.5) : 0.0;
-    double eye[3], f[3], r[3], dn[3];
-    for (int k = 0; k < 3; ++k) eye[k] = eye0[k] + s * right0[k];
-    for (int k = 0; k < 3; ++k) f[k] = target[k] - eye[k];
-    double nf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-    if (!(nf > 0)) return fail(DL_EINVAL, "degenerate rig (camera at the convergence point)");
-    for (int k = 0; k < 3; ++k) f[k] /= nf;
-    // right = down0 x forward, down = forward x right
-    r[0] = down0[1] * f[2] - down0[2] * f[1];
-    r[1] = down0[2] * f[0] - down0[0] * f[2];
-    r[2] = down0[0] * f[1] - down0[1] * f[0];
-    double nr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    if (!(nr > 0)) return fail(DL_EINVAL, "degenerate rig (forward parallel to down)");
-    for (int k = 0; k < 3; ++k) r[k] /= nr;
-    dn[0] = f[1] * r[2] - f[2] * r[1];
-    dn[1] = f[2] * r[0] - f[0] * r[2];
-    dn[2] = f[0] * r[1] - f[1] * r[0];
-    double* c = out + v * kCamDoubles;
-    for (int k = 0; k < 3; ++k) {
-      c[k] = r[k];
-      c[3 + k] = dn[k];
-      c[6 + k] = f[k];
-    }
-    for (int a = 0; a < 3; ++a) c[9 + a] = -(c[a * 3] * eye[0] + c[a * 3 + 1] * eye[1] + c[a * 3 + 2] * eye[2]);
-    for (int k = 0; k < 3; ++k) c[12 + k] = eye[k];
-    c[15] = 0.0;
-  }
+  const CamRig r = make_rig(d, pose);
+  for (int v = 0; v < d.n_views; ++v)
+    if (rig_camera(r, v, out + v * kCamDoubles))
+      return fail(DL_EINVAL, "degenerate rig (camera at the convergence point, or forward parallel to down)");
   return DL_OK;
 }
 
@@ -539,12 +520,13 @@ int render_frame(dl_ctx* C, const dl_scene* S, const dl_display* D, const dl_pos
 
   C->frame_begin();
   int mk = C->begin(DL_STAGE_UPLOAD, s);
-  if (mode.upload)
-    HIP_TRY(hipMemcpyAsync(C->cams.p, C->cams_host, (size_t)N * kCamDoubles * 8, hipMemcpyHostToDevice, s));
   if (C->prof >= 3) HIP_TRY(launch_fill_u64(C->stats.as<unsigned long long>(), kStatSlots * 3, 0ull, s));
+  // an eager frame's cameras are built by the frame's first kernel from the pose (the host has validated the same
+  // cameras above); a captured frame's are uploaded by its plan before every launch
   HIP_TRY(launch_frame_init(C->alive.as<uint8_t>(), standard ? nullptr : L->off.as<uint32_t>(), NT,
                             C->fhist.as<uint32_t>(), front_hist_size(N), C->dtotal.as<unsigned long long>(),
-                            mode.keep_max ? 1 : 3, s));
+                            mode.keep_max ? 1 : 3, mode.upload ? make_rig(d, pose) : CamRig{},
+                            mode.upload ? C->cams.as<double>() : nullptr, s));
   C->end(mk, s);
 
   ProjConst pc{};
